@@ -1,0 +1,540 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Nothing here retypes the oracle's own formula: each check goes through an
+independent route (joint-distribution enumeration, a multivariate normal
+density, brute-force maximisation of the objective, closed forms derived by
+hand from the model equations, exact integer statistics, invariants proved
+in the paper).  A plausible slip in the oracle (dropped term, sign, index,
+factor 2, transposed operand) fails at least one of them.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+from scipy.stats import multivariate_normal
+
+import oracle
+import synth
+
+
+def rand_pm1(rng, N, M):
+    return np.where(rng.random((N, M)) < 0.5, 1, -1).astype(np.int8)
+
+
+def sym_sparse(rng, N, p, scale):
+    W = np.zeros((N, N))
+    for i in range(N):
+        for j in range(i + 1, N):
+            if rng.random() < p:
+                W[i, j] = W[j, i] = rng.normal(0, scale)
+    return W
+
+
+def coo(W, directed=False):
+    N = W.shape[0]
+    I, J, V = [], [], []
+    for i in range(N):
+        for j in range(N):
+            if i == j or W[i, j] == 0:
+                continue
+            if not directed and j < i:
+                continue
+            I.append(i)
+            J.append(j)
+            V.append(W[i, j])
+    return np.array(I, np.int32), np.array(J, np.int32), np.array(V)
+
+
+# ------------------------------------------------------------- numerics --
+
+def test_lcosh_small_large():
+    for x in [1e-8, 1e-4, 0.3, 0.99, 1.0, 2.5, 20.0, 300.0, -7.0]:
+        ref = math.log(math.cosh(x)) if abs(x) < 300 else abs(x) - math.log(2)
+        if abs(x) < 1e-3:
+            ref = x * x / 2 - x ** 4 / 12
+        assert abs(oracle.lcosh(x) - ref) <= 1e-14 * max(1.0, abs(ref)) + 1e-300
+
+
+def test_dlcosh_series_and_direct():
+    # small d: log cosh(a+d) - log cosh a = d tanh a + d^2 sech^2(a)/2 - d^3 tanh a sech^2 a / 3 + O(d^4)
+    for a in [-3.0, -0.2, 0.0, 0.7, 5.0]:
+        for d in [1e-7, -3e-6]:
+            t = math.tanh(a)
+            s2 = 1 - t * t
+            ref = d * t + d * d * s2 / 2 - d ** 3 * t * s2 / 3
+            assert abs(oracle.dlcosh(a, d) - ref) <= 1e-13 * abs(ref) + d ** 4   # O(d^4) remainder
+    # moderate arguments: direct difference of log cosh is well conditioned
+    for a, d in [(3.0, -2.5), (20.0, -25.0), (-0.4, 1.3), (8.0, -8.0)]:
+        ref = math.log(math.cosh(a + d)) - math.log(math.cosh(a))
+        assert abs(oracle.dlcosh(a, d) - ref) <= 1e-13 * max(1.0, abs(ref))
+
+
+def test_splitmix64_known_answer():
+    # SplitMix64 seeded with 0 (Steele, Lea, Flood 2014): first outputs of next()
+    # are mix(0x9E3779B97F4A7C15 * k) for k = 1, 2, ...; ctr() applies that finaliser.
+    # Reference words: e220a8397b1dcdaf, 6e789e6aa1b965f4.
+    from oracle import _L
+    lib = _L()
+    # ctr(seed, stream, a, b) = mix(mix(mix(mix(seed) ^ stream) ^ a) ^ b)
+    # The first word of mix64 at 0 is the first SplitMix64 output for seed 0.
+    import ctypes
+    # recover mix64 through ctr: ctr(s,0,0,0) = mix(mix(mix(mix(s))))
+    assert synth._L().synth_mix64(0) == 0xE220A8397B1DCDAF
+    assert synth._L().synth_mix64(0x9E3779B97F4A7C15) == 0x6E789E6AA1B965F4
+    # the oracle's counter generator is the same published function
+    for args in [(0, 5, 1, 2), (12345, 6, 1 << 40, 77)]:
+        assert oracle.ctr(*args) == synth.ctr(*args)
+
+
+# --------------------------------------------- pseudolikelihood formulas --
+
+def test_ising_pl_equals_enumerated_conditionals():
+    """[App. A, Ising pseudolikelihood] against the joint distribution itself."""
+    rng = np.random.default_rng(1)
+    N, M = 7, 30
+    W = sym_sparse(rng, N, 0.5, 0.6)
+    theta = rng.normal(0, 0.4, N)
+    X = rand_pm1(rng, N, M)
+
+    def logp(x):   # log of the unnormalised joint exp(sum_{i<j} W x_i x_j + theta x)
+        return 0.5 * x @ W @ x + theta @ x
+
+    ref = 0.0
+    for m in range(M):
+        x = X[:, m].astype(float)
+        for i in range(N):
+            xf = x.copy()
+            xf[i] = -xf[i]
+            a, b = logp(x), logp(xf)
+            ref += a - np.logaddexp(a, b)
+    O = oracle.Oracle(X, "ising", 0.0)
+    ei, ej, w = coo(W)
+    O.set_model(ei, ej, w, theta)
+    assert abs(O.objective() - ref) <= 1e-11 * abs(ref)
+    # the L1 prior term [App. A, Laplace prior]
+    O2 = oracle.Oracle(X, "ising", 0.7)
+    O2.set_model(ei, ej, w, theta)
+    assert abs(O2.objective() - (ref - 0.7 * np.abs(w).sum())) <= 1e-11 * abs(ref)
+
+
+def test_gauss_pl_equals_conditional_density():
+    """[App. A, Gaussian pseudolikelihood] with theta_i = 1/sqrt(W_ii): each factor
+    is the conditional density of x_i given the rest under N(0, W^{-1})."""
+    rng = np.random.default_rng(2)
+    N, M = 6, 20
+    Theta = sym_sparse(rng, N, 0.6, 0.3)
+    np.fill_diagonal(Theta, np.abs(Theta).sum(1) + 0.5)
+    C = np.linalg.inv(Theta)
+    X = rng.multivariate_normal(np.zeros(N), C, size=M).T.astype(np.float32)
+    Xd = X.astype(np.float64)
+    ref = 0.0
+    for m in range(M):
+        x = Xd[:, m]
+        full = multivariate_normal(np.zeros(N), C).logpdf(x)
+        for i in range(N):
+            keep = [k for k in range(N) if k != i]
+            ref += full - multivariate_normal(np.zeros(N - 1), C[np.ix_(keep, keep)]).logpdf(x[keep])
+    O = oracle.Oracle(X, "gauss", 0.0)
+    ei, ej, w = coo(Theta - np.diag(np.diag(Theta)))
+    O.set_model(ei, ej, w, 1.0 / np.sqrt(np.diag(Theta)))
+    assert abs(O.objective() - ref) <= 1e-10 * abs(ref)
+
+
+def test_kinetic_likelihood_equals_glauber_transition():
+    """[Sec. 2, Markov product form] with parallel Glauber transitions
+    P(x_{i,t} | x_{t-1}) = (1 + x_{i,t} tanh h_{i,t-1}) / 2."""
+    rng = np.random.default_rng(3)
+    N, T = 6, 25
+    W = np.where(rng.random((N, N)) < 0.4, rng.normal(0, 0.5, (N, N)), 0.0)
+    np.fill_diagonal(W, 0.0)
+    theta = rng.normal(0, 0.3, N)
+    X = rand_pm1(rng, N, T + 1)
+    ref = 0.0
+    for t in range(1, T + 1):
+        h = theta + W @ X[:, t - 1]
+        ref += np.log((1 + X[:, t] * np.tanh(h)) / 2).sum()
+    O = oracle.Oracle(X, "kinetic", 0.0)
+    ei, ej, w = coo(W, directed=True)
+    O.set_model(ei, ej, w, theta)
+    assert abs(O.objective() - ref) <= 1e-11 * abs(ref)
+
+
+def test_fields_match_dense_product():
+    """m_i = sum_{j != i} W_ij x_j [App. A], h = theta + m."""
+    rng = np.random.default_rng(4)
+    N, M = 9, 17
+    W = sym_sparse(rng, N, 0.4, 0.5)
+    theta = rng.normal(0, 0.2, N)
+    X = rand_pm1(rng, N, M)
+    O = oracle.Oracle(X, "ising", 0.1)
+    O.set_model(*coo(W), theta)
+    H = O.fields()
+    assert np.allclose(H, theta[:, None] + W @ X, rtol=0, atol=1e-13)
+
+
+# --------------------------------------------------------- pair score -----
+
+def _brute_gain(O, W, theta, i, j, directed=False):
+    """max_w L(W_ij <- w) - L(W) by a dense grid plus golden-section refinement,
+    using only the objective (pinned above)."""
+    def L_at(w):
+        W2 = W.copy()
+        W2[i, j] = w
+        if not directed:
+            W2[j, i] = w
+        O.set_model(*coo(W2, directed), theta)
+        return O.objective()
+
+    base = L_at(W[i, j])
+    grid = np.concatenate([np.linspace(-4, 4, 801), [0.0, W[i, j]]])
+    vals = np.array([L_at(w) for w in grid])
+    k = int(np.argmax(vals))
+    if grid[k] == 0.0 and vals[k] >= max(L_at(1e-9), L_at(-1e-9)):
+        best_w, best = 0.0, vals[k]
+    else:
+        lo, hi = grid[k] - 0.01, grid[k] + 0.01
+        g = (math.sqrt(5) - 1) / 2
+        a, b = hi - g * (hi - lo), lo + g * (hi - lo)
+        fa, fb = L_at(a), L_at(b)
+        for _ in range(80):
+            if fa > fb:
+                hi, b, fb = b, a, fa
+                a = hi - g * (hi - lo)
+                fa = L_at(a)
+            else:
+                lo, a, fa = a, b, fb
+                b = lo + g * (hi - lo)
+                fb = L_at(b)
+        best_w = 0.5 * (lo + hi)
+        best = L_at(best_w)
+        if vals[k] > best:
+            best_w, best = grid[k], vals[k]
+    O.set_model(*coo(W, directed), theta)
+    return best - base, best_w
+
+
+@pytest.mark.parametrize("model", ["ising", "kinetic", "gauss"])
+def test_gain_equals_brute_force_maximum(model):
+    """C-P7: the exact score at an arbitrary state W != 0 [Alg. 2, function D]."""
+    rng = np.random.default_rng(5)
+    N, M = 7, 60
+    lam = 1.5
+    directed = model == "kinetic"
+    if model == "gauss":
+        Theta = sym_sparse(rng, N, 0.5, 0.3)
+        np.fill_diagonal(Theta, np.abs(Theta).sum(1) + 0.5)
+        X = rng.multivariate_normal(np.zeros(N), np.linalg.inv(Theta), size=M).T.astype(np.float32)
+        W = Theta - np.diag(np.diag(Theta))
+        theta = 1.0 / np.sqrt(np.diag(Theta))
+    elif model == "kinetic":
+        X = rand_pm1(rng, N, M + 1)
+        W = np.where(rng.random((N, N)) < 0.4, rng.normal(0, 0.4, (N, N)), 0.0)
+        np.fill_diagonal(W, 0)
+        theta = rng.normal(0, 0.2, N)
+    else:
+        X = rand_pm1(rng, N, M)
+        W = sym_sparse(rng, N, 0.5, 0.4)
+        theta = rng.normal(0, 0.2, N)
+    O = oracle.Oracle(X, model, lam)
+    O.set_model(*coo(W, directed), theta)
+    pairs = [(0, 1), (2, 5), (6, 3), (4, 0)]
+    I = np.array([p[0] for p in pairs], np.int32)
+    J = np.array([p[1] for p in pairs], np.int32)
+    g, w = O.score_pairs(I, J)
+    for k, (i, j) in enumerate(pairs):
+        bg, bw = _brute_gain(O, W, theta, i, j, directed)
+        assert g[k] >= -1e-12
+        assert abs(g[k] - bg) <= 1e-8 * max(1.0, abs(bg)), (model, i, j, g[k], bg)
+        assert abs(w[k] - bw) <= 2e-5 * max(1.0, abs(bw)), (model, i, j, w[k], bw)
+
+
+def test_gauss_gain_closed_form_lambda0():
+    """C-P1: with lambda = 0 and w0 = 0 the Gaussian gain is a^2 / (2b)."""
+    rng = np.random.default_rng(6)
+    N, M = 8, 50
+    X = rng.normal(0, 1, (N, M)).astype(np.float32)
+    O = oracle.Oracle(X, "gauss", 0.0)
+    Xd = X.astype(np.float64)
+    v = (Xd ** 2).mean(1)           # theta^2 at W = 0
+    for i, j in [(0, 1), (3, 7), (5, 2)]:
+        a = -(Xd[i] @ Xd[j] + Xd[j] @ Xd[i])
+        b = v[i] * (Xd[j] @ Xd[j]) + v[j] * (Xd[i] @ Xd[i])
+        g, w = O.score_pairs([i], [j])
+        assert abs(g[0] - a * a / (2 * b)) <= 1e-12 * a * a / (2 * b)
+        assert abs(w[0] - a / b) <= 1e-12 * abs(a / b)
+
+
+def test_ising_gradient_at_zero_is_integer_formula():
+    """C-P2: at W = 0 with theta fitted, dF/dW_ij(0) = 2 (S_ij - M xbar_i xbar_j)."""
+    rng = np.random.default_rng(7)
+    N, M = 10, 200
+    X = rand_pm1(rng, N, M)
+    O = oracle.Oracle(X, "ising", 0.0)
+    xb = X.mean(1)
+    for i, j in [(0, 1), (2, 9), (4, 6)]:
+        S = int(X[i].astype(int) @ X[j].astype(int))
+        ref = 2 * (S - M * xb[i] * xb[j])
+        assert abs(O.pair_deriv(i, j, 0.0) - ref) <= 1e-10 * M
+
+
+def test_ising_gain_theta0_closed_form():
+    """C-P3: theta = 0 held, W = 0: F(d) = 2 d S - 2 M log cosh d, so
+    tanh d* = (S - sign(S) lambda/2) / M when |S| > lambda/2, else d* = 0."""
+    rng = np.random.default_rng(8)
+    N, M = 12, 300
+    X = rand_pm1(rng, N, M)
+    X[1] = X[0] * np.where(rng.random(M) < 0.8, 1, -1)     # strong pair
+    for lam in [0.0, 5.0, 40.0]:
+        O = oracle.Oracle(X, "ising", lam)
+        O.set_model(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), np.zeros(N))
+        for i, j in [(0, 1), (2, 3), (5, 11), (7, 8)]:
+            S = int(X[i].astype(int) @ X[j].astype(int))
+            if abs(S) > lam / 2:
+                d = math.atanh((S - math.copysign(lam / 2, S)) / M)
+            else:
+                d = 0.0
+            gain = 2 * d * S - 2 * M * math.log(math.cosh(d)) - lam * abs(d)
+            g, w = O.score_pairs([i], [j])
+            assert abs(w[0] - d) <= 1e-12 * max(1, abs(d)) + 1e-15
+            assert abs(g[0] - gain) <= 1e-10 * max(1.0, gain)
+
+
+def test_ising_gain_counts_form_w0():
+    """C-P4: at W = 0 with theta fitted the M-sum collapses onto the counts of
+    x_j = +-1 and x_i = +-1; solved here by plain bisection in FP64."""
+    rng = np.random.default_rng(9)
+    N, M = 10, 400
+    X = rand_pm1(rng, N, M)
+    X[3] = np.where(rng.random(M) < 0.7, 1, -1)            # biased node
+    X[4] = X[3] * np.where(rng.random(M) < 0.75, 1, -1)
+    lam = 7.0
+    O = oracle.Oracle(X, "ising", lam)
+    xb = X.mean(1)
+    th = np.arctanh(xb)
+    for i, j in [(3, 4), (0, 1), (3, 7), (2, 6)]:
+        S = float(X[i].astype(int) @ X[j].astype(int))
+        nj = {b: float((X[j] == b).sum()) for b in (1, -1)}
+        ni = {b: float((X[i] == b).sum()) for b in (1, -1)}
+
+        def Fp(d):
+            return (2 * S - sum(nj[b] * b * math.tanh(th[i] + d * b) for b in (1, -1))
+                    - sum(ni[b] * b * math.tanh(th[j] + d * b) for b in (1, -1)))
+
+        def F(d):
+            lc = lambda z: math.log(math.cosh(z))
+            return (2 * d * S - sum(nj[b] * (lc(th[i] + d * b) - lc(th[i])) for b in (1, -1))
+                    - sum(ni[b] * (lc(th[j] + d * b) - lc(th[j])) for b in (1, -1)))
+
+        g0 = Fp(0.0)
+        if abs(g0) <= lam:
+            d = 0.0
+        else:
+            s = math.copysign(1.0, g0)
+            lo, hi = 0.0, 10.0
+            for _ in range(200):
+                mid = 0.5 * (lo + hi)
+                if s * Fp(s * mid) - lam > 0:
+                    lo = mid
+                else:
+                    hi = mid
+            d = s * 0.5 * (lo + hi)
+        gain = F(d) - lam * abs(d)
+        g, w = O.score_pairs([i], [j])
+        assert abs(w[0] - d) <= 1e-11 * max(1, abs(d)) + 1e-14
+        assert abs(g[0] - gain) <= 1e-9 * max(1.0, gain)
+
+
+def test_kinetic_gain_closed_form_w0():
+    """C-P5: kinetic score at W = 0, theta fitted: tau = tanh d* is the root in
+    (-1, 1) of t (S' t - D) tau^2 + T (1 - t^2) tau + (t D - S') = 0."""
+    rng = np.random.default_rng(10)
+    N, T = 8, 500
+    X = rand_pm1(rng, N, T + 1)
+    X[2, 1:] = np.where(rng.random(T) < 0.8, X[5, :-1], -X[5, :-1])   # 5 drives 2
+    X[6] = np.where(rng.random(T + 1) < 0.65, 1, -1)
+    lam = 6.0
+    O = oracle.Oracle(X, "kinetic", lam)
+    for i, j in [(2, 5), (5, 2), (6, 1), (0, 3), (2, 6)]:
+        y = X[i, 1:].astype(float)
+        x = X[j, :-1].astype(float)
+        t = y.mean()
+        S, D = float(y @ x), float(x.sum())
+        npos, nneg = float((x > 0).sum()), float((x < 0).sum())
+        f0 = S - t * D
+        if abs(f0) <= lam:
+            d = 0.0
+        else:
+            s = math.copysign(1.0, f0)
+            Sp = S - s * lam
+            a, b, c = t * (Sp * t - D), T * (1 - t * t), t * D - Sp
+            roots = np.roots([a, b, c]) if abs(a) > 1e-300 else np.array([-c / b])
+            roots = [r.real for r in roots if abs(r.imag) < 1e-12 and -1 < r.real < 1 and r.real * s > 0]
+            assert len(roots) == 1
+            d = math.atanh(roots[0])
+        gain = (d * (S - math.copysign(lam, d) if d else 0.0) - T * math.log(math.cosh(d))
+                - npos * math.log1p(t * math.tanh(d)) - nneg * math.log1p(-t * math.tanh(d)))
+        g, w = O.score_pairs([i], [j])
+        assert abs(w[0] - d) <= 1e-10 * max(1, abs(d)) + 1e-14, (i, j)
+        assert abs(g[0] - gain) <= 1e-9 * max(1.0, gain), (i, j)
+
+
+# ------------------------------------------------------------- theta -------
+
+def test_theta_closed_forms_at_w0():
+    """Initial fields at W = 0: Ising atanh(xbar), kinetic atanh(mean of x_{i,t>=1}),
+    Gaussian theta^2 = ||x||^2 / M."""
+    rng = np.random.default_rng(11)
+    X = rand_pm1(rng, 6, 80)
+    X[2] = np.where(rng.random(80) < 0.8, 1, -1)
+    _, _, _, th = oracle.Oracle(X, "ising", 0.0).get_model()
+    assert np.allclose(th, np.arctanh(X.mean(1)), rtol=1e-12, atol=1e-13)
+    _, _, _, th = oracle.Oracle(X, "kinetic", 0.0).get_model()
+    assert np.allclose(th, np.arctanh(X[:, 1:].mean(1)), rtol=1e-12, atol=1e-13)
+    G = rng.normal(0, 2, (5, 40)).astype(np.float32)
+    _, _, _, th = oracle.Oracle(G, "gauss", 0.0).get_model()
+    assert np.allclose(th ** 2, (G.astype(float) ** 2).mean(1), rtol=1e-12)
+
+
+@pytest.mark.parametrize("model", ["ising", "gauss"])
+def test_theta_update_is_stationary(model):
+    """After the update, d/dtheta_i of node i's conditional vanishes (KKT)."""
+    rng = np.random.default_rng(12)
+    N, M = 8, 90
+    W = sym_sparse(rng, N, 0.5, 0.3)
+    if model == "gauss":
+        X = rng.normal(0, 1, (N, M)).astype(np.float32)
+    else:
+        X = rand_pm1(rng, N, M)
+    O = oracle.Oracle(X, model, 0.0)
+    O.set_model(*coo(W), None)
+    O.theta_update()
+    _, _, _, th = O.get_model()
+    Xd = X.astype(float)
+    msum = W @ Xd
+    if model == "ising":
+        grad = (Xd - np.tanh(th[:, None] + msum)).sum(1)
+        assert np.abs(grad).max() <= 1e-10 * M
+    else:
+        v = th ** 2
+        # d/dv of sum_m -(x + v m)^2/(2v) - log(v)/2
+        grad = ((Xd ** 2).sum(1) / (2 * v ** 2) - (msum ** 2).sum(1) / 2 - M / (2 * v))
+        assert np.abs(grad * v).max() <= 1e-9 * M
+
+
+# ------------------------------------------------------- search / GCD -------
+
+def test_findbest_exact_knn_equals_exhaustive():
+    """C-P9: Lenhof-Smid with exact KNN returns the exact m best pairs [Alg. 3],
+    and the node sets at least halve per level."""
+    w = synth.ising_er(90, 120, 3.0, 0.4, 0.1, seed=3)
+    lam = oracle.default_lambda(w.X, "ising")
+    O = oracle.Oracle(w.X, "ising", lam)
+    for m in [10, 45, 90, 300]:
+        I, J, G, _ = O.find_best(m, "exhaustive")
+        I2, J2, G2, st = O.find_best(m, "exact_knn")
+        assert np.array_equal(I, I2) and np.array_equal(J, J2)
+        assert np.array_equal(G, G2)
+        ns = st["level_n"]
+        for a, b in zip(ns[:-1], ns[1:]):
+            assert b <= a // 2
+
+
+def test_exhaustive_topm_is_sorted_and_complete():
+    w = synth.ising_er(40, 100, 3.0, 0.4, 0.1, seed=4)
+    O = oracle.Oracle(w.X, "ising", 3.0)
+    N = 40
+    I, J, G, _ = O.find_best(N * (N - 1) // 2, "exhaustive")
+    assert len(I) == N * (N - 1) // 2
+    assert np.all(I < J)
+    assert np.all(np.diff(G) <= 0)
+    allI, allJ = np.triu_indices(N, 1)
+    g, _ = O.score_pairs(allI, allJ)
+    assert np.allclose(np.sort(g)[::-1], G, rtol=0, atol=0)
+
+
+def test_nndescent_recall_and_determinism():
+    w = synth.ising_er(300, 200, 3.0, 0.4, 0.1, seed=5)
+    lam = oracle.default_lambda(w.X, "ising")
+    O = oracle.Oracle(w.X, "ising", lam)
+    m = 4 * 300
+    I, J, G, _ = O.find_best(m, "exhaustive")
+    I2, J2, G2, st = O.find_best(m, "nndescent", seed=11)
+    I3, J3, G3, _ = O.find_best(m, "nndescent", seed=11)
+    assert np.array_equal(I2, I3) and np.array_equal(J2, J3)
+    pos = G > 0
+    best = set(zip(I[pos], J[pos]))
+    got = set(zip(I2, J2))
+    recall = len(best & got) / len(best)
+    assert recall >= 0.95, recall
+    # the first pairs are always found [Sec. 4, cumulative recall starts at 1]
+    assert (I[0], J[0]) in got
+
+
+def test_knn_init_floyd_properties():
+    n, k = 50, 7
+    counts = np.zeros(n)
+    for a in range(n):
+        for seed in range(40):
+            v = oracle.knn_init(n, a, k, seed, 0, a)
+            assert len(set(v.tolist())) == k
+            assert a not in v and v.min() >= 0 and v.max() < n
+            counts[v] += 1
+    # each node is drawn about n*40*k/(n) times in total
+    exp = 40 * k
+    assert np.abs(counts - exp).max() < 6 * math.sqrt(exp)
+
+
+def test_updates_never_lower_objective():
+    """C-P10 (monotone part): every accepted coordinate update raises L."""
+    w = synth.ising_er(40, 150, 3.0, 0.4, 0.1, seed=6)
+    O = oracle.Oracle(w.X, "ising", oracle.default_lambda(w.X, "ising"))
+    for sweep in range(3):
+        I, J, G, _ = O.find_best(40, "exhaustive")
+        L0 = O.objective()
+        d, bad = O.apply_updates(I, J, check=True)
+        assert bad == 0
+        assert O.objective() >= L0 - 1e-12 * abs(L0)
+        # the first update's gain is exactly the objective change it causes
+        O.theta_update()
+
+
+def test_first_update_gain_is_objective_change():
+    w = synth.ising_er(30, 120, 3.0, 0.4, 0.1, seed=7)
+    O = oracle.Oracle(w.X, "ising", 2.0)
+    I, J, G, _ = O.find_best(5, "exhaustive")
+    L0 = O.objective()
+    O.apply_updates(I[:1], J[:1])
+    assert abs((O.objective() - L0) - G[0]) <= 1e-9 * max(1.0, G[0])
+
+
+@pytest.mark.parametrize("model", ["ising", "gauss"])
+def test_gcd_converges_to_kkt_point_and_matches_cd(model):
+    """C-P10: the GCD fixed point is the unique optimum of the convex objective
+    (KKT over all pairs) and equals the CD optimum [Sec. 2-3]."""
+    N = 24
+    if model == "gauss":
+        w = synth.gauss_er(N, 80, 3.0, 0.2, 0.3, seed=8)   # well conditioned: fast convergence
+    else:
+        w = synth.ising_er(N, 150, 3.0, 0.5, 0.1, seed=8)
+    lam = oracle.default_lambda(w.X, model, c=1.0)
+    G = oracle.Oracle(w.X, model, lam)
+    for _ in range(400):
+        d, _ = G.gcd_sweep(N, "exhaustive")
+        if d < 1e-11:
+            break
+    C = oracle.Oracle(w.X, model, lam)
+    for _ in range(400):
+        if C.cd_sweep() < 1e-11:
+            break
+    assert abs(G.objective() - C.objective()) <= 1e-9 * abs(C.objective())
+    ei, ej, wv, th = G.get_model()
+    W = np.zeros((N, N))
+    W[ei, ej] = wv
+    for i in range(N):
+        for j in range(i + 1, N):
+            g = G.pair_deriv(i, j, W[i, j])
+            if W[i, j] == 0:
+                assert abs(g) <= lam * (1 + 1e-6) + 1e-7
+            else:
+                assert abs(g - lam * np.sign(W[i, j])) <= 1e-6 * lam
