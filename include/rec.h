@@ -1,0 +1,192 @@
+/*
+ * rec.h -- C ABI of the MI355X (gfx950) library for greedy coordinate descent
+ * (GCD) network reconstruction, after T. P. Peixoto, "Scalable network
+ * reconstruction in subquadratic time", arXiv 2401.01404.
+ *
+ * Problem [Sec. 2]: data X, an N x M matrix of M samples (or a Markov time
+ * series) of N nodes; unknown weights W (N x N, symmetric for the Ising and
+ * Gaussian models, directed for the kinetic Ising model) and node parameters
+ * theta; objective pi(W) = log pseudolikelihood [App. A] minus an L1
+ * (Laplace) penalty lambda * sum |W_ij| [App. A], maximised by GCD
+ * [Alg. 2] whose candidate search is FindBest [Alg. 3] over NNDescent
+ * [Alg. 4].  The score of a pair is the gain
+ *     gain(i,j) = max_w pi(W with W_ij = w) - pi(W)  >= 0,
+ * the negative of the paper's distance d(i,j) = -max_{W_ij} pi(W) up to the
+ * constant pi(W) [Alg. 2, function D].
+ *
+ * Conventions shared by every call:
+ *   - Every call returns rec_status; nothing throws across the ABI.
+ *   - Pointers named *_dev are device pointers (HIP global memory); *_host are
+ *     host pointers.  A call with a *_host output synchronises the context's
+ *     stream before it returns; all other work is queued on that stream.
+ *   - The caller owns X, the workspace and every output buffer; they must stay
+ *     valid until the queued work has finished.  The library allocates no
+ *     device memory: all of its state lives in the caller's workspace.
+ *   - Node indices are int32 in [0, N).  Symmetric models treat (i,j) and
+ *     (j,i) as one coordinate; the kinetic model's pair (i,j) is the ordered
+ *     coupling W_ij of source j on target i.
+ *   - A context is not thread safe; calls on one context must be serialised.
+ *   - Invalid arguments return REC_E_INVAL and change nothing.  A failure in
+ *     the middle of a sweep leaves the context in REC_E_STATE until
+ *     rec_set_model() restores a consistent model.  rec_last_error() gives a
+ *     per-context message for the last failure.
+ */
+#ifndef REC_H
+#define REC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rec_ctx rec_ctx;
+
+typedef enum {
+  REC_OK = 0,
+  REC_E_INVAL = -1,     /* bad argument (null pointer, index out of range, size) */
+  REC_E_NOMEM = -2,     /* workspace too small for the request                   */
+  REC_E_HIP = -3,       /* a HIP runtime call failed                             */
+  REC_E_NUMERIC = -4,   /* non-finite value in data or result                    */
+  REC_E_STATE = -5      /* context poisoned by an earlier failure                */
+} rec_status;
+
+/* Generative model of the data [App. A; Sec. 2 Markov product form]. */
+typedef enum {
+  REC_ISING = 0,        /* +-1 samples, symmetric W, pseudolikelihood prod_i e^{x_i h_i}/2cosh h_i */
+  REC_GAUSS = 1,        /* real samples, symmetric W, Gaussian pseudolikelihood, theta_i = 1/sqrt(W_ii) */
+  REC_KINETIC = 2       /* +-1 time series x_0..x_M, directed W, P(x_t | x_{t-1}) */
+} rec_model;
+
+typedef enum { REC_FP64 = 0, REC_FP32 = 1 } rec_prec;   /* arithmetic of fields and scores */
+typedef enum { REC_X_INT8 = 0, REC_X_FP32 = 1 } rec_xtype;
+
+typedef enum {
+  REC_SEARCH_NNDESCENT = 0,   /* FindBest [Alg. 3] over NNDescent [Alg. 4]      */
+  REC_SEARCH_EXHAUSTIVE = 1,  /* all pairs scored exactly, best m kept         */
+  REC_SEARCH_EXACT_KNN = 2    /* FindBest [Alg. 3] over exhaustive KNN lists    */
+} rec_search;
+
+typedef struct {
+  int32_t model;          /* rec_model                                                  */
+  int32_t xtype;          /* rec_xtype: REC_X_INT8 (+-1) for Ising/kinetic, REC_X_FP32 for Gauss */
+  int32_t prec;           /* rec_prec                                                   */
+  int32_t knn_k_override; /* 0: k = ceil(4m/|S|) [Alg. 3]; >0: fixed k at every level   */
+  int64_t N;              /* nodes, 2 <= N <= 2^20                                       */
+  int64_t M;              /* samples (kinetic: transitions; X then has M+1 columns)      */
+  int64_t ldx;            /* row stride of X in elements (node-major: X[i*ldx + m])      */
+  double lambda;          /* L1 penalty, >= 0, in units of the summed log-likelihood     */
+  double kappa;           /* greediness: m = round-half-up(kappa * N), at least 1 [Alg. 2] */
+  double nnd_eps;         /* NNDescent stop: changes / (k |S|) < nnd_eps [Alg. 4]        */
+  int32_t nnd_max_iter;   /* 0: 2 ceil(log_{2k} |S|) + 10                                */
+  int32_t reserved0;
+  uint64_t seed;          /* seed of the NNDescent initial lists and in-neighbour caps  */
+  int64_t max_nnz;        /* capacity for nonzero W entries (0: 64 * N)                  */
+  int32_t log2_cache;     /* score cache slots = 2^log2_cache (0: chosen from N)         */
+  int32_t reserved1;
+} rec_config;
+
+typedef struct {
+  double objective;       /* log pi(W) after the sweep (FP64 sum)                    */
+  double delta;           /* sum |W'_ij - W_ij| over the sweep's updates [Alg. 2]    */
+  int64_t accepted;       /* pairs of E_best whose weight changed                     */
+  int64_t n_best;         /* |E_best|                                                 */
+  int64_t pair_evals;     /* exact pair scores computed (cache hits not counted)      */
+  int64_t nnd_iters;      /* NNDescent iterations summed over FindBest levels         */
+  int64_t levels;         /* FindBest recursion levels                                */
+  int64_t rounds;         /* node-disjoint update rounds                               */
+  double t_search_ms;     /* wall time of FindBest                                     */
+  double t_update_ms;     /* wall time of the coordinate updates                       */
+  double t_theta_ms;      /* wall time of theta update, field refresh and objective    */
+} rec_sweep_stats;
+
+/* Bytes of workspace the library needs for cfg.  Host-only; no device work. */
+rec_status rec_workspace_size(const rec_config* cfg, size_t* bytes);
+
+/* Create a context on the current HIP device.  X_dev: node-major data
+ * (int8 +-1 or float32, see cfg->xtype) with row stride cfg->ldx; it is copied
+ * into the workspace (padded layout), so X_dev may be freed after the call.
+ * ws_dev: at least rec_workspace_size() bytes, 256-byte aligned.
+ * stream: the hipStream_t to queue all work on (NULL = default stream).
+ * Fits theta at W = 0 (the W = 0 optimum of every node's conditional).
+ * Synchronises the stream.  REC_E_NUMERIC if X holds a value other than +-1
+ * (int8 models) or a non-finite value (float32). */
+rec_status rec_create(const rec_config* cfg, const void* X_dev, void* ws_dev, size_t ws_bytes,
+                      void* stream, rec_ctx** out);
+
+rec_status rec_destroy(rec_ctx* ctx);
+
+/* Exact scores of P pairs at the current state [Alg. 2, function D]:
+ * gain_dev[p] = max_w pi(W_{i_p j_p} <- w) - pi(W), wopt_dev[p] = its argmax.
+ * i_dev, j_dev: P int32 indices; gain_dev, wopt_dev: P doubles (wopt_dev may
+ * be NULL).  FP64 mode computes everything in double; FP32 mode computes the
+ * per-sample terms in float with FP64 sums.  Synchronises the stream at the end
+ * to report invalid pairs (REC_E_INVAL: any index outside [0,N) or i == j;
+ * such pairs get gain NaN). */
+rec_status rec_score_pairs(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
+                           double* gain_dev, double* wopt_dev);
+
+/* The m best pairs at the current state [Alg. 3 when s is a FindBest search].
+ * Writes up to m pairs best first (gain desc, then min(i,j), max(i,j)) into
+ * i_dev/j_dev/gain_dev (capacity m each) and their count into *n_out_host.
+ * stats_host may be NULL; if given, its search fields are filled.  Synchronises. */
+rec_status rec_find_best(rec_ctx* ctx, int64_t m, int32_t search, int32_t* i_dev, int32_t* j_dev,
+                         double* gain_dev, int64_t* n_out_host, rec_sweep_stats* stats_host);
+
+/* One GCD iteration [Alg. 2]: E_best = FindBest(m = round(kappa N)); every
+ * pair of E_best updated to its argmax in rank order (run as node-disjoint
+ * rounds, which equals the sequential order); then theta refitted for all
+ * nodes, fields rebuilt from W and the objective evaluated.  Synchronises. */
+rec_status rec_gcd_sweep(rec_ctx* ctx, int32_t search, rec_sweep_stats* stats_host);
+
+/* Apply coordinate updates to the given P pairs in the given order
+ * [Alg. 2 loop body]: each W_ij set to its argmax with the current state.
+ * Writes Delta = sum |W' - W| to *delta_host.  Synchronises. */
+rec_status rec_apply_updates(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
+                             double* delta_host);
+
+/* Refit theta for all nodes, rebuild fields from W and return log pi(W)
+ * [App. A].  Synchronises. */
+rec_status rec_theta_update(rec_ctx* ctx, double* objective_host);
+
+/* log pi(W) at the current state (FP64 sum).  Synchronises. */
+rec_status rec_objective(rec_ctx* ctx, double* objective_host);
+
+/* Export the model: nonzero W entries (symmetric: i < j) into ei/ej/w
+ * (capacity cap) and theta (N doubles, may be NULL).  *nnz_host receives the
+ * number of nonzero entries (which may exceed cap).  Synchronises. */
+rec_status rec_get_model(rec_ctx* ctx, int64_t cap, int32_t* ei_dev, int32_t* ej_dev,
+                         double* w_dev, double* theta_dev, int64_t* nnz_host);
+
+/* Replace the model (W entries and theta; theta_dev NULL keeps theta) and
+ * rebuild the fields.  Clears REC_E_STATE.  Synchronises. */
+rec_status rec_set_model(rec_ctx* ctx, int64_t nnz, const int32_t* ei_dev, const int32_t* ej_dev,
+                         const double* w_dev, const double* theta_dev);
+
+/* Fields in the working precision, converted to double: h = theta + sum_j W_ij x_j
+ * (Gaussian: residual x_i + theta_i^2 sum_j W_ij x_j), N x M row-major. */
+rec_status rec_get_fields(rec_ctx* ctx, double* H_dev);
+
+/* KNN lists of FindKNN [Alg. 4] (mode REC_SEARCH_NNDESCENT) or exact KNN
+ * (REC_SEARCH_EXACT_KNN) over the node subset S (n sorted indices) at
+ * FindBest level `level`: writes n*k neighbour indices and gains, best first
+ * per node; *iters_host gets the NNDescent iteration count.  Synchronises. */
+rec_status rec_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int32_t k, int32_t level,
+                   int32_t mode, int32_t* nbr_dev, double* gain_dev, int32_t* iters_host);
+
+/* Instrumentation: when on, every launch of the pair-score kernel is
+ * bracketed by HIP events on the context's stream.  rec_kernel_time returns
+ * the summed kernel time (ms), the number of launches and the pairs they
+ * scored since timing was switched on (synchronises), then resets them. */
+rec_status rec_set_timing(rec_ctx* ctx, int32_t on);
+rec_status rec_kernel_time(rec_ctx* ctx, double* score_ms_host, int64_t* launches_host,
+                           int64_t* pairs_host);
+
+const char* rec_status_str(rec_status s);
+const char* rec_last_error(const rec_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* REC_H */

@@ -99,8 +99,11 @@ class Oracle:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
-            _L().orc_destroy(h)
+        if h and _lib is not None:
+            try:
+                _lib.orc_destroy(h)
+            except Exception:
+                pass
             self.h = None
 
     # --- state ---------------------------------------------------------

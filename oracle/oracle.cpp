@@ -36,8 +36,8 @@
 //      counters; one iteration replaces every list at once by the top-k of
 //      (old list + second neighbours), the order-independent form of the
 //      per-node update; U(j) = out(j) + at most k in-neighbours of j, those
-//      with the smallest counter hash; stop when changes/(k|S|) < eps or at
-//      2 ceil(log_{2k}|S|) + 10 iterations.
+//      with the smallest (32-bit counter hash, index); stop when
+//      changes/(k|S|) < eps or at 2 ceil(log_{2k}|S|) + 10 iterations.
 //   R6 theta is refitted for every node after each sweep's W updates; its
 //      initial value is the W = 0 optimum; it is clamped to [-8, 8].
 //   R7 kinetic Ising: P(x_t | x_{t-1}) = prod_i exp(x_{i,t} h_{i,t-1}) /
@@ -453,7 +453,7 @@ std::vector<std::vector<Nb>> knn_nndescent(const Problem& P, const std::vector<i
       for (auto& e : G[a]) {
         int64_t b = loc[e.j];
         uint64_t h = ctr(seed, STREAM_CAP, ((uint64_t)level << 32) | (uint32_t)it,
-                         ((uint64_t)(uint32_t)S[a] << 32) | (uint32_t)e.j);
+                         ((uint64_t)(uint32_t)S[a] << 32) | (uint32_t)e.j) >> 32;
         in[b].push_back({h, (int)a});
       }
     std::vector<std::vector<int>> U(n);

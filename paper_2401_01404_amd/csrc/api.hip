@@ -1,0 +1,501 @@
+// C ABI of the library: context set-up, workspace layout and the entry points
+// declared in include/rec.h.  Host code only; every step of the method runs in
+// the kernels of score.hip, fields.hip, sort.hip and search.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+#include "ctx.hpp"
+
+namespace {
+
+inline int64_t pow2_at_least(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+inline double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Sizes {
+  int npl;
+  int64_t Mp, m, mcap, max_nnz, wcap, list_cap, cand_cap, ccap, pool_cap, pcap, dcap, sort_cap,
+      best_cap, ex_cap;
+};
+
+rec_status plan(const rec_config* c, Sizes* z, const char** why) {
+  if (c->N < 2 || c->N > (int64_t(1) << 20)) { *why = "N must be in [2, 2^20]"; return REC_E_INVAL; }
+  if (c->M < 1 || c->M > 2048) { *why = "M must be in [1, 2048]"; return REC_E_INVAL; }
+  if (c->model < 0 || c->model > 2) { *why = "unknown model"; return REC_E_INVAL; }
+  if ((c->model == REC_GAUSS) != (c->xtype == REC_X_FP32)) {
+    *why = "Gaussian model needs float32 data, Ising/kinetic need int8 +-1";
+    return REC_E_INVAL;
+  }
+  if (c->prec != REC_FP32 && c->prec != REC_FP64) { *why = "unknown precision"; return REC_E_INVAL; }
+  int64_t cols = c->model == REC_KINETIC ? c->M + 1 : c->M;
+  if (c->ldx < cols) { *why = "ldx smaller than the number of columns"; return REC_E_INVAL; }
+  if (!(c->lambda >= 0) || !std::isfinite(c->lambda)) { *why = "lambda must be finite and >= 0"; return REC_E_INVAL; }
+  if (!(c->kappa > 0) || !std::isfinite(c->kappa)) { *why = "kappa must be > 0"; return REC_E_INVAL; }
+  const int64_t N = c->N;
+  int npl = 1;
+  while (64 * npl < c->M) npl *= 2;
+  z->npl = npl;
+  z->Mp = 64 * (int64_t)npl;
+  z->m = std::max<int64_t>(1, (int64_t)std::floor(c->kappa * (double)N + 0.5));
+  const int64_t pairs = N * (N - 1) / (c->model == REC_KINETIC ? 1 : 2);
+  z->mcap = std::min<int64_t>(pairs, std::max<int64_t>(4 * z->m, 4096));
+  z->max_nnz = c->max_nnz > 0 ? c->max_nnz : 64 * N;
+  z->wcap = pow2_at_least(2 * z->max_nnz);
+  int64_t k0 = std::max<int64_t>(1, std::min<int64_t>((4 * z->mcap + N - 1) / N, N - 1));
+  if (c->knn_k_override > 0) k0 = std::min<int64_t>(c->knn_k_override, N - 1);
+  z->list_cap = std::max<int64_t>(4 * z->mcap + N, N * k0) + 1024;
+  int64_t want = N * std::min<int64_t>(4 * k0 * k0, N - 1);
+  want = std::max(want, 2 * z->mcap + N);
+  z->cand_cap = std::min<int64_t>(std::max<int64_t>(want, 1 << 16), int64_t(1) << 26);
+  int lc = c->log2_cache;
+  if (lc <= 0) {
+    int64_t target = std::min<int64_t>(4 * z->cand_cap, 2 * pairs + 1024);
+    lc = 16;
+    while ((int64_t(1) << lc) < target && lc < 30) ++lc;
+  }
+  if (lc < 10 || lc > 31) { *why = "log2_cache must be in [10, 31]"; return REC_E_INVAL; }
+  z->ccap = int64_t(1) << lc;
+  int levels_max = 2;
+  for (int64_t v = 1; v < N; v <<= 1) ++levels_max;
+  z->pool_cap = 2 * z->mcap * (levels_max + 1) + 1024;
+  z->pcap = pow2_at_least(2 * z->pool_cap);
+  z->dcap = pow2_at_least(8 * z->mcap + 1024);
+  z->ex_cap = std::min<int64_t>(z->cand_cap, int64_t(1) << 24);
+  z->sort_cap = std::max({2 * z->max_nnz, z->list_cap, z->pool_cap, z->ex_cap + z->mcap}) + 1024;
+  z->best_cap = std::max<int64_t>(z->mcap, 1024);
+  return REC_OK;
+}
+
+// Carve the workspace; with a.base == nullptr only the size is computed.
+void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
+  const int64_t N = c->N;
+  const size_t rs = c->prec == REC_FP32 ? 4 : 8;
+  const int64_t nsz = N * z.Mp;
+  Fields& F = x->F;
+  F.xs = a.take<int8_t>(nsz);
+  F.ys = c->model == REC_KINETIC ? a.take<int8_t>(nsz) : F.xs;
+  F.xf = c->model == REC_GAUSS ? a.take<float>(nsz) : nullptr;
+  F.H = a.take<char>(nsz * rs);
+  F.T = c->model == REC_GAUSS ? nullptr : (void*)a.take<char>(nsz * rs);
+  F.sq = a.take<double>(N);
+  F.theta = a.take<double>(N);
+  x->W.keys = a.take<uint64_t>(z.wcap);
+  x->W.vals = a.take<double>(z.wcap);
+  x->W.mask = (uint64_t)(z.wcap - 1);
+  x->W.count = a.take<int64_t>(1);
+  x->row_off = a.take<int64_t>(N + 1);
+  x->col = a.take<int32_t>(2 * z.max_nnz);
+  x->colw = a.take<double>(2 * z.max_nnz);
+  x->wi = a.take<int32_t>(z.max_nnz);
+  x->wj = a.take<int32_t>(z.max_nnz);
+  x->wv = a.take<double>(z.max_nnz);
+  x->counter = a.take<int64_t>(16);
+  x->dscratch = a.take<double>(std::max<int64_t>(N, 1024));
+  x->dresult = a.take<double>(16);
+  x->err_flag = a.take<int32_t>(4);
+  for (int b = 0; b < 2; ++b) {
+    x->sb.khi[b] = a.take<uint64_t>(z.sort_cap);
+    x->sb.klo[b] = a.take<uint64_t>(z.sort_cap);
+    x->sb.val[b] = a.take<uint32_t>(z.sort_cap);
+  }
+  x->sb.hist = a.take<uint32_t>(256 * ((z.sort_cap + 4095) / 4096 + 1));
+  x->sb.cap = z.sort_cap;
+  x->C.keys = a.take<uint64_t>(z.ccap);
+  x->C.vals = a.take<double>(z.ccap);
+  x->C.mask = (uint64_t)(z.ccap - 1);
+  x->C.ovf = a.take<double>(z.cand_cap);
+  x->C.ovf_cap = z.cand_cap;
+  x->list_cap = z.list_cap;
+  x->Gidx = a.take<int32_t>(z.list_cap);
+  x->Gidx2 = a.take<int32_t>(z.list_cap);
+  x->Ggain = a.take<double>(z.list_cap);
+  x->Ggain2 = a.take<double>(z.list_cap);
+  x->S = a.take<int32_t>(N);
+  x->S2 = a.take<int32_t>(N);
+  x->loc = nullptr;
+  x->cnt = a.take<int64_t>(N + 2);
+  x->off = a.take<int64_t>(N + 2);
+  x->cand_cap = z.cand_cap;
+  x->cand_v = a.take<int32_t>(z.cand_cap);
+  x->cand_slot = a.take<uint32_t>(z.cand_cap);
+  x->ts_i = a.take<int32_t>(z.cand_cap);
+  x->ts_j = a.take<int32_t>(z.cand_cap);
+  x->ts_slot = a.take<uint32_t>(z.cand_cap);
+  x->inoff = a.take<int64_t>(N + 2);
+  x->in_src = a.take<int32_t>(z.list_cap);
+  x->dset_keys = a.take<uint64_t>(z.dcap);
+  x->dset_mask = (uint64_t)(z.dcap - 1);
+  x->pset_keys = a.take<uint64_t>(z.pcap);
+  x->pset_mask = (uint64_t)(z.pcap - 1);
+  x->pool_cap = z.pool_cap;
+  x->pool_hi = a.take<uint64_t>(z.pool_cap);
+  x->pool_lo = a.take<uint64_t>(z.pool_cap);
+  x->scan_tmp = a.take<int64_t>(2 * N + 4096);
+  x->best_cap = z.best_cap;
+  x->best_i = a.take<int32_t>(z.best_cap);
+  x->best_j = a.take<int32_t>(z.best_cap);
+  x->best_g = a.take<double>(z.best_cap);
+  x->first = a.take<int32_t>(N);
+  x->done = a.take<uint8_t>(z.best_cap);
+  x->dw = a.take<double>(z.best_cap);
+  x->ex_cap = z.ex_cap;
+  x->max_nnz = z.max_nnz;
+}
+
+__global__ void k_check_pairs(const int32_t* I, const int32_t* J, int64_t P, int64_t N, int32_t* err) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  int i = I[p], j = J[p];
+  if (i < 0 || j < 0 || i >= N || j >= N || i == j) atomicOr(err, 1);
+}
+
+// S strictly increasing and inside [0, N)
+__global__ void k_check_set(const int32_t* S, int64_t n, int64_t N, int32_t* err) {
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  if (S[a] < 0 || S[a] >= N || (a > 0 && S[a - 1] >= S[a])) atomicOr(err, 1);
+}
+
+template <class R>
+__global__ void k_fields_out(const R* H, int64_t N, int64_t M, int64_t Mp, double* out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * M) return;
+  int64_t i = e / M, s = e % M;
+  out[e] = (double)H[i * Mp + s];
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+
+rec_status fail(rec_ctx* ctx, rec_status s, const char* msg) {
+  if (ctx && msg) ctx->err = msg;
+  return s;
+}
+
+rec_status read_err(rec_ctx* ctx, int32_t* e) {
+  REC_HIP(hipMemcpyAsync(e, ctx->err_flag, 4, hipMemcpyDeviceToHost, ctx->stream));
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  return REC_OK;
+}
+
+rec_status clear_err(rec_ctx* ctx) {
+  REC_HIP(hipMemsetAsync(ctx->err_flag, 0, 4, ctx->stream));
+  return REC_OK;
+}
+
+#define REC_TRY(expr)                       \
+  do {                                      \
+    rec_status s_ = (expr);                 \
+    if (s_ != REC_OK) return s_;            \
+  } while (0)
+
+#define REC_CHECK_CTX(ctx)                                                    \
+  do {                                                                        \
+    if (!(ctx)) return REC_E_INVAL;                                           \
+    if ((ctx)->state != REC_OK) return fail(ctx, REC_E_STATE, "context poisoned by an earlier failure; call rec_set_model"); \
+  } while (0)
+
+// refresh fields from W with the current theta, refit theta, evaluate
+rec_status refresh(rec_ctx* ctx, double* obj) {
+  REC_TRY(rec_rebuild_fields(ctx));
+  REC_TRY(rec_fit_theta(ctx));
+  return rec_eval_objective(ctx, obj);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rec_status_str(rec_status s) {
+  switch (s) {
+    case REC_OK: return "ok";
+    case REC_E_INVAL: return "invalid argument";
+    case REC_E_NOMEM: return "workspace too small";
+    case REC_E_HIP: return "HIP runtime error";
+    case REC_E_NUMERIC: return "numeric error";
+    case REC_E_STATE: return "context in failed state";
+  }
+  return "unknown status";
+}
+
+const char* rec_last_error(const rec_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+rec_status rec_workspace_size(const rec_config* cfg, size_t* bytes) {
+  if (!cfg || !bytes) return REC_E_INVAL;
+  Sizes z;
+  const char* why = nullptr;
+  rec_status s = plan(cfg, &z, &why);
+  if (s != REC_OK) return s;
+  rec_ctx tmp;
+  tmp.cfg = *cfg;
+  Arena a;
+  a.base = nullptr;
+  a.size = 0;
+  layout(&tmp, cfg, z, a);
+  *bytes = a.used + 256;
+  return REC_OK;
+}
+
+rec_status rec_create(const rec_config* cfg, const void* X_dev, void* ws_dev, size_t ws_bytes,
+                      void* stream, rec_ctx** out) {
+  if (!cfg || !X_dev || !ws_dev || !out) return REC_E_INVAL;
+  *out = nullptr;
+  Sizes z;
+  const char* why = nullptr;
+  rec_status s = plan(cfg, &z, &why);
+  if (s != REC_OK) return s;
+  rec_ctx* ctx = new (std::nothrow) rec_ctx();
+  if (!ctx) return REC_E_NOMEM;
+  ctx->cfg = *cfg;
+  if (ctx->cfg.nnd_eps <= 0) ctx->cfg.nnd_eps = 1e-3;
+  ctx->stream = (hipStream_t)stream;
+  ctx->fp32 = cfg->prec == REC_FP32;
+  ctx->m_default = z.m;
+  if (hipGetDevice(&ctx->dev) != hipSuccess) { delete ctx; return REC_E_HIP; }
+  Arena a;
+  a.base = (char*)(((uintptr_t)ws_dev + 255) & ~uintptr_t(255));
+  a.size = ws_bytes - (size_t)(a.base - (char*)ws_dev);
+  layout(ctx, cfg, z, a);
+  if (a.used > a.size) { delete ctx; return REC_E_NOMEM; }
+  Fields& F = ctx->F;
+  F.N = cfg->N;
+  F.M = cfg->M;
+  F.Mp = z.Mp;
+  F.npl = z.npl;
+  F.model = cfg->model;
+  auto bad = [&](rec_status st) { delete ctx; return st; };
+  if (hipMemsetAsync(ctx->err_flag, 0, 16, ctx->stream) != hipSuccess) return bad(REC_E_HIP);
+  if (hipMemsetAsync(ctx->counter, 0, 16 * 8, ctx->stream) != hipSuccess) return bad(REC_E_HIP);
+  rec_wtable_clear(ctx);
+  if (rec_load_data(ctx, X_dev, cfg->ldx) != REC_OK) return bad(REC_E_HIP);
+  hipLaunchKernelGGL(k_fill_f64, dim3((cfg->N + 255) / 256), dim3(256), 0, ctx->stream, F.theta,
+                     cfg->N, cfg->model == REC_GAUSS ? 1.0 : 0.0);
+  int32_t e = 0;
+  if (read_err(ctx, &e) != REC_OK) return bad(REC_E_HIP);
+  if (e & 4) return bad(REC_E_NUMERIC);
+  double obj;
+  if (refresh(ctx, &obj) != REC_OK) return bad(REC_E_HIP);
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bad(REC_E_HIP);
+  *out = ctx;
+  return REC_OK;
+}
+
+rec_status rec_destroy(rec_ctx* ctx) {
+  if (!ctx) return REC_E_INVAL;
+  hipStreamSynchronize(ctx->stream);
+  delete ctx;
+  return REC_OK;
+}
+
+rec_status rec_score_pairs(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
+                           double* gain_dev, double* wopt_dev) {
+  REC_CHECK_CTX(ctx);
+  if (P < 0 || (P > 0 && (!i_dev || !j_dev || !gain_dev))) return fail(ctx, REC_E_INVAL, "bad arguments");
+  if (P == 0) return REC_OK;
+  REC_TRY(clear_err(ctx));
+  REC_TRY(rec_launch_score(ctx, P, i_dev, j_dev, nullptr, gain_dev, wopt_dev, nullptr));
+  int32_t e = 0;
+  REC_TRY(read_err(ctx, &e));
+  if (e & 1) return fail(ctx, REC_E_INVAL, "pair index out of range or i == j");
+  return REC_OK;
+}
+
+rec_status rec_find_best(rec_ctx* ctx, int64_t m, int32_t search, int32_t* i_dev, int32_t* j_dev,
+                         double* gain_dev, int64_t* n_out_host, rec_sweep_stats* st) {
+  REC_CHECK_CTX(ctx);
+  if (m < 1 || !i_dev || !j_dev || !gain_dev || !n_out_host || search < 0 || search > 2)
+    return fail(ctx, REC_E_INVAL, "bad arguments");
+  if (m > ctx->best_cap) return fail(ctx, REC_E_INVAL, "m exceeds the capacity planned for kappa");
+  REC_TRY(clear_err(ctx));
+  rec_sweep_stats local{};
+  double t0 = now_ms();
+  int64_t n = 0;
+  rec_status s = rec_search_best(ctx, m, search, &n, &local);
+  if (s != REC_OK) return s;
+  REC_HIP(hipMemcpyAsync(i_dev, ctx->best_i, n * 4, hipMemcpyDeviceToDevice, ctx->stream));
+  REC_HIP(hipMemcpyAsync(j_dev, ctx->best_j, n * 4, hipMemcpyDeviceToDevice, ctx->stream));
+  REC_HIP(hipMemcpyAsync(gain_dev, ctx->best_g, n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  *n_out_host = n;
+  local.n_best = n;
+  local.t_search_ms = now_ms() - t0;
+  if (st) *st = local;
+  return REC_OK;
+}
+
+rec_status rec_apply_updates(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
+                             double* delta_host) {
+  REC_CHECK_CTX(ctx);
+  if (P < 0 || (P > 0 && (!i_dev || !j_dev))) return fail(ctx, REC_E_INVAL, "bad arguments");
+  if (P > ctx->best_cap) return fail(ctx, REC_E_INVAL, "too many pairs for one call");
+  double d = 0.0;
+  if (P > 0) {
+    REC_TRY(clear_err(ctx));
+    hipLaunchKernelGGL(k_check_pairs, dim3((P + 255) / 256), dim3(256), 0, ctx->stream, i_dev, j_dev,
+                       P, ctx->cfg.N, ctx->err_flag);
+    int32_t e = 0;
+    REC_TRY(read_err(ctx, &e));
+    if (e & 1) return fail(ctx, REC_E_INVAL, "pair index out of range or i == j");
+    REC_HIP(hipMemcpyAsync(ctx->best_i, i_dev, P * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    REC_HIP(hipMemcpyAsync(ctx->best_j, j_dev, P * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    int64_t acc, rounds;
+    rec_status s = rec_apply_best(ctx, P, ctx->best_i, ctx->best_j, &d, &acc, &rounds);
+    if (s != REC_OK) { ctx->state = REC_E_STATE; return s; }
+  }
+  if (delta_host) *delta_host = d;
+  return REC_OK;
+}
+
+rec_status rec_gcd_sweep(rec_ctx* ctx, int32_t search, rec_sweep_stats* st) {
+  REC_CHECK_CTX(ctx);
+  if (search < 0 || search > 2) return fail(ctx, REC_E_INVAL, "unknown search");
+  REC_TRY(clear_err(ctx));
+  rec_sweep_stats S{};
+  double t0 = now_ms();
+  int64_t n = 0;
+  rec_status s = rec_search_best(ctx, ctx->m_default, search, &n, &S);
+  if (s != REC_OK) return s;
+  double t1 = now_ms();
+  int64_t acc = 0, rounds = 0;
+  double delta = 0.0;
+  s = rec_apply_best(ctx, n, ctx->best_i, ctx->best_j, &delta, &acc, &rounds);
+  if (s != REC_OK) { ctx->state = REC_E_STATE; return s; }
+  double t2 = now_ms();
+  double obj = 0.0;
+  s = refresh(ctx, &obj);
+  if (s != REC_OK) { ctx->state = REC_E_STATE; return s; }
+  double t3 = now_ms();
+  S.objective = obj;
+  S.delta = delta;
+  S.accepted = acc;
+  S.n_best = n;
+  S.rounds = rounds;
+  S.t_search_ms = t1 - t0;
+  S.t_update_ms = t2 - t1;
+  S.t_theta_ms = t3 - t2;
+  if (st) *st = S;
+  return REC_OK;
+}
+
+rec_status rec_theta_update(rec_ctx* ctx, double* objective_host) {
+  REC_CHECK_CTX(ctx);
+  double obj;
+  rec_status s = refresh(ctx, &obj);
+  if (s != REC_OK) { ctx->state = REC_E_STATE; return s; }
+  if (objective_host) *objective_host = obj;
+  return REC_OK;
+}
+
+rec_status rec_objective(rec_ctx* ctx, double* objective_host) {
+  REC_CHECK_CTX(ctx);
+  if (!objective_host) return fail(ctx, REC_E_INVAL, "null output");
+  return rec_eval_objective(ctx, objective_host);
+}
+
+rec_status rec_get_model(rec_ctx* ctx, int64_t cap, int32_t* ei_dev, int32_t* ej_dev, double* w_dev,
+                         double* theta_dev, int64_t* nnz_host) {
+  if (!ctx || !nnz_host || cap < 0) return REC_E_INVAL;
+  if (cap > 0 && (!ei_dev || !ej_dev || !w_dev)) return fail(ctx, REC_E_INVAL, "null output");
+  int64_t nnz = 0;
+  REC_TRY(rec_wtable_compact(ctx, &nnz));
+  int64_t c = std::min(cap, nnz);
+  if (c > 0) {
+    REC_HIP(hipMemcpyAsync(ei_dev, ctx->wi, c * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    REC_HIP(hipMemcpyAsync(ej_dev, ctx->wj, c * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    REC_HIP(hipMemcpyAsync(w_dev, ctx->wv, c * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  if (theta_dev)
+    REC_HIP(hipMemcpyAsync(theta_dev, ctx->F.theta, ctx->cfg.N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  *nnz_host = nnz;
+  return REC_OK;
+}
+
+rec_status rec_set_model(rec_ctx* ctx, int64_t nnz, const int32_t* ei_dev, const int32_t* ej_dev,
+                         const double* w_dev, const double* theta_dev) {
+  if (!ctx || nnz < 0 || (nnz > 0 && (!ei_dev || !ej_dev || !w_dev))) return REC_E_INVAL;
+  if (nnz > ctx->max_nnz) return fail(ctx, REC_E_NOMEM, "more entries than max_nnz");
+  REC_TRY(clear_err(ctx));
+  rec_wtable_clear(ctx);
+  REC_TRY(rec_wtable_insert_list(ctx, nnz, ei_dev, ej_dev, w_dev));
+  if (theta_dev)
+    REC_HIP(hipMemcpyAsync(ctx->F.theta, theta_dev, ctx->cfg.N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  int32_t e = 0;
+  REC_TRY(read_err(ctx, &e));
+  if (e & 8) { ctx->state = REC_E_STATE; return fail(ctx, REC_E_INVAL, "bad W entry (index or value)"); }
+  if (e & 2) { ctx->state = REC_E_STATE; return fail(ctx, REC_E_NOMEM, "W table full"); }
+  REC_TRY(rec_rebuild_fields(ctx));
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->state = REC_OK;
+  return REC_OK;
+}
+
+rec_status rec_get_fields(rec_ctx* ctx, double* H_dev) {
+  if (!ctx || !H_dev) return REC_E_INVAL;
+  int64_t n = ctx->cfg.N * ctx->cfg.M;
+  if (ctx->fp32)
+    hipLaunchKernelGGL(k_fields_out<float>, dim3((n + 255) / 256), dim3(256), 0, ctx->stream,
+                       (const float*)ctx->F.H, ctx->cfg.N, ctx->cfg.M, ctx->F.Mp, H_dev);
+  else
+    hipLaunchKernelGGL(k_fields_out<double>, dim3((n + 255) / 256), dim3(256), 0, ctx->stream,
+                       (const double*)ctx->F.H, ctx->cfg.N, ctx->cfg.M, ctx->F.Mp, H_dev);
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  return REC_OK;
+}
+
+rec_status rec_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int32_t k, int32_t level,
+                   int32_t mode, int32_t* nbr_dev, double* gain_dev, int32_t* iters_host) {
+  REC_CHECK_CTX(ctx);
+  if (n < 2 || n > ctx->cfg.N || k < 1 || k > n - 1 || !S_dev || !nbr_dev || !gain_dev ||
+      (mode != REC_SEARCH_NNDESCENT && mode != REC_SEARCH_EXACT_KNN))
+    return fail(ctx, REC_E_INVAL, "bad arguments");
+  REC_TRY(clear_err(ctx));
+  hipLaunchKernelGGL(k_check_set, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, S_dev, n,
+                     ctx->cfg.N, ctx->err_flag);
+  int32_t e = 0;
+  REC_TRY(read_err(ctx, &e));
+  if (e & 1) return fail(ctx, REC_E_INVAL, "S must be strictly increasing node indices in [0, N)");
+  int it = 0;
+  rec_status s = rec_search_knn(ctx, n, S_dev, k, level, mode == REC_SEARCH_EXACT_KNN ? 1 : 0,
+                                nbr_dev, gain_dev, &it);
+  if (s != REC_OK) return s;
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  if (iters_host) *iters_host = it;
+  return REC_OK;
+}
+
+rec_status rec_set_timing(rec_ctx* ctx, int32_t on) {
+  if (!ctx) return REC_E_INVAL;
+  REC_TRY(rec_timing_resolve(ctx));
+  ctx->timing = on != 0;
+  ctx->score_ms = 0.0;
+  ctx->score_launches = ctx->score_pairs = 0;
+  return REC_OK;
+}
+
+rec_status rec_kernel_time(rec_ctx* ctx, double* score_ms_host, int64_t* launches_host,
+                           int64_t* pairs_host) {
+  if (!ctx) return REC_E_INVAL;
+  REC_TRY(rec_timing_resolve(ctx));
+  if (score_ms_host) *score_ms_host = ctx->score_ms;
+  if (launches_host) *launches_host = ctx->score_launches;
+  if (pairs_host) *pairs_host = ctx->score_pairs;
+  ctx->score_ms = 0.0;
+  ctx->score_launches = ctx->score_pairs = 0;
+  return REC_OK;
+}
+
+}  // extern "C"

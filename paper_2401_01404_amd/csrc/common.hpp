@@ -1,0 +1,105 @@
+// Shared device helpers of the gfx950 reconstruction library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define REC_WAVE 64
+
+// ------------------------------------------------------------------ RNG --
+// SplitMix64 output function (Steele, Lea, Flood, OOPSLA 2014) and the
+// counter generator key(seed, stream, a, b) built from it.
+__host__ __device__ __forceinline__ uint64_t rec_mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+__host__ __device__ __forceinline__ uint64_t rec_ctr(uint64_t seed, uint64_t stream, uint64_t a,
+                                                     uint64_t b) {
+  return rec_mix64(rec_mix64(rec_mix64(rec_mix64(seed) ^ stream) ^ a) ^ b);
+}
+// floor(r * bound / 2^64): an integer in [0, bound)
+__device__ __forceinline__ uint64_t rec_below(uint64_t r, uint64_t bound) {
+  return __umul64hi(r, bound);
+}
+
+constexpr uint64_t REC_STREAM_INIT = 5;  // NNDescent initial lists
+constexpr uint64_t REC_STREAM_CAP = 6;   // in-neighbour sampling of the undirected graph U
+
+// ------------------------------------------------------------ pair keys --
+// Symmetric models: one key per unordered pair; kinetic: ordered (i <- j).
+__host__ __device__ __forceinline__ uint64_t rec_pair_key(int i, int j, bool directed) {
+  if (!directed && i > j) { int t = i; i = j; j = t; }
+  return ((uint64_t)(uint32_t)i << 32) | (uint32_t)j;
+}
+constexpr uint64_t REC_EMPTY = ~0ULL;
+
+// Order-preserving map of a double to uint64 (ascending) and its inverse.
+__host__ __device__ __forceinline__ uint64_t rec_ord(double g) {
+  uint64_t u = __builtin_bit_cast(uint64_t, g);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ULL);
+}
+__host__ __device__ __forceinline__ double rec_unord(uint64_t o) {
+  uint64_t u = (o >> 63) ? (o & 0x7FFFFFFFFFFFFFFFULL) : ~o;
+  return __builtin_bit_cast(double, u);
+}
+// key that sorts gains in descending order under an ascending sort
+__host__ __device__ __forceinline__ uint64_t rec_desc_key(double g) { return ~rec_ord(g); }
+__host__ __device__ __forceinline__ double rec_desc_gain(uint64_t k) { return rec_unord(~k); }
+
+// ----------------------------------------------------------- open hashing --
+__device__ __forceinline__ uint64_t rec_hash_slot(uint64_t key, uint64_t mask) {
+  return rec_mix64(key) & mask;
+}
+
+// Look up key in a linear-probing table; returns the slot or -1.
+__device__ __forceinline__ int64_t rec_hash_find(const uint64_t* keys, uint64_t mask, uint64_t key,
+                                                 int max_probe) {
+  uint64_t s = rec_hash_slot(key, mask);
+  for (int p = 0; p < max_probe; ++p) {
+    uint64_t k = __atomic_load_n(&keys[s], __ATOMIC_RELAXED);
+    if (k == key) return (int64_t)s;
+    if (k == REC_EMPTY) return -1;
+    s = (s + 1) & mask;
+  }
+  return -1;
+}
+
+// Insert key if absent.  Returns the slot; *inserted tells whether this call
+// created it.  Returns -1 when max_probe slots were all taken by other keys.
+__device__ __forceinline__ int64_t rec_hash_insert(uint64_t* keys, uint64_t mask, uint64_t key,
+                                                   int max_probe, bool* inserted) {
+  uint64_t s = rec_hash_slot(key, mask);
+  *inserted = false;
+  for (int p = 0; p < max_probe; ++p) {
+    uint64_t k = __atomic_load_n(&keys[s], __ATOMIC_RELAXED);
+    if (k == key) return (int64_t)s;
+    if (k == REC_EMPTY) {
+      uint64_t prev = atomicCAS((unsigned long long*)&keys[s], (unsigned long long)REC_EMPTY,
+                                (unsigned long long)key);
+      if (prev == REC_EMPTY) { *inserted = true; return (int64_t)s; }
+      if (prev == key) return (int64_t)s;
+    }
+    s = (s + 1) & mask;
+  }
+  return -1;
+}
+
+// ------------------------------------------------------- wave reductions --
+template <class T>
+__device__ __forceinline__ T rec_wave_sum(T v) {
+  // butterfly: every lane ends with the same bits (each step adds a commuting pair)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, REC_WAVE);
+  return v;
+}
+
+__device__ __forceinline__ int rec_lane() { return (int)(threadIdx.x & (REC_WAVE - 1)); }
+
+// numerics shared by the kernels (double)
+__device__ __forceinline__ double rec_lcosh_tau(double tau) {   // log cosh(atanh tau)
+  return -0.5 * log1p(-tau * tau);
+}
+__device__ __forceinline__ double rec_atanh(double tau) {
+  return 0.5 * log1p(2.0 * tau / (1.0 - tau));
+}

@@ -1,0 +1,175 @@
+// Context state of the library and the host-side entry points of each
+// kernel family (definitions in the .hip files).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/rec.h"
+
+// Device view of the data and fields, passed by value to kernels.
+struct Fields {
+  const int8_t* xs;     // N x Mp input side +-1 (kinetic: x_{j,t-1}); padding 0
+  const int8_t* ys;     // N x Mp target side (kinetic: x_{i,t}); symmetric: == xs
+  const float* xf;      // Gaussian data N x Mp (padding 0), else null
+  void* H;              // N x Mp fields (Gaussian: residuals), real
+  void* T;              // N x Mp tanh(H) (Ising/kinetic), real
+  const double* sq;     // Gaussian: ||x_i||^2
+  double* theta;        // N
+  int64_t N, M, Mp;     // valid samples M, padded row length Mp = 64 * npl
+  int npl;              // samples per lane
+  int model;            // rec_model
+};
+
+// Open-addressing table of W entries: key = pair key, value = weight.
+struct WTable {
+  uint64_t* keys;
+  double* vals;
+  uint64_t mask;        // capacity - 1
+  int64_t* count;       // device counter of occupied slots
+};
+
+// Score memo inside one FindBest call [App. B, caching].
+struct Cache {
+  uint64_t* keys;
+  double* vals;
+  uint64_t mask;
+  double* ovf;          // values of pairs that found no free slot
+  int64_t ovf_cap;
+};
+
+constexpr int REC_MAX_PROBE = 64;
+
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  template <class T>
+  T* take(size_t n) {
+    size_t bytes = ((n * sizeof(T)) + 255) & ~size_t(255);
+    size_t off = used;
+    used += bytes;
+    if (base == nullptr || used > size) return nullptr;
+    return reinterpret_cast<T*>(base + off);
+  }
+};
+
+struct SortBufs {
+  uint64_t* khi[2];
+  uint64_t* klo[2];
+  uint32_t* val[2];
+  uint32_t* hist;
+  int64_t cap;
+};
+
+struct rec_ctx {
+  rec_config cfg;
+  hipStream_t stream;
+  int dev;
+  rec_status state = REC_OK;
+  std::string err;
+  bool fp32;
+  int64_t m_default;
+
+  Fields F;
+  WTable W;
+  Cache C;
+  SortBufs sb;
+  int64_t max_nnz;
+
+  // W as sorted row lists (CSR) for the field rebuild
+  int64_t* row_off;     // N+1
+  int32_t* col;         // 2 max_nnz
+  double* colw;         // 2 max_nnz
+  // scratch for compaction of the W table
+  int32_t* wi; int32_t* wj; double* wv;   // max_nnz each
+  int64_t* counter;     // small device counters [16]
+  double* dscratch;     // per-block partial sums (N)
+  double* dresult;      // small double results [16]
+  int32_t* err_flag;    // device error flag
+
+  // search state (see search.hip)
+  int64_t list_cap;     // capacity of KNN list entries (>= 4m + N)
+  int32_t *Gidx, *Gidx2; double *Ggain, *Ggain2;
+  int32_t *S, *S2, *loc;
+  int64_t *cnt, *off;   // per node counts / offsets (N + 1)
+  int64_t cand_cap;
+  int32_t* cand_v; uint32_t* cand_slot;
+  int32_t *ts_i, *ts_j; uint32_t* ts_slot;    // to-score list
+  int32_t* inoff_cnt;   // N
+  int64_t* inoff;       // N + 1
+  int32_t* in_src;      // list_cap
+  uint64_t* dset_keys; uint64_t dset_mask;
+  uint64_t* pset_keys; uint64_t pset_mask;
+  int64_t pool_cap;
+  uint64_t *pool_hi, *pool_lo;
+  int32_t* flags;       // N
+  int64_t* scan_tmp;    // block sums for scans
+  // E_best and update rounds
+  int64_t best_cap;
+  int32_t *best_i, *best_j; double* best_g;
+  int32_t* first;       // N
+  uint8_t* done;        // best_cap
+  double* dw;           // best_cap
+  // exhaustive search chunk buffers
+  int64_t ex_cap;
+  // pair-score kernel timing (instrumentation)
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t ev_used = 0;
+  double score_ms = 0.0;
+  int64_t score_launches = 0, score_pairs = 0;
+  ~rec_ctx() {
+    for (auto& e : ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  }
+};
+
+rec_status rec_timing_resolve(rec_ctx* ctx);
+
+// ---- launch helpers (implemented in the .hip files) ----
+#define REC_HIP(call)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);            \
+      return REC_E_HIP;                                                        \
+    }                                                                          \
+  } while (0)
+
+// fields.hip
+rec_status rec_load_data(rec_ctx* ctx, const void* X, int64_t ldx);
+rec_status rec_rebuild_fields(rec_ctx* ctx);              // from W table and theta
+rec_status rec_fit_theta(rec_ctx* ctx);                   // theta update + field shift
+rec_status rec_eval_objective(rec_ctx* ctx, double* out);
+rec_status rec_wtable_compact(rec_ctx* ctx, int64_t* nnz); // W table -> wi/wj/wv (sorted)
+void rec_wtable_clear(rec_ctx* ctx);
+rec_status rec_wtable_insert_list(rec_ctx* ctx, int64_t n, const int32_t* ei, const int32_t* ej,
+                                  const double* w);
+
+// score.hip
+// Score pairs (I[p], J[p]); results to gain_out[slot ? slot[p] : p] (and the
+// cache overflow area for slots >= cache capacity when cache != null).
+rec_status rec_launch_score(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
+                            const uint32_t* slot, double* gain_out, double* w_out,
+                            const Cache* cache);
+// Apply one round of node-disjoint updates (see update kernels).
+rec_status rec_launch_update_round(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
+                                   const int32_t* first, uint8_t* done, double* dw);
+
+// sort.hip
+// Stable LSD radix sort of (khi, klo, val) by the 8-bit digits listed
+// (word 0 = klo, 1 = khi; shift in bits), in the given order.
+struct Digit { int word, shift; };
+rec_status rec_radix_sort(rec_ctx* ctx, int64_t n, const Digit* digits, int nd, int* cur);
+rec_status rec_exclusive_scan(rec_ctx* ctx, const int64_t* in, int64_t* out, int64_t n,
+                              int64_t* total_dev);
+
+// search.hip
+rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,
+                           rec_sweep_stats* st);
+rec_status rec_search_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int k, int level, int mode,
+                          int32_t* nbr, double* gain, int* iters);
+rec_status rec_apply_best(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
+                          double* delta, int64_t* accepted, int64_t* rounds);

@@ -1,0 +1,476 @@
+// Data layout, fields, theta and the objective.
+//
+// Layout: node-major rows padded to Mp = 64 * npl samples (zeros past M), so
+// a wavefront reads whole rows with one contiguous block per load.
+//
+// Fields [App. A, "keeping track of the weighted sum of the neighbors"]:
+// m_i = sum_{j != i} W_ij x_j per sample, summed in FP64 over the sorted
+// row list of W and rounded once to the working precision; Ising and kinetic
+// store h = theta + m and t = tanh h, the Gaussian model stores the residual
+// r = x + theta^2 m.
+//
+// Objective [App. A]: sum over nodes and samples of the log conditional plus
+// the L1 prior -lambda sum |W_ij|, summed in FP64 in a fixed order (per-row
+// partials, then one block), so repeated evaluations give the same bits.
+#include <math.h>
+
+#include "common.hpp"
+#include "ctx.hpp"
+
+namespace {
+
+constexpr int FT = 256;   // threads per row block
+
+template <class R> __device__ __forceinline__ R tanh_(R x);
+template <> __device__ __forceinline__ float tanh_<float>(float x) { return tanhf(x); }
+template <> __device__ __forceinline__ double tanh_<double>(double x) { return tanh(x); }
+
+// log(2 cosh h) in the working precision, stable for large |h|
+__device__ __forceinline__ float log2cosh_(float h) {
+  float a = fabsf(h);
+  return a + log1pf(__expf(-2.f * a));
+}
+__device__ __forceinline__ double log2cosh_(double h) {
+  double a = fabs(h);
+  return a + log1p(exp(-2.0 * a));
+}
+
+__device__ double block_sum(double v, double* sh) {
+  const int tid = threadIdx.x;
+  v = rec_wave_sum(v);
+  if ((tid & (REC_WAVE - 1)) == 0) sh[tid / REC_WAVE] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (tid == 0) {
+    for (int w = 0; w < FT / REC_WAVE; ++w) s += sh[w];
+    sh[0] = s;
+  }
+  __syncthreads();
+  s = sh[0];
+  __syncthreads();
+  return s;
+}
+
+// X (caller layout) -> padded int8 rows; kinetic: input side columns 0..M-1,
+// target side columns 1..M.  Flags any value other than +-1.
+__global__ __launch_bounds__(FT) void k_load_int8(const int8_t* __restrict__ X, int64_t ldx,
+                                                  int64_t M, int64_t Mp, int kinetic,
+                                                  int8_t* __restrict__ xs, int8_t* __restrict__ ys,
+                                                  int32_t* err) {
+  const int64_t i = blockIdx.x;
+  for (int64_t s = threadIdx.x; s < Mp; s += FT) {
+    int8_t a = 0, b = 0;
+    if (s < M) {
+      a = X[i * ldx + s];
+      b = kinetic ? X[i * ldx + s + 1] : a;
+      if ((a != 1 && a != -1) || (b != 1 && b != -1)) atomicOr(err, 4);
+    }
+    xs[i * Mp + s] = a;
+    if (kinetic) ys[i * Mp + s] = b;
+  }
+}
+
+__global__ __launch_bounds__(FT) void k_load_f32(const float* __restrict__ X, int64_t ldx, int64_t M,
+                                                 int64_t Mp, float* __restrict__ xf,
+                                                 double* __restrict__ sq, int32_t* err) {
+  __shared__ double sh[FT / REC_WAVE];
+  const int64_t i = blockIdx.x;
+  double s2 = 0.0;
+  for (int64_t s = threadIdx.x; s < Mp; s += FT) {
+    float a = 0.f;
+    if (s < M) {
+      a = X[i * ldx + s];
+      if (!isfinite(a)) atomicOr(err, 4);
+      s2 += (double)a * (double)a;
+    }
+    xf[i * Mp + s] = a;
+  }
+  double tot = block_sum(s2, sh);
+  if (threadIdx.x == 0) sq[i] = tot;
+}
+
+// Rebuild the fields of row i from its sorted W row list.
+template <class R, int MODEL>
+__global__ __launch_bounds__(FT) void k_fields(Fields F, const int64_t* __restrict__ row_off,
+                                               const int32_t* __restrict__ col,
+                                               const double* __restrict__ colw) {
+  const int64_t i = blockIdx.x;
+  const int64_t e0 = row_off ? row_off[i] : 0, e1 = row_off ? row_off[i + 1] : 0;
+  const double th = F.theta[i];
+  R* H = reinterpret_cast<R*>(F.H);
+  R* T = reinterpret_cast<R*>(F.T);
+  for (int64_t s = threadIdx.x; s < F.Mp; s += FT) {
+    double acc = 0.0;
+    if (s < F.M) {
+      for (int64_t e = e0; e < e1; ++e) {
+        int64_t j = col[e];
+        double x = MODEL == REC_GAUSS ? (double)F.xf[j * F.Mp + s] : (double)F.xs[j * F.Mp + s];
+        acc += colw[e] * x;
+      }
+    }
+    int64_t idx = i * F.Mp + s;
+    if (MODEL == REC_GAUSS) {
+      H[idx] = s < F.M ? (R)((double)F.xf[idx] + th * th * acc) : R(0);
+    } else {
+      R h = s < F.M ? (R)(th + acc) : R(0);
+      H[idx] = h;
+      T[idx] = s < F.M ? tanh_<R>(h) : R(0);
+    }
+  }
+}
+
+// Refit theta_i [App. A, theta updated alongside W]:
+//   Ising / kinetic: root of sum_m (y_m - tanh(theta + m_m)) on [-8, 8]
+//   (Newton inside the bracket, bisection otherwise), m = h - theta_old;
+//   Gaussian: v = theta^2 is the positive root of C v^2 + M v - A = 0,
+//   A = sum x^2, C = sum m^2, m = (r - x) / theta_old^2.
+// Then the row's fields are shifted to the new theta.
+template <class R, int MODEL>
+__global__ __launch_bounds__(FT) void k_theta(Fields F) {
+  __shared__ double sh[FT / REC_WAVE];
+  const int64_t i = blockIdx.x;
+  const double th0 = F.theta[i];
+  R* H = reinterpret_cast<R*>(F.H);
+  R* T = reinterpret_cast<R*>(F.T);
+  const int8_t* Y = MODEL == REC_KINETIC ? F.ys : F.xs;
+  double th = th0;
+  if (MODEL == REC_GAUSS) {
+    double A = 0.0, C = 0.0;
+    double v0 = th0 * th0;
+    for (int64_t s = threadIdx.x; s < F.M; s += FT) {
+      double x = F.xf[i * F.Mp + s];
+      double mm = ((double)H[i * F.Mp + s] - x) / v0;
+      A += x * x;
+      C += mm * mm;
+    }
+    A = block_sum(A, sh);
+    C = block_sum(C, sh);
+    double M = (double)F.M;
+    double v = C > 0 ? (-M + sqrt(M * M + 4.0 * A * C)) / (2.0 * C) : A / M;
+    th = sqrt(v);
+    for (int64_t s = threadIdx.x; s < F.M; s += FT) {
+      double x = F.xf[i * F.Mp + s];
+      double mm = ((double)H[i * F.Mp + s] - x) / v0;
+      H[i * F.Mp + s] = (R)(x + v * mm);
+    }
+  } else {
+    auto eval = [&](double t, double& f, double& df) {
+      double a = 0.0, b = 0.0;
+      for (int64_t s = threadIdx.x; s < F.M; s += FT) {
+        double mm = (double)H[i * F.Mp + s] - th0;
+        R tt = tanh_<R>((R)(t + mm));
+        a += (double)Y[i * F.Mp + s] - (double)tt;
+        b -= 1.0 - (double)tt * (double)tt;
+      }
+      f = block_sum(a, sh);
+      df = block_sum(b, sh);
+    };
+    const double TMAX = 8.0;
+    double f, df;
+    eval(TMAX, f, df);
+    if (f >= 0) th = TMAX;
+    else {
+      eval(-TMAX, f, df);
+      if (f <= 0) th = -TMAX;
+      else {
+        double lo = -TMAX, hi = TMAX;
+        double t = fmin(fmax(th0, lo), hi);
+        eval(t, f, df);
+        for (int it = 0; it < 100; ++it) {
+          if (f == 0.0) break;
+          if (f > 0) lo = t; else hi = t;
+          double tn = df < 0 ? t - f / df : 0.5 * (lo + hi);
+          if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+          double step = tn - t;
+          t = tn;
+          if (fabs(step) <= (sizeof(R) == 4 ? 1e-9 : 1e-15) * fmax(1.0, fabs(t)) || hi - lo < 1e-300)
+            break;
+          eval(t, f, df);
+        }
+        th = t;
+      }
+    }
+    for (int64_t s = threadIdx.x; s < F.M; s += FT) {
+      double mm = (double)H[i * F.Mp + s] - th0;
+      R h = (R)(th + mm);
+      H[i * F.Mp + s] = h;
+      T[i * F.Mp + s] = tanh_<R>(h);
+    }
+  }
+  if (threadIdx.x == 0) F.theta[i] = th;
+}
+
+// Per-row log pseudolikelihood into part[i].
+template <class R, int MODEL>
+__global__ __launch_bounds__(FT) void k_rowll(Fields F, double* part) {
+  __shared__ double sh[FT / REC_WAVE];
+  const int64_t i = blockIdx.x;
+  const R* H = reinterpret_cast<const R*>(F.H);
+  double acc = 0.0;
+  if (MODEL == REC_GAUSS) {
+    double v = F.theta[i] * F.theta[i];
+    for (int64_t s = threadIdx.x; s < F.M; s += FT) {
+      double r = (double)H[i * F.Mp + s];
+      acc += -r * r / (2.0 * v);
+    }
+  } else {
+    const int8_t* Y = MODEL == REC_KINETIC ? F.ys : F.xs;
+    for (int64_t s = threadIdx.x; s < F.M; s += FT) {
+      R h = H[i * F.Mp + s];
+      R y = (R)Y[i * F.Mp + s];
+      acc += (double)(y * h - log2cosh_(h));
+    }
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    if (MODEL == REC_GAUSS)
+      acc += (double)F.M * (-log(F.theta[i]) - 0.5 * log(2.0 * M_PI));
+    part[i] = acc;
+  }
+}
+
+// Sum part[0..n) in a fixed order (one block): result = sum * scale + add0
+__global__ __launch_bounds__(FT) void k_sum(const double* part, int64_t n, double* out) {
+  __shared__ double sh[FT / REC_WAVE];
+  double acc = 0.0;
+  int64_t per = (n + FT - 1) / FT;
+  int64_t b = (int64_t)threadIdx.x * per, e = b + per < n ? b + per : n;
+  for (int64_t k = b; k < e; ++k) acc += part[k];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) *out = acc;
+}
+
+// sum |w| over the sorted W list
+__global__ __launch_bounds__(FT) void k_abs_partial(const double* w, int64_t n, double* part,
+                                                    int64_t nchunk) {
+  int64_t c = (int64_t)blockIdx.x * FT + threadIdx.x;
+  if (c >= nchunk) return;
+  int64_t per = (n + nchunk - 1) / nchunk;
+  int64_t b = c * per, e = b + per < n ? b + per : n;
+  double acc = 0.0;
+  for (int64_t k = b; k < e; ++k) acc += fabs(w[k]);
+  part[c] = acc;
+}
+
+__global__ void k_combine_obj(const double* ll, const double* pen, double lambda, double* out) {
+  *out = *ll - lambda * *pen;
+}
+
+// ---- W table ----
+__global__ void k_winsert(WTable W, int64_t n, const int32_t* ei, const int32_t* ej,
+                          const double* w, int64_t N, int directed, int32_t* err) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  int i = ei[e], j = ej[e];
+  double v = w[e];
+  if (i < 0 || j < 0 || i >= N || j >= N || i == j || !isfinite(v)) { atomicOr(err, 8); return; }
+  if (v == 0.0) return;
+  bool ins;
+  int64_t s = rec_hash_insert(W.keys, W.mask, rec_pair_key(i, j, directed), REC_MAX_PROBE, &ins);
+  if (s < 0) { atomicOr(err, 2); return; }
+  W.vals[s] = v;
+  if (ins) atomicAdd((unsigned long long*)W.count, 1ULL);
+}
+
+// occupied, nonzero table entries -> sort records (key = pair key, val = slot)
+__global__ void k_wcompact(WTable W, uint64_t cap, uint64_t* klo, uint32_t* val, int64_t* n,
+                           int64_t max_n) {
+  uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= cap) return;
+  uint64_t k = W.keys[s];
+  if (k == REC_EMPTY || W.vals[s] == 0.0) return;
+  int64_t p = (int64_t)atomicAdd((unsigned long long*)n, 1ULL);
+  if (p < max_n) { klo[p] = k; val[p] = (uint32_t)s; }
+}
+
+__global__ void k_wunpack(const uint64_t* klo, const uint32_t* val, const double* wvals, int64_t n,
+                          int32_t* wi, int32_t* wj, double* wv) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  wi[e] = (int32_t)(klo[e] >> 32);
+  wj[e] = (int32_t)(klo[e] & 0xffffffffu);
+  wv[e] = wvals[val[e]];
+}
+
+// CSR records: one per (row, col) direction
+__global__ void k_csr_records(const int32_t* wi, const int32_t* wj, int64_t n, int directed,
+                              uint64_t* klo, uint32_t* val, int64_t* rowcnt) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  int i = wi[e], j = wj[e];
+  if (directed) {
+    klo[e] = ((uint64_t)(uint32_t)i << 32) | (uint32_t)j;
+    val[e] = (uint32_t)e;
+    atomicAdd((unsigned long long*)&rowcnt[i], 1ULL);
+  } else {
+    klo[2 * e] = ((uint64_t)(uint32_t)i << 32) | (uint32_t)j;
+    val[2 * e] = (uint32_t)e;
+    klo[2 * e + 1] = ((uint64_t)(uint32_t)j << 32) | (uint32_t)i;
+    val[2 * e + 1] = (uint32_t)e;
+    atomicAdd((unsigned long long*)&rowcnt[i], 1ULL);
+    atomicAdd((unsigned long long*)&rowcnt[j], 1ULL);
+  }
+}
+
+__global__ void k_csr_fill(const uint64_t* klo, const uint32_t* val, const double* wv, int64_t n,
+                           int32_t* col, double* colw) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  col[e] = (int32_t)(klo[e] & 0xffffffffu);
+  colw[e] = wv[val[e]];
+}
+
+int bits_for(int64_t v) {
+  int b = 0;
+  while (b < 63 && (int64_t(1) << b) < v) ++b;
+  return b < 1 ? 1 : b;
+}
+
+template <class R>
+rec_status launch_fields_r(rec_ctx* ctx) {
+  dim3 g(ctx->cfg.N), b(FT);
+  switch (ctx->cfg.model) {
+    case REC_ISING:
+      hipLaunchKernelGGL((k_fields<R, REC_ISING>), g, b, 0, ctx->stream, ctx->F, ctx->row_off, ctx->col, ctx->colw);
+      break;
+    case REC_GAUSS:
+      hipLaunchKernelGGL((k_fields<R, REC_GAUSS>), g, b, 0, ctx->stream, ctx->F, ctx->row_off, ctx->col, ctx->colw);
+      break;
+    default:
+      hipLaunchKernelGGL((k_fields<R, REC_KINETIC>), g, b, 0, ctx->stream, ctx->F, ctx->row_off, ctx->col, ctx->colw);
+  }
+  REC_HIP(hipGetLastError());
+  return REC_OK;
+}
+
+template <class R>
+rec_status launch_theta_r(rec_ctx* ctx) {
+  dim3 g(ctx->cfg.N), b(FT);
+  switch (ctx->cfg.model) {
+    case REC_ISING: hipLaunchKernelGGL((k_theta<R, REC_ISING>), g, b, 0, ctx->stream, ctx->F); break;
+    case REC_GAUSS: hipLaunchKernelGGL((k_theta<R, REC_GAUSS>), g, b, 0, ctx->stream, ctx->F); break;
+    default: hipLaunchKernelGGL((k_theta<R, REC_KINETIC>), g, b, 0, ctx->stream, ctx->F);
+  }
+  REC_HIP(hipGetLastError());
+  return REC_OK;
+}
+
+template <class R>
+rec_status launch_rowll_r(rec_ctx* ctx) {
+  dim3 g(ctx->cfg.N), b(FT);
+  switch (ctx->cfg.model) {
+    case REC_ISING: hipLaunchKernelGGL((k_rowll<R, REC_ISING>), g, b, 0, ctx->stream, ctx->F, ctx->dscratch); break;
+    case REC_GAUSS: hipLaunchKernelGGL((k_rowll<R, REC_GAUSS>), g, b, 0, ctx->stream, ctx->F, ctx->dscratch); break;
+    default: hipLaunchKernelGGL((k_rowll<R, REC_KINETIC>), g, b, 0, ctx->stream, ctx->F, ctx->dscratch);
+  }
+  REC_HIP(hipGetLastError());
+  return REC_OK;
+}
+
+}  // namespace
+
+rec_status rec_load_data(rec_ctx* ctx, const void* X, int64_t ldx) {
+  const int64_t N = ctx->cfg.N;
+  if (ctx->cfg.model == REC_GAUSS) {
+    hipLaunchKernelGGL(k_load_f32, dim3(N), dim3(FT), 0, ctx->stream, (const float*)X, ldx,
+                       ctx->F.M, ctx->F.Mp, (float*)ctx->F.xf, (double*)ctx->F.sq, ctx->err_flag);
+  } else {
+    hipLaunchKernelGGL(k_load_int8, dim3(N), dim3(FT), 0, ctx->stream, (const int8_t*)X, ldx,
+                       ctx->F.M, ctx->F.Mp, ctx->cfg.model == REC_KINETIC ? 1 : 0,
+                       (int8_t*)ctx->F.xs, (int8_t*)ctx->F.ys, ctx->err_flag);
+  }
+  REC_HIP(hipGetLastError());
+  return REC_OK;
+}
+
+void rec_wtable_clear(rec_ctx* ctx) {
+  hipMemsetAsync(ctx->W.keys, 0xff, (ctx->W.mask + 1) * sizeof(uint64_t), ctx->stream);
+  hipMemsetAsync(ctx->W.count, 0, sizeof(int64_t), ctx->stream);
+}
+
+rec_status rec_wtable_insert_list(rec_ctx* ctx, int64_t n, const int32_t* ei, const int32_t* ej,
+                                  const double* w) {
+  if (n <= 0) return REC_OK;
+  hipLaunchKernelGGL(k_winsert, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, ctx->W, n, ei, ej,
+                     w, ctx->cfg.N, ctx->cfg.model == REC_KINETIC ? 1 : 0, ctx->err_flag);
+  REC_HIP(hipGetLastError());
+  return REC_OK;
+}
+
+// Sorted list of nonzero W entries into wi/wj/wv, then the row lists.
+rec_status rec_wtable_compact(rec_ctx* ctx, int64_t* nnz_out) {
+  const uint64_t cap = ctx->W.mask + 1;
+  int64_t* d_n = ctx->counter + 4;
+  REC_HIP(hipMemsetAsync(d_n, 0, sizeof(int64_t), ctx->stream));
+  hipLaunchKernelGGL(k_wcompact, dim3((cap + 255) / 256), dim3(256), 0, ctx->stream, ctx->W, cap,
+                     ctx->sb.klo[0], ctx->sb.val[0], d_n, ctx->max_nnz);
+  int64_t n = 0;
+  REC_HIP(hipMemcpyAsync(&n, d_n, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  if (n > ctx->max_nnz) {
+    ctx->err = "more nonzero couplings than max_nnz";
+    return REC_E_NOMEM;
+  }
+  const int nb = bits_for(ctx->cfg.N);
+  Digit dg[8];
+  int nd = 0;
+  for (int s = 0; s < nb; s += 8) dg[nd++] = {0, s};
+  for (int s = 0; s < nb; s += 8) dg[nd++] = {0, 32 + s};
+  int cur = 0;
+  rec_status st = rec_radix_sort(ctx, n, dg, nd, &cur);
+  if (st != REC_OK) return st;
+  if (n > 0)
+    hipLaunchKernelGGL(k_wunpack, dim3((n + 255) / 256), dim3(256), 0, ctx->stream,
+                       ctx->sb.klo[cur], ctx->sb.val[cur], ctx->W.vals, n, ctx->wi, ctx->wj, ctx->wv);
+  // row lists: both directions for symmetric models
+  const int directed = ctx->cfg.model == REC_KINETIC;
+  int64_t nrec = directed ? n : 2 * n;
+  REC_HIP(hipMemsetAsync(ctx->cnt, 0, sizeof(int64_t) * (ctx->cfg.N + 1), ctx->stream));
+  if (n > 0)
+    hipLaunchKernelGGL(k_csr_records, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, ctx->wi,
+                       ctx->wj, n, directed, ctx->sb.klo[0], ctx->sb.val[0], ctx->cnt);
+  cur = 0;
+  st = rec_radix_sort(ctx, nrec, dg, nd, &cur);
+  if (st != REC_OK) return st;
+  st = rec_exclusive_scan(ctx, ctx->cnt, ctx->row_off, ctx->cfg.N + 1, nullptr);
+  if (st != REC_OK) return st;
+  if (nrec > 0)
+    hipLaunchKernelGGL(k_csr_fill, dim3((nrec + 255) / 256), dim3(256), 0, ctx->stream,
+                       ctx->sb.klo[cur], ctx->sb.val[cur], ctx->wv, nrec, ctx->col, ctx->colw);
+  REC_HIP(hipGetLastError());
+  *nnz_out = n;
+  return REC_OK;
+}
+
+rec_status rec_rebuild_fields(rec_ctx* ctx) {
+  int64_t nnz;
+  rec_status st = rec_wtable_compact(ctx, &nnz);
+  if (st != REC_OK) return st;
+  return ctx->fp32 ? launch_fields_r<float>(ctx) : launch_fields_r<double>(ctx);
+}
+
+rec_status rec_fit_theta(rec_ctx* ctx) {
+  return ctx->fp32 ? launch_theta_r<float>(ctx) : launch_theta_r<double>(ctx);
+}
+
+rec_status rec_eval_objective(rec_ctx* ctx, double* out) {
+  rec_status st = ctx->fp32 ? launch_rowll_r<float>(ctx) : launch_rowll_r<double>(ctx);
+  if (st != REC_OK) return st;
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(FT), 0, ctx->stream, ctx->dscratch, ctx->cfg.N,
+                     ctx->dresult + 0);
+  // penalty over the sorted W list (wi/wj/wv are current after a compaction)
+  int64_t nnz;
+  st = rec_wtable_compact(ctx, &nnz);
+  if (st != REC_OK) return st;
+  const int64_t nchunk = 1024;
+  hipLaunchKernelGGL(k_abs_partial, dim3(nchunk / 256), dim3(256), 0, ctx->stream, ctx->wv, nnz,
+                     ctx->dscratch, nchunk);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(FT), 0, ctx->stream, ctx->dscratch, nchunk,
+                     ctx->dresult + 1);
+  hipLaunchKernelGGL(k_combine_obj, dim3(1), dim3(1), 0, ctx->stream, ctx->dresult + 0,
+                     ctx->dresult + 1, ctx->cfg.lambda, ctx->dresult + 2);
+  REC_HIP(hipMemcpyAsync(out, ctx->dresult + 2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  REC_HIP(hipGetLastError());
+  return REC_OK;
+}

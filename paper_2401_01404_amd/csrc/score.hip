@@ -1,0 +1,502 @@
+// Exact pair scores [Alg. 2, function D] and coordinate updates [Alg. 2 loop
+// body] on gfx950.
+//
+// One 64-lane wavefront owns one pair at a time; its lanes split the M
+// samples (lane l holds samples c*64*VEC + l*VEC + k, so every load
+// instruction of the wave reads one contiguous block).  The j-side row is
+// read once into registers and every Newton step afterwards is register
+// only; consecutive pairs with the same i keep the i-side row.
+//
+// Ising / kinetic score.  For x in {-1, 0, 1} (0 = padding) and t = tanh h,
+//   x tanh(h + delta x) = (u + tau) / (1 + u tau),   u = x t,  tau = tanh delta
+// (tanh addition formula), and
+//   log cosh(h + delta x) - log cosh h = log cosh delta + log(1 + u tau).
+// So the derivative of the smooth part of the objective change,
+//   Phi(tau) = c S - sum_m y_m,  y_m = (u_m + tau) / (1 + u_m tau),
+// costs one reciprocal per sample and side, and the gain at the root is
+//   c delta S - n M log cosh delta - sum log(1 + u tau) - lambda (|w| - |w0|)
+// (c = n = 2 for the symmetric Ising model, whose pair touches the
+// conditionals of i and j [App. A]; c = n = 1 for the kinetic model, where
+// only row i's conditional depends on W_ij).  Phi is decreasing in tau, and
+// the L1 kink sits at tau0 = tanh(-w0) (w = 0): if |Phi(tau0)| <= lambda the
+// optimum is w = 0, else the root of Phi = s lambda (s = sign Phi(tau0))
+// lies in (tau0, 1) or (-1, tau0); Newton steps inside that bracket,
+// bisection otherwise.  dPhi/dtau uses 1 - y^2 = (1 - u^2)(1 - tau^2)/(1 + u tau)^2.
+//
+// Gaussian score: closed form.  With residuals r_i = x_i + theta_i^2 m_i the
+// change of the two conditionals [App. A] is a delta - b delta^2 / 2 with
+// a = -(r_i . x_j + r_j . x_i), b = theta_i^2 |x_j|^2 + theta_j^2 |x_i|^2,
+// maximised with the L1 term by soft thresholding.
+#include <math.h>
+
+#include "common.hpp"
+#include "ctx.hpp"
+
+namespace {
+
+template <class R> struct Prec;
+template <> struct Prec<float> {
+  static constexpr double tol = 3e-5;   // next Newton error ~ tol^2, below float noise
+  static constexpr int maxit = 24;
+};
+template <> struct Prec<double> {
+  static constexpr double tol = 1e-12;
+  static constexpr int maxit = 60;
+};
+
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ float tanh_(float x) { return tanhf(x); }
+__device__ __forceinline__ double tanh_(double x) { return tanh(x); }
+__device__ __forceinline__ float log_(float x) { return __logf(x); }
+__device__ __forceinline__ double log_(double x) { return log(x); }
+
+// load VEC int8 samples as floats
+template <int VEC>
+__device__ __forceinline__ void ld_x(const int8_t* p, float* o) {
+  if constexpr (VEC == 4) {
+    int v = *reinterpret_cast<const int*>(p);
+    o[0] = (float)(int8_t)(v & 0xff);
+    o[1] = (float)(int8_t)((v >> 8) & 0xff);
+    o[2] = (float)(int8_t)((v >> 16) & 0xff);
+    o[3] = (float)(int8_t)((v >> 24) & 0xff);
+  } else if constexpr (VEC == 2) {
+    short v = *reinterpret_cast<const short*>(p);
+    o[0] = (float)(int8_t)(v & 0xff);
+    o[1] = (float)(int8_t)((v >> 8) & 0xff);
+  } else {
+    o[0] = (float)p[0];
+  }
+}
+
+template <int VEC, class R>
+__device__ __forceinline__ void ld_r(const R* p, R* o) {
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) o[k] = p[k];
+}
+
+template <int VEC>
+__device__ __forceinline__ void ld_f(const float* p, float* o) {
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) o[k] = p[k];
+}
+
+// offset of this lane's k-th sample of chunk c
+template <int VEC>
+__device__ __forceinline__ int64_t smp(int c, int lane) {
+  return (int64_t)c * (REC_WAVE * VEC) + (int64_t)lane * VEC;
+}
+
+__device__ __forceinline__ double lookup_w(const WTable& W, int i, int j, bool directed) {
+  if (W.keys == nullptr) return 0.0;
+  int64_t s = rec_hash_find(W.keys, W.mask, rec_pair_key(i, j, directed), REC_MAX_PROBE);
+  return s < 0 ? 0.0 : W.vals[s];
+}
+
+// Per-pair registers of one lane.
+template <class R, int NPL>
+struct Lane {
+  R ti[NPL];      // i side: tanh h_i (Ising / kinetic); r_i (Gaussian)
+  R xi[NPL];      // i side: x_i (symmetric) or target y_i (kinetic)
+  R u[NPL];       // x_j t_i (Ising / kinetic); x_j (Gaussian)
+  R v[NPL];       // x_i t_j (Ising); r_j (Gaussian)
+};
+
+// sum over the lane's samples of y = (a + tau)/(1 + a tau) and y^2
+template <class R, int NPL>
+__device__ __forceinline__ void side_sums(const R* a, R tau, R& A, R& Q) {
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    R d = fma(a[k], tau, R(1));
+    R r = rcp_(d);
+    R y = (a[k] + tau) * r;
+    A += y;
+    Q = fma(y, y, Q);
+  }
+}
+
+// sum over the lane's samples of log(1 + a tau), by products of 4 factors
+template <class R, int NPL>
+__device__ __forceinline__ double side_logs(const R* a, R tau) {
+  double L = 0.0;
+#pragma unroll
+  for (int k0 = 0; k0 < NPL; k0 += 4) {
+    R prod = R(1);
+#pragma unroll
+    for (int k = k0; k < k0 + 4 && k < NPL; ++k) prod *= fma(a[k], tau, R(1));
+    L += (double)log_(prod);
+  }
+  return L;
+}
+
+struct PairOut { double gain, w, w0; };
+
+// Exact score of pair (i, j) for the Ising (TWO = true) or kinetic model,
+// with the lane registers already holding u (and v).  Sc = c S (exact).
+template <class R, int NPL, bool TWO>
+__device__ PairOut solve_ising(const Lane<R, NPL>& L, double Sc, double w0, double lambda,
+                               int64_t M, int64_t Mp) {
+  constexpr double nsides = TWO ? 2.0 : 1.0;
+  const double npad = (double)(Mp - M);
+  auto eval = [&](double tau, double& phi, double& dphi) {
+    // the two sides are summed apart and added once, so (i,j) and (j,i) give
+    // the same bits
+    R A = R(0), Q = R(0), A2 = R(0), Q2 = R(0);
+    side_sums<R, NPL>(L.u, (R)tau, A, Q);
+    if constexpr (TWO) side_sums<R, NPL>(L.v, (R)tau, A2, Q2);
+    double As = rec_wave_sum((double)A + (double)A2);
+    double Qs = rec_wave_sum((double)Q + (double)Q2);
+    double t = (double)(R)tau;
+    phi = Sc - As + nsides * npad * t;
+    double om = 1.0 - t * t;
+    dphi = -((nsides * (double)Mp - Qs) / om - nsides * npad);
+  };
+  PairOut o;
+  o.w0 = w0;
+  double tau0 = (w0 == 0.0) ? 0.0 : (double)tanh_((R)(-w0));
+  double phi, dphi;
+  eval(tau0, phi, dphi);
+  double tau;
+  if (fabs(phi) <= lambda) {
+    if (w0 == 0.0) { o.gain = 0.0; o.w = 0.0; return o; }
+    tau = tau0;
+    o.w = 0.0;
+  } else {
+    double s = phi > 0 ? 1.0 : -1.0;
+    double target = s * lambda;
+    double lo = s > 0 ? tau0 : -1.0, hi = s > 0 ? 1.0 : tau0;
+    double f = phi - target, df = dphi;
+    tau = tau0;
+    for (int it = 0; it < Prec<R>::maxit; ++it) {
+      if (f > 0) lo = tau; else hi = tau;
+      double tn = (df < 0) ? tau - f / df : 0.5 * (lo + hi);
+      if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+      double step = tn - tau;
+      tau = tn;
+      if (fabs(step) <= Prec<R>::tol * fmax(fabs(tau), 1e-4)) break;
+      eval(tau, phi, dphi);
+      f = phi - target;
+      df = dphi;
+    }
+    tau = (double)(R)tau;
+    double d = rec_atanh(tau);
+    double w = w0 + d;
+    o.w = s > 0 ? fmax(w, 0.0) : fmin(w, 0.0);
+  }
+  double Ls = side_logs<R, NPL>(L.u, (R)tau);
+  if constexpr (TWO) Ls += side_logs<R, NPL>(L.v, (R)tau);
+  Ls = rec_wave_sum(Ls);
+  double d = rec_atanh(tau);
+  double g = Sc * d - nsides * (double)M * rec_lcosh_tau(tau) - Ls -
+             lambda * (fabs(o.w) - fabs(w0));
+  o.gain = g;
+  return o;
+}
+
+// Gaussian closed form with u = x_j, v = r_j, ti = r_i, xi = x_i in the lane.
+template <class R, int NPL>
+__device__ PairOut solve_gauss(const Lane<R, NPL>& L, double vi, double vj, double sqi, double sqj,
+                               double w0, double lambda) {
+  R a = R(0);
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) a = fma(L.ti[k], L.u[k], fma(L.v[k], L.xi[k], a));
+  double as = -rec_wave_sum((double)a);
+  double b = vi * sqj + vj * sqi;
+  double z = w0 + as / b;
+  double ws = z > 0 ? fmax(z - lambda / b, 0.0) : fmin(z + lambda / b, 0.0);
+  double d = ws - w0;
+  PairOut o;
+  o.w0 = w0;
+  o.w = ws;
+  o.gain = as * d - 0.5 * b * d * d - lambda * (fabs(ws) - fabs(w0));
+  return o;
+}
+
+// Load the i-side registers of node i.
+template <class R, int NPL, int MODEL>
+__device__ __forceinline__ void load_i(const Fields& F, int i, Lane<R, NPL>& L, int lane) {
+  constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  const R* Hr = reinterpret_cast<const R*>(MODEL == REC_GAUSS ? F.H : F.T) + (int64_t)i * F.Mp;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    int64_t o = smp<VEC>(c, lane);
+    ld_r<VEC>(Hr + o, L.ti + c * VEC);
+    float xv[VEC];
+    if constexpr (MODEL == REC_GAUSS) ld_f<VEC>(F.xf + (int64_t)i * F.Mp + o, xv);
+    else ld_x<VEC>((MODEL == REC_KINETIC ? F.ys : F.xs) + (int64_t)i * F.Mp + o, xv);
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) L.xi[c * VEC + k] = (R)xv[k];
+  }
+}
+
+// Load the j side and form u, v; returns c S for the Ising / kinetic models.
+template <class R, int NPL, int MODEL>
+__device__ __forceinline__ double load_j(const Fields& F, int j, Lane<R, NPL>& L, int lane) {
+  constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    int64_t o = smp<VEC>(c, lane);
+    float xv[VEC];
+    if constexpr (MODEL == REC_GAUSS) {
+      ld_f<VEC>(F.xf + (int64_t)j * F.Mp + o, xv);
+      R rv[VEC];
+      ld_r<VEC>(reinterpret_cast<const R*>(F.H) + (int64_t)j * F.Mp + o, rv);
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) { L.u[c * VEC + k] = (R)xv[k]; L.v[c * VEC + k] = rv[k]; }
+    } else {
+      ld_x<VEC>(F.xs + (int64_t)j * F.Mp + o, xv);
+      R tv[VEC];
+      if constexpr (MODEL == REC_ISING)
+        ld_r<VEC>(reinterpret_cast<const R*>(F.T) + (int64_t)j * F.Mp + o, tv);
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        int q = c * VEC + k;
+        L.u[q] = (R)xv[k] * L.ti[q];
+        if constexpr (MODEL == REC_ISING) L.v[q] = L.xi[q] * tv[k];
+        s += xv[k] * (float)L.xi[q];      // +-1 products: exact in float
+      }
+    }
+  }
+  if constexpr (MODEL == REC_GAUSS) return 0.0;
+  int si = (int)s;
+  si = rec_wave_sum(si);
+  return (MODEL == REC_ISING ? 2.0 : 1.0) * (double)si;
+}
+
+template <class R, int NPL, int MODEL>
+__device__ __forceinline__ PairOut solve(const Fields& F, const Lane<R, NPL>& L, double Sc, int i,
+                                         int j, double w0, double lambda) {
+  if constexpr (MODEL == REC_GAUSS) {
+    double vi = F.theta[i] * F.theta[i], vj = F.theta[j] * F.theta[j];
+    return solve_gauss<R, NPL>(L, vi, vj, F.sq[i], F.sq[j], w0, lambda);
+  } else {
+    return solve_ising<R, NPL, MODEL == REC_ISING>(L, Sc, w0, lambda, F.M, F.Mp);
+  }
+}
+
+template <class R, int NPL, int MODEL>
+__global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda, int64_t P,
+                                               const int32_t* __restrict__ I,
+                                               const int32_t* __restrict__ J,
+                                               const uint32_t* __restrict__ slot,
+                                               double* __restrict__ gain_out,
+                                               double* __restrict__ w_out, double* __restrict__ ovf,
+                                               uint64_t cache_cap, int32_t* err, int ppw,
+                                               int64_t* evals) {
+  const int lane = rec_lane();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE;
+  int64_t p0 = wave * ppw;
+  if (p0 >= P) return;
+  int64_t p1 = p0 + ppw < P ? p0 + ppw : P;
+  Lane<R, NPL> L;
+  int cur = -1;
+  int64_t n_eval = 0;
+  for (int64_t p = p0; p < p1; ++p) {
+    int i = I[p], j = J[p];
+    uint64_t o = slot ? (uint64_t)slot[p] : (uint64_t)p;
+    double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
+    if (i < 0 || j < 0 || i >= F.N || j >= F.N || i == j) {
+      if (lane == 0) {
+        *dst = __builtin_nan("");
+        if (w_out) w_out[p] = __builtin_nan("");
+        atomicOr(err, 1);
+      }
+      continue;
+    }
+    if (i != cur) { load_i<R, NPL, MODEL>(F, i, L, lane); cur = i; }
+    double Sc = load_j<R, NPL, MODEL>(F, j, L, lane);
+    double w0 = lookup_w(W, i, j, MODEL == REC_KINETIC);
+    PairOut r = solve<R, NPL, MODEL>(F, L, Sc, i, j, w0, lambda);
+    double g = r.gain;
+    if constexpr (sizeof(R) == 4) g = (double)(float)g;   // FP32 scores
+    if (lane == 0) {
+      *dst = g;
+      if (w_out) w_out[p] = r.w;
+    }
+    ++n_eval;
+  }
+  if (lane == 0 && evals) atomicAdd((unsigned long long*)evals, (unsigned long long)n_eval);
+}
+
+// One round of node-disjoint updates: pair p runs when it is the earliest
+// pending pair of both its rows (first[i] == first[j] == p); such pairs touch
+// disjoint rows, so the round equals the sequential rank order.
+template <class R, int NPL, int MODEL>
+__global__ __launch_bounds__(256) void k_update(Fields F, WTable W, double lambda, int64_t m,
+                                                const int32_t* __restrict__ I,
+                                                const int32_t* __restrict__ J,
+                                                const int32_t* __restrict__ first, uint8_t* done,
+                                                double* dw, int32_t* err) {
+  constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  const int lane = rec_lane();
+  const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE;
+  if (p >= m || done[p]) return;
+  int i = I[p], j = J[p];
+  if (first[i] != (int32_t)p) return;
+  if (MODEL != REC_KINETIC && first[j] != (int32_t)p) return;
+  Lane<R, NPL> L;
+  load_i<R, NPL, MODEL>(F, i, L, lane);
+  double Sc = load_j<R, NPL, MODEL>(F, j, L, lane);
+  bool directed = MODEL == REC_KINETIC;
+  double w0 = lookup_w(W, i, j, directed);
+  PairOut r = solve<R, NPL, MODEL>(F, L, Sc, i, j, w0, lambda);
+  double d = r.w - w0;
+  if (d != 0.0) {
+    // rows of H (and T): h_i += d x_j, h_j += d x_i [App. A, O(1) field bookkeeping]
+    R* H = reinterpret_cast<R*>(F.H);
+    R* T = reinterpret_cast<R*>(F.T);
+    for (int side = 0; side < (MODEL == REC_KINETIC ? 1 : 2); ++side) {
+      int row = side == 0 ? i : j, other = side == 0 ? j : i;
+      double scale = d;
+      if constexpr (MODEL == REC_GAUSS) scale = d * F.theta[row] * F.theta[row];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        int64_t o = smp<VEC>(c, lane);
+        float xv[VEC];
+        if constexpr (MODEL == REC_GAUSS) ld_f<VEC>(F.xf + (int64_t)other * F.Mp + o, xv);
+        else ld_x<VEC>(F.xs + (int64_t)other * F.Mp + o, xv);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          int64_t idx = (int64_t)row * F.Mp + o + k;
+          R h = H[idx] + (R)(scale * (double)xv[k]);
+          if (o + k < F.M) {
+            H[idx] = h;
+            if constexpr (MODEL != REC_GAUSS) T[idx] = tanh_(h);
+          }
+        }
+      }
+    }
+    if (lane == 0) {
+      bool ins;
+      int64_t s = rec_hash_insert(W.keys, W.mask, rec_pair_key(i, j, directed), REC_MAX_PROBE, &ins);
+      if (s < 0) atomicOr(err, 2);
+      else {
+        W.vals[s] = r.w;
+        if (ins) atomicAdd((unsigned long long*)W.count, 1ULL);
+      }
+    }
+  }
+  if (lane == 0) {
+    dw[p] = fabs(d);
+    done[p] = 1;
+  }
+}
+
+template <class R, int MODEL>
+rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
+                          const uint32_t* slot, double* gain_out, double* w_out, const Cache* C) {
+  const int ppw = 8;
+  int64_t waves = (P + ppw - 1) / ppw;
+  int64_t blocks = (waves * REC_WAVE + 255) / 256;
+  double* ovf = C ? C->ovf : nullptr;
+  uint64_t cap = C ? (C->mask + 1) : 0;
+  int64_t* ev = ctx->counter + 1;
+#define REC_SC(NPL)                                                                              \
+  hipLaunchKernelGGL((k_score<R, NPL, MODEL>), dim3(blocks), dim3(256), 0, ctx->stream, ctx->F,  \
+                     ctx->W, ctx->cfg.lambda, P, I, J, slot, gain_out, w_out, ovf, cap,          \
+                     ctx->err_flag, ppw, ev)
+  switch (ctx->F.npl) {
+    case 1: REC_SC(1); break;
+    case 2: REC_SC(2); break;
+    case 4: REC_SC(4); break;
+    case 8: REC_SC(8); break;
+    case 16: REC_SC(16); break;
+    case 32: REC_SC(32); break;
+    default: ctx->err = "unsupported sample count"; return REC_E_INVAL;
+  }
+#undef REC_SC
+  REC_HIP(hipGetLastError());
+  return REC_OK;
+}
+
+template <class R, int MODEL>
+rec_status launch_update_m(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
+                           const int32_t* first, uint8_t* done, double* dw) {
+  int64_t blocks = (m * REC_WAVE + 255) / 256;
+#define REC_UP(NPL)                                                                              \
+  hipLaunchKernelGGL((k_update<R, NPL, MODEL>), dim3(blocks), dim3(256), 0, ctx->stream, ctx->F, \
+                     ctx->W, ctx->cfg.lambda, m, I, J, first, done, dw, ctx->err_flag)
+  switch (ctx->F.npl) {
+    case 1: REC_UP(1); break;
+    case 2: REC_UP(2); break;
+    case 4: REC_UP(4); break;
+    case 8: REC_UP(8); break;
+    case 16: REC_UP(16); break;
+    case 32: REC_UP(32); break;
+    default: ctx->err = "unsupported sample count"; return REC_E_INVAL;
+  }
+#undef REC_UP
+  REC_HIP(hipGetLastError());
+  return REC_OK;
+}
+
+template <class R>
+rec_status launch_score_r(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
+                          const uint32_t* slot, double* g, double* w, const Cache* C) {
+  switch (ctx->cfg.model) {
+    case REC_ISING: return launch_score_m<R, REC_ISING>(ctx, P, I, J, slot, g, w, C);
+    case REC_GAUSS: return launch_score_m<R, REC_GAUSS>(ctx, P, I, J, slot, g, w, C);
+    case REC_KINETIC: return launch_score_m<R, REC_KINETIC>(ctx, P, I, J, slot, g, w, C);
+  }
+  return REC_E_INVAL;
+}
+
+template <class R>
+rec_status launch_update_r(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
+                           const int32_t* first, uint8_t* done, double* dw) {
+  switch (ctx->cfg.model) {
+    case REC_ISING: return launch_update_m<R, REC_ISING>(ctx, m, I, J, first, done, dw);
+    case REC_GAUSS: return launch_update_m<R, REC_GAUSS>(ctx, m, I, J, first, done, dw);
+    case REC_KINETIC: return launch_update_m<R, REC_KINETIC>(ctx, m, I, J, first, done, dw);
+  }
+  return REC_E_INVAL;
+}
+
+}  // namespace
+
+rec_status rec_timing_resolve(rec_ctx* ctx) {
+  for (size_t k = 0; k < ctx->ev_used; ++k) {
+    REC_HIP(hipEventSynchronize(ctx->ev[k].second));
+    float ms = 0.f;
+    REC_HIP(hipEventElapsedTime(&ms, ctx->ev[k].first, ctx->ev[k].second));
+    ctx->score_ms += ms;
+  }
+  ctx->ev_used = 0;
+  return REC_OK;
+}
+
+rec_status rec_launch_score(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
+                            const uint32_t* slot, double* gain_out, double* w_out,
+                            const Cache* cache) {
+  if (P <= 0) return REC_OK;
+  if (ctx->timing) {
+    if (ctx->ev_used == 256) {
+      rec_status st = rec_timing_resolve(ctx);
+      if (st != REC_OK) return st;
+    }
+    if (ctx->ev_used == ctx->ev.size()) {
+      hipEvent_t a, b;
+      REC_HIP(hipEventCreate(&a));
+      REC_HIP(hipEventCreate(&b));
+      ctx->ev.push_back({a, b});
+    }
+    REC_HIP(hipEventRecord(ctx->ev[ctx->ev_used].first, ctx->stream));
+  }
+  rec_status st = ctx->fp32 ? launch_score_r<float>(ctx, P, I, J, slot, gain_out, w_out, cache)
+                            : launch_score_r<double>(ctx, P, I, J, slot, gain_out, w_out, cache);
+  if (ctx->timing && st == REC_OK) {
+    REC_HIP(hipEventRecord(ctx->ev[ctx->ev_used].second, ctx->stream));
+    ++ctx->ev_used;
+    ++ctx->score_launches;
+    ctx->score_pairs += P;
+  }
+  return st;
+}
+
+rec_status rec_launch_update_round(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
+                                   const int32_t* first, uint8_t* done, double* dw) {
+  if (m <= 0) return REC_OK;
+  return ctx->fp32 ? launch_update_r<float>(ctx, m, I, J, first, done, dw)
+                   : launch_update_r<double>(ctx, m, I, J, first, done, dw);
+}

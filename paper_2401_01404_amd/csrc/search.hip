@@ -1,0 +1,943 @@
+// Candidate search: FindBest [Alg. 3] over NNDescent [Alg. 4] or exact KNN,
+// the exhaustive top-m, and the update rounds of GCD [Alg. 2].
+//
+// Within one FindBest level the node set S is held as a sorted array of
+// global ids and every KNN list uses local indices into S (so "index asc"
+// ties break the same way on local and global ids).
+//
+// NNDescent, order-independent form: every iteration builds the undirected
+// view U of the current lists G (out-neighbours plus at most k in-neighbours
+// per node, the k with the smallest (32-bit counter hash, index)), then for
+// every node a at once G'[a] = top-k of G[a] and all second neighbours of a
+// in U, ranked by (gain desc, index asc) [Alg. 4, parallel per node as in
+// App. B].  Scores go through a per-call cache [App. B, caching]: a pair is
+// claimed in an open-addressing table the first time it is met and scored
+// once; later meetings read the stored gain.
+//
+// FindBest level: D+ = the 2m best directed edges of G ranked by (gain desc,
+// min id, max id, source), D = their unordered pairs, S' = nodes whose every
+// out-edge lies in D, recurse on S'; the base case |S|^2 <= 4m scores all
+// pairs of S.  D of every level goes to a pool whose best m are returned.
+#include <algorithm>
+#include <chrono>
+#include <vector>
+
+#include "common.hpp"
+#include "ctx.hpp"
+
+namespace {
+
+constexpr int BT = 256;
+
+__device__ __forceinline__ bool better(double g1, int i1, double g2, int i2) {
+  // NaN ranks last
+  if (g1 != g1) return false;
+  if (g2 != g2) return true;
+  return g1 > g2 || (g1 == g2 && i1 < i2);
+}
+
+// Claim a score slot for pair (i, j) (global ids).  A new claim is queued on
+// the to-score list.  Returns the value slot (>= table size: overflow area).
+struct ClaimArgs {
+  Cache C;
+  int32_t* ts_i;
+  int32_t* ts_j;
+  uint32_t* ts_slot;
+  int64_t* ts_n;
+  int64_t ts_cap;
+  int64_t* ovf_n;
+  int32_t* err;
+  int directed;
+};
+
+__device__ uint32_t claim(const ClaimArgs& A, int i, int j) {
+  bool ins = false;
+  int64_t s = rec_hash_insert(A.C.keys, A.C.mask, rec_pair_key(i, j, A.directed != 0),
+                              REC_MAX_PROBE, &ins);
+  uint64_t slot;
+  if (s >= 0 && !ins) return (uint32_t)s;
+  if (s < 0) {
+    int64_t o = (int64_t)atomicAdd((unsigned long long*)A.ovf_n, 1ULL);
+    if (o >= A.C.ovf_cap) { atomicOr(A.err, 16); return 0xffffffffu; }
+    slot = (A.C.mask + 1) + (uint64_t)o;
+  } else {
+    slot = (uint64_t)s;
+  }
+  int64_t p = (int64_t)atomicAdd((unsigned long long*)A.ts_n, 1ULL);
+  if (p >= A.ts_cap) { atomicOr(A.err, 16); return 0xffffffffu; }
+  A.ts_i[p] = i;
+  A.ts_j[p] = j;
+  A.ts_slot[p] = (uint32_t)slot;
+  return (uint32_t)slot;
+}
+
+__device__ __forceinline__ double slot_gain(const Cache& C, uint32_t slot) {
+  if (slot == 0xffffffffu) return __builtin_nan("");
+  uint64_t cap = C.mask + 1;
+  return slot < cap ? C.vals[slot] : C.ovf[slot - cap];
+}
+
+// ---------------------------------------------------------------- init --
+// Random initial list of node a [Alg. 4, first step]: Floyd's sampling of k
+// distinct values from the n-1 other local indices, draws from the counter
+// generator keyed by (level, global id of a, draw index).
+__global__ __launch_bounds__(REC_WAVE) void k_knn_init(const int32_t* S, int64_t n, int k,
+                                                       uint64_t seed, int level, int use_bitmap,
+                                                       int32_t* cand_v, uint32_t* cand_slot,
+                                                       ClaimArgs A) {
+  extern __shared__ uint32_t bm[];
+  const int64_t a = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t words = (n + 31) / 32;
+  if (use_bitmap)
+    for (int64_t w = lane; w < words; w += REC_WAVE) bm[w] = 0;
+  __syncthreads();
+  int32_t* out = cand_v + a * k;
+  if (lane == 0) {
+    const uint64_t tag = ((uint64_t)(uint32_t)level << 32) | (uint32_t)S[a];
+    int c = 0;
+    for (int64_t t = (n - 1) - k; t <= n - 2; ++t) {
+      int64_t v = (int64_t)rec_below(rec_ctr(seed, REC_STREAM_INIT, tag, (uint64_t)t), (uint64_t)(t + 1));
+      bool has;
+      if (use_bitmap) has = (bm[v >> 5] >> (v & 31)) & 1u;
+      else {
+        has = false;
+        for (int q = 0; q < c; ++q) {
+          int64_t b = out[q];
+          int64_t vb = b < a ? b : b - 1;   // back to the value space [0, n-2]
+          if (vb == v) { has = true; break; }
+        }
+      }
+      int64_t pick = has ? t : v;
+      if (use_bitmap) bm[pick >> 5] |= 1u << (pick & 31);
+      out[c++] = (int32_t)(pick < a ? pick : pick + 1);
+    }
+  }
+  __syncthreads();
+  for (int c = lane; c < k; c += REC_WAVE) {
+    int b = out[c];
+    cand_slot[a * k + c] = claim(A, S[a], S[b]);
+  }
+}
+
+// ------------------------------------------------------------ in-edges --
+// One record per directed edge a -> b of G: sort key (b, hash32, a).
+__global__ void k_in_records(const int32_t* S, const int32_t* Gidx, int64_t n, int k,
+                             uint64_t seed, int level, int iter, uint64_t* khi, uint64_t* klo,
+                             uint32_t* val, int64_t* indeg) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * k) return;
+  int64_t a = e / k;
+  int b = Gidx[e];
+  uint64_t h = rec_ctr(seed, REC_STREAM_CAP, ((uint64_t)(uint32_t)level << 32) | (uint32_t)iter,
+                       ((uint64_t)(uint32_t)S[a] << 32) | (uint32_t)S[b]) >> 32;
+  khi[e] = (uint64_t)b;
+  klo[e] = (h << 32) | (uint64_t)a;
+  val[e] = 0;
+  atomicAdd((unsigned long long*)&indeg[b], 1ULL);
+}
+
+__global__ void k_in_src(const uint64_t* klo, int64_t ne, int32_t* in_src) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ne) in_src[e] = (int32_t)(klo[e] & 0xffffffffu);
+}
+
+// ---------------------------------------------------------- candidates --
+// mode 0: second neighbours in U (NNDescent); mode 1: all of S (exact KNN).
+// pass 0 counts the distinct candidates of a, pass 1 writes them at off[a]
+// (relative to base) and claims their scores.
+struct CandArgs {
+  const int32_t* S;
+  const int32_t* Gidx;
+  const int64_t* inoff;
+  const int32_t* in_src;
+  int64_t n;
+  int k;
+  int mode;
+};
+
+__device__ __forceinline__ int u_size(const CandArgs& P, int64_t b) {
+  int64_t deg = P.inoff[b + 1] - P.inoff[b];
+  return P.k + (int)(deg < P.k ? deg : P.k);
+}
+__device__ __forceinline__ int u_get(const CandArgs& P, int64_t b, int c) {
+  return c < P.k ? P.Gidx[b * P.k + c] : P.in_src[P.inoff[b] + (c - P.k)];
+}
+
+__global__ __launch_bounds__(BT) void k_cand(CandArgs P, int pass, int64_t a0, int64_t a1,
+                                             int64_t* cnt, const int64_t* off, int64_t base,
+                                             int32_t* cand_v, uint32_t* cand_slot, ClaimArgs A) {
+  extern __shared__ uint32_t sm[];
+  const int64_t a = a0 + blockIdx.x;
+  if (a >= a1) return;
+  const int tid = threadIdx.x;
+  const int64_t words = (P.n + 31) / 32;
+  uint32_t* bm = sm;
+  int32_t* ul = reinterpret_cast<int32_t*>(sm + words);   // U(a), at most 2k entries
+  __shared__ int32_t s_cnt;
+  __shared__ int32_t s_nu;
+  for (int64_t w = tid; w < words; w += BT) bm[w] = 0;
+  if (tid == 0) s_cnt = 0;
+  __syncthreads();
+  // exclude a and its current list
+  if (tid == 0) atomicOr(&bm[a >> 5], 1u << (a & 31));
+  if (P.mode == 0)
+    for (int c = tid; c < P.k; c += BT) {
+      int b = P.Gidx[a * P.k + c];
+      atomicOr(&bm[b >> 5], 1u << (b & 31));
+    }
+  int nu = 0;
+  if (P.mode == 0) {
+    nu = u_size(P, a);
+    for (int c = tid; c < nu; c += BT) ul[c] = u_get(P, a, c);
+  }
+  if (tid == 0) s_nu = nu;
+  __syncthreads();
+  const int64_t obase = pass ? off[a] - base : 0;
+  auto emit = [&](int v) {
+    uint32_t old = atomicOr(&bm[v >> 5], 1u << (v & 31));
+    if (old & (1u << (v & 31))) return;
+    int q = atomicAdd(&s_cnt, 1);
+    if (pass) {
+      if (q >= cnt[a]) { atomicOr(A.err, 128); return; }   // count pass disagrees
+      int64_t pos = obase + q;
+      cand_v[pos] = v;
+      cand_slot[pos] = claim(A, P.S[a], P.S[v]);
+    }
+  };
+  if (P.mode == 0) {
+    const int span = 2 * P.k;
+    const int64_t total = (int64_t)s_nu * span;
+    for (int64_t q = tid; q < total; q += BT) {
+      int bi = (int)(q / span), c = (int)(q % span);
+      int b = ul[bi];
+      if (c < u_size(P, b)) emit(u_get(P, b, c));
+    }
+  } else {
+    for (int64_t v = tid; v < P.n; v += BT) emit((int)v);
+  }
+  __syncthreads();
+  if (pass == 0 && tid == 0) cnt[a] = s_cnt;
+}
+
+// ---------------------------------------------------------------- merge --
+// G2[a] = top-k of G[a] (unless start_empty) and the candidates of a; one
+// wave per node, list kept sorted in LDS; adds |G2[a] \ G[a]| to *delta.
+__global__ __launch_bounds__(REC_WAVE) void k_merge(int64_t a0, int64_t a1, int k, int start_empty,
+                                                    const int32_t* Gidx, const double* Ggain,
+                                                    int32_t* G2idx, double* G2gain,
+                                                    const int64_t* cnt, const int64_t* off,
+                                                    int64_t base, const int32_t* cand_v,
+                                                    const uint32_t* cand_slot, Cache C,
+                                                    int64_t* delta, int fixed_count, int32_t* err) {
+  extern __shared__ double lg[];
+  const int64_t a = a0 + blockIdx.x;
+  if (a >= a1) return;
+  const int lane = threadIdx.x;
+  int32_t* li = reinterpret_cast<int32_t*>(lg + k);
+  uint8_t* ln = reinterpret_cast<uint8_t*>(li + k);
+  int count = 0;
+  if (!start_empty) {
+    for (int c = lane; c < k; c += REC_WAVE) {
+      lg[c] = Ggain[a * k + c];
+      li[c] = Gidx[a * k + c];
+      ln[c] = 0;
+    }
+    count = k;
+  }
+  __syncthreads();
+  const int64_t nc = fixed_count ? fixed_count : cnt[a];
+  const int64_t o0 = (fixed_count ? a * (int64_t)fixed_count : off[a]) - base;
+  for (int64_t q0 = 0; q0 < nc; q0 += REC_WAVE) {
+    int64_t q = q0 + lane;
+    bool valid = q < nc;
+    double g = 0.0;
+    int v = 0;
+    if (valid) {
+      v = cand_v[o0 + q];
+      g = slot_gain(C, cand_slot[o0 + q]);
+    }
+    double wg = count == k ? lg[k - 1] : 0.0;
+    int wi = count == k ? li[k - 1] : 0;
+    bool pass = valid && (count < k || better(g, v, wg, wi));
+    uint64_t bal = __ballot(pass);
+    while (bal) {
+      int src = __ffsll((unsigned long long)bal) - 1;
+      bal &= bal - 1;
+      double cg = __shfl(g, src, REC_WAVE);
+      int cv = __shfl(v, src, REC_WAVE);
+      // still better than the current worst?
+      if (count == k && !better(cg, cv, lg[k - 1], li[k - 1])) continue;
+      // insertion point = number of entries better than (cg, cv)
+      int pos = 0;
+      for (int c = lane; c < count; c += REC_WAVE) pos += better(lg[c], li[c], cg, cv) ? 1 : 0;
+      pos = rec_wave_sum(pos);
+      int last = count < k ? count : k - 1;   // highest index written by the shift
+      // shift [pos, last) right by one, from the back in wave-sized chunks
+      for (int c0 = ((last - 1) / REC_WAVE) * REC_WAVE; c0 >= pos - (pos % REC_WAVE) && last > pos;
+           c0 -= REC_WAVE) {
+        int c = c0 + lane;
+        double tg = 0.0;
+        int ti = 0;
+        uint8_t tn = 0;
+        bool mv = c >= pos && c < last;
+        if (mv) { tg = lg[c]; ti = li[c]; tn = ln[c]; }
+        __syncthreads();
+        if (mv) { lg[c + 1] = tg; li[c + 1] = ti; ln[c + 1] = tn; }
+        __syncthreads();
+        if (c0 == 0) break;
+      }
+      if (lane == 0) { lg[pos] = cg; li[pos] = cv; ln[pos] = 1; }
+      __syncthreads();
+      if (count < k) ++count;
+    }
+  }
+  // invariant: a list never holds the same neighbour twice
+  int dupl = 0;
+  for (int c = lane; c < count; c += REC_WAVE)
+    for (int d = 0; d < c; ++d) dupl |= li[d] == li[c];
+  dupl = rec_wave_sum(dupl);
+  if (dupl && lane == 0) atomicOr(err, 64);
+  int nnew = 0;
+  for (int c = lane; c < count; c += REC_WAVE) {
+    G2gain[a * k + c] = lg[c];
+    G2idx[a * k + c] = li[c];
+    nnew += ln[c];
+  }
+  for (int c = count + lane; c < k; c += REC_WAVE) {   // only when n-1 < k (not used)
+    G2gain[a * k + c] = __builtin_nan("");
+    G2idx[a * k + c] = -1;
+  }
+  nnew = rec_wave_sum(nnew);
+  if (lane == 0 && !start_empty) atomicAdd((unsigned long long*)delta, (unsigned long long)nnew);
+}
+
+// ------------------------------------------------------------ level ops --
+// Directed edges a -> G[a][c] as sort records (gain desc, min, max, source).
+// klo = (min << (nb+1)) | (max << 1) | (source is max), nb = bits of an id.
+__global__ void k_edge_records(const int32_t* S, const int32_t* Gidx, const double* Ggain,
+                               int64_t n, int k, int nb, uint64_t* khi, uint64_t* klo,
+                               uint32_t* val) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * k) return;
+  int64_t a = e / k;
+  uint32_t ga = (uint32_t)S[a], gb = (uint32_t)S[Gidx[e]];
+  uint32_t lo = ga < gb ? ga : gb, hi = ga < gb ? gb : ga;
+  khi[e] = rec_desc_key(Ggain[e]);
+  klo[e] = ((uint64_t)lo << (nb + 1)) | ((uint64_t)hi << 1) | (uint64_t)(ga == hi ? 1 : 0);
+  val[e] = (uint32_t)e;
+}
+
+// D+ = first nsel sorted edges: mark their pairs in D, add new ones to the pool.
+__global__ void k_mark_d(const uint64_t* khi, const uint64_t* klo, int64_t nsel, int nb,
+                         uint64_t* dkeys, uint64_t dmask, uint64_t* pkeys, uint64_t pmask,
+                         uint64_t* pool_hi, uint64_t* pool_lo, int64_t* pool_n, int64_t pool_cap,
+                         int32_t* err) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nsel) return;
+  uint64_t lo = klo[e];
+  uint32_t mn = (uint32_t)(lo >> (nb + 1));
+  uint32_t mx = (uint32_t)((lo >> 1) & ((1ULL << nb) - 1));
+  uint64_t key = ((uint64_t)mn << 32) | mx;
+  bool ins;
+  if (rec_hash_insert(dkeys, dmask, key, 4096, &ins) < 0) { atomicOr(err, 32); return; }
+  if (rec_hash_insert(pkeys, pmask, key, 4096, &ins) < 0) { atomicOr(err, 32); return; }
+  if (ins) {
+    int64_t p = (int64_t)atomicAdd((unsigned long long*)pool_n, 1ULL);
+    if (p >= pool_cap) { atomicOr(err, 32); return; }
+    pool_hi[p] = khi[e];
+    pool_lo[p] = key;
+  }
+}
+
+__global__ void k_saturated(const int32_t* S, const int32_t* Gidx, int64_t n, int k,
+                            const uint64_t* dkeys, uint64_t dmask, int64_t* flags) {
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  int all = 1;
+  for (int c = 0; c < k && all; ++c) {
+    uint64_t key = rec_pair_key(S[a], S[Gidx[a * k + c]], false);
+    if (rec_hash_find(dkeys, dmask, key, 4096) < 0) all = 0;
+  }
+  flags[a] = all;
+}
+
+__global__ void k_compact_s(const int32_t* S, const int64_t* flags, const int64_t* pos, int64_t n,
+                            int32_t* S2) {
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a < n && flags[a]) S2[pos[a]] = S[a];
+}
+
+// all pairs a < b of S (base case): claim their scores
+__global__ __launch_bounds__(BT) void k_allpairs_claim(const int32_t* S, int64_t n, uint32_t* slots,
+                                                       ClaimArgs A) {
+  const int64_t a = blockIdx.x;
+  const int64_t rowbase = a * n - a * (a + 1) / 2;   // pairs of rows < a
+  for (int64_t b = a + 1 + threadIdx.x; b < n; b += BT)
+    slots[rowbase + (b - a - 1)] = claim(A, S[a], S[b]);
+}
+
+__global__ __launch_bounds__(BT) void k_allpairs_pool(const int32_t* S, int64_t n,
+                                                      const uint32_t* slots, Cache C,
+                                                      uint64_t* pkeys, uint64_t pmask,
+                                                      uint64_t* pool_hi, uint64_t* pool_lo,
+                                                      int64_t* pool_n, int64_t pool_cap,
+                                                      int32_t* err) {
+  const int64_t a = blockIdx.x;
+  const int64_t rowbase = a * n - a * (a + 1) / 2;
+  for (int64_t b = a + 1 + threadIdx.x; b < n; b += BT) {
+    double g = slot_gain(C, slots[rowbase + (b - a - 1)]);
+    uint64_t key = rec_pair_key(S[a], S[b], false);
+    bool ins;
+    if (rec_hash_insert(pkeys, pmask, key, 4096, &ins) < 0) { atomicOr(err, 32); continue; }
+    if (!ins) continue;
+    int64_t p = (int64_t)atomicAdd((unsigned long long*)pool_n, 1ULL);
+    if (p >= pool_cap) { atomicOr(err, 32); continue; }
+    pool_hi[p] = rec_desc_key(g);
+    pool_lo[p] = key;
+  }
+}
+
+__global__ void k_pool_to_sort(const uint64_t* ph, const uint64_t* pl, int64_t n, uint64_t* khi,
+                               uint64_t* klo, uint32_t* val) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  khi[e] = ph[e];
+  klo[e] = pl[e];
+  val[e] = 0;
+}
+
+__global__ void k_take_best(const uint64_t* khi, const uint64_t* klo, int64_t n, int32_t* oi,
+                            int32_t* oj, double* og) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  oi[e] = (int32_t)(klo[e] >> 32);
+  oj[e] = (int32_t)(klo[e] & 0xffffffffu);
+  og[e] = rec_desc_gain(khi[e]);
+}
+
+__global__ void k_iota(int32_t* S, int64_t n) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) S[e] = (int32_t)e;
+}
+
+__global__ void k_lists_out(const int32_t* S, const int32_t* Gidx, const double* Ggain,
+                            int64_t nk, int32_t* nbr, double* gain) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nk) return;
+  int b = Gidx[e];
+  nbr[e] = b >= 0 ? S[b] : -1;
+  gain[e] = Ggain[e];
+}
+
+// ---- exhaustive ----
+// pairs of rows [r0, r1): symmetric i < j, kinetic all j != i; enumerated
+// row by row into (I, J)
+__global__ __launch_bounds__(BT) void k_rowpairs(int64_t r0, int64_t N, int directed,
+                                                 const int64_t* roff, int32_t* I, int32_t* J) {
+  const int64_t i = r0 + blockIdx.x;
+  const int64_t o = roff[blockIdx.x];
+  if (directed) {
+    for (int64_t j = threadIdx.x; j < N - 1; j += BT) {
+      I[o + j] = (int32_t)i;
+      J[o + j] = (int32_t)(j < i ? j : j + 1);
+    }
+  } else {
+    for (int64_t j = i + 1 + threadIdx.x; j < N; j += BT) {
+      I[o + j - i - 1] = (int32_t)i;
+      J[o + j - i - 1] = (int32_t)j;
+    }
+  }
+}
+
+// append scored pairs with gain >= thr after the kept records
+__global__ void k_ex_append(const int32_t* I, const int32_t* J, const double* g, int64_t np,
+                            double thr, int directed, uint64_t* khi, uint64_t* klo, uint32_t* val,
+                            int64_t* n, int64_t cap) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= np) return;
+  double ge = g[e];
+  if (!(ge >= thr)) return;
+  int64_t p = (int64_t)atomicAdd((unsigned long long*)n, 1ULL);
+  if (p >= cap) return;
+  khi[p] = rec_desc_key(ge);
+  klo[p] = rec_pair_key(I[e], J[e], directed != 0);
+  val[p] = 0;
+}
+
+// ---- update rounds ----
+__global__ void k_first(const int32_t* I, const int32_t* J, int64_t m, const uint8_t* done,
+                        int32_t* first, int directed, int64_t* remaining) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int left = 0;
+  if (p < m && !done[p]) {
+    atomicMin(&first[I[p]], (int32_t)p);
+    if (!directed) atomicMin(&first[J[p]], (int32_t)p);
+    left = 1;
+  }
+  left = rec_wave_sum(left);
+  if (rec_lane() == 0 && left) atomicAdd((unsigned long long*)remaining, (unsigned long long)left);
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+
+__global__ void k_count_pos(const double* dw, int64_t m, int64_t* cnt) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int c = (p < m && dw[p] > 0.0) ? 1 : 0;
+  c = rec_wave_sum(c);
+  if (rec_lane() == 0 && c) atomicAdd((unsigned long long*)cnt, (unsigned long long)c);
+}
+
+__global__ void k_sum1(const double* x, int64_t n, double* out) {
+  __shared__ double sh[BT / REC_WAVE];
+  double acc = 0.0;
+  int64_t per = (n + BT - 1) / BT;
+  int64_t b = (int64_t)threadIdx.x * per, e = b + per < n ? b + per : n;
+  for (int64_t k = b; k < e; ++k) acc += x[k];
+  acc = rec_wave_sum(acc);
+  if (rec_lane() == 0) sh[threadIdx.x / REC_WAVE] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < BT / REC_WAVE; ++w) s += sh[w];
+    *out = s;
+  }
+}
+
+inline int64_t gridn(int64_t n, int b = 256) { return (n + b - 1) / b; }
+
+int bits_for(int64_t v) {
+  int b = 0;
+  while (b < 63 && (int64_t(1) << b) < v) ++b;
+  return b < 1 ? 1 : b;
+}
+
+inline double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Search {
+  rec_ctx* ctx;
+  ClaimArgs A;
+  int64_t* d_ts_n;
+  int64_t* d_ovf_n;
+  int64_t* d_delta;
+  int64_t* d_pool_n;
+  int64_t* d_tmp;
+  int64_t nnd_iters = 0;
+  int levels = 0;
+
+  explicit Search(rec_ctx* c) : ctx(c) {
+    d_ts_n = c->counter + 2;
+    d_ovf_n = c->counter + 3;
+    d_delta = c->counter + 5;
+    d_pool_n = c->counter + 7;
+    d_tmp = c->counter + 8;
+    A.C = c->C;
+    A.ts_i = c->ts_i;
+    A.ts_j = c->ts_j;
+    A.ts_slot = c->ts_slot;
+    A.ts_n = d_ts_n;
+    A.ts_cap = c->cand_cap;
+    A.ovf_n = d_ovf_n;
+    A.err = c->err_flag;
+    A.directed = c->cfg.model == REC_KINETIC;
+  }
+
+  rec_status get(int64_t* dev, int64_t* host) {
+    hipStream_t s = ctx->stream;
+    if (hipMemcpyAsync(host, dev, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      ctx->err = "readback failed";
+      return REC_E_HIP;
+    }
+    return REC_OK;
+  }
+
+  rec_status check_err() {
+    int32_t e = 0;
+    if (hipMemcpyAsync(&e, ctx->err_flag, 4, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      ctx->err = "readback failed";
+      return REC_E_HIP;
+    }
+    if (e & (16 | 32)) {
+      ctx->err = "search buffers exhausted (increase workspace)";
+      return REC_E_NOMEM;
+    }
+    if (e & 2) { ctx->err = "W table full (increase max_nnz)"; return REC_E_NOMEM; }
+    if (e & 64) { ctx->err = "internal: duplicate neighbour in a merged list"; return REC_E_NUMERIC; }
+    if (e & 128) { ctx->err = "internal: candidate passes disagree"; return REC_E_NUMERIC; }
+    if (e) { ctx->err = "device error flag " + std::to_string(e); return REC_E_NUMERIC; }
+    return REC_OK;
+  }
+
+  void clear_cache() {
+    hipMemsetAsync(ctx->C.keys, 0xff, (ctx->C.mask + 1) * sizeof(uint64_t), ctx->stream);
+  }
+
+  // Score every pair queued on the to-score list since the last call.
+  rec_status flush_scores() {
+    int64_t nts = 0;
+    rec_status st = get(d_ts_n, &nts);
+    if (st != REC_OK) return st;
+    if (nts > ctx->cand_cap) { ctx->err = "to-score list overflow"; return REC_E_NOMEM; }
+    st = rec_launch_score(ctx, nts, ctx->ts_i, ctx->ts_j, ctx->ts_slot, ctx->C.vals, nullptr,
+                          &ctx->C);
+    hipMemsetAsync(d_ts_n, 0, sizeof(int64_t), ctx->stream);
+    return st;
+  }
+
+  // KNN lists of S (n nodes) at a level into Gidx/Ggain (k per node).
+  rec_status knn(const int32_t* S, int64_t n, int k, int level, int mode, int* iters) {
+    hipStream_t s = ctx->stream;
+    const uint64_t seed = ctx->cfg.seed;
+    if ((int64_t)k * n > ctx->list_cap) { ctx->err = "KNN lists exceed capacity"; return REC_E_NOMEM; }
+    const int64_t words = (n + 31) / 32;
+    rec_status st;
+    *iters = 0;
+    size_t merge_lds = (size_t)k * (8 + 4 + 1) + 16;
+    if (merge_lds > 64 * 1024) { ctx->err = "k too large for the merge kernel"; return REC_E_INVAL; }
+    if (mode == 0) {
+      // random initial lists [Alg. 4]
+      if (n * (int64_t)k > ctx->cand_cap) { ctx->err = "candidate buffer too small for init"; return REC_E_NOMEM; }
+      int use_bm = words * 4 <= 48 * 1024 ? 1 : 0;
+      hipLaunchKernelGGL(k_knn_init, dim3(n), dim3(REC_WAVE), use_bm ? words * 4 : 0, s, S, n, k,
+                         seed, level, use_bm, ctx->cand_v, ctx->cand_slot, A);
+      if ((st = flush_scores()) != REC_OK) return st;
+      hipLaunchKernelGGL(k_merge, dim3(n), dim3(REC_WAVE), merge_lds, s, (int64_t)0, n, k, 1,
+                         ctx->Gidx, ctx->Ggain, ctx->Gidx, ctx->Ggain, ctx->cnt, ctx->off,
+                         (int64_t)0, ctx->cand_v, ctx->cand_slot, ctx->C, d_delta, k, ctx->err_flag);
+      if ((st = check_err()) != REC_OK) return st;
+    }
+    int max_iter = ctx->cfg.nnd_max_iter;
+    if (max_iter <= 0) {
+      int lg = 0;
+      for (double c = 1; c < (double)n; c *= 2.0 * k) ++lg;
+      max_iter = 2 * lg + 10;
+    }
+    const int iters_to_run = mode == 0 ? max_iter : 1;
+    CandArgs P{S, ctx->Gidx, ctx->inoff, ctx->in_src, n, k, mode};
+    size_t cand_lds = words * 4 + (mode == 0 ? (size_t)2 * k * 4 : 0);
+    if (cand_lds > 64 * 1024) { ctx->err = "node set too large for the candidate kernel"; return REC_E_INVAL; }
+    for (int it = 0; it < iters_to_run; ++it) {
+      P.Gidx = ctx->Gidx;   // the lists ping-pong between two buffers
+      if (mode == 0) {
+        // undirected view U: in-neighbour lists sorted by (hash32, source)
+        int64_t ne = n * k;
+        hipMemsetAsync(ctx->cnt, 0, sizeof(int64_t) * (n + 1), s);
+        hipLaunchKernelGGL(k_in_records, dim3(gridn(ne)), dim3(256), 0, s, S, ctx->Gidx, n, k, seed,
+                           level, it, ctx->sb.khi[0], ctx->sb.klo[0], ctx->sb.val[0], ctx->cnt);
+        int nb = bits_for(n);
+        Digit dg[16];
+        int nd = 0;
+        for (int b = 0; b < nb; b += 8) dg[nd++] = {0, b};
+        for (int b = 32; b < 64; b += 8) dg[nd++] = {0, b};
+        for (int b = 0; b < nb; b += 8) dg[nd++] = {1, b};
+        int cur = 0;
+        if ((st = rec_radix_sort(ctx, ne, dg, nd, &cur)) != REC_OK) return st;
+        if ((st = rec_exclusive_scan(ctx, ctx->cnt, ctx->inoff, n + 1, nullptr)) != REC_OK) return st;
+        hipLaunchKernelGGL(k_in_src, dim3(gridn(ne)), dim3(256), 0, s, ctx->sb.klo[cur], ne, ctx->in_src);
+      }
+      // count distinct candidates per node, then offsets
+      hipLaunchKernelGGL(k_cand, dim3(n), dim3(BT), cand_lds, s, P, 0, (int64_t)0, n, ctx->cnt,
+                         ctx->off, (int64_t)0, ctx->cand_v, ctx->cand_slot, A);
+      hipMemsetAsync(ctx->cnt + n, 0, sizeof(int64_t), s);
+      if ((st = rec_exclusive_scan(ctx, ctx->cnt, ctx->off, n + 1, nullptr)) != REC_OK) return st;
+      std::vector<int64_t> hoff(n + 1);
+      if (hipMemcpyAsync(hoff.data(), ctx->off, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) { ctx->err = "readback failed"; return REC_E_HIP; }
+      hipMemsetAsync(d_delta, 0, sizeof(int64_t), s);
+      // node chunks whose candidates fit the buffer
+      int64_t a0 = 0;
+      while (a0 < n) {
+        int64_t a1 = a0 + 1;
+        while (a1 < n && hoff[a1 + 1] - hoff[a0] <= ctx->cand_cap) ++a1;
+        if (hoff[a1] - hoff[a0] > ctx->cand_cap) { ctx->err = "candidate buffer too small"; return REC_E_NOMEM; }
+        int64_t base = hoff[a0];
+        hipLaunchKernelGGL(k_cand, dim3(a1 - a0), dim3(BT), cand_lds, s, P, 1, a0, a1, ctx->cnt,
+                           ctx->off, base, ctx->cand_v, ctx->cand_slot, A);
+        if ((st = flush_scores()) != REC_OK) return st;
+        hipLaunchKernelGGL(k_merge, dim3(a1 - a0), dim3(REC_WAVE), merge_lds, s, a0, a1, k,
+                           mode == 1 ? 1 : 0, ctx->Gidx, ctx->Ggain, ctx->Gidx2, ctx->Ggain2,
+                           ctx->cnt, ctx->off, base, ctx->cand_v, ctx->cand_slot, ctx->C, d_delta, 0,
+                           ctx->err_flag);
+        a0 = a1;
+      }
+      if ((st = check_err()) != REC_OK) return st;
+      std::swap(ctx->Gidx, ctx->Gidx2);
+      std::swap(ctx->Ggain, ctx->Ggain2);
+      *iters = it + 1;
+      if (mode == 0) {
+        int64_t delta = 0;
+        if ((st = get(d_delta, &delta)) != REC_OK) return st;
+        if ((double)delta < ctx->cfg.nnd_eps * (double)k * (double)n) break;
+      }
+    }
+    return REC_OK;
+  }
+
+  rec_status pool_add_allpairs(const int32_t* S, int64_t n) {
+    hipStream_t s = ctx->stream;
+    int64_t np = n * (n - 1) / 2;
+    if (np <= 0) return REC_OK;
+    if (np > ctx->cand_cap) { ctx->err = "base case larger than candidate buffer"; return REC_E_NOMEM; }
+    hipLaunchKernelGGL(k_allpairs_claim, dim3(n), dim3(BT), 0, s, S, n, ctx->cand_slot, A);
+    rec_status st = flush_scores();
+    if (st != REC_OK) return st;
+    hipLaunchKernelGGL(k_allpairs_pool, dim3(n), dim3(BT), 0, s, S, n, ctx->cand_slot, ctx->C,
+                       ctx->pset_keys, ctx->pset_mask, ctx->pool_hi, ctx->pool_lo, d_pool_n,
+                       ctx->pool_cap, ctx->err_flag);
+    return REC_OK;
+  }
+
+  // FindBest [Alg. 3] (mode 0 NNDescent, 1 exact KNN): best m pairs into best_*.
+  rec_status find_best(int64_t m, int mode, int64_t* n_out, int64_t level_n[], int levels_max) {
+    hipStream_t s = ctx->stream;
+    const int64_t N = ctx->cfg.N;
+    clear_cache();
+    hipMemsetAsync(ctx->pset_keys, 0xff, (ctx->pset_mask + 1) * 8, s);
+    hipMemsetAsync(ctx->counter + 2, 0, sizeof(int64_t) * 8, s);
+    hipLaunchKernelGGL(k_iota, dim3(gridn(N)), dim3(256), 0, s, ctx->S, N);
+    int32_t* S = ctx->S;
+    int32_t* S2 = ctx->S2;
+    int64_t n = N;
+    rec_status st;
+    levels = 0;
+    nnd_iters = 0;
+    for (int level = 0;; ++level) {
+      if (level < levels_max) level_n[level] = n;
+      ++levels;
+      if (n * n <= 4 * m || n < 2) {
+        if ((st = pool_add_allpairs(S, n)) != REC_OK) return st;
+        break;
+      }
+      int64_t kk = ctx->cfg.knn_k_override > 0 ? ctx->cfg.knn_k_override : (4 * m + n - 1) / n;
+      if (kk > n - 1) kk = n - 1;
+      int k = (int)kk;
+      int it = 0;
+      if ((st = knn(S, n, k, level, mode, &it)) != REC_OK) return st;
+      nnd_iters += it;
+      // D+ : the 2m best directed edges
+      int64_t ne = n * k;
+      int nb = bits_for(N);
+      hipLaunchKernelGGL(k_edge_records, dim3(gridn(ne)), dim3(256), 0, s, S, ctx->Gidx, ctx->Ggain,
+                         n, k, nb, ctx->sb.khi[0], ctx->sb.klo[0], ctx->sb.val[0]);
+      Digit dg[16];
+      int nd = 0;
+      for (int b = 0; b < 2 * nb + 1; b += 8) dg[nd++] = {0, b};
+      for (int b = ctx->fp32 ? 24 : 0; b < 64; b += 8) dg[nd++] = {1, b};
+      int cur = 0;
+      if ((st = rec_radix_sort(ctx, ne, dg, nd, &cur)) != REC_OK) return st;
+      int64_t nsel = std::min<int64_t>(2 * m, ne);
+      hipMemsetAsync(ctx->dset_keys, 0xff, (ctx->dset_mask + 1) * 8, s);
+      hipLaunchKernelGGL(k_mark_d, dim3(gridn(nsel)), dim3(256), 0, s, ctx->sb.khi[cur],
+                         ctx->sb.klo[cur], nsel, nb, ctx->dset_keys, ctx->dset_mask, ctx->pset_keys,
+                         ctx->pset_mask, ctx->pool_hi, ctx->pool_lo, d_pool_n, ctx->pool_cap,
+                         ctx->err_flag);
+      // S' = saturated nodes
+      hipLaunchKernelGGL(k_saturated, dim3(gridn(n)), dim3(256), 0, s, S, ctx->Gidx, n, k,
+                         ctx->dset_keys, ctx->dset_mask, ctx->cnt);
+      if ((st = rec_exclusive_scan(ctx, ctx->cnt, ctx->off, n, d_tmp)) != REC_OK) return st;
+      hipLaunchKernelGGL(k_compact_s, dim3(gridn(n)), dim3(256), 0, s, S, ctx->cnt, ctx->off, n, S2);
+      int64_t n2 = 0;
+      if ((st = get(d_tmp, &n2)) != REC_OK) return st;
+      if ((st = check_err()) != REC_OK) return st;
+      if (n2 >= n) break;   // cannot happen when n^2 > 4m (|S'| <= n/2); guard only
+      std::swap(S, S2);
+      n = n2;
+    }
+    // best m of the pool
+    int64_t np = 0;
+    if ((st = get(d_pool_n, &np)) != REC_OK) return st;
+    if (np > ctx->pool_cap) { ctx->err = "pool overflow"; return REC_E_NOMEM; }
+    return sort_pool_take(np, m, n_out);
+  }
+
+  rec_status sort_pool_take(int64_t np, int64_t m, int64_t* n_out) {
+    hipStream_t s = ctx->stream;
+    if (np > 0)
+      hipLaunchKernelGGL(k_pool_to_sort, dim3(gridn(np)), dim3(256), 0, s, ctx->pool_hi,
+                         ctx->pool_lo, np, ctx->sb.khi[0], ctx->sb.klo[0], ctx->sb.val[0]);
+    int cur = 0;
+    rec_status st = sort_records(np, &cur);
+    if (st != REC_OK) return st;
+    int64_t nb = std::min(np, m);
+    if (nb > ctx->best_cap) { ctx->err = "m exceeds capacity"; return REC_E_NOMEM; }
+    if (nb > 0)
+      hipLaunchKernelGGL(k_take_best, dim3(gridn(nb)), dim3(256), 0, s, ctx->sb.khi[cur],
+                         ctx->sb.klo[cur], nb, ctx->best_i, ctx->best_j, ctx->best_g);
+    *n_out = nb;
+    return check_err();
+  }
+
+  // sort records (desc gain key, pair key) in sort buffer 0
+  rec_status sort_records(int64_t n, int* cur) {
+    Digit dg[16];
+    int nd = 0;
+    int nb = bits_for(ctx->cfg.N);
+    for (int b = 0; b < nb; b += 8) dg[nd++] = {0, b};
+    for (int b = 0; b < nb; b += 8) dg[nd++] = {0, 32 + b};
+    for (int b = ctx->fp32 ? 24 : 0; b < 64; b += 8) dg[nd++] = {1, b};
+    *cur = 0;
+    return rec_radix_sort(ctx, n, dg, nd, cur);
+  }
+
+  // Exhaustive: every pair scored exactly, best m kept (chunks of rows).
+  rec_status exhaustive(int64_t m, int64_t* n_out) {
+    hipStream_t s = ctx->stream;
+    const int64_t N = ctx->cfg.N;
+    const int directed = ctx->cfg.model == REC_KINETIC;
+    const int64_t cap = ctx->ex_cap;
+    int64_t kept = 0;
+    double thr = -__builtin_inf();
+    std::vector<int64_t> roff;
+    int64_t r0 = 0;
+    rec_status st;
+    int32_t* I = ctx->ts_i;
+    int32_t* J = ctx->ts_j;
+    double* g = ctx->C.ovf;
+    while (r0 < N) {
+      roff.assign(1, 0);
+      int64_t r1 = r0;
+      while (r1 < N) {
+        int64_t np = directed ? N - 1 : N - 1 - r1;
+        if (roff.back() + np > cap && r1 > r0) break;
+        roff.push_back(roff.back() + np);
+        ++r1;
+      }
+      int64_t np = roff.back();
+      if (np > cap) { ctx->err = "exhaustive chunk exceeds buffer"; return REC_E_NOMEM; }
+      if (np > 0) {
+        hipMemcpyAsync(ctx->scan_tmp, roff.data(), sizeof(int64_t) * roff.size(), hipMemcpyHostToDevice, s);
+        hipLaunchKernelGGL(k_rowpairs, dim3(r1 - r0), dim3(BT), 0, s, r0, N, directed, ctx->scan_tmp, I, J);
+        if ((st = rec_launch_score(ctx, np, I, J, nullptr, g, nullptr, nullptr)) != REC_OK) return st;
+        int64_t* d_n = ctx->counter + 9;
+        hipMemcpyAsync(d_n, &kept, sizeof(int64_t), hipMemcpyHostToDevice, s);
+        hipLaunchKernelGGL(k_ex_append, dim3(gridn(np)), dim3(256), 0, s, I, J, g, np, thr, directed,
+                           ctx->sb.khi[0], ctx->sb.klo[0], ctx->sb.val[0], d_n, ctx->sb.cap);
+        int64_t tot = 0;
+        if ((st = get(d_n, &tot)) != REC_OK) return st;
+        if (tot > ctx->sb.cap) { ctx->err = "exhaustive keep buffer overflow"; return REC_E_NOMEM; }
+        int cur = 0;
+        if ((st = sort_records(tot, &cur)) != REC_OK) return st;
+        kept = std::min(tot, m);
+        if (cur != 0) {
+          hipMemcpyAsync(ctx->sb.khi[0], ctx->sb.khi[1], kept * 8, hipMemcpyDeviceToDevice, s);
+          hipMemcpyAsync(ctx->sb.klo[0], ctx->sb.klo[1], kept * 8, hipMemcpyDeviceToDevice, s);
+        }
+        if (kept == m) {
+          uint64_t kh = 0;
+          hipMemcpyAsync(&kh, ctx->sb.khi[0] + (m - 1), 8, hipMemcpyDeviceToHost, s);
+          hipStreamSynchronize(s);
+          thr = rec_desc_gain(kh);
+        }
+      }
+      r0 = r1;
+    }
+    if (kept > ctx->best_cap) { ctx->err = "m exceeds capacity"; return REC_E_NOMEM; }
+    if (kept > 0)
+      hipLaunchKernelGGL(k_take_best, dim3(gridn(kept)), dim3(256), 0, s, ctx->sb.khi[0],
+                         ctx->sb.klo[0], kept, ctx->best_i, ctx->best_j, ctx->best_g);
+    *n_out = kept;
+    return check_err();
+  }
+};
+
+}  // namespace
+
+rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,
+                           rec_sweep_stats* st) {
+  Search S(ctx);
+  hipMemsetAsync(ctx->counter + 1, 0, sizeof(int64_t), ctx->stream);
+  int64_t level_n[64];
+  rec_status r;
+  if (search == REC_SEARCH_EXHAUSTIVE) {
+    r = S.exhaustive(m, n_out);
+  } else {
+    if (ctx->cfg.model == REC_KINETIC) {
+      ctx->err = "FindBest over KNN lists is defined for symmetric models; use exhaustive";
+      return REC_E_INVAL;
+    }
+    r = S.find_best(m, search == REC_SEARCH_EXACT_KNN ? 1 : 0, n_out, level_n, 64);
+  }
+  if (r != REC_OK) return r;
+  if (st) {
+    int64_t ev = 0;
+    hipMemcpyAsync(&ev, ctx->counter + 1, 8, hipMemcpyDeviceToHost, ctx->stream);
+    hipStreamSynchronize(ctx->stream);
+    st->pair_evals = ev;
+    st->nnd_iters = S.nnd_iters;
+    st->levels = S.levels;
+  }
+  return REC_OK;
+}
+
+rec_status rec_search_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int k, int level, int mode,
+                          int32_t* nbr, double* gain, int* iters) {
+  if (ctx->cfg.model == REC_KINETIC) { ctx->err = "KNN lists need a symmetric model"; return REC_E_INVAL; }
+  Search S(ctx);
+  S.clear_cache();
+  hipMemsetAsync(ctx->counter + 1, 0, sizeof(int64_t) * 9, ctx->stream);
+  rec_status r = S.knn(S_dev, n, k, level, mode, iters);
+  if (r != REC_OK) return r;
+  hipLaunchKernelGGL(k_lists_out, dim3(gridn(n * k)), dim3(256), 0, ctx->stream, S_dev, ctx->Gidx,
+                     ctx->Ggain, n * k, nbr, gain);
+  return hipGetLastError() == hipSuccess ? REC_OK : REC_E_HIP;
+}
+
+// Coordinate updates of the m pairs in rank order [Alg. 2], as rounds of
+// node-disjoint pairs (Q: a pair runs once every earlier pair sharing a row
+// with it has run), which reproduces the sequential order exactly.
+rec_status rec_apply_best(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
+                          double* delta, int64_t* accepted, int64_t* rounds) {
+  hipStream_t s = ctx->stream;
+  const int64_t N = ctx->cfg.N;
+  const int directed = ctx->cfg.model == REC_KINETIC;
+  *delta = 0.0;
+  *accepted = 0;
+  *rounds = 0;
+  if (m <= 0) return REC_OK;
+  if (m > ctx->best_cap) { ctx->err = "too many pairs for the update buffers"; return REC_E_NOMEM; }
+  hipMemsetAsync(ctx->done, 0, m, s);
+  int64_t* d_rem = ctx->counter + 10;
+  int64_t pass = 0;
+  while (true) {
+    const int batch = 8;
+    std::vector<int64_t> rem(batch, 0);
+    hipMemsetAsync(ctx->scan_tmp, 0, sizeof(int64_t) * batch, s);
+    for (int b = 0; b < batch; ++b) {
+      hipLaunchKernelGGL(k_fill_i32, dim3(gridn(N)), dim3(256), 0, s, ctx->first, N, 0x7fffffff);
+      hipLaunchKernelGGL(k_first, dim3(gridn(m)), dim3(256), 0, s, I, J, m, ctx->done, ctx->first,
+                         directed, ctx->scan_tmp + b);
+      rec_status st = rec_launch_update_round(ctx, m, I, J, ctx->first, ctx->done, ctx->dw);
+      if (st != REC_OK) return st;
+    }
+    if (hipMemcpyAsync(rem.data(), ctx->scan_tmp, sizeof(int64_t) * batch, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { ctx->err = "readback failed"; return REC_E_HIP; }
+    bool finished = false;
+    for (int b = 0; b < batch; ++b) {
+      if (rem[b] > 0) ++pass;
+      else finished = true;
+    }
+    if (finished) break;
+    // the earliest pending pair is always ready, so m passes always suffice
+    if (pass > m + batch) { ctx->err = "update rounds did not drain"; return REC_E_NUMERIC; }
+  }
+  (void)d_rem;
+  *rounds = pass;
+  hipLaunchKernelGGL(k_sum1, dim3(1), dim3(BT), 0, s, ctx->dw, m, ctx->dresult + 3);
+  hipMemsetAsync(ctx->counter + 11, 0, sizeof(int64_t), s);
+  hipLaunchKernelGGL(k_count_pos, dim3(gridn(m)), dim3(256), 0, s, ctx->dw, m, ctx->counter + 11);
+  hipMemcpyAsync(delta, ctx->dresult + 3, sizeof(double), hipMemcpyDeviceToHost, s);
+  hipMemcpyAsync(accepted, ctx->counter + 11, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) { ctx->err = "sync failed"; return REC_E_HIP; }
+  int32_t e = 0;
+  hipMemcpy(&e, ctx->err_flag, 4, hipMemcpyDeviceToHost);
+  if (e & 2) { ctx->err = "W table full (increase max_nnz)"; return REC_E_NOMEM; }
+  return REC_OK;
+}
