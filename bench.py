@@ -28,11 +28,13 @@ WORKLOADS = {
     "C1": "Ising pseudolikelihood, N=100, M=500 +-1 Gibbs samples, ER mean degree 3, kappa=4",
 }
 
-# Algorithmic FP32 work of one exact Ising pair score (see the design notes):
-# per sample and side, 3 Newton evaluations of (fma, rcp, add, mul, add, fma)
-# = 8 flops each (fma = 2) plus the final log-product pass (fma, mul) = 3 flops.
-NEWTON_EVALS = 3
-FLOPS_PER_SAMPLE_SIDE = NEWTON_EVALS * 8 + 3
+# Algorithmic FP32 work of the pair-score kernel, counted per executed pass
+# over the M samples of one side (fma = 2 flops, rcp = 1):
+#   load/kink pass:  u = x t (1), sum u (1), 1 - u^2 and its sum (fma + add: 3)   = 5
+#   moment pass:     1 - u^2 (2), u-powers and sums (mul, add, mul, add, fma: 6)  = 8
+#   Newton pass:     1 + u tau (2), rcp (1), u + tau (1), mul (1), sums (add, fma: 3) = 8
+#   log pass:        1 + u tau (2), product (1)                                   = 3
+FLOPS_LOAD, FLOPS_MOMENT, FLOPS_EVAL, FLOPS_LOG = 5, 8, 8, 3
 # Peak of the non-packed FP32 vector pipe: 256 CUs x 4 SIMDs x 16 lanes x
 # 2.4 GHz x 2 flops per FMA = 78.6 TFLOP/s (packed FP32 is disabled in this
 # build, so the 157.3 TFLOP/s packed figure is not reachable).
@@ -54,9 +56,12 @@ def cpu_baseline(w, lam, seconds):
         O.score_pairs(I, J)
         return time.perf_counter() - t
 
-    dt = batch(64)
-    n = max(64, int(seconds / max(dt, 1e-6) * 64))
-    dt = batch(n)
+    batch(64)                      # warm-up (thread pool start)
+    n, dt, size = 0, 0.0, 256
+    while dt < seconds:            # grow batches until the time budget is spent
+        dt += batch(size)
+        n += size
+        size = min(size * 2, 1 << 16)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": n / dt, "unit": "pair-score evals/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} random pairs of the workload at W=0 (theta fitted), FP64, "
@@ -104,13 +109,15 @@ def main():
               f"evals {stats[-1]['pair_evals']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    score_ms, launches, scored = ctx.kernel_time()
+    score_ms, launches, work = ctx.kernel_time()
+    scored = work["pairs"]
     evals = sum(s["pair_evals"] for s in stats)
     value = evals / wall
 
     sides = 2 if w.model == "ising" else 1
-    flops_eval = sides * w.M * FLOPS_PER_SAMPLE_SIDE
-    achieved = flops_eval * scored / (score_ms / 1e3) / 1e12 if score_ms > 0 else None
+    flops = sides * w.M * (FLOPS_LOAD * work["pairs"] + FLOPS_MOMENT * work["moment_passes"]
+                           + FLOPS_EVAL * work["evals"] + FLOPS_LOG * work["log_passes"])
+    achieved = flops / (score_ms / 1e3) / 1e12 if score_ms > 0 else None
     line = {
         "metric": "pair-score evals/s (exact FindBest scores per second of GCD sweep wall time)",
         "value": value,
@@ -131,7 +138,8 @@ def main():
                      "frac": (achieved / PEAK_TFLOPS) if achieved else None, "traffic": None,
                      "kernel": "k_score (pair score)",
                      "kernel_ms_avg": score_ms / max(launches, 1), "launches": launches,
-                     "pairs_scored": scored, "flops_per_pair": flops_eval},
+                     "pairs_scored": scored, "flops_per_pair": flops / max(scored, 1),
+                     "work": work},
         "details": {
             "sweep_ms": [round(s["t_search_ms"] + s["t_update_ms"] + s["t_theta_ms"], 3) for s in stats],
             "search_ms": [round(s["t_search_ms"], 3) for s in stats],

@@ -175,13 +175,16 @@ rec_status rec_get_fields(rec_ctx* ctx, double* H_dev);
 rec_status rec_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int32_t k, int32_t level,
                    int32_t mode, int32_t* nbr_dev, double* gain_dev, int32_t* iters_host);
 
-/* Instrumentation: when on, every launch of the pair-score kernel is
- * bracketed by HIP events on the context's stream.  rec_kernel_time returns
- * the summed kernel time (ms), the number of launches and the pairs they
- * scored since timing was switched on (synchronises), then resets them. */
+/* Instrumentation (not part of the method): when on, every launch of the
+ * pair-score kernel is bracketed by HIP events on the context's stream.
+ * rec_kernel_time returns, for the launches since the last call (or since
+ * timing was switched on), the summed kernel time in ms, the number of
+ * launches and four work counters: pairs scored, moment passes, full Newton
+ * evaluations and log passes (each pass is one sweep over the M samples of
+ * the pair's one or two sides).  Synchronises; resets the sums. */
 rec_status rec_set_timing(rec_ctx* ctx, int32_t on);
 rec_status rec_kernel_time(rec_ctx* ctx, double* score_ms_host, int64_t* launches_host,
-                           int64_t* pairs_host);
+                           int64_t* work_host);
 
 const char* rec_status_str(rec_status s);
 const char* rec_last_error(const rec_ctx* ctx);

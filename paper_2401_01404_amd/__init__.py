@@ -81,7 +81,7 @@ def lib():
             "rec_get_fields": [vp, vp],
             "rec_knn": [vp, i64, vp, i32, i32, i32, vp, vp, ctypes.POINTER(i32)],
             "rec_set_timing": [vp, i32],
-            "rec_kernel_time": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(i64)],
+            "rec_kernel_time": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.c_void_p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -266,10 +266,11 @@ class Context:
         self._check(lib().rec_set_timing(self.h, 1 if on else 0), self.h)
 
     def kernel_time(self):
-        """(summed pair-score kernel ms, launches, pairs) since the last call."""
+        """Pair-score kernel time and work since the last call:
+        (ms, launches, {"pairs", "moment_passes", "evals", "log_passes"})."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
-        p = ctypes.c_int64()
-        self._check(lib().rec_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(p)),
-                    self.h)
-        return ms.value, n.value, p.value
+        w = (ctypes.c_int64 * 4)()
+        self._check(lib().rec_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n), w), self.h)
+        return ms.value, n.value, {"pairs": w[0], "moment_passes": w[1], "evals": w[2],
+                                   "log_passes": w[3]}

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "common.hpp"
 #include "ctx.hpp"
@@ -101,6 +102,7 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   x->wj = a.take<int32_t>(z.max_nnz);
   x->wv = a.take<double>(z.max_nnz);
   x->counter = a.take<int64_t>(16);
+  x->work = a.take<int64_t>(4 * REC_WORK_COPIES);
   x->dscratch = a.take<double>(std::max<int64_t>(N, 1024));
   x->dresult = a.take<double>(16);
   x->err_flag = a.take<int32_t>(4);
@@ -208,6 +210,21 @@ rec_status clear_err(rec_ctx* ctx) {
     if ((ctx)->state != REC_OK) return fail(ctx, REC_E_STATE, "context poisoned by an earlier failure; call rec_set_model"); \
   } while (0)
 
+}  // namespace
+
+// Sum of the work-counter copies (synchronises).
+rec_status rec_work_read(rec_ctx* ctx, int64_t out[4]) {
+  std::vector<int64_t> h(4 * REC_WORK_COPIES);
+  REC_HIP(hipMemcpyAsync(h.data(), ctx->work, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  for (int q = 0; q < 4; ++q) out[q] = 0;
+  for (int c = 0; c < REC_WORK_COPIES; ++c)
+    for (int q = 0; q < 4; ++q) out[q] += h[4 * c + q];
+  return REC_OK;
+}
+
+namespace {
+
 // refresh fields from W with the current theta, refit theta, evaluate
 rec_status refresh(rec_ctx* ctx, double* obj) {
   REC_TRY(rec_rebuild_fields(ctx));
@@ -279,6 +296,7 @@ rec_status rec_create(const rec_config* cfg, const void* X_dev, void* ws_dev, si
   auto bad = [&](rec_status st) { delete ctx; return st; };
   if (hipMemsetAsync(ctx->err_flag, 0, 16, ctx->stream) != hipSuccess) return bad(REC_E_HIP);
   if (hipMemsetAsync(ctx->counter, 0, 16 * 8, ctx->stream) != hipSuccess) return bad(REC_E_HIP);
+  if (hipMemsetAsync(ctx->work, 0, 4 * 8 * REC_WORK_COPIES, ctx->stream) != hipSuccess) return bad(REC_E_HIP);
   rec_wtable_clear(ctx);
   if (rec_load_data(ctx, X_dev, cfg->ldx) != REC_OK) return bad(REC_E_HIP);
   hipLaunchKernelGGL(k_fill_f64, dim3((cfg->N + 255) / 256), dim3(256), 0, ctx->stream, F.theta,
@@ -483,16 +501,20 @@ rec_status rec_set_timing(rec_ctx* ctx, int32_t on) {
   ctx->timing = on != 0;
   ctx->score_ms = 0.0;
   ctx->score_launches = ctx->score_pairs = 0;
-  return REC_OK;
+  return rec_work_read(ctx, ctx->work_base);
 }
 
 rec_status rec_kernel_time(rec_ctx* ctx, double* score_ms_host, int64_t* launches_host,
-                           int64_t* pairs_host) {
+                           int64_t* work_host) {
   if (!ctx) return REC_E_INVAL;
   REC_TRY(rec_timing_resolve(ctx));
+  int64_t w[4];
+  REC_TRY(rec_work_read(ctx, w));
   if (score_ms_host) *score_ms_host = ctx->score_ms;
   if (launches_host) *launches_host = ctx->score_launches;
-  if (pairs_host) *pairs_host = ctx->score_pairs;
+  if (work_host)
+    for (int q = 0; q < 4; ++q) work_host[q] = w[q] - ctx->work_base[q];
+  for (int q = 0; q < 4; ++q) ctx->work_base[q] = w[q];
   ctx->score_ms = 0.0;
   ctx->score_launches = ctx->score_pairs = 0;
   return REC_OK;

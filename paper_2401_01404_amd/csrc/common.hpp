@@ -96,6 +96,39 @@ __device__ __forceinline__ T rec_wave_sum(T v) {
 
 __device__ __forceinline__ int rec_lane() { return (int)(threadIdx.x & (REC_WAVE - 1)); }
 
+// Values known to be equal on every lane (wave reductions, broadcasts) moved
+// to scalar registers, so the compiler treats dependent control flow and
+// addressing as uniform.
+__device__ __forceinline__ int rec_uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double rec_uni(double v) {
+  uint64_t u = __builtin_bit_cast(uint64_t, v);
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T rec_wave_sum_uni(T v) { return rec_uni(rec_wave_sum(v)); }
+
+// Append from any subset of a wave's active lanes: one atomic per wave on the
+// shared cursor (ballot + popcount ranks), instead of one per lane.  Returns
+// the position of this lane's item, or -1 when pred is false.
+__device__ __forceinline__ int64_t rec_append(int64_t* cursor, bool pred) {
+  uint64_t mask = __ballot(pred);
+  if (!pred) return -1;
+  const int lane = rec_lane();
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  const uint64_t lt = lane ? (~0ULL >> (64 - lane)) : 0ULL;
+  long long base = 0;
+  if (lane == leader)
+    base = (long long)atomicAdd((unsigned long long*)cursor, (unsigned long long)__popcll(mask));
+  base = __shfl(base, leader, REC_WAVE);
+  return (int64_t)base + __popcll(mask & lt);
+}
+
+// Work counters are kept in REC_WORK_COPIES copies of 4 so that concurrent
+// waves do not serialise on one address; readers sum the copies.
+constexpr int REC_WORK_COPIES = 256;
+
 // numerics shared by the kernels (double)
 __device__ __forceinline__ double rec_lcosh_tau(double tau) {   // log cosh(atanh tau)
   return -0.5 * log1p(-tau * tau);

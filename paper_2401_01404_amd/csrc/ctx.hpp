@@ -86,6 +86,7 @@ struct rec_ctx {
   // scratch for compaction of the W table
   int32_t* wi; int32_t* wj; double* wv;   // max_nnz each
   int64_t* counter;     // small device counters [16]
+  int64_t* work;        // pair-score work counters [4]: pairs, moment passes, evaluations, log passes
   double* dscratch;     // per-block partial sums (N)
   double* dresult;      // small double results [16]
   int32_t* err_flag;    // device error flag
@@ -121,12 +122,14 @@ struct rec_ctx {
   size_t ev_used = 0;
   double score_ms = 0.0;
   int64_t score_launches = 0, score_pairs = 0;
+  int64_t work_base[4] = {0, 0, 0, 0};   // work counters when timing was switched on
   ~rec_ctx() {
     for (auto& e : ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   }
 };
 
 rec_status rec_timing_resolve(rec_ctx* ctx);
+rec_status rec_work_read(rec_ctx* ctx, int64_t out[4]);
 
 // ---- launch helpers (implemented in the .hip files) ----
 #define REC_HIP(call)                                                          \

@@ -269,18 +269,16 @@ __global__ void k_winsert(WTable W, int64_t n, const int32_t* ei, const int32_t*
   int64_t s = rec_hash_insert(W.keys, W.mask, rec_pair_key(i, j, directed), REC_MAX_PROBE, &ins);
   if (s < 0) { atomicOr(err, 2); return; }
   W.vals[s] = v;
-  if (ins) atomicAdd((unsigned long long*)W.count, 1ULL);
 }
 
 // occupied, nonzero table entries -> sort records (key = pair key, val = slot)
 __global__ void k_wcompact(WTable W, uint64_t cap, uint64_t* klo, uint32_t* val, int64_t* n,
                            int64_t max_n) {
   uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= cap) return;
-  uint64_t k = W.keys[s];
-  if (k == REC_EMPTY || W.vals[s] == 0.0) return;
-  int64_t p = (int64_t)atomicAdd((unsigned long long*)n, 1ULL);
-  if (p < max_n) { klo[p] = k; val[p] = (uint32_t)s; }
+  uint64_t k = s < cap ? W.keys[s] : REC_EMPTY;
+  bool keep = k != REC_EMPTY && W.vals[s] != 0.0;
+  int64_t p = rec_append(n, keep);
+  if (p >= 0 && p < max_n) { klo[p] = k; val[p] = (uint32_t)s; }
 }
 
 __global__ void k_wunpack(const uint64_t* klo, const uint32_t* val, const double* wvals, int64_t n,

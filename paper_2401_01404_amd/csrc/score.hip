@@ -23,6 +23,14 @@
 // lies in (tau0, 1) or (-1, tau0); Newton steps inside that bracket,
 // bisection otherwise.  dPhi/dtau uses 1 - y^2 = (1 - u^2)(1 - tau^2)/(1 + u tau)^2.
 //
+// Start of the search at w0 = 0 (every candidate not yet in W): at tau = 0,
+// y = u, so Phi(0) = c S - sum u and dPhi/dtau(0) = -sum (1 - u^2) come from
+// the load itself with no reciprocal; below the L1 threshold the pair is done.
+// Otherwise (u + tau)/(1 + u tau) = u + (1 - u^2) tau (1 - u tau + u^2 tau^2 ...)
+// gives Phi(tau) = Phi(0) - mu0 tau + mu1 tau^2 - mu2 tau^3 + mu3 tau^4 + ...
+// with mu_k = sum (1 - u^2) u^k; the root of that quartic starts Newton, which
+// then usually confirms convergence after one full evaluation.
+//
 // Gaussian score: closed form.  With residuals r_i = x_i + theta_i^2 m_i the
 // change of the two conditionals [App. A] is a delta - b delta^2 / 2 with
 // a = -(r_i . x_j + r_j . x_i), b = theta_i^2 |x_j|^2 + theta_j^2 |x_i|^2,
@@ -131,11 +139,16 @@ __device__ __forceinline__ double side_logs(const R* a, R tau) {
 
 struct PairOut { double gain, w, w0; };
 
+// Work counters of one wave: [0] pairs, [1] moment passes, [2] full Newton
+// evaluations, [3] log passes.
+struct Work { int64_t pairs = 0, moments = 0, evals = 0, logs = 0; };
+
 // Exact score of pair (i, j) for the Ising (TWO = true) or kinetic model,
-// with the lane registers already holding u (and v).  Sc = c S (exact).
+// with the lane registers already holding u (and v).  Sc = c S (exact);
+// A0 = sum u (+ v), Q0 = sum (1 - u^2) (+ (1 - v^2)) over all padded samples.
 template <class R, int NPL, bool TWO>
-__device__ PairOut solve_ising(const Lane<R, NPL>& L, double Sc, double w0, double lambda,
-                               int64_t M, int64_t Mp) {
+__device__ PairOut solve_ising(const Lane<R, NPL>& L, double Sc, double A0, double Q0, double w0,
+                               double lambda, int64_t M, int64_t Mp, Work& wk) {
   constexpr double nsides = TWO ? 2.0 : 1.0;
   const double npad = (double)(Mp - M);
   auto eval = [&](double tau, double& phi, double& dphi) {
@@ -144,18 +157,25 @@ __device__ PairOut solve_ising(const Lane<R, NPL>& L, double Sc, double w0, doub
     R A = R(0), Q = R(0), A2 = R(0), Q2 = R(0);
     side_sums<R, NPL>(L.u, (R)tau, A, Q);
     if constexpr (TWO) side_sums<R, NPL>(L.v, (R)tau, A2, Q2);
-    double As = rec_wave_sum((double)A + (double)A2);
-    double Qs = rec_wave_sum((double)Q + (double)Q2);
+    double As = rec_wave_sum_uni((double)A + (double)A2);
+    double Qs = rec_wave_sum_uni((double)Q + (double)Q2);
     double t = (double)(R)tau;
     phi = Sc - As + nsides * npad * t;
     double om = 1.0 - t * t;
     dphi = -((nsides * (double)Mp - Qs) / om - nsides * npad);
+    ++wk.evals;
   };
   PairOut o;
   o.w0 = w0;
-  double tau0 = (w0 == 0.0) ? 0.0 : (double)tanh_((R)(-w0));
-  double phi, dphi;
-  eval(tau0, phi, dphi);
+  double tau0, phi, dphi;
+  if (w0 == 0.0) {
+    tau0 = 0.0;
+    phi = Sc - A0;                       // padding has u = 0
+    dphi = -(Q0 - nsides * npad);        // padding has 1 - u^2 = 1
+  } else {
+    tau0 = (double)tanh_((R)(-w0));
+    eval(tau0, phi, dphi);
+  }
   double tau;
   if (fabs(phi) <= lambda) {
     if (w0 == 0.0) { o.gain = 0.0; o.w = 0.0; return o; }
@@ -167,6 +187,46 @@ __device__ PairOut solve_ising(const Lane<R, NPL>& L, double Sc, double w0, doub
     double lo = s > 0 ? tau0 : -1.0, hi = s > 0 ? 1.0 : tau0;
     double f = phi - target, df = dphi;
     tau = tau0;
+    if (w0 == 0.0) {
+      // quartic Taylor model of Phi around 0 from the moments mu1..mu3
+      R m1 = R(0), m2 = R(0), m3 = R(0), n1 = R(0), n2 = R(0), n3 = R(0);
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        R u = L.u[k];
+        R q = fma(-u, u, R(1));
+        R t1 = q * u;
+        m1 += t1;
+        R t2 = t1 * u;
+        m2 += t2;
+        m3 = fma(t2, u, m3);
+        if constexpr (TWO) {
+          R v = L.v[k];
+          R qv = fma(-v, v, R(1));
+          R s1 = qv * v;
+          n1 += s1;
+          R s2 = s1 * v;
+          n2 += s2;
+          n3 = fma(s2, v, n3);
+        }
+      }
+      double mu1 = rec_wave_sum_uni((double)m1 + (double)n1);
+      double mu2 = rec_wave_sum_uni((double)m2 + (double)n2);
+      double mu3 = rec_wave_sum_uni((double)m3 + (double)n3);
+      double mu0 = -df;
+      ++wk.moments;
+      double t = f / mu0;
+      for (int q = 0; q < 8; ++q) {
+        double P = f + t * (-mu0 + t * (mu1 + t * (-mu2 + t * mu3)));
+        double dP = -mu0 + t * (2.0 * mu1 + t * (-3.0 * mu2 + t * 4.0 * mu3));
+        if (!(dP < 0)) break;
+        t -= P / dP;
+      }
+      if (!(t > lo && t < hi)) t = 0.5 * (lo + hi);
+      tau = t;
+      eval(tau, phi, dphi);
+      f = phi - target;
+      df = dphi;
+    }
     for (int it = 0; it < Prec<R>::maxit; ++it) {
       if (f > 0) lo = tau; else hi = tau;
       double tn = (df < 0) ? tau - f / df : 0.5 * (lo + hi);
@@ -185,7 +245,8 @@ __device__ PairOut solve_ising(const Lane<R, NPL>& L, double Sc, double w0, doub
   }
   double Ls = side_logs<R, NPL>(L.u, (R)tau);
   if constexpr (TWO) Ls += side_logs<R, NPL>(L.v, (R)tau);
-  Ls = rec_wave_sum(Ls);
+  Ls = rec_wave_sum_uni(Ls);
+  ++wk.logs;
   double d = rec_atanh(tau);
   double g = Sc * d - nsides * (double)M * rec_lcosh_tau(tau) - Ls -
              lambda * (fabs(o.w) - fabs(w0));
@@ -200,7 +261,7 @@ __device__ PairOut solve_gauss(const Lane<R, NPL>& L, double vi, double vj, doub
   R a = R(0);
 #pragma unroll
   for (int k = 0; k < NPL; ++k) a = fma(L.ti[k], L.u[k], fma(L.v[k], L.xi[k], a));
-  double as = -rec_wave_sum((double)a);
+  double as = -rec_wave_sum_uni((double)a);
   double b = vi * sqj + vj * sqi;
   double z = w0 + as / b;
   double ws = z > 0 ? fmax(z - lambda / b, 0.0) : fmin(z + lambda / b, 0.0);
@@ -229,11 +290,14 @@ __device__ __forceinline__ void load_i(const Fields& F, int i, Lane<R, NPL>& L, 
   }
 }
 
-// Load the j side and form u, v; returns c S for the Ising / kinetic models.
+// Load the j side and form u, v; returns c S for the Ising / kinetic models
+// and the sums A0 = sum u (+ v), Q0 = sum (1 - u^2) (+ (1 - v^2)).
 template <class R, int NPL, int MODEL>
-__device__ __forceinline__ double load_j(const Fields& F, int j, Lane<R, NPL>& L, int lane) {
+__device__ __forceinline__ double load_j(const Fields& F, int j, Lane<R, NPL>& L, int lane,
+                                         double& A0, double& Q0) {
   constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
   float s = 0.f;
+  R a = R(0), q = R(0), a2 = R(0), q2 = R(0);
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     int64_t o = smp<VEC>(c, lane);
@@ -251,27 +315,39 @@ __device__ __forceinline__ double load_j(const Fields& F, int j, Lane<R, NPL>& L
         ld_r<VEC>(reinterpret_cast<const R*>(F.T) + (int64_t)j * F.Mp + o, tv);
 #pragma unroll
       for (int k = 0; k < VEC; ++k) {
-        int q = c * VEC + k;
-        L.u[q] = (R)xv[k] * L.ti[q];
-        if constexpr (MODEL == REC_ISING) L.v[q] = L.xi[q] * tv[k];
-        s += xv[k] * (float)L.xi[q];      // +-1 products: exact in float
+        int qk = c * VEC + k;
+        R u = (R)xv[k] * L.ti[qk];
+        L.u[qk] = u;
+        a += u;
+        q = fma(-u, u, q + R(1));
+        if constexpr (MODEL == REC_ISING) {
+          R v = L.xi[qk] * tv[k];
+          L.v[qk] = v;
+          a2 += v;
+          q2 = fma(-v, v, q2 + R(1));
+        }
+        s += xv[k] * (float)L.xi[qk];      // +-1 products: exact in float
       }
     }
   }
-  if constexpr (MODEL == REC_GAUSS) return 0.0;
+  if constexpr (MODEL == REC_GAUSS) { A0 = Q0 = 0.0; return 0.0; }
+  A0 = rec_wave_sum_uni((double)a + (double)a2);
+  Q0 = rec_wave_sum_uni((double)q + (double)q2);
   int si = (int)s;
-  si = rec_wave_sum(si);
+  si = rec_wave_sum_uni(si);
   return (MODEL == REC_ISING ? 2.0 : 1.0) * (double)si;
 }
 
 template <class R, int NPL, int MODEL>
-__device__ __forceinline__ PairOut solve(const Fields& F, const Lane<R, NPL>& L, double Sc, int i,
-                                         int j, double w0, double lambda) {
+__device__ __forceinline__ PairOut solve(const Fields& F, const Lane<R, NPL>& L, double Sc,
+                                         double A0, double Q0, int i, int j, double w0,
+                                         double lambda, Work& wk) {
+  ++wk.pairs;
   if constexpr (MODEL == REC_GAUSS) {
     double vi = F.theta[i] * F.theta[i], vj = F.theta[j] * F.theta[j];
     return solve_gauss<R, NPL>(L, vi, vj, F.sq[i], F.sq[j], w0, lambda);
   } else {
-    return solve_ising<R, NPL, MODEL == REC_ISING>(L, Sc, w0, lambda, F.M, F.Mp);
+    return solve_ising<R, NPL, MODEL == REC_ISING>(L, Sc, A0, Q0, w0, lambda, F.M, F.Mp, wk);
   }
 }
 
@@ -283,17 +359,28 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
                                                double* __restrict__ gain_out,
                                                double* __restrict__ w_out, double* __restrict__ ovf,
                                                uint64_t cache_cap, int32_t* err, int ppw,
-                                               int64_t* evals) {
+                                               int64_t* work) {
   const int lane = rec_lane();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE;
   int64_t p0 = wave * ppw;
   if (p0 >= P) return;
-  int64_t p1 = p0 + ppw < P ? p0 + ppw : P;
+  int np = (int)(p0 + ppw < P ? ppw : P - p0);
+  // lanes 0..np-1 fetch the pairs of this wave and their current weights at once
+  int li = -1, lj = -1;
+  double lw = 0.0;
+  if (lane < np) {
+    li = I[p0 + lane];
+    lj = J[p0 + lane];
+    if (li >= 0 && lj >= 0 && li < F.N && lj < F.N && li != lj)
+      lw = lookup_w(W, li, lj, MODEL == REC_KINETIC);
+  }
   Lane<R, NPL> L;
   int cur = -1;
-  int64_t n_eval = 0;
-  for (int64_t p = p0; p < p1; ++p) {
-    int i = I[p], j = J[p];
+  Work wk;
+  for (int q = 0; q < np; ++q) {
+    const int64_t p = p0 + q;
+    int i = rec_uni(__shfl(li, q, REC_WAVE)), j = rec_uni(__shfl(lj, q, REC_WAVE));
+    double w0 = rec_uni(__shfl(lw, q, REC_WAVE));
     uint64_t o = slot ? (uint64_t)slot[p] : (uint64_t)p;
     double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
     if (i < 0 || j < 0 || i >= F.N || j >= F.N || i == j) {
@@ -305,18 +392,23 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
       continue;
     }
     if (i != cur) { load_i<R, NPL, MODEL>(F, i, L, lane); cur = i; }
-    double Sc = load_j<R, NPL, MODEL>(F, j, L, lane);
-    double w0 = lookup_w(W, i, j, MODEL == REC_KINETIC);
-    PairOut r = solve<R, NPL, MODEL>(F, L, Sc, i, j, w0, lambda);
+    double A0, Q0;
+    double Sc = load_j<R, NPL, MODEL>(F, j, L, lane, A0, Q0);
+    PairOut r = solve<R, NPL, MODEL>(F, L, Sc, A0, Q0, i, j, w0, lambda, wk);
     double g = r.gain;
     if constexpr (sizeof(R) == 4) g = (double)(float)g;   // FP32 scores
     if (lane == 0) {
       *dst = g;
       if (w_out) w_out[p] = r.w;
     }
-    ++n_eval;
   }
-  if (lane == 0 && evals) atomicAdd((unsigned long long*)evals, (unsigned long long)n_eval);
+  if (lane == 0 && work) {
+    int64_t* wc = work + 4 * (wave & (REC_WORK_COPIES - 1));
+    atomicAdd((unsigned long long*)&wc[0], (unsigned long long)wk.pairs);
+    atomicAdd((unsigned long long*)&wc[1], (unsigned long long)wk.moments);
+    atomicAdd((unsigned long long*)&wc[2], (unsigned long long)wk.evals);
+    atomicAdd((unsigned long long*)&wc[3], (unsigned long long)wk.logs);
+  }
 }
 
 // One round of node-disjoint updates: pair p runs when it is the earliest
@@ -337,10 +429,12 @@ __global__ __launch_bounds__(256) void k_update(Fields F, WTable W, double lambd
   if (MODEL != REC_KINETIC && first[j] != (int32_t)p) return;
   Lane<R, NPL> L;
   load_i<R, NPL, MODEL>(F, i, L, lane);
-  double Sc = load_j<R, NPL, MODEL>(F, j, L, lane);
+  double A0, Q0;
+  double Sc = load_j<R, NPL, MODEL>(F, j, L, lane, A0, Q0);
   bool directed = MODEL == REC_KINETIC;
   double w0 = lookup_w(W, i, j, directed);
-  PairOut r = solve<R, NPL, MODEL>(F, L, Sc, i, j, w0, lambda);
+  Work wk;
+  PairOut r = solve<R, NPL, MODEL>(F, L, Sc, A0, Q0, i, j, w0, lambda, wk);
   double d = r.w - w0;
   if (d != 0.0) {
     // rows of H (and T): h_i += d x_j, h_j += d x_i [App. A, O(1) field bookkeeping]
@@ -371,10 +465,7 @@ __global__ __launch_bounds__(256) void k_update(Fields F, WTable W, double lambd
       bool ins;
       int64_t s = rec_hash_insert(W.keys, W.mask, rec_pair_key(i, j, directed), REC_MAX_PROBE, &ins);
       if (s < 0) atomicOr(err, 2);
-      else {
-        W.vals[s] = r.w;
-        if (ins) atomicAdd((unsigned long long*)W.count, 1ULL);
-      }
+      else W.vals[s] = r.w;
     }
   }
   if (lane == 0) {
@@ -391,7 +482,7 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
   int64_t blocks = (waves * REC_WAVE + 255) / 256;
   double* ovf = C ? C->ovf : nullptr;
   uint64_t cap = C ? (C->mask + 1) : 0;
-  int64_t* ev = ctx->counter + 1;
+  int64_t* ev = ctx->work;
 #define REC_SC(NPL)                                                                              \
   hipLaunchKernelGGL((k_score<R, NPL, MODEL>), dim3(blocks), dim3(256), 0, ctx->stream, ctx->F,  \
                      ctx->W, ctx->cfg.lambda, P, I, J, slot, gain_out, w_out, ovf, cap,          \

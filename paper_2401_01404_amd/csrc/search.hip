@@ -50,21 +50,22 @@ struct ClaimArgs {
   int directed;
 };
 
+// May be called from any subset of a wave's lanes; the cursors are advanced
+// once per wave.
 __device__ uint32_t claim(const ClaimArgs& A, int i, int j) {
   bool ins = false;
   int64_t s = rec_hash_insert(A.C.keys, A.C.mask, rec_pair_key(i, j, A.directed != 0),
                               REC_MAX_PROBE, &ins);
-  uint64_t slot;
-  if (s >= 0 && !ins) return (uint32_t)s;
-  if (s < 0) {
-    int64_t o = (int64_t)atomicAdd((unsigned long long*)A.ovf_n, 1ULL);
-    if (o >= A.C.ovf_cap) { atomicOr(A.err, 16); return 0xffffffffu; }
+  uint64_t slot = s >= 0 ? (uint64_t)s : 0;
+  int64_t o = rec_append(A.ovf_n, s < 0);         // no free slot: overflow area
+  if (o >= 0) {
+    if (o >= A.C.ovf_cap) atomicOr(A.err, 16);
     slot = (A.C.mask + 1) + (uint64_t)o;
-  } else {
-    slot = (uint64_t)s;
   }
-  int64_t p = (int64_t)atomicAdd((unsigned long long*)A.ts_n, 1ULL);
-  if (p >= A.ts_cap) { atomicOr(A.err, 16); return 0xffffffffu; }
+  bool queue = s < 0 || ins;                      // this lane scores the pair
+  int64_t p = rec_append(A.ts_n, queue);
+  if (!queue) return (uint32_t)slot;
+  if (p >= A.ts_cap || (s < 0 && o >= A.C.ovf_cap)) { atomicOr(A.err, 16); return 0xffffffffu; }
   A.ts_i[p] = i;
   A.ts_j[p] = j;
   A.ts_slot[p] = (uint32_t)slot;
@@ -340,14 +341,14 @@ __global__ void k_mark_d(const uint64_t* khi, const uint64_t* klo, int64_t nsel,
   uint32_t mx = (uint32_t)((lo >> 1) & ((1ULL << nb) - 1));
   uint64_t key = ((uint64_t)mn << 32) | mx;
   bool ins;
-  if (rec_hash_insert(dkeys, dmask, key, 4096, &ins) < 0) { atomicOr(err, 32); return; }
-  if (rec_hash_insert(pkeys, pmask, key, 4096, &ins) < 0) { atomicOr(err, 32); return; }
-  if (ins) {
-    int64_t p = (int64_t)atomicAdd((unsigned long long*)pool_n, 1ULL);
-    if (p >= pool_cap) { atomicOr(err, 32); return; }
-    pool_hi[p] = khi[e];
-    pool_lo[p] = key;
-  }
+  bool ok = rec_hash_insert(dkeys, dmask, key, 4096, &ins) >= 0;
+  ok = ok && rec_hash_insert(pkeys, pmask, key, 4096, &ins) >= 0;
+  if (!ok) atomicOr(err, 32);
+  int64_t p = rec_append(pool_n, ok && ins);
+  if (p < 0) return;
+  if (p >= pool_cap) { atomicOr(err, 32); return; }
+  pool_hi[p] = khi[e];
+  pool_lo[p] = key;
 }
 
 __global__ void k_saturated(const int32_t* S, const int32_t* Gidx, int64_t n, int k,
@@ -388,10 +389,11 @@ __global__ __launch_bounds__(BT) void k_allpairs_pool(const int32_t* S, int64_t 
   for (int64_t b = a + 1 + threadIdx.x; b < n; b += BT) {
     double g = slot_gain(C, slots[rowbase + (b - a - 1)]);
     uint64_t key = rec_pair_key(S[a], S[b], false);
-    bool ins;
-    if (rec_hash_insert(pkeys, pmask, key, 4096, &ins) < 0) { atomicOr(err, 32); continue; }
-    if (!ins) continue;
-    int64_t p = (int64_t)atomicAdd((unsigned long long*)pool_n, 1ULL);
+    bool ins = false;
+    bool ok = rec_hash_insert(pkeys, pmask, key, 4096, &ins) >= 0;
+    if (!ok) atomicOr(err, 32);
+    int64_t p = rec_append(pool_n, ok && ins);
+    if (p < 0) continue;
     if (p >= pool_cap) { atomicOr(err, 32); continue; }
     pool_hi[p] = rec_desc_key(g);
     pool_lo[p] = key;
@@ -455,11 +457,9 @@ __global__ void k_ex_append(const int32_t* I, const int32_t* J, const double* g,
                             double thr, int directed, uint64_t* khi, uint64_t* klo, uint32_t* val,
                             int64_t* n, int64_t cap) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= np) return;
-  double ge = g[e];
-  if (!(ge >= thr)) return;
-  int64_t p = (int64_t)atomicAdd((unsigned long long*)n, 1ULL);
-  if (p >= cap) return;
+  double ge = e < np ? g[e] : -__builtin_inf();
+  int64_t p = rec_append(n, e < np && ge >= thr);
+  if (p < 0 || p >= cap) return;
   khi[p] = rec_desc_key(ge);
   klo[p] = rec_pair_key(I[e], J[e], directed != 0);
   val[p] = 0;
@@ -853,7 +853,9 @@ struct Search {
 rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,
                            rec_sweep_stats* st) {
   Search S(ctx);
-  hipMemsetAsync(ctx->counter + 1, 0, sizeof(int64_t), ctx->stream);
+  // pair scores so far (the work counters are cumulative)
+  int64_t w0[4] = {0, 0, 0, 0};
+  if (st && rec_work_read(ctx, w0) != REC_OK) return REC_E_HIP;
   int64_t level_n[64];
   rec_status r;
   if (search == REC_SEARCH_EXHAUSTIVE) {
@@ -867,10 +869,9 @@ rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,
   }
   if (r != REC_OK) return r;
   if (st) {
-    int64_t ev = 0;
-    hipMemcpyAsync(&ev, ctx->counter + 1, 8, hipMemcpyDeviceToHost, ctx->stream);
-    hipStreamSynchronize(ctx->stream);
-    st->pair_evals = ev;
+    int64_t w1[4];
+    if (rec_work_read(ctx, w1) != REC_OK) return REC_E_HIP;
+    st->pair_evals = w1[0] - w0[0];
     st->nnd_iters = S.nnd_iters;
     st->levels = S.levels;
   }
@@ -882,7 +883,7 @@ rec_status rec_search_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int k, 
   if (ctx->cfg.model == REC_KINETIC) { ctx->err = "KNN lists need a symmetric model"; return REC_E_INVAL; }
   Search S(ctx);
   S.clear_cache();
-  hipMemsetAsync(ctx->counter + 1, 0, sizeof(int64_t) * 9, ctx->stream);
+  hipMemsetAsync(ctx->counter + 2, 0, sizeof(int64_t) * 8, ctx->stream);
   rec_status r = S.knn(S_dev, n, k, level, mode, iters);
   if (r != REC_OK) return r;
   hipLaunchKernelGGL(k_lists_out, dim3(gridn(n * k)), dim3(256), 0, ctx->stream, S_dev, ctx->Gidx,
