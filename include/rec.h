@@ -83,7 +83,7 @@ typedef struct {
   int32_t reserved0;
   uint64_t seed;          /* seed of the NNDescent initial lists and in-neighbour caps  */
   int64_t max_nnz;        /* capacity for nonzero W entries (0: 64 * N)                  */
-  int32_t log2_cache;     /* score cache slots = 2^log2_cache (0: chosen from N)         */
+  int32_t log2_cache;     /* score cache slots = 2^log2_cache, <= 30 (0: chosen from N)  */
   int32_t reserved1;
 } rec_config;
 

@@ -59,13 +59,14 @@ rec_status plan(const rec_config* c, Sizes* z, const char** why) {
   int64_t want = N * std::min<int64_t>(4 * k0 * k0, N - 1);
   want = std::max(want, 2 * z->mcap + N);
   z->cand_cap = std::min<int64_t>(std::max<int64_t>(want, 1 << 16), int64_t(1) << 26);
+  // slot words: cache slots + overflow slots must stay below 2^31 (top bit = owner)
   int lc = c->log2_cache;
   if (lc <= 0) {
     int64_t target = std::min<int64_t>(4 * z->cand_cap, 2 * pairs + 1024);
     lc = 16;
     while ((int64_t(1) << lc) < target && lc < 30) ++lc;
   }
-  if (lc < 10 || lc > 31) { *why = "log2_cache must be in [10, 31]"; return REC_E_INVAL; }
+  if (lc < 10 || lc > 30) { *why = "log2_cache must be in [10, 30]"; return REC_E_INVAL; }
   z->ccap = int64_t(1) << lc;
   int levels_max = 2;
   for (int64_t v = 1; v < N; v <<= 1) ++levels_max;
@@ -130,11 +131,14 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   x->off = a.take<int64_t>(N + 2);
   x->cand_cap = z.cand_cap;
   x->cand_v = a.take<int32_t>(z.cand_cap);
+  x->cand_gi = a.take<int32_t>(z.cand_cap);
   x->cand_slot = a.take<uint32_t>(z.cand_cap);
   x->ts_i = a.take<int32_t>(z.cand_cap);
   x->ts_j = a.take<int32_t>(z.cand_cap);
   x->ts_slot = a.take<uint32_t>(z.cand_cap);
   x->inoff = a.take<int64_t>(N + 2);
+  x->inoff_cnt = a.take<int32_t>(N);
+  x->capcnt = a.take<int32_t>(N);
   x->in_src = a.take<int32_t>(z.list_cap);
   x->dset_keys = a.take<uint64_t>(z.dcap);
   x->dset_mask = (uint64_t)(z.dcap - 1);

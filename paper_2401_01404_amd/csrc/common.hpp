@@ -109,6 +109,54 @@ __device__ __forceinline__ double rec_uni(double v) {
 template <class T>
 __device__ __forceinline__ T rec_wave_sum_uni(T v) { return rec_uni(rec_wave_sum(v)); }
 
+// Full-wave sums with DPP row operations (xor 1, xor 2, half-row mirror,
+// row mirror: every lane of a 16-lane row then holds the row sum) and four
+// readlanes for the rows; the result is uniform (scalar).  All 64 lanes must
+// be active.  The order of additions is fixed, so the bits do not depend on
+// which lane holds which partial sum.
+namespace rec_dpp {
+constexpr int QP_XOR1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);   // quad_perm [1,0,3,2]
+constexpr int QP_XOR2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);   // quad_perm [2,3,0,1]
+constexpr int ROW_HALF_MIRROR = 0x141;
+constexpr int ROW_MIRROR = 0x140;
+template <int CTRL>
+__device__ __forceinline__ int mov(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float mov(float v) {
+  return __builtin_bit_cast(float, mov<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double mov(double v) {
+  uint64_t u = __builtin_bit_cast(uint64_t, v);
+  int lo = mov<CTRL>((int)(uint32_t)u);
+  int hi = mov<CTRL>((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float lane_read(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+  uint64_t u = __builtin_bit_cast(uint64_t, v);
+  uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+}  // namespace rec_dpp
+
+template <class T>
+__device__ __forceinline__ T rec_wave_sum_dpp(T v) {
+  using namespace rec_dpp;
+  v += mov<QP_XOR1>(v);
+  v += mov<QP_XOR2>(v);
+  v += mov<ROW_HALF_MIRROR>(v);
+  v += mov<ROW_MIRROR>(v);
+  T r0 = lane_read(v, 0), r1 = lane_read(v, 16), r2 = lane_read(v, 32), r3 = lane_read(v, 48);
+  return (r0 + r1) + (r2 + r3);
+}
+
 // Append from any subset of a wave's active lanes: one atomic per wave on the
 // shared cursor (ballot + popcount ranks), instead of one per lane.  Returns
 // the position of this lane's item, or -1 when pred is false.
@@ -123,6 +171,26 @@ __device__ __forceinline__ int64_t rec_append(int64_t* cursor, bool pred) {
     base = (long long)atomicAdd((unsigned long long*)cursor, (unsigned long long)__popcll(mask));
   base = __shfl(base, leader, REC_WAVE);
   return (int64_t)base + __popcll(mask & lt);
+}
+
+// Append from the lanes of a whole block (all threads must call): one atomic
+// per block on the shared cursor.  sh: NW + 1 ints of LDS, NW = waves per block.
+template <int NW>
+__device__ __forceinline__ int64_t rec_block_append(int64_t* cursor, bool pred, long long* sh) {
+  const int lane = rec_lane(), wave = (int)(threadIdx.x / REC_WAVE);
+  uint64_t mask = __ballot(pred);
+  const uint64_t lt = lane ? (~0ULL >> (64 - lane)) : 0ULL;
+  if (lane == 0) sh[wave] = (long long)__popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long tot = 0;
+    for (int w = 0; w < NW; ++w) { long long c = sh[w]; sh[w] = tot; tot += c; }
+    sh[NW] = tot ? (long long)atomicAdd((unsigned long long*)cursor, (unsigned long long)tot) : 0;
+  }
+  __syncthreads();
+  int64_t pos = pred ? (int64_t)(sh[NW] + sh[wave] + __popcll(mask & lt)) : -1;
+  __syncthreads();
+  return pos;
 }
 
 // Work counters are kept in REC_WORK_COPIES copies of 4 so that concurrent

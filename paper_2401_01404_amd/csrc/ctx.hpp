@@ -97,11 +97,12 @@ struct rec_ctx {
   int32_t *S, *S2, *loc;
   int64_t *cnt, *off;   // per node counts / offsets (N + 1)
   int64_t cand_cap;
-  int32_t* cand_v; uint32_t* cand_slot;
+  int32_t* cand_v; int32_t* cand_gi; uint32_t* cand_slot;
   int32_t *ts_i, *ts_j; uint32_t* ts_slot;    // to-score list
-  int32_t* inoff_cnt;   // N
+  int32_t* inoff_cnt;   // N (fill cursors)
   int64_t* inoff;       // N + 1
-  int32_t* in_src;      // list_cap
+  int32_t* in_src;      // list_cap: capped in-neighbours, k per node
+  int32_t* capcnt;      // N
   uint64_t* dset_keys; uint64_t dset_mask;
   uint64_t* pset_keys; uint64_t pset_mask;
   int64_t pool_cap;
@@ -157,6 +158,10 @@ rec_status rec_wtable_insert_list(rec_ctx* ctx, int64_t n, const int32_t* ei, co
 rec_status rec_launch_score(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
                             const uint32_t* slot, double* gain_out, double* w_out,
                             const Cache* cache);
+// Score the candidates whose slot word carries the owner bit: pair
+// (gi[p], S[v[p]]), gain to the cache slot.
+rec_status rec_launch_score_owned(rec_ctx* ctx, int64_t P, const int32_t* gi, const int32_t* v,
+                                  const int32_t* S, const uint32_t* slot, const Cache* cache);
 // Apply one round of node-disjoint updates (see update kernels).
 rec_status rec_launch_update_round(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
                                    const int32_t* first, uint8_t* done, double* dw);

@@ -272,12 +272,13 @@ __global__ void k_winsert(WTable W, int64_t n, const int32_t* ei, const int32_t*
 }
 
 // occupied, nonzero table entries -> sort records (key = pair key, val = slot)
-__global__ void k_wcompact(WTable W, uint64_t cap, uint64_t* klo, uint32_t* val, int64_t* n,
-                           int64_t max_n) {
+__global__ __launch_bounds__(256) void k_wcompact(WTable W, uint64_t cap, uint64_t* klo,
+                                                  uint32_t* val, int64_t* n, int64_t max_n) {
+  __shared__ long long sh[256 / REC_WAVE + 1];
   uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t k = s < cap ? W.keys[s] : REC_EMPTY;
   bool keep = k != REC_EMPTY && W.vals[s] != 0.0;
-  int64_t p = rec_append(n, keep);
+  int64_t p = rec_block_append<256 / REC_WAVE>(n, keep, sh);
   if (p >= 0 && p < max_n) { klo[p] = k; val[p] = (uint32_t)s; }
 }
 

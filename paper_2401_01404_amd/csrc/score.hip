@@ -110,6 +110,55 @@ struct Lane {
   R v[NPL];       // x_i t_j (Ising); r_j (Gaussian)
 };
 
+// Raw j-side row of one lane, loaded ahead of its use.
+template <class R, int NPL, int MODEL>
+struct JRaw {
+  static constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  int xb[CH];                                      // VEC int8 samples per chunk
+  R t[MODEL == REC_KINETIC ? 1 : NPL];             // t_j (Ising) or r_j (Gaussian)
+  float xg[MODEL == REC_GAUSS ? NPL : 1];          // x_j (Gaussian)
+};
+
+template <int VEC>
+__device__ __forceinline__ int ld_bytes(const int8_t* p) {
+  if constexpr (VEC == 4) return *reinterpret_cast<const int*>(p);
+  else if constexpr (VEC == 2) return (int)*reinterpret_cast<const unsigned short*>(p);
+  else return (int)(unsigned char)p[0];
+}
+__device__ __forceinline__ float byte_at(int w, int k) { return (float)(int8_t)((w >> (8 * k)) & 0xff); }
+
+template <int VEC, class R>
+__device__ __forceinline__ void ld_vec(const R* p, R* o) {
+  if constexpr (VEC == 4 && sizeof(R) == 4) {
+    float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  } else if constexpr (VEC == 4 && sizeof(R) == 8) {
+    double2 a = *reinterpret_cast<const double2*>(p);
+    double2 b = *reinterpret_cast<const double2*>(p + 2);
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+  } else {
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) o[k] = p[k];
+  }
+}
+
+template <class R, int NPL, int MODEL>
+__device__ __forceinline__ void fetch_j(const Fields& F, int j, JRaw<R, NPL, MODEL>& r, int lane) {
+  constexpr int VEC = JRaw<R, NPL, MODEL>::VEC, CH = JRaw<R, NPL, MODEL>::CH;
+  const int64_t row = (int64_t)j * F.Mp;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    int64_t o = smp<VEC>(c, lane);
+    if constexpr (MODEL == REC_GAUSS) {
+      ld_vec<VEC>(F.xf + row + o, r.xg + c * VEC);
+      ld_vec<VEC>(reinterpret_cast<const R*>(F.H) + row + o, r.t + c * VEC);
+    } else {
+      r.xb[c] = ld_bytes<VEC>(F.xs + row + o);
+      if constexpr (MODEL == REC_ISING) ld_vec<VEC>(reinterpret_cast<const R*>(F.T) + row + o, r.t + c * VEC);
+    }
+  }
+}
+
 // sum over the lane's samples of y = (a + tau)/(1 + a tau) and y^2
 template <class R, int NPL>
 __device__ __forceinline__ void side_sums(const R* a, R tau, R& A, R& Q) {
@@ -139,47 +188,113 @@ __device__ __forceinline__ double side_logs(const R* a, R tau) {
 
 struct PairOut { double gain, w, w0; };
 
-// Work counters of one wave: [0] pairs, [1] moment passes, [2] full Newton
-// evaluations, [3] log passes.
+// Work counters of one wave: pairs, moment passes, full Newton evaluations,
+// log passes.
 struct Work { int64_t pairs = 0, moments = 0, evals = 0, logs = 0; };
 
+// Ising / kinetic: u (and v) into the lane registers; returns this lane's part
+// of Phi(0) = c S - sum u (- sum v) and its part of S in *s_lane.
+template <class R, int NPL, int MODEL>
+__device__ __forceinline__ double form_j(const JRaw<R, NPL, MODEL>& r, Lane<R, NPL>& L,
+                                         float* s_lane) {
+  constexpr int VEC = JRaw<R, NPL, MODEL>::VEC, CH = JRaw<R, NPL, MODEL>::CH;
+  float s = 0.f;
+  R a = R(0), a2 = R(0);
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      const int q = c * VEC + k;
+      if constexpr (MODEL == REC_GAUSS) {
+        L.u[q] = (R)r.xg[q];
+        L.v[q] = r.t[q];
+      } else {
+        float x = byte_at(r.xb[c], k);
+        R u = (R)x * L.ti[q];
+        L.u[q] = u;
+        a += u;
+        if constexpr (MODEL == REC_ISING) {
+          R v = L.xi[q] * r.t[q];
+          L.v[q] = v;
+          a2 += v;
+        }
+        s += x * (float)L.xi[q];      // +-1 products: exact in float
+      }
+    }
+  }
+  *s_lane = s;
+  constexpr double c = MODEL == REC_ISING ? 2.0 : 1.0;
+  return c * (double)s - ((double)a + (double)a2);
+}
+
 // Exact score of pair (i, j) for the Ising (TWO = true) or kinetic model,
-// with the lane registers already holding u (and v).  Sc = c S (exact);
-// A0 = sum u (+ v), Q0 = sum (1 - u^2) (+ (1 - v^2)) over all padded samples.
+// lane registers holding u (and v); phi0 = Phi(0) (uniform); s_lane = this
+// lane's part of S.
 template <class R, int NPL, bool TWO>
-__device__ PairOut solve_ising(const Lane<R, NPL>& L, double Sc, double A0, double Q0, double w0,
+__device__ PairOut solve_ising(const Lane<R, NPL>& L, double phi0, float s_lane, double w0,
                                double lambda, int64_t M, int64_t Mp, Work& wk) {
   constexpr double nsides = TWO ? 2.0 : 1.0;
+  constexpr double c = TWO ? 2.0 : 1.0;
   const double npad = (double)(Mp - M);
+  PairOut o;
+  o.w0 = w0;
+  if (w0 == 0.0 && fabs(phi0) <= lambda) { o.gain = 0.0; o.w = 0.0; return o; }
+  const double Sc = c * (double)rec_wave_sum_dpp((int)s_lane);
   auto eval = [&](double tau, double& phi, double& dphi) {
     // the two sides are summed apart and added once, so (i,j) and (j,i) give
     // the same bits
     R A = R(0), Q = R(0), A2 = R(0), Q2 = R(0);
     side_sums<R, NPL>(L.u, (R)tau, A, Q);
     if constexpr (TWO) side_sums<R, NPL>(L.v, (R)tau, A2, Q2);
-    double As = rec_wave_sum_uni((double)A + (double)A2);
-    double Qs = rec_wave_sum_uni((double)Q + (double)Q2);
+    double As = rec_wave_sum_dpp((double)A + (double)A2);
+    double Qs = rec_wave_sum_dpp((double)Q + (double)Q2);
     double t = (double)(R)tau;
     phi = Sc - As + nsides * npad * t;
     double om = 1.0 - t * t;
     dphi = -((nsides * (double)Mp - Qs) / om - nsides * npad);
     ++wk.evals;
   };
-  PairOut o;
-  o.w0 = w0;
   double tau0, phi, dphi;
+  double mu1 = 0.0, mu2 = 0.0, mu3 = 0.0;
   if (w0 == 0.0) {
+    // moments mu_k = sum (1 - u^2) u^k; padding has u = 0, so only mu0 sees it
+    R m0 = R(0), m1 = R(0), m2 = R(0), m3 = R(0), n0 = R(0), n1 = R(0), n2 = R(0), n3 = R(0);
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      R u = L.u[k];
+      R q = fma(-u, u, R(1));
+      m0 += q;
+      R t1 = q * u;
+      m1 += t1;
+      R t2 = t1 * u;
+      m2 += t2;
+      m3 = fma(t2, u, m3);
+      if constexpr (TWO) {
+        R v = L.v[k];
+        R qv = fma(-v, v, R(1));
+        n0 += qv;
+        R s1 = qv * v;
+        n1 += s1;
+        R s2 = s1 * v;
+        n2 += s2;
+        n3 = fma(s2, v, n3);
+      }
+    }
+    double mu0 = rec_wave_sum_dpp((double)m0 + (double)n0) - nsides * npad;
+    mu1 = rec_wave_sum_dpp((double)m1 + (double)n1);
+    mu2 = rec_wave_sum_dpp((double)m2 + (double)n2);
+    mu3 = rec_wave_sum_dpp((double)m3 + (double)n3);
+    ++wk.moments;
     tau0 = 0.0;
-    phi = Sc - A0;                       // padding has u = 0
-    dphi = -(Q0 - nsides * npad);        // padding has 1 - u^2 = 1
+    phi = phi0;
+    dphi = -mu0;
   } else {
     tau0 = (double)tanh_((R)(-w0));
     eval(tau0, phi, dphi);
   }
   double tau;
   if (fabs(phi) <= lambda) {
-    if (w0 == 0.0) { o.gain = 0.0; o.w = 0.0; return o; }
-    tau = tau0;
+    tau = tau0;     // w0 != 0 here: the optimum is w = 0
     o.w = 0.0;
   } else {
     double s = phi > 0 ? 1.0 : -1.0;
@@ -188,32 +303,8 @@ __device__ PairOut solve_ising(const Lane<R, NPL>& L, double Sc, double A0, doub
     double f = phi - target, df = dphi;
     tau = tau0;
     if (w0 == 0.0) {
-      // quartic Taylor model of Phi around 0 from the moments mu1..mu3
-      R m1 = R(0), m2 = R(0), m3 = R(0), n1 = R(0), n2 = R(0), n3 = R(0);
-#pragma unroll
-      for (int k = 0; k < NPL; ++k) {
-        R u = L.u[k];
-        R q = fma(-u, u, R(1));
-        R t1 = q * u;
-        m1 += t1;
-        R t2 = t1 * u;
-        m2 += t2;
-        m3 = fma(t2, u, m3);
-        if constexpr (TWO) {
-          R v = L.v[k];
-          R qv = fma(-v, v, R(1));
-          R s1 = qv * v;
-          n1 += s1;
-          R s2 = s1 * v;
-          n2 += s2;
-          n3 = fma(s2, v, n3);
-        }
-      }
-      double mu1 = rec_wave_sum_uni((double)m1 + (double)n1);
-      double mu2 = rec_wave_sum_uni((double)m2 + (double)n2);
-      double mu3 = rec_wave_sum_uni((double)m3 + (double)n3);
-      double mu0 = -df;
-      ++wk.moments;
+      // root of the quartic model f - mu0 t + mu1 t^2 - mu2 t^3 + mu3 t^4
+      const double mu0 = -df;
       double t = f / mu0;
       for (int q = 0; q < 8; ++q) {
         double P = f + t * (-mu0 + t * (mu1 + t * (-mu2 + t * mu3)));
@@ -245,7 +336,7 @@ __device__ PairOut solve_ising(const Lane<R, NPL>& L, double Sc, double A0, doub
   }
   double Ls = side_logs<R, NPL>(L.u, (R)tau);
   if constexpr (TWO) Ls += side_logs<R, NPL>(L.v, (R)tau);
-  Ls = rec_wave_sum_uni(Ls);
+  Ls = rec_wave_sum_dpp(Ls);
   ++wk.logs;
   double d = rec_atanh(tau);
   double g = Sc * d - nsides * (double)M * rec_lcosh_tau(tau) - Ls -
@@ -261,7 +352,7 @@ __device__ PairOut solve_gauss(const Lane<R, NPL>& L, double vi, double vj, doub
   R a = R(0);
 #pragma unroll
   for (int k = 0; k < NPL; ++k) a = fma(L.ti[k], L.u[k], fma(L.v[k], L.xi[k], a));
-  double as = -rec_wave_sum_uni((double)a);
+  double as = -rec_wave_sum_dpp((double)a);
   double b = vi * sqj + vj * sqi;
   double z = w0 + as / b;
   double ws = z > 0 ? fmax(z - lambda / b, 0.0) : fmin(z + lambda / b, 0.0);
@@ -281,81 +372,49 @@ __device__ __forceinline__ void load_i(const Fields& F, int i, Lane<R, NPL>& L, 
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     int64_t o = smp<VEC>(c, lane);
-    ld_r<VEC>(Hr + o, L.ti + c * VEC);
-    float xv[VEC];
-    if constexpr (MODEL == REC_GAUSS) ld_f<VEC>(F.xf + (int64_t)i * F.Mp + o, xv);
-    else ld_x<VEC>((MODEL == REC_KINETIC ? F.ys : F.xs) + (int64_t)i * F.Mp + o, xv);
-#pragma unroll
-    for (int k = 0; k < VEC; ++k) L.xi[c * VEC + k] = (R)xv[k];
-  }
-}
-
-// Load the j side and form u, v; returns c S for the Ising / kinetic models
-// and the sums A0 = sum u (+ v), Q0 = sum (1 - u^2) (+ (1 - v^2)).
-template <class R, int NPL, int MODEL>
-__device__ __forceinline__ double load_j(const Fields& F, int j, Lane<R, NPL>& L, int lane,
-                                         double& A0, double& Q0) {
-  constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
-  float s = 0.f;
-  R a = R(0), q = R(0), a2 = R(0), q2 = R(0);
-#pragma unroll
-  for (int c = 0; c < CH; ++c) {
-    int64_t o = smp<VEC>(c, lane);
-    float xv[VEC];
+    ld_vec<VEC>(Hr + o, L.ti + c * VEC);
     if constexpr (MODEL == REC_GAUSS) {
-      ld_f<VEC>(F.xf + (int64_t)j * F.Mp + o, xv);
-      R rv[VEC];
-      ld_r<VEC>(reinterpret_cast<const R*>(F.H) + (int64_t)j * F.Mp + o, rv);
+      float xv[VEC];
+      ld_vec<VEC>(F.xf + (int64_t)i * F.Mp + o, xv);
 #pragma unroll
-      for (int k = 0; k < VEC; ++k) { L.u[c * VEC + k] = (R)xv[k]; L.v[c * VEC + k] = rv[k]; }
+      for (int k = 0; k < VEC; ++k) L.xi[c * VEC + k] = (R)xv[k];
     } else {
-      ld_x<VEC>(F.xs + (int64_t)j * F.Mp + o, xv);
-      R tv[VEC];
-      if constexpr (MODEL == REC_ISING)
-        ld_r<VEC>(reinterpret_cast<const R*>(F.T) + (int64_t)j * F.Mp + o, tv);
+      int w = ld_bytes<VEC>((MODEL == REC_KINETIC ? F.ys : F.xs) + (int64_t)i * F.Mp + o);
 #pragma unroll
-      for (int k = 0; k < VEC; ++k) {
-        int qk = c * VEC + k;
-        R u = (R)xv[k] * L.ti[qk];
-        L.u[qk] = u;
-        a += u;
-        q = fma(-u, u, q + R(1));
-        if constexpr (MODEL == REC_ISING) {
-          R v = L.xi[qk] * tv[k];
-          L.v[qk] = v;
-          a2 += v;
-          q2 = fma(-v, v, q2 + R(1));
-        }
-        s += xv[k] * (float)L.xi[qk];      // +-1 products: exact in float
-      }
+      for (int k = 0; k < VEC; ++k) L.xi[c * VEC + k] = (R)byte_at(w, k);
     }
   }
-  if constexpr (MODEL == REC_GAUSS) { A0 = Q0 = 0.0; return 0.0; }
-  A0 = rec_wave_sum_uni((double)a + (double)a2);
-  Q0 = rec_wave_sum_uni((double)q + (double)q2);
-  int si = (int)s;
-  si = rec_wave_sum_uni(si);
-  return (MODEL == REC_ISING ? 2.0 : 1.0) * (double)si;
 }
 
 template <class R, int NPL, int MODEL>
-__device__ __forceinline__ PairOut solve(const Fields& F, const Lane<R, NPL>& L, double Sc,
-                                         double A0, double Q0, int i, int j, double w0,
-                                         double lambda, Work& wk) {
+__device__ __forceinline__ PairOut solve(const Fields& F, const Lane<R, NPL>& L, double phi0,
+                                         float s_lane, int i, int j, double w0, double lambda,
+                                         Work& wk) {
   ++wk.pairs;
   if constexpr (MODEL == REC_GAUSS) {
     double vi = F.theta[i] * F.theta[i], vj = F.theta[j] * F.theta[j];
     return solve_gauss<R, NPL>(L, vi, vj, F.sq[i], F.sq[j], w0, lambda);
   } else {
-    return solve_ising<R, NPL, MODEL == REC_ISING>(L, Sc, A0, Q0, w0, lambda, F.M, F.Mp, wk);
+    return solve_ising<R, NPL, MODEL == REC_ISING>(L, phi0, s_lane, w0, lambda, F.M, F.Mp, wk);
   }
 }
 
+__device__ __forceinline__ bool pair_ok(int i, int j, int64_t N) {
+  return i >= 0 && j >= 0 && i < N && j < N && i != j;
+}
+
+constexpr int SKIP = -2;   // pair not owned by this launch (owner mode)
+constexpr uint32_t OWNER = 0x80000000u;
+
+// Pairs (I[p], J[p]) (J through Smap when given).  slot == null: results to
+// gain_out[p]; otherwise to the cache slot slot[p] (owner mode: only entries
+// whose slot word has the owner bit are scored).
 template <class R, int NPL, int MODEL>
 __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda, int64_t P,
                                                const int32_t* __restrict__ I,
                                                const int32_t* __restrict__ J,
-                                               const uint32_t* __restrict__ slot,
+                                               const int32_t* __restrict__ Smap,
+                                               const uint32_t* __restrict__ slot, int owned,
                                                double* __restrict__ gain_out,
                                                double* __restrict__ w_out, double* __restrict__ ovf,
                                                uint64_t cache_cap, int32_t* err, int ppw,
@@ -369,21 +428,42 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
   int li = -1, lj = -1;
   double lw = 0.0;
   if (lane < np) {
-    li = I[p0 + lane];
-    lj = J[p0 + lane];
-    if (li >= 0 && lj >= 0 && li < F.N && lj < F.N && li != lj)
-      lw = lookup_w(W, li, lj, MODEL == REC_KINETIC);
+    uint32_t sw = slot ? slot[p0 + lane] : 0u;
+    if (owned && !(sw & OWNER)) {
+      li = SKIP;
+    } else {
+      li = I[p0 + lane];
+      lj = J[p0 + lane];
+      if (Smap) lj = Smap[lj];
+      if (pair_ok(li, lj, F.N)) lw = lookup_w(W, li, lj, MODEL == REC_KINETIC);
+    }
   }
   Lane<R, NPL> L;
+  JRaw<R, NPL, MODEL> nx;
   int cur = -1;
   Work wk;
-  for (int q = 0; q < np; ++q) {
+  // the pairs this wave scores, in order: one bit per lane holding one
+  uint64_t todo = __ballot(lane < np && li != SKIP);
+  if (todo) {
+    int q0 = __ffsll((unsigned long long)todo) - 1;
+    int i0 = rec_uni(__shfl(li, q0, REC_WAVE)), j0 = rec_uni(__shfl(lj, q0, REC_WAVE));
+    if (pair_ok(i0, j0, F.N)) fetch_j<R, NPL, MODEL>(F, j0, nx, lane);
+  }
+  while (todo) {
+    const int q = __ffsll((unsigned long long)todo) - 1;
+    todo &= todo - 1;
     const int64_t p = p0 + q;
     int i = rec_uni(__shfl(li, q, REC_WAVE)), j = rec_uni(__shfl(lj, q, REC_WAVE));
     double w0 = rec_uni(__shfl(lw, q, REC_WAVE));
-    uint64_t o = slot ? (uint64_t)slot[p] : (uint64_t)p;
+    JRaw<R, NPL, MODEL> rw = nx;   // holds this pair's row (fetched ahead)
+    if (todo) {                    // next pair's row in flight while this one computes
+      const int q1 = __ffsll((unsigned long long)todo) - 1;
+      int i1 = rec_uni(__shfl(li, q1, REC_WAVE)), j1 = rec_uni(__shfl(lj, q1, REC_WAVE));
+      if (pair_ok(i1, j1, F.N)) fetch_j<R, NPL, MODEL>(F, j1, nx, lane);
+    }
+    uint64_t o = slot ? (uint64_t)(slot[p] & ~OWNER) : (uint64_t)p;
     double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
-    if (i < 0 || j < 0 || i >= F.N || j >= F.N || i == j) {
+    if (!pair_ok(i, j, F.N)) {
       if (lane == 0) {
         *dst = __builtin_nan("");
         if (w_out) w_out[p] = __builtin_nan("");
@@ -392,9 +472,10 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
       continue;
     }
     if (i != cur) { load_i<R, NPL, MODEL>(F, i, L, lane); cur = i; }
-    double A0, Q0;
-    double Sc = load_j<R, NPL, MODEL>(F, j, L, lane, A0, Q0);
-    PairOut r = solve<R, NPL, MODEL>(F, L, Sc, A0, Q0, i, j, w0, lambda, wk);
+    float s_lane;
+    double phi_l = form_j<R, NPL, MODEL>(rw, L, &s_lane);
+    double phi0 = MODEL == REC_GAUSS ? 0.0 : rec_wave_sum_dpp(phi_l);
+    PairOut r = solve<R, NPL, MODEL>(F, L, phi0, s_lane, i, j, w0, lambda, wk);
     double g = r.gain;
     if constexpr (sizeof(R) == 4) g = (double)(float)g;   // FP32 scores
     if (lane == 0) {
@@ -429,12 +510,15 @@ __global__ __launch_bounds__(256) void k_update(Fields F, WTable W, double lambd
   if (MODEL != REC_KINETIC && first[j] != (int32_t)p) return;
   Lane<R, NPL> L;
   load_i<R, NPL, MODEL>(F, i, L, lane);
-  double A0, Q0;
-  double Sc = load_j<R, NPL, MODEL>(F, j, L, lane, A0, Q0);
+  JRaw<R, NPL, MODEL> rw;
+  fetch_j<R, NPL, MODEL>(F, j, rw, lane);
+  float s_lane;
+  double phi_l = form_j<R, NPL, MODEL>(rw, L, &s_lane);
+  double phi0 = MODEL == REC_GAUSS ? 0.0 : rec_wave_sum_dpp(phi_l);
   bool directed = MODEL == REC_KINETIC;
-  double w0 = lookup_w(W, i, j, directed);
+  double w0 = rec_uni(lookup_w(W, i, j, directed));
   Work wk;
-  PairOut r = solve<R, NPL, MODEL>(F, L, Sc, A0, Q0, i, j, w0, lambda, wk);
+  PairOut r = solve<R, NPL, MODEL>(F, L, phi0, s_lane, i, j, w0, lambda, wk);
   double d = r.w - w0;
   if (d != 0.0) {
     // rows of H (and T): h_i += d x_j, h_j += d x_i [App. A, O(1) field bookkeeping]
@@ -476,8 +560,10 @@ __global__ __launch_bounds__(256) void k_update(Fields F, WTable W, double lambd
 
 template <class R, int MODEL>
 rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
-                          const uint32_t* slot, double* gain_out, double* w_out, const Cache* C) {
-  const int ppw = 8;
+                          const int32_t* Smap, const uint32_t* slot, int owned, double* gain_out,
+                          double* w_out, const Cache* C) {
+  // pairs per wave: owner mode reads 32 candidates of which roughly half are scored
+  const int ppw = owned ? 32 : 8;
   int64_t waves = (P + ppw - 1) / ppw;
   int64_t blocks = (waves * REC_WAVE + 255) / 256;
   double* ovf = C ? C->ovf : nullptr;
@@ -485,8 +571,8 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
   int64_t* ev = ctx->work;
 #define REC_SC(NPL)                                                                              \
   hipLaunchKernelGGL((k_score<R, NPL, MODEL>), dim3(blocks), dim3(256), 0, ctx->stream, ctx->F,  \
-                     ctx->W, ctx->cfg.lambda, P, I, J, slot, gain_out, w_out, ovf, cap,          \
-                     ctx->err_flag, ppw, ev)
+                     ctx->W, ctx->cfg.lambda, P, I, J, Smap, slot, owned, gain_out, w_out, ovf,  \
+                     cap, ctx->err_flag, ppw, ev)
   switch (ctx->F.npl) {
     case 1: REC_SC(1); break;
     case 2: REC_SC(2); break;
@@ -524,11 +610,12 @@ rec_status launch_update_m(rec_ctx* ctx, int64_t m, const int32_t* I, const int3
 
 template <class R>
 rec_status launch_score_r(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
-                          const uint32_t* slot, double* g, double* w, const Cache* C) {
+                          const int32_t* Smap, const uint32_t* slot, int owned, double* g,
+                          double* w, const Cache* C) {
   switch (ctx->cfg.model) {
-    case REC_ISING: return launch_score_m<R, REC_ISING>(ctx, P, I, J, slot, g, w, C);
-    case REC_GAUSS: return launch_score_m<R, REC_GAUSS>(ctx, P, I, J, slot, g, w, C);
-    case REC_KINETIC: return launch_score_m<R, REC_KINETIC>(ctx, P, I, J, slot, g, w, C);
+    case REC_ISING: return launch_score_m<R, REC_ISING>(ctx, P, I, J, Smap, slot, owned, g, w, C);
+    case REC_GAUSS: return launch_score_m<R, REC_GAUSS>(ctx, P, I, J, Smap, slot, owned, g, w, C);
+    case REC_KINETIC: return launch_score_m<R, REC_KINETIC>(ctx, P, I, J, Smap, slot, owned, g, w, C);
   }
   return REC_E_INVAL;
 }
@@ -557,9 +644,27 @@ rec_status rec_timing_resolve(rec_ctx* ctx) {
   return REC_OK;
 }
 
+namespace {
+rec_status launch_score_any(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
+                            const int32_t* Smap, const uint32_t* slot, int owned,
+                            double* gain_out, double* w_out, const Cache* cache);
+}
+
 rec_status rec_launch_score(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
                             const uint32_t* slot, double* gain_out, double* w_out,
                             const Cache* cache) {
+  return launch_score_any(ctx, P, I, J, nullptr, slot, 0, gain_out, w_out, cache);
+}
+
+rec_status rec_launch_score_owned(rec_ctx* ctx, int64_t P, const int32_t* gi, const int32_t* v,
+                                  const int32_t* S, const uint32_t* slot, const Cache* cache) {
+  return launch_score_any(ctx, P, gi, v, S, slot, 1, cache->vals, nullptr, cache);
+}
+
+namespace {
+rec_status launch_score_any(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
+                            const int32_t* Smap, const uint32_t* slot, int owned,
+                            double* gain_out, double* w_out, const Cache* cache) {
   if (P <= 0) return REC_OK;
   if (ctx->timing) {
     if (ctx->ev_used == 256) {
@@ -574,8 +679,9 @@ rec_status rec_launch_score(rec_ctx* ctx, int64_t P, const int32_t* I, const int
     }
     REC_HIP(hipEventRecord(ctx->ev[ctx->ev_used].first, ctx->stream));
   }
-  rec_status st = ctx->fp32 ? launch_score_r<float>(ctx, P, I, J, slot, gain_out, w_out, cache)
-                            : launch_score_r<double>(ctx, P, I, J, slot, gain_out, w_out, cache);
+  rec_status st = ctx->fp32
+                      ? launch_score_r<float>(ctx, P, I, J, Smap, slot, owned, gain_out, w_out, cache)
+                      : launch_score_r<double>(ctx, P, I, J, Smap, slot, owned, gain_out, w_out, cache);
   if (ctx->timing && st == REC_OK) {
     REC_HIP(hipEventRecord(ctx->ev[ctx->ev_used].second, ctx->stream));
     ++ctx->ev_used;
@@ -584,6 +690,7 @@ rec_status rec_launch_score(rec_ctx* ctx, int64_t P, const int32_t* I, const int
   }
   return st;
 }
+}  // namespace
 
 rec_status rec_launch_update_round(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
                                    const int32_t* first, uint8_t* done, double* dw) {

@@ -72,8 +72,25 @@ __device__ uint32_t claim(const ClaimArgs& A, int i, int j) {
   return (uint32_t)slot;
 }
 
+// Candidate claims mark the lane that must score the pair with the top bit
+// of its slot word (REC_OWNER) instead of queueing it, so no shared cursor is
+// touched; the score kernel then runs over the candidate array itself.
+constexpr uint32_t REC_OWNER = 0x80000000u;
+constexpr uint32_t REC_SLOT_BAD = 0x7fffffffu;
+
+__device__ uint32_t claim_owned(const ClaimArgs& A, int i, int j) {
+  bool ins = false;
+  int64_t s = rec_hash_insert(A.C.keys, A.C.mask, rec_pair_key(i, j, A.directed != 0),
+                              REC_MAX_PROBE, &ins);
+  int64_t o = rec_append(A.ovf_n, s < 0);         // no free slot: overflow area (rare)
+  if (s >= 0) return (uint32_t)s | (ins ? REC_OWNER : 0u);
+  if (o >= A.C.ovf_cap) { atomicOr(A.err, 16); return REC_SLOT_BAD; }
+  return (uint32_t)((A.C.mask + 1) + (uint64_t)o) | REC_OWNER;
+}
+
 __device__ __forceinline__ double slot_gain(const Cache& C, uint32_t slot) {
-  if (slot == 0xffffffffu) return __builtin_nan("");
+  slot &= ~REC_OWNER;
+  if (slot == REC_SLOT_BAD || slot == 0x7fffffffu) return __builtin_nan("");
   uint64_t cap = C.mask + 1;
   return slot < cap ? C.vals[slot] : C.ovf[slot - cap];
 }
@@ -122,25 +139,61 @@ __global__ __launch_bounds__(REC_WAVE) void k_knn_init(const int32_t* S, int64_t
 }
 
 // ------------------------------------------------------------ in-edges --
-// One record per directed edge a -> b of G: sort key (b, hash32, a).
-__global__ void k_in_records(const int32_t* S, const int32_t* Gidx, int64_t n, int k,
-                             uint64_t seed, int level, int iter, uint64_t* khi, uint64_t* klo,
-                             uint32_t* val, int64_t* indeg) {
+// Undirected view U: every node b keeps all its out-neighbours and, of its
+// in-neighbours a (edges a -> b), the k with the smallest (hash32, a) keys.
+__global__ void k_in_count(const int32_t* Gidx, int64_t n, int k, int64_t* indeg) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * k) return;
+  atomicAdd((unsigned long long*)&indeg[Gidx[e]], 1ULL);
+}
+
+__global__ void k_in_fill(const int32_t* S, const int32_t* Gidx, int64_t n, int k, uint64_t seed,
+                          int level, int iter, const int64_t* inoff, int32_t* cursor,
+                          uint64_t* in_key) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * k) return;
   int64_t a = e / k;
   int b = Gidx[e];
   uint64_t h = rec_ctr(seed, REC_STREAM_CAP, ((uint64_t)(uint32_t)level << 32) | (uint32_t)iter,
                        ((uint64_t)(uint32_t)S[a] << 32) | (uint32_t)S[b]) >> 32;
-  khi[e] = (uint64_t)b;
-  klo[e] = (h << 32) | (uint64_t)a;
-  val[e] = 0;
-  atomicAdd((unsigned long long*)&indeg[b], 1ULL);
+  int64_t pos = inoff[b] + atomicAdd(&cursor[b], 1);
+  in_key[pos] = (h << 32) | (uint64_t)a;
 }
 
-__global__ void k_in_src(const uint64_t* klo, int64_t ne, int32_t* in_src) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < ne) in_src[e] = (int32_t)(klo[e] & 0xffffffffu);
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    uint64_t w = __shfl_xor(v, o, REC_WAVE);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+// one wave per node: capin[b*k + c] = sources of the (up to) k smallest keys
+__global__ __launch_bounds__(REC_WAVE) void k_in_select(int64_t n, int k, const int64_t* inoff,
+                                                        const uint64_t* in_key, int32_t* capin,
+                                                        int32_t* capcnt) {
+  const int64_t b = blockIdx.x;
+  if (b >= n) return;
+  const int lane = threadIdx.x;
+  const int64_t e0 = inoff[b], deg = inoff[b + 1] - e0;
+  if (deg <= k) {
+    for (int64_t c = lane; c < deg; c += REC_WAVE) capin[b * k + c] = (int32_t)(in_key[e0 + c] & 0xffffffffu);
+    if (lane == 0) capcnt[b] = (int32_t)deg;
+    return;
+  }
+  uint64_t prev = 0;
+  for (int r = 0; r < k; ++r) {
+    uint64_t best = ~0ULL;
+    for (int64_t c = lane; c < deg; c += REC_WAVE) {
+      uint64_t key = in_key[e0 + c];
+      if ((r == 0 || key > prev) && key < best) best = key;
+    }
+    best = wave_min_u64(best);
+    if (lane == 0) capin[b * k + r] = (int32_t)(best & 0xffffffffu);
+    prev = best;
+  }
+  if (lane == 0) capcnt[b] = k;
 }
 
 // ---------------------------------------------------------- candidates --
@@ -150,28 +203,28 @@ __global__ void k_in_src(const uint64_t* klo, int64_t ne, int32_t* in_src) {
 struct CandArgs {
   const int32_t* S;
   const int32_t* Gidx;
-  const int64_t* inoff;
-  const int32_t* in_src;
+  const int32_t* capin;    // n x k capped in-neighbours
+  const int32_t* capcnt;   // n
   int64_t n;
   int k;
   int mode;
 };
 
-__device__ __forceinline__ int u_size(const CandArgs& P, int64_t b) {
-  int64_t deg = P.inoff[b + 1] - P.inoff[b];
-  return P.k + (int)(deg < P.k ? deg : P.k);
-}
+__device__ __forceinline__ int u_size(const CandArgs& P, int64_t b) { return P.k + P.capcnt[b]; }
 __device__ __forceinline__ int u_get(const CandArgs& P, int64_t b, int c) {
-  return c < P.k ? P.Gidx[b * P.k + c] : P.in_src[P.inoff[b] + (c - P.k)];
+  return c < P.k ? P.Gidx[b * P.k + c] : P.capin[b * P.k + (c - P.k)];
 }
 
-__global__ __launch_bounds__(BT) void k_cand(CandArgs P, int pass, int64_t a0, int64_t a1,
+template <int pass>
+__global__ __launch_bounds__(BT) void k_cand(CandArgs P, int64_t a0, int64_t a1,
                                              int64_t* cnt, const int64_t* off, int64_t base,
-                                             int32_t* cand_v, uint32_t* cand_slot, ClaimArgs A) {
+                                             int32_t* cand_v, int32_t* cand_gi,
+                                             uint32_t* cand_slot, ClaimArgs A) {
   extern __shared__ uint32_t sm[];
   const int64_t a = a0 + blockIdx.x;
   if (a >= a1) return;
   const int tid = threadIdx.x;
+  const int lane = tid & (REC_WAVE - 1);
   const int64_t words = (P.n + 31) / 32;
   uint32_t* bm = sm;
   int32_t* ul = reinterpret_cast<int32_t*>(sm + words);   // U(a), at most 2k entries
@@ -195,27 +248,42 @@ __global__ __launch_bounds__(BT) void k_cand(CandArgs P, int pass, int64_t a0, i
   if (tid == 0) s_nu = nu;
   __syncthreads();
   const int64_t obase = pass ? off[a] - base : 0;
-  auto emit = [&](int v) {
-    uint32_t old = atomicOr(&bm[v >> 5], 1u << (v & 31));
-    if (old & (1u << (v & 31))) return;
-    int q = atomicAdd(&s_cnt, 1);
-    if (pass) {
-      if (q >= cnt[a]) { atomicOr(A.err, 128); return; }   // count pass disagrees
-      int64_t pos = obase + q;
-      cand_v[pos] = v;
-      cand_slot[pos] = claim(A, P.S[a], P.S[v]);
+  const int ga = P.S[a];
+  const uint64_t lt = lane ? (~0ULL >> (64 - lane)) : 0ULL;
+  // all threads run the same number of rounds so the wave ballots see every lane
+  const int64_t total = P.mode == 0 ? (int64_t)s_nu * (2 * P.k) : P.n;
+  const int64_t rounds = (total + BT - 1) / BT;
+  for (int64_t r = 0; r < rounds; ++r) {
+    const int64_t q = r * BT + tid;
+    int v = -1;
+    if (q < total) {
+      if (P.mode == 0) {
+        const int span = 2 * P.k;
+        int bi = (int)(q / span), c = (int)(q % span);
+        int b = ul[bi];
+        if (c < u_size(P, b)) v = u_get(P, b, c);
+      } else {
+        v = (int)q;
+      }
     }
-  };
-  if (P.mode == 0) {
-    const int span = 2 * P.k;
-    const int64_t total = (int64_t)s_nu * span;
-    for (int64_t q = tid; q < total; q += BT) {
-      int bi = (int)(q / span), c = (int)(q % span);
-      int b = ul[bi];
-      if (c < u_size(P, b)) emit(u_get(P, b, c));
+    bool fresh = false;
+    if (v >= 0) {
+      uint32_t bit = 1u << (v & 31);
+      fresh = !(atomicOr(&bm[v >> 5], bit) & bit);
     }
-  } else {
-    for (int64_t v = tid; v < P.n; v += BT) emit((int)v);
+    uint64_t mask = __ballot(fresh);
+    int wbase = 0;
+    if (lane == 0 && mask) wbase = atomicAdd(&s_cnt, (int)__popcll(mask));
+    wbase = __shfl(wbase, 0, REC_WAVE);
+    if (pass && fresh) {
+      int64_t pos = obase + wbase + __popcll(mask & lt);
+      if (pos - obase >= cnt[a]) atomicOr(A.err, 128);   // count pass disagrees
+      else {
+        cand_v[pos] = v;
+        cand_gi[pos] = ga;
+        cand_slot[pos] = claim_owned(A, ga, P.S[v]);
+      }
+    }
   }
   __syncthreads();
   if (pass == 0 && tid == 0) cnt[a] = s_cnt;
@@ -621,31 +689,26 @@ struct Search {
       max_iter = 2 * lg + 10;
     }
     const int iters_to_run = mode == 0 ? max_iter : 1;
-    CandArgs P{S, ctx->Gidx, ctx->inoff, ctx->in_src, n, k, mode};
+    CandArgs P{S, ctx->Gidx, ctx->in_src, ctx->capcnt, n, k, mode};
     size_t cand_lds = words * 4 + (mode == 0 ? (size_t)2 * k * 4 : 0);
     if (cand_lds > 64 * 1024) { ctx->err = "node set too large for the candidate kernel"; return REC_E_INVAL; }
     for (int it = 0; it < iters_to_run; ++it) {
       P.Gidx = ctx->Gidx;   // the lists ping-pong between two buffers
       if (mode == 0) {
-        // undirected view U: in-neighbour lists sorted by (hash32, source)
+        // undirected view U: the k in-neighbours of each node with the smallest keys
         int64_t ne = n * k;
         hipMemsetAsync(ctx->cnt, 0, sizeof(int64_t) * (n + 1), s);
-        hipLaunchKernelGGL(k_in_records, dim3(gridn(ne)), dim3(256), 0, s, S, ctx->Gidx, n, k, seed,
-                           level, it, ctx->sb.khi[0], ctx->sb.klo[0], ctx->sb.val[0], ctx->cnt);
-        int nb = bits_for(n);
-        Digit dg[16];
-        int nd = 0;
-        for (int b = 0; b < nb; b += 8) dg[nd++] = {0, b};
-        for (int b = 32; b < 64; b += 8) dg[nd++] = {0, b};
-        for (int b = 0; b < nb; b += 8) dg[nd++] = {1, b};
-        int cur = 0;
-        if ((st = rec_radix_sort(ctx, ne, dg, nd, &cur)) != REC_OK) return st;
+        hipMemsetAsync(ctx->inoff_cnt, 0, sizeof(int32_t) * n, s);
+        hipLaunchKernelGGL(k_in_count, dim3(gridn(ne)), dim3(256), 0, s, ctx->Gidx, n, k, ctx->cnt);
         if ((st = rec_exclusive_scan(ctx, ctx->cnt, ctx->inoff, n + 1, nullptr)) != REC_OK) return st;
-        hipLaunchKernelGGL(k_in_src, dim3(gridn(ne)), dim3(256), 0, s, ctx->sb.klo[cur], ne, ctx->in_src);
+        hipLaunchKernelGGL(k_in_fill, dim3(gridn(ne)), dim3(256), 0, s, S, ctx->Gidx, n, k, seed,
+                           level, it, ctx->inoff, ctx->inoff_cnt, ctx->sb.klo[0]);
+        hipLaunchKernelGGL(k_in_select, dim3(n), dim3(REC_WAVE), 0, s, n, k, ctx->inoff,
+                           ctx->sb.klo[0], ctx->in_src, ctx->capcnt);
       }
       // count distinct candidates per node, then offsets
-      hipLaunchKernelGGL(k_cand, dim3(n), dim3(BT), cand_lds, s, P, 0, (int64_t)0, n, ctx->cnt,
-                         ctx->off, (int64_t)0, ctx->cand_v, ctx->cand_slot, A);
+      hipLaunchKernelGGL(k_cand<0>, dim3(n), dim3(BT), cand_lds, s, P, (int64_t)0, n, ctx->cnt,
+                         ctx->off, (int64_t)0, ctx->cand_v, ctx->cand_gi, ctx->cand_slot, A);
       hipMemsetAsync(ctx->cnt + n, 0, sizeof(int64_t), s);
       if ((st = rec_exclusive_scan(ctx, ctx->cnt, ctx->off, n + 1, nullptr)) != REC_OK) return st;
       std::vector<int64_t> hoff(n + 1);
@@ -659,9 +722,11 @@ struct Search {
         while (a1 < n && hoff[a1 + 1] - hoff[a0] <= ctx->cand_cap) ++a1;
         if (hoff[a1] - hoff[a0] > ctx->cand_cap) { ctx->err = "candidate buffer too small"; return REC_E_NOMEM; }
         int64_t base = hoff[a0];
-        hipLaunchKernelGGL(k_cand, dim3(a1 - a0), dim3(BT), cand_lds, s, P, 1, a0, a1, ctx->cnt,
-                           ctx->off, base, ctx->cand_v, ctx->cand_slot, A);
-        if ((st = flush_scores()) != REC_OK) return st;
+        hipLaunchKernelGGL(k_cand<1>, dim3(a1 - a0), dim3(BT), cand_lds, s, P, a0, a1, ctx->cnt,
+                           ctx->off, base, ctx->cand_v, ctx->cand_gi, ctx->cand_slot, A);
+        // score the claimed candidates in place (owner bit set)
+        if ((st = rec_launch_score_owned(ctx, hoff[a1] - hoff[a0], ctx->cand_gi, ctx->cand_v, S,
+                                         ctx->cand_slot, &ctx->C)) != REC_OK) return st;
         hipLaunchKernelGGL(k_merge, dim3(a1 - a0), dim3(REC_WAVE), merge_lds, s, a0, a1, k,
                            mode == 1 ? 1 : 0, ctx->Gidx, ctx->Ggain, ctx->Gidx2, ctx->Ggain2,
                            ctx->cnt, ctx->off, base, ctx->cand_v, ctx->cand_slot, ctx->C, d_delta, 0,
