@@ -128,9 +128,13 @@ rec_status rec_score_pairs(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const 
                            double* gain_dev, double* wopt_dev);
 
 /* The m best pairs at the current state [Alg. 3 when s is a FindBest search].
- * Writes up to m pairs best first (gain desc, then min(i,j), max(i,j)) into
- * i_dev/j_dev/gain_dev (capacity m each) and their count into *n_out_host.
- * stats_host may be NULL; if given, its search fields are filled.  Synchronises. */
+ * Writes up to m pairs best first (gain desc, then min(i,j), max(i,j);
+ * kinetic: gain desc, i, j) into i_dev/j_dev/gain_dev (capacity m each) and
+ * their count into *n_out_host.  For the kinetic model FindBest runs over
+ * unordered pairs scored by max(gain(i <- j), gain(j <- i)), and the m best
+ * directed pairs are taken from both directions of the m pairs it finds.
+ * stats_host may be NULL; if given, its search fields are filled (pair_evals
+ * counts directed scores for the kinetic model).  Synchronises. */
 rec_status rec_find_best(rec_ctx* ctx, int64_t m, int32_t search, int32_t* i_dev, int32_t* j_dev,
                          double* gain_dev, int64_t* n_out_host, rec_sweep_stats* stats_host);
 
@@ -171,7 +175,8 @@ rec_status rec_get_fields(rec_ctx* ctx, double* H_dev);
 /* KNN lists of FindKNN [Alg. 4] (mode REC_SEARCH_NNDESCENT) or exact KNN
  * (REC_SEARCH_EXACT_KNN) over the node subset S (n sorted indices) at
  * FindBest level `level`: writes n*k neighbour indices and gains, best first
- * per node; *iters_host gets the NNDescent iteration count.  Synchronises. */
+ * per node; *iters_host gets the NNDescent iteration count (kinetic model:
+ * under the score max(gain(i <- j), gain(j <- i))).  Synchronises. */
 rec_status rec_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int32_t k, int32_t level,
                    int32_t mode, int32_t* nbr_dev, double* gain_dev, int32_t* iters_host);
 

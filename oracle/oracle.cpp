@@ -41,7 +41,12 @@
 //   R6 theta is refitted for every node after each sweep's W updates; its
 //      initial value is the W = 0 optimum; it is clamped to [-8, 8].
 //   R7 kinetic Ising: P(x_t | x_{t-1}) = prod_i exp(x_{i,t} h_{i,t-1}) /
-//      2cosh(h_{i,t-1}), W directed, pairs are ordered (i <- j).
+//      2cosh(h_{i,t-1}), W directed, pairs are ordered (i <- j).  FindBest
+//      [Alg. 3] needs a symmetric d: it runs over unordered pairs scored by
+//      max(gain(i <- j), gain(j <- i)) and the best m directed pairs are
+//      taken from both directions of the m unordered pairs it returns (exact
+//      when the KNN lists are exact, since at most m unordered pairs reach the
+//      m-th best directed gain).
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -382,11 +387,20 @@ bool nb_less(const Nb& a, const Nb& b) {
   return a.j < b.j;
 }
 
+// Search score of an unordered pair.  Symmetric models: the gain.  Kinetic
+// model (directed W, R14): FindBest runs over unordered pairs {i, j} scored by
+// max(gain(i <- j), gain(j <- i)); the best m directed pairs are then taken
+// from both directions of the m pairs found (see find_best_kinetic).
 struct ScoreFn {
   const Problem& P;
   double operator()(int i, int j) const {
     double g, w;
     pair_gain(P, i, j, &g, &w);
+    if (P.model == KINETIC) {
+      double g2, w2;
+      pair_gain(P, j, i, &g2, &w2);
+      g = std::max(g, g2);
+    }
     return g;
   }
 };
@@ -516,6 +530,26 @@ std::vector<Pair> exhaustive(const Problem& P, const std::vector<int>& S) {
   return all;
 }
 
+// All unordered pairs of S under the search score, best first (base case of
+// FindBest; for the symmetric models this is exhaustive()).
+std::vector<Pair> exhaustive_sym(const Problem& P, const std::vector<int>& S) {
+  if (P.model != KINETIC) return exhaustive(P, S);
+  int64_t n = S.size();
+  std::vector<std::vector<Pair>> rows(n);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t a = 0; a < n; ++a)
+    for (int64_t b = a + 1; b < n; ++b)
+      rows[a].push_back({S[a], S[b], ScoreFn{P}(S[a], S[b])});
+  std::vector<Pair> all;
+  for (auto& r : rows) all.insert(all.end(), r.begin(), r.end());
+  std::sort(all.begin(), all.end(), [](const Pair& x, const Pair& y) {
+    if (x.g != y.g) return x.g > y.g;
+    if (x.i != y.i) return x.i < y.i;
+    return x.j < y.j;
+  });
+  return all;
+}
+
 // FindBest(m, S, d) [Alg. 3] for the symmetric models, written as a loop over
 // recursion levels that accumulates D in a pool and returns its best m.
 // mode 1: exact KNN; mode 2: NNDescent.
@@ -530,7 +564,7 @@ std::vector<Pair> find_best(const Problem& P, int64_t m, int mode, uint64_t seed
     int64_t n = S.size();
     if (st && level < 64) st->level_n[level] = n;
     if (n * n <= 4 * m || n < 2) {         // base case: exhaustive over S
-      for (auto& p : exhaustive(P, S)) pool[{p.i, p.j}] = p.g;
+      for (auto& p : exhaustive_sym(P, S)) pool[{p.i, p.j}] = p.g;
       if (st) { st->evals += n * (n - 1) / 2; if (level < 64) st->level_k[level] = 0; }
       ++level;
       break;
@@ -573,9 +607,26 @@ std::vector<Pair> find_best(const Problem& P, int64_t m, int mode, uint64_t seed
   if (st) st->levels = level;
   std::vector<Pair> res;
   for (auto& kv : pool) res.push_back({kv.first.first, kv.first.second, kv.second});
-  std::sort(res.begin(), res.end(), [&](const Pair& x, const Pair& y) { return pair_less(P, x, y); });
+  // unordered pairs: (gain desc, min, max)
+  std::sort(res.begin(), res.end(), [](const Pair& x, const Pair& y) {
+    if (x.g != y.g) return x.g > y.g;
+    if (x.i != y.i) return x.i < y.i;
+    return x.j < y.j;
+  });
   if ((int64_t)res.size() > m) res.resize(m);
-  return res;
+  if (P.model != KINETIC) return res;
+  // kinetic: the best m directed pairs among both directions of the m found
+  std::vector<Pair> dir;
+  for (auto& p : res)
+    for (int d = 0; d < 2; ++d) {
+      int i = d ? p.j : p.i, j = d ? p.i : p.j;
+      double g, w;
+      pair_gain(P, i, j, &g, &w);
+      dir.push_back({i, j, g});
+    }
+  std::sort(dir.begin(), dir.end(), [&](const Pair& x, const Pair& y) { return pair_less(P, x, y); });
+  if ((int64_t)dir.size() > m) dir.resize(m);
+  return dir;
 }
 
 }  // namespace

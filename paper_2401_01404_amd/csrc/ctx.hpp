@@ -117,6 +117,9 @@ struct rec_ctx {
   double* dw;           // best_cap
   // exhaustive search chunk buffers
   int64_t ex_cap;
+  // kinetic model inside FindBest: pairs are unordered and scored by the
+  // larger of the two directed gains
+  bool sym_search = false;
   // pair-score kernel timing (instrumentation)
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;

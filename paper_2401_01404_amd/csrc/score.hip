@@ -31,6 +31,12 @@
 // with mu_k = sum (1 - u^2) u^k; the root of that quartic starts Newton, which
 // then usually confirms convergence after one full evaluation.
 //
+// Kinetic search score: FindBest needs a symmetric score, so inside it the
+// unordered pair {i, j} of the kinetic model is scored by the larger of the
+// gains of W_ij and W_ji.  One wave loads both nodes' rows once and runs the
+// two one-sided solves (u = x_j t_i against targets y_i, v = x_i t_j against
+// y_j) back to back.
+//
 // Gaussian score: closed form.  With residuals r_i = x_i + theta_i^2 m_i the
 // change of the two conditionals [App. A] is a delta - b delta^2 / 2 with
 // a = -(r_i . x_j + r_j . x_i), b = theta_i^2 |x_j|^2 + theta_j^2 |x_i|^2,
@@ -41,6 +47,9 @@
 #include "ctx.hpp"
 
 namespace {
+
+// the kinetic model's symmetrised search score (internal model tag)
+constexpr int REC_KINSYM = 3;
 
 template <class R> struct Prec;
 template <> struct Prec<float> {
@@ -104,10 +113,12 @@ __device__ __forceinline__ double lookup_w(const WTable& W, int i, int j, bool d
 // Per-pair registers of one lane.
 template <class R, int NPL>
 struct Lane {
+  static constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
   R ti[NPL];      // i side: tanh h_i (Ising / kinetic); r_i (Gaussian)
   R xi[NPL];      // i side: x_i (symmetric) or target y_i (kinetic)
   R u[NPL];       // x_j t_i (Ising / kinetic); x_j (Gaussian)
-  R v[NPL];       // x_i t_j (Ising); r_j (Gaussian)
+  R v[NPL];       // x_i t_j (Ising, kinetic search); r_j (Gaussian)
+  int xin[CH];    // kinetic search: input-side samples x_i, VEC bytes per chunk
 };
 
 // Raw j-side row of one lane, loaded ahead of its use.
@@ -115,7 +126,8 @@ template <class R, int NPL, int MODEL>
 struct JRaw {
   static constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
   int xb[CH];                                      // VEC int8 samples per chunk
-  R t[MODEL == REC_KINETIC ? 1 : NPL];             // t_j (Ising) or r_j (Gaussian)
+  int yb[MODEL == REC_KINSYM ? CH : 1];            // kinetic search: targets y_j
+  R t[MODEL == REC_KINETIC ? 1 : NPL];             // t_j (Ising, kinetic search) or r_j (Gaussian)
   float xg[MODEL == REC_GAUSS ? NPL : 1];          // x_j (Gaussian)
 };
 
@@ -154,7 +166,9 @@ __device__ __forceinline__ void fetch_j(const Fields& F, int j, JRaw<R, NPL, MOD
       ld_vec<VEC>(reinterpret_cast<const R*>(F.H) + row + o, r.t + c * VEC);
     } else {
       r.xb[c] = ld_bytes<VEC>(F.xs + row + o);
-      if constexpr (MODEL == REC_ISING) ld_vec<VEC>(reinterpret_cast<const R*>(F.T) + row + o, r.t + c * VEC);
+      if constexpr (MODEL == REC_KINSYM) r.yb[c] = ld_bytes<VEC>(F.ys + row + o);
+      if constexpr (MODEL == REC_ISING || MODEL == REC_KINSYM)
+        ld_vec<VEC>(reinterpret_cast<const R*>(F.T) + row + o, r.t + c * VEC);
     }
   }
 }
@@ -227,12 +241,44 @@ __device__ __forceinline__ double form_j(const JRaw<R, NPL, MODEL>& r, Lane<R, N
   return c * (double)s - ((double)a + (double)a2);
 }
 
+// Kinetic search: u = x_j t_i and v = x_i t_j into the lane registers;
+// returns this lane's parts of Phi_a(0) = S_a - sum u and Phi_b(0) =
+// S_b - sum v (S_a = sum x_j y_i, S_b = sum x_i y_j) and of S_a, S_b.
+template <class R, int NPL>
+__device__ __forceinline__ void form_j_sym(const JRaw<R, NPL, REC_KINSYM>& r, Lane<R, NPL>& L,
+                                           double* phi_a, double* phi_b, float* sa, float* sb) {
+  constexpr int VEC = JRaw<R, NPL, REC_KINSYM>::VEC, CH = JRaw<R, NPL, REC_KINSYM>::CH;
+  float s1 = 0.f, s2 = 0.f;
+  R a = R(0), b = R(0);
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      const int q = c * VEC + k;
+      float xj = byte_at(r.xb[c], k), yj = byte_at(r.yb[c], k), xi = byte_at(L.xin[c], k);
+      R u = (R)xj * L.ti[q];
+      R v = (R)xi * r.t[q];
+      L.u[q] = u;
+      L.v[q] = v;
+      a += u;
+      b += v;
+      s1 += xj * (float)L.xi[q];     // +-1 products: exact in float
+      s2 += xi * yj;
+    }
+  }
+  *sa = s1;
+  *sb = s2;
+  *phi_a = (double)s1 - (double)a;
+  *phi_b = (double)s2 - (double)b;
+}
+
 // Exact score of pair (i, j) for the Ising (TWO = true) or kinetic model,
-// lane registers holding u (and v); phi0 = Phi(0) (uniform); s_lane = this
-// lane's part of S.
+// with u (and v) the lane's sample terms; phi0 = Phi(0) (uniform); s_lane =
+// this lane's part of S.
 template <class R, int NPL, bool TWO>
-__device__ PairOut solve_ising(const Lane<R, NPL>& L, double phi0, float s_lane, double w0,
-                               double lambda, int64_t M, int64_t Mp, Work& wk) {
+__device__ __forceinline__ PairOut solve_ising(const R (&Lu)[NPL], const R (&Lv)[NPL], double phi0,
+                                               float s_lane, double w0, double lambda, int64_t M,
+                                               int64_t Mp, Work& wk) {
   constexpr double nsides = TWO ? 2.0 : 1.0;
   constexpr double c = TWO ? 2.0 : 1.0;
   const double npad = (double)(Mp - M);
@@ -244,8 +290,8 @@ __device__ PairOut solve_ising(const Lane<R, NPL>& L, double phi0, float s_lane,
     // the two sides are summed apart and added once, so (i,j) and (j,i) give
     // the same bits
     R A = R(0), Q = R(0), A2 = R(0), Q2 = R(0);
-    side_sums<R, NPL>(L.u, (R)tau, A, Q);
-    if constexpr (TWO) side_sums<R, NPL>(L.v, (R)tau, A2, Q2);
+    side_sums<R, NPL>(Lu, (R)tau, A, Q);
+    if constexpr (TWO) side_sums<R, NPL>(Lv, (R)tau, A2, Q2);
     double As = rec_wave_sum_dpp((double)A + (double)A2);
     double Qs = rec_wave_sum_dpp((double)Q + (double)Q2);
     double t = (double)(R)tau;
@@ -261,7 +307,7 @@ __device__ PairOut solve_ising(const Lane<R, NPL>& L, double phi0, float s_lane,
     R m0 = R(0), m1 = R(0), m2 = R(0), m3 = R(0), n0 = R(0), n1 = R(0), n2 = R(0), n3 = R(0);
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
-      R u = L.u[k];
+      R u = Lu[k];
       R q = fma(-u, u, R(1));
       m0 += q;
       R t1 = q * u;
@@ -270,7 +316,7 @@ __device__ PairOut solve_ising(const Lane<R, NPL>& L, double phi0, float s_lane,
       m2 += t2;
       m3 = fma(t2, u, m3);
       if constexpr (TWO) {
-        R v = L.v[k];
+        R v = Lv[k];
         R qv = fma(-v, v, R(1));
         n0 += qv;
         R s1 = qv * v;
@@ -334,8 +380,8 @@ __device__ PairOut solve_ising(const Lane<R, NPL>& L, double phi0, float s_lane,
     double w = w0 + d;
     o.w = s > 0 ? fmax(w, 0.0) : fmin(w, 0.0);
   }
-  double Ls = side_logs<R, NPL>(L.u, (R)tau);
-  if constexpr (TWO) Ls += side_logs<R, NPL>(L.v, (R)tau);
+  double Ls = side_logs<R, NPL>(Lu, (R)tau);
+  if constexpr (TWO) Ls += side_logs<R, NPL>(Lv, (R)tau);
   Ls = rec_wave_sum_dpp(Ls);
   ++wk.logs;
   double d = rec_atanh(tau);
@@ -379,9 +425,11 @@ __device__ __forceinline__ void load_i(const Fields& F, int i, Lane<R, NPL>& L, 
 #pragma unroll
       for (int k = 0; k < VEC; ++k) L.xi[c * VEC + k] = (R)xv[k];
     } else {
-      int w = ld_bytes<VEC>((MODEL == REC_KINETIC ? F.ys : F.xs) + (int64_t)i * F.Mp + o);
+      constexpr bool kin = MODEL == REC_KINETIC || MODEL == REC_KINSYM;
+      int w = ld_bytes<VEC>((kin ? F.ys : F.xs) + (int64_t)i * F.Mp + o);
 #pragma unroll
       for (int k = 0; k < VEC; ++k) L.xi[c * VEC + k] = (R)byte_at(w, k);
+      if constexpr (MODEL == REC_KINSYM) L.xin[c] = ld_bytes<VEC>(F.xs + (int64_t)i * F.Mp + o);
     }
   }
 }
@@ -395,8 +443,20 @@ __device__ __forceinline__ PairOut solve(const Fields& F, const Lane<R, NPL>& L,
     double vi = F.theta[i] * F.theta[i], vj = F.theta[j] * F.theta[j];
     return solve_gauss<R, NPL>(L, vi, vj, F.sq[i], F.sq[j], w0, lambda);
   } else {
-    return solve_ising<R, NPL, MODEL == REC_ISING>(L, phi0, s_lane, w0, lambda, F.M, F.Mp, wk);
+    return solve_ising<R, NPL, MODEL == REC_ISING>(L.u, L.v, phi0, s_lane, w0, lambda, F.M, F.Mp, wk);
   }
+}
+
+// Kinetic search score: the better of the directed gains of W_ij (u) and
+// W_ji (v); both count as pair scores.
+template <class R, int NPL>
+__device__ __forceinline__ PairOut solve_sym(const Fields& F, const Lane<R, NPL>& L, double phi_a,
+                                             double phi_b, float sa, float sb, double wa, double wb,
+                                             double lambda, Work& wk) {
+  wk.pairs += 2;
+  PairOut a = solve_ising<R, NPL, false>(L.u, L.u, phi_a, sa, wa, lambda, F.M, F.Mp, wk);
+  PairOut b = solve_ising<R, NPL, false>(L.v, L.v, phi_b, sb, wb, lambda, F.M, F.Mp, wk);
+  return b.gain > a.gain ? b : a;
 }
 
 __device__ __forceinline__ bool pair_ok(int i, int j, int64_t N) {
@@ -426,7 +486,7 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
   int np = (int)(p0 + ppw < P ? ppw : P - p0);
   // lanes 0..np-1 fetch the pairs of this wave and their current weights at once
   int li = -1, lj = -1;
-  double lw = 0.0;
+  double lw = 0.0, lw2 = 0.0;
   if (lane < np) {
     uint32_t sw = slot ? slot[p0 + lane] : 0u;
     if (owned && !(sw & OWNER)) {
@@ -435,7 +495,10 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
       li = I[p0 + lane];
       lj = J[p0 + lane];
       if (Smap) lj = Smap[lj];
-      if (pair_ok(li, lj, F.N)) lw = lookup_w(W, li, lj, MODEL == REC_KINETIC);
+      if (pair_ok(li, lj, F.N)) {
+        lw = lookup_w(W, li, lj, MODEL == REC_KINETIC || MODEL == REC_KINSYM);
+        if constexpr (MODEL == REC_KINSYM) lw2 = lookup_w(W, lj, li, true);
+      }
     }
   }
   Lane<R, NPL> L;
@@ -472,10 +535,21 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
       continue;
     }
     if (i != cur) { load_i<R, NPL, MODEL>(F, i, L, lane); cur = i; }
-    float s_lane;
-    double phi_l = form_j<R, NPL, MODEL>(rw, L, &s_lane);
-    double phi0 = MODEL == REC_GAUSS ? 0.0 : rec_wave_sum_dpp(phi_l);
-    PairOut r = solve<R, NPL, MODEL>(F, L, phi0, s_lane, i, j, w0, lambda, wk);
+    PairOut r;
+    if constexpr (MODEL == REC_KINSYM) {
+      double w0b = rec_uni(__shfl(lw2, q, REC_WAVE));
+      double pa, pb;
+      float sa, sb;
+      form_j_sym<R, NPL>(rw, L, &pa, &pb, &sa, &sb);
+      pa = rec_wave_sum_dpp(pa);
+      pb = rec_wave_sum_dpp(pb);
+      r = solve_sym<R, NPL>(F, L, pa, pb, sa, sb, w0, w0b, lambda, wk);
+    } else {
+      float s_lane;
+      double phi_l = form_j<R, NPL, MODEL>(rw, L, &s_lane);
+      double phi0 = MODEL == REC_GAUSS ? 0.0 : rec_wave_sum_dpp(phi_l);
+      r = solve<R, NPL, MODEL>(F, L, phi0, s_lane, i, j, w0, lambda, wk);
+    }
     double g = r.gain;
     if constexpr (sizeof(R) == 4) g = (double)(float)g;   // FP32 scores
     if (lane == 0) {
@@ -615,7 +689,9 @@ rec_status launch_score_r(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
   switch (ctx->cfg.model) {
     case REC_ISING: return launch_score_m<R, REC_ISING>(ctx, P, I, J, Smap, slot, owned, g, w, C);
     case REC_GAUSS: return launch_score_m<R, REC_GAUSS>(ctx, P, I, J, Smap, slot, owned, g, w, C);
-    case REC_KINETIC: return launch_score_m<R, REC_KINETIC>(ctx, P, I, J, Smap, slot, owned, g, w, C);
+    case REC_KINETIC:
+      if (ctx->sym_search) return launch_score_m<R, REC_KINSYM>(ctx, P, I, J, Smap, slot, owned, g, w, C);
+      return launch_score_m<R, REC_KINETIC>(ctx, P, I, J, Smap, slot, owned, g, w, C);
   }
   return REC_E_INVAL;
 }

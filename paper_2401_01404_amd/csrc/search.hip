@@ -14,6 +14,10 @@
 // claimed in an open-addressing table the first time it is met and scored
 // once; later meetings read the stored gain.
 //
+// Kinetic model: FindBest needs a symmetric score, so it runs over unordered
+// pairs scored by max(gain(i <- j), gain(j <- i)); the best m directed pairs
+// are then taken from both directions of the m unordered pairs it returns.
+//
 // FindBest level: D+ = the 2m best directed edges of G ranked by (gain desc,
 // min id, max id, source), D = their unordered pairs, S' = nodes whose every
 // out-edge lies in D, recurse on S'; the base case |S|^2 <= 4m scores all
@@ -533,6 +537,17 @@ __global__ void k_ex_append(const int32_t* I, const int32_t* J, const double* g,
   val[p] = 0;
 }
 
+// kinetic FindBest result: both directions of each unordered pair
+__global__ void k_expand_dir(const int32_t* bi, const int32_t* bj, int64_t n, int32_t* I,
+                             int32_t* J) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  I[2 * e] = bi[e];
+  J[2 * e] = bj[e];
+  I[2 * e + 1] = bj[e];
+  J[2 * e + 1] = bi[e];
+}
+
 // ---- update rounds ----
 __global__ void k_first(const int32_t* I, const int32_t* J, int64_t m, const uint8_t* done,
                         int32_t* first, int directed, int64_t* remaining) {
@@ -760,8 +775,70 @@ struct Search {
     return REC_OK;
   }
 
+  // Kinetic model: FindBest runs over unordered pairs under the score
+  // max(gain(i <- j), gain(j <- i)); this switches the score kernel and the
+  // cache keys to that view for the lifetime of the object.
+  struct SymView {
+    Search* S;
+    explicit SymView(Search* s) : S(s) {
+      if (S->ctx->cfg.model == REC_KINETIC) { S->ctx->sym_search = true; S->A.directed = 0; }
+    }
+    ~SymView() {
+      S->ctx->sym_search = false;
+      S->A.directed = S->ctx->cfg.model == REC_KINETIC;
+    }
+  };
+
+  // Kinetic model: the best m directed pairs among both directions of the nb
+  // unordered pairs in best_* (exact when those are the exact top m under
+  // the max score: at most m unordered pairs reach the m-th best directed gain).
+  rec_status directed_best(int64_t nb, int64_t m, int64_t* n_out) {
+    hipStream_t s = ctx->stream;
+    const int64_t nd = 2 * nb;
+    if (nd > ctx->cand_cap || nd > ctx->sb.cap) { ctx->err = "m exceeds capacity"; return REC_E_NOMEM; }
+    int32_t* I = ctx->ts_i;
+    int32_t* J = ctx->ts_j;
+    double* g = ctx->C.ovf;
+    if (nb > 0) {
+      hipLaunchKernelGGL(k_expand_dir, dim3(gridn(nb)), dim3(256), 0, s, ctx->best_i, ctx->best_j,
+                         nb, I, J);
+      rec_status st = rec_launch_score(ctx, nd, I, J, nullptr, g, nullptr, nullptr);
+      if (st != REC_OK) return st;
+    }
+    int64_t* d_n = ctx->counter + 9;
+    hipMemsetAsync(d_n, 0, sizeof(int64_t), s);
+    if (nd > 0)
+      hipLaunchKernelGGL(k_ex_append, dim3(gridn(nd)), dim3(256), 0, s, I, J, g, nd,
+                         -__builtin_inf(), 1, ctx->sb.khi[0], ctx->sb.klo[0], ctx->sb.val[0], d_n,
+                         ctx->sb.cap);
+    int cur = 0;
+    rec_status st = sort_records(nd, &cur);
+    if (st != REC_OK) return st;
+    int64_t keep = std::min(nd, m);
+    if (keep > ctx->best_cap) { ctx->err = "m exceeds capacity"; return REC_E_NOMEM; }
+    if (keep > 0)
+      hipLaunchKernelGGL(k_take_best, dim3(gridn(keep)), dim3(256), 0, s, ctx->sb.khi[cur],
+                         ctx->sb.klo[cur], keep, ctx->best_i, ctx->best_j, ctx->best_g);
+    *n_out = keep;
+    return check_err();
+  }
+
   // FindBest [Alg. 3] (mode 0 NNDescent, 1 exact KNN): best m pairs into best_*.
   rec_status find_best(int64_t m, int mode, int64_t* n_out, int64_t level_n[], int levels_max) {
+    if (ctx->cfg.model == REC_KINETIC) {
+      int64_t nb = 0;
+      rec_status st;
+      {
+        SymView view(this);
+        st = find_best_sym(m, mode, &nb, level_n, levels_max);
+      }
+      if (st != REC_OK) return st;
+      return directed_best(nb, m, n_out);
+    }
+    return find_best_sym(m, mode, n_out, level_n, levels_max);
+  }
+
+  rec_status find_best_sym(int64_t m, int mode, int64_t* n_out, int64_t level_n[], int levels_max) {
     hipStream_t s = ctx->stream;
     const int64_t N = ctx->cfg.N;
     clear_cache();
@@ -926,10 +1003,6 @@ rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,
   if (search == REC_SEARCH_EXHAUSTIVE) {
     r = S.exhaustive(m, n_out);
   } else {
-    if (ctx->cfg.model == REC_KINETIC) {
-      ctx->err = "FindBest over KNN lists is defined for symmetric models; use exhaustive";
-      return REC_E_INVAL;
-    }
     r = S.find_best(m, search == REC_SEARCH_EXACT_KNN ? 1 : 0, n_out, level_n, 64);
   }
   if (r != REC_OK) return r;
@@ -945,11 +1018,14 @@ rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,
 
 rec_status rec_search_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int k, int level, int mode,
                           int32_t* nbr, double* gain, int* iters) {
-  if (ctx->cfg.model == REC_KINETIC) { ctx->err = "KNN lists need a symmetric model"; return REC_E_INVAL; }
   Search S(ctx);
   S.clear_cache();
   hipMemsetAsync(ctx->counter + 2, 0, sizeof(int64_t) * 8, ctx->stream);
-  rec_status r = S.knn(S_dev, n, k, level, mode, iters);
+  rec_status r;
+  {
+    Search::SymView view(&S);   // kinetic: lists under the max of both directions
+    r = S.knn(S_dev, n, k, level, mode, iters);
+  }
   if (r != REC_OK) return r;
   hipLaunchKernelGGL(k_lists_out, dim3(gridn(n * k)), dim3(256), 0, ctx->stream, S_dev, ctx->Gidx,
                      ctx->Ggain, n * k, nbr, gain);

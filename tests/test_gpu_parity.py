@@ -204,14 +204,23 @@ def mid_state():
     return w, lam, O
 
 
-def compare_lists(nbr, g, Jo, Go, rtol):
-    """Gains per rank agree; neighbour ids agree except between near-tied gains."""
+def compare_lists(nbr, g, Jo, Go, rtol, score=None, S=None):
+    """Gains per rank agree; neighbour ids agree except between near-tied
+    gains: a different id must have, by the oracle's own score(a, b), a gain
+    within 1e-9 relative of the oracle's entry at that rank (a tie in exact
+    arithmetic that rounding order splits either way)."""
     assert close(g, Go, rtol, 1.0).all()
     mism = nbr != Jo
     for a, c in zip(*np.nonzero(mism)):
-        row = Go[a]
-        near = np.abs(row - Go[a, c]) <= 1e-9 * max(1.0, abs(Go[a, c]))
-        assert near.sum() >= 2, (a, c, nbr[a], Jo[a], Go[a])
+        ga = Go[a, c]
+        if score is not None:
+            ia = int(S[a]) if S is not None else int(a)
+            other = score(ia, int(nbr[a, c]))
+        else:
+            near = np.abs(Go[a] - ga) <= 1e-9 * max(1.0, abs(ga))
+            assert near.sum() >= 2, (a, c, nbr[a], Jo[a], Go[a])
+            continue
+        assert abs(other - ga) <= 1e-9 * max(1.0, abs(ga)), (a, c, nbr[a], Jo[a], Go[a], other)
 
 
 @pytest.mark.parametrize("subset", [False, True])
@@ -278,4 +287,93 @@ def test_nndescent_sweeps_raise_objective():
         st = C.sweep("nndescent")
         assert st["objective"] >= prev - 1e-6 * abs(prev), (s, st, prev)
         assert st["n_best"] == C.m
+        prev = st["objective"]
+
+
+# -------------------------------------------------------------- kinetic --
+
+@pytest.fixture(scope="module")
+def kin_state():
+    """N=200 kinetic Ising problem at a W != 0 state made by oracle sweeps."""
+    w = synth.kinetic_er(200, 300, 4.0, 0.3, seed=5)
+    lam = oracle.default_lambda(w.X, "kinetic")
+    O = oracle.Oracle(w.X, "kinetic", lam)
+    O.gcd_sweep(400, "exhaustive")
+    return w, lam, O
+
+
+def kin_ctx(kin_state, prec="fp64"):
+    w, lam, O = kin_state
+    ei, ej, wv, th = O.get_model()
+    C = ctx_for(w, lam, prec)
+    C.set_model(ei, ej, wv, th)
+    return C
+
+
+@pytest.mark.parametrize("subset", [False, True])
+def test_kinetic_knn_lists_match_oracle(kin_state, subset):
+    """KNN lists under the symmetrised kinetic score max(gain(i<-j), gain(j<-i))."""
+    w, lam, O = kin_state
+    C = kin_ctx(kin_state)
+    S = np.arange(0, w.N, 3 if subset else 1, dtype=np.int32)
+    k = 6
+
+    def sym_score(i, j):
+        g, _ = O.score_pairs(np.array([i, j], np.int32), np.array([j, i], np.int32))
+        return max(g)
+
+    for mode, omode in [("exact_knn", "exact"), ("nndescent", "nndescent")]:
+        Jo, Go, it_o = O.knn(S, k, omode, seed=0, level=1 if subset else 0)
+        nbr, g, it = C.knn(S, k, 1 if subset else 0, mode)
+        compare_lists(nbr.cpu().numpy(), g.cpu().numpy(), Jo, Go, 1e-10, sym_score, S)
+        if mode == "nndescent":
+            assert it == it_o
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_kinetic_findbest_exact_knn_equals_exhaustive(kin_state, prec):
+    """Directed top m from FindBest with exact KNN equals the exhaustive search
+    over all ordered pairs, and both match the oracle."""
+    w, lam, O = kin_state
+    C = kin_ctx(kin_state, prec)
+    for m in [50, 200, 800]:
+        I, J, G, _ = C.find_best(m, "exhaustive")
+        I2, J2, G2, st = C.find_best(m, "exact_knn")
+        assert np.array_equal(I.cpu().numpy(), I2.cpu().numpy())
+        assert np.array_equal(J.cpu().numpy(), J2.cpu().numpy())
+        assert np.array_equal(G.cpu().numpy(), G2.cpu().numpy())
+        Io, Jo, Go, _ = O.find_best(m, "exhaustive")
+        assert close(G.cpu().numpy(), Go, RTOL[prec], w.M).all()
+        if prec == "fp64":
+            diff = set(zip(Io.tolist(), Jo.tolist())) ^ set(zip(I.cpu().numpy().tolist(), J.cpu().numpy().tolist()))
+            assert len(diff) <= 2
+
+
+def test_kinetic_findbest_nndescent_matches_oracle(kin_state):
+    w, lam, O = kin_state
+    C = kin_ctx(kin_state)
+    m = 2 * w.N
+    Io, Jo, Go, sto = O.find_best(m, "nndescent", seed=0)
+    I, J, G, st = C.find_best(m, "nndescent")
+    assert st["levels"] == sto["levels"]
+    assert close(G.cpu().numpy(), Go, 1e-10, w.M).all()
+    diff = set(zip(Io.tolist(), Jo.tolist())) ^ set(zip(I.cpu().numpy().tolist(), J.cpu().numpy().tolist()))
+    assert len(diff) <= 2
+
+
+def test_kinetic_sweeps_track_oracle():
+    w = synth.kinetic_er(150, 300, 4.0, 0.3, seed=6)
+    lam = oracle.default_lambda(w.X, "kinetic")
+    O = oracle.Oracle(w.X, "kinetic", lam)
+    C = ctx_for(w, lam, "fp64", kappa=1.0)
+    for s in range(3):
+        d_or, obj_or = O.gcd_sweep(w.N, "exact_knn")
+        st = C.sweep("exact_knn")
+        assert abs(st["objective"] - obj_or) <= 1e-9 * abs(obj_or), (s, st, obj_or)
+        assert abs(st["delta"] - d_or) <= 1e-8 * max(1.0, d_or)
+    C2 = ctx_for(w, lam, "fp32")
+    prev = C2.objective()
+    for s in range(3):
+        st = C2.sweep("nndescent")
+        assert st["objective"] >= prev - 1e-6 * abs(prev), (s, st, prev)
         prev = st["objective"]

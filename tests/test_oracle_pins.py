@@ -440,6 +440,26 @@ def test_findbest_exact_knn_equals_exhaustive():
             assert b <= a // 2
 
 
+def test_kinetic_findbest_exact_knn_equals_directed_exhaustive():
+    """Kinetic model (directed W): FindBest over unordered pairs under the
+    score max(gain(i <- j), gain(j <- i)) with exact KNN, then the best m of
+    both directions, equals the brute-force top m over all N(N-1) ordered
+    pairs (gain desc, i, j), at W = 0 and at a W != 0 state."""
+    w = synth.kinetic_er(80, 200, 4.0, 0.3, seed=2)
+    lam = oracle.default_lambda(w.X, "kinetic")
+    O = oracle.Oracle(w.X, "kinetic", lam)
+    N = w.N
+    for state in range(2):
+        allI, allJ = np.nonzero(~np.eye(N, dtype=bool))
+        g, _ = O.score_pairs(allI.astype(np.int32), allJ.astype(np.int32))
+        order = np.lexsort((allJ, allI, -g))
+        for m in [20, 80, 320]:
+            I2, J2, G2, st = O.find_best(m, "exact_knn")
+            assert np.array_equal(I2, allI[order[:m]]) and np.array_equal(J2, allJ[order[:m]])
+            assert np.array_equal(G2, g[order[:m]])
+        O.gcd_sweep(2 * N, "exhaustive")
+
+
 def test_exhaustive_topm_is_sorted_and_complete():
     w = synth.ising_er(40, 100, 3.0, 0.4, 0.1, seed=4)
     O = oracle.Oracle(w.X, "ising", 3.0)
