@@ -11,8 +11,13 @@ by FindBest during the timed sweeps / their wall time (kinetic model: directed
 scores, two per unordered pair of the symmetrised search).
 
 The pair-score kernel is timed live with HIP events on the library's stream
-for the roofline entry; the CPU oracle is timed on a bounded random sample of
-pairs of the same workload for the cpu_baseline entry.
+for the roofline entry.  Its binding roof is HBM: per pair it streams the j
+side's rows (sign words and fp16 residuals for the screen, the tanh row when
+the screen does not settle the pair) and does a few flops per byte.  The
+kernels count the algorithmic bytes they need (indices, scores, the rows
+fetched, at M samples) and achieved = those bytes / kernel time.  The CPU
+oracle is timed on a bounded random sample of pairs of the same workload for
+the cpu_baseline entry.
 """
 import argparse
 import json
@@ -43,6 +48,7 @@ FLOPS_LOAD, FLOPS_MOMENT, FLOPS_EVAL, FLOPS_LOG = 5, 8, 8, 3
 # 2.4 GHz x 2 flops per FMA = 78.6 TFLOP/s (packed FP32 is disabled in this
 # build, so the 157.3 TFLOP/s packed figure is not reachable).
 PEAK_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
 
 
 def cpu_baseline(w, lam, seconds):
@@ -72,6 +78,19 @@ def cpu_baseline(w, lam, seconds):
                       f"{dt:.1f} s on {cores} threads"}
 
 
+def copy_probe(mib):
+    """Plain copies of a known size: each reads and writes mib MiB once."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "copies": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,11 +101,17 @@ def main():
     ap.add_argument("--search", default="nndescent", choices=["nndescent", "exhaustive", "exact_knn"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (5 times): the "
+                         "reference kernel for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "sharding of this path is described in the design notes, not built.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
 
     import numpy as np
     import torch
@@ -121,7 +146,9 @@ def main():
     sides = 2 if w.model == "ising" else 1
     flops = sides * w.M * (FLOPS_LOAD * work["pairs"] + FLOPS_MOMENT * work["moment_passes"]
                            + FLOPS_EVAL * work["evals"] + FLOPS_LOG * work["log_passes"])
-    achieved = flops / (score_ms / 1e3) / 1e12 if score_ms > 0 else None
+    tflops = flops / (score_ms / 1e3) / 1e12 if score_ms > 0 else None
+    nbytes = work["bytes"]
+    achieved = nbytes / (score_ms / 1e3) / 1e9 if score_ms > 0 else None
     line = {
         "metric": "pair-score evals/s (exact FindBest scores per second of GCD sweep wall time)",
         "value": value,
@@ -138,11 +165,16 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "N": w.N, "M": w.M,
                    "kappa": kappa, "m": ctx.m, "lambda": lam, "search": args.search,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": (achieved / PEAK_TFLOPS) if achieved else None, "traffic": None,
-                     "kernel": "k_score (pair score)",
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
+                     "traffic": None,
+                     "kernel": "k_score_scr / k_score (pair score)",
                      "kernel_ms_avg": score_ms / max(launches, 1), "launches": launches,
-                     "pairs_scored": scored, "flops_per_pair": flops / max(scored, 1),
+                     "bytes_per_launch": nbytes / max(launches, 1),
+                     "pairs_scored": scored, "bytes_per_pair": nbytes / max(scored, 1),
+                     "alu_view": {"achieved_tflops": tflops, "peak_tflops": PEAK_TFLOPS,
+                                  "frac": (tflops / PEAK_TFLOPS) if tflops else None,
+                                  "flops_per_pair": flops / max(scored, 1)},
                      "work": work},
         "details": {
             "sweep_ms": [round(s["t_search_ms"] + s["t_update_ms"] + s["t_theta_ms"], 3) for s in stats],

@@ -184,9 +184,13 @@ rec_status rec_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int32_t k, int
  * pair-score kernel is bracketed by HIP events on the context's stream.
  * rec_kernel_time returns, for the launches since the last call (or since
  * timing was switched on), the summed kernel time in ms, the number of
- * launches and four work counters: pairs scored, moment passes, full Newton
- * evaluations and log passes (each pass is one sweep over the M samples of
- * the pair's one or two sides).  Synchronises; resets the sums. */
+ * launches and eight work counters (work_host: 8 int64, may be NULL): pairs
+ * scored, moment passes, full Newton evaluations, log passes (each pass is
+ * one sweep over the M samples of the pair's one or two sides), pair sides
+ * settled by the fp16 residual screen, j-side rows fetched, i-side row
+ * loads, and the algorithmic bytes the kernels read and write (indices,
+ * scores and the rows they need, at M samples).  Synchronises; resets the
+ * sums. */
 rec_status rec_set_timing(rec_ctx* ctx, int32_t on);
 rec_status rec_kernel_time(rec_ctx* ctx, double* score_ms_host, int64_t* launches_host,
                            int64_t* work_host);

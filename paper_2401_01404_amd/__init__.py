@@ -266,11 +266,13 @@ class Context:
         self._check(lib().rec_set_timing(self.h, 1 if on else 0), self.h)
 
     def kernel_time(self):
-        """Pair-score kernel time and work since the last call:
-        (ms, launches, {"pairs", "moment_passes", "evals", "log_passes"})."""
+        """Pair-score kernel time and work since the last call: (ms, launches,
+        {"pairs", "moment_passes", "evals", "log_passes", "screened",
+        "t_fetches", "i_loads", "bytes"})."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
-        w = (ctypes.c_int64 * 4)()
+        w = (ctypes.c_int64 * 8)()
         self._check(lib().rec_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n), w), self.h)
         return ms.value, n.value, {"pairs": w[0], "moment_passes": w[1], "evals": w[2],
-                                   "log_passes": w[3]}
+                                   "log_passes": w[3], "screened": w[4], "t_fetches": w[5],
+                                   "i_loads": w[6], "bytes": w[7]}

@@ -90,6 +90,14 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   F.xf = c->model == REC_GAUSS ? a.take<float>(nsz) : nullptr;
   F.H = a.take<char>(nsz * rs);
   F.T = c->model == REC_GAUSS ? nullptr : (void*)a.take<char>(nsz * rs);
+  if (c->model != REC_GAUSS) {
+    F.xq = a.take<uint32_t>(N * 64);
+    F.yq = c->model == REC_KINETIC ? a.take<uint32_t>(N * 64) : F.xq;
+    F.rh = a.take<uint16_t>(nsz);
+  } else {
+    F.xq = F.yq = nullptr;
+    F.rh = nullptr;
+  }
   F.sq = a.take<double>(N);
   F.theta = a.take<double>(N);
   x->W.keys = a.take<uint64_t>(z.wcap);
@@ -103,7 +111,7 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   x->wj = a.take<int32_t>(z.max_nnz);
   x->wv = a.take<double>(z.max_nnz);
   x->counter = a.take<int64_t>(16);
-  x->work = a.take<int64_t>(4 * REC_WORK_COPIES);
+  x->work = a.take<int64_t>(REC_WORK_N * REC_WORK_COPIES);
   x->dscratch = a.take<double>(std::max<int64_t>(N, 1024));
   x->dresult = a.take<double>(16);
   x->err_flag = a.take<int32_t>(4);
@@ -217,13 +225,13 @@ rec_status clear_err(rec_ctx* ctx) {
 }  // namespace
 
 // Sum of the work-counter copies (synchronises).
-rec_status rec_work_read(rec_ctx* ctx, int64_t out[4]) {
-  std::vector<int64_t> h(4 * REC_WORK_COPIES);
+rec_status rec_work_read(rec_ctx* ctx, int64_t out[8]) {
+  std::vector<int64_t> h(REC_WORK_N * REC_WORK_COPIES);
   REC_HIP(hipMemcpyAsync(h.data(), ctx->work, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
   REC_HIP(hipStreamSynchronize(ctx->stream));
-  for (int q = 0; q < 4; ++q) out[q] = 0;
+  for (int q = 0; q < REC_WORK_N; ++q) out[q] = 0;
   for (int c = 0; c < REC_WORK_COPIES; ++c)
-    for (int q = 0; q < 4; ++q) out[q] += h[4 * c + q];
+    for (int q = 0; q < REC_WORK_N; ++q) out[q] += h[REC_WORK_N * c + q];
   return REC_OK;
 }
 
@@ -297,10 +305,16 @@ rec_status rec_create(const rec_config* cfg, const void* X_dev, void* ws_dev, si
   F.Mp = z.Mp;
   F.npl = z.npl;
   F.model = cfg->model;
+  // The screen compares sum_m x_m rh_m with lambda: rounding y - tanh h
+  // (|.| < 2) to fp16 moves each term by at most 2^-10 (one fp16 ulp at the
+  // top binade, covering double rounding through float) plus 2^-24 below the
+  // normal range, so |sum| moves by at most M (2^-9 + 2^-24); 0.01 covers the
+  // float partial sums of both the screen and the exact path.
+  F.scr = cfg->lambda - ((double)cfg->M * (std::ldexp(1.0, -9) + std::ldexp(1.0, -24)) + 0.01);
   auto bad = [&](rec_status st) { delete ctx; return st; };
   if (hipMemsetAsync(ctx->err_flag, 0, 16, ctx->stream) != hipSuccess) return bad(REC_E_HIP);
   if (hipMemsetAsync(ctx->counter, 0, 16 * 8, ctx->stream) != hipSuccess) return bad(REC_E_HIP);
-  if (hipMemsetAsync(ctx->work, 0, 4 * 8 * REC_WORK_COPIES, ctx->stream) != hipSuccess) return bad(REC_E_HIP);
+  if (hipMemsetAsync(ctx->work, 0, REC_WORK_N * 8 * REC_WORK_COPIES, ctx->stream) != hipSuccess) return bad(REC_E_HIP);
   rec_wtable_clear(ctx);
   if (rec_load_data(ctx, X_dev, cfg->ldx) != REC_OK) return bad(REC_E_HIP);
   hipLaunchKernelGGL(k_fill_f64, dim3((cfg->N + 255) / 256), dim3(256), 0, ctx->stream, F.theta,
@@ -512,13 +526,13 @@ rec_status rec_kernel_time(rec_ctx* ctx, double* score_ms_host, int64_t* launche
                            int64_t* work_host) {
   if (!ctx) return REC_E_INVAL;
   REC_TRY(rec_timing_resolve(ctx));
-  int64_t w[4];
+  int64_t w[REC_WORK_N];
   REC_TRY(rec_work_read(ctx, w));
   if (score_ms_host) *score_ms_host = ctx->score_ms;
   if (launches_host) *launches_host = ctx->score_launches;
   if (work_host)
-    for (int q = 0; q < 4; ++q) work_host[q] = w[q] - ctx->work_base[q];
-  for (int q = 0; q < 4; ++q) ctx->work_base[q] = w[q];
+    for (int q = 0; q < REC_WORK_N; ++q) work_host[q] = w[q] - ctx->work_base[q];
+  for (int q = 0; q < REC_WORK_N; ++q) ctx->work_base[q] = w[q];
   ctx->score_ms = 0.0;
   ctx->score_launches = ctx->score_pairs = 0;
   return REC_OK;

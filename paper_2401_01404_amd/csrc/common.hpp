@@ -193,9 +193,21 @@ __device__ __forceinline__ int64_t rec_block_append(int64_t* cursor, bool pred, 
   return pos;
 }
 
-// Work counters are kept in REC_WORK_COPIES copies of 4 so that concurrent
-// waves do not serialise on one address; readers sum the copies.
+// Work counters of the pair-score kernel (REC_WORK_N per copy) are kept in
+// REC_WORK_COPIES copies so that concurrent waves do not serialise on one
+// address; readers sum the copies.  Order: pairs scored, moment passes, full
+// evaluations, log passes, sides decided by the residual screen, j-side
+// tanh rows fetched, i-side row loads, reserved.
 constexpr int REC_WORK_COPIES = 256;
+constexpr int REC_WORK_N = 8;
+
+// fp16 bits of v (round to nearest even) and back
+__device__ __forceinline__ uint16_t rec_f16_bits(float v) {
+  return __builtin_bit_cast(uint16_t, (_Float16)v);
+}
+__device__ __forceinline__ float rec_f16_val(uint32_t bits16) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
+}
 
 // numerics shared by the kernels (double)
 __device__ __forceinline__ double rec_lcosh_tau(double tau) {   // log cosh(atanh tau)

@@ -19,6 +19,14 @@ struct Fields {
   void* T;              // N x Mp tanh(H) (Ising/kinetic), real
   const double* sq;     // Gaussian: ||x_i||^2
   double* theta;        // N
+  // Ising / kinetic screen data.  xq, yq: N x 64 lane words, bit c*VEC + k of
+  // lane l is sample c*64*VEC + l*VEC + k of xs (yq: ys) being +1 (padding
+  // reads as -1 and is cancelled by zeros on the other side); rh: N x Mp
+  // fp16 residuals y - tanh h (padding 0).
+  const uint32_t* xq;
+  const uint32_t* yq;
+  uint16_t* rh;
+  double scr;           // screen threshold: lambda minus the fp16 error bound
   int64_t N, M, Mp;     // valid samples M, padded row length Mp = 64 * npl
   int npl;              // samples per lane
   int model;            // rec_model
@@ -86,7 +94,7 @@ struct rec_ctx {
   // scratch for compaction of the W table
   int32_t* wi; int32_t* wj; double* wv;   // max_nnz each
   int64_t* counter;     // small device counters [16]
-  int64_t* work;        // pair-score work counters [4]: pairs, moment passes, evaluations, log passes
+  int64_t* work;        // pair-score work counters, REC_WORK_N x REC_WORK_COPIES
   double* dscratch;     // per-block partial sums (N)
   double* dresult;      // small double results [16]
   int32_t* err_flag;    // device error flag
@@ -126,14 +134,14 @@ struct rec_ctx {
   size_t ev_used = 0;
   double score_ms = 0.0;
   int64_t score_launches = 0, score_pairs = 0;
-  int64_t work_base[4] = {0, 0, 0, 0};   // work counters when timing was switched on
+  int64_t work_base[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // work counters when timing was switched on
   ~rec_ctx() {
     for (auto& e : ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   }
 };
 
 rec_status rec_timing_resolve(rec_ctx* ctx);
-rec_status rec_work_read(rec_ctx* ctx, int64_t out[4]);
+rec_status rec_work_read(rec_ctx* ctx, int64_t out[8]);
 
 // ---- launch helpers (implemented in the .hip files) ----
 #define REC_HIP(call)                                                          \

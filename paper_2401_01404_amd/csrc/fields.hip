@@ -70,6 +70,22 @@ __global__ __launch_bounds__(FT) void k_load_int8(const int8_t* __restrict__ X, 
   }
 }
 
+// Lane words of the screen: bit c*VEC + k of lane l = sample
+// c*64*VEC + l*VEC + k is +1 (one wave per node).
+__global__ __launch_bounds__(REC_WAVE) void k_pack_bits(const int8_t* __restrict__ x, int64_t Mp,
+                                                        int npl, uint32_t* __restrict__ q) {
+  const int64_t i = blockIdx.x;
+  const int l = threadIdx.x;
+  const int vec = npl < 4 ? npl : 4, ch = npl / vec;
+  uint32_t w = 0;
+  for (int c = 0; c < ch; ++c)
+    for (int k = 0; k < vec; ++k) {
+      int64_t s = (int64_t)c * REC_WAVE * vec + (int64_t)l * vec + k;
+      if (x[i * Mp + s] > 0) w |= 1u << (c * vec + k);
+    }
+  q[i * REC_WAVE + l] = w;
+}
+
 __global__ __launch_bounds__(FT) void k_load_f32(const float* __restrict__ X, int64_t ldx, int64_t M,
                                                  int64_t Mp, float* __restrict__ xf,
                                                  double* __restrict__ sq, int32_t* err) {
@@ -112,9 +128,12 @@ __global__ __launch_bounds__(FT) void k_fields(Fields F, const int64_t* __restri
     if (MODEL == REC_GAUSS) {
       H[idx] = s < F.M ? (R)((double)F.xf[idx] + th * th * acc) : R(0);
     } else {
+      const int8_t* Y = MODEL == REC_KINETIC ? F.ys : F.xs;
       R h = s < F.M ? (R)(th + acc) : R(0);
+      R t = s < F.M ? tanh_<R>(h) : R(0);
       H[idx] = h;
-      T[idx] = s < F.M ? tanh_<R>(h) : R(0);
+      T[idx] = t;
+      F.rh[idx] = rec_f16_bits((float)((R)Y[idx] - t));
     }
   }
 }
@@ -193,8 +212,10 @@ __global__ __launch_bounds__(FT) void k_theta(Fields F) {
     for (int64_t s = threadIdx.x; s < F.M; s += FT) {
       double mm = (double)H[i * F.Mp + s] - th0;
       R h = (R)(th + mm);
+      R t = tanh_<R>(h);
       H[i * F.Mp + s] = h;
-      T[i * F.Mp + s] = tanh_<R>(h);
+      T[i * F.Mp + s] = t;
+      F.rh[i * F.Mp + s] = rec_f16_bits((float)((R)Y[i * F.Mp + s] - t));
     }
   }
   if (threadIdx.x == 0) F.theta[i] = th;
@@ -377,6 +398,11 @@ rec_status rec_load_data(rec_ctx* ctx, const void* X, int64_t ldx) {
     hipLaunchKernelGGL(k_load_int8, dim3(N), dim3(FT), 0, ctx->stream, (const int8_t*)X, ldx,
                        ctx->F.M, ctx->F.Mp, ctx->cfg.model == REC_KINETIC ? 1 : 0,
                        (int8_t*)ctx->F.xs, (int8_t*)ctx->F.ys, ctx->err_flag);
+    hipLaunchKernelGGL(k_pack_bits, dim3(N), dim3(REC_WAVE), 0, ctx->stream, ctx->F.xs, ctx->F.Mp,
+                       ctx->F.npl, const_cast<uint32_t*>(ctx->F.xq));
+    if (ctx->cfg.model == REC_KINETIC)
+      hipLaunchKernelGGL(k_pack_bits, dim3(N), dim3(REC_WAVE), 0, ctx->stream, ctx->F.ys, ctx->F.Mp,
+                         ctx->F.npl, const_cast<uint32_t*>(ctx->F.yq));
   }
   REC_HIP(hipGetLastError());
   return REC_OK;

@@ -126,8 +126,7 @@ template <class R, int NPL, int MODEL>
 struct JRaw {
   static constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
   int xb[CH];                                      // VEC int8 samples per chunk
-  int yb[MODEL == REC_KINSYM ? CH : 1];            // kinetic search: targets y_j
-  R t[MODEL == REC_KINETIC ? 1 : NPL];             // t_j (Ising, kinetic search) or r_j (Gaussian)
+  R t[MODEL == REC_KINETIC ? 1 : NPL];             // t_j (Ising) or r_j (Gaussian)
   float xg[MODEL == REC_GAUSS ? NPL : 1];          // x_j (Gaussian)
 };
 
@@ -166,9 +165,7 @@ __device__ __forceinline__ void fetch_j(const Fields& F, int j, JRaw<R, NPL, MOD
       ld_vec<VEC>(reinterpret_cast<const R*>(F.H) + row + o, r.t + c * VEC);
     } else {
       r.xb[c] = ld_bytes<VEC>(F.xs + row + o);
-      if constexpr (MODEL == REC_KINSYM) r.yb[c] = ld_bytes<VEC>(F.ys + row + o);
-      if constexpr (MODEL == REC_ISING || MODEL == REC_KINSYM)
-        ld_vec<VEC>(reinterpret_cast<const R*>(F.T) + row + o, r.t + c * VEC);
+      if constexpr (MODEL == REC_ISING) ld_vec<VEC>(reinterpret_cast<const R*>(F.T) + row + o, r.t + c * VEC);
     }
   }
 }
@@ -203,8 +200,22 @@ __device__ __forceinline__ double side_logs(const R* a, R tau) {
 struct PairOut { double gain, w, w0; };
 
 // Work counters of one wave: pairs, moment passes, full Newton evaluations,
-// log passes.
-struct Work { int64_t pairs = 0, moments = 0, evals = 0, logs = 0; };
+// log passes, sides decided by the residual screen, j-side tanh rows fetched,
+// i-side row loads, and the algorithmic bytes read and written (the data the
+// method needs per unit, not cache-line traffic): per pair its indices, cache
+// slot and score; per j-side read the bytes of the rows it fetches; per i
+// row load that row's data, all at M samples.
+struct Work {
+  int64_t pairs = 0, moments = 0, evals = 0, logs = 0, screened = 0, tfetch = 0, iloads = 0;
+  int64_t bytes = 0;
+  __device__ void flush(int64_t* work, int64_t wave) const {
+    int64_t* wc = work + REC_WORK_N * (wave & (REC_WORK_COPIES - 1));
+    const int64_t v[8] = {pairs, moments, evals, logs, screened, tfetch, iloads, bytes};
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (v[q]) atomicAdd((unsigned long long*)&wc[q], (unsigned long long)v[q]);
+  }
+};
 
 // Ising / kinetic: u (and v) into the lane registers; returns this lane's part
 // of Phi(0) = c S - sum u (- sum v) and its part of S in *s_lane.
@@ -239,37 +250,6 @@ __device__ __forceinline__ double form_j(const JRaw<R, NPL, MODEL>& r, Lane<R, N
   *s_lane = s;
   constexpr double c = MODEL == REC_ISING ? 2.0 : 1.0;
   return c * (double)s - ((double)a + (double)a2);
-}
-
-// Kinetic search: u = x_j t_i and v = x_i t_j into the lane registers;
-// returns this lane's parts of Phi_a(0) = S_a - sum u and Phi_b(0) =
-// S_b - sum v (S_a = sum x_j y_i, S_b = sum x_i y_j) and of S_a, S_b.
-template <class R, int NPL>
-__device__ __forceinline__ void form_j_sym(const JRaw<R, NPL, REC_KINSYM>& r, Lane<R, NPL>& L,
-                                           double* phi_a, double* phi_b, float* sa, float* sb) {
-  constexpr int VEC = JRaw<R, NPL, REC_KINSYM>::VEC, CH = JRaw<R, NPL, REC_KINSYM>::CH;
-  float s1 = 0.f, s2 = 0.f;
-  R a = R(0), b = R(0);
-#pragma unroll
-  for (int c = 0; c < CH; ++c) {
-#pragma unroll
-    for (int k = 0; k < VEC; ++k) {
-      const int q = c * VEC + k;
-      float xj = byte_at(r.xb[c], k), yj = byte_at(r.yb[c], k), xi = byte_at(L.xin[c], k);
-      R u = (R)xj * L.ti[q];
-      R v = (R)xi * r.t[q];
-      L.u[q] = u;
-      L.v[q] = v;
-      a += u;
-      b += v;
-      s1 += xj * (float)L.xi[q];     // +-1 products: exact in float
-      s2 += xi * yj;
-    }
-  }
-  *sa = s1;
-  *sb = s2;
-  *phi_a = (double)s1 - (double)a;
-  *phi_b = (double)s2 - (double)b;
 }
 
 // Exact score of pair (i, j) for the Ising (TWO = true) or kinetic model,
@@ -447,18 +427,6 @@ __device__ __forceinline__ PairOut solve(const Fields& F, const Lane<R, NPL>& L,
   }
 }
 
-// Kinetic search score: the better of the directed gains of W_ij (u) and
-// W_ji (v); both count as pair scores.
-template <class R, int NPL>
-__device__ __forceinline__ PairOut solve_sym(const Fields& F, const Lane<R, NPL>& L, double phi_a,
-                                             double phi_b, float sa, float sb, double wa, double wb,
-                                             double lambda, Work& wk) {
-  wk.pairs += 2;
-  PairOut a = solve_ising<R, NPL, false>(L.u, L.u, phi_a, sa, wa, lambda, F.M, F.Mp, wk);
-  PairOut b = solve_ising<R, NPL, false>(L.v, L.v, phi_b, sb, wb, lambda, F.M, F.Mp, wk);
-  return b.gain > a.gain ? b : a;
-}
-
 __device__ __forceinline__ bool pair_ok(int i, int j, int64_t N) {
   return i >= 0 && j >= 0 && i < N && j < N && i != j;
 }
@@ -486,7 +454,7 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
   int np = (int)(p0 + ppw < P ? ppw : P - p0);
   // lanes 0..np-1 fetch the pairs of this wave and their current weights at once
   int li = -1, lj = -1;
-  double lw = 0.0, lw2 = 0.0;
+  double lw = 0.0;
   if (lane < np) {
     uint32_t sw = slot ? slot[p0 + lane] : 0u;
     if (owned && !(sw & OWNER)) {
@@ -495,10 +463,7 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
       li = I[p0 + lane];
       lj = J[p0 + lane];
       if (Smap) lj = Smap[lj];
-      if (pair_ok(li, lj, F.N)) {
-        lw = lookup_w(W, li, lj, MODEL == REC_KINETIC || MODEL == REC_KINSYM);
-        if constexpr (MODEL == REC_KINSYM) lw2 = lookup_w(W, lj, li, true);
-      }
+      if (pair_ok(li, lj, F.N)) lw = lookup_w(W, li, lj, MODEL == REC_KINETIC);
     }
   }
   Lane<R, NPL> L;
@@ -534,21 +499,244 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
       }
       continue;
     }
-    if (i != cur) { load_i<R, NPL, MODEL>(F, i, L, lane); cur = i; }
-    PairOut r;
-    if constexpr (MODEL == REC_KINSYM) {
-      double w0b = rec_uni(__shfl(lw2, q, REC_WAVE));
-      double pa, pb;
-      float sa, sb;
-      form_j_sym<R, NPL>(rw, L, &pa, &pb, &sa, &sb);
-      pa = rec_wave_sum_dpp(pa);
-      pb = rec_wave_sum_dpp(pb);
-      r = solve_sym<R, NPL>(F, L, pa, pb, sa, sb, w0, w0b, lambda, wk);
+    if (i != cur) { load_i<R, NPL, MODEL>(F, i, L, lane); cur = i; ++wk.iloads; }
+    ++wk.tfetch;
+    float s_lane;
+    double phi_l = form_j<R, NPL, MODEL>(rw, L, &s_lane);
+    double phi0 = MODEL == REC_GAUSS ? 0.0 : rec_wave_sum_dpp(phi_l);
+    PairOut r = solve<R, NPL, MODEL>(F, L, phi0, s_lane, i, j, w0, lambda, wk);
+    double g = r.gain;
+    if constexpr (sizeof(R) == 4) g = (double)(float)g;   // FP32 scores
+    if (lane == 0) {
+      *dst = g;
+      if (w_out) w_out[p] = r.w;
+    }
+  }
+  if (lane == 0 && work) {
+    const int64_t M = F.M, rs = sizeof(R);
+    const int64_t jb = MODEL == REC_ISING ? M + rs * M : MODEL == REC_KINETIC ? M : 4 * M + rs * M;
+    const int64_t ib = MODEL == REC_GAUSS ? rs * M + 4 * M : rs * M + M;
+    wk.bytes = wk.tfetch * (16 + (slot ? 4 : 0) + jb) + wk.iloads * ib;
+    wk.flush(work, wave);
+  }
+}
+
+// ------------------------------------------------------------ screened --
+// Ising and the kinetic search score, with the j side read in two steps.
+//
+// At w0 = 0 the pair's gain is zero exactly when |Phi(0)| <= lambda (the L1
+// kink test).  Phi(0) splits into a part that needs only the signs of x_j
+// and the resident i row, and a part sum_m x_i (y_j - t_j) that needs the j
+// row's tanh values.  The first read fetches the sign words of x_j (and of
+// y_j for the kinetic search) and fp16 copies of y_j - t_j (2.1 bytes per
+// sample instead of 5-6); their error moves the second part by at most the
+// bound folded into F.scr, so |screen| <= F.scr proves |Phi(0)| <= lambda
+// and the side's gain is exactly zero, the value the full evaluation gives.
+// Otherwise the fp32/fp64 tanh row of j is fetched and the side is scored
+// exactly as by k_score: the result is the same bits either way.
+template <int NPL, bool SYM>
+struct JScr {
+  static constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC, HW = NPL >= 2 ? NPL / 2 : 1;
+  uint32_t xw;             // signs of x_j (bit q = lane register q)
+  uint32_t yw;             // kinetic search: signs of the targets y_j
+  uint32_t hw[HW];         // fp16 y_j - t_j, two per word (register q in word q / 2)
+};
+
+template <int NPL, bool SYM>
+__device__ __forceinline__ void fetch_scr(const Fields& F, int j, JScr<NPL, SYM>& r, int lane) {
+  constexpr int VEC = JScr<NPL, SYM>::VEC, CH = JScr<NPL, SYM>::CH;
+  r.xw = F.xq[(int64_t)j * REC_WAVE + lane];
+  if constexpr (SYM) r.yw = F.yq[(int64_t)j * REC_WAVE + lane];
+  const uint16_t* hr = F.rh + (int64_t)j * F.Mp;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int64_t o = smp<VEC>(c, lane);
+    if constexpr (VEC == 4) {
+      uint2 v = *reinterpret_cast<const uint2*>(hr + o);
+      r.hw[2 * c] = v.x;
+      r.hw[2 * c + 1] = v.y;
+    } else if constexpr (VEC == 2) {
+      r.hw[c] = *reinterpret_cast<const uint32_t*>(hr + o);
     } else {
-      float s_lane;
-      double phi_l = form_j<R, NPL, MODEL>(rw, L, &s_lane);
-      double phi0 = MODEL == REC_GAUSS ? 0.0 : rec_wave_sum_dpp(phi_l);
-      r = solve<R, NPL, MODEL>(F, L, phi0, s_lane, i, j, w0, lambda, wk);
+      r.hw[0] = hr[o];
+    }
+  }
+}
+
+__device__ __forceinline__ float sgn_at(uint32_t w, int q) { return ((w >> q) & 1u) ? 1.f : -1.f; }
+template <int HW>
+__device__ __forceinline__ float h_at(const uint32_t (&hw)[HW], int q) {
+  uint32_t w = hw[q >> 1];
+  return rec_f16_val((q & 1) ? (w >> 16) : (w & 0xffffu));
+}
+
+// the j row of tanh values, fetched only for pairs the screen does not settle
+template <class R, int NPL>
+__device__ __forceinline__ void fetch_t(const Fields& F, int j, R (&t)[NPL], int lane) {
+  constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  const R* Tr = reinterpret_cast<const R*>(F.T) + (int64_t)j * F.Mp;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) ld_vec<VEC>(Tr + smp<VEC>(c, lane), t + c * VEC);
+}
+
+template <class R, int NPL, int MODEL>
+__global__ __launch_bounds__(256) void k_score_scr(Fields F, WTable W, double lambda, int64_t P,
+                                                   const int32_t* __restrict__ I,
+                                                   const int32_t* __restrict__ J,
+                                                   const int32_t* __restrict__ Smap,
+                                                   const uint32_t* __restrict__ slot, int owned,
+                                                   double* __restrict__ gain_out,
+                                                   double* __restrict__ w_out,
+                                                   double* __restrict__ ovf, uint64_t cache_cap,
+                                                   int32_t* err, int ppw, int64_t* work) {
+  constexpr bool SYM = MODEL == REC_KINSYM;
+  constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  const int lane = rec_lane();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE;
+  int64_t p0 = wave * ppw;
+  if (p0 >= P) return;
+  int np = (int)(p0 + ppw < P ? ppw : P - p0);
+  int li = -1, lj = -1;
+  double lw = 0.0, lw2 = 0.0;
+  if (lane < np) {
+    uint32_t sw = slot ? slot[p0 + lane] : 0u;
+    if (owned && !(sw & OWNER)) {
+      li = SKIP;
+    } else {
+      li = I[p0 + lane];
+      lj = J[p0 + lane];
+      if (Smap) lj = Smap[lj];
+      if (pair_ok(li, lj, F.N)) {
+        lw = lookup_w(W, li, lj, SYM);
+        if constexpr (SYM) lw2 = lookup_w(W, lj, li, true);
+      }
+    }
+  }
+  Lane<R, NPL> L;
+  JScr<NPL, SYM> nx;
+  int cur = -1;
+  Work wk;
+  uint64_t todo = __ballot(lane < np && li != SKIP);
+  if (todo) {
+    int q0 = __ffsll((unsigned long long)todo) - 1;
+    int i0 = rec_uni(__shfl(li, q0, REC_WAVE)), j0 = rec_uni(__shfl(lj, q0, REC_WAVE));
+    if (pair_ok(i0, j0, F.N)) fetch_scr<NPL, SYM>(F, j0, nx, lane);
+  }
+  while (todo) {
+    const int q = __ffsll((unsigned long long)todo) - 1;
+    todo &= todo - 1;
+    const int64_t p = p0 + q;
+    int i = rec_uni(__shfl(li, q, REC_WAVE)), j = rec_uni(__shfl(lj, q, REC_WAVE));
+    double w0 = rec_uni(__shfl(lw, q, REC_WAVE));
+    JScr<NPL, SYM> rw = nx;
+    if (todo) {
+      const int q1 = __ffsll((unsigned long long)todo) - 1;
+      int i1 = rec_uni(__shfl(li, q1, REC_WAVE)), j1 = rec_uni(__shfl(lj, q1, REC_WAVE));
+      if (pair_ok(i1, j1, F.N)) fetch_scr<NPL, SYM>(F, j1, nx, lane);
+    }
+    uint64_t o = slot ? (uint64_t)(slot[p] & ~OWNER) : (uint64_t)p;
+    double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
+    if (!pair_ok(i, j, F.N)) {
+      if (lane == 0) {
+        *dst = __builtin_nan("");
+        if (w_out) w_out[p] = __builtin_nan("");
+        atomicOr(err, 1);
+      }
+      continue;
+    }
+    if (i != cur) { load_i<R, NPL, MODEL>(F, i, L, lane); cur = i; ++wk.iloads; }
+    PairOut r;
+    if constexpr (MODEL == REC_ISING) {
+      bool need = true;
+      if (w0 == 0.0) {
+        float sc = 0.f;
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) {
+          float xi = (float)L.xi[k];
+          sc = fmaf(sgn_at(rw.xw, k), xi - (float)L.ti[k], sc);
+          sc = fmaf(xi, h_at(rw.hw, k), sc);
+        }
+        need = fabs(rec_wave_sum_dpp((double)sc)) > F.scr;
+      }
+      ++wk.pairs;
+      if (!need) {
+        ++wk.screened;
+        r.gain = 0.0;
+        r.w = 0.0;
+        r.w0 = 0.0;
+      } else {
+        ++wk.tfetch;
+        R tj[NPL];
+        fetch_t<R, NPL>(F, j, tj, lane);
+        float s = 0.f;
+        R a = R(0), a2 = R(0);
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) {
+          float xj = sgn_at(rw.xw, k);
+          R u = (R)xj * L.ti[k];
+          L.u[k] = u;
+          a += u;
+          R v = L.xi[k] * tj[k];
+          L.v[k] = v;
+          a2 += v;
+          s += xj * (float)L.xi[k];
+        }
+        double phi0 = rec_wave_sum_dpp(2.0 * (double)s - ((double)a + (double)a2));
+        r = solve_ising<R, NPL, true>(L.u, L.v, phi0, s, w0, lambda, F.M, F.Mp, wk);
+      }
+    } else {
+      const double w0b = rec_uni(__shfl(lw2, q, REC_WAVE));
+      // direction i <- j: exact, from the signs of x_j and the resident row i
+      float s1 = 0.f;
+      R a = R(0);
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        float xj = sgn_at(rw.xw, k);
+        R u = (R)xj * L.ti[k];
+        L.u[k] = u;
+        a += u;
+        s1 += xj * (float)L.xi[k];
+      }
+      double pa = rec_wave_sum_dpp((double)s1 - (double)a);
+      // direction j <- i: screen first
+      bool need_b = true;
+      if (w0b == 0.0) {
+        float sc = 0.f;
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+#pragma unroll
+          for (int k = 0; k < VEC; ++k) sc = fmaf(byte_at(L.xin[c], k), h_at(rw.hw, c * VEC + k), sc);
+        need_b = fabs(rec_wave_sum_dpp((double)sc)) > F.scr;
+      }
+      wk.pairs += 2;
+      PairOut ra = solve_ising<R, NPL, false>(L.u, L.u, pa, s1, w0, lambda, F.M, F.Mp, wk);
+      PairOut rb;
+      rb.gain = 0.0;
+      rb.w = 0.0;
+      rb.w0 = w0b;
+      if (!need_b) {
+        ++wk.screened;
+      } else {
+        ++wk.tfetch;
+        R tj[NPL];
+        fetch_t<R, NPL>(F, j, tj, lane);
+        float s2 = 0.f;
+        R b = R(0);
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+#pragma unroll
+          for (int k = 0; k < VEC; ++k) {
+            const int qq = c * VEC + k;
+            float xi = byte_at(L.xin[c], k);
+            R v = (R)xi * tj[qq];
+            L.v[qq] = v;
+            b += v;
+            s2 += xi * sgn_at(rw.yw, qq);
+          }
+        double pb = rec_wave_sum_dpp((double)s2 - (double)b);
+        rb = solve_ising<R, NPL, false>(L.v, L.v, pb, s2, w0b, lambda, F.M, F.Mp, wk);
+      }
+      r = rb.gain > ra.gain ? rb : ra;
     }
     double g = r.gain;
     if constexpr (sizeof(R) == 4) g = (double)(float)g;   // FP32 scores
@@ -558,11 +746,12 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
     }
   }
   if (lane == 0 && work) {
-    int64_t* wc = work + 4 * (wave & (REC_WORK_COPIES - 1));
-    atomicAdd((unsigned long long*)&wc[0], (unsigned long long)wk.pairs);
-    atomicAdd((unsigned long long*)&wc[1], (unsigned long long)wk.moments);
-    atomicAdd((unsigned long long*)&wc[2], (unsigned long long)wk.evals);
-    atomicAdd((unsigned long long*)&wc[3], (unsigned long long)wk.logs);
+    const int64_t M = F.M, rs = sizeof(R);
+    const int64_t items = SYM ? wk.pairs / 2 : wk.pairs;
+    const int64_t sb = (M + 7) / 8 * (SYM ? 2 : 1) + 2 * M;       // signs + fp16 residuals
+    wk.bytes = items * (16 + (slot ? 4 : 0) + sb) + wk.tfetch * rs * M +
+               wk.iloads * (rs * M + M * (SYM ? 2 : 1));
+    wk.flush(work, wave);
   }
 }
 
@@ -614,7 +803,12 @@ __global__ __launch_bounds__(256) void k_update(Fields F, WTable W, double lambd
           R h = H[idx] + (R)(scale * (double)xv[k]);
           if (o + k < F.M) {
             H[idx] = h;
-            if constexpr (MODEL != REC_GAUSS) T[idx] = tanh_(h);
+            if constexpr (MODEL != REC_GAUSS) {
+              R t = tanh_(h);
+              T[idx] = t;
+              const int8_t* Y = MODEL == REC_KINETIC ? F.ys : F.xs;
+              F.rh[idx] = rec_f16_bits((float)((R)Y[idx] - t));
+            }
           }
         }
       }
@@ -643,10 +837,16 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
   double* ovf = C ? C->ovf : nullptr;
   uint64_t cap = C ? (C->mask + 1) : 0;
   int64_t* ev = ctx->work;
+  // Ising and the kinetic search read the j side through the residual screen
 #define REC_SC(NPL)                                                                              \
-  hipLaunchKernelGGL((k_score<R, NPL, MODEL>), dim3(blocks), dim3(256), 0, ctx->stream, ctx->F,  \
-                     ctx->W, ctx->cfg.lambda, P, I, J, Smap, slot, owned, gain_out, w_out, ovf,  \
-                     cap, ctx->err_flag, ppw, ev)
+  if constexpr (MODEL == REC_ISING || MODEL == REC_KINSYM)                                       \
+    hipLaunchKernelGGL((k_score_scr<R, NPL, MODEL>), dim3(blocks), dim3(256), 0, ctx->stream,    \
+                       ctx->F, ctx->W, ctx->cfg.lambda, P, I, J, Smap, slot, owned, gain_out,    \
+                       w_out, ovf, cap, ctx->err_flag, ppw, ev);                                 \
+  else                                                                                           \
+    hipLaunchKernelGGL((k_score<R, NPL, MODEL>), dim3(blocks), dim3(256), 0, ctx->stream,        \
+                       ctx->F, ctx->W, ctx->cfg.lambda, P, I, J, Smap, slot, owned, gain_out,    \
+                       w_out, ovf, cap, ctx->err_flag, ppw, ev)
   switch (ctx->F.npl) {
     case 1: REC_SC(1); break;
     case 2: REC_SC(2); break;

@@ -996,7 +996,7 @@ rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,
                            rec_sweep_stats* st) {
   Search S(ctx);
   // pair scores so far (the work counters are cumulative)
-  int64_t w0[4] = {0, 0, 0, 0};
+  int64_t w0[REC_WORK_N] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (st && rec_work_read(ctx, w0) != REC_OK) return REC_E_HIP;
   int64_t level_n[64];
   rec_status r;
@@ -1007,7 +1007,7 @@ rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,
   }
   if (r != REC_OK) return r;
   if (st) {
-    int64_t w1[4];
+    int64_t w1[REC_WORK_N];
     if (rec_work_read(ctx, w1) != REC_OK) return REC_E_HIP;
     st->pair_evals = w1[0] - w0[0];
     st->nnd_iters = S.nnd_iters;

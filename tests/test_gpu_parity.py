@@ -377,3 +377,89 @@ def test_kinetic_sweeps_track_oracle():
         st = C2.sweep("nndescent")
         assert st["objective"] >= prev - 1e-6 * abs(prev), (s, st, prev)
         prev = st["objective"]
+
+
+# ------------------------------------------------------ residual screen --
+
+def zero_sets_agree(g, go, prec, M):
+    """FP64: the zero gains are exactly the oracle's.  FP32: a gain just above
+    the kink is ~(|Phi| - lambda)^2 / (2 mu0) and the float sums carry ~1e-5
+    of absolute error, so one side may be 0 where the other is below the
+    absolute tolerance; beyond that the zero sets agree."""
+    if prec == "fp64":
+        assert np.array_equal(g == 0, go == 0), np.flatnonzero((g == 0) != (go == 0))[:5]
+    else:
+        tol = RTOL[prec] * M * 1e-3
+        assert np.all(go[g == 0] <= tol) and np.all(g[go == 0] <= tol)
+
+
+def lambda_in_gap(phi):
+    """A lambda in the widest gap between sorted |Phi(0)| values near their
+    median, so no pair's kink test is closer to lambda than half that gap."""
+    a = np.sort(np.abs(phi))
+    n = len(a)
+    lo, hi = n // 4, 3 * n // 4
+    gaps = a[lo + 1:hi] - a[lo:hi - 1]
+    k = lo + int(np.argmax(gaps))
+    return 0.5 * (a[k] + a[k + 1]), a[k + 1] - a[k]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_screen_zero_set_ising(c1, prec):
+    """With lambda inside the bulk of |Phi(0)|, about half the pairs sit below
+    the kink; the fp16 residual screen must settle exactly the pairs the
+    exact kink test zeroes: the zero sets agree with the oracle's, and the
+    other gains agree to tolerance.  Checked at W = 0 and at W != 0."""
+    I, J = all_pairs(c1.N)
+    O0 = oracle.Oracle(c1.X, "ising", 1.0)
+    phi = np.array([O0.pair_deriv(i, j, 0.0) for i, j in zip(I, J)])
+    lam, gap = lambda_in_gap(phi)
+    assert gap > 1e-3
+    O = oracle.Oracle(c1.X, "ising", lam)
+    C = ctx_for(c1, lam, prec)
+    for state in range(2):
+        go, _ = O.score_pairs(I, J)
+        g, _ = C.score_pairs(I, J)
+        g = g.cpu().numpy()
+        zero_sets_agree(g, go, prec, c1.M)
+        assert close(g, go, RTOL[prec], c1.M).all()
+        assert 0.2 < (go == 0).mean() < 0.8
+        # move to a W != 0 state (both sides get the oracle's model)
+        O.gcd_sweep(c1.N, "exhaustive")
+        ei, ej, wv, th = O.get_model()
+        C.set_model(ei, ej, wv, th)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_screen_kinetic_search_scores(prec):
+    """Kinetic search scores max(gain(i<-j), gain(j<-i)) through the screen:
+    with exact KNN lists of length N-1 every unordered pair is scored, and each
+    node's sorted list equals the oracle's sorted scores of that node's pairs
+    (zero entries exactly)."""
+    w = synth.kinetic_er(60, 400, 4.0, 0.3, seed=7)
+    N = w.N
+    O0 = oracle.Oracle(w.X, "kinetic", 1.0)
+    phi = np.array([O0.pair_deriv(i, j, 0.0) for i in range(N) for j in range(N) if i != j])
+    lam, gap = lambda_in_gap(phi)
+    assert gap > 1e-3
+    O = oracle.Oracle(w.X, "kinetic", lam)
+    C = ctx_for(w, lam, prec)
+    S = np.arange(N, dtype=np.int32)
+    for state in range(2):
+        nbr, g, _ = C.knn(S, N - 1, 0, "exact_knn")
+        nbr, g = nbr.cpu().numpy(), g.cpu().numpy()
+        I = np.repeat(np.arange(N), N - 1).astype(np.int32)
+        J = np.array([j for i in range(N) for j in range(N) if j != i], np.int32)
+        go, _ = O.score_pairs(I, J)
+        gd = go.reshape(N, N - 1)
+        full = np.zeros((N, N))
+        full[I, J] = go
+        sym = np.maximum(full, full.T)
+        for a in range(N):
+            ref = np.sort(np.delete(sym[a], a))[::-1]
+            zero_sets_agree(g[a], ref, prec, w.M)
+            assert close(g[a], ref, RTOL[prec], w.M).all(), (state, a)
+        assert 0.1 < (gd == 0).mean() < 0.9
+        O.gcd_sweep(N, "exhaustive")
+        ei, ej, wv, th = O.get_model()
+        C.set_model(ei, ej, wv, th)
