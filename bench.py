@@ -32,6 +32,9 @@ WORKLOADS = {
     "C4": "kinetic Ising time series, N=100000, T=1000 transitions of +-1 spins under parallel "
           "Glauber updates, directed ER mean out-degree 5, w~N(0,0.3^2), kappa=4 (m=400000), "
           "FP32 scores with FP64 sums",
+    "C3": "Gaussian pseudolikelihood, N=20000, M=200 float32 samples from N(0, Theta^-1), ER mean "
+          "degree 4, offdiag U[-0.2,0.2], diagonally dominant, kappa=4 (m=80000); exhaustive "
+          "search through the BF16 MFMA screen (--search screen) with exact rescoring",
     "C2": "Ising pseudolikelihood, N=10000, M=1000 +-1 Gibbs samples, random 3-regular graph, "
           "w~U[-0.4,0.4], kappa=4 (m=40000), FP32 scores with FP64 sums",
     "C1": "Ising pseudolikelihood, N=100, M=500 +-1 Gibbs samples, ER mean degree 3, kappa=4",
@@ -98,7 +101,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C4", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--search", default="nndescent", choices=["nndescent", "exhaustive", "exact_knn"])
+    ap.add_argument("--search", default="nndescent", choices=["nndescent", "exhaustive", "exact_knn", "screen"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",

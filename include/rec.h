@@ -65,7 +65,12 @@ typedef enum { REC_X_INT8 = 0, REC_X_FP32 = 1 } rec_xtype;
 typedef enum {
   REC_SEARCH_NNDESCENT = 0,   /* FindBest [Alg. 3] over NNDescent [Alg. 4]      */
   REC_SEARCH_EXHAUSTIVE = 1,  /* all pairs scored exactly, best m kept         */
-  REC_SEARCH_EXACT_KNN = 2    /* FindBest [Alg. 3] over exhaustive KNN lists    */
+  REC_SEARCH_SURROGATE = 2,   /* reserved: learned proposal ahead of NNDescent  */
+  REC_SEARCH_EXACT_KNN = 3,   /* FindBest [Alg. 3] over exhaustive KNN lists    */
+  REC_SEARCH_SCREEN = 4       /* Gaussian only: every pair screened at once by a
+                                 BF16 MFMA contraction with a proven error bound,
+                                 survivors rescored exactly; returns the
+                                 exhaustive search's positive-gain top m       */
 } rec_search;
 
 typedef struct {
@@ -135,7 +140,7 @@ rec_status rec_score_pairs(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const 
  * directed pairs are taken from both directions of the m pairs it finds.
  * stats_host may be NULL; if given, its search fields are filled (pair_evals
  * counts directed scores for the kinetic model).  Synchronises. */
-rec_status rec_find_best(rec_ctx* ctx, int64_t m, int32_t search, int32_t* i_dev, int32_t* j_dev,
+rec_status rec_find_best_candidates(rec_ctx* ctx, int64_t m, int32_t search, int32_t* i_dev, int32_t* j_dev,
                          double* gain_dev, int64_t* n_out_host, rec_sweep_stats* stats_host);
 
 /* One GCD iteration [Alg. 2]: E_best = FindBest(m = round(kappa N)); every

@@ -18,10 +18,10 @@ LIB_PATH = os.path.join(_HERE, "librec.so")
 
 MODELS = {"ising": 0, "gauss": 1, "kinetic": 2}
 PREC = {"fp64": 0, "fp32": 1}
-SEARCH = {"nndescent": 0, "exhaustive": 1, "exact_knn": 2}
+SEARCH = {"nndescent": 0, "exhaustive": 1, "exact_knn": 3, "screen": 4}
 
 # every symbol include/rec.h declares
-SYMBOLS = ["rec_workspace_size", "rec_create", "rec_destroy", "rec_score_pairs", "rec_find_best",
+SYMBOLS = ["rec_workspace_size", "rec_create", "rec_destroy", "rec_score_pairs", "rec_find_best_candidates",
            "rec_gcd_sweep", "rec_apply_updates", "rec_theta_update", "rec_objective",
            "rec_get_model", "rec_set_model", "rec_get_fields", "rec_knn", "rec_set_timing",
            "rec_kernel_time", "rec_status_str", "rec_last_error"]
@@ -71,7 +71,7 @@ def lib():
             "rec_create": [ctypes.POINTER(RecConfig), vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
             "rec_destroy": [vp],
             "rec_score_pairs": [vp, i64, vp, vp, vp, vp],
-            "rec_find_best": [vp, i64, i32, vp, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(SweepStats)],
+            "rec_find_best_candidates": [vp, i64, i32, vp, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(SweepStats)],
             "rec_gcd_sweep": [vp, i32, ctypes.POINTER(SweepStats)],
             "rec_apply_updates": [vp, i64, vp, vp, ctypes.POINTER(dbl)],
             "rec_theta_update": [vp, ctypes.POINTER(dbl)],
@@ -196,7 +196,7 @@ class Context:
         G = t.empty(m, dtype=t.float64, device=self.device)
         n = ctypes.c_int64()
         st = SweepStats()
-        self._check(lib().rec_find_best(self.h, m, SEARCH[search], _ptr(I), _ptr(J), _ptr(G),
+        self._check(lib().rec_find_best_candidates(self.h, m, SEARCH[search], _ptr(I), _ptr(J), _ptr(G),
                                         ctypes.byref(n), ctypes.byref(st)), self.h)
         k = n.value
         return I[:k], J[:k], G[:k], st.as_dict()

@@ -165,6 +165,16 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   x->dw = a.take<double>(z.best_cap);
   x->ex_cap = z.ex_cap;
   x->max_nnz = z.max_nnz;
+  if (c->model == REC_GAUSS) {
+    x->sc_kp = (int)((2 * c->M + 31) / 32 * 32);
+    x->sc_a = a.take<__bf16>(N * x->sc_kp);
+    x->sc_b = a.take<__bf16>(N * x->sc_kp);
+    x->sc_nrm = a.take<float>(N);
+    x->sc_th2 = a.take<float>(N);
+    x->sc_sq = a.take<float>(N);
+    x->sc_hist = a.take<uint32_t>(4096);
+    x->sc_tau = a.take<float>(64);
+  }
 }
 
 __global__ void k_check_pairs(const int32_t* I, const int32_t* J, int64_t P, int64_t N, int32_t* err) {
@@ -349,10 +359,11 @@ rec_status rec_score_pairs(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const 
   return REC_OK;
 }
 
-rec_status rec_find_best(rec_ctx* ctx, int64_t m, int32_t search, int32_t* i_dev, int32_t* j_dev,
+rec_status rec_find_best_candidates(rec_ctx* ctx, int64_t m, int32_t search, int32_t* i_dev, int32_t* j_dev,
                          double* gain_dev, int64_t* n_out_host, rec_sweep_stats* st) {
   REC_CHECK_CTX(ctx);
-  if (m < 1 || !i_dev || !j_dev || !gain_dev || !n_out_host || search < 0 || search > 2)
+  if (m < 1 || !i_dev || !j_dev || !gain_dev || !n_out_host || search < 0 || search > REC_SEARCH_SCREEN ||
+      search == REC_SEARCH_SURROGATE)
     return fail(ctx, REC_E_INVAL, "bad arguments");
   if (m > ctx->best_cap) return fail(ctx, REC_E_INVAL, "m exceeds the capacity planned for kappa");
   REC_TRY(clear_err(ctx));
@@ -397,7 +408,8 @@ rec_status rec_apply_updates(rec_ctx* ctx, int64_t P, const int32_t* i_dev, cons
 
 rec_status rec_gcd_sweep(rec_ctx* ctx, int32_t search, rec_sweep_stats* st) {
   REC_CHECK_CTX(ctx);
-  if (search < 0 || search > 2) return fail(ctx, REC_E_INVAL, "unknown search");
+  if (search < 0 || search > REC_SEARCH_SCREEN || search == REC_SEARCH_SURROGATE)
+    return fail(ctx, REC_E_INVAL, "unknown search");
   REC_TRY(clear_err(ctx));
   rec_sweep_stats S{};
   double t0 = now_ms();

@@ -128,6 +128,13 @@ struct rec_ctx {
   // kinetic model inside FindBest: pairs are unordered and scored by the
   // larger of the two directed gains
   bool sym_search = false;
+  // screening contraction (Gaussian): bf16 operands N x sc_kp, row norms,
+  // theta^2, |x|^2, histogram and threshold
+  __bf16* sc_a = nullptr;
+  __bf16* sc_b = nullptr;
+  int sc_kp = 0;
+  float *sc_nrm = nullptr, *sc_th2 = nullptr, *sc_sq = nullptr, *sc_tau = nullptr;
+  uint32_t* sc_hist = nullptr;
   // pair-score kernel timing (instrumentation)
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -184,6 +191,9 @@ struct Digit { int word, shift; };
 rec_status rec_radix_sort(rec_ctx* ctx, int64_t n, const Digit* digits, int nd, int* cur);
 rec_status rec_exclusive_scan(rec_ctx* ctx, const int64_t* in, int64_t* out, int64_t n,
                               int64_t* total_dev);
+
+// screen.hip: candidates of the exhaustive screen into ts_i/ts_j (count *n_out)
+rec_status rec_screen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out);
 
 // search.hip
 rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,

@@ -613,6 +613,7 @@ struct Search {
   int64_t* d_tmp;
   int64_t nnd_iters = 0;
   int levels = 0;
+  int64_t screened = 0;
 
   explicit Search(rec_ctx* c) : ctx(c) {
     d_ts_n = c->counter + 2;
@@ -654,6 +655,7 @@ struct Search {
     }
     if (e & 2) { ctx->err = "W table full (increase max_nnz)"; return REC_E_NOMEM; }
     if (e & 64) { ctx->err = "internal: duplicate neighbour in a merged list"; return REC_E_NUMERIC; }
+    if (e & 256) { ctx->err = "screen candidates exceed the candidate buffer"; return REC_E_NOMEM; }
     if (e & 128) { ctx->err = "internal: candidate passes disagree"; return REC_E_NUMERIC; }
     if (e) { ctx->err = "device error flag " + std::to_string(e); return REC_E_NUMERIC; }
     return REC_OK;
@@ -929,6 +931,52 @@ struct Search {
     return rec_radix_sort(ctx, n, dg, nd, cur);
   }
 
+  // Exhaustive through the screening contraction (Gaussian): candidates from
+  // the MFMA screen plus the current couplings, rescored exactly; the best m
+  // with positive gain are kept (see screen.hip for why none is missed).
+  rec_status screen(int64_t m, int64_t* n_out) {
+    hipStream_t s = ctx->stream;
+    if (ctx->cfg.model != REC_GAUSS) {
+      ctx->err = "the screening search is defined for the Gaussian model";
+      return REC_E_INVAL;
+    }
+    int64_t nnz = 0;
+    rec_status st = rec_wtable_compact(ctx, &nnz);
+    if (st != REC_OK) return st;
+    int64_t nc = 0;
+    if ((st = rec_screen_candidates(ctx, m + nnz, &nc)) != REC_OK) return st;
+    if ((st = check_err()) != REC_OK) return st;
+    const int64_t np = nc + nnz;
+    if (np > ctx->cand_cap || np > ctx->sb.cap) { ctx->err = "screen candidates exceed the buffers"; return REC_E_NOMEM; }
+    int32_t* I = ctx->ts_i;
+    int32_t* J = ctx->ts_j;
+    double* g = ctx->C.ovf;
+    if (nnz > 0) {
+      hipMemcpyAsync(I + nc, ctx->wi, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+      hipMemcpyAsync(J + nc, ctx->wj, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+    }
+    if ((st = rec_launch_score(ctx, np, I, J, nullptr, g, nullptr, nullptr)) != REC_OK) return st;
+    int64_t* d_n = ctx->counter + 9;
+    hipMemsetAsync(d_n, 0, sizeof(int64_t), s);
+    // keep positive gains only
+    if (np > 0)
+      hipLaunchKernelGGL(k_ex_append, dim3(gridn(np)), dim3(256), 0, s, I, J, g, np,
+                         __builtin_bit_cast(double, (uint64_t)1), 0, ctx->sb.khi[0], ctx->sb.klo[0],
+                         ctx->sb.val[0], d_n, ctx->sb.cap);
+    int64_t tot = 0;
+    if ((st = get(d_n, &tot)) != REC_OK) return st;
+    int cur = 0;
+    if ((st = sort_records(tot, &cur)) != REC_OK) return st;
+    int64_t keep = std::min(tot, m);
+    if (keep > ctx->best_cap) { ctx->err = "m exceeds capacity"; return REC_E_NOMEM; }
+    if (keep > 0)
+      hipLaunchKernelGGL(k_take_best, dim3(gridn(keep)), dim3(256), 0, s, ctx->sb.khi[cur],
+                         ctx->sb.klo[cur], keep, ctx->best_i, ctx->best_j, ctx->best_g);
+    screened = nc;
+    *n_out = keep;
+    return check_err();
+  }
+
   // Exhaustive: every pair scored exactly, best m kept (chunks of rows).
   rec_status exhaustive(int64_t m, int64_t* n_out) {
     hipStream_t s = ctx->stream;
@@ -1002,6 +1050,8 @@ rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,
   rec_status r;
   if (search == REC_SEARCH_EXHAUSTIVE) {
     r = S.exhaustive(m, n_out);
+  } else if (search == REC_SEARCH_SCREEN) {
+    r = S.screen(m, n_out);
   } else {
     r = S.find_best(m, search == REC_SEARCH_EXACT_KNN ? 1 : 0, n_out, level_n, 64);
   }

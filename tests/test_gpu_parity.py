@@ -463,3 +463,46 @@ def test_screen_kinetic_search_scores(prec):
         O.gcd_sweep(N, "exhaustive")
         ei, ej, wv, th = O.get_model()
         C.set_model(ei, ej, wv, th)
+
+
+# ------------------------------------------- MFMA screening contraction --
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_screen_search_equals_exhaustive_gauss(prec):
+    """The BF16 MFMA screen with its error bound drops no pair of the top m:
+    the screened search returns exactly the exhaustive search's positive-gain
+    top m, at W = 0 and at W != 0 states (N = 700: five full 128-row tiles and
+    a ragged one; M = 200 gives K = 400 padded to 416)."""
+    w = synth.gauss_er(700, 200, 4.0, 0.2, 1e-3, seed=8)
+    lam = oracle.default_lambda(w.X, "gauss")
+    C = ctx_for(w, lam, prec)
+    O = oracle.Oracle(w.X, "gauss", lam)
+    m = 4 * w.N
+    for state in range(3):
+        I, J, G, _ = C.find_best(m, "exhaustive")
+        I2, J2, G2, _ = C.find_best(m, "screen")
+        I, J, G = I.cpu().numpy(), J.cpu().numpy(), G.cpu().numpy()
+        npos = int(min((G > 0).sum(), m))
+        assert npos > m // 4, npos
+        assert len(I2) == npos
+        assert np.array_equal(I[:npos], I2.cpu().numpy())
+        assert np.array_equal(J[:npos], J2.cpu().numpy())
+        assert np.array_equal(G[:npos], G2.cpu().numpy())
+        if prec == "fp64" and state == 0:
+            Io, Jo, Go, _ = O.find_best(m, "exhaustive")
+            assert close(G2.cpu().numpy(), Go[:npos], 1e-10, w.M).all()
+        C.sweep("screen")
+
+
+def test_screen_sweeps_track_oracle_gauss():
+    w = synth.gauss_er(300, 200, 4.0, 0.2, 1e-3, seed=9)
+    lam = oracle.default_lambda(w.X, "gauss")
+    O = oracle.Oracle(w.X, "gauss", lam)
+    C = ctx_for(w, lam, "fp64", kappa=1.0)
+    for s in range(3):
+        I, J, G, _ = O.find_best(w.N, "exhaustive")
+        npos = int((G > 0).sum())
+        assert npos >= w.N   # the screen returns positive gains only
+        d_or, obj_or = O.gcd_sweep(w.N, "exhaustive")
+        st = C.sweep("screen")
+        assert abs(st["objective"] - obj_or) <= 1e-9 * abs(obj_or), (s, st, obj_or)
