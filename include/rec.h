@@ -185,6 +185,66 @@ rec_status rec_get_fields(rec_ctx* ctx, double* H_dev);
 rec_status rec_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int32_t k, int32_t level,
                    int32_t mode, int32_t* nbr_dev, double* gain_dev, int32_t* iters_host);
 
+/* ---- Learned proposal (not part of the paper) --------------------------
+ * A ranking MLP over per-node sketches orders the candidate pairs of the
+ * second-neighbour search [Alg. 4] so that only the most promising fraction
+ * is scored exactly [Alg. 2, function D]; the exact score judges every pair
+ * that enters a list.  Sketch of node i (64 floats): 28 + 28 random +-1
+ * projections P(x_i + r_i)/sqrt(M), P(x_i - r_i)/sqrt(M) (r = y - tanh h;
+ * Gaussian: the residual; P[d][m] = -1 iff the top bit of SplitMix64
+ * ctr(seed, 7, d, m) is set), then mean y, mean t, var t, mean |h|, mean r^2,
+ * log(1 + degree), sum |W_i.|, theta_i.  Pair feature: [s_i*s_j, |s_i-s_j|,
+ * s_i+s_j] (192) -> 128 -> 128 -> 1 with ReLU; trained on log(1 + gain).
+ * Flat parameters (REC_SUR_NPARAM floats): W1[192][128], b1[128],
+ * W2[128][128], b2[128], w3[128], b3. */
+#define REC_SUR_SKETCH_DIM 64
+#define REC_SUR_NPARAM 41345
+#define REC_SUR_MAX_BATCH 8192
+
+/* Sketches of every node at the current state into the context (and into
+ * S_dev, N x 64 floats, when not NULL).  Synchronises. */
+rec_status rec_sketch(rec_ctx* ctx, float* S_dev);
+
+/* Copy the parameters out to get_dev (may be NULL), then replace them by
+ * set_dev (may be NULL; resets the Adam state).  Device pointers of
+ * REC_SUR_NPARAM floats.  Synchronises. */
+rec_status rec_mlp_params(rec_ctx* ctx, float* get_dev, const float* set_dev);
+
+/* MLP scores of P pairs under the context's sketches (BF16 MFMA with FP32
+ * accumulation; h1 rounded to bf16 between the layers).  Synchronises. */
+rec_status rec_mlp_infer(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
+                         float* out_dev);
+
+/* FP32 loss mean (out - y)^2 / 2 and its gradient for a batch of
+ * 1 <= P <= REC_SUR_MAX_BATCH pairs with targets y_dev (grad_dev: NPARAM
+ * floats, may be NULL).  Synchronises. */
+rec_status rec_mlp_grad(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
+                        const float* y_dev, float* grad_dev, double* loss_host);
+
+/* `steps` Adam steps (beta 0.9/0.999, eps 1e-8, bias-corrected) on one batch;
+ * *loss_host gets the loss before the last step.  Synchronises. */
+rec_status rec_mlp_train(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
+                         const float* y_dev, int32_t steps, float lr, double* loss_host);
+
+/* The proposal inside FindBest (search REC_SEARCH_SURROGATE, NNDescent
+ * underneath).  rho: fraction of each candidate chunk scored exactly (by
+ * predicted rank); recall_min: the proposal filters only while its last
+ * recall estimate of positive-gain candidates reaches this (else the plain
+ * search runs and the network is evaluated in shadow: exact recall); after
+ * every such FindBest call the network takes train_steps Adam steps (lr) on
+ * the call's exact scores (all positive gains, zeros sampled 1 in
+ * 2^zero_log2); 1 in 2^audit_log2 of the filtered-out candidates is scored
+ * anyway to estimate the recall.  Defaults: 0.25, 0.99, 50, 1e-3, 4, 6. */
+rec_status rec_surrogate_config(rec_ctx* ctx, double rho, double recall_min, int32_t train_steps,
+                                float lr, int32_t audit_log2, int32_t zero_log2);
+
+/* After the last REC_SEARCH_SURROGATE call: [0] 1 = plain search with
+ * shadow evaluation, 2 = filtered; [1] recall estimate; [2] fraction of
+ * candidates scored exactly; [3] positives kept; [4] positives missed
+ * (estimated when filtered); [5], [6] training records (positive, zero);
+ * [7] training loss; [8] calls so far; [9] rho.  Host array of 10. */
+rec_status rec_surrogate_stats(rec_ctx* ctx, double* out_host);
+
 /* Instrumentation (not part of the method): when on, every launch of the
  * pair-score kernel is bracketed by HIP events on the context's stream.
  * rec_kernel_time returns, for the launches since the last call (or since

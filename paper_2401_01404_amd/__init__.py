@@ -18,13 +18,18 @@ LIB_PATH = os.path.join(_HERE, "librec.so")
 
 MODELS = {"ising": 0, "gauss": 1, "kinetic": 2}
 PREC = {"fp64": 0, "fp32": 1}
-SEARCH = {"nndescent": 0, "exhaustive": 1, "exact_knn": 3, "screen": 4}
+SEARCH = {"nndescent": 0, "exhaustive": 1, "surrogate": 2, "exact_knn": 3, "screen": 4}
 
 # every symbol include/rec.h declares
 SYMBOLS = ["rec_workspace_size", "rec_create", "rec_destroy", "rec_score_pairs", "rec_find_best_candidates",
            "rec_gcd_sweep", "rec_apply_updates", "rec_theta_update", "rec_objective",
            "rec_get_model", "rec_set_model", "rec_get_fields", "rec_knn", "rec_set_timing",
-           "rec_kernel_time", "rec_status_str", "rec_last_error"]
+           "rec_kernel_time", "rec_status_str", "rec_last_error", "rec_sketch", "rec_mlp_params",
+           "rec_mlp_infer", "rec_mlp_grad", "rec_mlp_train", "rec_surrogate_config",
+           "rec_surrogate_stats"]
+SUR_NPARAM = 41345
+SUR_SKETCH_DIM = 64
+SUR_MAX_BATCH = 8192
 
 
 class RecConfig(ctypes.Structure):
@@ -82,6 +87,13 @@ def lib():
             "rec_knn": [vp, i64, vp, i32, i32, i32, vp, vp, ctypes.POINTER(i32)],
             "rec_set_timing": [vp, i32],
             "rec_kernel_time": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.c_void_p],
+            "rec_sketch": [vp, vp],
+            "rec_mlp_params": [vp, vp, vp],
+            "rec_mlp_infer": [vp, i64, vp, vp, vp],
+            "rec_mlp_grad": [vp, i64, vp, vp, vp, vp, ctypes.POINTER(dbl)],
+            "rec_mlp_train": [vp, i64, vp, vp, vp, i32, ctypes.c_float, ctypes.POINTER(dbl)],
+            "rec_surrogate_config": [vp, dbl, dbl, i32, ctypes.c_float, i32, i32],
+            "rec_surrogate_stats": [vp, ctypes.POINTER(dbl)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -261,6 +273,60 @@ class Context:
         self._check(lib().rec_knn(self.h, len(S), _ptr(S), k, level, SEARCH[mode], _ptr(nbr), _ptr(g),
                                   ctypes.byref(it)), self.h)
         return nbr, g, it.value
+
+    # --- learned proposal ---------------------------------------------
+    def _f32(self, a):
+        t = self.torch
+        return t.as_tensor(a, dtype=t.float32).to(self.device).contiguous()
+
+    def sketch(self):
+        t = self.torch
+        S = t.empty((self.N, SUR_SKETCH_DIM), dtype=t.float32, device=self.device)
+        self._check(lib().rec_sketch(self.h, _ptr(S)), self.h)
+        return S
+
+    def mlp_params(self, new=None):
+        """Current flat parameters (copy); replaces them by `new` when given."""
+        t = self.torch
+        cur = t.empty(SUR_NPARAM, dtype=t.float32, device=self.device)
+        src = None if new is None else self._f32(new)
+        self._check(lib().rec_mlp_params(self.h, _ptr(cur), _ptr(src)), self.h)
+        return cur
+
+    def mlp_infer(self, I, J):
+        t = self.torch
+        I, J = self._i32(I), self._i32(J)
+        out = t.empty(len(I), dtype=t.float32, device=self.device)
+        self._check(lib().rec_mlp_infer(self.h, len(I), _ptr(I), _ptr(J), _ptr(out)), self.h)
+        return out
+
+    def mlp_grad(self, I, J, y):
+        t = self.torch
+        I, J, y = self._i32(I), self._i32(J), self._f32(y)
+        g = t.empty(SUR_NPARAM, dtype=t.float32, device=self.device)
+        loss = ctypes.c_double()
+        self._check(lib().rec_mlp_grad(self.h, len(I), _ptr(I), _ptr(J), _ptr(y), _ptr(g),
+                                       ctypes.byref(loss)), self.h)
+        return loss.value, g
+
+    def mlp_train(self, I, J, y, steps: int = 1, lr: float = 1e-3):
+        I, J, y = self._i32(I), self._i32(J), self._f32(y)
+        loss = ctypes.c_double()
+        self._check(lib().rec_mlp_train(self.h, len(I), _ptr(I), _ptr(J), _ptr(y), int(steps),
+                                        float(lr), ctypes.byref(loss)), self.h)
+        return loss.value
+
+    def surrogate_config(self, rho=0.25, recall_min=0.99, train_steps=50, lr=1e-3, audit_log2=4,
+                         zero_log2=6):
+        self._check(lib().rec_surrogate_config(self.h, float(rho), float(recall_min), int(train_steps),
+                                               float(lr), int(audit_log2), int(zero_log2)), self.h)
+
+    def surrogate_stats(self):
+        o = (ctypes.c_double * 10)()
+        self._check(lib().rec_surrogate_stats(self.h, o), self.h)
+        keys = ["mode", "recall", "scored_frac", "pos_kept", "pos_missed", "records_pos",
+                "records_zero", "loss", "calls", "rho"]
+        return dict(zip(keys, list(o)))
 
     def set_timing(self, on: bool = True):
         self._check(lib().rec_set_timing(self.h, 1 if on else 0), self.h)

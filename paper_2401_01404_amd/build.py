@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librec.so")
-SOURCES = ["api.hip", "score.hip", "fields.hip", "sort.hip", "search.hip", "screen.hip"]
+SOURCES = ["api.hip", "score.hip", "fields.hip", "sort.hip", "search.hip", "screen.hip", "surrogate.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17",
          # packed FP32 instructions are left to nobody: see the design notes

@@ -165,6 +165,34 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   x->dw = a.take<double>(z.best_cap);
   x->ex_cap = z.ex_cap;
   x->max_nnz = z.max_nnz;
+  {
+    const int64_t B = REC_SUR_BATCH, NP = REC_SUR_NPARAM;
+    x->sur_pbits = a.take<uint32_t>(z.Mp);
+    x->sur_S = a.take<float>(N * REC_SUR_SDIM);
+    x->sur_Sb = a.take<__bf16>(N * REC_SUR_SDIM);
+    x->sur_par = a.take<float>(NP);
+    x->sur_m = a.take<float>(NP);
+    x->sur_v = a.take<float>(NP);
+    x->sur_g = a.take<float>(NP);
+    x->sur_w1t = a.take<__bf16>(192 * 128);
+    x->sur_w2t = a.take<__bf16>(128 * 128);
+    x->sur_phi = a.take<float>(B * 192);
+    x->sur_z1 = a.take<float>(B * 128);
+    x->sur_h1 = a.take<float>(B * 128);
+    x->sur_z2 = a.take<float>(B * 128);
+    x->sur_h2 = a.take<float>(B * 128);
+    x->sur_out = a.take<float>(B);
+    x->sur_dout = a.take<float>(B);
+    x->sur_lterm = a.take<double>(B);
+    x->sur_pred = a.take<float>(z.cand_cap);
+    x->sur_flag = a.take<uint8_t>(z.cand_cap);
+    x->sur_hist = a.take<uint32_t>(4096);
+    x->sur_thr = a.take<uint32_t>(64);
+    x->sur_cnt = a.take<int64_t>(16);
+    x->sur_ri = a.take<int32_t>(2 * B);
+    x->sur_rj = a.take<int32_t>(2 * B);
+    x->sur_ry = a.take<float>(2 * B);
+  }
   if (c->model == REC_GAUSS) {
     x->sc_kp = (int)((2 * c->M + 31) / 32 * 32);
     x->sc_a = a.take<__bf16>(N * x->sc_kp);
@@ -334,6 +362,7 @@ rec_status rec_create(const rec_config* cfg, const void* X_dev, void* ws_dev, si
   if (e & 4) return bad(REC_E_NUMERIC);
   double obj;
   if (refresh(ctx, &obj) != REC_OK) return bad(REC_E_HIP);
+  if (rec_sur_init(ctx) != REC_OK) return bad(REC_E_HIP);
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bad(REC_E_HIP);
   *out = ctx;
   return REC_OK;
@@ -362,8 +391,7 @@ rec_status rec_score_pairs(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const 
 rec_status rec_find_best_candidates(rec_ctx* ctx, int64_t m, int32_t search, int32_t* i_dev, int32_t* j_dev,
                          double* gain_dev, int64_t* n_out_host, rec_sweep_stats* st) {
   REC_CHECK_CTX(ctx);
-  if (m < 1 || !i_dev || !j_dev || !gain_dev || !n_out_host || search < 0 || search > REC_SEARCH_SCREEN ||
-      search == REC_SEARCH_SURROGATE)
+  if (m < 1 || !i_dev || !j_dev || !gain_dev || !n_out_host || search < 0 || search > REC_SEARCH_SCREEN)
     return fail(ctx, REC_E_INVAL, "bad arguments");
   if (m > ctx->best_cap) return fail(ctx, REC_E_INVAL, "m exceeds the capacity planned for kappa");
   REC_TRY(clear_err(ctx));
@@ -408,8 +436,7 @@ rec_status rec_apply_updates(rec_ctx* ctx, int64_t P, const int32_t* i_dev, cons
 
 rec_status rec_gcd_sweep(rec_ctx* ctx, int32_t search, rec_sweep_stats* st) {
   REC_CHECK_CTX(ctx);
-  if (search < 0 || search > REC_SEARCH_SCREEN || search == REC_SEARCH_SURROGATE)
-    return fail(ctx, REC_E_INVAL, "unknown search");
+  if (search < 0 || search > REC_SEARCH_SCREEN) return fail(ctx, REC_E_INVAL, "unknown search");
   REC_TRY(clear_err(ctx));
   rec_sweep_stats S{};
   double t0 = now_ms();
@@ -522,6 +549,111 @@ rec_status rec_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int32_t k, int
   if (s != REC_OK) return s;
   REC_HIP(hipStreamSynchronize(ctx->stream));
   if (iters_host) *iters_host = it;
+  return REC_OK;
+}
+
+// ---- learned proposal ----
+rec_status rec_sketch(rec_ctx* ctx, float* S_dev) {
+  REC_CHECK_CTX(ctx);
+  REC_TRY(rec_sur_sketch(ctx));
+  if (S_dev)
+    REC_HIP(hipMemcpyAsync(S_dev, ctx->sur_S, ctx->cfg.N * REC_SUR_SDIM * sizeof(float),
+                           hipMemcpyDeviceToDevice, ctx->stream));
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  return REC_OK;
+}
+
+rec_status rec_mlp_params(rec_ctx* ctx, float* get_dev, const float* set_dev) {
+  REC_CHECK_CTX(ctx);
+  const size_t bytes = REC_SUR_NPARAM * sizeof(float);
+  if (get_dev) REC_HIP(hipMemcpyAsync(get_dev, ctx->sur_par, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  if (set_dev) {
+    REC_HIP(hipMemcpyAsync(ctx->sur_par, set_dev, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    REC_HIP(hipMemsetAsync(ctx->sur_m, 0, bytes, ctx->stream));
+    REC_HIP(hipMemsetAsync(ctx->sur_v, 0, bytes, ctx->stream));
+    ctx->sur_t = 0;
+    REC_TRY(rec_sur_pack(ctx));
+  }
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  return REC_OK;
+}
+
+namespace {
+rec_status check_pairs_arg(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J) {
+  REC_TRY(clear_err(ctx));
+  hipLaunchKernelGGL(k_check_pairs, dim3((P + 255) / 256), dim3(256), 0, ctx->stream, I, J, P,
+                     ctx->cfg.N, ctx->err_flag);
+  int32_t e = 0;
+  REC_TRY(read_err(ctx, &e));
+  if (e & 1) return fail(ctx, REC_E_INVAL, "pair indices outside [0, N) or i == j");
+  return REC_OK;
+}
+}  // namespace
+
+rec_status rec_mlp_infer(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
+                         float* out_dev) {
+  REC_CHECK_CTX(ctx);
+  if (P < 0 || (P > 0 && (!i_dev || !j_dev || !out_dev))) return fail(ctx, REC_E_INVAL, "bad arguments");
+  if (P == 0) return REC_OK;
+  REC_TRY(check_pairs_arg(ctx, P, i_dev, j_dev));
+  REC_TRY(rec_sur_infer(ctx, P, i_dev, j_dev, nullptr, nullptr, out_dev));
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  return REC_OK;
+}
+
+rec_status rec_mlp_grad(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
+                        const float* y_dev, float* grad_dev, double* loss_host) {
+  REC_CHECK_CTX(ctx);
+  if (P < 1 || P > REC_SUR_BATCH || !i_dev || !j_dev || !y_dev)
+    return fail(ctx, REC_E_INVAL, "bad arguments (1 <= P <= 8192)");
+  REC_TRY(check_pairs_arg(ctx, P, i_dev, j_dev));
+  REC_TRY(rec_sur_grad(ctx, P, i_dev, j_dev, y_dev));
+  if (grad_dev)
+    REC_HIP(hipMemcpyAsync(grad_dev, ctx->sur_g, REC_SUR_NPARAM * sizeof(float), hipMemcpyDeviceToDevice,
+                           ctx->stream));
+  double l = 0.0;
+  REC_HIP(hipMemcpyAsync(&l, ctx->dresult + 8, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  if (loss_host) *loss_host = l;
+  return REC_OK;
+}
+
+rec_status rec_mlp_train(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
+                         const float* y_dev, int32_t steps, float lr, double* loss_host) {
+  REC_CHECK_CTX(ctx);
+  if (P < 1 || P > REC_SUR_BATCH || !i_dev || !j_dev || !y_dev || steps < 1 || !(lr > 0.f))
+    return fail(ctx, REC_E_INVAL, "bad arguments (1 <= P <= 8192, steps >= 1, lr > 0)");
+  REC_TRY(check_pairs_arg(ctx, P, i_dev, j_dev));
+  for (int s = 0; s < steps; ++s) {
+    REC_TRY(rec_sur_grad(ctx, P, i_dev, j_dev, y_dev));
+    REC_TRY(rec_sur_adam(ctx, lr));
+  }
+  REC_TRY(rec_sur_pack(ctx));
+  double l = 0.0;
+  REC_HIP(hipMemcpyAsync(&l, ctx->dresult + 8, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  if (loss_host) *loss_host = l;
+  return REC_OK;
+}
+
+rec_status rec_surrogate_config(rec_ctx* ctx, double rho, double recall_min, int32_t train_steps,
+                                float lr, int32_t audit_log2, int32_t zero_log2) {
+  REC_CHECK_CTX(ctx);
+  if (!(rho > 0.0 && rho <= 1.0) || !(recall_min >= 0.0 && recall_min <= 1.0) || train_steps < 0 ||
+      !(lr > 0.f) || audit_log2 < 0 || audit_log2 > 20 || zero_log2 < 0 || zero_log2 > 30)
+    return fail(ctx, REC_E_INVAL, "bad surrogate configuration");
+  ctx->sur_rho = rho;
+  ctx->sur_recall_min = recall_min;
+  ctx->sur_steps = train_steps;
+  ctx->sur_lr = lr;
+  ctx->sur_audit = 1u << audit_log2;
+  ctx->sur_zbits = zero_log2;
+  return REC_OK;
+}
+
+rec_status rec_surrogate_stats(rec_ctx* ctx, double* out_host) {
+  if (!ctx || !out_host) return REC_E_INVAL;
+  for (int q = 0; q < 10; ++q) out_host[q] = ctx->sur_stats[q];
   return REC_OK;
 }
 

@@ -25,6 +25,14 @@ __device__ __forceinline__ uint64_t rec_below(uint64_t r, uint64_t bound) {
 
 constexpr uint64_t REC_STREAM_INIT = 5;  // NNDescent initial lists
 constexpr uint64_t REC_STREAM_CAP = 6;   // in-neighbour sampling of the undirected graph U
+constexpr uint64_t REC_STREAM_PROJ = 7;  // +-1 projections of the sketches
+constexpr uint64_t REC_STREAM_INIT_W = 8;  // initial MLP weights
+constexpr uint64_t REC_STREAM_AUDIT = 9;   // audit and training-record sampling
+
+// learned proposal: sketch width, parameter count, training batch cap
+constexpr int REC_SUR_SDIM = 64;
+constexpr int64_t REC_SUR_NPARAM = 192 * 128 + 128 + 128 * 128 + 128 + 128 + 1;
+constexpr int64_t REC_SUR_BATCH = 8192;
 
 // ------------------------------------------------------------ pair keys --
 // Symmetric models: one key per unordered pair; kinetic: ordered (i <- j).

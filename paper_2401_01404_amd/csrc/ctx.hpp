@@ -135,6 +135,33 @@ struct rec_ctx {
   int sc_kp = 0;
   float *sc_nrm = nullptr, *sc_th2 = nullptr, *sc_sq = nullptr, *sc_tau = nullptr;
   uint32_t* sc_hist = nullptr;
+  // learned proposal (surrogate.hip): projection bits, sketches, parameters,
+  // Adam state, bf16 weight copies, training work arrays
+  uint32_t* sur_pbits = nullptr;
+  float* sur_S = nullptr;
+  __bf16* sur_Sb = nullptr;
+  float *sur_par = nullptr, *sur_m = nullptr, *sur_v = nullptr, *sur_g = nullptr;
+  __bf16 *sur_w1t = nullptr, *sur_w2t = nullptr;
+  float *sur_phi = nullptr, *sur_z1 = nullptr, *sur_h1 = nullptr, *sur_z2 = nullptr, *sur_h2 = nullptr;
+  float *sur_out = nullptr, *sur_dout = nullptr;
+  double* sur_lterm = nullptr;
+  int64_t sur_t = 0;
+  // proposal inside the search: predictions, flags, threshold, counters, records
+  float* sur_pred = nullptr;
+  uint8_t* sur_flag = nullptr;
+  uint32_t *sur_hist = nullptr, *sur_thr = nullptr;
+  int64_t* sur_cnt = nullptr;
+  int32_t *sur_ri = nullptr, *sur_rj = nullptr;
+  float* sur_ry = nullptr;
+  // configuration and state
+  double sur_rho = 0.25, sur_recall_min = 0.99;
+  int sur_steps = 50, sur_zbits = 6;
+  uint32_t sur_audit = 16;
+  float sur_lr = 1e-3f;
+  int sur_mode = 0;            // inside a FindBest call: 0 off, 1 shadow (plain search), 2 active
+  bool sur_trained = false;
+  double sur_recall = -1.0;    // last estimate (-1: none yet)
+  double sur_stats[10] = {0, -1, 0, 0, 0, 0, 0, 0, 0, 0};
   // pair-score kernel timing (instrumentation)
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -194,6 +221,19 @@ rec_status rec_exclusive_scan(rec_ctx* ctx, const int64_t* in, int64_t* out, int
 
 // screen.hip: candidates of the exhaustive screen into ts_i/ts_j (count *n_out)
 rec_status rec_screen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out);
+
+// surrogate.hip
+rec_status rec_sur_init(rec_ctx* ctx);     // projection bits, initial weights, Adam state
+rec_status rec_sur_pack(rec_ctx* ctx);     // bf16 weight copies for inference
+rec_status rec_sur_sketch(rec_ctx* ctx);   // sketches at the current state
+rec_status rec_sur_infer(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
+                         const int32_t* Jmap, const uint32_t* slot, float* out);
+rec_status rec_sur_grad(rec_ctx* ctx, int64_t B, const int32_t* I, const int32_t* J, const float* y);
+rec_status rec_sur_adam(rec_ctx* ctx, float lr);
+rec_status rec_sur_filter(rec_ctx* ctx, int64_t n, const int32_t* gi, const int32_t* v,
+                          const int32_t* S, uint32_t* slot, int shadow);
+rec_status rec_sur_count(rec_ctx* ctx, int64_t n, const uint32_t* slot);
+rec_status rec_sur_collect_train(rec_ctx* ctx, double* loss, int64_t* npos, int64_t* nzero);
 
 // search.hip
 rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,

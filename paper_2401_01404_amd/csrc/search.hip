@@ -332,7 +332,8 @@ __global__ __launch_bounds__(REC_WAVE) void k_merge(int64_t a0, int64_t a1, int 
     }
     double wg = count == k ? lg[k - 1] : 0.0;
     int wi = count == k ? li[k - 1] : 0;
-    bool pass = valid && (count < k || better(g, v, wg, wi));
+    // a NaN gain marks a pair the learned proposal left unscored: never listed
+    bool pass = valid && g == g && (count < k || better(g, v, wg, wi));
     uint64_t bal = __ballot(pass);
     while (bal) {
       int src = __ffsll((unsigned long long)bal) - 1;
@@ -414,9 +415,12 @@ __global__ void k_mark_d(const uint64_t* khi, const uint64_t* klo, int64_t nsel,
   uint64_t key = ((uint64_t)mn << 32) | mx;
   bool ins;
   bool ok = rec_hash_insert(dkeys, dmask, key, 4096, &ins) >= 0;
-  ok = ok && rec_hash_insert(pkeys, pmask, key, 4096, &ins) >= 0;
+  // unscored pairs (NaN gain) stay out of the pool
+  const double g = rec_desc_gain(khi[e]);
+  bool pool = g == g;
+  if (pool) ok = ok && rec_hash_insert(pkeys, pmask, key, 4096, &ins) >= 0;
   if (!ok) atomicOr(err, 32);
-  int64_t p = rec_append(pool_n, ok && ins);
+  int64_t p = rec_append(pool_n, pool && ok && ins);
   if (p < 0) return;
   if (p >= pool_cap) { atomicOr(err, 32); return; }
   pool_hi[p] = khi[e];
@@ -462,9 +466,11 @@ __global__ __launch_bounds__(BT) void k_allpairs_pool(const int32_t* S, int64_t 
     double g = slot_gain(C, slots[rowbase + (b - a - 1)]);
     uint64_t key = rec_pair_key(S[a], S[b], false);
     bool ins = false;
-    bool ok = rec_hash_insert(pkeys, pmask, key, 4096, &ins) >= 0;
+    bool ok = true;
+    // unscored pairs (NaN gain, left by the learned proposal) stay out of the pool
+    if (g == g) ok = rec_hash_insert(pkeys, pmask, key, 4096, &ins) >= 0;
     if (!ok) atomicOr(err, 32);
-    int64_t p = rec_append(pool_n, ok && ins);
+    int64_t p = rec_append(pool_n, g == g && ok && ins);
     if (p < 0) continue;
     if (p >= pool_cap) { atomicOr(err, 32); continue; }
     pool_hi[p] = rec_desc_key(g);
@@ -741,9 +747,15 @@ struct Search {
         int64_t base = hoff[a0];
         hipLaunchKernelGGL(k_cand<1>, dim3(a1 - a0), dim3(BT), cand_lds, s, P, a0, a1, ctx->cnt,
                            ctx->off, base, ctx->cand_v, ctx->cand_gi, ctx->cand_slot, A);
+        const int64_t nch = hoff[a1] - hoff[a0];
+        // learned proposal: only the best-ranked fraction keeps its owner bit
+        if (ctx->sur_mode != 0 &&
+            (st = rec_sur_filter(ctx, nch, ctx->cand_gi, ctx->cand_v, S, ctx->cand_slot,
+                                 ctx->sur_mode == 1 ? 1 : 0)) != REC_OK) return st;
         // score the claimed candidates in place (owner bit set)
-        if ((st = rec_launch_score_owned(ctx, hoff[a1] - hoff[a0], ctx->cand_gi, ctx->cand_v, S,
+        if ((st = rec_launch_score_owned(ctx, nch, ctx->cand_gi, ctx->cand_v, S,
                                          ctx->cand_slot, &ctx->C)) != REC_OK) return st;
+        if (ctx->sur_mode != 0 && (st = rec_sur_count(ctx, nch, ctx->cand_slot)) != REC_OK) return st;
         hipLaunchKernelGGL(k_merge, dim3(a1 - a0), dim3(REC_WAVE), merge_lds, s, a0, a1, k,
                            mode == 1 ? 1 : 0, ctx->Gidx, ctx->Ggain, ctx->Gidx2, ctx->Ggain2,
                            ctx->cnt, ctx->off, base, ctx->cand_v, ctx->cand_slot, ctx->C, d_delta, 0,
@@ -1040,6 +1052,52 @@ struct Search {
 
 }  // namespace
 
+// FindBest over NNDescent with the learned proposal.  Active (the network is
+// trained and its last recall estimate reaches the bar): each chunk's
+// candidates are ranked and only the top fraction rho is scored, plus an
+// audit sample of the rest (1 in sur_audit, by pair hash) from which the
+// recall of positive gains is estimated.  Otherwise (fallback): the plain
+// search, with the network run in shadow to measure the recall it would have
+// had.  Either way the exact scores of this call then train the network.
+namespace {
+rec_status surrogate_find_best(rec_ctx* ctx, Search& S, int64_t m, int64_t* n_out, int64_t* level_n) {
+  hipStream_t s = ctx->stream;
+  rec_status r = rec_sur_sketch(ctx);
+  if (r != REC_OK) return r;
+  const bool active = ctx->sur_trained && ctx->sur_recall >= ctx->sur_recall_min;
+  ctx->sur_mode = active ? 2 : 1;
+  hipMemsetAsync(ctx->sur_cnt, 0, 16 * sizeof(int64_t), s);
+  r = S.find_best(m, 0, n_out, level_n, 64);
+  ctx->sur_mode = 0;
+  if (r != REC_OK) return r;
+  int64_t c[8];
+  if (hipMemcpyAsync(c, ctx->sur_cnt, sizeof(c), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) { ctx->err = "readback failed"; return REC_E_HIP; }
+  // c: kept positives, below-threshold positives (scored), kept, below scored, dropped
+  const double scale = active ? (double)ctx->sur_audit : 1.0;
+  const double miss = scale * (double)c[1];
+  const double est = (c[0] + miss) > 0 ? (double)c[0] / ((double)c[0] + miss) : 1.0;
+  const double owned = (double)(c[2] + c[3] + c[4]);
+  double loss = 0.0;
+  int64_t np = 0, nz = 0;
+  if ((r = rec_sur_collect_train(ctx, &loss, &np, &nz)) != REC_OK) return r;
+  ctx->sur_trained = true;
+  ctx->sur_recall = est;
+  double* o = ctx->sur_stats;
+  o[0] = active ? 2 : 1;
+  o[1] = est;
+  o[2] = owned > 0 ? (double)(c[2] + c[3]) / owned : 0.0;   // fraction scored exactly
+  o[3] = (double)c[0];
+  o[4] = miss;
+  o[5] = (double)np;
+  o[6] = (double)nz;
+  o[7] = loss;
+  o[8] = ctx->sur_stats[8] + 1;
+  o[9] = ctx->sur_rho;
+  return REC_OK;
+}
+}  // namespace
+
 rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,
                            rec_sweep_stats* st) {
   Search S(ctx);
@@ -1052,6 +1110,8 @@ rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,
     r = S.exhaustive(m, n_out);
   } else if (search == REC_SEARCH_SCREEN) {
     r = S.screen(m, n_out);
+  } else if (search == REC_SEARCH_SURROGATE) {
+    r = surrogate_find_best(ctx, S, m, n_out, level_n);
   } else {
     r = S.find_best(m, search == REC_SEARCH_EXACT_KNN ? 1 : 0, n_out, level_n, 64);
   }

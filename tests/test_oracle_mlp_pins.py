@@ -1,0 +1,98 @@
+"""Pins of the FP64 reference of the learned proposal (oracle/mlp.py) to
+mathematics rather than to itself: central differences for the gradients,
+the closed form of Adam's first steps, a hand-solvable forward pass, the +-1
+structure of the projection and the sketch's estimate of the kink-test value
+Phi(0) of the paper's score [Alg. 2, function D]."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.mlp as mlp
+import synth
+
+
+def rand_params(rng, scale=0.3):
+    return rng.normal(0, scale, mlp.NPARAM)
+
+
+def test_gradient_matches_central_differences():
+    rng = np.random.default_rng(0)
+    p = rand_params(rng, 0.2)
+    phi = rng.normal(0, 1, (6, mlp.PHI))
+    y = rng.normal(0, 1, 6)
+    loss, g = mlp.loss_and_grad(p, phi, y)
+    idx = np.concatenate([rng.choice(mlp.NPARAM, 300, replace=False),
+                          np.arange(mlp.NPARAM - 129, mlp.NPARAM)])   # w3 and b3 in full
+    h = 1e-6
+    for k in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        fd = (mlp.loss_and_grad(pp, phi, y)[0] - mlp.loss_and_grad(pm, phi, y)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])), (k, fd, g[k])
+
+
+def test_adam_first_steps_closed_form():
+    """With a constant gradient the bias-corrected moments are g and g^2, so
+    every step moves each parameter by lr * g / (|g| + eps)."""
+    rng = np.random.default_rng(1)
+    p0 = rng.normal(0, 1, 50)
+    g = rng.normal(0, 1, 50)
+    m = np.zeros(50)
+    v = np.zeros(50)
+    p = p0.copy()
+    lr = 1e-3
+    for t in (1, 2, 3):
+        p, m, v = mlp.adam_step(p, g, m, v, t, lr)
+        want = p0 - t * lr * g / (np.abs(g) + mlp.ADAM_EPS)
+        assert np.allclose(p, want, rtol=0, atol=1e-12)
+
+
+def test_forward_special_case():
+    """W1 selects feature k into unit 0, W2 = identity, w3 = e_0: the output
+    is max(phi_k, 0) + b3; phi = [s_i s_j, |s_i - s_j|, s_i + s_j]."""
+    rng = np.random.default_rng(2)
+    S = rng.normal(0, 1, (5, mlp.S_DIM))
+    I, J = np.array([0, 1, 2, 3]), np.array([4, 3, 0, 1])
+    phi = mlp.pair_features(S, I, J)
+    for k, ref in [(5, S[I, 5] * S[J, 5]), (64 + 7, np.abs(S[I, 7] - S[J, 7])),
+                   (128 + 63, S[I, 63] + S[J, 63])]:
+        W1 = np.zeros((mlp.PHI, mlp.H1))
+        W1[k, 0] = 1.0
+        p = mlp.pack(W1, np.zeros(mlp.H1), np.eye(mlp.H1), np.zeros(mlp.H2),
+                     np.eye(mlp.H2)[0], 0.25)
+        out, _ = mlp.forward(p, phi)
+        assert np.allclose(out, np.maximum(ref, 0) + 0.25, rtol=0, atol=1e-14)
+
+
+def test_projection_is_pm1_from_the_counter_generator():
+    P = mlp.projection(40, seed=3)
+    assert set(np.unique(P)) <= {-1.0, 1.0}
+    # column norms are exact for +-1 entries: |P e_k|^2 = 28
+    assert np.all((P * P).sum(0) == mlp.D)
+    for d, m in [(0, 0), (5, 17), (27, 39)]:
+        top = oracle.ctr(3, 7, d, m) >> 63
+        assert P[d, m] == (-1.0 if top else 1.0)
+
+
+def test_sketch_estimates_the_kink_test_value():
+    """sum_d s_i[d] s_j[d] - s_i[28+d] s_j[28+d] has expectation
+    (56/M) Phi_ij(0) over P; across the pairs of C1 at W = 0 it must track
+    the oracle's own Phi(0) (an independent computation in oracle.cpp).  With
+    28 projections its noise is ~|x_i| |r_j| / sqrt(28), several times the
+    spread of Phi(0) over unrelated pairs, so the correlation is moderate
+    (0.37 here); a sign or index mistake in either half drives it to ~0."""
+    w = synth.config("C1")
+    lam = oracle.default_lambda(w.X, "ising")
+    O = oracle.Oracle(w.X, "ising", lam)
+    ei, ej, wv, th = O.get_model()
+    S = mlp.sketch("ising", w.X, O.fields(), th, ei, ej, wv, seed=0)
+    I, J = np.triu_indices(w.N, 1)
+    est = ((S[I, :28] * S[J, :28]).sum(1) - (S[I, 28:56] * S[J, 28:56]).sum(1)) * w.M / 56.0
+    phi = np.array([O.pair_deriv(i, j, 0.0) for i, j in zip(I, J)])
+    c = np.corrcoef(est, phi)[0, 1]
+    assert c > 0.25, c
+    # statistics block
+    assert np.allclose(S[:, 56], w.X.mean(1))
+    assert np.allclose(S[:, 61], 0) and np.allclose(S[:, 62], 0)
+    assert np.allclose(S[:, 63], th)
