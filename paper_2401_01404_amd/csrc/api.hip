@@ -58,7 +58,7 @@ rec_status plan(const rec_config* c, Sizes* z, const char** why) {
   z->list_cap = std::max<int64_t>(4 * z->mcap + N, N * k0) + 1024;
   int64_t want = N * std::min<int64_t>(4 * k0 * k0, N - 1);
   want = std::max(want, 2 * z->mcap + N);
-  z->cand_cap = std::min<int64_t>(std::max<int64_t>(want, 1 << 16), int64_t(1) << 26);
+  z->cand_cap = std::min<int64_t>(std::max<int64_t>(want, 1 << 16), int64_t(1) << 27);
   // slot words: cache slots + overflow slots must stay below 2^31 (top bit = owner)
   int lc = c->log2_cache;
   if (lc <= 0) {
@@ -165,6 +165,8 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   x->dw = a.take<double>(z.best_cap);
   x->ex_cap = z.ex_cap;
   x->max_nnz = z.max_nnz;
+  x->scr_qcap = std::min<int64_t>(z.cand_cap, int64_t(1) << 30);
+  x->scr_queue = a.take<uint32_t>(x->scr_qcap);
   {
     const int64_t B = REC_SUR_BATCH, NP = REC_SUR_NPARAM;
     x->sur_pbits = a.take<uint32_t>(z.Mp);
@@ -343,12 +345,16 @@ rec_status rec_create(const rec_config* cfg, const void* X_dev, void* ws_dev, si
   F.Mp = z.Mp;
   F.npl = z.npl;
   F.model = cfg->model;
-  // The screen compares sum_m x_m rh_m with lambda: rounding y - tanh h
-  // (|.| < 2) to fp16 moves each term by at most 2^-10 (one fp16 ulp at the
-  // top binade, covering double rounding through float) plus 2^-24 below the
-  // normal range, so |sum| moves by at most M (2^-9 + 2^-24); 0.01 covers the
-  // float partial sums of both the screen and the exact path.
-  F.scr = cfg->lambda - ((double)cfg->M * (std::ldexp(1.0, -9) + std::ldexp(1.0, -24)) + 0.01);
+  // The screens compare kink sums with lambda.  Rounding y - tanh h (|.| < 2)
+  // to fp16 moves each term by at most 2^-10 (one fp16 ulp at the top
+  // binade, covering double rounding through float) plus 2^-24 below the
+  // normal range: M (2^-9 + 2^-24) for a sum.  The exact-sign part uses r_i =
+  // y - t rounded once in the working precision (<= 2^-23 per term) and float
+  // partial sums of at most 32 terms per lane in both the screen and the exact
+  // path; 0.02 covers those sums (<= 64 lanes x 2 x 32 x 32 x 2^-24 < 4e-3).
+  const double eps_sign = (double)cfg->M * std::ldexp(1.0, -22) + 0.02;
+  F.scr = cfg->lambda - ((double)cfg->M * (std::ldexp(1.0, -9) + std::ldexp(1.0, -24)) + eps_sign);
+  F.scra = cfg->lambda - eps_sign;
   auto bad = [&](rec_status st) { delete ctx; return st; };
   if (hipMemsetAsync(ctx->err_flag, 0, 16, ctx->stream) != hipSuccess) return bad(REC_E_HIP);
   if (hipMemsetAsync(ctx->counter, 0, 16 * 8, ctx->stream) != hipSuccess) return bad(REC_E_HIP);

@@ -26,7 +26,8 @@ struct Fields {
   const uint32_t* xq;
   const uint32_t* yq;
   uint16_t* rh;
-  double scr;           // screen threshold: lambda minus the fp16 error bound
+  double scr;           // screen threshold: lambda minus the fp16 (and float) error bound
+  double scra;          // exact-sign screen threshold: lambda minus the float rounding bound
   int64_t N, M, Mp;     // valid samples M, padded row length Mp = 64 * npl
   int npl;              // samples per lane
   int model;            // rec_model
@@ -125,6 +126,9 @@ struct rec_ctx {
   double* dw;           // best_cap
   // exhaustive search chunk buffers
   int64_t ex_cap;
+  // queue of the screened scoring's unsettled pairs (k_kink -> k_exact)
+  uint32_t* scr_queue = nullptr;
+  int64_t scr_qcap = 0;
   // kinetic model inside FindBest: pairs are unordered and scored by the
   // larger of the two directed gains
   bool sym_search = false;

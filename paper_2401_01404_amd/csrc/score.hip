@@ -532,8 +532,10 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
 // sample instead of 5-6); their error moves the second part by at most the
 // bound folded into F.scr, so |screen| <= F.scr proves |Phi(0)| <= lambda
 // and the side's gain is exactly zero, the value the full evaluation gives.
-// Otherwise the fp32/fp64 tanh row of j is fetched and the side is scored
-// exactly as by k_score: the result is the same bits either way.
+// The first part is screened the same way from a resident fp32/fp64 copy of
+// r_i (its only error is float rounding, bounded in F.scra).  Otherwise the
+// tanh rows are fetched and the side is scored exactly as by k_score: the
+// result is the same bits either way.
 template <int NPL, bool SYM>
 struct JScr {
   static constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC, HW = NPL >= 2 ? NPL / 2 : 1;
@@ -579,18 +581,77 @@ __device__ __forceinline__ void fetch_t(const Fields& F, int j, R (&t)[NPL], int
   for (int c = 0; c < CH; ++c) ld_vec<VEC>(Tr + smp<VEC>(c, lane), t + c * VEC);
 }
 
+// The i side of the screened kernels keeps only what the kink tests need in
+// registers: r_i = y_i - t_i (zero in the padding) and the sign words of the
+// inputs x_i.  Both kink sums are then one select and one add per sample:
+//   sum_m x_{j,m} r_{i,m}  (the i <- j part, exact signs)     and
+//   sum_m x_{i,m} rh_{j,m} (the j <- i part, fp16 residuals of j),
+// with padding cancelled by the zeros of r_i and rh_j.  The exact path (a
+// side whose test does not settle it) reloads t_i and the int8 rows of i,
+// which the wave's previous pairs keep in cache, and evaluates the side with
+// the same arithmetic as k_score, so its results are the same bits.
+template <class R, int NPL>
+struct LaneR {
+  R ri[NPL];
+  uint32_t xw;   // signs of the inputs x_i (lane word)
+};
+
 template <class R, int NPL, int MODEL>
-__global__ __launch_bounds__(256) void k_score_scr(Fields F, WTable W, double lambda, int64_t P,
-                                                   const int32_t* __restrict__ I,
-                                                   const int32_t* __restrict__ J,
-                                                   const int32_t* __restrict__ Smap,
-                                                   const uint32_t* __restrict__ slot, int owned,
-                                                   double* __restrict__ gain_out,
-                                                   double* __restrict__ w_out,
-                                                   double* __restrict__ ovf, uint64_t cache_cap,
-                                                   int32_t* err, int ppw, int64_t* work) {
-  constexpr bool SYM = MODEL == REC_KINSYM;
+__device__ __forceinline__ void load_i_r(const Fields& F, int i, LaneR<R, NPL>& L, int lane) {
   constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  const int64_t row = (int64_t)i * F.Mp;
+  const R* Tr = reinterpret_cast<const R*>(F.T) + row;
+  const int8_t* Y = (MODEL == REC_KINSYM ? F.ys : F.xs) + row;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int64_t o = smp<VEC>(c, lane);
+    R t[VEC];
+    ld_vec<VEC>(Tr + o, t);
+    const int yb = ld_bytes<VEC>(Y + o);
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) L.ri[c * VEC + k] = (R)byte_at(yb, k) - t[k];
+  }
+  L.xw = F.xq[(int64_t)i * REC_WAVE + lane];
+}
+
+// exact-path i side: t_i and the int8 rows (targets, and inputs for the
+// kinetic search) as in k_score
+template <class R, int NPL, int MODEL>
+__device__ __forceinline__ void load_i_exact(const Fields& F, int i, R (&ti)[NPL], int (&yb)[NPL < 4 ? 1 : NPL / 4],
+                                             int (&xb)[NPL < 4 ? 1 : NPL / 4], int lane) {
+  constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  const int64_t row = (int64_t)i * F.Mp;
+  const R* Tr = reinterpret_cast<const R*>(F.T) + row;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int64_t o = smp<VEC>(c, lane);
+    ld_vec<VEC>(Tr + o, ti + c * VEC);
+    yb[c] = ld_bytes<VEC>((MODEL == REC_KINSYM ? F.ys : F.xs) + row + o);
+    if constexpr (MODEL == REC_KINSYM) xb[c] = ld_bytes<VEC>(F.xs + row + o);
+  }
+}
+
+// Screened scoring runs as two kernels.  k_kink settles every side whose
+// kink test is decided by the fast sums and writes the zero gains; it keeps
+// only the resident r_i row, sign words and the prefetched screen data in
+// registers, so many waves fit per SIMD and many j rows are in flight.  The
+// rest (a few percent of the pairs) go to a queue, and k_exact scores them
+// with the full arithmetic.  Queue entry: pair index | QA (side i <- j, or
+// the whole Ising pair) | QB (side j <- i of the kinetic search).
+constexpr uint32_t QA = 1u << 30, QB = 1u << 31, QIDX = QA - 1;
+
+template <class R, int NPL, int MODEL>
+__global__ __launch_bounds__(256) void k_kink(Fields F, WTable W, int64_t P,
+                                              const int32_t* __restrict__ I,
+                                              const int32_t* __restrict__ J,
+                                              const int32_t* __restrict__ Smap,
+                                              const uint32_t* __restrict__ slot, int owned,
+                                              double* __restrict__ gain_out,
+                                              double* __restrict__ w_out,
+                                              double* __restrict__ ovf, uint64_t cache_cap,
+                                              int32_t* err, int ppw, uint32_t* __restrict__ queue,
+                                              int64_t* qn, int64_t qcap, int64_t* work) {
+  constexpr bool SYM = MODEL == REC_KINSYM;
   const int lane = rec_lane();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE;
   int64_t p0 = wave * ppw;
@@ -612,16 +673,19 @@ __global__ __launch_bounds__(256) void k_score_scr(Fields F, WTable W, double la
       }
     }
   }
-  Lane<R, NPL> L;
-  JScr<NPL, SYM> nx;
+  LaneR<R, NPL> L;
+  JScr<NPL, SYM> nx, nx2;   // screen data of the next two pairs, in flight
   int cur = -1;
   Work wk;
+  uint32_t mine = 0;   // lane q: queue entry of the wave's pair q (0: none)
   uint64_t todo = __ballot(lane < np && li != SKIP);
-  if (todo) {
-    int q0 = __ffsll((unsigned long long)todo) - 1;
-    int i0 = rec_uni(__shfl(li, q0, REC_WAVE)), j0 = rec_uni(__shfl(lj, q0, REC_WAVE));
-    if (pair_ok(i0, j0, F.N)) fetch_scr<NPL, SYM>(F, j0, nx, lane);
-  }
+  auto prefetch = [&](uint64_t bits, JScr<NPL, SYM>& dst) {
+    const int qq = __ffsll((unsigned long long)bits) - 1;
+    int ii = rec_uni(__shfl(li, qq, REC_WAVE)), jj = rec_uni(__shfl(lj, qq, REC_WAVE));
+    if (pair_ok(ii, jj, F.N)) fetch_scr<NPL, SYM>(F, jj, dst, lane);
+  };
+  if (todo) prefetch(todo, nx);
+  if (todo & (todo - 1)) prefetch(todo & (todo - 1), nx2);
   while (todo) {
     const int q = __ffsll((unsigned long long)todo) - 1;
     todo &= todo - 1;
@@ -629,11 +693,8 @@ __global__ __launch_bounds__(256) void k_score_scr(Fields F, WTable W, double la
     int i = rec_uni(__shfl(li, q, REC_WAVE)), j = rec_uni(__shfl(lj, q, REC_WAVE));
     double w0 = rec_uni(__shfl(lw, q, REC_WAVE));
     JScr<NPL, SYM> rw = nx;
-    if (todo) {
-      const int q1 = __ffsll((unsigned long long)todo) - 1;
-      int i1 = rec_uni(__shfl(li, q1, REC_WAVE)), j1 = rec_uni(__shfl(lj, q1, REC_WAVE));
-      if (pair_ok(i1, j1, F.N)) fetch_scr<NPL, SYM>(F, j1, nx, lane);
-    }
+    nx = nx2;
+    if (todo & (todo - 1)) prefetch(todo & (todo - 1), nx2);
     uint64_t o = slot ? (uint64_t)(slot[p] & ~OWNER) : (uint64_t)p;
     double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
     if (!pair_ok(i, j, F.N)) {
@@ -644,82 +705,142 @@ __global__ __launch_bounds__(256) void k_score_scr(Fields F, WTable W, double la
       }
       continue;
     }
-    if (i != cur) { load_i<R, NPL, MODEL>(F, i, L, lane); cur = i; ++wk.iloads; }
-    PairOut r;
+    if (i != cur) { load_i_r<R, NPL, MODEL>(F, i, L, lane); cur = i; ++wk.iloads; }
+    R sa = R(0);
+    float sb = 0.f;
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      sa += ((rw.xw >> k) & 1u) ? L.ri[k] : -L.ri[k];
+      const float h = h_at(rw.hw, k);
+      sb += ((L.xw >> k) & 1u) ? h : -h;
+    }
+    bool na, nb = false;
     if constexpr (MODEL == REC_ISING) {
-      bool need = true;
-      if (w0 == 0.0) {
-        float sc = 0.f;
-#pragma unroll
-        for (int k = 0; k < NPL; ++k) {
-          float xi = (float)L.xi[k];
-          sc = fmaf(sgn_at(rw.xw, k), xi - (float)L.ti[k], sc);
-          sc = fmaf(xi, h_at(rw.hw, k), sc);
-        }
-        need = fabs(rec_wave_sum_dpp((double)sc)) > F.scr;
-      }
+      na = w0 != 0.0 || fabs(rec_wave_sum_dpp((double)sa + (double)sb)) > F.scr;
       ++wk.pairs;
-      if (!need) {
-        ++wk.screened;
-        r.gain = 0.0;
-        r.w = 0.0;
-        r.w0 = 0.0;
-      } else {
-        ++wk.tfetch;
-        R tj[NPL];
-        fetch_t<R, NPL>(F, j, tj, lane);
-        float s = 0.f;
-        R a = R(0), a2 = R(0);
-#pragma unroll
-        for (int k = 0; k < NPL; ++k) {
-          float xj = sgn_at(rw.xw, k);
-          R u = (R)xj * L.ti[k];
-          L.u[k] = u;
-          a += u;
-          R v = L.xi[k] * tj[k];
-          L.v[k] = v;
-          a2 += v;
-          s += xj * (float)L.xi[k];
-        }
-        double phi0 = rec_wave_sum_dpp(2.0 * (double)s - ((double)a + (double)a2));
-        r = solve_ising<R, NPL, true>(L.u, L.v, phi0, s, w0, lambda, F.M, F.Mp, wk);
-      }
+      if (!na) ++wk.screened;
     } else {
       const double w0b = rec_uni(__shfl(lw2, q, REC_WAVE));
-      // direction i <- j: exact, from the signs of x_j and the resident row i
-      float s1 = 0.f;
-      R a = R(0);
-#pragma unroll
-      for (int k = 0; k < NPL; ++k) {
-        float xj = sgn_at(rw.xw, k);
-        R u = (R)xj * L.ti[k];
-        L.u[k] = u;
-        a += u;
-        s1 += xj * (float)L.xi[k];
+      na = w0 != 0.0 || fabs(rec_wave_sum_dpp((double)sa)) > F.scra;
+      nb = w0b != 0.0 || fabs(rec_wave_sum_dpp((double)sb)) > F.scr;
+      wk.pairs += 2;
+      wk.screened += (na ? 0 : 1) + (nb ? 0 : 1);
+    }
+    if (!na && !nb) {
+      if (lane == 0) {
+        *dst = 0.0;
+        if (w_out) w_out[p] = 0.0;
       }
-      double pa = rec_wave_sum_dpp((double)s1 - (double)a);
-      // direction j <- i: screen first
-      bool need_b = true;
-      if (w0b == 0.0) {
-        float sc = 0.f;
+    } else if (lane == q) {
+      mine = (uint32_t)p | (na ? QA : 0u) | (nb ? QB : 0u);
+    }
+  }
+  // one atomic per wave for its queued pairs
+  const int64_t pos = rec_append(qn, mine != 0u);
+  if (pos >= 0) {
+    if (pos < qcap) queue[pos] = mine;
+    else atomicOr(err, 512);
+  }
+  if (lane == 0 && work) {
+    const int64_t M = F.M, rs = sizeof(R);
+    const int64_t items = SYM ? wk.pairs / 2 : wk.pairs;
+    const int64_t sbytes = (M + 7) / 8 * (SYM ? 2 : 1) + 2 * M;   // signs + fp16 residuals
+    wk.bytes = items * (16 + (slot ? 4 : 0) + sbytes) + wk.iloads * (rs * M + M + (M + 7) / 8);
+    wk.flush(work, wave);
+  }
+}
+
+// The queued pairs, in contiguous ranges per wave (consecutive entries
+// usually share i, whose exact rows are then loaded once).
+template <class R, int NPL, int MODEL>
+__global__ __launch_bounds__(256) void k_exact(Fields F, WTable W, double lambda,
+                                               const int32_t* __restrict__ I,
+                                               const int32_t* __restrict__ J,
+                                               const int32_t* __restrict__ Smap,
+                                               const uint32_t* __restrict__ slot,
+                                               double* __restrict__ gain_out,
+                                               double* __restrict__ w_out,
+                                               double* __restrict__ ovf, uint64_t cache_cap,
+                                               const uint32_t* __restrict__ queue,
+                                               const int64_t* __restrict__ qn, int64_t qcap,
+                                               int64_t* work) {
+  constexpr bool SYM = MODEL == REC_KINSYM;
+  constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  const int lane = rec_lane();
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / REC_WAVE);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE;
+  int64_t n = *qn;
+  if (n > qcap) n = qcap;
+  const int64_t per = (n + nwaves - 1) / nwaves;
+  const int64_t e0 = wave * per, e1 = e0 + per < n ? e0 + per : n;
+  Work wk;
+  R ti[NPL], wv[NPL];
+  int yb[CH], xb[CH];
+  int cur = -1;
+  for (int64_t e = e0; e < e1; ++e) {
+    const uint32_t ent = queue[e];
+    const int64_t p = ent & QIDX;
+    const bool na = (ent & QA) != 0, nb = (ent & QB) != 0;
+    const int i = rec_uni(I[p]);
+    int j = J[p];
+    if (Smap) j = Smap[j];
+    j = rec_uni(j);
+    uint64_t o = slot ? (uint64_t)(slot[p] & ~OWNER) : (uint64_t)p;
+    double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
+    if (i != cur) { load_i_exact<R, NPL, MODEL>(F, i, ti, yb, xb, lane); cur = i; ++wk.iloads; }
+    const uint32_t xw = F.xq[(int64_t)j * REC_WAVE + lane];
+    PairOut r;
+    if constexpr (MODEL == REC_ISING) {
+      const double w0 = rec_uni(lookup_w(W, i, j, false));
+      ++wk.tfetch;
+      R u[NPL];
+      fetch_t<R, NPL>(F, j, wv, lane);
+      float s = 0.f;
+      R a = R(0), a2 = R(0);
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          const int qq = c * VEC + k;
+          float xj = sgn_at(xw, qq);
+          float xi = byte_at(yb[c], k);
+          R uu = (R)xj * ti[qq];
+          u[qq] = uu;
+          a += uu;
+          R v = (R)xi * wv[qq];
+          wv[qq] = v;
+          a2 += v;
+          s += xj * xi;
+        }
+      double phi0 = rec_wave_sum_dpp(2.0 * (double)s - ((double)a + (double)a2));
+      r = solve_ising<R, NPL, true>(u, wv, phi0, s, w0, lambda, F.M, F.Mp, wk);
+    } else {
+      const double w0 = rec_uni(lookup_w(W, i, j, true));
+      const double w0b = rec_uni(lookup_w(W, j, i, true));
+      PairOut ra, rb;
+      ra.gain = 0.0; ra.w = 0.0; ra.w0 = w0;
+      rb.gain = 0.0; rb.w = 0.0; rb.w0 = w0b;
+      if (na) {
+        float s1 = 0.f;
+        R a = R(0);
 #pragma unroll
         for (int c = 0; c < CH; ++c)
 #pragma unroll
-          for (int k = 0; k < VEC; ++k) sc = fmaf(byte_at(L.xin[c], k), h_at(rw.hw, c * VEC + k), sc);
-        need_b = fabs(rec_wave_sum_dpp((double)sc)) > F.scr;
+          for (int k = 0; k < VEC; ++k) {
+            const int qq = c * VEC + k;
+            float xj = sgn_at(xw, qq);
+            R uu = (R)xj * ti[qq];
+            wv[qq] = uu;
+            a += uu;
+            s1 += xj * byte_at(yb[c], k);
+          }
+        double pa = rec_wave_sum_dpp((double)s1 - (double)a);
+        ra = solve_ising<R, NPL, false>(wv, wv, pa, s1, w0, lambda, F.M, F.Mp, wk);
       }
-      wk.pairs += 2;
-      PairOut ra = solve_ising<R, NPL, false>(L.u, L.u, pa, s1, w0, lambda, F.M, F.Mp, wk);
-      PairOut rb;
-      rb.gain = 0.0;
-      rb.w = 0.0;
-      rb.w0 = w0b;
-      if (!need_b) {
-        ++wk.screened;
-      } else {
+      if (nb) {
         ++wk.tfetch;
-        R tj[NPL];
-        fetch_t<R, NPL>(F, j, tj, lane);
+        const uint32_t yw = F.yq[(int64_t)j * REC_WAVE + lane];
+        fetch_t<R, NPL>(F, j, wv, lane);
         float s2 = 0.f;
         R b = R(0);
 #pragma unroll
@@ -727,14 +848,14 @@ __global__ __launch_bounds__(256) void k_score_scr(Fields F, WTable W, double la
 #pragma unroll
           for (int k = 0; k < VEC; ++k) {
             const int qq = c * VEC + k;
-            float xi = byte_at(L.xin[c], k);
-            R v = (R)xi * tj[qq];
-            L.v[qq] = v;
+            float xi = byte_at(xb[c], k);
+            R v = (R)xi * wv[qq];
+            wv[qq] = v;
             b += v;
-            s2 += xi * sgn_at(rw.yw, qq);
+            s2 += xi * sgn_at(yw, qq);
           }
         double pb = rec_wave_sum_dpp((double)s2 - (double)b);
-        rb = solve_ising<R, NPL, false>(L.v, L.v, pb, s2, w0b, lambda, F.M, F.Mp, wk);
+        rb = solve_ising<R, NPL, false>(wv, wv, pb, s2, w0b, lambda, F.M, F.Mp, wk);
       }
       r = rb.gain > ra.gain ? rb : ra;
     }
@@ -747,10 +868,7 @@ __global__ __launch_bounds__(256) void k_score_scr(Fields F, WTable W, double la
   }
   if (lane == 0 && work) {
     const int64_t M = F.M, rs = sizeof(R);
-    const int64_t items = SYM ? wk.pairs / 2 : wk.pairs;
-    const int64_t sb = (M + 7) / 8 * (SYM ? 2 : 1) + 2 * M;       // signs + fp16 residuals
-    wk.bytes = items * (16 + (slot ? 4 : 0) + sb) + wk.tfetch * rs * M +
-               wk.iloads * (rs * M + M * (SYM ? 2 : 1));
+    wk.bytes = wk.tfetch * rs * M + wk.iloads * (rs * M + M * (SYM ? 2 : 1)) + (e1 > e0 ? (e1 - e0) * 24 : 0);
     wk.flush(work, wave);
   }
 }
@@ -837,16 +955,46 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
   double* ovf = C ? C->ovf : nullptr;
   uint64_t cap = C ? (C->mask + 1) : 0;
   int64_t* ev = ctx->work;
-  // Ising and the kinetic search read the j side through the residual screen
+  if constexpr (MODEL == REC_ISING || MODEL == REC_KINSYM) {
+    // settled sides in k_kink, the queue of the rest in k_exact (chunks of at
+    // most the queue's capacity)
+    int64_t* qn = ctx->counter + 13;
+    const int64_t qcap = ctx->scr_qcap;
+    const int64_t exact_blocks = 2048;
+    for (int64_t c0 = 0; c0 < P; c0 += qcap) {
+      const int64_t pc = P - c0 < qcap ? P - c0 : qcap;
+      const int64_t cw = (pc + ppw - 1) / ppw, cb = (cw * REC_WAVE + 255) / 256;
+      const int32_t* Ic = I + c0;
+      const int32_t* Jc = J + c0;
+      const uint32_t* sc = slot ? slot + c0 : nullptr;
+      double* gc = slot ? gain_out : gain_out + c0;
+      double* wc = w_out ? w_out + c0 : nullptr;
+      REC_HIP(hipMemsetAsync(qn, 0, sizeof(int64_t), ctx->stream));
 #define REC_SC(NPL)                                                                              \
-  if constexpr (MODEL == REC_ISING || MODEL == REC_KINSYM)                                       \
-    hipLaunchKernelGGL((k_score_scr<R, NPL, MODEL>), dim3(blocks), dim3(256), 0, ctx->stream,    \
-                       ctx->F, ctx->W, ctx->cfg.lambda, P, I, J, Smap, slot, owned, gain_out,    \
-                       w_out, ovf, cap, ctx->err_flag, ppw, ev);                                 \
-  else                                                                                           \
-    hipLaunchKernelGGL((k_score<R, NPL, MODEL>), dim3(blocks), dim3(256), 0, ctx->stream,        \
-                       ctx->F, ctx->W, ctx->cfg.lambda, P, I, J, Smap, slot, owned, gain_out,    \
-                       w_out, ovf, cap, ctx->err_flag, ppw, ev)
+      hipLaunchKernelGGL((k_kink<R, NPL, MODEL>), dim3(cb), dim3(256), 0, ctx->stream, ctx->F,   \
+                         ctx->W, pc, Ic, Jc, Smap, sc, owned, gc, wc, ovf, cap, ctx->err_flag,   \
+                         ppw, ctx->scr_queue, qn, qcap, ev);                                     \
+      hipLaunchKernelGGL((k_exact<R, NPL, MODEL>), dim3(exact_blocks), dim3(256), 0, ctx->stream, \
+                         ctx->F, ctx->W, ctx->cfg.lambda, Ic, Jc, Smap, sc, gc, wc, ovf, cap,    \
+                         ctx->scr_queue, qn, qcap, ev)
+      switch (ctx->F.npl) {
+        case 1: REC_SC(1); break;
+        case 2: REC_SC(2); break;
+        case 4: REC_SC(4); break;
+        case 8: REC_SC(8); break;
+        case 16: REC_SC(16); break;
+        case 32: REC_SC(32); break;
+        default: ctx->err = "unsupported sample count"; return REC_E_INVAL;
+      }
+#undef REC_SC
+    }
+    REC_HIP(hipGetLastError());
+    return REC_OK;
+  }
+#define REC_SC(NPL)                                                                              \
+  hipLaunchKernelGGL((k_score<R, NPL, MODEL>), dim3(blocks), dim3(256), 0, ctx->stream,          \
+                     ctx->F, ctx->W, ctx->cfg.lambda, P, I, J, Smap, slot, owned, gain_out,      \
+                     w_out, ovf, cap, ctx->err_flag, ppw, ev)
   switch (ctx->F.npl) {
     case 1: REC_SC(1); break;
     case 2: REC_SC(2); break;

@@ -293,6 +293,89 @@ __global__ __launch_bounds__(BT) void k_cand(CandArgs P, int64_t a0, int64_t a1,
   if (pass == 0 && tid == 0) cnt[a] = s_cnt;
 }
 
+// Single pass (NNDescent): one block per node collects the node's distinct
+// candidates in LDS (at most lcap = min(4k^2, n-1): |U(b)| <= 2k), reserves
+// their space with one atomic on a shared cursor, then writes and claims
+// them.  off[a]/cnt[a] locate the node's run; the order of the runs depends
+// on scheduling, which no result depends on (lists rank by (gain, index),
+// every pair's score is the same bits whichever node claims it).
+__global__ __launch_bounds__(BT) void k_cand_once(CandArgs P, int64_t a0, int64_t a1, int lcap,
+                                                  int64_t* cnt, int64_t* off, int64_t* cursor,
+                                                  int64_t cap, int32_t* cand_v, int32_t* cand_gi,
+                                                  uint32_t* cand_slot, ClaimArgs A) {
+  extern __shared__ uint32_t sm[];
+  const int64_t a = a0 + blockIdx.x;
+  if (a >= a1) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & (REC_WAVE - 1);
+  const int64_t words = (P.n + 31) / 32;
+  uint32_t* bm = sm;
+  int32_t* ul = reinterpret_cast<int32_t*>(sm + words);   // U(a): at most 2k entries
+  int32_t* lb = ul + 2 * P.k;                              // the node's candidates
+  __shared__ int32_t s_cnt;
+  __shared__ int32_t s_nu;
+  __shared__ long long s_base;
+  for (int64_t w = tid; w < words; w += BT) bm[w] = 0;
+  if (tid == 0) s_cnt = 0;
+  __syncthreads();
+  if (tid == 0) atomicOr(&bm[a >> 5], 1u << (a & 31));
+  for (int c = tid; c < P.k; c += BT) {
+    int b = P.Gidx[a * P.k + c];
+    atomicOr(&bm[b >> 5], 1u << (b & 31));
+  }
+  const int nu = u_size(P, a);
+  for (int c = tid; c < nu; c += BT) ul[c] = u_get(P, a, c);
+  if (tid == 0) s_nu = nu;
+  __syncthreads();
+  const uint64_t lt = lane ? (~0ULL >> (64 - lane)) : 0ULL;
+  const int span = 2 * P.k;
+  const int64_t total = (int64_t)s_nu * span;
+  const int64_t rounds = (total + BT - 1) / BT;
+  for (int64_t r = 0; r < rounds; ++r) {
+    const int64_t q = r * BT + tid;
+    int v = -1;
+    if (q < total) {
+      int bi = (int)(q / span), c = (int)(q % span);
+      int b = ul[bi];
+      if (c < u_size(P, b)) v = u_get(P, b, c);
+    }
+    bool fresh = false;
+    if (v >= 0) {
+      uint32_t bit = 1u << (v & 31);
+      fresh = !(atomicOr(&bm[v >> 5], bit) & bit);
+    }
+    uint64_t mask = __ballot(fresh);
+    int wbase = 0;
+    if (lane == 0 && mask) wbase = atomicAdd(&s_cnt, (int)__popcll(mask));
+    wbase = __shfl(wbase, 0, REC_WAVE);
+    if (fresh) {
+      int pos = wbase + __popcll(mask & lt);
+      if (pos < lcap) lb[pos] = v;
+      else atomicOr(A.err, 128);
+    }
+  }
+  __syncthreads();
+  const int nc = s_cnt < lcap ? s_cnt : lcap;
+  if (tid == 0) {
+    long long b = (long long)atomicAdd((unsigned long long*)cursor, (unsigned long long)nc);
+    if (b + nc > cap) { atomicOr(A.err, 16); b = -1; }
+    s_base = b;
+    off[a] = b < 0 ? 0 : b;
+    cnt[a] = b < 0 ? 0 : nc;
+  }
+  __syncthreads();
+  const long long base = s_base;
+  if (base < 0) return;
+  const int ga = P.S[a];
+  for (int c = tid; c < nc; c += BT) {
+    const int v = lb[c];
+    const int64_t pos = base + c;
+    cand_v[pos] = v;
+    cand_gi[pos] = ga;
+    cand_slot[pos] = claim_owned(A, ga, P.S[v]);
+  }
+}
+
 // ---------------------------------------------------------------- merge --
 // G2[a] = top-k of G[a] (unless start_empty) and the candidates of a; one
 // wave per node, list kept sorted in LDS; adds |G2[a] \ G[a]| to *delta.
@@ -617,6 +700,7 @@ struct Search {
   int64_t* d_delta;
   int64_t* d_pool_n;
   int64_t* d_tmp;
+  int64_t* d_cur;
   int64_t nnd_iters = 0;
   int levels = 0;
   int64_t screened = 0;
@@ -627,6 +711,7 @@ struct Search {
     d_delta = c->counter + 5;
     d_pool_n = c->counter + 7;
     d_tmp = c->counter + 8;
+    d_cur = c->counter + 14;
     A.C = c->C;
     A.ts_i = c->ts_i;
     A.ts_j = c->ts_j;
@@ -662,6 +747,7 @@ struct Search {
     if (e & 2) { ctx->err = "W table full (increase max_nnz)"; return REC_E_NOMEM; }
     if (e & 64) { ctx->err = "internal: duplicate neighbour in a merged list"; return REC_E_NUMERIC; }
     if (e & 256) { ctx->err = "screen candidates exceed the candidate buffer"; return REC_E_NOMEM; }
+    if (e & 512) { ctx->err = "internal: exact-scoring queue overflow"; return REC_E_NUMERIC; }
     if (e & 128) { ctx->err = "internal: candidate passes disagree"; return REC_E_NUMERIC; }
     if (e) { ctx->err = "device error flag " + std::to_string(e); return REC_E_NUMERIC; }
     return REC_OK;
@@ -728,6 +814,41 @@ struct Search {
                            level, it, ctx->inoff, ctx->inoff_cnt, ctx->sb.klo[0]);
         hipLaunchKernelGGL(k_in_select, dim3(n), dim3(REC_WAVE), 0, s, n, k, ctx->inoff,
                            ctx->sb.klo[0], ctx->in_src, ctx->capcnt);
+      }
+      // NNDescent with the node's candidates fitting LDS: one pass per chunk
+      const int64_t lcap = std::min<int64_t>(4 * (int64_t)k * k, n - 1);
+      const size_t once_lds = (size_t)words * 4 + (size_t)(2 * k + lcap) * 4;
+      if (mode == 0 && once_lds <= 64 * 1024) {
+        hipMemsetAsync(d_delta, 0, sizeof(int64_t), s);
+        const int64_t per = std::max<int64_t>(1, ctx->cand_cap / lcap);
+        for (int64_t a0 = 0; a0 < n; a0 += per) {
+          const int64_t a1 = std::min(n, a0 + per);
+          hipMemsetAsync(d_cur, 0, sizeof(int64_t), s);
+          hipLaunchKernelGGL(k_cand_once, dim3(a1 - a0), dim3(BT), once_lds, s, P, a0, a1, (int)lcap,
+                             ctx->cnt, ctx->off, d_cur, ctx->cand_cap, ctx->cand_v, ctx->cand_gi,
+                             ctx->cand_slot, A);
+          int64_t nch = 0;
+          if ((st = get(d_cur, &nch)) != REC_OK) return st;
+          if (nch > ctx->cand_cap) { ctx->err = "candidate buffer too small"; return REC_E_NOMEM; }
+          if (ctx->sur_mode != 0 &&
+              (st = rec_sur_filter(ctx, nch, ctx->cand_gi, ctx->cand_v, S, ctx->cand_slot,
+                                   ctx->sur_mode == 1 ? 1 : 0)) != REC_OK) return st;
+          if ((st = rec_launch_score_owned(ctx, nch, ctx->cand_gi, ctx->cand_v, S, ctx->cand_slot,
+                                           &ctx->C)) != REC_OK) return st;
+          if (ctx->sur_mode != 0 && (st = rec_sur_count(ctx, nch, ctx->cand_slot)) != REC_OK) return st;
+          hipLaunchKernelGGL(k_merge, dim3(a1 - a0), dim3(REC_WAVE), merge_lds, s, a0, a1, k, 0,
+                             ctx->Gidx, ctx->Ggain, ctx->Gidx2, ctx->Ggain2, ctx->cnt, ctx->off,
+                             (int64_t)0, ctx->cand_v, ctx->cand_slot, ctx->C, d_delta, 0,
+                             ctx->err_flag);
+        }
+        if ((st = check_err()) != REC_OK) return st;
+        std::swap(ctx->Gidx, ctx->Gidx2);
+        std::swap(ctx->Ggain, ctx->Ggain2);
+        *iters = it + 1;
+        int64_t delta = 0;
+        if ((st = get(d_delta, &delta)) != REC_OK) return st;
+        if ((double)delta < ctx->cfg.nnd_eps * (double)k * (double)n) break;
+        continue;
       }
       // count distinct candidates per node, then offsets
       hipLaunchKernelGGL(k_cand<0>, dim3(n), dim3(BT), cand_lds, s, P, (int64_t)0, n, ctx->cnt,
