@@ -948,8 +948,9 @@ template <class R, int MODEL>
 rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
                           const int32_t* Smap, const uint32_t* slot, int owned, double* gain_out,
                           double* w_out, const Cache* C) {
-  // pairs per wave: owner mode reads 32 candidates of which roughly half are scored
-  const int ppw = owned ? 32 : 8;
+  // pairs per wave: owner mode reads 64 candidates, of which only the owned
+  // (new) pairs are scored: most candidates after the first iteration are cache hits
+  const int ppw = owned ? 64 : 8;
   int64_t waves = (P + ppw - 1) / ppw;
   int64_t blocks = (waves * REC_WAVE + 255) / 256;
   double* ovf = C ? C->ovf : nullptr;

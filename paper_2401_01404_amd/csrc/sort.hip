@@ -1,7 +1,8 @@
 // Stable LSD radix sort of (khi, klo, val) records and an exclusive scan.
 //
 // One pass per 8-bit digit: a 256-bin histogram per tile of 4096 records,
-// one exclusive scan of the digit-major histogram table, and a stable scatter
+// an exclusive scan of the digit-major histogram table (rows, then digit
+// offsets), and a stable scatter
 // that ranks records inside each tile with wave ballots (8 ballots give every
 // lane the set of lanes holding the same digit).  Records in a tile are taken
 // in index order (round r covers records r*256 .. r*256+255), so equal digits
@@ -36,42 +37,72 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t* __restri
   hist[(int64_t)tid * nblocks + blockIdx.x] = h[tid];
 }
 
-// Exclusive scan of a uint32 table with one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ hist, int64_t total) {
-  __shared__ uint32_t part[1024];
-  const int tid = threadIdx.x;
-  int64_t per = (total + 1023) / 1024;
-  int64_t b = (int64_t)tid * per, e = b + per < total ? b + per : total;
-  uint32_t s = 0;
-  for (int64_t k = b; k < e; ++k) s += hist[k];
-  part[tid] = s;
+// Exclusive scan of the digit-major table in two steps: one block per digit
+// scans its row of tile counts (coalesced, 256 at a time) and leaves the row
+// total in rowsum; then one block turns the 256 totals into digit offsets.
+// The scatter adds a digit's offset to its row entry.
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scan_rows(uint32_t* __restrict__ hist,
+                                                             int64_t nblocks,
+                                                             uint32_t* __restrict__ rowsum) {
+  __shared__ uint32_t wsum[RS_THREADS / REC_WAVE];
+  __shared__ uint32_t run;
+  const int tid = threadIdx.x, lane = tid & (REC_WAVE - 1), wave = tid / REC_WAVE;
+  uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
+  if (tid == 0) run = 0;
   __syncthreads();
-  // Hillis-Steele inclusive scan over the 1024 partial sums
-  for (int o = 1; o < 1024; o <<= 1) {
-    uint32_t v = tid >= o ? part[tid - o] : 0u;
+  for (int64_t c0 = 0; c0 < nblocks; c0 += RS_THREADS) {
+    const int64_t k = c0 + tid;
+    const uint32_t v = k < nblocks ? row[k] : 0u;
+    // inclusive scan inside the wave, then across the waves
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < REC_WAVE; o <<= 1) {
+      uint32_t y = __shfl_up(x, o, REC_WAVE);
+      if (lane >= o) x += y;
+    }
+    if (lane == REC_WAVE - 1) wsum[wave] = x;
     __syncthreads();
-    part[tid] += v;
+    uint32_t before = run;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    if (k < nblocks) row[k] = before + x - v;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t t = 0;
+      for (int w = 0; w < RS_THREADS / REC_WAVE; ++w) t += wsum[w];
+      run += t;
+    }
     __syncthreads();
   }
-  uint32_t run = tid ? part[tid - 1] : 0u;
-  for (int64_t k = b; k < e; ++k) {
-    uint32_t v = hist[k];
-    hist[k] = run;
-    run += v;
+  if (tid == 0) rowsum[blockIdx.x] = run;
+}
+
+__global__ __launch_bounds__(256) void k_rs_scan_bins(uint32_t* __restrict__ rowsum) {
+  __shared__ uint32_t sh[256];
+  const int tid = threadIdx.x;
+  const uint32_t v = rowsum[tid];
+  sh[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    uint32_t a = tid >= o ? sh[tid - o] : 0u;
+    __syncthreads();
+    sh[tid] += a;
+    __syncthreads();
   }
+  rowsum[tid] = sh[tid] - v;
 }
 
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     const uint64_t* __restrict__ klo_in, const uint64_t* __restrict__ khi_in,
     const uint32_t* __restrict__ val_in, uint64_t* __restrict__ klo_out,
     uint64_t* __restrict__ khi_out, uint32_t* __restrict__ val_out, int64_t n, int word, int shift,
-    const uint32_t* __restrict__ hist, int64_t nblocks, int use_hi, int use_val) {
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ binoff, int64_t nblocks,
+    int use_hi, int use_val) {
   __shared__ uint32_t base[256];
   __shared__ uint32_t cnt[RS_THREADS / REC_WAVE][256];
   const int tid = threadIdx.x;
   const int wave = tid / REC_WAVE;
   const int lane = tid % REC_WAVE;
-  base[tid] = hist[(int64_t)tid * nblocks + blockIdx.x];
+  base[tid] = hist[(int64_t)tid * nblocks + blockIdx.x] + binoff[tid];
   for (int w = 0; w < RS_THREADS / REC_WAVE; ++w) cnt[w][tid] = 0;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
@@ -197,12 +228,14 @@ rec_status rec_radix_sort(rec_ctx* ctx, int64_t n, const Digit* digits, int nd, 
     hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(RS_THREADS), 0, ctx->stream,
                        ctx->sb.klo[c], ctx->sb.khi[c], n, digits[d].word, digits[d].shift,
                        ctx->sb.hist, nblocks);
-    hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, ctx->stream, ctx->sb.hist,
-                       nblocks * 256);
+    uint32_t* binoff = ctx->sb.hist + 256 * nblocks;   // the table's spare row of 256
+    hipLaunchKernelGGL(k_rs_scan_rows, dim3(256), dim3(RS_THREADS), 0, ctx->stream, ctx->sb.hist,
+                       nblocks, binoff);
+    hipLaunchKernelGGL(k_rs_scan_bins, dim3(1), dim3(256), 0, ctx->stream, binoff);
     hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(RS_THREADS), 0, ctx->stream,
                        ctx->sb.klo[c], ctx->sb.khi[c], ctx->sb.val[c], ctx->sb.klo[1 - c],
                        ctx->sb.khi[1 - c], ctx->sb.val[1 - c], n, digits[d].word,
-                       digits[d].shift, ctx->sb.hist, nblocks, use_hi, 1);
+                       digits[d].shift, ctx->sb.hist, binoff, nblocks, use_hi, 1);
     c = 1 - c;
   }
   *cur = c;
