@@ -641,7 +641,7 @@ __device__ __forceinline__ void load_i_exact(const Fields& F, int i, R (&ti)[NPL
 constexpr uint32_t QA = 1u << 30, QB = 1u << 31, QIDX = QA - 1;
 
 template <class R, int NPL, int MODEL>
-__global__ __launch_bounds__(256) void k_kink(Fields F, WTable W, int64_t P,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_kink(Fields F, WTable W, int64_t P,
                                               const int32_t* __restrict__ I,
                                               const int32_t* __restrict__ J,
                                               const int32_t* __restrict__ Smap,
@@ -649,13 +649,25 @@ __global__ __launch_bounds__(256) void k_kink(Fields F, WTable W, int64_t P,
                                               double* __restrict__ gain_out,
                                               double* __restrict__ w_out,
                                               double* __restrict__ ovf, uint64_t cache_cap,
-                                              int32_t* err, int ppw, uint32_t* __restrict__ queue,
-                                              int64_t* qn, int64_t qcap, int64_t* work) {
+                                              int32_t* err, int ppw, int groups,
+                                              uint32_t* __restrict__ queue, int64_t* qn,
+                                              int64_t qcap, int64_t* work) {
   constexpr bool SYM = MODEL == REC_KINSYM;
   const int lane = rec_lane();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE;
-  int64_t p0 = wave * ppw;
-  if (p0 >= P) return;
+  // a wave walks `groups` consecutive groups of ppw slots (owner mode: most
+  // slots are cache hits, so one group holds few pairs; the i row and the
+  // wave's set-up are shared by the groups)
+  const int64_t wbeg = wave * ppw * groups;
+  if (wbeg >= P) return;
+  LaneR<R, NPL> L;
+  JScr<NPL, SYM> nx;   // screen data of the next pair, in flight
+  int cur = -1;
+  Work wk;
+  for (int g = 0; g < groups; ++g) {
+  uint32_t mine = 0;   // lane q: queue entry of the group's pair q (0: none)
+  const int64_t p0 = wbeg + (int64_t)g * ppw;
+  if (p0 >= P) break;
   int np = (int)(p0 + ppw < P ? ppw : P - p0);
   int li = -1, lj = -1;
   double lw = 0.0, lw2 = 0.0;
@@ -673,11 +685,6 @@ __global__ __launch_bounds__(256) void k_kink(Fields F, WTable W, int64_t P,
       }
     }
   }
-  LaneR<R, NPL> L;
-  JScr<NPL, SYM> nx, nx2;   // screen data of the next two pairs, in flight
-  int cur = -1;
-  Work wk;
-  uint32_t mine = 0;   // lane q: queue entry of the wave's pair q (0: none)
   uint64_t todo = __ballot(lane < np && li != SKIP);
   auto prefetch = [&](uint64_t bits, JScr<NPL, SYM>& dst) {
     const int qq = __ffsll((unsigned long long)bits) - 1;
@@ -685,7 +692,6 @@ __global__ __launch_bounds__(256) void k_kink(Fields F, WTable W, int64_t P,
     if (pair_ok(ii, jj, F.N)) fetch_scr<NPL, SYM>(F, jj, dst, lane);
   };
   if (todo) prefetch(todo, nx);
-  if (todo & (todo - 1)) prefetch(todo & (todo - 1), nx2);
   while (todo) {
     const int q = __ffsll((unsigned long long)todo) - 1;
     todo &= todo - 1;
@@ -693,8 +699,7 @@ __global__ __launch_bounds__(256) void k_kink(Fields F, WTable W, int64_t P,
     int i = rec_uni(__shfl(li, q, REC_WAVE)), j = rec_uni(__shfl(lj, q, REC_WAVE));
     double w0 = rec_uni(__shfl(lw, q, REC_WAVE));
     JScr<NPL, SYM> rw = nx;
-    nx = nx2;
-    if (todo & (todo - 1)) prefetch(todo & (todo - 1), nx2);
+    if (todo) prefetch(todo, nx);
     uint64_t o = slot ? (uint64_t)(slot[p] & ~OWNER) : (uint64_t)p;
     double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
     if (!pair_ok(i, j, F.N)) {
@@ -735,11 +740,12 @@ __global__ __launch_bounds__(256) void k_kink(Fields F, WTable W, int64_t P,
       mine = (uint32_t)p | (na ? QA : 0u) | (nb ? QB : 0u);
     }
   }
-  // one atomic per wave for its queued pairs
+  // one atomic per wave and group for the queued pairs
   const int64_t pos = rec_append(qn, mine != 0u);
   if (pos >= 0) {
     if (pos < qcap) queue[pos] = mine;
     else atomicOr(err, 512);
+  }
   }
   if (lane == 0 && work) {
     const int64_t M = F.M, rs = sizeof(R);
@@ -964,7 +970,9 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
     const int64_t exact_blocks = 2048;
     for (int64_t c0 = 0; c0 < P; c0 += qcap) {
       const int64_t pc = P - c0 < qcap ? P - c0 : qcap;
-      const int64_t cw = (pc + ppw - 1) / ppw, cb = (cw * REC_WAVE + 255) / 256;
+      const int groups = owned ? 4 : 1;
+      const int64_t span = (int64_t)ppw * groups;
+      const int64_t cw = (pc + span - 1) / span, cb = (cw * REC_WAVE + 255) / 256;
       const int32_t* Ic = I + c0;
       const int32_t* Jc = J + c0;
       const uint32_t* sc = slot ? slot + c0 : nullptr;
@@ -974,7 +982,7 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
 #define REC_SC(NPL)                                                                              \
       hipLaunchKernelGGL((k_kink<R, NPL, MODEL>), dim3(cb), dim3(256), 0, ctx->stream, ctx->F,   \
                          ctx->W, pc, Ic, Jc, Smap, sc, owned, gc, wc, ovf, cap, ctx->err_flag,   \
-                         ppw, ctx->scr_queue, qn, qcap, ev);                                     \
+                         ppw, groups, ctx->scr_queue, qn, qcap, ev);                             \
       hipLaunchKernelGGL((k_exact<R, NPL, MODEL>), dim3(exact_blocks), dim3(256), 0, ctx->stream, \
                          ctx->F, ctx->W, ctx->cfg.lambda, Ic, Jc, Smap, sc, gc, wc, ovf, cap,    \
                          ctx->scr_queue, qn, qcap, ev)
