@@ -53,6 +53,25 @@ FLOPS_LOAD, FLOPS_MOMENT, FLOPS_EVAL, FLOPS_LOG = 5, 8, 8, 3
 PEAK_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
+# HBM traffic of the pair-score kernels (k_kink + k_exact, or k_score) per
+# algorithmic byte, from two rocprofv3 --pmc runs (FETCH_SIZE, then
+# WRITE_SIZE) of `bench.py --workload W --steps 6 --warmup 0 --no-cpu`, each
+# scaled by a 1 GiB device copy (`bench.py --copy-probe 1024`: FETCH_SIZE
+# reads 0.5x the bytes copied, WRITE_SIZE 1.0x).  Valid only for the score
+# kernel source it was measured on: `traffic` is null once that file changes.
+TRAFFIC = {
+    "C4": {"source_sha256": "d2223f25323d3d7c770349d9dca534e7fc7919d19dd373331e979719c34d0242",
+           "hbm_over_algorithmic": 1.1321,
+           "measured_hbm_bytes_per_launch": 1.7071e+10},
+}
+
+
+def score_source_sha():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2401_01404_amd", "csrc", "score.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
 
 def cpu_baseline(w, lam, seconds):
     """The FP64 oracle scoring random pairs of the workload at W = 0."""
@@ -152,6 +171,10 @@ def main():
     tflops = flops / (score_ms / 1e3) / 1e12 if score_ms > 0 else None
     nbytes = work["bytes"]
     achieved = nbytes / (score_ms / 1e3) / 1e9 if score_ms > 0 else None
+    tr = TRAFFIC.get(args.workload)
+    traffic = None
+    if tr and tr["source_sha256"] == score_source_sha() and launches > 0:
+        traffic = tr["hbm_over_algorithmic"] * nbytes / launches
     line = {
         "metric": "pair-score evals/s (exact FindBest scores per second of GCD sweep wall time)",
         "value": value,
@@ -170,7 +193,9 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
-                     "traffic": None,
+                     "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (measured HBM / algorithmic bytes x "
+                                     "this run's algorithmic bytes per launch)",
                      "kernel": "k_score_scr / k_score (pair score)",
                      "kernel_ms_avg": score_ms / max(launches, 1), "launches": launches,
                      "bytes_per_launch": nbytes / max(launches, 1),

@@ -506,3 +506,85 @@ def test_screen_sweeps_track_oracle_gauss():
         d_or, obj_or = O.gcd_sweep(w.N, "exhaustive")
         st = C.sweep("screen")
         assert abs(st["objective"] - obj_or) <= 1e-9 * abs(obj_or), (s, st, obj_or)
+
+
+# ------------------------------------------------------------ edge cases --
+
+@pytest.mark.parametrize("model", ["ising", "kinetic", "gauss"])
+@pytest.mark.parametrize("M", [1, 3, 65, 129, 1000])
+def test_scores_ragged_sample_counts(model, M):
+    """Every lane layout (1, 2, 4, 8, 16 samples per lane) and a ragged tail:
+    all pairs of a small problem against the oracle, FP64 and FP32."""
+    N = 40
+    if model == "ising":
+        w = synth.ising_er(N, M, 3.0, 0.4, 0.1, seed=20 + M)
+    elif model == "kinetic":
+        w = synth.kinetic_er(N, M, 3.0, 0.3, seed=20 + M)
+    else:
+        w = synth.gauss_er(N, max(M, 2), 3.0, 0.2, 1e-3, seed=20 + M)
+    lam = oracle.default_lambda(w.X, model)
+    O = oracle.Oracle(w.X, model, lam)
+    if model == "kinetic":
+        I, J = np.nonzero(~np.eye(N, dtype=bool))
+    else:
+        I, J = np.triu_indices(N, 1)
+    I, J = I.astype(np.int32), J.astype(np.int32)
+    go, _ = O.score_pairs(I, J)
+    for prec in ("fp64", "fp32"):
+        C = ctx_for(w, lam, prec)
+        g, _ = C.score_pairs(I, J)
+        ok = close(g.cpu().numpy(), go, RTOL[prec], w.M)
+        assert ok.all(), (model, M, prec, np.flatnonzero(~ok)[:5])
+
+
+def test_two_nodes_and_constant_node():
+    """N = 2 (one pair), and a node whose samples are all +1 (theta clamped at
+    8, its conditional nearly deterministic): scores, FindBest and a sweep
+    match the oracle."""
+    rng = np.random.default_rng(5)
+    X = np.where(rng.random((2, 200)) < 0.5, 1, -1).astype(np.int8)
+    lam = 1.0
+    O = oracle.Oracle(X, "ising", lam)
+    import torch
+    import paper_2401_01404_amd as rec
+    C = rec.Context(torch.as_tensor(X).cuda(), "ising", lam, prec="fp64", kappa=0.5)
+    g, _ = C.score_pairs([0], [1])
+    go, _ = O.score_pairs(np.array([0], np.int32), np.array([1], np.int32))
+    assert close(g.cpu().numpy(), go, 1e-10, 200).all()
+    for search in ("exhaustive", "nndescent"):
+        I, J, G, _ = C.find_best(1, search)
+        assert len(I) == 1 and int(I[0]) == 0 and int(J[0]) == 1
+    # constant node
+    w = synth.ising_er(30, 300, 3.0, 0.4, 0.1, seed=6)
+    X = w.X.copy()
+    X[7, :] = 1
+    lam = oracle.default_lambda(X, "ising")
+    O = oracle.Oracle(X, "ising", lam)
+    C = rec.Context(torch.as_tensor(X).cuda(), "ising", lam, prec="fp64")
+    _, _, _, tho = O.get_model()
+    _, _, _, th = C.get_model()
+    assert abs(th.cpu().numpy()[7] - tho[7]) <= 1e-12 and tho[7] == 8.0
+    I, J = np.triu_indices(30, 1)
+    I, J = I.astype(np.int32), J.astype(np.int32)
+    go, _ = O.score_pairs(I, J)
+    g, _ = C.score_pairs(I, J)
+    assert close(g.cpu().numpy(), go, 1e-10, 300).all()
+    d_or, obj_or = O.gcd_sweep(30, "exhaustive")
+    st = C.sweep("exhaustive")
+    assert abs(st["objective"] - obj_or) <= 1e-9 * abs(obj_or)
+
+
+def test_empty_inputs():
+    """Zero pairs to score, and find_best / sweep on a problem with no
+    positive gain (lambda huge): empty results, unchanged objective."""
+    w = synth.config("C1")
+    import torch
+    import paper_2401_01404_amd as rec
+    C = rec.Context(torch.as_tensor(w.X).cuda(), "ising", 1e9, prec="fp32")
+    g, _ = C.score_pairs(np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert len(g) == 0
+    obj0 = C.objective()
+    I, J, G, _ = C.find_best(50, "exhaustive")
+    assert np.all(G.cpu().numpy() == 0)
+    st = C.sweep("nndescent")
+    assert st["accepted"] == 0 and abs(st["objective"] - obj0) <= 1e-9 * abs(obj0)
