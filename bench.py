@@ -196,7 +196,7 @@ def main():
                      "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (measured HBM / algorithmic bytes x "
                                      "this run's algorithmic bytes per launch)",
-                     "kernel": "k_score_scr / k_score (pair score)",
+                     "kernel": "pair score: k_kink + k_exact (k_score for directed and Gaussian pairs)",
                      "kernel_ms_avg": score_ms / max(launches, 1), "launches": launches,
                      "bytes_per_launch": nbytes / max(launches, 1),
                      "pairs_scored": scored, "bytes_per_pair": nbytes / max(scored, 1),
