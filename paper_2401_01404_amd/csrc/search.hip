@@ -54,12 +54,69 @@ struct ClaimArgs {
   int directed;
 };
 
+// Score-cache keys carry, in bits the pair ids leave free (ids < 2^20), the
+// search level + 1 at which each endpoint last took the pair as a candidate:
+// bits 56..63 for the smaller id, 24..31 for the larger.  A node that meets a
+// pair it already merged at this level skips it: its list only improved
+// since, so a pair that did not enter then cannot enter now [Alg. 4], and one
+// that did is in the list.  Key comparisons mask the tags.
+constexpr uint64_t REC_TAG_MASK = 0xFF000000FF000000ULL;
+
+// Insert key (untagged) if absent; *ins tells whether this call created it.
+__device__ __forceinline__ int64_t cache_insert(uint64_t* keys, uint64_t mask, uint64_t key,
+                                                bool* ins) {
+  uint64_t s = rec_hash_slot(key, mask);
+  *ins = false;
+  for (int p = 0; p < REC_MAX_PROBE; ++p) {
+    uint64_t k = __atomic_load_n(&keys[s], __ATOMIC_RELAXED);
+    if (k == REC_EMPTY) {
+      uint64_t prev = atomicCAS((unsigned long long*)&keys[s], (unsigned long long)REC_EMPTY,
+                                (unsigned long long)key);
+      if (prev == REC_EMPTY) { *ins = true; return (int64_t)s; }
+      k = prev;
+    }
+    if ((k & ~REC_TAG_MASK) == key) return (int64_t)s;
+    s = (s + 1) & mask;
+  }
+  return -1;
+}
+
+// The same, setting this endpoint's level tag; *seen tells whether the tag
+// already held `tag` (the endpoint took the pair as a candidate at this level).
+__device__ __forceinline__ int64_t cache_insert_tag(uint64_t* keys, uint64_t mask, uint64_t key,
+                                                    int shift, uint64_t tag, bool* ins, bool* seen) {
+  uint64_t s = rec_hash_slot(key, mask);
+  const uint64_t tmask = 0xFFull << shift, tval = tag << shift;
+  *ins = false;
+  *seen = false;
+  for (int p = 0; p < REC_MAX_PROBE; ++p) {
+    uint64_t k = __atomic_load_n(&keys[s], __ATOMIC_RELAXED);
+    if (k == REC_EMPTY) {
+      uint64_t prev = atomicCAS((unsigned long long*)&keys[s], (unsigned long long)REC_EMPTY,
+                                (unsigned long long)(key | tval));
+      if (prev == REC_EMPTY) { *ins = true; return (int64_t)s; }
+      k = prev;
+    }
+    if ((k & ~REC_TAG_MASK) == key) {
+      while ((k & tmask) != tval) {
+        uint64_t prev = atomicCAS((unsigned long long*)&keys[s], (unsigned long long)k,
+                                  (unsigned long long)((k & ~tmask) | tval));
+        if (prev == k) return (int64_t)s;
+        k = prev;   // the other endpoint changed its tag: retry
+      }
+      *seen = true;
+      return (int64_t)s;
+    }
+    s = (s + 1) & mask;
+  }
+  return -1;
+}
+
 // May be called from any subset of a wave's lanes; the cursors are advanced
 // once per wave.
 __device__ uint32_t claim(const ClaimArgs& A, int i, int j) {
   bool ins = false;
-  int64_t s = rec_hash_insert(A.C.keys, A.C.mask, rec_pair_key(i, j, A.directed != 0),
-                              REC_MAX_PROBE, &ins);
+  int64_t s = cache_insert(A.C.keys, A.C.mask, rec_pair_key(i, j, A.directed != 0), &ins);
   uint64_t slot = s >= 0 ? (uint64_t)s : 0;
   int64_t o = rec_append(A.ovf_n, s < 0);         // no free slot: overflow area
   if (o >= 0) {
@@ -82,10 +139,14 @@ __device__ uint32_t claim(const ClaimArgs& A, int i, int j) {
 constexpr uint32_t REC_OWNER = 0x80000000u;
 constexpr uint32_t REC_SLOT_BAD = 0x7fffffffu;
 
-__device__ uint32_t claim_owned(const ClaimArgs& A, int i, int j) {
+// Candidate claim by node i of pair (i, j) at search level `level`.
+// *seen: i already took this pair as a candidate at this level (skip it).
+__device__ uint32_t claim_owned(const ClaimArgs& A, int i, int j, int level, bool* seen) {
   bool ins = false;
-  int64_t s = rec_hash_insert(A.C.keys, A.C.mask, rec_pair_key(i, j, A.directed != 0),
-                              REC_MAX_PROBE, &ins);
+  const uint64_t key = rec_pair_key(i, j, A.directed != 0);
+  const int shift = i < j ? 56 : 24;
+  int64_t s = cache_insert_tag(A.C.keys, A.C.mask, key, shift, (uint64_t)((level + 1) & 0xff), &ins,
+                               seen);
   int64_t o = rec_append(A.ovf_n, s < 0);         // no free slot: overflow area (rare)
   if (s >= 0) return (uint32_t)s | (ins ? REC_OWNER : 0u);
   if (o >= A.C.ovf_cap) { atomicOr(A.err, 16); return REC_SLOT_BAD; }
@@ -220,7 +281,7 @@ __device__ __forceinline__ int u_get(const CandArgs& P, int64_t b, int c) {
 }
 
 template <int pass>
-__global__ __launch_bounds__(BT) void k_cand(CandArgs P, int64_t a0, int64_t a1,
+__global__ __launch_bounds__(BT) void k_cand(CandArgs P, int level, int64_t a0, int64_t a1,
                                              int64_t* cnt, const int64_t* off, int64_t base,
                                              int32_t* cand_v, int32_t* cand_gi,
                                              uint32_t* cand_slot, ClaimArgs A) {
@@ -283,9 +344,11 @@ __global__ __launch_bounds__(BT) void k_cand(CandArgs P, int64_t a0, int64_t a1,
       int64_t pos = obase + wbase + __popcll(mask & lt);
       if (pos - obase >= cnt[a]) atomicOr(A.err, 128);   // count pass disagrees
       else {
-        cand_v[pos] = v;
+        bool seen;
+        const uint32_t sw = claim_owned(A, ga, P.S[v], level, &seen);
+        cand_v[pos] = seen ? -1 : v;   // -1: merged before at this level
         cand_gi[pos] = ga;
-        cand_slot[pos] = claim_owned(A, ga, P.S[v]);
+        cand_slot[pos] = sw;
       }
     }
   }
@@ -299,7 +362,7 @@ __global__ __launch_bounds__(BT) void k_cand(CandArgs P, int64_t a0, int64_t a1,
 // them.  off[a]/cnt[a] locate the node's run; the order of the runs depends
 // on scheduling, which no result depends on (lists rank by (gain, index),
 // every pair's score is the same bits whichever node claims it).
-__global__ __launch_bounds__(BT) void k_cand_once(CandArgs P, int64_t a0, int64_t a1, int lcap,
+__global__ __launch_bounds__(BT) void k_cand_once(CandArgs P, int level, int64_t a0, int64_t a1, int lcap,
                                                   int64_t* cnt, int64_t* off, int64_t* cursor,
                                                   int64_t cap, int32_t* cand_v, int32_t* cand_gi,
                                                   uint32_t* cand_slot, ClaimArgs A) {
@@ -370,13 +433,94 @@ __global__ __launch_bounds__(BT) void k_cand_once(CandArgs P, int64_t a0, int64_
   for (int c = tid; c < nc; c += BT) {
     const int v = lb[c];
     const int64_t pos = base + c;
-    cand_v[pos] = v;
+    bool seen;
+    const uint32_t sw = claim_owned(A, ga, P.S[v], level, &seen);
+    cand_v[pos] = seen ? -1 : v;   // -1: merged before at this level
     cand_gi[pos] = ga;
-    cand_slot[pos] = claim_owned(A, ga, P.S[v]);
+    cand_slot[pos] = sw;
   }
 }
 
 // ---------------------------------------------------------------- merge --
+// Lists of k <= 64 entries (NNDescent iterations): lane c holds entry c of the
+// sorted list.  Candidates come 64 at a time; those better than the current
+// k-th are merged at once: each entry's new rank = the entries of both sets
+// that beat it (all distinct: candidates exclude the list and each other), and
+// the entries ranked below k are placed through LDS.  No per-candidate shift.
+__global__ __launch_bounds__(REC_WAVE) void k_merge_small(int64_t a0, int64_t a1, int k,
+                                                          const int32_t* Gidx, const double* Ggain,
+                                                          int32_t* G2idx, double* G2gain,
+                                                          const int64_t* cnt, const int64_t* off,
+                                                          int64_t base, const int32_t* cand_v,
+                                                          const uint32_t* cand_slot, Cache C,
+                                                          int64_t* delta, int32_t* err) {
+  __shared__ double sg[REC_WAVE];
+  __shared__ int32_t sv[REC_WAVE];
+  __shared__ uint8_t sn[REC_WAVE];
+  const int64_t a = a0 + blockIdx.x;
+  if (a >= a1) return;
+  const int lane = threadIdx.x;
+  const bool in_list = lane < k;
+  double lg = in_list ? Ggain[a * k + lane] : 0.0;
+  int li = in_list ? Gidx[a * k + lane] : -1;
+  int lnew = 0;
+  const int64_t nc = cnt[a];
+  const int64_t o0 = off[a] - base;
+  for (int64_t q0 = 0; q0 < nc; q0 += REC_WAVE) {
+    const int64_t q = q0 + lane;
+    double cg = 0.0;
+    int cv = -1;
+    if (q < nc) {
+      cv = cand_v[o0 + q];
+      if (cv >= 0) cg = slot_gain(C, cand_slot[o0 + q]);
+    }
+    const double wg = rec_dpp::lane_read(lg, k - 1);
+    const int wi = rec_dpp::lane_read(li, k - 1);
+    // a NaN gain marks a pair the learned proposal left unscored: never listed
+    const bool cand = cv >= 0 && cg == cg && better(cg, cv, wg, wi);
+    uint64_t sur = __ballot(cand);
+    if (!sur) continue;
+    // ranks: list entry c is beaten by the c entries before it and by the
+    // candidates that beat it; a candidate by the list entries and candidates
+    // that beat it
+    int rl = lane, rc = 0;
+    for (int c = 0; c < k; ++c) {
+      const double g = rec_dpp::lane_read(lg, c);
+      const int v = rec_dpp::lane_read(li, c);
+      rc += (cand && better(g, v, cg, cv)) ? 1 : 0;
+    }
+    uint64_t bits = sur;
+    while (bits) {
+      const int src = __ffsll((unsigned long long)bits) - 1;
+      bits &= bits - 1;
+      const double g = rec_dpp::lane_read(cg, src);
+      const int v = rec_dpp::lane_read(cv, src);
+      if (in_list && better(g, v, lg, li)) ++rl;
+      if (cand && src != lane && better(g, v, cg, cv)) ++rc;
+    }
+    if (in_list && rl < k) { sg[rl] = lg; sv[rl] = li; sn[rl] = (uint8_t)lnew; }
+    if (cand && rc < k) { sg[rc] = cg; sv[rc] = cv; sn[rc] = 1; }
+    __syncthreads();
+    if (in_list) { lg = sg[lane]; li = sv[lane]; lnew = sn[lane]; }
+    __syncthreads();
+  }
+  // invariant: a list never holds the same neighbour twice
+  int dupl = 0;
+  for (int c = 0; c < k; ++c) {
+    const int v = rec_dpp::lane_read(li, c);
+    dupl |= (in_list && lane != c && v == li) ? 1 : 0;
+  }
+  dupl = rec_wave_sum(dupl);
+  if (dupl && lane == 0) atomicOr(err, 64);
+  if (in_list) {
+    G2gain[a * k + lane] = lg;
+    G2idx[a * k + lane] = li;
+  }
+  const int nnew = rec_wave_sum(in_list ? lnew : 0);
+  if (lane == 0 && nnew) atomicAdd((unsigned long long*)delta, (unsigned long long)nnew);
+}
+
+// ---- general merge (any k; also the first fill and exact-KNN lists) ----
 // G2[a] = top-k of G[a] (unless start_empty) and the candidates of a; one
 // wave per node, list kept sorted in LDS; adds |G2[a] \ G[a]| to *delta.
 __global__ __launch_bounds__(REC_WAVE) void k_merge(int64_t a0, int64_t a1, int k, int start_empty,
@@ -411,7 +555,8 @@ __global__ __launch_bounds__(REC_WAVE) void k_merge(int64_t a0, int64_t a1, int 
     int v = 0;
     if (valid) {
       v = cand_v[o0 + q];
-      g = slot_gain(C, cand_slot[o0 + q]);
+      valid = v >= 0;   // a pair this node merged before at this level
+      if (valid) g = slot_gain(C, cand_slot[o0 + q]);
     }
     double wg = count == k ? lg[k - 1] : 0.0;
     int wi = count == k ? li[k - 1] : 0;
@@ -824,7 +969,7 @@ struct Search {
         for (int64_t a0 = 0; a0 < n; a0 += per) {
           const int64_t a1 = std::min(n, a0 + per);
           hipMemsetAsync(d_cur, 0, sizeof(int64_t), s);
-          hipLaunchKernelGGL(k_cand_once, dim3(a1 - a0), dim3(BT), once_lds, s, P, a0, a1, (int)lcap,
+          hipLaunchKernelGGL(k_cand_once, dim3(a1 - a0), dim3(BT), once_lds, s, P, level, a0, a1, (int)lcap,
                              ctx->cnt, ctx->off, d_cur, ctx->cand_cap, ctx->cand_v, ctx->cand_gi,
                              ctx->cand_slot, A);
           int64_t nch = 0;
@@ -836,10 +981,16 @@ struct Search {
           if ((st = rec_launch_score_owned(ctx, nch, ctx->cand_gi, ctx->cand_v, S, ctx->cand_slot,
                                            &ctx->C)) != REC_OK) return st;
           if (ctx->sur_mode != 0 && (st = rec_sur_count(ctx, nch, ctx->cand_slot)) != REC_OK) return st;
-          hipLaunchKernelGGL(k_merge, dim3(a1 - a0), dim3(REC_WAVE), merge_lds, s, a0, a1, k, 0,
-                             ctx->Gidx, ctx->Ggain, ctx->Gidx2, ctx->Ggain2, ctx->cnt, ctx->off,
-                             (int64_t)0, ctx->cand_v, ctx->cand_slot, ctx->C, d_delta, 0,
-                             ctx->err_flag);
+          if (k <= REC_WAVE)
+            hipLaunchKernelGGL(k_merge_small, dim3(a1 - a0), dim3(REC_WAVE), 0, s, a0, a1, k,
+                               ctx->Gidx, ctx->Ggain, ctx->Gidx2, ctx->Ggain2, ctx->cnt, ctx->off,
+                               (int64_t)0, ctx->cand_v, ctx->cand_slot, ctx->C, d_delta,
+                               ctx->err_flag);
+          else
+            hipLaunchKernelGGL(k_merge, dim3(a1 - a0), dim3(REC_WAVE), merge_lds, s, a0, a1, k, 0,
+                               ctx->Gidx, ctx->Ggain, ctx->Gidx2, ctx->Ggain2, ctx->cnt, ctx->off,
+                               (int64_t)0, ctx->cand_v, ctx->cand_slot, ctx->C, d_delta, 0,
+                               ctx->err_flag);
         }
         if ((st = check_err()) != REC_OK) return st;
         std::swap(ctx->Gidx, ctx->Gidx2);
@@ -851,7 +1002,7 @@ struct Search {
         continue;
       }
       // count distinct candidates per node, then offsets
-      hipLaunchKernelGGL(k_cand<0>, dim3(n), dim3(BT), cand_lds, s, P, (int64_t)0, n, ctx->cnt,
+      hipLaunchKernelGGL(k_cand<0>, dim3(n), dim3(BT), cand_lds, s, P, level, (int64_t)0, n, ctx->cnt,
                          ctx->off, (int64_t)0, ctx->cand_v, ctx->cand_gi, ctx->cand_slot, A);
       hipMemsetAsync(ctx->cnt + n, 0, sizeof(int64_t), s);
       if ((st = rec_exclusive_scan(ctx, ctx->cnt, ctx->off, n + 1, nullptr)) != REC_OK) return st;
@@ -866,7 +1017,7 @@ struct Search {
         while (a1 < n && hoff[a1 + 1] - hoff[a0] <= ctx->cand_cap) ++a1;
         if (hoff[a1] - hoff[a0] > ctx->cand_cap) { ctx->err = "candidate buffer too small"; return REC_E_NOMEM; }
         int64_t base = hoff[a0];
-        hipLaunchKernelGGL(k_cand<1>, dim3(a1 - a0), dim3(BT), cand_lds, s, P, a0, a1, ctx->cnt,
+        hipLaunchKernelGGL(k_cand<1>, dim3(a1 - a0), dim3(BT), cand_lds, s, P, level, a0, a1, ctx->cnt,
                            ctx->off, base, ctx->cand_v, ctx->cand_gi, ctx->cand_slot, A);
         const int64_t nch = hoff[a1] - hoff[a0];
         // learned proposal: only the best-ranked fraction keeps its owner bit

@@ -616,6 +616,7 @@ __global__ void k_sur_collect(Cache C, uint64_t seed, int zbits, int32_t* __rest
   uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t cap = C.mask + 1;
   uint64_t key = s < cap ? C.keys[s] : REC_EMPTY;
+  if (key != REC_EMPTY) key &= ~0xFF000000FF000000ULL;   // drop the search-level tags
   double g = key != REC_EMPTY ? C.vals[s] : 0.0;
   const bool ok = key != REC_EMPTY && g == g;
   const bool pos = ok && g > 0.0;
