@@ -65,12 +65,16 @@ typedef enum { REC_X_INT8 = 0, REC_X_FP32 = 1 } rec_xtype;
 typedef enum {
   REC_SEARCH_NNDESCENT = 0,   /* FindBest [Alg. 3] over NNDescent [Alg. 4]      */
   REC_SEARCH_EXHAUSTIVE = 1,  /* all pairs scored exactly, best m kept         */
-  REC_SEARCH_SURROGATE = 2,   /* reserved: learned proposal ahead of NNDescent  */
+  REC_SEARCH_SURROGATE = 2,   /* learned proposal ahead of NNDescent            */
   REC_SEARCH_EXACT_KNN = 3,   /* FindBest [Alg. 3] over exhaustive KNN lists    */
-  REC_SEARCH_SCREEN = 4       /* Gaussian only: every pair screened at once by a
-                                 BF16 MFMA contraction with a proven error bound,
-                                 survivors rescored exactly; returns the
-                                 exhaustive search's positive-gain top m       */
+  REC_SEARCH_SCREEN = 4       /* every pair screened at once by an MFMA
+                                 contraction of samples with residuals (the
+                                 gradient at the current state, Gaussian: BF16,
+                                 Ising/kinetic: FP16) under proven bounds on
+                                 each pair's gain; survivors and current
+                                 couplings rescored exactly.  Returns the
+                                 exhaustive search's positive-gain top m
+                                 (kinetic: ordered pairs).                     */
 } rec_search;
 
 typedef struct {

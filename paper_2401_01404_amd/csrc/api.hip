@@ -204,6 +204,11 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
     x->sc_sq = a.take<float>(N);
     x->sc_hist = a.take<uint32_t>(4096);
     x->sc_tau = a.take<float>(64);
+  } else {
+    x->sc_l1 = a.take<float>(N);
+    x->sc_cv = a.take<float>(N);
+    x->sc_hist = a.take<uint32_t>(4096);
+    x->sc_tau = a.take<float>(64);
   }
 }
 

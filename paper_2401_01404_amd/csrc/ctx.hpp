@@ -132,12 +132,15 @@ struct rec_ctx {
   // kinetic model inside FindBest: pairs are unordered and scored by the
   // larger of the two directed gains
   bool sym_search = false;
-  // screening contraction (Gaussian): bf16 operands N x sc_kp, row norms,
-  // theta^2, |x|^2, histogram and threshold
+  // screening contraction, Gaussian: bf16 operands N x sc_kp, row norms,
+  // theta^2, |x|^2; all models: histogram and threshold
   __bf16* sc_a = nullptr;
   __bf16* sc_b = nullptr;
   int sc_kp = 0;
   float *sc_nrm = nullptr, *sc_th2 = nullptr, *sc_sq = nullptr, *sc_tau = nullptr;
+  // Ising / kinetic screen: per node |r_i|_1 and curvature sum (1 - t^2)
+  float *sc_l1 = nullptr, *sc_cv = nullptr;
+  int64_t sc_retries = 0;   // screens that needed the second collect pass
   uint32_t* sc_hist = nullptr;
   // learned proposal (surrogate.hip): projection bits, sketches, parameters,
   // Adam state, bf16 weight copies, training work arrays

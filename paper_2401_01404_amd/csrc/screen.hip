@@ -1,9 +1,9 @@
-// Exhaustive screening contraction on the matrix cores (Gaussian model).
+// Exhaustive screening contraction on the matrix cores.
 //
-// For every pair at once, a_ij = x_i . r_j + r_i . x_j is one entry of
-// S = A B^T with A_i = [x_i | r_i] and B_j = [r_j | x_j] (K = 2M, padded to a
-// multiple of 32 with zeros), r the residuals of the Gaussian pseudolikelihood
-// [App. A].  The closed-form gain of a pair at w0 = 0 is
+// Gaussian model: for every pair at once, a_ij = x_i . r_j + r_i . x_j is one
+// entry of S = A B^T with A_i = [x_i | r_i] and B_j = [r_j | x_j] (K = 2M,
+// padded to a multiple of 32 with zeros), r the residuals of the Gaussian
+// pseudolikelihood [App. A].  The closed-form gain of a pair at w0 = 0 is
 // (|a| - lambda)^2 / (2 b) for |a| > lambda, else 0, with
 // b = theta_i^2 |x_j|^2 + theta_j^2 |x_i|^2 (the score kernel's formula).
 //
@@ -18,7 +18,12 @@
 // g_up >= tau and g_up > 0; they and the current nonzero couplings are then
 // rescored by the exact score kernel.  The result equals the exhaustive
 // search's positive-gain top m: the screen drops no pair that could reach it.
+//
+// Ising and kinetic models: the same two passes over an FP16 contraction of
+// the +-1 samples with the residuals, with gain bounds from the curvature of
+// the log-cosh terms (see the second half of this file).
 #include <math.h>
+#include <string.h>
 
 #include "common.hpp"
 #include "ctx.hpp"
@@ -195,13 +200,545 @@ __global__ void k_screen_tau(const uint32_t* hist, int64_t target, float* tau) {
   *tau = t;
 }
 
+
+// ---------------------------------------------------------------------------
+// Ising and kinetic models.  The smooth part f(w) of a pair's objective
+// (coupling w, the rest of W fixed) has f'(0) = a, the contraction entry
+//   Ising:   a_ij = x_i . r_j + r_i . x_j   (r = x - tanh h)
+//   kinetic: a_ij = r_i . x_j               (i <- j; r_i = x_{i,t} - tanh h_{i,t-1},
+//                                            x_j = x_{j,t-1})
+// and curvature C(w) = -f''(w) = sum over the affected samples of
+// sech^2(h + w x) with x = +-1.  Since cosh h e^{-|w|} <= cosh(h + w x) <=
+// cosh h e^{|w|},  c e^{-2|w|} <= C(w) <= c e^{2|w|}  with c = C(0) = sum of
+// (1 - tanh^2 h) over those samples (Ising: c_i + c_j; kinetic: c_i).  For a
+// pair with w0 = 0 and e = |a| - lambda > 0, integrating f' twice under these
+// bounds brackets the best gain of the L1-penalised step [Alg. 2, function D]:
+//   (c/4) phi(q) <= gain <= (c/4) psi(q),   q = 2e/c,
+//   phi(q) = (1 + q) ln(1 + q) - q,   psi(q) = q + (1 - q) ln(1 - q)  (q < 1; else no bound),
+// and gain = 0 when |a| <= lambda (the kink test).  a is formed in FP16 on the
+// matrix cores (x = +-1 exact; r rounded to fp16 with relative error 2^-11)
+// with FP32 accumulation, so |a - a_exact| <= ce (|r_i|_1 + |r_j|_1) + el.
+// The two passes then run as for the Gaussian screen: a histogram of the
+// lower bounds gives tau, and every w0 = 0 pair whose upper bound reaches tau
+// goes to the exact score kernel together with the current couplings.  The
+// result equals the exhaustive search's positive-gain top m.
+
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+
+struct KScreenArgs {
+  const int8_t* xs;     // N x Mp input side (+-1, padding 0)
+  const uint16_t* rh;   // N x Mp fp16 residuals (padding 0)
+  int64_t N, Mp;
+  int nsteps;           // k steps of 32: Ising 2 Mp / 32, kinetic Mp / 32
+  const float* l1;      // |r_i|_1, rounded up
+  const float* cv;      // c_i = sum_t (1 - tanh^2 h_it)
+  const float* cvmin;   // min_i c_i (Ising: bounds c_i + c_j from below per row)
+  float lam, ce, el;
+  uint32_t* hist;
+  const float* tau;     // collect threshold
+  const float* hfloor;  // histogram floor (null: none)
+  int32_t* ovf;         // set when a block queue overflowed (the pass is then incomplete)
+  WTable W;
+  int32_t* oi;
+  int32_t* oj;
+  int64_t* cursor;
+  int64_t cap;
+  int32_t* err;
+};
+
+// per node: |r_i|_1 (from the fp16 residuals the contraction reads) and c_i
+template <class R>
+__global__ __launch_bounds__(256) void k_kscreen_prep(Fields F, float* __restrict__ l1,
+                                                      float* __restrict__ cv) {
+  __shared__ double sh[8];
+  const int64_t i = blockIdx.x;
+  const R* T = reinterpret_cast<const R*>(F.T) + i * F.Mp;
+  const uint16_t* rh = F.rh + i * F.Mp;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t k = threadIdx.x; k < F.Mp; k += blockDim.x) {
+    s1 += fabs((double)rec_f16_val(rh[k]));
+    if (k < F.M) { const double t = (double)T[k]; s2 += 1.0 - t * t; }
+  }
+  s1 = rec_wave_sum(s1);
+  s2 = rec_wave_sum(s2);
+  const int w = threadIdx.x / REC_WAVE;
+  if ((threadIdx.x & (REC_WAVE - 1)) == 0) { sh[w] = s1; sh[4 + w] = s2; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < (int)(blockDim.x / REC_WAVE); ++q) { a += sh[q]; b += sh[4 + q]; }
+    l1[i] = (float)(a * (1.0 + 1e-6));
+    cv[i] = (float)b;
+  }
+}
+
+// min_i c_i (one block)
+__global__ __launch_bounds__(1024) void k_ks_cvmin(const float* __restrict__ cv, int64_t N, float* out) {
+  __shared__ float sh[16];
+  float v = __builtin_inff();
+  for (int64_t i = threadIdx.x; i < N; i += 1024) v = fminf(v, cv[i]);
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, REC_WAVE));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = sh[0];
+    for (int q = 1; q < 16; ++q) m = fminf(m, sh[q]);
+    *out = m;
+  }
+}
+
+// lower bound (c/4) phi(q) and upper bound (c/4) psi(q) in float with a
+// relative slack that covers the float evaluation
+__device__ __forceinline__ float kgain_lo(float e, float c) {
+  c *= 1.f + 1e-6f;
+  const float q = 2.f * e / c;
+  float p;
+  if (q <= 1.f)   // alternating series with decreasing terms: stop after a negative one
+    p = q * q * (0.5f - q * (1.f / 6.f - q * (1.f / 12.f - q * (1.f / 20.f))));
+  else
+    p = (1.f + q) * log1pf(q) - q;
+  return 0.25f * c * p * (1.f - 1e-5f);
+}
+
+__device__ __forceinline__ float kgain_up(float e, float c) {
+  c *= 1.f - 1e-6f;
+  const float q = 2.f * e / c;
+  if (q >= 1.f) return __builtin_inff();
+  float p;
+  if (q <= 0.5f)  // positive series q^k / (k (k-1)), tail from k = 6 bounded geometrically
+    p = q * q * (0.5f + q * (1.f / 6.f + q * (1.f / 12.f + q * (1.f / 20.f + q * q / (30.f * (1.f - q))))));
+  else
+    p = q + (1.f - q) * log1pf(-q);
+  return 0.25f * c * p * (1.f + 1e-5f);
+}
+
+// 16 int8 samples (+-1 / 0) -> 16 fp16 values (two 16-byte words)
+__device__ __forceinline__ void x16_to_f16(uint4 v, uint4* lo, uint4* hi) {
+  uint32_t w[4] = {v.x, v.y, v.z, v.w}, o[8];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t a = (w[q] & 0xFFu) | ((w[q] & 0xFF00u) << 8);
+    const uint32_t b = ((w[q] >> 16) & 0xFFu) | ((w[q] >> 8) & 0x00FF0000u);
+    o[2 * q] = ((a & 0x00010001u) * 0x3C00u) | ((a & 0x00800080u) << 8);
+    o[2 * q + 1] = ((b & 0x00010001u) * 0x3C00u) | ((b & 0x00800080u) << 8);
+  }
+  *lo = make_uint4(o[0], o[1], o[2], o[3]);
+  *hi = make_uint4(o[4], o[5], o[6], o[7]);
+}
+
+// Histogram of positive float bounds for the Ising / kinetic screen: 16 bins
+// per octave over [2^-31, 2^33); smaller values are not counted (a threshold
+// of 0 then remains valid), larger ones land in the top bin (whose lower edge
+// still bounds them from below).
+constexpr int KS_BINS = 1024;
+constexpr int KS_EXP0 = 96;   // biased exponent of the lowest bin
+__device__ __forceinline__ int ks_bin(float g) {
+  const int b = (int)(__builtin_bit_cast(uint32_t, g) >> 19) - KS_EXP0 * 16;
+  return b < 0 ? -1 : (b >= KS_BINS ? KS_BINS - 1 : b);
+}
+__host__ __device__ inline float ks_edge(int b) {
+  const uint32_t bits = (uint32_t)(b + KS_EXP0 * 16) << 19;
+  float f;
+  __builtin_memcpy(&f, &bits, 4);
+  return f;
+}
+
+// Tile order.  Hardware hands block b to XCD b % 8; blocks that run together
+// on one XCD should share their operand rows in that XCD's L2.  Logical tiles
+// form super-tiles of 8 x 8 (8 row tiles x 8 column tiles: the ~64 blocks an
+// XCD runs at once), super-tiles are dealt to the XCDs round-robin, and an XCD
+// walks its super-tiles in order.
+struct TileMap {
+  int nbi, nbj;     // row tiles (after sampling) and column tiles
+  int sbj;          // super-tile columns
+  int nS;           // super-tiles
+};
+__device__ __forceinline__ bool ks_tile(const TileMap& T, int b, int* bi, int* bj) {
+  const int x = b & 7, q = b >> 3;
+  const int S = (q >> 6) * 8 + x, w = q & 63;
+  if (S >= T.nS) return false;
+  *bi = (S / T.sbj) * 8 + (w & 7);
+  *bj = (S % T.sbj) * 8 + (w >> 3);
+  return *bi < T.nbi && *bj < T.nbj;
+}
+
+// One 128 x 128 tile of the contraction per block (4 waves of 64 x 64, each
+// 4 x 4 MFMA 16x16x32 blocks).  Operands go global -> registers two k steps
+// ahead of use and registers -> LDS one step ahead (LDS double-buffered), so
+// a load has two steps of MFMA work to arrive.  Ising: tiles on or above the
+// diagonal, k in [0, Mp) pairs x_i with r_j and k in [Mp, 2Mp) r_i with x_j.
+// Kinetic: every tile, rows are targets (r_i), columns sources (x_j).
+// MODE 0: histogram of lower bounds; 1: collect pairs whose upper bound
+// reaches *tau; 2: both.  Row tiles are taken every row_step-th (sampling).
+struct KRegs { uint4 x, r0, r1; };
+
+constexpr int KS_Q = 512;   // per-block queue of elements that passed the cheap tests (LDS)
+
+template <int MODE, int KIN, int ROBUST>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_kscreen(KScreenArgs P, TileMap TM, int row_step) {
+  int bi, bj;
+  if (!ks_tile(TM, blockIdx.x, &bi, &bj)) return;
+  bi *= row_step;
+  if (!KIN && bi > bj) return;
+  constexpr bool HIST = MODE != 1, COLLECT = MODE != 0;
+  __shared__ __attribute__((aligned(16))) _Float16 As[2][SC_T * SC_LD];
+  __shared__ __attribute__((aligned(16))) _Float16 Bs[2][SC_T * SC_LD];
+  __shared__ uint32_t hs[HIST ? KS_BINS : 1];
+  __shared__ uint32_t kq_key[KS_Q];   // bit 31: collect (else histogram); row << 7 | column in the tile
+  __shared__ float kq_e[KS_Q], kq_c[KS_Q];
+  __shared__ int kq_n, kc_n;
+  __shared__ int64_t kbase;
+  const int tid = threadIdx.x, lane = tid & (REC_WAVE - 1), w = tid / REC_WAVE;
+  const int64_t r0 = (int64_t)bi * SC_T, c0 = (int64_t)bj * SC_T;
+  if (HIST)
+    for (int q = tid; q < KS_BINS; q += 256) hs[q] = 0;
+  if (tid == 0) { kq_n = 0; kc_n = 0; }
+  // staging assignment: x chunk (16 samples) = row tid/2, half tid%2;
+  // r chunks (8 samples) = rows q/4, part q%4 for q = tid, tid + 256
+  const int xrow = tid >> 1, xhalf = tid & 1;
+  const int n = P.nsteps;
+  auto load = [&](int s, KRegs& R) {
+    const bool first = !KIN && (int64_t)s * SC_K < P.Mp;
+    const int64_t k = (int64_t)s * SC_K - (KIN || first ? 0 : P.Mp);
+    // x side: A rows in the first half (Ising), else B rows
+    const int64_t gx = (first ? r0 : c0) + xrow;
+    R.x = make_uint4(0u, 0u, 0u, 0u);
+    if (gx < P.N) R.x = *reinterpret_cast<const uint4*>(P.xs + gx * P.Mp + k + xhalf * 16);
+    const int64_t rb = first ? c0 : r0;
+    const int64_t g0 = rb + (tid >> 2), g1 = rb + ((tid + 256) >> 2);
+    R.r0 = R.r1 = make_uint4(0u, 0u, 0u, 0u);
+    if (g0 < P.N) R.r0 = *reinterpret_cast<const uint4*>(P.rh + g0 * P.Mp + k + (tid & 3) * 8);
+    if (g1 < P.N) R.r1 = *reinterpret_cast<const uint4*>(P.rh + g1 * P.Mp + k + (tid & 3) * 8);
+  };
+  auto store = [&](int s, const KRegs& R, int buf) {
+    const bool first = !KIN && (int64_t)s * SC_K < P.Mp;
+    _Float16* Xs = first ? As[buf] : Bs[buf];
+    _Float16* Rs = first ? Bs[buf] : As[buf];
+    uint4 lo, hi;
+    x16_to_f16(R.x, &lo, &hi);
+    *reinterpret_cast<uint4*>(Xs + xrow * SC_LD + xhalf * 16) = lo;
+    *reinterpret_cast<uint4*>(Xs + xrow * SC_LD + xhalf * 16 + 8) = hi;
+    *reinterpret_cast<uint4*>(Rs + (tid >> 2) * SC_LD + (tid & 3) * 8) = R.r0;
+    *reinterpret_cast<uint4*>(Rs + ((tid + 256) >> 2) * SC_LD + (tid & 3) * 8) = R.r1;
+  };
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[m][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  auto compute = [&](int buf) {
+    halfx8 af[4], bf[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      af[m] = *reinterpret_cast<const halfx8*>(As[buf] + (wr + m * 16 + (lane & 15)) * SC_LD + (lane >> 4) * 8);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      bf[q] = *reinterpret_cast<const halfx8*>(Bs[buf] + (wc + q * 16 + (lane & 15)) * SC_LD + (lane >> 4) * 8);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[m], bf[q], acc[m][q], 0, 0, 0);
+  };
+  KRegs R0, R1;
+  load(0, R0);
+  if (n > 1) load(1, R1);
+  store(0, R0, 0);
+  __syncthreads();
+  // step s reads LDS buffer s % 2; registers hold step s + 1 while step s + 2 loads
+  for (int s = 0; s < n; s += 2) {
+    if (s + 2 < n) load(s + 2, R0);
+    compute(0);
+    if (s + 1 < n) store(s + 1, R1, 1);
+    __syncthreads();
+    if (s + 1 >= n) break;
+    if (s + 3 < n) load(s + 3, R1);
+    compute(1);
+    if (s + 2 < n) store(s + 2, R0, 0);
+    __syncthreads();
+  }
+  // Epilogue: lane holds rows 4*(lane/16) + r, column lane % 16 of each
+  // 16x16 block.  Each element first meets per-row and per-column necessary
+  // conditions (a few ALU operations); the rare survivors go to a block
+  // queue in LDS and get the exact bound afterwards.  With q = 2e/c:
+  // (c/4) psi(q) <= e^2 / (2 (c - 2e)), so an upper bound can reach tau only
+  // if e >= sqrt(4 tau^2 + 2 tau c) - 2 tau;  (c/4) phi(q) <= e^2 / (2c), so
+  // a lower bound can reach the floor f only if e >= sqrt(2 f c).  Both grow
+  // with c, and c >= c_i + min c (Ising) or c = c_i (kinetic).
+  const float tau = COLLECT ? *P.tau : 0.f;
+  const float fl = HIST && P.hfloor ? *P.hfloor : 0.f;
+  const float cmin = KIN ? 0.f : *P.cvmin;
+  auto thr_up = [&](float c) {
+    return tau > 0.f ? (sqrtf(4.f * tau * tau + 2.f * tau * c) - 2.f * tau) * (1.f - 1e-4f) : 0.f;
+  };
+  auto thr_lo = [&](float c) { return fl > 0.f ? sqrtf(2.f * fl * c) * (1.f - 1e-4f) : 0.f; };
+  // exact bound of one queued element (histogram or collect)
+  auto settle = [&](bool coll, int i, int j, float e, float c) {
+    if (!coll) {
+      const int hb = ks_bin(kgain_lo(e, c));
+      if (hb >= 0) atomicAdd(&hs[hb], 1u);
+      return;
+    }
+    if (kgain_up(e, c) < tau) return;
+    if (P.W.keys != nullptr) {
+      // a current (nonzero) coupling is rescored from the W list instead
+      const int64_t ws = rec_hash_find(P.W.keys, P.W.mask, rec_pair_key(i, j, KIN != 0), REC_MAX_PROBE);
+      if (ws >= 0 && P.W.vals[ws] != 0.0) return;
+    }
+    if (!ROBUST) {
+      const int p = atomicAdd(&kc_n, 1);   // p < KS_Q: at most one per queued element
+      kq_key[p] = (uint32_t)(i - r0) << 7 | (uint32_t)(j - c0);
+    } else {
+      const int64_t pos = (int64_t)atomicAdd((unsigned long long*)P.cursor, 1ull);
+      if (pos < P.cap) {
+        P.oi[pos] = i;
+        P.oj[pos] = j;
+      }
+    }
+  };
+  auto push = [&](bool coll, int li, int lj, float e, float c) {
+    if (ROBUST) {
+      settle(coll, (int)r0 + li, (int)c0 + lj, e, c);
+      return;
+    }
+    const int p = atomicAdd(&kq_n, 1);
+    if (p < KS_Q) {
+      kq_key[p] = (coll ? 0x80000000u : 0u) | (uint32_t)li << 7 | (uint32_t)lj;
+      kq_e[p] = e;
+      kq_c[p] = c;
+    }
+  };
+  float cl1[4], ccv[4], cu[4], ch[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = c0 + wc + q * 16 + (lane & 15);
+    cl1[q] = j < P.N && !KIN ? P.l1[j] : 0.f;
+    ccv[q] = j < P.N && !KIN ? P.cv[j] : 0.f;
+    cu[q] = KIN ? 0.f : thr_up(ccv[q] + cmin);
+    ch[q] = KIN ? 0.f : thr_lo(ccv[q] + cmin);
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int li = wr + m * 16 + 4 * (lane >> 4) + r;
+      const int64_t i = r0 + li;
+      const float rl1 = i < P.N ? P.l1[i] : 0.f, rcv = i < P.N ? P.cv[i] : 0.f;
+      const float ru = thr_up(rcv + cmin), rh = thr_lo(rcv + cmin);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int lj = wc + q * 16 + (lane & 15);
+        const int64_t j = c0 + lj;
+        const bool ok = KIN ? (i < P.N && j < P.N && i != j) : (i < j && j < P.N);
+        const float aa = fabsf(acc[m][q][r]);
+        const float er = P.ce * (rl1 + cl1[q]) + P.el;
+        if (HIST) {
+          const float e = aa - er - P.lam;
+          if (ok && e > 0.f && e >= rh && e >= ch[q]) push(false, li, lj, e, rcv + ccv[q]);
+        }
+        if (COLLECT) {
+          const float e = aa + er - P.lam;
+          if (ok && e > 0.f && e >= ru && e >= cu[q]) push(true, li, lj, e, rcv + ccv[q]);
+        }
+      }
+    }
+  __syncthreads();
+  if (!ROBUST) {
+    const int nq = min(kq_n, KS_Q);
+    if (tid == 0 && kq_n > KS_Q) atomicOr(P.ovf, 1);
+    // settle the queue; collected pairs are compacted into the queue's
+    // front (each slot is read before any write can reach it: writes go to
+    // slots below the running count of kept entries, reads happen first)
+    uint32_t key[2] = {0u, 0u};
+    float ev[2] = {0.f, 0.f}, cv2[2] = {0.f, 0.f};
+    for (int t0 = 0; t0 < nq; t0 += 512) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int t = t0 + u * 256 + tid;
+        if (t < nq) { key[u] = kq_key[t]; ev[u] = kq_e[t]; cv2[u] = kq_c[t]; }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int t = t0 + u * 256 + tid;
+        if (t < nq)
+          settle((key[u] >> 31) != 0, (int)r0 + (int)((key[u] >> 7) & 127), (int)c0 + (int)(key[u] & 127),
+                 ev[u], cv2[u]);
+      }
+    }
+    if (COLLECT) {
+      __syncthreads();
+      const int nc = kc_n;
+      if (tid == 0 && nc > 0) kbase = (int64_t)atomicAdd((unsigned long long*)P.cursor, (unsigned long long)nc);
+      __syncthreads();
+      for (int t = tid; t < nc; t += 256) {
+        const int64_t pos = kbase + t;
+        if (pos < P.cap) {
+          P.oi[pos] = (int32_t)(r0 + ((kq_key[t] >> 7) & 127));
+          P.oj[pos] = (int32_t)(c0 + (kq_key[t] & 127));
+        }
+      }
+    }
+  }
+  if (HIST) {
+    __syncthreads();
+    for (int q = tid; q < KS_BINS; q += 256)
+      if (hs[q]) atomicAdd(&P.hist[q], hs[q]);
+  }
+}
+
+// tau = lower edge of the bin where the count from the top first reaches
+// target (0 if it never does).  out[0] = tau.
+// floor_out (optional) = tau, the histogram floor of the full pass: bins at
+// or above it are counted exactly, so a proven threshold at or above the
+// collect threshold is found whenever one exists.
+__global__ void k_ks_tau(const uint32_t* hist, int64_t target, float* out, float* floor_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t cum = 0;
+  float t = 0.f;
+  for (int q = KS_BINS - 1; q >= 0; --q) {
+    cum += hist[q];
+    if (cum >= target) { t = ks_edge(q); break; }
+  }
+  *out = t;
+  if (floor_out) *floor_out = t;
+}
+
+}  // namespace
+
+namespace {
+// Ising / kinetic.  A sample of the row tiles (every step-th, step up to
+// KS_SAMPLE) is histogrammed first for an estimate tau_s of the threshold,
+// taken at twice the proportional count so that it errs low; one full pass
+// then histograms the lower bounds from tau_s up and collects at tau_s.  When
+// the full histogram's threshold tau (a proven lower bound on the m-th best
+// gain) is at least tau_s, every pair whose upper bound reaches tau was
+// collected, so the set is complete; otherwise, or when a buffer overflowed,
+// a collect pass at tau runs.
+constexpr int KS_SAMPLE = 16;   // largest sampling step of the row tiles
+
+TileMap tile_map(int nbi, int nbj, int64_t* grid) {
+  TileMap T;
+  T.nbi = nbi;
+  T.nbj = nbj;
+  T.sbj = (nbj + 7) / 8;
+  const int sbi = (nbi + 7) / 8;
+  T.nS = sbi * T.sbj;
+  *grid = (int64_t)((T.nS + 7) / 8) * 8 * 64;
+  return T;
+}
+
+template <int MODE, int ROBUST>
+void launch_ks(rec_ctx* ctx, const KScreenArgs& P, int nbi, int nbj, int row_step) {
+  int64_t grid = 0;
+  const TileMap T = tile_map(nbi, nbj, &grid);
+  if (ctx->cfg.model == REC_KINETIC)
+    hipLaunchKernelGGL((k_kscreen<MODE, 1, ROBUST>), dim3((unsigned)grid), dim3(256), 0, ctx->stream, P, T,
+                       row_step);
+  else
+    hipLaunchKernelGGL((k_kscreen<MODE, 0, ROBUST>), dim3((unsigned)grid), dim3(256), 0, ctx->stream, P, T,
+                       row_step);
+}
+
+rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
+  hipStream_t s = ctx->stream;
+  const int64_t N = ctx->cfg.N;
+  const int kin = ctx->cfg.model == REC_KINETIC;
+  if (ctx->sc_l1 == nullptr || ctx->F.rh == nullptr) { ctx->err = "screen buffers missing"; return REC_E_INVAL; }
+  float* tau_c = ctx->sc_tau;       // threshold the collect pass uses
+  float* tau_f = ctx->sc_tau + 1;   // proven threshold from the full histogram
+  float* floor = ctx->sc_tau + 2;   // histogram floor of the full pass
+  float* cvmin = ctx->sc_tau + 3;
+  if (ctx->fp32)
+    hipLaunchKernelGGL(k_kscreen_prep<float>, dim3(N), dim3(256), 0, s, ctx->F, ctx->sc_l1, ctx->sc_cv);
+  else
+    hipLaunchKernelGGL(k_kscreen_prep<double>, dim3(N), dim3(256), 0, s, ctx->F, ctx->sc_l1, ctx->sc_cv);
+  hipLaunchKernelGGL(k_ks_cvmin, dim3(1), dim3(1024), 0, s, ctx->sc_cv, N, cvmin);
+  KScreenArgs P;
+  P.xs = ctx->F.xs;
+  P.rh = ctx->F.rh;
+  P.N = N;
+  P.Mp = ctx->F.Mp;
+  const int64_t K = kin ? ctx->F.Mp : 2 * ctx->F.Mp;
+  P.nsteps = (int)(K / SC_K);
+  P.l1 = ctx->sc_l1;
+  P.cv = ctx->sc_cv;
+  P.cvmin = cvmin;
+  P.lam = (float)ctx->cfg.lambda;
+  // fp16 rounding of r (and of its float source), fp32 accumulation over K terms
+  P.ce = (float)(std::ldexp(1.0, -11) * (1.0 + std::ldexp(1.0, -10)) + std::ldexp(1.0, -22) +
+                 (double)K * std::ldexp(1.0, -23));
+  // lambda's float rounding, fp16 subnormals, the exact kernel's own rounding
+  P.el = (float)(1e-6 * ctx->cfg.lambda + (double)K * std::ldexp(1.0, -24) + 1e-30);
+  P.W = ctx->W;
+  P.oi = ctx->ts_i;
+  P.oj = ctx->ts_j;
+  P.cursor = ctx->counter + 12;
+  P.cap = ctx->cand_cap;
+  P.err = ctx->err_flag;
+  P.tau = tau_c;
+  P.hfloor = nullptr;
+  int32_t* ovf = (int32_t*)(ctx->sc_tau + 4);
+  P.ovf = ovf;
+  const int nb = (int)((N + SC_T - 1) / SC_T);
+  uint32_t* hist_s = ctx->sc_hist;
+  uint32_t* hist_f = ctx->sc_hist + KS_BINS;
+  REC_HIP(hipMemsetAsync(ctx->sc_hist, 0, 2 * KS_BINS * sizeof(uint32_t), s));
+  REC_HIP(hipMemsetAsync(P.cursor, 0, sizeof(int64_t), s));
+  REC_HIP(hipMemsetAsync(ovf, 0, sizeof(int32_t), s));
+  // sample: every step-th row tile, histogrammed without a floor (inline path)
+  const int step = std::max(1, std::min(KS_SAMPLE, nb / 8));
+  const int nbs = (nb + step - 1) / step;
+  P.hist = hist_s;
+  launch_ks<0, 1>(ctx, P, nbs, nb, step);
+  const int64_t ts = std::max<int64_t>(1, 2 * target / step);
+  hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_s, ts, tau_c, floor);
+  // full pass: histogram from the floor up, collect at tau_c
+  P.hist = hist_f;
+  P.hfloor = floor;
+  launch_ks<2, 0>(ctx, P, nb, nb, 1);
+  hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_f, target, tau_f, (float*)nullptr);
+  REC_HIP(hipGetLastError());
+  int64_t n = 0;
+  float tau[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  REC_HIP(hipMemcpyAsync(&n, P.cursor, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  REC_HIP(hipMemcpyAsync(tau, ctx->sc_tau, 5 * sizeof(float), hipMemcpyDeviceToHost, s));
+  REC_HIP(hipStreamSynchronize(s));
+  int32_t over = 0;
+  memcpy(&over, &tau[4], sizeof(int32_t));
+  // The collected set is complete when the proven threshold is at least the
+  // one used and no block queue overflowed.  Otherwise collect again at the
+  // proven threshold (inline path), first refreshing the histogram without a
+  // floor when the threshold fell below the floor (counts under it are
+  // partial) or a queue overflowed (counts were dropped).
+  if (over || n > ctx->cand_cap || tau[1] < tau[0]) {
+    if (over || tau[1] < tau[2]) {
+      REC_HIP(hipMemsetAsync(hist_f, 0, KS_BINS * sizeof(uint32_t), s));
+      P.hfloor = nullptr;
+      launch_ks<0, 1>(ctx, P, nb, nb, 1);
+      hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_f, target, tau_f, (float*)nullptr);
+    }
+    REC_HIP(hipMemcpyAsync(tau_c, tau_f, sizeof(float), hipMemcpyDeviceToDevice, s));
+    REC_HIP(hipMemsetAsync(P.cursor, 0, sizeof(int64_t), s));
+    launch_ks<1, 1>(ctx, P, nb, nb, 1);
+    REC_HIP(hipGetLastError());
+    REC_HIP(hipMemcpyAsync(&n, P.cursor, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    REC_HIP(hipStreamSynchronize(s));
+    ++ctx->sc_retries;
+  }
+  if (n > ctx->cand_cap) { ctx->err = "screen candidates exceed the candidate buffer"; return REC_E_NOMEM; }
+  *n_out = n;
+  return REC_OK;
+}
 }  // namespace
 
 rec_status rec_screen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
   hipStream_t s = ctx->stream;
   const int64_t N = ctx->cfg.N;
   const int Kp = ctx->sc_kp;
-  if (ctx->sc_a == nullptr) { ctx->err = "the screening contraction needs the Gaussian model"; return REC_E_INVAL; }
+  if (ctx->cfg.model != REC_GAUSS) return kscreen_candidates(ctx, target, n_out);
+  if (ctx->sc_a == nullptr) { ctx->err = "screen buffers missing"; return REC_E_INVAL; }
   if (ctx->fp32)
     hipLaunchKernelGGL(k_screen_prep<float>, dim3(N), dim3(256), 0, s, ctx->F, Kp, ctx->sc_a, ctx->sc_b,
                        ctx->sc_nrm, ctx->sc_th2, ctx->sc_sq);

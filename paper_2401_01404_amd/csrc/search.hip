@@ -1215,15 +1215,12 @@ struct Search {
     return rec_radix_sort(ctx, n, dg, nd, cur);
   }
 
-  // Exhaustive through the screening contraction (Gaussian): candidates from
-  // the MFMA screen plus the current couplings, rescored exactly; the best m
-  // with positive gain are kept (see screen.hip for why none is missed).
+  // Exhaustive through the screening contraction: candidates from the MFMA
+  // screen plus the current couplings, rescored exactly; the best m with
+  // positive gain are kept (see screen.hip for why none is missed).  Kinetic
+  // pairs are ordered, as in the exhaustive search.
   rec_status screen(int64_t m, int64_t* n_out) {
     hipStream_t s = ctx->stream;
-    if (ctx->cfg.model != REC_GAUSS) {
-      ctx->err = "the screening search is defined for the Gaussian model";
-      return REC_E_INVAL;
-    }
     int64_t nnz = 0;
     rec_status st = rec_wtable_compact(ctx, &nnz);
     if (st != REC_OK) return st;
@@ -1245,7 +1242,8 @@ struct Search {
     // keep positive gains only
     if (np > 0)
       hipLaunchKernelGGL(k_ex_append, dim3(gridn(np)), dim3(256), 0, s, I, J, g, np,
-                         __builtin_bit_cast(double, (uint64_t)1), 0, ctx->sb.khi[0], ctx->sb.klo[0],
+                         __builtin_bit_cast(double, (uint64_t)1), ctx->cfg.model == REC_KINETIC ? 1 : 0,
+                         ctx->sb.khi[0], ctx->sb.klo[0],
                          ctx->sb.val[0], d_n, ctx->sb.cap);
     int64_t tot = 0;
     if ((st = get(d_n, &tot)) != REC_OK) return st;

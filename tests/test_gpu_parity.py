@@ -508,6 +508,73 @@ def test_screen_sweeps_track_oracle_gauss():
         assert abs(st["objective"] - obj_or) <= 1e-9 * abs(obj_or), (s, st, obj_or)
 
 
+SCREEN_CASES = {
+    # N = 700 / 600: several 128-row tiles and a ragged one; M = 400 pads to 448
+    "ising": lambda: synth.ising_regular(700, 400, 3, 0.4, seed=11),
+    "kinetic": lambda: synth.kinetic_er(600, 400, 5.0, 0.3, seed=12),
+}
+
+
+def screen_equals_exhaustive(C, m):
+    I, J, G, _ = C.find_best(m, "exhaustive")
+    I2, J2, G2, st = C.find_best(m, "screen")
+    I, J, G = I.cpu().numpy(), J.cpu().numpy(), G.cpu().numpy()
+    npos = int(min((G > 0).sum(), m))
+    assert len(I2) == npos
+    assert np.array_equal(I[:npos], I2.cpu().numpy())
+    assert np.array_equal(J[:npos], J2.cpu().numpy())
+    assert np.array_equal(G[:npos], G2.cpu().numpy())
+    return npos, G2.cpu().numpy()
+
+
+@pytest.mark.parametrize("model", ["ising", "kinetic"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_screen_search_equals_exhaustive(model, prec):
+    """The FP16 MFMA screen with its curvature bounds drops no pair of the top
+    m: the screened search returns exactly the exhaustive search's
+    positive-gain top m (kinetic: ordered pairs), at W = 0 and at W != 0."""
+    w = SCREEN_CASES[model]()
+    lam = oracle.default_lambda(w.X, model)
+    C = ctx_for(w, lam, prec)
+    m = 4 * w.N
+    for state in range(3):
+        npos, G2 = screen_equals_exhaustive(C, m)
+        assert npos > m // 8, npos
+        if prec == "fp64" and state == 0:
+            O = oracle.Oracle(w.X, model, lam)
+            Io, Jo, Go, _ = O.find_best(m, "exhaustive")
+            assert close(G2, Go[:npos], 1e-10, w.M).all()
+        C.sweep("screen")
+
+
+@pytest.mark.parametrize("model", ["ising", "kinetic"])
+def test_screen_sweeps_track_oracle(model):
+    """GCD sweeps over the screened search against the oracle.  The ranked
+    gains equal the oracle's exhaustive top m to 1e-10 relative; the oracle
+    then applies the GPU's E_best in its rank order (the two rank orders may
+    differ inside near-tied gains, and sequential updates of pairs that share
+    a node depend on their order) and refits theta: the objectives agree to
+    1e-9 relative."""
+    w = SCREEN_CASES[model]()
+    lam = oracle.default_lambda(w.X, model)
+    O = oracle.Oracle(w.X, model, lam)
+    C = ctx_for(w, lam, "fp64", kappa=1.0)
+    m = w.N
+    for s in range(3):
+        I, J, G, _ = C.find_best(m, "screen")
+        I, J, G = I.cpu().numpy(), J.cpu().numpy(), G.cpu().numpy()
+        Io, Jo, Go, _ = O.find_best(m, "exhaustive")
+        npos = int((Go > 0).sum())
+        assert len(G) == min(npos, m)
+        assert close(G, Go[:len(G)], 1e-10, w.M).all(), s
+        st = C.sweep("screen")
+        d_or, _ = O.apply_updates(I, J)
+        O.theta_update()
+        obj_or = O.objective()
+        assert abs(st["objective"] - obj_or) <= 1e-9 * abs(obj_or), (s, st, obj_or)
+        assert abs(st["delta"] - d_or) <= 1e-8 * max(1.0, d_or)
+
+
 # ------------------------------------------------------------ edge cases --
 
 @pytest.mark.parametrize("model", ["ising", "kinetic", "gauss"])
