@@ -1,23 +1,30 @@
 #!/usr/bin/env python
-"""Benchmark: GCD sweeps [Alg. 2] with FindBest over NNDescent [Alg. 3, 4] on
-one MI355X, reported as exact pair-score evaluations per second.
+"""Benchmark: GCD sweeps [Alg. 2] on one MI355X.
 
-One step = one full GCD sweep: FindBest of m = kappa N pairs (NNDescent
-lists, U caps, candidate scoring, top-k merges, D+/S' levels, exhaustive base
-case), the coordinate updates of E_best in node-disjoint rounds, the field
-rebuild, the theta refit and the FP64 objective.  W warm-up sweeps run first
-(from W = 0), then K sweeps are timed.  value = exact pair scores computed
-by FindBest during the timed sweeps / their wall time (kinetic model: directed
-scores, two per unordered pair of the symmetrised search).
+One step = one full GCD sweep: the search for the m = kappa N best pairs, the
+coordinate updates of E_best in node-disjoint rounds, the field rebuild, the
+theta refit and the FP64 objective.  W warm-up sweeps run first (from W = 0),
+then K sweeps are timed.
 
-The pair-score kernel is timed live with HIP events on the library's stream
-for the roofline entry.  Its binding roof is HBM: per pair it streams the j
-side's rows (sign words and fp16 residuals for the screen, the tanh row when
-the screen does not settle the pair) and does a few flops per byte.  The
-kernels count the algorithmic bytes they need (indices, scores, the rows
-fetched, at M samples) and achieved = those bytes / kernel time.  The CPU
-oracle is timed on a bounded random sample of pairs of the same workload for
-the cpu_baseline entry.
+Default search (--search screen): every pair of the workload is decided each
+sweep -- its gain is bounded through the FP16 MFMA contraction of the samples
+with the residuals, and the pairs whose upper bound can reach the m-th best
+gain are scored exactly -- so the sweep returns the exhaustive search's top m
+(recall 1).  value = pairs decided / sweep wall time.  The dominant kernel is
+the contraction (matrix cores, FP16 in, FP32 accumulate); its roofline entry
+is its algorithmic flops (2 M per ordered pair, or per unordered pair and
+side) over its event-timed kernel time, against the dense FP16 peak.  After
+the timed sweeps the same state is searched once with FindBest over NNDescent
+[Alg. 3, 4] and once with the screen, and NNDescent's recall of the exact top
+m is reported beside its time.
+
+--search nndescent: FindBest over NNDescent, value = exact pair scores per
+second of sweep wall time; the roofline entry is then the pair-score kernel's
+HBM traffic (algorithmic bytes it counts / its kernel time).
+
+The CPU oracle is timed on a bounded random sample of pairs of the same
+workload for the cpu_baseline entry (exact FP64 scores: one decided pair
+each).
 """
 import argparse
 import json
@@ -52,6 +59,7 @@ FLOPS_LOAD, FLOPS_MOMENT, FLOPS_EVAL, FLOPS_LOG = 5, 8, 8, 3
 # build, so the 157.3 TFLOP/s packed figure is not reachable).
 PEAK_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+PEAK_F16_MFMA_TFLOPS = 2500.0   # dense FP16 matrix-core peak
 
 # HBM traffic of the pair-score kernels (k_kink + k_exact, or k_score) per
 # algorithmic byte, from two rocprofv3 --pmc runs (FETCH_SIZE, then
@@ -66,9 +74,16 @@ TRAFFIC = {
 }
 
 
-def score_source_sha():
+# HBM traffic of the contraction's full pass (k_kscreen<2,...>) per launch,
+# from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
+# `bench.py --workload W --steps 2 --warmup 0 --no-cpu`, scaled by the same
+# 1 GiB copy probe.  Valid only for the source it was measured on.
+TRAFFIC_SCREEN = {}
+
+
+def source_sha(name="score.hip"):
     import hashlib
-    path = os.path.join(ROOT, "paper_2401_01404_amd", "csrc", "score.hip")
+    path = os.path.join(ROOT, "paper_2401_01404_amd", "csrc", name)
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
 
@@ -100,6 +115,27 @@ def cpu_baseline(w, lam, seconds):
                       f"{dt:.1f} s on {cores} threads"}
 
 
+def compare_searches(ctx, torch):
+    """At the current state: FindBest over NNDescent [Alg. 3, 4] and the
+    screened exhaustive search, each timed once (after one untimed call);
+    NNDescent's recall of the exact positive-gain top m."""
+    out = {}
+    res = {}
+    for search in ("screen", "nndescent"):
+        ctx.find_best(ctx.m, search)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        I, J, G, st = ctx.find_best(ctx.m, search)
+        torch.cuda.synchronize()
+        out[f"{search}_find_best_ms"] = (time.perf_counter() - t) * 1e3
+        out[f"{search}_exact_evals"] = st["pair_evals"]
+        res[search] = set(zip(I.cpu().tolist(), J.cpu().tolist()))
+    best = res["screen"]
+    out["exact_top_m"] = len(best)
+    out["nndescent_recall"] = len(best & res["nndescent"]) / max(1, len(best))
+    return out
+
+
 def copy_probe(mib):
     """Plain copies of a known size: each reads and writes mib MiB once."""
     import torch
@@ -120,7 +156,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C4", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--search", default="nndescent", choices=["nndescent", "exhaustive", "exact_knn", "screen"])
+    ap.add_argument("--search", default="screen", choices=["nndescent", "exhaustive", "exact_knn", "screen"])
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the NNDescent-vs-screen comparison after the timed sweeps")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -161,9 +199,12 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     score_ms, launches, work = ctx.kernel_time()
+    scr = ctx.screen_time()
     scored = work["pairs"]
     evals = sum(s["pair_evals"] for s in stats)
-    value = evals / wall
+    screen = args.search == "screen"
+    decided = scr["pairs_decided"]
+    value = (decided if screen else evals) / wall
 
     sides = 2 if w.model == "ising" else 1
     flops = sides * w.M * (FLOPS_LOAD * work["pairs"] + FLOPS_MOMENT * work["moment_passes"]
@@ -173,10 +214,43 @@ def main():
     achieved = nbytes / (score_ms / 1e3) / 1e9 if score_ms > 0 else None
     tr = TRAFFIC.get(args.workload)
     traffic = None
-    if tr and tr["source_sha256"] == score_source_sha() and launches > 0:
+    if tr and tr["source_sha256"] == source_sha() and launches > 0:
         traffic = tr["hbm_over_algorithmic"] * nbytes / launches
+    roof_score = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                  "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
+                  "traffic": traffic,
+                  "traffic_unit": "HBM bytes per launch (measured HBM / algorithmic bytes x "
+                                  "this run's algorithmic bytes per launch)",
+                  "kernel": "pair score: k_kink + k_exact (k_score for directed and Gaussian pairs)",
+                  "kernel_ms_avg": score_ms / max(launches, 1), "launches": launches,
+                  "bytes_per_launch": nbytes / max(launches, 1),
+                  "pairs_scored": scored, "bytes_per_pair": nbytes / max(scored, 1),
+                  "alu_view": {"achieved_tflops": tflops, "peak_tflops": PEAK_TFLOPS,
+                               "frac": (tflops / PEAK_TFLOPS) if tflops else None,
+                               "flops_per_pair": flops / max(scored, 1)},
+                  "work": work}
+    roof_screen = None
+    if screen and scr["full_launches"] > 0 and scr["full_ms"] > 0:
+        sflops = scr["full_flops"] / scr["full_launches"]
+        sms = scr["full_ms"] / scr["full_launches"]
+        ach = sflops / (sms / 1e3) / 1e12
+        ts = TRAFFIC_SCREEN.get(args.workload)
+        straffic = ts["hbm_bytes_per_launch"] if ts and ts["source_sha256"] == source_sha("screen.hip") else None
+        roof_screen = {"bound": "mfma", "achieved": ach, "peak": PEAK_F16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                       "frac": ach / PEAK_F16_MFMA_TFLOPS, "traffic": straffic,
+                       "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
+                       "kernel": "screening contraction full pass: k_kscreen (FP16 MFMA 16x16x32, "
+                                 "FP32 accumulate, histogram + collect epilogue)",
+                       "kernel_ms_avg": sms, "launches": int(scr["full_launches"]),
+                       "flops_per_launch": sflops,
+                       "sample_pass_ms_avg": scr["sample_ms"] / max(scr["sample_launches"], 1),
+                       "rescored_exactly": scr["rescored"], "second_collect": scr["second_collect"]}
+    metric = ("pair-score evals/s: pairs decided (scored exactly, or excluded from the top m by a "
+              "proven bound) per second of GCD sweep wall time; recall 1 against the exhaustive search"
+              if screen else
+              "pair-score evals/s (exact FindBest scores per second of GCD sweep wall time)")
     line = {
-        "metric": "pair-score evals/s (exact FindBest scores per second of GCD sweep wall time)",
+        "metric": metric,
         "value": value,
         "unit": "pair-score evals/s",
         "n_gpus": 1,
@@ -186,30 +260,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.prec == "fp32" else "f64",
+        "dtype": "f16-mfma+f32" if screen and args.prec == "fp32" else ("f32" if args.prec == "fp32" else "f64"),
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "N": w.N, "M": w.M,
                    "kappa": kappa, "m": ctx.m, "lambda": lam, "search": args.search,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
-                     "traffic": traffic,
-                     "traffic_unit": "HBM bytes per launch (measured HBM / algorithmic bytes x "
-                                     "this run's algorithmic bytes per launch)",
-                     "kernel": "pair score: k_kink + k_exact (k_score for directed and Gaussian pairs)",
-                     "kernel_ms_avg": score_ms / max(launches, 1), "launches": launches,
-                     "bytes_per_launch": nbytes / max(launches, 1),
-                     "pairs_scored": scored, "bytes_per_pair": nbytes / max(scored, 1),
-                     "alu_view": {"achieved_tflops": tflops, "peak_tflops": PEAK_TFLOPS,
-                                  "frac": (tflops / PEAK_TFLOPS) if tflops else None,
-                                  "flops_per_pair": flops / max(scored, 1)},
-                     "work": work},
+        "roofline": roof_screen if roof_screen else roof_score,
         "details": {
             "sweep_ms": [round(s["t_search_ms"] + s["t_update_ms"] + s["t_theta_ms"], 3) for s in stats],
             "search_ms": [round(s["t_search_ms"], 3) for s in stats],
             "update_ms": [round(s["t_update_ms"], 3) for s in stats],
             "theta_ms": [round(s["t_theta_ms"], 3) for s in stats],
             "pair_evals": [s["pair_evals"] for s in stats],
+            "exact_evals_per_s": evals / wall,
             "nnd_iters": [s["nnd_iters"] for s in stats],
             "levels": [s["levels"] for s in stats],
             "rounds": [s["rounds"] for s in stats],
@@ -219,6 +282,10 @@ def main():
             "generate_s": round(t_gen, 2),
         },
     }
+    if roof_screen:
+        line["roofline_score_kernel"] = roof_score
+    if screen and not args.no_compare:
+        line["compare"] = compare_searches(ctx, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, lam, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -264,6 +264,17 @@ rec_status rec_set_timing(rec_ctx* ctx, int32_t on);
 rec_status rec_kernel_time(rec_ctx* ctx, double* score_ms_host, int64_t* launches_host,
                            int64_t* work_host);
 
+/* Instrumentation of REC_SEARCH_SCREEN, since the last call (or since
+ * rec_set_timing): out_host (9 doubles) = [0] kernel ms of the full
+ * contraction passes (event-timed while timing is on), [1] their launches,
+ * [2] their algorithmic flops (2 M flops per ordered pair for the kinetic
+ * model, per unordered pair and side for the symmetric ones), [3] kernel ms
+ * of the sampling passes, [4] their launches, [5] screen calls, [6] pairs
+ * decided (every pair of each call: scored exactly or excluded by the
+ * bounds), [7] pairs rescored exactly, [8] calls that needed a second
+ * collect pass.  Synchronises; resets the sums. */
+rec_status rec_screen_time(rec_ctx* ctx, double* out_host);
+
 const char* rec_status_str(rec_status s);
 const char* rec_last_error(const rec_ctx* ctx);
 

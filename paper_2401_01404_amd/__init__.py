@@ -26,7 +26,7 @@ SYMBOLS = ["rec_workspace_size", "rec_create", "rec_destroy", "rec_score_pairs",
            "rec_get_model", "rec_set_model", "rec_get_fields", "rec_knn", "rec_set_timing",
            "rec_kernel_time", "rec_status_str", "rec_last_error", "rec_sketch", "rec_mlp_params",
            "rec_mlp_infer", "rec_mlp_grad", "rec_mlp_train", "rec_surrogate_config",
-           "rec_surrogate_stats"]
+           "rec_surrogate_stats", "rec_screen_time"]
 SUR_NPARAM = 41345
 SUR_SKETCH_DIM = 64
 SUR_MAX_BATCH = 8192
@@ -87,6 +87,7 @@ def lib():
             "rec_knn": [vp, i64, vp, i32, i32, i32, vp, vp, ctypes.POINTER(i32)],
             "rec_set_timing": [vp, i32],
             "rec_kernel_time": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.c_void_p],
+            "rec_screen_time": [vp, ctypes.c_void_p],
             "rec_sketch": [vp, vp],
             "rec_mlp_params": [vp, vp, vp],
             "rec_mlp_infer": [vp, i64, vp, vp, vp],
@@ -330,6 +331,14 @@ class Context:
 
     def set_timing(self, on: bool = True):
         self._check(lib().rec_set_timing(self.h, 1 if on else 0), self.h)
+
+    def screen_time(self):
+        """Screening-contraction instrumentation since the last call."""
+        o = (ctypes.c_double * 9)()
+        self._check(lib().rec_screen_time(self.h, o), self.h)
+        keys = ["full_ms", "full_launches", "full_flops", "sample_ms", "sample_launches", "calls",
+                "pairs_decided", "rescored", "second_collect"]
+        return {k: o[q] for q, k in enumerate(keys)}
 
     def kernel_time(self):
         """Pair-score kernel time and work since the last call: (ms, launches,

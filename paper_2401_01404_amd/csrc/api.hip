@@ -671,10 +671,22 @@ rec_status rec_surrogate_stats(rec_ctx* ctx, double* out_host) {
 rec_status rec_set_timing(rec_ctx* ctx, int32_t on) {
   if (!ctx) return REC_E_INVAL;
   REC_TRY(rec_timing_resolve(ctx));
+  REC_TRY(rec_screen_resolve(ctx));
+  for (int q = 0; q < 9; ++q) ctx->sc_stat[q] = 0.0;
   ctx->timing = on != 0;
   ctx->score_ms = 0.0;
   ctx->score_launches = ctx->score_pairs = 0;
   return rec_work_read(ctx, ctx->work_base);
+}
+
+rec_status rec_screen_time(rec_ctx* ctx, double* out_host) {
+  if (!ctx || !out_host) return REC_E_INVAL;
+  REC_TRY(rec_screen_resolve(ctx));
+  for (int q = 0; q < 9; ++q) {
+    out_host[q] = ctx->sc_stat[q];
+    ctx->sc_stat[q] = 0.0;
+  }
+  return REC_OK;
 }
 
 rec_status rec_kernel_time(rec_ctx* ctx, double* score_ms_host, int64_t* launches_host,

@@ -140,7 +140,14 @@ struct rec_ctx {
   float *sc_nrm = nullptr, *sc_th2 = nullptr, *sc_sq = nullptr, *sc_tau = nullptr;
   // Ising / kinetic screen: per node |r_i|_1 and curvature sum (1 - t^2)
   float *sc_l1 = nullptr, *sc_cv = nullptr;
-  int64_t sc_retries = 0;   // screens that needed the second collect pass
+  // screen instrumentation: [0] full-pass ms, [1] full-pass launches, [2]
+  // their algorithmic flops, [3] sample-pass ms, [4] sample launches, [5]
+  // screen calls, [6] pairs decided, [7] pairs rescored exactly, [8] calls
+  // that needed a second collect pass
+  double sc_stat[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  struct ScrEv { hipEvent_t a, b; int kind; double flops; };
+  std::vector<ScrEv> sev;
+  size_t sev_used = 0;
   uint32_t* sc_hist = nullptr;
   // learned proposal (surrogate.hip): projection bits, sketches, parameters,
   // Adam state, bf16 weight copies, training work arrays
@@ -178,6 +185,7 @@ struct rec_ctx {
   int64_t work_base[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // work counters when timing was switched on
   ~rec_ctx() {
     for (auto& e : ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto& e : sev) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
   }
 };
 
@@ -228,6 +236,7 @@ rec_status rec_exclusive_scan(rec_ctx* ctx, const int64_t* in, int64_t* out, int
 
 // screen.hip: candidates of the exhaustive screen into ts_i/ts_j (count *n_out)
 rec_status rec_screen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out);
+rec_status rec_screen_resolve(rec_ctx* ctx);   // fold finished screen events into sc_stat
 
 // surrogate.hip
 rec_status rec_sur_init(rec_ctx* ctx);     // projection bits, initial weights, Adam state

@@ -518,6 +518,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     cu[q] = KIN ? 0.f : thr_up(ccv[q] + cmin);
     ch[q] = KIN ? 0.f : thr_lo(ccv[q] + cmin);
   }
+  // One gate per element: |a| must reach lambda - er + the collect
+  // threshold or lambda + er + the histogram threshold (kinetic: one value
+  // per row).  Range and triangle checks run only behind the gate (padding
+  // rows and columns hold a = 0).
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -526,20 +530,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const int64_t i = r0 + li;
       const float rl1 = i < P.N ? P.l1[i] : 0.f, rcv = i < P.N ? P.cv[i] : 0.f;
       const float ru = thr_up(rcv + cmin), rh = thr_lo(rcv + cmin);
+      const float er_row = P.ce * rl1 + P.el;
+      const float big = __builtin_inff();
+      const float gate_row = fminf(COLLECT ? P.lam - er_row + ru : big, HIST ? P.lam + er_row + rh : big);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int lj = wc + q * 16 + (lane & 15);
-        const int64_t j = c0 + lj;
-        const bool ok = KIN ? (i < P.N && j < P.N && i != j) : (i < j && j < P.N);
         const float aa = fabsf(acc[m][q][r]);
-        const float er = P.ce * (rl1 + cl1[q]) + P.el;
-        if (HIST) {
-          const float e = aa - er - P.lam;
-          if (ok && e > 0.f && e >= rh && e >= ch[q]) push(false, li, lj, e, rcv + ccv[q]);
+        float gate = gate_row;
+        if (!KIN) {
+          const float er = er_row + P.ce * cl1[q];
+          gate = fminf(COLLECT ? P.lam - er + fmaxf(ru, cu[q]) : big,
+                       HIST ? P.lam + er + fmaxf(rh, ch[q]) : big);
         }
-        if (COLLECT) {
-          const float e = aa + er - P.lam;
-          if (ok && e > 0.f && e >= ru && e >= cu[q]) push(true, li, lj, e, rcv + ccv[q]);
+        if (aa >= gate) {
+          const int lj = wc + q * 16 + (lane & 15);
+          const int64_t j = c0 + lj;
+          const bool ok = KIN ? (i < P.N && j < P.N && i != j) : (i < j && j < P.N);
+          const float er = P.ce * (rl1 + cl1[q]) + P.el;
+          if (HIST) {
+            const float e = aa - er - P.lam;
+            if (ok && e > 0.f && e >= rh && e >= ch[q]) push(false, li, lj, e, rcv + ccv[q]);
+          }
+          if (COLLECT) {
+            const float e = aa + er - P.lam;
+            if (ok && e > 0.f && e >= ru && e >= cu[q]) push(true, li, lj, e, rcv + ccv[q]);
+          }
         }
       }
     }
@@ -618,6 +633,12 @@ namespace {
 // a collect pass at tau runs.
 constexpr int KS_SAMPLE = 16;   // largest sampling step of the row tiles
 
+#define REC_TRY_ST(...)                      \
+  do {                                       \
+    rec_status st_ = (__VA_ARGS__);          \
+    if (st_ != REC_OK) return st_;           \
+  } while (0)
+
 TileMap tile_map(int nbi, int nbj, int64_t* grid) {
   TileMap T;
   T.nbi = nbi;
@@ -629,16 +650,49 @@ TileMap tile_map(int nbi, int nbj, int64_t* grid) {
   return T;
 }
 
+// Instrumentation: bracket a contraction pass with events (kind 0: full
+// pass with its algorithmic flops, 1: sample pass) when timing is on.
+rec_status ev_begin(rec_ctx* ctx) {
+  if (!ctx->timing) return REC_OK;
+  if (ctx->sev_used == 64) {
+    rec_status st = rec_screen_resolve(ctx);
+    if (st != REC_OK) return st;
+  }
+  if (ctx->sev_used == ctx->sev.size()) {
+    rec_ctx::ScrEv e{};
+    REC_HIP(hipEventCreate(&e.a));
+    REC_HIP(hipEventCreate(&e.b));
+    ctx->sev.push_back(e);
+  }
+  REC_HIP(hipEventRecord(ctx->sev[ctx->sev_used].a, ctx->stream));
+  return REC_OK;
+}
+rec_status ev_end(rec_ctx* ctx, int kind, double flops) {
+  if (!ctx->timing) return REC_OK;
+  rec_ctx::ScrEv& e = ctx->sev[ctx->sev_used++];
+  e.kind = kind;
+  e.flops = flops;
+  REC_HIP(hipEventRecord(e.b, ctx->stream));
+  return REC_OK;
+}
+
 template <int MODE, int ROBUST>
-void launch_ks(rec_ctx* ctx, const KScreenArgs& P, int nbi, int nbj, int row_step) {
+rec_status launch_ks(rec_ctx* ctx, const KScreenArgs& P, int nbi, int nbj, int row_step) {
   int64_t grid = 0;
   const TileMap T = tile_map(nbi, nbj, &grid);
+  // algorithmic work of a full pass: one M-term dot product (2 flops a term)
+  // per ordered pair (kinetic) or two per unordered pair (Ising)
+  const double N = (double)ctx->cfg.N;
+  const double flops = 2.0 * N * (N - 1.0) * (double)ctx->cfg.M;
+  rec_status st = ev_begin(ctx);
+  if (st != REC_OK) return st;
   if (ctx->cfg.model == REC_KINETIC)
     hipLaunchKernelGGL((k_kscreen<MODE, 1, ROBUST>), dim3((unsigned)grid), dim3(256), 0, ctx->stream, P, T,
                        row_step);
   else
     hipLaunchKernelGGL((k_kscreen<MODE, 0, ROBUST>), dim3((unsigned)grid), dim3(256), 0, ctx->stream, P, T,
                        row_step);
+  return ev_end(ctx, row_step == 1 ? 0 : 1, row_step == 1 ? flops : 0.0);
 }
 
 rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
@@ -691,13 +745,13 @@ rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
   const int step = std::max(1, std::min(KS_SAMPLE, nb / 8));
   const int nbs = (nb + step - 1) / step;
   P.hist = hist_s;
-  launch_ks<0, 1>(ctx, P, nbs, nb, step);
+  REC_TRY_ST(launch_ks<0, 1>(ctx, P, nbs, nb, step));
   const int64_t ts = std::max<int64_t>(1, 2 * target / step);
   hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_s, ts, tau_c, floor);
   // full pass: histogram from the floor up, collect at tau_c
   P.hist = hist_f;
   P.hfloor = floor;
-  launch_ks<2, 0>(ctx, P, nb, nb, 1);
+  REC_TRY_ST(launch_ks<2, 0>(ctx, P, nb, nb, 1));
   hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_f, target, tau_f, (float*)nullptr);
   REC_HIP(hipGetLastError());
   int64_t n = 0;
@@ -716,22 +770,38 @@ rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
     if (over || tau[1] < tau[2]) {
       REC_HIP(hipMemsetAsync(hist_f, 0, KS_BINS * sizeof(uint32_t), s));
       P.hfloor = nullptr;
-      launch_ks<0, 1>(ctx, P, nb, nb, 1);
+      REC_TRY_ST(launch_ks<0, 1>(ctx, P, nb, nb, 1));
       hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_f, target, tau_f, (float*)nullptr);
     }
     REC_HIP(hipMemcpyAsync(tau_c, tau_f, sizeof(float), hipMemcpyDeviceToDevice, s));
     REC_HIP(hipMemsetAsync(P.cursor, 0, sizeof(int64_t), s));
-    launch_ks<1, 1>(ctx, P, nb, nb, 1);
+    REC_TRY_ST(launch_ks<1, 1>(ctx, P, nb, nb, 1));
     REC_HIP(hipGetLastError());
     REC_HIP(hipMemcpyAsync(&n, P.cursor, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     REC_HIP(hipStreamSynchronize(s));
-    ++ctx->sc_retries;
+    ctx->sc_stat[8] += 1;
   }
   if (n > ctx->cand_cap) { ctx->err = "screen candidates exceed the candidate buffer"; return REC_E_NOMEM; }
+  ctx->sc_stat[5] += 1;
+  ctx->sc_stat[6] += kin ? (double)N * (double)(N - 1) : 0.5 * (double)N * (double)(N - 1);
   *n_out = n;
   return REC_OK;
 }
 }  // namespace
+
+rec_status rec_screen_resolve(rec_ctx* ctx) {
+  for (size_t k = 0; k < ctx->sev_used; ++k) {
+    rec_ctx::ScrEv& e = ctx->sev[k];
+    REC_HIP(hipEventSynchronize(e.b));
+    float ms = 0.f;
+    REC_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+    ctx->sc_stat[e.kind == 0 ? 0 : 3] += ms;
+    ctx->sc_stat[e.kind == 0 ? 1 : 4] += 1;
+    ctx->sc_stat[2] += e.flops;
+  }
+  ctx->sev_used = 0;
+  return REC_OK;
+}
 
 rec_status rec_screen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
   hipStream_t s = ctx->stream;
@@ -767,14 +837,21 @@ rec_status rec_screen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
   const int nb = (int)((N + SC_T - 1) / SC_T);
   REC_HIP(hipMemsetAsync(ctx->sc_hist, 0, SC_BINS * sizeof(uint32_t), s));
   REC_HIP(hipMemsetAsync(P.cursor, 0, sizeof(int64_t), s));
+  const double flops = 2.0 * (double)N * (double)(N - 1) * (double)ctx->cfg.M;
+  REC_TRY_ST(ev_begin(ctx));
   hipLaunchKernelGGL(k_screen<0>, dim3(nb, nb), dim3(256), 0, s, P);
+  REC_TRY_ST(ev_end(ctx, 0, flops));
   hipLaunchKernelGGL(k_screen_tau, dim3(1), dim3(64), 0, s, ctx->sc_hist, target, ctx->sc_tau);
+  REC_TRY_ST(ev_begin(ctx));
   hipLaunchKernelGGL(k_screen<1>, dim3(nb, nb), dim3(256), 0, s, P);
+  REC_TRY_ST(ev_end(ctx, 0, flops));
   REC_HIP(hipGetLastError());
   int64_t n = 0;
   REC_HIP(hipMemcpyAsync(&n, P.cursor, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   REC_HIP(hipStreamSynchronize(s));
   if (n > ctx->cand_cap) { ctx->err = "screen candidates exceed the candidate buffer"; return REC_E_NOMEM; }
+  ctx->sc_stat[5] += 1;
+  ctx->sc_stat[6] += 0.5 * (double)N * (double)(N - 1);
   *n_out = n;
   return REC_OK;
 }

@@ -1229,6 +1229,7 @@ struct Search {
     if ((st = check_err()) != REC_OK) return st;
     const int64_t np = nc + nnz;
     if (np > ctx->cand_cap || np > ctx->sb.cap) { ctx->err = "screen candidates exceed the buffers"; return REC_E_NOMEM; }
+    ctx->sc_stat[7] += (double)np;
     int32_t* I = ctx->ts_i;
     int32_t* J = ctx->ts_j;
     double* g = ctx->C.ovf;
