@@ -93,10 +93,11 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   if (c->model != REC_GAUSS) {
     F.xq = a.take<uint32_t>(N * 64);
     F.yq = c->model == REC_KINETIC ? a.take<uint32_t>(N * 64) : F.xq;
-    F.rh = a.take<uint16_t>(nsz);
+    F.rh = a.take<uint16_t>((N + REC_TAIL_ROWS) * z.Mp);
+    F.xh = a.take<uint16_t>((N + REC_TAIL_ROWS) * z.Mp);
   } else {
     F.xq = F.yq = nullptr;
-    F.rh = nullptr;
+    F.rh = F.xh = nullptr;
   }
   F.sq = a.take<double>(N);
   F.theta = a.take<double>(N);

@@ -10,6 +10,8 @@
 
 #include "../../include/rec.h"
 
+constexpr int64_t REC_TAIL_ROWS = 128;   // zero rows after the N rows of rh and xh
+
 // Device view of the data and fields, passed by value to kernels.
 struct Fields {
   const int8_t* xs;     // N x Mp input side +-1 (kinetic: x_{j,t-1}); padding 0
@@ -26,6 +28,9 @@ struct Fields {
   const uint32_t* xq;
   const uint32_t* yq;
   uint16_t* rh;
+  // fp16 copy of xs for the screening contraction; rh and xh carry
+  // REC_TAIL_ROWS zero rows past N
+  uint16_t* xh;
   double scr;           // screen threshold: lambda minus the fp16 (and float) error bound
   double scra;          // exact-sign screen threshold: lambda minus the float rounding bound
   int64_t N, M, Mp;     // valid samples M, padded row length Mp = 64 * npl

@@ -70,6 +70,16 @@ __global__ __launch_bounds__(FT) void k_load_int8(const int8_t* __restrict__ X, 
   }
 }
 
+// fp16 copy of the +-1 input side (the screening contraction's operand)
+__global__ __launch_bounds__(FT) void k_x_half(const int8_t* __restrict__ xs, int64_t Mp,
+                                               uint16_t* __restrict__ xh) {
+  const int64_t i = blockIdx.x;
+  for (int64_t s = threadIdx.x; s < Mp; s += FT) {
+    const int8_t v = xs[i * Mp + s];
+    xh[i * Mp + s] = v > 0 ? 0x3C00u : (v < 0 ? 0xBC00u : 0u);
+  }
+}
+
 // Lane words of the screen: bit c*VEC + k of lane l = sample
 // c*64*VEC + l*VEC + k is +1 (one wave per node).
 __global__ __launch_bounds__(REC_WAVE) void k_pack_bits(const int8_t* __restrict__ x, int64_t Mp,
@@ -403,6 +413,10 @@ rec_status rec_load_data(rec_ctx* ctx, const void* X, int64_t ldx) {
     if (ctx->cfg.model == REC_KINETIC)
       hipLaunchKernelGGL(k_pack_bits, dim3(N), dim3(REC_WAVE), 0, ctx->stream, ctx->F.ys, ctx->F.Mp,
                          ctx->F.npl, const_cast<uint32_t*>(ctx->F.yq));
+    hipLaunchKernelGGL(k_x_half, dim3(N), dim3(FT), 0, ctx->stream, ctx->F.xs, ctx->F.Mp, ctx->F.xh);
+    const size_t tail = (size_t)(REC_TAIL_ROWS * ctx->F.Mp) * sizeof(uint16_t);
+    REC_HIP(hipMemsetAsync(ctx->F.xh + N * ctx->F.Mp, 0, tail, ctx->stream));
+    REC_HIP(hipMemsetAsync(ctx->F.rh + N * ctx->F.Mp, 0, tail, ctx->stream));
   }
   REC_HIP(hipGetLastError());
   return REC_OK;

@@ -226,8 +226,8 @@ __global__ void k_screen_tau(const uint32_t* hist, int64_t target, float* tau) {
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 struct KScreenArgs {
-  const int8_t* xs;     // N x Mp input side (+-1, padding 0)
-  const uint16_t* rh;   // N x Mp fp16 residuals (padding 0)
+  const uint16_t* xh;   // (N + 128) x Mp fp16 input side (+-1; padding and tail rows 0)
+  const uint16_t* rh;   // (N + 128) x Mp fp16 residuals (padding and tail rows 0)
   int64_t N, Mp;
   int nsteps;           // k steps of 32: Ising 2 Mp / 32, kinetic Mp / 32
   const float* l1;      // |r_i|_1, rounded up
@@ -312,19 +312,14 @@ __device__ __forceinline__ float kgain_up(float e, float c) {
   return 0.25f * c * p * (1.f + 1e-5f);
 }
 
-// 16 int8 samples (+-1 / 0) -> 16 fp16 values (two 16-byte words)
-__device__ __forceinline__ void x16_to_f16(uint4 v, uint4* lo, uint4* hi) {
-  uint32_t w[4] = {v.x, v.y, v.z, v.w}, o[8];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t a = (w[q] & 0xFFu) | ((w[q] & 0xFF00u) << 8);
-    const uint32_t b = ((w[q] >> 16) & 0xFFu) | ((w[q] >> 8) & 0x00FF0000u);
-    o[2 * q] = ((a & 0x00010001u) * 0x3C00u) | ((a & 0x00800080u) << 8);
-    o[2 * q + 1] = ((b & 0x00010001u) * 0x3C00u) | ((b & 0x00800080u) << 8);
-  }
-  *lo = make_uint4(o[0], o[1], o[2], o[3]);
-  *hi = make_uint4(o[4], o[5], o[6], o[7]);
-}
+// LDS operand layout: 128 rows x 32 fp16 (64-byte rows, no padding); the
+// 16-byte chunk c of row r sits at chunk position c ^ f(r) with
+// f(r) = ((r >> 1) ^ (r >> 3)) & 3.  A fragment read (rows 16k..16k+15 at
+// one chunk) and a staging write (whole rows 4j..4j+3) then touch distinct
+// 16-byte bank groups within every 8 lanes (128-byte bank rows) and every 16
+// lanes (256-byte bank rows): no bank conflicts either way.
+__device__ __forceinline__ int ks_swz(int r, int c) { return r * SC_K + 8 * (c ^ (((r >> 1) ^ (r >> 3)) & 3)); }
+
 
 // Histogram of positive float bounds for the Ising / kinetic screen: 16 bins
 // per octave over [2^-31, 2^33); smaller values are not counted (a threshold
@@ -381,8 +376,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   bi *= row_step;
   if (!KIN && bi > bj) return;
   constexpr bool HIST = MODE != 1, COLLECT = MODE != 0;
-  __shared__ __attribute__((aligned(16))) _Float16 As[2][SC_T * SC_LD];
-  __shared__ __attribute__((aligned(16))) _Float16 Bs[2][SC_T * SC_LD];
+  __shared__ __attribute__((aligned(16))) _Float16 As[2][SC_T * SC_K];
+  __shared__ __attribute__((aligned(16))) _Float16 Bs[2][SC_T * SC_K];
   __shared__ uint32_t hs[HIST ? KS_BINS : 1];
   __shared__ uint32_t kq_key[KS_Q];   // bit 31: collect (else histogram); row << 7 | column in the tile
   __shared__ float kq_e[KS_Q], kq_c[KS_Q];
@@ -393,33 +388,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   if (HIST)
     for (int q = tid; q < KS_BINS; q += 256) hs[q] = 0;
   if (tid == 0) { kq_n = 0; kc_n = 0; }
-  // staging assignment: x chunk (16 samples) = row tid/2, half tid%2;
-  // r chunks (8 samples) = rows q/4, part q%4 for q = tid, tid + 256
-  const int xrow = tid >> 1, xhalf = tid & 1;
+  // Staging: thread tid moves the 8-sample chunks (tid & 3) of rows tid/4 and
+  // tid/4 + 64 of both operands.  Operand rows are fp16 (x copy and
+  // residuals) with 128 zero rows past N, so no load needs a bound check.
+  // Ising: in the first half of k, A = x and B = r; in the second, A = r and
+  // B = x.  Kinetic: A = r (targets), B = x (sources).
   const int n = P.nsteps;
-  auto load = [&](int s, KRegs& R) {
+  const int sr = tid >> 2, part = tid & 3;
+  const uint32_t oa0 = (uint32_t)((r0 + sr) * P.Mp + part * 8), oa1 = (uint32_t)((r0 + sr + 64) * P.Mp + part * 8);
+  const uint32_t ob0 = (uint32_t)((c0 + sr) * P.Mp + part * 8), ob1 = (uint32_t)((c0 + sr + 64) * P.Mp + part * 8);
+  const int wa0 = ks_swz(sr, part), wa1 = ks_swz(sr + 64, part);
+  // staged values travel by value (no addressable aggregates: they stay in
+  // registers)
+  struct Stage { uint4 a0, a1, b0, b1; };
+  auto load = [&](int s) -> Stage {
     const bool first = !KIN && (int64_t)s * SC_K < P.Mp;
     const int64_t k = (int64_t)s * SC_K - (KIN || first ? 0 : P.Mp);
-    // x side: A rows in the first half (Ising), else B rows
-    const int64_t gx = (first ? r0 : c0) + xrow;
-    R.x = make_uint4(0u, 0u, 0u, 0u);
-    if (gx < P.N) R.x = *reinterpret_cast<const uint4*>(P.xs + gx * P.Mp + k + xhalf * 16);
-    const int64_t rb = first ? c0 : r0;
-    const int64_t g0 = rb + (tid >> 2), g1 = rb + ((tid + 256) >> 2);
-    R.r0 = R.r1 = make_uint4(0u, 0u, 0u, 0u);
-    if (g0 < P.N) R.r0 = *reinterpret_cast<const uint4*>(P.rh + g0 * P.Mp + k + (tid & 3) * 8);
-    if (g1 < P.N) R.r1 = *reinterpret_cast<const uint4*>(P.rh + g1 * P.Mp + k + (tid & 3) * 8);
+    const uint16_t* pa = (first ? P.xh : P.rh) + k;
+    const uint16_t* pb = (first ? P.rh : P.xh) + k;
+    Stage R;
+    R.a0 = *reinterpret_cast<const uint4*>(pa + oa0);
+    R.a1 = *reinterpret_cast<const uint4*>(pa + oa1);
+    R.b0 = *reinterpret_cast<const uint4*>(pb + ob0);
+    R.b1 = *reinterpret_cast<const uint4*>(pb + ob1);
+    return R;
   };
-  auto store = [&](int s, const KRegs& R, int buf) {
-    const bool first = !KIN && (int64_t)s * SC_K < P.Mp;
-    _Float16* Xs = first ? As[buf] : Bs[buf];
-    _Float16* Rs = first ? Bs[buf] : As[buf];
-    uint4 lo, hi;
-    x16_to_f16(R.x, &lo, &hi);
-    *reinterpret_cast<uint4*>(Xs + xrow * SC_LD + xhalf * 16) = lo;
-    *reinterpret_cast<uint4*>(Xs + xrow * SC_LD + xhalf * 16 + 8) = hi;
-    *reinterpret_cast<uint4*>(Rs + (tid >> 2) * SC_LD + (tid & 3) * 8) = R.r0;
-    *reinterpret_cast<uint4*>(Rs + ((tid + 256) >> 2) * SC_LD + (tid & 3) * 8) = R.r1;
+  auto store = [&](Stage R, int buf) {
+    *reinterpret_cast<uint4*>(As[buf] + wa0) = R.a0;
+    *reinterpret_cast<uint4*>(As[buf] + wa1) = R.a1;
+    *reinterpret_cast<uint4*>(Bs[buf] + wa0) = R.b0;
+    *reinterpret_cast<uint4*>(Bs[buf] + wa1) = R.b1;
   };
   floatx4 acc[4][4];
 #pragma unroll
@@ -427,35 +425,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[m][q] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  int fa[4], fb[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    fa[f] = ks_swz(wr + f * 16 + (lane & 15), lane >> 4);
+    fb[f] = ks_swz(wc + f * 16 + (lane & 15), lane >> 4);
+  }
   auto compute = [&](int buf) {
     halfx8 af[4], bf[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-      af[m] = *reinterpret_cast<const halfx8*>(As[buf] + (wr + m * 16 + (lane & 15)) * SC_LD + (lane >> 4) * 8);
+    for (int m = 0; m < 4; ++m) af[m] = *reinterpret_cast<const halfx8*>(As[buf] + fa[m]);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      bf[q] = *reinterpret_cast<const halfx8*>(Bs[buf] + (wc + q * 16 + (lane & 15)) * SC_LD + (lane >> 4) * 8);
+    for (int q = 0; q < 4; ++q) bf[q] = *reinterpret_cast<const halfx8*>(Bs[buf] + fb[q]);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
       for (int q = 0; q < 4; ++q)
         acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[m], bf[q], acc[m][q], 0, 0, 0);
   };
-  KRegs R0, R1;
-  load(0, R0);
-  if (n > 1) load(1, R1);
-  store(0, R0, 0);
+  // n is even (Mp is a multiple of 64).  The loop body has no branches, so
+  // every iteration leaves the same loads in flight and none is waited on
+  // before its data is needed; past the end, loads repeat the last step and
+  // the stores land in a buffer nobody reads.
+  Stage R0 = load(0), R1 = load(1);
+  store(R0, 0);
   __syncthreads();
   // step s reads LDS buffer s % 2; registers hold step s + 1 while step s + 2 loads
   for (int s = 0; s < n; s += 2) {
-    if (s + 2 < n) load(s + 2, R0);
+    R0 = load(min(s + 2, n - 1));
     compute(0);
-    if (s + 1 < n) store(s + 1, R1, 1);
+    store(R1, 1);
     __syncthreads();
-    if (s + 1 >= n) break;
-    if (s + 3 < n) load(s + 3, R1);
+    R1 = load(min(s + 3, n - 1));
     compute(1);
-    if (s + 2 < n) store(s + 2, R0, 0);
+    store(R0, 0);
     __syncthreads();
   }
   // Epilogue: lane holds rows 4*(lane/16) + r, column lane % 16 of each
@@ -710,7 +713,7 @@ rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
     hipLaunchKernelGGL(k_kscreen_prep<double>, dim3(N), dim3(256), 0, s, ctx->F, ctx->sc_l1, ctx->sc_cv);
   hipLaunchKernelGGL(k_ks_cvmin, dim3(1), dim3(1024), 0, s, ctx->sc_cv, N, cvmin);
   KScreenArgs P;
-  P.xs = ctx->F.xs;
+  P.xh = ctx->F.xh;
   P.rh = ctx->F.rh;
   P.N = N;
   P.Mp = ctx->F.Mp;
