@@ -78,7 +78,10 @@ TRAFFIC = {
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
 # `bench.py --workload W --steps 2 --warmup 0 --no-cpu`, scaled by the same
 # 1 GiB copy probe.  Valid only for the source it was measured on.
-TRAFFIC_SCREEN = {}
+TRAFFIC_SCREEN = {
+    "C4": {"source_sha256": "5694bc0441926bae7940794bb4203487f9ce75bb8bfb14e91a13371b91b4638d",
+           "hbm_bytes_per_launch": 2.2155e+10},
+}
 
 
 def source_sha(name="score.hip"):
