@@ -242,6 +242,10 @@ rec_status rec_exclusive_scan(rec_ctx* ctx, const int64_t* in, int64_t* out, int
 // screen.hip: candidates of the exhaustive screen into ts_i/ts_j (count *n_out)
 rec_status rec_screen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out);
 rec_status rec_screen_resolve(rec_ctx* ctx);   // fold finished screen events into sc_stat
+// Ising/kinetic, after rec_screen_candidates: append the current couplings
+// (wi/wj/wv, nnz) whose gain bound reaches the screen's threshold; *n_out =
+// candidates + appended couplings
+rec_status rec_screen_couplings(rec_ctx* ctx, int64_t nnz, int64_t* n_out);
 
 // surrogate.hip
 rec_status rec_sur_init(rec_ctx* ctx);     // projection bits, initial weights, Adam state

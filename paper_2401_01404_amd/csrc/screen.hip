@@ -606,6 +606,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 }
 
+// Current couplings (w0 != 0).  With s = sign(w0), |w0 + d| - |w0| >= s d for
+// every step d, so the gain is at most the best gain of the smooth concave
+// g(d) = f(w0 + d) - f(w0) - lambda s d, whose slope at 0 is a - lambda s
+// (a = f'(w0), the gradient at the current state) and whose curvature obeys
+// the same bounds as above: gain <= (c/4) psi(2 |a - lambda s| / c).  One
+// wavefront per coupling forms a from the fp16 rows (error bounded as for the
+// contraction); couplings whose bound reaches *tau are appended after the
+// collected candidates.
+template <int KIN>
+__global__ __launch_bounds__(256) void k_ks_couple(KScreenArgs P, const int32_t* __restrict__ wi,
+                                                   const int32_t* __restrict__ wj,
+                                                   const double* __restrict__ wv, int64_t nnz) {
+  const int lane = threadIdx.x & (REC_WAVE - 1);
+  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x / REC_WAVE);
+  if (e >= nnz) return;
+  const int64_t i = wi[e], j = wj[e];
+  const uint16_t* ri = P.rh + i * P.Mp;
+  const uint16_t* xj = P.xh + j * P.Mp;
+  const uint16_t* rj = P.rh + j * P.Mp;
+  const uint16_t* xi = P.xh + i * P.Mp;
+  float acc = 0.f;
+  for (int64_t k = (int64_t)lane * 8; k < P.Mp; k += 8 * REC_WAVE) {
+    const halfx8 a = *reinterpret_cast<const halfx8*>(ri + k);
+    const halfx8 b = *reinterpret_cast<const halfx8*>(xj + k);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += (float)a[q] * (float)b[q];
+    if (!KIN) {
+      const halfx8 c = *reinterpret_cast<const halfx8*>(rj + k);
+      const halfx8 d = *reinterpret_cast<const halfx8*>(xi + k);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += (float)c[q] * (float)d[q];
+    }
+  }
+  acc = rec_wave_sum(acc);
+  if (lane != 0) return;
+  const float sgn = wv[e] > 0.0 ? 1.f : -1.f;
+  const float er = P.ce * (P.l1[i] + (KIN ? 0.f : P.l1[j])) + P.el;
+  const float c = P.cv[i] + (KIN ? 0.f : P.cv[j]);
+  if (kgain_up(fabsf(acc - sgn * P.lam) + er, c) < *P.tau) return;
+  const int64_t pos = (int64_t)atomicAdd((unsigned long long*)P.cursor, 1ull);
+  if (pos < P.cap) {
+    P.oi[pos] = (int32_t)i;
+    P.oj[pos] = (int32_t)j;
+  }
+}
+
 // tau = lower edge of the bin where the count from the top first reaches
 // target (0 if it never does).  out[0] = tau.
 // floor_out (optional) = tau, the histogram floor of the full pass: bins at
@@ -698,6 +744,37 @@ rec_status launch_ks(rec_ctx* ctx, const KScreenArgs& P, int nbi, int nbj, int r
   return ev_end(ctx, row_step == 1 ? 0 : 1, row_step == 1 ? flops : 0.0);
 }
 
+KScreenArgs ks_args(rec_ctx* ctx) {
+  const int kin = ctx->cfg.model == REC_KINETIC;
+  KScreenArgs P;
+  P.xh = ctx->F.xh;
+  P.rh = ctx->F.rh;
+  P.N = ctx->cfg.N;
+  P.Mp = ctx->F.Mp;
+  const int64_t K = kin ? ctx->F.Mp : 2 * ctx->F.Mp;
+  P.nsteps = (int)(K / SC_K);
+  P.l1 = ctx->sc_l1;
+  P.cv = ctx->sc_cv;
+  P.cvmin = ctx->sc_tau + 3;
+  P.lam = (float)ctx->cfg.lambda;
+  // fp16 rounding of r (and of its float source), fp32 accumulation over K terms
+  P.ce = (float)(std::ldexp(1.0, -11) * (1.0 + std::ldexp(1.0, -10)) + std::ldexp(1.0, -22) +
+                 (double)K * std::ldexp(1.0, -23));
+  // lambda's float rounding, fp16 subnormals, the exact kernel's own rounding
+  P.el = (float)(1e-6 * ctx->cfg.lambda + (double)K * std::ldexp(1.0, -24) + 1e-30);
+  P.W = ctx->W;
+  P.oi = ctx->ts_i;
+  P.oj = ctx->ts_j;
+  P.cursor = ctx->counter + 12;
+  P.cap = ctx->cand_cap;
+  P.err = ctx->err_flag;
+  P.tau = ctx->sc_tau;
+  P.hfloor = nullptr;
+  P.hist = nullptr;
+  P.ovf = nullptr;
+  return P;
+}
+
 rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
   hipStream_t s = ctx->stream;
   const int64_t N = ctx->cfg.N;
@@ -712,30 +789,7 @@ rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
   else
     hipLaunchKernelGGL(k_kscreen_prep<double>, dim3(N), dim3(256), 0, s, ctx->F, ctx->sc_l1, ctx->sc_cv);
   hipLaunchKernelGGL(k_ks_cvmin, dim3(1), dim3(1024), 0, s, ctx->sc_cv, N, cvmin);
-  KScreenArgs P;
-  P.xh = ctx->F.xh;
-  P.rh = ctx->F.rh;
-  P.N = N;
-  P.Mp = ctx->F.Mp;
-  const int64_t K = kin ? ctx->F.Mp : 2 * ctx->F.Mp;
-  P.nsteps = (int)(K / SC_K);
-  P.l1 = ctx->sc_l1;
-  P.cv = ctx->sc_cv;
-  P.cvmin = cvmin;
-  P.lam = (float)ctx->cfg.lambda;
-  // fp16 rounding of r (and of its float source), fp32 accumulation over K terms
-  P.ce = (float)(std::ldexp(1.0, -11) * (1.0 + std::ldexp(1.0, -10)) + std::ldexp(1.0, -22) +
-                 (double)K * std::ldexp(1.0, -23));
-  // lambda's float rounding, fp16 subnormals, the exact kernel's own rounding
-  P.el = (float)(1e-6 * ctx->cfg.lambda + (double)K * std::ldexp(1.0, -24) + 1e-30);
-  P.W = ctx->W;
-  P.oi = ctx->ts_i;
-  P.oj = ctx->ts_j;
-  P.cursor = ctx->counter + 12;
-  P.cap = ctx->cand_cap;
-  P.err = ctx->err_flag;
-  P.tau = tau_c;
-  P.hfloor = nullptr;
+  KScreenArgs P = ks_args(ctx);
   int32_t* ovf = (int32_t*)(ctx->sc_tau + 4);
   P.ovf = ovf;
   const int nb = (int)((N + SC_T - 1) / SC_T);
@@ -791,6 +845,25 @@ rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
   return REC_OK;
 }
 }  // namespace
+
+rec_status rec_screen_couplings(rec_ctx* ctx, int64_t nnz, int64_t* n_out) {
+  hipStream_t s = ctx->stream;
+  KScreenArgs P = ks_args(ctx);
+  if (nnz > 0) {
+    const unsigned grid = (unsigned)((nnz + 3) / 4);
+    if (ctx->cfg.model == REC_KINETIC)
+      hipLaunchKernelGGL(k_ks_couple<1>, dim3(grid), dim3(256), 0, s, P, ctx->wi, ctx->wj, ctx->wv, nnz);
+    else
+      hipLaunchKernelGGL(k_ks_couple<0>, dim3(grid), dim3(256), 0, s, P, ctx->wi, ctx->wj, ctx->wv, nnz);
+    REC_HIP(hipGetLastError());
+  }
+  int64_t n = 0;
+  REC_HIP(hipMemcpyAsync(&n, P.cursor, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  REC_HIP(hipStreamSynchronize(s));
+  if (n > ctx->cand_cap) { ctx->err = "screen candidates exceed the candidate buffer"; return REC_E_NOMEM; }
+  *n_out = n;
+  return REC_OK;
+}
 
 rec_status rec_screen_resolve(rec_ctx* ctx) {
   for (size_t k = 0; k < ctx->sev_used; ++k) {

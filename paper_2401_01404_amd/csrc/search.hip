@@ -1227,16 +1227,22 @@ struct Search {
     int64_t nc = 0;
     if ((st = rec_screen_candidates(ctx, m + nnz, &nc)) != REC_OK) return st;
     if ((st = check_err()) != REC_OK) return st;
-    const int64_t np = nc + nnz;
-    if (np > ctx->cand_cap || np > ctx->sb.cap) { ctx->err = "screen candidates exceed the buffers"; return REC_E_NOMEM; }
-    ctx->sc_stat[7] += (double)np;
     int32_t* I = ctx->ts_i;
     int32_t* J = ctx->ts_j;
     double* g = ctx->C.ovf;
-    if (nnz > 0) {
-      hipMemcpyAsync(I + nc, ctx->wi, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
-      hipMemcpyAsync(J + nc, ctx->wj, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+    int64_t np = nc + nnz;
+    if (ctx->cfg.model == REC_GAUSS) {
+      // every current coupling is rescored
+      if (np > ctx->cand_cap) { ctx->err = "screen candidates exceed the buffers"; return REC_E_NOMEM; }
+      if (nnz > 0) {
+        hipMemcpyAsync(I + nc, ctx->wi, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+        hipMemcpyAsync(J + nc, ctx->wj, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+      }
+    } else if ((st = rec_screen_couplings(ctx, nnz, &np)) != REC_OK) {
+      return st;
     }
+    if (np > ctx->cand_cap || np > ctx->sb.cap) { ctx->err = "screen candidates exceed the buffers"; return REC_E_NOMEM; }
+    ctx->sc_stat[7] += (double)np;
     if ((st = rec_launch_score(ctx, np, I, J, nullptr, g, nullptr, nullptr)) != REC_OK) return st;
     int64_t* d_n = ctx->counter + 9;
     hipMemsetAsync(d_n, 0, sizeof(int64_t), s);

@@ -75,3 +75,32 @@ def test_gain_bounds_hold(model):
         checked += pos.sum()
         O.gcd_sweep(N, "exhaustive")
     assert checked > 100
+
+
+@pytest.mark.parametrize("model", ["ising", "kinetic"])
+def test_gain_bound_of_current_couplings(model):
+    """A coupling w0 != 0: with s = sign(w0) the step's penalty change is at
+    least lambda s d, so gain <= (c/4) psi(2 |a - lambda s| / c) with a the
+    derivative of the smooth part at w0 and c the curvature at the current
+    fields.  Checked for every coupling after a few oracle sweeps."""
+    if model == "ising":
+        w = synth.ising_er(60, 300, 3.0, 0.5, 0.3, seed=23)
+    else:
+        w = synth.kinetic_er(60, 300, 4.0, 0.5, seed=24)
+    lam = 0.5 * oracle.default_lambda(w.X, model)
+    O = oracle.Oracle(w.X, model, lam)
+    checked = 0
+    for sweep in range(3):
+        O.gcd_sweep(w.N // 2, "exhaustive")
+        ei, ej, wv, _ = O.get_model()
+        nz = wv != 0
+        ei, ej, wv = ei[nz], ej[nz], wv[nz]
+        cv = curvatures(O, model)
+        g, _ = O.score_pairs(ei, ej)
+        a = np.array([O.pair_deriv(i, j, v) for i, j, v in zip(ei, ej, wv)])
+        c = cv[ei] if model == "kinetic" else cv[ei] + cv[ej]
+        q = 2 * np.abs(a - lam * np.sign(wv)) / c
+        up = 0.25 * c * psi(q)
+        assert np.all(g <= up + 1e-9 * np.maximum(1.0, g)), (sweep, np.max(g - up))
+        checked += len(g)
+    assert checked > 30
