@@ -241,6 +241,7 @@ struct KScreenArgs {
   WTable W;
   int32_t* oi;
   int32_t* oj;
+  float* og;            // upper bound of each collected pair
   int64_t* cursor;
   int64_t cap;
   int32_t* err;
@@ -483,7 +484,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       if (hb >= 0) atomicAdd(&hs[hb], 1u);
       return;
     }
-    if (kgain_up(e, c) < tau) return;
+    const float gu = kgain_up(e, c);
+    if (gu < tau) return;
     if (P.W.keys != nullptr) {
       // a current (nonzero) coupling is rescored from the W list instead
       const int64_t ws = rec_hash_find(P.W.keys, P.W.mask, rec_pair_key(i, j, KIN != 0), REC_MAX_PROBE);
@@ -492,11 +494,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     if (!ROBUST) {
       const int p = atomicAdd(&kc_n, 1);   // p < KS_Q: at most one per queued element
       kq_key[p] = (uint32_t)(i - r0) << 7 | (uint32_t)(j - c0);
+      kq_e[p] = gu;
     } else {
       const int64_t pos = (int64_t)atomicAdd((unsigned long long*)P.cursor, 1ull);
       if (pos < P.cap) {
         P.oi[pos] = i;
         P.oj[pos] = j;
+        P.og[pos] = gu;
       }
     }
   };
@@ -595,6 +599,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         if (pos < P.cap) {
           P.oi[pos] = (int32_t)(r0 + ((kq_key[t] >> 7) & 127));
           P.oj[pos] = (int32_t)(c0 + (kq_key[t] & 127));
+          P.og[pos] = kq_e[t];
         }
       }
     }
@@ -649,6 +654,23 @@ __global__ __launch_bounds__(256) void k_ks_couple(KScreenArgs P, const int32_t*
   if (pos < P.cap) {
     P.oi[pos] = (int32_t)i;
     P.oj[pos] = (int32_t)j;
+  }
+}
+
+// Keep the collected pairs whose upper bound reaches *tau (the proven
+// threshold, at least the one they were collected at), compacted from the
+// front; the count goes to *cursor.
+__global__ __launch_bounds__(256) void k_ks_filter(const int32_t* __restrict__ I, const int32_t* __restrict__ J,
+                                                   const float* __restrict__ g, int64_t n, const float* tau,
+                                                   int32_t* __restrict__ oI, int32_t* __restrict__ oJ,
+                                                   int64_t* cursor) {
+  __shared__ long long sh[256 / REC_WAVE + 1];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool keep = e < n && g[e] >= *tau;
+  const int64_t p = rec_block_append<256 / REC_WAVE>(cursor, keep, sh);
+  if (p >= 0) {
+    oI[p] = I[e];
+    oJ[p] = J[e];
   }
 }
 
@@ -765,6 +787,7 @@ KScreenArgs ks_args(rec_ctx* ctx) {
   P.W = ctx->W;
   P.oi = ctx->ts_i;
   P.oj = ctx->ts_j;
+  P.og = reinterpret_cast<float*>(ctx->cand_slot);
   P.cursor = ctx->counter + 12;
   P.cap = ctx->cand_cap;
   P.err = ctx->err_flag;
@@ -839,6 +862,16 @@ rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
     ctx->sc_stat[8] += 1;
   }
   if (n > ctx->cand_cap) { ctx->err = "screen candidates exceed the candidate buffer"; return REC_E_NOMEM; }
+  // keep the candidates whose bound reaches the proven threshold
+  if (n > 0) {
+    REC_HIP(hipMemsetAsync(P.cursor, 0, sizeof(int64_t), s));
+    hipLaunchKernelGGL(k_ks_filter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ctx->ts_i, ctx->ts_j,
+                       P.og, n, tau_f, ctx->cand_gi, ctx->cand_v, P.cursor);
+    REC_HIP(hipMemcpyAsync(&n, P.cursor, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    REC_HIP(hipStreamSynchronize(s));
+    REC_HIP(hipMemcpyAsync(ctx->ts_i, ctx->cand_gi, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    REC_HIP(hipMemcpyAsync(ctx->ts_j, ctx->cand_v, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  }
   ctx->sc_stat[5] += 1;
   ctx->sc_stat[6] += kin ? (double)N * (double)(N - 1) : 0.5 * (double)N * (double)(N - 1);
   *n_out = n;
@@ -849,6 +882,7 @@ rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
 rec_status rec_screen_couplings(rec_ctx* ctx, int64_t nnz, int64_t* n_out) {
   hipStream_t s = ctx->stream;
   KScreenArgs P = ks_args(ctx);
+  P.tau = ctx->sc_tau + 1;   // the proven threshold
   if (nnz > 0) {
     const unsigned grid = (unsigned)((nnz + 3) / 4);
     if (ctx->cfg.model == REC_KINETIC)
