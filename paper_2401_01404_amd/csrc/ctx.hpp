@@ -10,7 +10,7 @@
 
 #include "../../include/rec.h"
 
-constexpr int64_t REC_TAIL_ROWS = 128;   // zero rows after the N rows of rh and xh
+constexpr int64_t REC_TAIL_ROWS = 256;   // zero rows after the N rows of rh and xh
 
 // Device view of the data and fields, passed by value to kernels.
 struct Fields {

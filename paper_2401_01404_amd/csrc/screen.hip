@@ -237,11 +237,11 @@ struct KScreenArgs {
   uint32_t* hist;
   const float* tau;     // collect threshold
   const float* hfloor;  // histogram floor (null: none)
-  int32_t* ovf;         // set when a block queue overflowed (the pass is then incomplete)
   WTable W;
   int32_t* oi;
   int32_t* oj;
   float* og;            // upper bound of each collected pair
+  int32_t* ovf;         // set when a block queue overflowed (that pass is then incomplete)
   int64_t* cursor;
   int64_t cap;
   int32_t* err;
@@ -366,83 +366,96 @@ __device__ __forceinline__ bool ks_tile(const TileMap& T, int b, int* bi, int* b
 // Kinetic: every tile, rows are targets (r_i), columns sources (x_j).
 // MODE 0: histogram of lower bounds; 1: collect pairs whose upper bound
 // reaches *tau; 2: both.  Row tiles are taken every row_step-th (sampling).
-struct KRegs { uint4 x, r0, r1; };
-
 constexpr int KS_Q = 512;   // per-block queue of elements that passed the cheap tests (LDS)
+// Tile of the contraction: 4 wavefronts in 2 x 2, each KS_WM x KS_WN blocks of
+// 16 x 16 outputs; the block covers KS_BM rows x KS_BN columns.
+constexpr int KS_WM = 8, KS_WN = 4;
+constexpr int KS_BM = 2 * KS_WM * 16, KS_BN = 2 * KS_WN * 16;
+static_assert(KS_BM <= REC_TAIL_ROWS && KS_BN <= REC_TAIL_ROWS, "tiles must stay inside the zero tail");
+static_assert(KS_BM <= 256 && KS_BN <= 128, "queue keys hold 8-bit rows and 7-bit columns");
 
 template <int MODE, int KIN, int ROBUST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_kscreen(KScreenArgs P, TileMap TM, int row_step) {
   int bi, bj;
   if (!ks_tile(TM, blockIdx.x, &bi, &bj)) return;
   bi *= row_step;
-  if (!KIN && bi > bj) return;
+  const int64_t r0 = (int64_t)bi * KS_BM, c0 = (int64_t)bj * KS_BN;
+  if (!KIN && r0 >= c0 + KS_BN - 1) return;   // no pair i < j in the tile
   constexpr bool HIST = MODE != 1, COLLECT = MODE != 0;
-  __shared__ __attribute__((aligned(16))) _Float16 As[2][SC_T * SC_K];
-  __shared__ __attribute__((aligned(16))) _Float16 Bs[2][SC_T * SC_K];
+  __shared__ __attribute__((aligned(16))) _Float16 As[2][KS_BM * SC_K];
+  __shared__ __attribute__((aligned(16))) _Float16 Bs[2][KS_BN * SC_K];
   __shared__ uint32_t hs[HIST ? KS_BINS : 1];
   __shared__ uint32_t kq_key[KS_Q];   // bit 31: collect (else histogram); row << 7 | column in the tile
   __shared__ float kq_e[KS_Q], kq_c[KS_Q];
   __shared__ int kq_n, kc_n;
   __shared__ int64_t kbase;
   const int tid = threadIdx.x, lane = tid & (REC_WAVE - 1), w = tid / REC_WAVE;
-  const int64_t r0 = (int64_t)bi * SC_T, c0 = (int64_t)bj * SC_T;
   if (HIST)
     for (int q = tid; q < KS_BINS; q += 256) hs[q] = 0;
   if (tid == 0) { kq_n = 0; kc_n = 0; }
-  // Staging: thread tid moves the 8-sample chunks (tid & 3) of rows tid/4 and
-  // tid/4 + 64 of both operands.  Operand rows are fp16 (x copy and
-  // residuals) with 128 zero rows past N, so no load needs a bound check.
-  // Ising: in the first half of k, A = x and B = r; in the second, A = r and
-  // B = x.  Kinetic: A = r (targets), B = x (sources).
+  // Staging: thread tid moves the 8-sample chunk (tid & 3) of rows tid/4 +
+  // 64u of both operands (u < KS_BM/64 for A, < KS_BN/64 for B).  Operand rows
+  // are fp16 (x copy and residuals) with zero rows past N, so no load needs a
+  // bound check.  Ising: in the first half of k, A = x and B = r; in the
+  // second, A = r and B = x.  Kinetic: A = r (targets), B = x (sources).
   const int n = P.nsteps;
   const int sr = tid >> 2, part = tid & 3;
-  const uint32_t oa0 = (uint32_t)((r0 + sr) * P.Mp + part * 8), oa1 = (uint32_t)((r0 + sr + 64) * P.Mp + part * 8);
-  const uint32_t ob0 = (uint32_t)((c0 + sr) * P.Mp + part * 8), ob1 = (uint32_t)((c0 + sr + 64) * P.Mp + part * 8);
-  const int wa0 = ks_swz(sr, part), wa1 = ks_swz(sr + 64, part);
+  uint32_t oa[4], ob[2];
+  int wa[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    oa[u] = (uint32_t)((r0 + sr + 64 * u) * P.Mp + part * 8);
+    wa[u] = ks_swz(sr + 64 * u, part);
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) ob[u] = (uint32_t)((c0 + sr + 64 * u) * P.Mp + part * 8);
   // staged values travel by value (no addressable aggregates: they stay in
   // registers)
-  struct Stage { uint4 a0, a1, b0, b1; };
+  struct Stage { uint4 a0, a1, a2, a3, b0, b1; };
   auto load = [&](int s) -> Stage {
     const bool first = !KIN && (int64_t)s * SC_K < P.Mp;
     const int64_t k = (int64_t)s * SC_K - (KIN || first ? 0 : P.Mp);
     const uint16_t* pa = (first ? P.xh : P.rh) + k;
     const uint16_t* pb = (first ? P.rh : P.xh) + k;
     Stage R;
-    R.a0 = *reinterpret_cast<const uint4*>(pa + oa0);
-    R.a1 = *reinterpret_cast<const uint4*>(pa + oa1);
-    R.b0 = *reinterpret_cast<const uint4*>(pb + ob0);
-    R.b1 = *reinterpret_cast<const uint4*>(pb + ob1);
+    R.a0 = *reinterpret_cast<const uint4*>(pa + oa[0]);
+    R.a1 = *reinterpret_cast<const uint4*>(pa + oa[1]);
+    R.a2 = *reinterpret_cast<const uint4*>(pa + oa[2]);
+    R.a3 = *reinterpret_cast<const uint4*>(pa + oa[3]);
+    R.b0 = *reinterpret_cast<const uint4*>(pb + ob[0]);
+    R.b1 = *reinterpret_cast<const uint4*>(pb + ob[1]);
     return R;
   };
   auto store = [&](Stage R, int buf) {
-    *reinterpret_cast<uint4*>(As[buf] + wa0) = R.a0;
-    *reinterpret_cast<uint4*>(As[buf] + wa1) = R.a1;
-    *reinterpret_cast<uint4*>(Bs[buf] + wa0) = R.b0;
-    *reinterpret_cast<uint4*>(Bs[buf] + wa1) = R.b1;
+    *reinterpret_cast<uint4*>(As[buf] + wa[0]) = R.a0;
+    *reinterpret_cast<uint4*>(As[buf] + wa[1]) = R.a1;
+    *reinterpret_cast<uint4*>(As[buf] + wa[2]) = R.a2;
+    *reinterpret_cast<uint4*>(As[buf] + wa[3]) = R.a3;
+    *reinterpret_cast<uint4*>(Bs[buf] + wa[0]) = R.b0;
+    *reinterpret_cast<uint4*>(Bs[buf] + wa[1]) = R.b1;
   };
-  floatx4 acc[4][4];
+  floatx4 acc[KS_WM][KS_WN];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < KS_WM; ++m)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[m][q] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
-  int fa[4], fb[4];
+    for (int q = 0; q < KS_WN; ++q) acc[m][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int wr = (w >> 1) * (KS_WM * 16), wc = (w & 1) * (KS_WN * 16);
+  int fa[KS_WM], fb[KS_WN];
 #pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    fa[f] = ks_swz(wr + f * 16 + (lane & 15), lane >> 4);
-    fb[f] = ks_swz(wc + f * 16 + (lane & 15), lane >> 4);
-  }
+  for (int f = 0; f < KS_WM; ++f) fa[f] = ks_swz(wr + f * 16 + (lane & 15), lane >> 4);
+#pragma unroll
+  for (int f = 0; f < KS_WN; ++f) fb[f] = ks_swz(wc + f * 16 + (lane & 15), lane >> 4);
   auto compute = [&](int buf) {
-    halfx8 af[4], bf[4];
+    halfx8 bf[KS_WN];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) af[m] = *reinterpret_cast<const halfx8*>(As[buf] + fa[m]);
+    for (int q = 0; q < KS_WN; ++q) bf[q] = *reinterpret_cast<const halfx8*>(Bs[buf] + fb[q]);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) bf[q] = *reinterpret_cast<const halfx8*>(Bs[buf] + fb[q]);
+    for (int m = 0; m < KS_WM; ++m) {
+      const halfx8 af = *reinterpret_cast<const halfx8*>(As[buf] + fa[m]);
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[m], bf[q], acc[m][q], 0, 0, 0);
+      for (int q = 0; q < KS_WN; ++q)
+        acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af, bf[q], acc[m][q], 0, 0, 0);
+    }
   };
   // n is even (Mp is a multiple of 64).  The loop body has no branches, so
   // every iteration leaves the same loads in flight and none is waited on
@@ -477,116 +490,127 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     return tau > 0.f ? (sqrtf(4.f * tau * tau + 2.f * tau * c) - 2.f * tau) * (1.f - 1e-4f) : 0.f;
   };
   auto thr_lo = [&](float c) { return fl > 0.f ? sqrtf(2.f * fl * c) * (1.f - 1e-4f) : 0.f; };
-  // exact bound of one queued element (histogram or collect)
-  auto settle = [&](bool coll, int i, int j, float e, float c) {
-    if (!coll) {
-      const int hb = ks_bin(kgain_lo(e, c));
-      if (hb >= 0) atomicAdd(&hs[hb], 1u);
-      return;
-    }
-    const float gu = kgain_up(e, c);
-    if (gu < tau) return;
-    if (P.W.keys != nullptr) {
-      // a current (nonzero) coupling is rescored from the W list instead
-      const int64_t ws = rec_hash_find(P.W.keys, P.W.mask, rec_pair_key(i, j, KIN != 0), REC_MAX_PROBE);
-      if (ws >= 0 && P.W.vals[ws] != 0.0) return;
-    }
-    if (!ROBUST) {
-      const int p = atomicAdd(&kc_n, 1);   // p < KS_Q: at most one per queued element
-      kq_key[p] = (uint32_t)(i - r0) << 7 | (uint32_t)(j - c0);
-      kq_e[p] = gu;
-    } else {
-      const int64_t pos = (int64_t)atomicAdd((unsigned long long*)P.cursor, 1ull);
-      if (pos < P.cap) {
-        P.oi[pos] = i;
-        P.oj[pos] = j;
-        P.og[pos] = gu;
-      }
-    }
-  };
-  auto push = [&](bool coll, int li, int lj, float e, float c) {
-    if (ROBUST) {
-      settle(coll, (int)r0 + li, (int)c0 + lj, e, c);
-      return;
-    }
-    const int p = atomicAdd(&kq_n, 1);
-    if (p < KS_Q) {
-      kq_key[p] = (coll ? 0x80000000u : 0u) | (uint32_t)li << 7 | (uint32_t)lj;
-      kq_e[p] = e;
-      kq_c[p] = c;
-    }
-  };
-  float cl1[4], ccv[4], cu[4], ch[4];
+  float cl1[KS_WN], ccv[KS_WN], cu[KS_WN], ch[KS_WN];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < KS_WN; ++q) {
     const int64_t j = c0 + wc + q * 16 + (lane & 15);
     cl1[q] = j < P.N && !KIN ? P.l1[j] : 0.f;
     ccv[q] = j < P.N && !KIN ? P.cv[j] : 0.f;
     cu[q] = KIN ? 0.f : thr_up(ccv[q] + cmin);
     ch[q] = KIN ? 0.f : thr_lo(ccv[q] + cmin);
   }
-  // One gate per element: |a| must reach lambda - er + the collect
-  // threshold or lambda + er + the histogram threshold (kinetic: one value
-  // per row).  Range and triangle checks run only behind the gate (padding
-  // rows and columns hold a = 0).
+  // Every element that passes its gate and the range/threshold checks
+  // enters the block queue (key: bit 31 histogram, bit 30 collect, row << 7 |
+  // column; then |a| and c), which is then settled.  ROBUST: once the queue
+  // is full the rest wait for the next round (done bits: element (m, r, q) is
+  // bit (m*4 + r)*KS_WN + q) until a round fits; otherwise one round, and an
+  // overflow is flagged for the caller.  MODE 0 without ROBUST is the
+  // sampling estimate and histograms inline.
+  uint32_t done[KS_WM * 4 * KS_WN / 32];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int d = 0; d < KS_WM * 4 * KS_WN / 32; ++d) done[d] = 0u;
+  for (;;) {
+    // One gate per element: |a| must reach lambda - er + the collect
+    // threshold or lambda + er + the histogram threshold (kinetic: one value
+    // per row).  Range and triangle checks run only behind the gate (padding
+    // rows and columns hold a = 0).
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int li = wr + m * 16 + 4 * (lane >> 4) + r;
-      const int64_t i = r0 + li;
-      const float rl1 = i < P.N ? P.l1[i] : 0.f, rcv = i < P.N ? P.cv[i] : 0.f;
-      const float ru = thr_up(rcv + cmin), rh = thr_lo(rcv + cmin);
-      const float er_row = P.ce * rl1 + P.el;
-      const float big = __builtin_inff();
-      const float gate_row = fminf(COLLECT ? P.lam - er_row + ru : big, HIST ? P.lam + er_row + rh : big);
+    for (int m = 0; m < KS_WM; ++m)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float aa = fabsf(acc[m][q][r]);
-        float gate = gate_row;
-        if (!KIN) {
-          const float er = er_row + P.ce * cl1[q];
-          gate = fminf(COLLECT ? P.lam - er + fmaxf(ru, cu[q]) : big,
-                       HIST ? P.lam + er + fmaxf(rh, ch[q]) : big);
-        }
-        if (aa >= gate) {
-          const int lj = wc + q * 16 + (lane & 15);
-          const int64_t j = c0 + lj;
-          const bool ok = KIN ? (i < P.N && j < P.N && i != j) : (i < j && j < P.N);
-          const float er = P.ce * (rl1 + cl1[q]) + P.el;
-          if (HIST) {
+      for (int r = 0; r < 4; ++r) {
+        const int li = wr + m * 16 + 4 * (lane >> 4) + r;
+        const int64_t i = r0 + li;
+        const float rl1 = i < P.N ? P.l1[i] : 0.f, rcv = i < P.N ? P.cv[i] : 0.f;
+        const float ru = thr_up(rcv + cmin), rh = thr_lo(rcv + cmin);
+        const float er_row = P.ce * rl1 + P.el;
+        const float big = __builtin_inff();
+        const float gate_row = fminf(COLLECT ? P.lam - er_row + ru : big, HIST ? P.lam + er_row + rh : big);
+#pragma unroll
+        for (int q = 0; q < KS_WN; ++q) {
+          const int bit = (m * 4 + r) * KS_WN + q;
+          const float aa = fabsf(acc[m][q][r]);
+          if (MODE == 0 && !ROBUST) {
+            // sampling estimate: histogram e^2 / (2c) (the quadratic model of
+            // the gain) inline, no queue
+            const float er = er_row + P.ce * cl1[q];
             const float e = aa - er - P.lam;
-            if (ok && e > 0.f && e >= rh && e >= ch[q]) push(false, li, lj, e, rcv + ccv[q]);
+            if (e > 0.f) {
+              const int lj = wc + q * 16 + (lane & 15);
+              const int64_t j = c0 + lj;
+              const bool ok = KIN ? (i < P.N && j < P.N && i != j) : (i < j && j < P.N);
+              const int hb = ks_bin(e * e / (2.f * (rcv + ccv[q])));
+              if (ok && hb >= 0) atomicAdd(&hs[hb], 1u);
+            }
+            continue;
           }
-          if (COLLECT) {
-            const float e = aa + er - P.lam;
-            if (ok && e > 0.f && e >= ru && e >= cu[q]) push(true, li, lj, e, rcv + ccv[q]);
+          float gate = gate_row;
+          if (!KIN) {
+            const float er = er_row + P.ce * cl1[q];
+            gate = fminf(COLLECT ? P.lam - er + fmaxf(ru, cu[q]) : big,
+                         HIST ? P.lam + er + fmaxf(rh, ch[q]) : big);
+          }
+          if (aa >= gate && !((done[bit >> 5] >> (bit & 31)) & 1u)) {
+            const int lj = wc + q * 16 + (lane & 15);
+            const int64_t j = c0 + lj;
+            const bool ok = KIN ? (i < P.N && j < P.N && i != j) : (i < j && j < P.N);
+            const float er = P.ce * (rl1 + cl1[q]) + P.el;
+            const float el = aa - er - P.lam, eu = aa + er - P.lam;
+            const bool h = HIST && ok && el > 0.f && el >= rh && el >= ch[q];
+            const bool cc = COLLECT && ok && eu > 0.f && eu >= ru && eu >= cu[q];
+            bool fin = true;
+            if (h || cc) {
+              const int p = atomicAdd(&kq_n, 1);
+              if (p < KS_Q) {
+                kq_key[p] = (h ? 0x80000000u : 0u) | (cc ? 0x40000000u : 0u) | (uint32_t)li << 7 | (uint32_t)lj;
+                kq_e[p] = aa;
+                kq_c[p] = rcv + ccv[q];
+              } else {
+                fin = false;
+              }
+            }
+            if (fin) done[bit >> 5] |= 1u << (bit & 31);
           }
         }
       }
-    }
-  __syncthreads();
-  if (!ROBUST) {
+    __syncthreads();
+    if (MODE == 0 && !ROBUST) break;
     const int nq = min(kq_n, KS_Q);
-    if (tid == 0 && kq_n > KS_Q) atomicOr(P.ovf, 1);
-    // settle the queue; collected pairs are compacted into the queue's
-    // front (each slot is read before any write can reach it: writes go to
-    // slots below the running count of kept entries, reads happen first)
+    const bool more = kq_n > KS_Q;
+    if (!ROBUST && more && tid == 0) atomicOr(P.ovf, 1);   // the caller falls back to the robust pass
+    // settle: exact bounds; collected pairs are compacted into the queue's
+    // front (every slot of the round is read before the sync, written after)
     uint32_t key[2] = {0u, 0u};
-    float ev[2] = {0.f, 0.f}, cv2[2] = {0.f, 0.f};
-    for (int t0 = 0; t0 < nq; t0 += 512) {
+    float av[2] = {0.f, 0.f}, cv2[2] = {0.f, 0.f};
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int t = t0 + u * 256 + tid;
-        if (t < nq) { key[u] = kq_key[t]; ev[u] = kq_e[t]; cv2[u] = kq_c[t]; }
+    for (int u = 0; u < 2; ++u) {
+      const int t = u * 256 + tid;
+      if (t < nq) { key[u] = kq_key[t]; av[u] = kq_e[t]; cv2[u] = kq_c[t]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int t = u * 256 + tid;
+      if (t >= nq) continue;
+      const int li = (int)((key[u] >> 7) & 255), lj = (int)(key[u] & 127);
+      const int i = (int)r0 + li, j = (int)c0 + lj;
+      const float er = P.ce * (P.l1[i] + (KIN ? 0.f : P.l1[j])) + P.el;
+      if (HIST && (key[u] >> 31)) {
+        const int hb = ks_bin(kgain_lo(av[u] - er - P.lam, cv2[u]));
+        if (hb >= 0) atomicAdd(&hs[hb], 1u);
       }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int t = t0 + u * 256 + tid;
-        if (t < nq)
-          settle((key[u] >> 31) != 0, (int)r0 + (int)((key[u] >> 7) & 127), (int)c0 + (int)(key[u] & 127),
-                 ev[u], cv2[u]);
+      if (COLLECT && ((key[u] >> 30) & 1u)) {
+        const float gu = kgain_up(av[u] + er - P.lam, cv2[u]);
+        bool keep = gu >= tau;
+        if (keep && P.W.keys != nullptr) {
+          // a current (nonzero) coupling is handled with the W list instead
+          const int64_t ws = rec_hash_find(P.W.keys, P.W.mask, rec_pair_key(i, j, KIN != 0), REC_MAX_PROBE);
+          if (ws >= 0 && P.W.vals[ws] != 0.0) keep = false;
+        }
+        if (keep) {
+          const int pc = atomicAdd(&kc_n, 1);   // pc < KS_Q: at most one per queued element
+          kq_key[pc] = (uint32_t)li << 7 | (uint32_t)lj;
+          kq_e[pc] = gu;
+        }
       }
     }
     if (COLLECT) {
@@ -597,18 +621,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       for (int t = tid; t < nc; t += 256) {
         const int64_t pos = kbase + t;
         if (pos < P.cap) {
-          P.oi[pos] = (int32_t)(r0 + ((kq_key[t] >> 7) & 127));
+          P.oi[pos] = (int32_t)(r0 + ((kq_key[t] >> 7) & 255));
           P.oj[pos] = (int32_t)(c0 + (kq_key[t] & 127));
           P.og[pos] = kq_e[t];
         }
       }
     }
-  }
-  if (HIST) {
     __syncthreads();
+    if (!ROBUST || !more) break;
+    if (tid == 0) { kq_n = 0; kc_n = 0; }
+    __syncthreads();
+  }
+  if (HIST)
     for (int q = tid; q < KS_BINS; q += 256)
       if (hs[q]) atomicAdd(&P.hist[q], hs[q]);
-  }
 }
 
 // Current couplings (w0 != 0).  With s = sign(w0), |w0 + d| - |w0| >= s d for
@@ -794,7 +820,7 @@ KScreenArgs ks_args(rec_ctx* ctx) {
   P.tau = ctx->sc_tau;
   P.hfloor = nullptr;
   P.hist = nullptr;
-  P.ovf = nullptr;
+  P.ovf = reinterpret_cast<int32_t*>(ctx->sc_tau + 4);
   return P;
 }
 
@@ -813,25 +839,24 @@ rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
     hipLaunchKernelGGL(k_kscreen_prep<double>, dim3(N), dim3(256), 0, s, ctx->F, ctx->sc_l1, ctx->sc_cv);
   hipLaunchKernelGGL(k_ks_cvmin, dim3(1), dim3(1024), 0, s, ctx->sc_cv, N, cvmin);
   KScreenArgs P = ks_args(ctx);
-  int32_t* ovf = (int32_t*)(ctx->sc_tau + 4);
-  P.ovf = ovf;
-  const int nb = (int)((N + SC_T - 1) / SC_T);
+  const int nb = (int)((N + KS_BM - 1) / KS_BM);     // row tiles
+  const int nbc = (int)((N + KS_BN - 1) / KS_BN);    // column tiles
   uint32_t* hist_s = ctx->sc_hist;
   uint32_t* hist_f = ctx->sc_hist + KS_BINS;
   REC_HIP(hipMemsetAsync(ctx->sc_hist, 0, 2 * KS_BINS * sizeof(uint32_t), s));
   REC_HIP(hipMemsetAsync(P.cursor, 0, sizeof(int64_t), s));
-  REC_HIP(hipMemsetAsync(ovf, 0, sizeof(int32_t), s));
-  // sample: every step-th row tile, histogrammed without a floor (inline path)
+  REC_HIP(hipMemsetAsync(P.ovf, 0, sizeof(int32_t), s));
+  // sample: every step-th row tile, histogram of the quadratic gain model
   const int step = std::max(1, std::min(KS_SAMPLE, nb / 8));
   const int nbs = (nb + step - 1) / step;
   P.hist = hist_s;
-  REC_TRY_ST(launch_ks<0, 1>(ctx, P, nbs, nb, step));
+  REC_TRY_ST(launch_ks<0, 0>(ctx, P, nbs, nbc, step));
   const int64_t ts = std::max<int64_t>(1, 2 * target / step);
   hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_s, ts, tau_c, floor);
   // full pass: histogram from the floor up, collect at tau_c
   P.hist = hist_f;
   P.hfloor = floor;
-  REC_TRY_ST(launch_ks<2, 0>(ctx, P, nb, nb, 1));
+  REC_TRY_ST(launch_ks<2, 0>(ctx, P, nb, nbc, 1));
   hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_f, target, tau_f, (float*)nullptr);
   REC_HIP(hipGetLastError());
   int64_t n = 0;
@@ -843,19 +868,19 @@ rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
   memcpy(&over, &tau[4], sizeof(int32_t));
   // The collected set is complete when the proven threshold is at least the
   // one used and no block queue overflowed.  Otherwise collect again at the
-  // proven threshold (inline path), first refreshing the histogram without a
-  // floor when the threshold fell below the floor (counts under it are
-  // partial) or a queue overflowed (counts were dropped).
+  // proven threshold with the robust kernel, first refreshing the histogram
+  // without a floor when the threshold fell below the floor (the counts
+  // under it are partial) or a queue overflowed (counts were dropped).
   if (over || n > ctx->cand_cap || tau[1] < tau[0]) {
     if (over || tau[1] < tau[2]) {
       REC_HIP(hipMemsetAsync(hist_f, 0, KS_BINS * sizeof(uint32_t), s));
       P.hfloor = nullptr;
-      REC_TRY_ST(launch_ks<0, 1>(ctx, P, nb, nb, 1));
+      REC_TRY_ST(launch_ks<0, 1>(ctx, P, nb, nbc, 1));
       hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_f, target, tau_f, (float*)nullptr);
     }
     REC_HIP(hipMemcpyAsync(tau_c, tau_f, sizeof(float), hipMemcpyDeviceToDevice, s));
     REC_HIP(hipMemsetAsync(P.cursor, 0, sizeof(int64_t), s));
-    REC_TRY_ST(launch_ks<1, 1>(ctx, P, nb, nb, 1));
+    REC_TRY_ST(launch_ks<1, 1>(ctx, P, nb, nbc, 1));
     REC_HIP(hipGetLastError());
     REC_HIP(hipMemcpyAsync(&n, P.cursor, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     REC_HIP(hipStreamSynchronize(s));

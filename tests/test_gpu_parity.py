@@ -548,6 +548,22 @@ def test_screen_search_equals_exhaustive(model, prec):
 
 
 @pytest.mark.parametrize("model", ["ising", "kinetic"])
+def test_screen_overflow_fallback(model):
+    """With m = 20 N the survivors of a tile outnumber the block queue, so the
+    full pass flags an overflow and the call finishes through the robust
+    (round-based) histogram and collect passes; the result is still the
+    exhaustive search's positive-gain top m."""
+    w = SCREEN_CASES[model]()
+    lam = oracle.default_lambda(w.X, model)
+    C = ctx_for(w, lam, "fp32", kappa=20.0)
+    C.screen_time()
+    npos, _ = screen_equals_exhaustive(C, C.m)
+    assert npos > w.N
+    st = C.screen_time()
+    assert st["second_collect"] >= 1, st
+
+
+@pytest.mark.parametrize("model", ["ising", "kinetic"])
 def test_screen_sweeps_track_oracle(model):
     """GCD sweeps over the screened search against the oracle.  The ranked
     gains equal the oracle's exhaustive top m to 1e-10 relative; the oracle
