@@ -313,13 +313,16 @@ __device__ __forceinline__ float kgain_up(float e, float c) {
   return 0.25f * c * p * (1.f + 1e-5f);
 }
 
-// LDS operand layout: 128 rows x 32 fp16 (64-byte rows, no padding); the
-// 16-byte chunk c of row r sits at chunk position c ^ f(r) with
-// f(r) = ((r >> 1) ^ (r >> 3)) & 3.  A fragment read (rows 16k..16k+15 at
-// one chunk) and a staging write (whole rows 4j..4j+3) then touch distinct
-// 16-byte bank groups within every 8 lanes (128-byte bank rows) and every 16
-// lanes (256-byte bank rows): no bank conflicts either way.
-__device__ __forceinline__ int ks_swz(int r, int c) { return r * SC_K + 8 * (c ^ (((r >> 1) ^ (r >> 3)) & 3)); }
+// LDS operand layout: rows of 32 fp16 (64 bytes, no padding), two rows per
+// 128-byte line; the 16-byte chunk c of row r sits at slot
+// ((r & 1) * 4 + c) ^ ((r >> 1) & 7) of line r >> 1.  Measured on gfx950 with
+// the LDS bank-conflict counters: a fragment read (16 consecutive rows at one
+// chunk per 16 lanes) and a staging write (4 lanes per row) are both
+// conflict-free; 80-byte padded rows, plain 64-byte rows and an XOR over
+// 256-byte lines all give 2-way conflicts on the fragment reads.
+__device__ __forceinline__ int ks_swz(int r, int c) {
+  return (r >> 1) * (2 * SC_K) + 8 * ((((r & 1) << 2) | c) ^ ((r >> 1) & 7));
+}
 
 
 // Histogram of positive float bounds for the Ising / kinetic screen: 16 bins
@@ -490,14 +493,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     return tau > 0.f ? (sqrtf(4.f * tau * tau + 2.f * tau * c) - 2.f * tau) * (1.f - 1e-4f) : 0.f;
   };
   auto thr_lo = [&](float c) { return fl > 0.f ? sqrtf(2.f * fl * c) * (1.f - 1e-4f) : 0.f; };
+  // Per-row and per-column terms, one thread per row / column, into LDS (the
+  // operand buffers are free after the k loop): row (er_i, c_i, up_i, lo_i)
+  // with er_i = ce |r_i|_1 + el and up/lo the gate thresholds at c_i + min c;
+  // column (ce |r_j|_1, c_j, up_j, lo_j) (Ising; zeros for kinetic).
+  float4* rowv = reinterpret_cast<float4*>(&As[0][0]);
+  float4* colv = rowv + KS_BM;
+  for (int t = tid; t < KS_BM + KS_BN; t += 256) {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (t < KS_BM) {
+      const int64_t i = r0 + t;
+      const float l1 = i < P.N ? P.l1[i] : 0.f, c = i < P.N ? P.cv[i] : 0.f;
+      v = make_float4(P.ce * l1 + P.el, c, thr_up(c + cmin), thr_lo(c + cmin));
+      rowv[t] = v;
+    } else if (!KIN) {
+      const int64_t j = c0 + (t - KS_BM);
+      const float l1 = j < P.N ? P.l1[j] : 0.f, c = j < P.N ? P.cv[j] : 0.f;
+      v = make_float4(P.ce * l1, c, thr_up(c + cmin), thr_lo(c + cmin));
+      colv[t - KS_BM] = v;
+    } else {
+      colv[t - KS_BM] = v;
+    }
+  }
+  __syncthreads();
   float cl1[KS_WN], ccv[KS_WN], cu[KS_WN], ch[KS_WN];
 #pragma unroll
   for (int q = 0; q < KS_WN; ++q) {
-    const int64_t j = c0 + wc + q * 16 + (lane & 15);
-    cl1[q] = j < P.N && !KIN ? P.l1[j] : 0.f;
-    ccv[q] = j < P.N && !KIN ? P.cv[j] : 0.f;
-    cu[q] = KIN ? 0.f : thr_up(ccv[q] + cmin);
-    ch[q] = KIN ? 0.f : thr_lo(ccv[q] + cmin);
+    const float4 v = colv[wc + q * 16 + (lane & 15)];
+    cl1[q] = v.x;
+    ccv[q] = v.y;
+    cu[q] = v.z;
+    ch[q] = v.w;
   }
   // Every element that passes its gate and the range/threshold checks
   // enters the block queue (key: bit 31 histogram, bit 30 collect, row << 7 |
@@ -520,9 +546,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       for (int r = 0; r < 4; ++r) {
         const int li = wr + m * 16 + 4 * (lane >> 4) + r;
         const int64_t i = r0 + li;
-        const float rl1 = i < P.N ? P.l1[i] : 0.f, rcv = i < P.N ? P.cv[i] : 0.f;
-        const float ru = thr_up(rcv + cmin), rh = thr_lo(rcv + cmin);
-        const float er_row = P.ce * rl1 + P.el;
+        const float4 rv = rowv[li];
+        const float er_row = rv.x, rcv = rv.y, ru = rv.z, rh = rv.w;
         const float big = __builtin_inff();
         const float gate_row = fminf(COLLECT ? P.lam - er_row + ru : big, HIST ? P.lam + er_row + rh : big);
 #pragma unroll
@@ -532,7 +557,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           if (MODE == 0 && !ROBUST) {
             // sampling estimate: histogram e^2 / (2c) (the quadratic model of
             // the gain) inline, no queue
-            const float er = er_row + P.ce * cl1[q];
+            const float er = er_row + cl1[q];
             const float e = aa - er - P.lam;
             if (e > 0.f) {
               const int lj = wc + q * 16 + (lane & 15);
@@ -545,7 +570,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           }
           float gate = gate_row;
           if (!KIN) {
-            const float er = er_row + P.ce * cl1[q];
+            const float er = er_row + cl1[q];
             gate = fminf(COLLECT ? P.lam - er + fmaxf(ru, cu[q]) : big,
                          HIST ? P.lam + er + fmaxf(rh, ch[q]) : big);
           }
@@ -553,7 +578,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             const int lj = wc + q * 16 + (lane & 15);
             const int64_t j = c0 + lj;
             const bool ok = KIN ? (i < P.N && j < P.N && i != j) : (i < j && j < P.N);
-            const float er = P.ce * (rl1 + cl1[q]) + P.el;
+            const float er = er_row + cl1[q];
             const float el = aa - er - P.lam, eu = aa + er - P.lam;
             const bool h = HIST && ok && el > 0.f && el >= rh && el >= ch[q];
             const bool cc = COLLECT && ok && eu > 0.f && eu >= ru && eu >= cu[q];
