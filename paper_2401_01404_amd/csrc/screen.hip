@@ -361,24 +361,29 @@ __device__ __forceinline__ bool ks_tile(const TileMap& T, int b, int* bi, int* b
   return *bi < T.nbi && *bj < T.nbj;
 }
 
-// One 128 x 128 tile of the contraction per block (4 waves of 64 x 64, each
-// 4 x 4 MFMA 16x16x32 blocks).  Operands go global -> registers two k steps
-// ahead of use and registers -> LDS one step ahead (LDS double-buffered), so
-// a load has two steps of MFMA work to arrive.  Ising: tiles on or above the
-// diagonal, k in [0, Mp) pairs x_i with r_j and k in [Mp, 2Mp) r_i with x_j.
+// One KS_BM x KS_BN tile of the contraction per block (8 waves of 128 x 64,
+// each 8 x 4 MFMA 16x16x32 blocks).  Operands go global -> registers two k
+// steps ahead of use and registers -> LDS one step ahead (LDS double-buffered),
+// so a load has two steps of MFMA work to arrive.  Ising: tiles that hold a
+// pair i < j, k in [0, Mp) pairs x_i with r_j and k in [Mp, 2Mp) r_i with x_j.
 // Kinetic: every tile, rows are targets (r_i), columns sources (x_j).
 // MODE 0: histogram of lower bounds; 1: collect pairs whose upper bound
 // reaches *tau; 2: both.  Row tiles are taken every row_step-th (sampling).
-constexpr int KS_Q = 512;   // per-block queue of elements that passed the cheap tests (LDS)
-// Tile of the contraction: 4 wavefronts in 2 x 2, each KS_WM x KS_WN blocks of
-// 16 x 16 outputs; the block covers KS_BM rows x KS_BN columns.
+// Tile of the contraction: KS_THREADS / 64 wavefronts in KS_WR x KS_WC, each
+// KS_WM x KS_WN blocks of 16 x 16 outputs; the block covers KS_BM rows x
+// KS_BN columns.
+constexpr int KS_THREADS = 512;
+constexpr int KS_WR = 2, KS_WC = 4;
 constexpr int KS_WM = 8, KS_WN = 4;
-constexpr int KS_BM = 2 * KS_WM * 16, KS_BN = 2 * KS_WN * 16;
+constexpr int KS_BM = KS_WR * KS_WM * 16, KS_BN = KS_WC * KS_WN * 16;
+constexpr int KS_Q = 2 * KS_THREADS;   // per-block queue of elements that passed the cheap tests (LDS)
+static_assert(KS_WR * KS_WC * REC_WAVE == KS_THREADS, "one wavefront per sub-tile");
 static_assert(KS_BM <= REC_TAIL_ROWS && KS_BN <= REC_TAIL_ROWS, "tiles must stay inside the zero tail");
-static_assert(KS_BM <= 256 && KS_BN <= 128, "queue keys hold 8-bit rows and 7-bit columns");
+static_assert(KS_BM <= 256 && KS_BN <= 256, "queue keys hold 8-bit rows and columns");
+static_assert(KS_BM % (KS_THREADS / 4) == 0 && KS_BN % (KS_THREADS / 4) == 0, "staging rows per thread");
 
 template <int MODE, int KIN, int ROBUST>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_kscreen(KScreenArgs P, TileMap TM, int row_step) {
+__global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_kscreen(KScreenArgs P, TileMap TM, int row_step) {
   int bi, bj;
   if (!ks_tile(TM, blockIdx.x, &bi, &bj)) return;
   bi *= row_step;
@@ -388,33 +393,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   __shared__ __attribute__((aligned(16))) _Float16 As[2][KS_BM * SC_K];
   __shared__ __attribute__((aligned(16))) _Float16 Bs[2][KS_BN * SC_K];
   __shared__ uint32_t hs[HIST ? KS_BINS : 1];
-  __shared__ uint32_t kq_key[KS_Q];   // bit 31: collect (else histogram); row << 7 | column in the tile
+  __shared__ uint32_t kq_key[KS_Q];   // bit 31 histogram, bit 30 collect; row << 8 | column in the tile
   __shared__ float kq_e[KS_Q], kq_c[KS_Q];
   __shared__ int kq_n, kc_n;
   __shared__ int64_t kbase;
   const int tid = threadIdx.x, lane = tid & (REC_WAVE - 1), w = tid / REC_WAVE;
   if (HIST)
-    for (int q = tid; q < KS_BINS; q += 256) hs[q] = 0;
+    for (int q = tid; q < KS_BINS; q += KS_THREADS) hs[q] = 0;
   if (tid == 0) { kq_n = 0; kc_n = 0; }
   // Staging: thread tid moves the 8-sample chunk (tid & 3) of rows tid/4 +
-  // 64u of both operands (u < KS_BM/64 for A, < KS_BN/64 for B).  Operand rows
-  // are fp16 (x copy and residuals) with zero rows past N, so no load needs a
-  // bound check.  Ising: in the first half of k, A = x and B = r; in the
-  // second, A = r and B = x.  Kinetic: A = r (targets), B = x (sources).
+  // (KS_THREADS/4) u of both operands.  Operand rows are fp16 (x copy and
+  // residuals) with zero rows past N, so no load needs a bound check.  Ising:
+  // in the first half of k, A = x and B = r; in the second, A = r and B = x.
+  // Kinetic: A = r (targets), B = x (sources).
+  constexpr int SRS = KS_THREADS / 4;   // staging row stride
+  constexpr int NA = KS_BM / SRS, NB = KS_BN / SRS;
+  static_assert(NA == 2 && NB == 2, "stage layout below holds two rows per operand");
   const int n = P.nsteps;
   const int sr = tid >> 2, part = tid & 3;
-  uint32_t oa[4], ob[2];
-  int wa[4];
+  uint32_t oa[NA], ob[NB];
+  int wa[NA];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    oa[u] = (uint32_t)((r0 + sr + 64 * u) * P.Mp + part * 8);
-    wa[u] = ks_swz(sr + 64 * u, part);
+  for (int u = 0; u < NA; ++u) {
+    oa[u] = (uint32_t)((r0 + sr + SRS * u) * P.Mp + part * 8);
+    wa[u] = ks_swz(sr + SRS * u, part);
   }
 #pragma unroll
-  for (int u = 0; u < 2; ++u) ob[u] = (uint32_t)((c0 + sr + 64 * u) * P.Mp + part * 8);
+  for (int u = 0; u < NB; ++u) ob[u] = (uint32_t)((c0 + sr + SRS * u) * P.Mp + part * 8);
   // staged values travel by value (no addressable aggregates: they stay in
   // registers)
-  struct Stage { uint4 a0, a1, a2, a3, b0, b1; };
+  struct Stage { uint4 a0, a1, b0, b1; };
   auto load = [&](int s) -> Stage {
     const bool first = !KIN && (int64_t)s * SC_K < P.Mp;
     const int64_t k = (int64_t)s * SC_K - (KIN || first ? 0 : P.Mp);
@@ -423,8 +431,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     Stage R;
     R.a0 = *reinterpret_cast<const uint4*>(pa + oa[0]);
     R.a1 = *reinterpret_cast<const uint4*>(pa + oa[1]);
-    R.a2 = *reinterpret_cast<const uint4*>(pa + oa[2]);
-    R.a3 = *reinterpret_cast<const uint4*>(pa + oa[3]);
     R.b0 = *reinterpret_cast<const uint4*>(pb + ob[0]);
     R.b1 = *reinterpret_cast<const uint4*>(pb + ob[1]);
     return R;
@@ -432,8 +438,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   auto store = [&](Stage R, int buf) {
     *reinterpret_cast<uint4*>(As[buf] + wa[0]) = R.a0;
     *reinterpret_cast<uint4*>(As[buf] + wa[1]) = R.a1;
-    *reinterpret_cast<uint4*>(As[buf] + wa[2]) = R.a2;
-    *reinterpret_cast<uint4*>(As[buf] + wa[3]) = R.a3;
     *reinterpret_cast<uint4*>(Bs[buf] + wa[0]) = R.b0;
     *reinterpret_cast<uint4*>(Bs[buf] + wa[1]) = R.b1;
   };
@@ -442,7 +446,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   for (int m = 0; m < KS_WM; ++m)
 #pragma unroll
     for (int q = 0; q < KS_WN; ++q) acc[m][q] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int wr = (w >> 1) * (KS_WM * 16), wc = (w & 1) * (KS_WN * 16);
+  const int wr = (w / KS_WC) * (KS_WM * 16), wc = (w % KS_WC) * (KS_WN * 16);
   int fa[KS_WM], fb[KS_WN];
 #pragma unroll
   for (int f = 0; f < KS_WM; ++f) fa[f] = ks_swz(wr + f * 16 + (lane & 15), lane >> 4);
@@ -499,7 +503,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   // column (ce |r_j|_1, c_j, up_j, lo_j) (Ising; zeros for kinetic).
   float4* rowv = reinterpret_cast<float4*>(&As[0][0]);
   float4* colv = rowv + KS_BM;
-  for (int t = tid; t < KS_BM + KS_BN; t += 256) {
+  for (int t = tid; t < KS_BM + KS_BN; t += KS_THREADS) {
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
     if (t < KS_BM) {
       const int64_t i = r0 + t;
@@ -526,7 +530,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     ch[q] = v.w;
   }
   // Every element that passes its gate and the range/threshold checks
-  // enters the block queue (key: bit 31 histogram, bit 30 collect, row << 7 |
+  // enters the block queue (key: bit 31 histogram, bit 30 collect, row << 8 |
   // column; then |a| and c), which is then settled.  ROBUST: once the queue
   // is full the rest wait for the next round (done bits: element (m, r, q) is
   // bit (m*4 + r)*KS_WN + q) until a round fits; otherwise one round, and an
@@ -586,7 +590,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             if (h || cc) {
               const int p = atomicAdd(&kq_n, 1);
               if (p < KS_Q) {
-                kq_key[p] = (h ? 0x80000000u : 0u) | (cc ? 0x40000000u : 0u) | (uint32_t)li << 7 | (uint32_t)lj;
+                kq_key[p] = (h ? 0x80000000u : 0u) | (cc ? 0x40000000u : 0u) | (uint32_t)li << 8 | (uint32_t)lj;
                 kq_e[p] = aa;
                 kq_c[p] = rcv + ccv[q];
               } else {
@@ -608,15 +612,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     float av[2] = {0.f, 0.f}, cv2[2] = {0.f, 0.f};
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int t = u * 256 + tid;
+      const int t = u * KS_THREADS + tid;
       if (t < nq) { key[u] = kq_key[t]; av[u] = kq_e[t]; cv2[u] = kq_c[t]; }
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int t = u * 256 + tid;
+      const int t = u * KS_THREADS + tid;
       if (t >= nq) continue;
-      const int li = (int)((key[u] >> 7) & 255), lj = (int)(key[u] & 127);
+      const int li = (int)((key[u] >> 8) & 255), lj = (int)(key[u] & 255);
       const int i = (int)r0 + li, j = (int)c0 + lj;
       const float er = P.ce * (P.l1[i] + (KIN ? 0.f : P.l1[j])) + P.el;
       if (HIST && (key[u] >> 31)) {
@@ -633,7 +637,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
         if (keep) {
           const int pc = atomicAdd(&kc_n, 1);   // pc < KS_Q: at most one per queued element
-          kq_key[pc] = (uint32_t)li << 7 | (uint32_t)lj;
+          kq_key[pc] = (uint32_t)li << 8 | (uint32_t)lj;
           kq_e[pc] = gu;
         }
       }
@@ -643,11 +647,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const int nc = kc_n;
       if (tid == 0 && nc > 0) kbase = (int64_t)atomicAdd((unsigned long long*)P.cursor, (unsigned long long)nc);
       __syncthreads();
-      for (int t = tid; t < nc; t += 256) {
+      for (int t = tid; t < nc; t += KS_THREADS) {
         const int64_t pos = kbase + t;
         if (pos < P.cap) {
-          P.oi[pos] = (int32_t)(r0 + ((kq_key[t] >> 7) & 255));
-          P.oj[pos] = (int32_t)(c0 + (kq_key[t] & 127));
+          P.oi[pos] = (int32_t)(r0 + ((kq_key[t] >> 8) & 255));
+          P.oj[pos] = (int32_t)(c0 + (kq_key[t] & 255));
           P.og[pos] = kq_e[t];
         }
       }
@@ -658,7 +662,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     __syncthreads();
   }
   if (HIST)
-    for (int q = tid; q < KS_BINS; q += 256)
+    for (int q = tid; q < KS_BINS; q += KS_THREADS)
       if (hs[q]) atomicAdd(&P.hist[q], hs[q]);
 }
 
@@ -809,10 +813,10 @@ rec_status launch_ks(rec_ctx* ctx, const KScreenArgs& P, int nbi, int nbj, int r
   rec_status st = ev_begin(ctx);
   if (st != REC_OK) return st;
   if (ctx->cfg.model == REC_KINETIC)
-    hipLaunchKernelGGL((k_kscreen<MODE, 1, ROBUST>), dim3((unsigned)grid), dim3(256), 0, ctx->stream, P, T,
+    hipLaunchKernelGGL((k_kscreen<MODE, 1, ROBUST>), dim3((unsigned)grid), dim3(KS_THREADS), 0, ctx->stream, P, T,
                        row_step);
   else
-    hipLaunchKernelGGL((k_kscreen<MODE, 0, ROBUST>), dim3((unsigned)grid), dim3(256), 0, ctx->stream, P, T,
+    hipLaunchKernelGGL((k_kscreen<MODE, 0, ROBUST>), dim3((unsigned)grid), dim3(KS_THREADS), 0, ctx->stream, P, T,
                        row_step);
   return ev_end(ctx, row_step == 1 ? 0 : 1, row_step == 1 ? flops : 0.0);
 }
