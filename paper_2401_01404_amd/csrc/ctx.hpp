@@ -92,6 +92,10 @@ struct rec_ctx {
   Cache C;
   SortBufs sb;
   int64_t max_nnz;
+  // W changes bump w_version; a compaction (sorted lists, row lists) is
+  // reused while the version it was made at is current
+  uint64_t w_version = 1, w_compacted = 0;
+  int64_t w_nnz = 0;
 
   // W as sorted row lists (CSR) for the field rebuild
   int64_t* row_off;     // N+1
@@ -214,6 +218,8 @@ rec_status rec_fit_theta(rec_ctx* ctx);                   // theta update + fiel
 rec_status rec_eval_objective(rec_ctx* ctx, double* out);
 rec_status rec_wtable_compact(rec_ctx* ctx, int64_t* nnz); // W table -> wi/wj/wv (sorted)
 void rec_wtable_clear(rec_ctx* ctx);
+// sum of n doubles into *out (device), deterministic; uses dscratch
+rec_status rec_sum_device(rec_ctx* ctx, const double* x, int64_t n, double* out);
 rec_status rec_wtable_insert_list(rec_ctx* ctx, int64_t n, const int32_t* ei, const int32_t* ej,
                                   const double* w);
 

@@ -283,6 +283,18 @@ __global__ __launch_bounds__(FT) void k_abs_partial(const double* w, int64_t n, 
   part[c] = acc;
 }
 
+// Contiguous-chunk partial sums (fixed order, so the total is reproducible).
+__global__ __launch_bounds__(FT) void k_sum_partial(const double* x, int64_t n, double* part,
+                                                    int64_t nchunk) {
+  int64_t c = (int64_t)blockIdx.x * FT + threadIdx.x;
+  if (c >= nchunk) return;
+  int64_t per = (n + nchunk - 1) / nchunk;
+  int64_t b = c * per, e = b + per < n ? b + per : n;
+  double acc = 0.0;
+  for (int64_t k = b; k < e; ++k) acc += x[k];
+  part[c] = acc;
+}
+
 __global__ void k_combine_obj(const double* ll, const double* pen, double lambda, double* out) {
   *out = *ll - lambda * *pen;
 }
@@ -423,6 +435,7 @@ rec_status rec_load_data(rec_ctx* ctx, const void* X, int64_t ldx) {
 }
 
 void rec_wtable_clear(rec_ctx* ctx) {
+  ++ctx->w_version;
   hipMemsetAsync(ctx->W.keys, 0xff, (ctx->W.mask + 1) * sizeof(uint64_t), ctx->stream);
   hipMemsetAsync(ctx->W.count, 0, sizeof(int64_t), ctx->stream);
 }
@@ -430,6 +443,7 @@ void rec_wtable_clear(rec_ctx* ctx) {
 rec_status rec_wtable_insert_list(rec_ctx* ctx, int64_t n, const int32_t* ei, const int32_t* ej,
                                   const double* w) {
   if (n <= 0) return REC_OK;
+  ++ctx->w_version;
   hipLaunchKernelGGL(k_winsert, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, ctx->W, n, ei, ej,
                      w, ctx->cfg.N, ctx->cfg.model == REC_KINETIC ? 1 : 0, ctx->err_flag);
   REC_HIP(hipGetLastError());
@@ -438,6 +452,10 @@ rec_status rec_wtable_insert_list(rec_ctx* ctx, int64_t n, const int32_t* ei, co
 
 // Sorted list of nonzero W entries into wi/wj/wv, then the row lists.
 rec_status rec_wtable_compact(rec_ctx* ctx, int64_t* nnz_out) {
+  if (ctx->w_compacted == ctx->w_version) {
+    *nnz_out = ctx->w_nnz;
+    return REC_OK;
+  }
   const uint64_t cap = ctx->W.mask + 1;
   int64_t* d_n = ctx->counter + 4;
   REC_HIP(hipMemsetAsync(d_n, 0, sizeof(int64_t), ctx->stream));
@@ -477,6 +495,8 @@ rec_status rec_wtable_compact(rec_ctx* ctx, int64_t* nnz_out) {
     hipLaunchKernelGGL(k_csr_fill, dim3((nrec + 255) / 256), dim3(256), 0, ctx->stream,
                        ctx->sb.klo[cur], ctx->sb.val[cur], ctx->wv, nrec, ctx->col, ctx->colw);
   REC_HIP(hipGetLastError());
+  ctx->w_compacted = ctx->w_version;
+  ctx->w_nnz = n;
   *nnz_out = n;
   return REC_OK;
 }
@@ -490,6 +510,15 @@ rec_status rec_rebuild_fields(rec_ctx* ctx) {
 
 rec_status rec_fit_theta(rec_ctx* ctx) {
   return ctx->fp32 ? launch_theta_r<float>(ctx) : launch_theta_r<double>(ctx);
+}
+
+rec_status rec_sum_device(rec_ctx* ctx, const double* x, int64_t n, double* out) {
+  const int64_t nchunk = 1024;
+  hipLaunchKernelGGL(k_sum_partial, dim3((unsigned)(nchunk / FT)), dim3(FT), 0, ctx->stream, x, n,
+                     ctx->dscratch, nchunk);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(FT), 0, ctx->stream, ctx->dscratch, nchunk, out);
+  REC_HIP(hipGetLastError());
+  return REC_OK;
 }
 
 rec_status rec_eval_objective(rec_ctx* ctx, double* out) {

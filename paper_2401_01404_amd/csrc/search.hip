@@ -808,21 +808,6 @@ __global__ void k_count_pos(const double* dw, int64_t m, int64_t* cnt) {
   if (rec_lane() == 0 && c) atomicAdd((unsigned long long*)cnt, (unsigned long long)c);
 }
 
-__global__ void k_sum1(const double* x, int64_t n, double* out) {
-  __shared__ double sh[BT / REC_WAVE];
-  double acc = 0.0;
-  int64_t per = (n + BT - 1) / BT;
-  int64_t b = (int64_t)threadIdx.x * per, e = b + per < n ? b + per : n;
-  for (int64_t k = b; k < e; ++k) acc += x[k];
-  acc = rec_wave_sum(acc);
-  if (rec_lane() == 0) sh[threadIdx.x / REC_WAVE] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < BT / REC_WAVE; ++w) s += sh[w];
-    *out = s;
-  }
-}
 
 inline int64_t gridn(int64_t n, int b = 256) { return (n + b - 1) / b; }
 
@@ -1459,7 +1444,8 @@ rec_status rec_apply_best(rec_ctx* ctx, int64_t m, const int32_t* I, const int32
   }
   (void)d_rem;
   *rounds = pass;
-  hipLaunchKernelGGL(k_sum1, dim3(1), dim3(BT), 0, s, ctx->dw, m, ctx->dresult + 3);
+  ++ctx->w_version;   // the rounds changed W
+  if (rec_sum_device(ctx, ctx->dw, m, ctx->dresult + 3) != REC_OK) return REC_E_HIP;
   hipMemsetAsync(ctx->counter + 11, 0, sizeof(int64_t), s);
   hipLaunchKernelGGL(k_count_pos, dim3(gridn(m)), dim3(256), 0, s, ctx->dw, m, ctx->counter + 11);
   hipMemcpyAsync(delta, ctx->dresult + 3, sizeof(double), hipMemcpyDeviceToHost, s);
