@@ -706,3 +706,26 @@ def test_full_size_screen_equals_exhaustive(cid):
     assert close(G2[pick], go, RTOL["fp32"], w.M).all()
     del C
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("cid", ["C2", "C4"])
+def test_full_size_sweep_objective_matches_oracle(cid):
+    """One screened GCD sweep at the full benchmark size in FP32 against the
+    FP64 oracle: the oracle applies the GPU's E_best (the exhaustive top m,
+    see the test above) in its rank order and refits theta; the objectives
+    agree to 1e-6 relative and the summed |dW| to 1e-5."""
+    import torch
+    w = synth.config(cid)
+    lam = oracle.default_lambda(w.X, w.model)
+    C = ctx_for(w, lam, "fp32")
+    I, J, G, _ = C.find_best(C.m, "screen")
+    I, J = I.cpu().numpy(), J.cpu().numpy()
+    st = C.sweep("screen")
+    O = oracle.Oracle(w.X, w.model, lam)
+    d_or, _ = O.apply_updates(I, J)
+    O.theta_update()
+    obj = O.objective()
+    assert abs(st["objective"] - obj) <= 1e-6 * abs(obj), (st, obj)
+    assert abs(st["delta"] - d_or) <= 1e-5 * max(1.0, d_or), (st["delta"], d_or)
+    del C
+    torch.cuda.empty_cache()
