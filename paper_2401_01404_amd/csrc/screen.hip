@@ -313,16 +313,13 @@ __device__ __forceinline__ float kgain_up(float e, float c) {
   return 0.25f * c * p * (1.f + 1e-5f);
 }
 
-// LDS operand layout: rows of 32 fp16 (64 bytes, no padding), two rows per
-// 128-byte line; the 16-byte chunk c of row r sits at slot
-// ((r & 1) * 4 + c) ^ ((r >> 1) & 7) of line r >> 1.  Measured on gfx950 with
-// the LDS bank-conflict counters: a fragment read (16 consecutive rows at one
-// chunk per 16 lanes) and a staging write (4 lanes per row) are both
-// conflict-free; 80-byte padded rows, plain 64-byte rows and an XOR over
-// 256-byte lines all give 2-way conflicts on the fragment reads.
-__device__ __forceinline__ int ks_swz(int r, int c) {
-  return (r >> 1) * (2 * SC_K) + 8 * ((((r & 1) << 2) | c) ^ ((r >> 1) & 7));
-}
+// LDS operand layout: rows of KS_K = 64 fp16 (128 bytes, no padding); the
+// 16-byte chunk c of row r sits at slot c ^ (r & 7).  A fragment read (rows
+// 16k..16k+15 at one chunk) and a staging write (8 lanes per row) touch 8
+// distinct 16-byte slots in every 8 lanes: no bank conflicts (checked with
+// the LDS bank-conflict counters on gfx950, which serve ds_read_b128 in
+// 8-lane groups; padded rows and XORs over wider lines conflict 2-way).
+__device__ __forceinline__ int ks_swz(int r, int c) { return r * 64 + 8 * (c ^ (r & 7)); }
 
 
 // Histogram of positive float bounds for the Ising / kinetic screen: 16 bins
@@ -373,6 +370,7 @@ __device__ __forceinline__ bool ks_tile(const TileMap& T, int b, int* bi, int* b
 // KS_WM x KS_WN blocks of 16 x 16 outputs; the block covers KS_BM rows x
 // KS_BN columns.
 constexpr int KS_THREADS = 512;
+constexpr int KS_K = 64;   // samples per k step (two MFMA k-substeps)
 constexpr int KS_WR = 2, KS_WC = 4;
 constexpr int KS_WM = 8, KS_WN = 4;
 constexpr int KS_BM = KS_WR * KS_WM * 16, KS_BN = KS_WC * KS_WN * 16;
@@ -380,7 +378,7 @@ constexpr int KS_Q = 2 * KS_THREADS;   // per-block queue of elements that passe
 static_assert(KS_WR * KS_WC * REC_WAVE == KS_THREADS, "one wavefront per sub-tile");
 static_assert(KS_BM <= REC_TAIL_ROWS && KS_BN <= REC_TAIL_ROWS, "tiles must stay inside the zero tail");
 static_assert(KS_BM <= 256 && KS_BN <= 256, "queue keys hold 8-bit rows and columns");
-static_assert(KS_BM % (KS_THREADS / 4) == 0 && KS_BN % (KS_THREADS / 4) == 0, "staging rows per thread");
+static_assert(KS_BM % (KS_THREADS / 8) == 0 && KS_BN % (KS_THREADS / 8) == 0, "staging rows per thread");
 
 template <int MODE, int KIN, int ROBUST>
 __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_kscreen(KScreenArgs P, TileMap TM, int row_step) {
@@ -390,8 +388,8 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   const int64_t r0 = (int64_t)bi * KS_BM, c0 = (int64_t)bj * KS_BN;
   if (!KIN && r0 >= c0 + KS_BN - 1) return;   // no pair i < j in the tile
   constexpr bool HIST = MODE != 1, COLLECT = MODE != 0;
-  __shared__ __attribute__((aligned(16))) _Float16 As[2][KS_BM * SC_K];
-  __shared__ __attribute__((aligned(16))) _Float16 Bs[2][KS_BN * SC_K];
+  __shared__ __attribute__((aligned(16))) _Float16 As[2][KS_BM * KS_K];
+  __shared__ __attribute__((aligned(16))) _Float16 Bs[2][KS_BN * KS_K];
   __shared__ uint32_t hs[HIST ? KS_BINS : 1];
   __shared__ uint32_t kq_key[KS_Q];   // bit 31 histogram, bit 30 collect; row << 8 | column in the tile
   __shared__ float kq_e[KS_Q], kq_c[KS_Q];
@@ -401,16 +399,16 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   if (HIST)
     for (int q = tid; q < KS_BINS; q += KS_THREADS) hs[q] = 0;
   if (tid == 0) { kq_n = 0; kc_n = 0; }
-  // Staging: thread tid moves the 8-sample chunk (tid & 3) of rows tid/4 +
-  // (KS_THREADS/4) u of both operands.  Operand rows are fp16 (x copy and
+  // Staging: thread tid moves the 8-sample chunk (tid & 7) of rows tid/8 +
+  // (KS_THREADS/8) u of both operands.  Operand rows are fp16 (x copy and
   // residuals) with zero rows past N, so no load needs a bound check.  Ising:
   // in the first half of k, A = x and B = r; in the second, A = r and B = x.
   // Kinetic: A = r (targets), B = x (sources).
-  constexpr int SRS = KS_THREADS / 4;   // staging row stride
+  constexpr int SRS = KS_THREADS / 8;   // staging row stride
   constexpr int NA = KS_BM / SRS, NB = KS_BN / SRS;
-  static_assert(NA == 2 && NB == 2, "stage layout below holds two rows per operand");
+  static_assert(NA == 4 && NB == 4, "stage layout below holds four rows per operand");
   const int n = P.nsteps;
-  const int sr = tid >> 2, part = tid & 3;
+  const int sr = tid >> 3, part = tid & 7;
   uint32_t oa[NA], ob[NB];
   int wa[NA];
 #pragma unroll
@@ -422,24 +420,32 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   for (int u = 0; u < NB; ++u) ob[u] = (uint32_t)((c0 + sr + SRS * u) * P.Mp + part * 8);
   // staged values travel by value (no addressable aggregates: they stay in
   // registers)
-  struct Stage { uint4 a0, a1, b0, b1; };
+  struct Stage { uint4 a0, a1, a2, a3, b0, b1, b2, b3; };
   auto load = [&](int s) -> Stage {
-    const bool first = !KIN && (int64_t)s * SC_K < P.Mp;
-    const int64_t k = (int64_t)s * SC_K - (KIN || first ? 0 : P.Mp);
+    const bool first = !KIN && (int64_t)s * KS_K < P.Mp;
+    const int64_t k = (int64_t)s * KS_K - (KIN || first ? 0 : P.Mp);
     const uint16_t* pa = (first ? P.xh : P.rh) + k;
     const uint16_t* pb = (first ? P.rh : P.xh) + k;
     Stage R;
     R.a0 = *reinterpret_cast<const uint4*>(pa + oa[0]);
     R.a1 = *reinterpret_cast<const uint4*>(pa + oa[1]);
+    R.a2 = *reinterpret_cast<const uint4*>(pa + oa[2]);
+    R.a3 = *reinterpret_cast<const uint4*>(pa + oa[3]);
     R.b0 = *reinterpret_cast<const uint4*>(pb + ob[0]);
     R.b1 = *reinterpret_cast<const uint4*>(pb + ob[1]);
+    R.b2 = *reinterpret_cast<const uint4*>(pb + ob[2]);
+    R.b3 = *reinterpret_cast<const uint4*>(pb + ob[3]);
     return R;
   };
   auto store = [&](Stage R, int buf) {
     *reinterpret_cast<uint4*>(As[buf] + wa[0]) = R.a0;
     *reinterpret_cast<uint4*>(As[buf] + wa[1]) = R.a1;
+    *reinterpret_cast<uint4*>(As[buf] + wa[2]) = R.a2;
+    *reinterpret_cast<uint4*>(As[buf] + wa[3]) = R.a3;
     *reinterpret_cast<uint4*>(Bs[buf] + wa[0]) = R.b0;
     *reinterpret_cast<uint4*>(Bs[buf] + wa[1]) = R.b1;
+    *reinterpret_cast<uint4*>(Bs[buf] + wa[2]) = R.b2;
+    *reinterpret_cast<uint4*>(Bs[buf] + wa[3]) = R.b3;
   };
   floatx4 acc[KS_WM][KS_WN];
 #pragma unroll
@@ -447,32 +453,40 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
     for (int q = 0; q < KS_WN; ++q) acc[m][q] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int wr = (w / KS_WC) * (KS_WM * 16), wc = (w % KS_WC) * (KS_WN * 16);
-  int fa[KS_WM], fb[KS_WN];
+  // fragments of k-substep h: lane l reads row (block base + l % 16), chunk
+  // 4h + l / 16
+  int fa[KS_WM][2], fb[KS_WN][2];
 #pragma unroll
-  for (int f = 0; f < KS_WM; ++f) fa[f] = ks_swz(wr + f * 16 + (lane & 15), lane >> 4);
+  for (int h = 0; h < 2; ++h) {
 #pragma unroll
-  for (int f = 0; f < KS_WN; ++f) fb[f] = ks_swz(wc + f * 16 + (lane & 15), lane >> 4);
+    for (int f = 0; f < KS_WM; ++f) fa[f][h] = ks_swz(wr + f * 16 + (lane & 15), 4 * h + (lane >> 4));
+#pragma unroll
+    for (int f = 0; f < KS_WN; ++f) fb[f][h] = ks_swz(wc + f * 16 + (lane & 15), 4 * h + (lane >> 4));
+  }
   auto compute = [&](int buf) {
-    halfx8 bf[KS_WN];
 #pragma unroll
-    for (int q = 0; q < KS_WN; ++q) bf[q] = *reinterpret_cast<const halfx8*>(Bs[buf] + fb[q]);
+    for (int h = 0; h < 2; ++h) {
+      halfx8 bf[KS_WN];
 #pragma unroll
-    for (int m = 0; m < KS_WM; ++m) {
-      const halfx8 af = *reinterpret_cast<const halfx8*>(As[buf] + fa[m]);
+      for (int q = 0; q < KS_WN; ++q) bf[q] = *reinterpret_cast<const halfx8*>(Bs[buf] + fb[q][h]);
 #pragma unroll
-      for (int q = 0; q < KS_WN; ++q)
-        acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af, bf[q], acc[m][q], 0, 0, 0);
+      for (int m = 0; m < KS_WM; ++m) {
+        const halfx8 af = *reinterpret_cast<const halfx8*>(As[buf] + fa[m][h]);
+#pragma unroll
+        for (int q = 0; q < KS_WN; ++q)
+          acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af, bf[q], acc[m][q], 0, 0, 0);
+      }
     }
   };
-  // n is even (Mp is a multiple of 64).  The loop body has no branches, so
-  // every iteration leaves the same loads in flight and none is waited on
-  // before its data is needed; past the end, loads repeat the last step and
-  // the stores land in a buffer nobody reads.
-  Stage R0 = load(0), R1 = load(1);
+  // The loop body has no branches, so every iteration leaves the same loads
+  // in flight and none is waited on before its data is needed; past the end,
+  // loads repeat the last step and the stores land in a buffer nobody reads.
+  // An odd last step (already in buffer 0) runs after the loop.
+  Stage R0 = load(0), R1 = load(min(1, n - 1));
   store(R0, 0);
   __syncthreads();
   // step s reads LDS buffer s % 2; registers hold step s + 1 while step s + 2 loads
-  for (int s = 0; s < n; s += 2) {
+  for (int s = 0; s + 1 < n; s += 2) {
     R0 = load(min(s + 2, n - 1));
     compute(0);
     store(R1, 1);
@@ -480,6 +494,10 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     R1 = load(min(s + 3, n - 1));
     compute(1);
     store(R0, 0);
+    __syncthreads();
+  }
+  if (n & 1) {
+    compute(0);
     __syncthreads();
   }
   // Epilogue: lane holds rows 4*(lane/16) + r, column lane % 16 of each
@@ -829,7 +847,7 @@ KScreenArgs ks_args(rec_ctx* ctx) {
   P.N = ctx->cfg.N;
   P.Mp = ctx->F.Mp;
   const int64_t K = kin ? ctx->F.Mp : 2 * ctx->F.Mp;
-  P.nsteps = (int)(K / SC_K);
+  P.nsteps = (int)(K / KS_K);
   P.l1 = ctx->sc_l1;
   P.cv = ctx->sc_cv;
   P.cvmin = ctx->sc_tau + 3;

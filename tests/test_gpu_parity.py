@@ -548,6 +548,23 @@ def test_screen_search_equals_exhaustive(model, prec):
 
 
 @pytest.mark.parametrize("model", ["ising", "kinetic"])
+@pytest.mark.parametrize("M", [50, 100])
+def test_screen_short_rows(model, M):
+    """Few samples: the contraction runs one or two k steps (an odd count
+    for the kinetic model at M = 50); the screen still equals the exhaustive
+    search."""
+    if model == "ising":
+        w = synth.ising_regular(300, M, 3, 0.4, seed=31)
+    else:
+        w = synth.kinetic_er(300, M, 5.0, 0.3, seed=32)
+    lam = oracle.default_lambda(w.X, model)
+    C = ctx_for(w, lam, "fp32")
+    for state in range(2):
+        screen_equals_exhaustive(C, C.m)
+        C.sweep("screen")
+
+
+@pytest.mark.parametrize("model", ["ising", "kinetic"])
 def test_screen_overflow_fallback(model):
     """With m = 20 N the survivors of a tile outnumber the block queue, so the
     full pass flags an overflow and the call finishes through the robust
