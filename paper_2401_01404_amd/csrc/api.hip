@@ -164,6 +164,8 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   x->first = a.take<int32_t>(N);
   x->done = a.take<uint8_t>(z.best_cap);
   x->dw = a.take<double>(z.best_cap);
+  x->ready = a.take<int32_t>(z.best_cap);
+  x->best_slot = a.take<int64_t>(z.best_cap);
   x->ex_cap = z.ex_cap;
   x->max_nnz = z.max_nnz;
   x->scr_qcap = std::min<int64_t>(z.cand_cap, int64_t(1) << 30);
@@ -208,6 +210,7 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   } else {
     x->sc_l1 = a.take<float>(N);
     x->sc_cv = a.take<float>(N);
+    x->sc_wa = a.take<float>(z.max_nnz);
     x->sc_hist = a.take<uint32_t>(4096);
     x->sc_tau = a.take<float>(64);
   }

@@ -133,6 +133,8 @@ struct rec_ctx {
   int32_t* first;       // N
   uint8_t* done;        // best_cap
   double* dw;           // best_cap
+  int32_t* ready;       // best_cap: the pairs of the current update round
+  int64_t* best_slot;   // best_cap: W table slot of each pair being applied
   // exhaustive search chunk buffers
   int64_t ex_cap;
   // queue of the screened scoring's unsettled pairs (k_kink -> k_exact)
@@ -147,8 +149,9 @@ struct rec_ctx {
   __bf16* sc_b = nullptr;
   int sc_kp = 0;
   float *sc_nrm = nullptr, *sc_th2 = nullptr, *sc_sq = nullptr, *sc_tau = nullptr;
-  // Ising / kinetic screen: per node |r_i|_1 and curvature sum (1 - t^2)
-  float *sc_l1 = nullptr, *sc_cv = nullptr;
+  // Ising / kinetic screen: per node |r_i|_1 and curvature sum (1 - t^2);
+  // per current coupling its gradient from the fp16 rows (max_nnz)
+  float *sc_l1 = nullptr, *sc_cv = nullptr, *sc_wa = nullptr;
   // screen instrumentation: [0] full-pass ms, [1] full-pass launches, [2]
   // their algorithmic flops, [3] sample-pass ms, [4] sample launches, [5]
   // screen calls, [6] pairs decided, [7] pairs rescored exactly, [8] calls
@@ -233,9 +236,11 @@ rec_status rec_launch_score(rec_ctx* ctx, int64_t P, const int32_t* I, const int
 // (gi[p], S[v[p]]), gain to the cache slot.
 rec_status rec_launch_score_owned(rec_ctx* ctx, int64_t P, const int32_t* gi, const int32_t* v,
                                   const int32_t* S, const uint32_t* slot, const Cache* cache);
-// Apply one round of node-disjoint updates (see update kernels).
+// Apply one round of node-disjoint updates: the pairs ready[0..*nready) of
+// the rank-ordered list (I, J); at most m of them (see update kernels).
 rec_status rec_launch_update_round(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
-                                   const int32_t* first, uint8_t* done, double* dw);
+                                   const int32_t* ready, const int64_t* nready, uint8_t* done,
+                                   double* dw);
 
 // sort.hip
 // Stable LSD radix sort of (khi, klo, val) by the 8-bit digits listed
@@ -246,7 +251,9 @@ rec_status rec_exclusive_scan(rec_ctx* ctx, const int64_t* in, int64_t* out, int
                               int64_t* total_dev);
 
 // screen.hip: candidates of the exhaustive screen into ts_i/ts_j (count *n_out)
-rec_status rec_screen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out);
+// for the best m pairs, with nnz current couplings in the compacted W list
+// (wi/wj/wv)
+rec_status rec_screen_candidates(rec_ctx* ctx, int64_t m, int64_t nnz, int64_t* n_out);
 rec_status rec_screen_resolve(rec_ctx* ctx);   // fold finished screen events into sc_stat
 // Ising/kinetic, after rec_screen_candidates: append the current couplings
 // (wi/wj/wv, nnz) whose gain bound reaches the screen's threshold; *n_out =

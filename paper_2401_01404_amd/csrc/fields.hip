@@ -14,6 +14,8 @@
 // partials, then one block), so repeated evaluations give the same bits.
 #include <math.h>
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "ctx.hpp"
 
@@ -115,84 +117,158 @@ __global__ __launch_bounds__(FT) void k_load_f32(const float* __restrict__ X, in
   if (threadIdx.x == 0) sq[i] = tot;
 }
 
-// Rebuild the fields of row i from its sorted W row list.
-template <class R, int MODEL>
+// One wavefront per row; lane l holds the samples c * 64 * VEC + l * VEC + k
+// (k < VEC, c < NPL / VEC), so each load or store of the wave covers one
+// contiguous run of the row.
+template <int NPL> struct RowLayout {
+  static constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  __device__ static int64_t at(int c, int lane) { return (int64_t)c * (REC_WAVE * VEC) + (int64_t)lane * VEC; }
+};
+
+template <class T, int VEC> struct alignas(sizeof(T) * VEC) Pack { T v[VEC]; };
+
+template <int VEC>
+__device__ __forceinline__ void ld_i8(const int8_t* p, double* o) {
+  const Pack<int8_t, VEC> q = *reinterpret_cast<const Pack<int8_t, VEC>*>(p);
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) o[k] = (double)q.v[k];
+}
+template <int VEC>
+__device__ __forceinline__ void ld_f32(const float* p, double* o) {
+  const Pack<float, VEC> q = *reinterpret_cast<const Pack<float, VEC>*>(p);
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) o[k] = (double)q.v[k];
+}
+
+// Rebuild the fields of row i from its sorted W row list (summed over the
+// list in order, per sample, in FP64; rounded once).  Padding samples get
+// h = t = 0 (their x and y are 0).
+template <class R, int NPL, int MODEL>
 __global__ __launch_bounds__(FT) void k_fields(Fields F, const int64_t* __restrict__ row_off,
                                                const int32_t* __restrict__ col,
                                                const double* __restrict__ colw) {
-  const int64_t i = blockIdx.x;
+  using L = RowLayout<NPL>;
+  constexpr int VEC = L::VEC, CH = L::CH;
+  const int lane = threadIdx.x & (REC_WAVE - 1);
+  const int64_t i = (int64_t)blockIdx.x * (FT / REC_WAVE) + threadIdx.x / REC_WAVE;
+  if (i >= F.N) return;
   const int64_t e0 = row_off ? row_off[i] : 0, e1 = row_off ? row_off[i + 1] : 0;
+  double acc[NPL];
+#pragma unroll
+  for (int q = 0; q < NPL; ++q) acc[q] = 0.0;
+  for (int64_t e = e0; e < e1; ++e) {
+    const int64_t j = col[e];
+    const double w = colw[e];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      double x[VEC];
+      if (MODEL == REC_GAUSS) ld_f32<VEC>(F.xf + j * F.Mp + L::at(c, lane), x);
+      else ld_i8<VEC>(F.xs + j * F.Mp + L::at(c, lane), x);
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) acc[c * VEC + k] += w * x[k];
+    }
+  }
   const double th = F.theta[i];
   R* H = reinterpret_cast<R*>(F.H);
   R* T = reinterpret_cast<R*>(F.T);
-  for (int64_t s = threadIdx.x; s < F.Mp; s += FT) {
-    double acc = 0.0;
-    if (s < F.M) {
-      for (int64_t e = e0; e < e1; ++e) {
-        int64_t j = col[e];
-        double x = MODEL == REC_GAUSS ? (double)F.xf[j * F.Mp + s] : (double)F.xs[j * F.Mp + s];
-        acc += colw[e] * x;
-      }
-    }
-    int64_t idx = i * F.Mp + s;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int64_t o = L::at(c, lane), idx = i * F.Mp + o;
+    Pack<R, VEC> hv, tv;
+    Pack<uint16_t, VEC> rv;
     if (MODEL == REC_GAUSS) {
-      H[idx] = s < F.M ? (R)((double)F.xf[idx] + th * th * acc) : R(0);
+      double x[VEC];
+      ld_f32<VEC>(F.xf + idx, x);
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) hv.v[k] = o + k < F.M ? (R)(x[k] + th * th * acc[c * VEC + k]) : R(0);
+      *reinterpret_cast<Pack<R, VEC>*>(H + idx) = hv;
     } else {
       const int8_t* Y = MODEL == REC_KINETIC ? F.ys : F.xs;
-      R h = s < F.M ? (R)(th + acc) : R(0);
-      R t = s < F.M ? tanh_<R>(h) : R(0);
-      H[idx] = h;
-      T[idx] = t;
-      F.rh[idx] = rec_f16_bits((float)((R)Y[idx] - t));
+      double y[VEC];
+      ld_i8<VEC>(Y + idx, y);
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        const bool in = o + k < F.M;
+        const R h = in ? (R)(th + acc[c * VEC + k]) : R(0);
+        const R t = in ? tanh_<R>(h) : R(0);
+        hv.v[k] = h;
+        tv.v[k] = t;
+        rv.v[k] = rec_f16_bits((float)((R)y[k] - t));
+      }
+      *reinterpret_cast<Pack<R, VEC>*>(H + idx) = hv;
+      *reinterpret_cast<Pack<R, VEC>*>(T + idx) = tv;
+      *reinterpret_cast<Pack<uint16_t, VEC>*>(F.rh + idx) = rv;
     }
   }
 }
 
-// Refit theta_i [App. A, theta updated alongside W]:
+// Refit theta_i [App. A, theta updated alongside W], one wavefront per row
+// with the row's samples held in registers:
 //   Ising / kinetic: root of sum_m (y_m - tanh(theta + m_m)) on [-8, 8]
 //   (Newton inside the bracket, bisection otherwise), m = h - theta_old;
 //   Gaussian: v = theta^2 is the positive root of C v^2 + M v - A = 0,
 //   A = sum x^2, C = sum m^2, m = (r - x) / theta_old^2.
 // Then the row's fields are shifted to the new theta.
-template <class R, int MODEL>
+template <class R, int NPL, int MODEL>
 __global__ __launch_bounds__(FT) void k_theta(Fields F) {
-  __shared__ double sh[FT / REC_WAVE];
-  const int64_t i = blockIdx.x;
+  using L = RowLayout<NPL>;
+  constexpr int VEC = L::VEC, CH = L::CH;
+  const int lane = threadIdx.x & (REC_WAVE - 1);
+  const int64_t i = (int64_t)blockIdx.x * (FT / REC_WAVE) + threadIdx.x / REC_WAVE;
+  if (i >= F.N) return;
   const double th0 = F.theta[i];
   R* H = reinterpret_cast<R*>(F.H);
   R* T = reinterpret_cast<R*>(F.T);
   const int8_t* Y = MODEL == REC_KINETIC ? F.ys : F.xs;
+  double mm[NPL], y[NPL];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int64_t idx = i * F.Mp + L::at(c, lane);
+    const Pack<R, VEC> hv = *reinterpret_cast<const Pack<R, VEC>*>(H + idx);
+    if (MODEL == REC_GAUSS) ld_f32<VEC>(F.xf + idx, y + c * VEC);
+    else ld_i8<VEC>(Y + idx, y + c * VEC);
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      const double hh = (double)hv.v[k];
+      mm[c * VEC + k] = MODEL == REC_GAUSS ? (hh - y[c * VEC + k]) / (th0 * th0) : hh - th0;
+    }
+  }
+  auto valid = [&](int q) { return L::at(q / VEC, lane) + q % VEC < F.M; };
   double th = th0;
   if (MODEL == REC_GAUSS) {
     double A = 0.0, C = 0.0;
-    double v0 = th0 * th0;
-    for (int64_t s = threadIdx.x; s < F.M; s += FT) {
-      double x = F.xf[i * F.Mp + s];
-      double mm = ((double)H[i * F.Mp + s] - x) / v0;
-      A += x * x;
-      C += mm * mm;
-    }
-    A = block_sum(A, sh);
-    C = block_sum(C, sh);
-    double M = (double)F.M;
-    double v = C > 0 ? (-M + sqrt(M * M + 4.0 * A * C)) / (2.0 * C) : A / M;
+#pragma unroll
+    for (int q = 0; q < NPL; ++q)
+      if (valid(q)) {
+        A += y[q] * y[q];
+        C += mm[q] * mm[q];
+      }
+    A = rec_wave_sum(A);
+    C = rec_wave_sum(C);
+    const double M = (double)F.M;
+    const double v = C > 0 ? (-M + sqrt(M * M + 4.0 * A * C)) / (2.0 * C) : A / M;
     th = sqrt(v);
-    for (int64_t s = threadIdx.x; s < F.M; s += FT) {
-      double x = F.xf[i * F.Mp + s];
-      double mm = ((double)H[i * F.Mp + s] - x) / v0;
-      H[i * F.Mp + s] = (R)(x + v * mm);
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int64_t idx = i * F.Mp + L::at(c, lane);
+      Pack<R, VEC> hv;
+#pragma unroll
+      for (int k = 0; k < VEC; ++k)
+        hv.v[k] = valid(c * VEC + k) ? (R)(y[c * VEC + k] + v * mm[c * VEC + k]) : R(0);
+      *reinterpret_cast<Pack<R, VEC>*>(H + idx) = hv;
     }
   } else {
     auto eval = [&](double t, double& f, double& df) {
       double a = 0.0, b = 0.0;
-      for (int64_t s = threadIdx.x; s < F.M; s += FT) {
-        double mm = (double)H[i * F.Mp + s] - th0;
-        R tt = tanh_<R>((R)(t + mm));
-        a += (double)Y[i * F.Mp + s] - (double)tt;
-        b -= 1.0 - (double)tt * (double)tt;
-      }
-      f = block_sum(a, sh);
-      df = block_sum(b, sh);
+#pragma unroll
+      for (int q = 0; q < NPL; ++q)
+        if (valid(q)) {
+          const R tt = tanh_<R>((R)(t + mm[q]));
+          a += y[q] - (double)tt;
+          b -= 1.0 - (double)tt * (double)tt;
+        }
+      f = rec_wave_sum(a);
+      df = rec_wave_sum(b);
     };
     const double TMAX = 8.0;
     double f, df;
@@ -210,7 +286,7 @@ __global__ __launch_bounds__(FT) void k_theta(Fields F) {
           if (f > 0) lo = t; else hi = t;
           double tn = df < 0 ? t - f / df : 0.5 * (lo + hi);
           if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-          double step = tn - t;
+          const double step = tn - t;
           t = tn;
           if (fabs(step) <= (sizeof(R) == 4 ? 1e-9 : 1e-15) * fmax(1.0, fabs(t)) || hi - lo < 1e-300)
             break;
@@ -219,16 +295,26 @@ __global__ __launch_bounds__(FT) void k_theta(Fields F) {
         th = t;
       }
     }
-    for (int64_t s = threadIdx.x; s < F.M; s += FT) {
-      double mm = (double)H[i * F.Mp + s] - th0;
-      R h = (R)(th + mm);
-      R t = tanh_<R>(h);
-      H[i * F.Mp + s] = h;
-      T[i * F.Mp + s] = t;
-      F.rh[i * F.Mp + s] = rec_f16_bits((float)((R)Y[i * F.Mp + s] - t));
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int64_t idx = i * F.Mp + L::at(c, lane);
+      Pack<R, VEC> hv, tv;
+      Pack<uint16_t, VEC> rv;
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        const bool in = valid(c * VEC + k);
+        const R h = in ? (R)(th + mm[c * VEC + k]) : R(0);
+        const R t = in ? tanh_<R>(h) : R(0);
+        hv.v[k] = h;
+        tv.v[k] = t;
+        rv.v[k] = rec_f16_bits((float)((R)y[c * VEC + k] - t));
+      }
+      *reinterpret_cast<Pack<R, VEC>*>(H + idx) = hv;
+      *reinterpret_cast<Pack<R, VEC>*>(T + idx) = tv;
+      *reinterpret_cast<Pack<uint16_t, VEC>*>(F.rh + idx) = rv;
     }
   }
-  if (threadIdx.x == 0) F.theta[i] = th;
+  if (lane == 0) F.theta[i] = th;
 }
 
 // Per-row log pseudolikelihood into part[i].
@@ -260,38 +346,33 @@ __global__ __launch_bounds__(FT) void k_rowll(Fields F, double* part) {
   }
 }
 
-// Sum part[0..n) in a fixed order (one block): result = sum * scale + add0
+// Sum part[0..n) in a fixed order (one block, strided loads): *out = the sum
 __global__ __launch_bounds__(FT) void k_sum(const double* part, int64_t n, double* out) {
   __shared__ double sh[FT / REC_WAVE];
   double acc = 0.0;
-  int64_t per = (n + FT - 1) / FT;
-  int64_t b = (int64_t)threadIdx.x * per, e = b + per < n ? b + per : n;
-  for (int64_t k = b; k < e; ++k) acc += part[k];
+  for (int64_t k = threadIdx.x; k < n; k += FT) acc += part[k];
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) *out = acc;
 }
 
-// sum |w| over the sorted W list
+// sum |w| over the sorted W list, strided like k_sum_partial
 __global__ __launch_bounds__(FT) void k_abs_partial(const double* w, int64_t n, double* part,
                                                     int64_t nchunk) {
   int64_t c = (int64_t)blockIdx.x * FT + threadIdx.x;
   if (c >= nchunk) return;
-  int64_t per = (n + nchunk - 1) / nchunk;
-  int64_t b = c * per, e = b + per < n ? b + per : n;
   double acc = 0.0;
-  for (int64_t k = b; k < e; ++k) acc += fabs(w[k]);
+  for (int64_t k = c; k < n; k += nchunk) acc += fabs(w[k]);
   part[c] = acc;
 }
 
-// Contiguous-chunk partial sums (fixed order, so the total is reproducible).
+// Strided partial sums: slot c adds x[c], x[c + nchunk], ... (coalesced, and a fixed order for a
+// given nchunk, so the total is reproducible).
 __global__ __launch_bounds__(FT) void k_sum_partial(const double* x, int64_t n, double* part,
                                                     int64_t nchunk) {
   int64_t c = (int64_t)blockIdx.x * FT + threadIdx.x;
   if (c >= nchunk) return;
-  int64_t per = (n + nchunk - 1) / nchunk;
-  int64_t b = c * per, e = b + per < n ? b + per : n;
   double acc = 0.0;
-  for (int64_t k = b; k < e; ++k) acc += x[k];
+  for (int64_t k = c; k < n; k += nchunk) acc += x[k];
   part[c] = acc;
 }
 
@@ -368,34 +449,52 @@ int bits_for(int64_t v) {
   return b < 1 ? 1 : b;
 }
 
-template <class R>
-rec_status launch_fields_r(rec_ctx* ctx) {
-  dim3 g(ctx->cfg.N), b(FT);
+template <class R, int NPL>
+rec_status launch_fields_n(rec_ctx* ctx) {
+  dim3 g((unsigned)((ctx->cfg.N + FT / REC_WAVE - 1) / (FT / REC_WAVE))), b(FT);
   switch (ctx->cfg.model) {
     case REC_ISING:
-      hipLaunchKernelGGL((k_fields<R, REC_ISING>), g, b, 0, ctx->stream, ctx->F, ctx->row_off, ctx->col, ctx->colw);
+      hipLaunchKernelGGL((k_fields<R, NPL, REC_ISING>), g, b, 0, ctx->stream, ctx->F, ctx->row_off, ctx->col, ctx->colw);
       break;
     case REC_GAUSS:
-      hipLaunchKernelGGL((k_fields<R, REC_GAUSS>), g, b, 0, ctx->stream, ctx->F, ctx->row_off, ctx->col, ctx->colw);
+      hipLaunchKernelGGL((k_fields<R, NPL, REC_GAUSS>), g, b, 0, ctx->stream, ctx->F, ctx->row_off, ctx->col, ctx->colw);
       break;
     default:
-      hipLaunchKernelGGL((k_fields<R, REC_KINETIC>), g, b, 0, ctx->stream, ctx->F, ctx->row_off, ctx->col, ctx->colw);
+      hipLaunchKernelGGL((k_fields<R, NPL, REC_KINETIC>), g, b, 0, ctx->stream, ctx->F, ctx->row_off, ctx->col, ctx->colw);
   }
   REC_HIP(hipGetLastError());
   return REC_OK;
 }
 
-template <class R>
-rec_status launch_theta_r(rec_ctx* ctx) {
-  dim3 g(ctx->cfg.N), b(FT);
+template <class R, int NPL>
+rec_status launch_theta_n(rec_ctx* ctx) {
+  dim3 g((unsigned)((ctx->cfg.N + FT / REC_WAVE - 1) / (FT / REC_WAVE))), b(FT);
   switch (ctx->cfg.model) {
-    case REC_ISING: hipLaunchKernelGGL((k_theta<R, REC_ISING>), g, b, 0, ctx->stream, ctx->F); break;
-    case REC_GAUSS: hipLaunchKernelGGL((k_theta<R, REC_GAUSS>), g, b, 0, ctx->stream, ctx->F); break;
-    default: hipLaunchKernelGGL((k_theta<R, REC_KINETIC>), g, b, 0, ctx->stream, ctx->F);
+    case REC_ISING: hipLaunchKernelGGL((k_theta<R, NPL, REC_ISING>), g, b, 0, ctx->stream, ctx->F); break;
+    case REC_GAUSS: hipLaunchKernelGGL((k_theta<R, NPL, REC_GAUSS>), g, b, 0, ctx->stream, ctx->F); break;
+    default: hipLaunchKernelGGL((k_theta<R, NPL, REC_KINETIC>), g, b, 0, ctx->stream, ctx->F);
   }
   REC_HIP(hipGetLastError());
   return REC_OK;
 }
+
+// the row kernels keep NPL samples per lane in registers
+#define REC_NPL_SWITCH(FN, R)                                   \
+  switch (ctx->F.npl) {                                         \
+    case 1: return FN<R, 1>(ctx);                               \
+    case 2: return FN<R, 2>(ctx);                               \
+    case 4: return FN<R, 4>(ctx);                               \
+    case 8: return FN<R, 8>(ctx);                               \
+    case 16: return FN<R, 16>(ctx);                             \
+    case 32: return FN<R, 32>(ctx);                             \
+    default: ctx->err = "unsupported sample count"; return REC_E_INVAL; \
+  }
+
+template <class R>
+rec_status launch_fields_r(rec_ctx* ctx) { REC_NPL_SWITCH(launch_fields_n, R) }
+
+template <class R>
+rec_status launch_theta_r(rec_ctx* ctx) { REC_NPL_SWITCH(launch_theta_n, R) }
 
 template <class R>
 rec_status launch_rowll_r(rec_ctx* ctx) {
@@ -513,8 +612,9 @@ rec_status rec_fit_theta(rec_ctx* ctx) {
 }
 
 rec_status rec_sum_device(rec_ctx* ctx, const double* x, int64_t n, double* out) {
-  const int64_t nchunk = 1024;
-  hipLaunchKernelGGL(k_sum_partial, dim3((unsigned)(nchunk / FT)), dim3(FT), 0, ctx->stream, x, n,
+  const int64_t nchunk = std::min<int64_t>(std::max<int64_t>(ctx->cfg.N, 1024),
+                                           std::max<int64_t>(1024, (n + 255) / 256));
+  hipLaunchKernelGGL(k_sum_partial, dim3((unsigned)((nchunk + FT - 1) / FT)), dim3(FT), 0, ctx->stream, x, n,
                      ctx->dscratch, nchunk);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(FT), 0, ctx->stream, ctx->dscratch, nchunk, out);
   REC_HIP(hipGetLastError());
@@ -530,9 +630,11 @@ rec_status rec_eval_objective(rec_ctx* ctx, double* out) {
   int64_t nnz;
   st = rec_wtable_compact(ctx, &nnz);
   if (st != REC_OK) return st;
-  const int64_t nchunk = 1024;
-  hipLaunchKernelGGL(k_abs_partial, dim3(nchunk / 256), dim3(256), 0, ctx->stream, ctx->wv, nnz,
-                     ctx->dscratch, nchunk);
+  // about 256 couplings per partial, at most one partial per dscratch slot
+  const int64_t nchunk = std::min<int64_t>(std::max<int64_t>(ctx->cfg.N, 1024),
+                                           std::max<int64_t>(1024, (nnz + 255) / 256));
+  hipLaunchKernelGGL(k_abs_partial, dim3((unsigned)((nchunk + FT - 1) / FT)), dim3(FT), 0, ctx->stream, ctx->wv,
+                     nnz, ctx->dscratch, nchunk);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(FT), 0, ctx->stream, ctx->dscratch, nchunk,
                      ctx->dresult + 1);
   hipLaunchKernelGGL(k_combine_obj, dim3(1), dim3(1), 0, ctx->stream, ctx->dresult + 0,

@@ -41,6 +41,7 @@
 // change of the two conditionals [App. A] is a delta - b delta^2 / 2 with
 // a = -(r_i . x_j + r_j . x_i), b = theta_i^2 |x_j|^2 + theta_j^2 |x_i|^2,
 // maximised with the L1 term by soft thresholding.
+#include <algorithm>
 #include <math.h>
 
 #include "common.hpp"
@@ -879,22 +880,17 @@ __global__ __launch_bounds__(256) void k_exact(Fields F, WTable W, double lambda
   }
 }
 
-// One round of node-disjoint updates: pair p runs when it is the earliest
-// pending pair of both its rows (first[i] == first[j] == p); such pairs touch
-// disjoint rows, so the round equals the sequential rank order.
+// Solve pair p of the rank-ordered list and apply its update (one wave).
 template <class R, int NPL, int MODEL>
-__global__ __launch_bounds__(256) void k_update(Fields F, WTable W, double lambda, int64_t m,
-                                                const int32_t* __restrict__ I,
-                                                const int32_t* __restrict__ J,
-                                                const int32_t* __restrict__ first, uint8_t* done,
-                                                double* dw, int32_t* err) {
+__device__ __forceinline__ void update_pair(const Fields& F, const WTable& W, double lambda, int64_t p,
+                                            const int32_t* __restrict__ I,
+                                            const int32_t* __restrict__ J,
+                                            const int64_t* __restrict__ wslot, uint8_t* done,
+                                            double* dw) {
   constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
   const int lane = rec_lane();
-  const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE;
-  if (p >= m || done[p]) return;
-  int i = I[p], j = J[p];
-  if (first[i] != (int32_t)p) return;
-  if (MODEL != REC_KINETIC && first[j] != (int32_t)p) return;
+  const int i = I[p], j = J[p];
+  const int64_t ws = wslot[p];
   Lane<R, NPL> L;
   load_i<R, NPL, MODEL>(F, i, L, lane);
   JRaw<R, NPL, MODEL> rw;
@@ -902,8 +898,7 @@ __global__ __launch_bounds__(256) void k_update(Fields F, WTable W, double lambd
   float s_lane;
   double phi_l = form_j<R, NPL, MODEL>(rw, L, &s_lane);
   double phi0 = MODEL == REC_GAUSS ? 0.0 : rec_wave_sum_dpp(phi_l);
-  bool directed = MODEL == REC_KINETIC;
-  double w0 = rec_uni(lookup_w(W, i, j, directed));
+  const double w0 = rec_uni(ws >= 0 ? W.vals[ws] : 0.0);
   Work wk;
   PairOut r = solve<R, NPL, MODEL>(F, L, phi0, s_lane, i, j, w0, lambda, wk);
   double d = r.w - w0;
@@ -937,17 +932,34 @@ __global__ __launch_bounds__(256) void k_update(Fields F, WTable W, double lambd
         }
       }
     }
-    if (lane == 0) {
-      bool ins;
-      int64_t s = rec_hash_insert(W.keys, W.mask, rec_pair_key(i, j, directed), REC_MAX_PROBE, &ins);
-      if (s < 0) atomicOr(err, 2);
-      else W.vals[s] = r.w;
-    }
+    if (lane == 0 && ws >= 0) W.vals[ws] = r.w;
   }
   if (lane == 0) {
     dw[p] = fabs(d);
     done[p] = 1;
   }
+}
+
+// One round of node-disjoint updates over the list ready[0..*nready) of pairs
+// that are the earliest pending pair of each of their rows; such pairs touch
+// disjoint rows, so the round equals the sequential rank order. The grid is
+// sized for the device, not the list: each wave takes list entries in a
+// grid-stride loop, so every resident wave solves a ready pair.  W entries
+// are reached through the slots reserved for the list before the rounds
+// (wslot[p], no probing on the serial path of a pair); a pair's entry is
+// written only by that pair, so its value is current when the pair runs.
+template <class R, int NPL, int MODEL>
+__global__ __launch_bounds__(256) void k_update(Fields F, WTable W, double lambda,
+                                                const int32_t* __restrict__ I,
+                                                const int32_t* __restrict__ J,
+                                                const int32_t* __restrict__ ready,
+                                                const int64_t* __restrict__ nready,
+                                                const int64_t* __restrict__ wslot, uint8_t* done,
+                                                double* dw) {
+  const int64_t n = *nready;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / REC_WAVE);
+  for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE; q < n; q += nw)
+    update_pair<R, NPL, MODEL>(F, W, lambda, ready[q], I, J, wslot, done, dw);
 }
 
 template <class R, int MODEL>
@@ -1020,11 +1032,12 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
 
 template <class R, int MODEL>
 rec_status launch_update_m(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
-                           const int32_t* first, uint8_t* done, double* dw) {
-  int64_t blocks = (m * REC_WAVE + 255) / 256;
+                           const int32_t* ready, const int64_t* nready, uint8_t* done, double* dw) {
+  // enough 4-wave blocks to fill every CU a few times over, never more than the pairs
+  const int64_t blocks = std::min<int64_t>((m + 3) / 4, 256 * 8);
 #define REC_UP(NPL)                                                                              \
-  hipLaunchKernelGGL((k_update<R, NPL, MODEL>), dim3(blocks), dim3(256), 0, ctx->stream, ctx->F, \
-                     ctx->W, ctx->cfg.lambda, m, I, J, first, done, dw, ctx->err_flag)
+  hipLaunchKernelGGL((k_update<R, NPL, MODEL>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream, \
+                     ctx->F, ctx->W, ctx->cfg.lambda, I, J, ready, nready, ctx->best_slot, done, dw)
   switch (ctx->F.npl) {
     case 1: REC_UP(1); break;
     case 2: REC_UP(2); break;
@@ -1055,11 +1068,11 @@ rec_status launch_score_r(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
 
 template <class R>
 rec_status launch_update_r(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
-                           const int32_t* first, uint8_t* done, double* dw) {
+                           const int32_t* ready, const int64_t* nready, uint8_t* done, double* dw) {
   switch (ctx->cfg.model) {
-    case REC_ISING: return launch_update_m<R, REC_ISING>(ctx, m, I, J, first, done, dw);
-    case REC_GAUSS: return launch_update_m<R, REC_GAUSS>(ctx, m, I, J, first, done, dw);
-    case REC_KINETIC: return launch_update_m<R, REC_KINETIC>(ctx, m, I, J, first, done, dw);
+    case REC_ISING: return launch_update_m<R, REC_ISING>(ctx, m, I, J, ready, nready, done, dw);
+    case REC_GAUSS: return launch_update_m<R, REC_GAUSS>(ctx, m, I, J, ready, nready, done, dw);
+    case REC_KINETIC: return launch_update_m<R, REC_KINETIC>(ctx, m, I, J, ready, nready, done, dw);
   }
   return REC_E_INVAL;
 }
@@ -1126,8 +1139,9 @@ rec_status launch_score_any(rec_ctx* ctx, int64_t P, const int32_t* I, const int
 }  // namespace
 
 rec_status rec_launch_update_round(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
-                                   const int32_t* first, uint8_t* done, double* dw) {
+                                   const int32_t* ready, const int64_t* nready, uint8_t* done,
+                                   double* dw) {
   if (m <= 0) return REC_OK;
-  return ctx->fp32 ? launch_update_r<float>(ctx, m, I, J, first, done, dw)
-                   : launch_update_r<double>(ctx, m, I, J, first, done, dw);
+  return ctx->fp32 ? launch_update_r<float>(ctx, m, I, J, ready, nready, done, dw)
+                   : launch_update_r<double>(ctx, m, I, J, ready, nready, done, dw);
 }

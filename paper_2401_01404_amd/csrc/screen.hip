@@ -684,49 +684,89 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
       if (hs[q]) atomicAdd(&P.hist[q], hs[q]);
 }
 
-// Current couplings (w0 != 0).  With s = sign(w0), |w0 + d| - |w0| >= s d for
-// every step d, so the gain is at most the best gain of the smooth concave
-// g(d) = f(w0 + d) - f(w0) - lambda s d, whose slope at 0 is a - lambda s
-// (a = f'(w0), the gradient at the current state) and whose curvature obeys
-// the same bounds as above: gain <= (c/4) psi(2 |a - lambda s| / c).  One
-// wavefront per coupling forms a from the fp16 rows (error bounded as for the
-// contraction); couplings whose bound reaches *tau are appended after the
-// collected candidates.
+// Current couplings (w0 != 0), first pass, before the full pass's threshold
+// is taken: one wavefront per coupling forms a, the gradient at the current
+// state, from the fp16 rows (error bounded as for the contraction) and keeps
+// it in wa.  The contraction histograms every pair as if it were new,
+// couplings included; here each coupling adds one count in the bin of an
+// upper bound on the value the contraction could have binned for it (a off
+// by at most er on each side, 0.1% slack for the float evaluation), so that
+// the full histogram minus these counts bounds from below, over every bin
+// edge, the number of new pairs (w0 = 0) whose lower bound reaches it.
+constexpr int KS_CA_PER_BLOCK = 64;   // couplings per block of k_ks_couple_a
+template <int KIN>
+__global__ __launch_bounds__(256) void k_ks_couple_a(KScreenArgs P, const int32_t* __restrict__ wi,
+                                                     const int32_t* __restrict__ wj, int64_t nnz,
+                                                     float* __restrict__ wa, uint32_t* __restrict__ hist_c) {
+  // the block's counts gather in LDS first: couplings near their optimum
+  // crowd a few bins, which would serialise global atomics
+  __shared__ uint32_t hb_s[KS_BINS];
+  for (int q = threadIdx.x; q < KS_BINS; q += 256) hb_s[q] = 0u;
+  __syncthreads();
+  const int lane = threadIdx.x & (REC_WAVE - 1);
+  const int64_t e_end = min(nnz, ((int64_t)blockIdx.x + 1) * KS_CA_PER_BLOCK);
+  for (int64_t e = (int64_t)blockIdx.x * KS_CA_PER_BLOCK + (threadIdx.x / REC_WAVE); e < e_end; e += 4) {
+    const int64_t i = wi[e], j = wj[e];
+    const uint16_t* ri = P.rh + i * P.Mp;
+    const uint16_t* xj = P.xh + j * P.Mp;
+    const uint16_t* rj = P.rh + j * P.Mp;
+    const uint16_t* xi = P.xh + i * P.Mp;
+    float acc = 0.f;
+    for (int64_t k = (int64_t)lane * 8; k < P.Mp; k += 8 * REC_WAVE) {
+      const halfx8 a = *reinterpret_cast<const halfx8*>(ri + k);
+      const halfx8 b = *reinterpret_cast<const halfx8*>(xj + k);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += (float)a[q] * (float)b[q];
+      if (!KIN) {
+        const halfx8 c = *reinterpret_cast<const halfx8*>(rj + k);
+        const halfx8 d = *reinterpret_cast<const halfx8*>(xi + k);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc += (float)c[q] * (float)d[q];
+      }
+    }
+    acc = rec_wave_sum(acc);
+    if (lane == 0) {
+      wa[e] = acc;
+      const float er = P.ce * (P.l1[i] + (KIN ? 0.f : P.l1[j])) + P.el;
+      const float c = P.cv[i] + (KIN ? 0.f : P.cv[j]);
+      const float eu = fabsf(acc) + er - P.lam;
+      if (eu > 0.f) {
+        const int hb = ks_bin(kgain_lo(eu, c) * 1.001f);
+        if (hb >= 0) atomicAdd(&hb_s[hb], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < KS_BINS; q += 256)
+    if (hb_s[q]) atomicAdd(&hist_c[q], hb_s[q]);
+}
+
+// Current couplings, second pass.  With s = sign(w0), |w0 + d| - |w0| >= s d
+// for every step d, so the gain is at most the best gain of the smooth
+// concave g(d) = f(w0 + d) - f(w0) - lambda s d, whose slope at 0 is
+// a - lambda s and whose curvature obeys the same bounds as for a new pair:
+// gain <= (c/4) psi(2 |a - lambda s| / c).  Couplings whose bound reaches
+// *tau are appended after the collected candidates.
 template <int KIN>
 __global__ __launch_bounds__(256) void k_ks_couple(KScreenArgs P, const int32_t* __restrict__ wi,
                                                    const int32_t* __restrict__ wj,
-                                                   const double* __restrict__ wv, int64_t nnz) {
-  const int lane = threadIdx.x & (REC_WAVE - 1);
-  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x / REC_WAVE);
-  if (e >= nnz) return;
-  const int64_t i = wi[e], j = wj[e];
-  const uint16_t* ri = P.rh + i * P.Mp;
-  const uint16_t* xj = P.xh + j * P.Mp;
-  const uint16_t* rj = P.rh + j * P.Mp;
-  const uint16_t* xi = P.xh + i * P.Mp;
-  float acc = 0.f;
-  for (int64_t k = (int64_t)lane * 8; k < P.Mp; k += 8 * REC_WAVE) {
-    const halfx8 a = *reinterpret_cast<const halfx8*>(ri + k);
-    const halfx8 b = *reinterpret_cast<const halfx8*>(xj + k);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc += (float)a[q] * (float)b[q];
-    if (!KIN) {
-      const halfx8 c = *reinterpret_cast<const halfx8*>(rj + k);
-      const halfx8 d = *reinterpret_cast<const halfx8*>(xi + k);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) acc += (float)c[q] * (float)d[q];
-    }
+                                                   const double* __restrict__ wv,
+                                                   const float* __restrict__ wa, int64_t nnz) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool keep = false;
+  int32_t i = 0, j = 0;
+  if (e < nnz) {
+    i = wi[e];
+    j = wj[e];
+    const float sgn = wv[e] > 0.0 ? 1.f : -1.f;
+    const float er = P.ce * (P.l1[i] + (KIN ? 0.f : P.l1[j])) + P.el;
+    const float c = P.cv[i] + (KIN ? 0.f : P.cv[j]);
+    keep = kgain_up(fabsf(wa[e] - sgn * P.lam) + er, c) >= *P.tau;
   }
-  acc = rec_wave_sum(acc);
-  if (lane != 0) return;
-  const float sgn = wv[e] > 0.0 ? 1.f : -1.f;
-  const float er = P.ce * (P.l1[i] + (KIN ? 0.f : P.l1[j])) + P.el;
-  const float c = P.cv[i] + (KIN ? 0.f : P.cv[j]);
-  if (kgain_up(fabsf(acc - sgn * P.lam) + er, c) < *P.tau) return;
-  const int64_t pos = (int64_t)atomicAdd((unsigned long long*)P.cursor, 1ull);
-  if (pos < P.cap) {
-    P.oi[pos] = (int32_t)i;
-    P.oj[pos] = (int32_t)j;
+  const int64_t pos = rec_append(P.cursor, keep);
+  if (keep && pos < P.cap) {
+    P.oi[pos] = i;
+    P.oj[pos] = j;
   }
 }
 
@@ -747,17 +787,18 @@ __global__ __launch_bounds__(256) void k_ks_filter(const int32_t* __restrict__ I
   }
 }
 
-// tau = lower edge of the bin where the count from the top first reaches
-// target (0 if it never does).  out[0] = tau.
+// tau = lower edge of the bin where the count from the top (of hist, minus
+// sub when given) first reaches target (0 if it never does).  out[0] = tau.
 // floor_out (optional) = tau, the histogram floor of the full pass: bins at
 // or above it are counted exactly, so a proven threshold at or above the
 // collect threshold is found whenever one exists.
-__global__ void k_ks_tau(const uint32_t* hist, int64_t target, float* out, float* floor_out) {
+__global__ void k_ks_tau(const uint32_t* hist, const uint32_t* sub, int64_t target, float* out,
+                         float* floor_out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int64_t cum = 0;
   float t = 0.f;
   for (int q = KS_BINS - 1; q >= 0; --q) {
-    cum += hist[q];
+    cum += (int64_t)hist[q] - (sub ? (int64_t)sub[q] : 0);
     if (cum >= target) { t = ks_edge(q); break; }
   }
   *out = t;
@@ -871,7 +912,7 @@ KScreenArgs ks_args(rec_ctx* ctx) {
   return P;
 }
 
-rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
+rec_status kscreen_candidates(rec_ctx* ctx, int64_t m, int64_t nnz, int64_t* n_out) {
   hipStream_t s = ctx->stream;
   const int64_t N = ctx->cfg.N;
   const int kin = ctx->cfg.model == REC_KINETIC;
@@ -890,21 +931,32 @@ rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
   const int nbc = (int)((N + KS_BN - 1) / KS_BN);    // column tiles
   uint32_t* hist_s = ctx->sc_hist;
   uint32_t* hist_f = ctx->sc_hist + KS_BINS;
-  REC_HIP(hipMemsetAsync(ctx->sc_hist, 0, 2 * KS_BINS * sizeof(uint32_t), s));
+  uint32_t* hist_c = ctx->sc_hist + 2 * KS_BINS;   // current couplings' share of hist_f
+  REC_HIP(hipMemsetAsync(ctx->sc_hist, 0, 3 * KS_BINS * sizeof(uint32_t), s));
   REC_HIP(hipMemsetAsync(P.cursor, 0, sizeof(int64_t), s));
   REC_HIP(hipMemsetAsync(P.ovf, 0, sizeof(int32_t), s));
   // sample: every step-th row tile, histogram of the quadratic gain model
+  // (it counts the couplings too: the estimate keeps room for all of them)
   const int step = std::max(1, std::min(KS_SAMPLE, nb / 8));
   const int nbs = (nb + step - 1) / step;
   P.hist = hist_s;
   REC_TRY_ST(launch_ks<0, 0>(ctx, P, nbs, nbc, step));
-  const int64_t ts = std::max<int64_t>(1, 2 * target / step);
-  hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_s, ts, tau_c, floor);
-  // full pass: histogram from the floor up, collect at tau_c
+  const int64_t ts = std::max<int64_t>(1, 2 * (m + nnz) / step);
+  hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_s, (const uint32_t*)nullptr, ts, tau_c, floor);
+  // the couplings' gradients and their upper bins
+  if (nnz > 0) {
+    const unsigned grid = (unsigned)((nnz + KS_CA_PER_BLOCK - 1) / KS_CA_PER_BLOCK);
+    if (kin)
+      hipLaunchKernelGGL(k_ks_couple_a<1>, dim3(grid), dim3(256), 0, s, P, ctx->wi, ctx->wj, nnz, ctx->sc_wa, hist_c);
+    else
+      hipLaunchKernelGGL(k_ks_couple_a<0>, dim3(grid), dim3(256), 0, s, P, ctx->wi, ctx->wj, nnz, ctx->sc_wa, hist_c);
+  }
+  // full pass: histogram from the floor up, collect at tau_c; the proven
+  // threshold counts m new pairs
   P.hist = hist_f;
   P.hfloor = floor;
   REC_TRY_ST(launch_ks<2, 0>(ctx, P, nb, nbc, 1));
-  hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_f, target, tau_f, (float*)nullptr);
+  hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_f, hist_c, m, tau_f, (float*)nullptr);
   REC_HIP(hipGetLastError());
   int64_t n = 0;
   float tau[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -923,7 +975,7 @@ rec_status kscreen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
       REC_HIP(hipMemsetAsync(hist_f, 0, KS_BINS * sizeof(uint32_t), s));
       P.hfloor = nullptr;
       REC_TRY_ST(launch_ks<0, 1>(ctx, P, nb, nbc, 1));
-      hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_f, target, tau_f, (float*)nullptr);
+      hipLaunchKernelGGL(k_ks_tau, dim3(1), dim3(64), 0, s, hist_f, hist_c, m, tau_f, (float*)nullptr);
     }
     REC_HIP(hipMemcpyAsync(tau_c, tau_f, sizeof(float), hipMemcpyDeviceToDevice, s));
     REC_HIP(hipMemsetAsync(P.cursor, 0, sizeof(int64_t), s));
@@ -956,11 +1008,11 @@ rec_status rec_screen_couplings(rec_ctx* ctx, int64_t nnz, int64_t* n_out) {
   KScreenArgs P = ks_args(ctx);
   P.tau = ctx->sc_tau + 1;   // the proven threshold
   if (nnz > 0) {
-    const unsigned grid = (unsigned)((nnz + 3) / 4);
+    const unsigned grid = (unsigned)((nnz + 255) / 256);
     if (ctx->cfg.model == REC_KINETIC)
-      hipLaunchKernelGGL(k_ks_couple<1>, dim3(grid), dim3(256), 0, s, P, ctx->wi, ctx->wj, ctx->wv, nnz);
+      hipLaunchKernelGGL(k_ks_couple<1>, dim3(grid), dim3(256), 0, s, P, ctx->wi, ctx->wj, ctx->wv, ctx->sc_wa, nnz);
     else
-      hipLaunchKernelGGL(k_ks_couple<0>, dim3(grid), dim3(256), 0, s, P, ctx->wi, ctx->wj, ctx->wv, nnz);
+      hipLaunchKernelGGL(k_ks_couple<0>, dim3(grid), dim3(256), 0, s, P, ctx->wi, ctx->wj, ctx->wv, ctx->sc_wa, nnz);
     REC_HIP(hipGetLastError());
   }
   int64_t n = 0;
@@ -985,11 +1037,13 @@ rec_status rec_screen_resolve(rec_ctx* ctx) {
   return REC_OK;
 }
 
-rec_status rec_screen_candidates(rec_ctx* ctx, int64_t target, int64_t* n_out) {
+rec_status rec_screen_candidates(rec_ctx* ctx, int64_t m, int64_t nnz, int64_t* n_out) {
   hipStream_t s = ctx->stream;
   const int64_t N = ctx->cfg.N;
   const int Kp = ctx->sc_kp;
-  if (ctx->cfg.model != REC_GAUSS) return kscreen_candidates(ctx, target, n_out);
+  if (ctx->cfg.model != REC_GAUSS) return kscreen_candidates(ctx, m, nnz, n_out);
+  // every current coupling is rescored; the threshold leaves room for all of them
+  const int64_t target = m + nnz;
   if (ctx->sc_a == nullptr) { ctx->err = "screen buffers missing"; return REC_E_INVAL; }
   if (ctx->fp32)
     hipLaunchKernelGGL(k_screen_prep<float>, dim3(N), dim3(256), 0, s, ctx->F, Kp, ctx->sc_a, ctx->sc_b,

@@ -771,6 +771,23 @@ __global__ void k_ex_append(const int32_t* I, const int32_t* J, const double* g,
   val[p] = 0;
 }
 
+// pairs (I, J) as sort records keyed by i (then the original order)
+__global__ void k_pack_i(const int32_t* I, const int32_t* J, int64_t n, uint64_t* klo, uint64_t* khi,
+                         uint32_t* val) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  klo[e] = ((uint64_t)(uint32_t)I[e] << 32) | (uint32_t)J[e];
+  khi[e] = 0;
+  val[e] = 0;
+}
+
+__global__ void k_unpack_ij(const uint64_t* klo, int64_t n, int32_t* I, int32_t* J) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  I[e] = (int32_t)(klo[e] >> 32);
+  J[e] = (int32_t)(klo[e] & 0xffffffffu);
+}
+
 // kinetic FindBest result: both directions of each unordered pair
 __global__ void k_expand_dir(const int32_t* bi, const int32_t* bj, int64_t n, int32_t* I,
                              int32_t* J) {
@@ -794,6 +811,36 @@ __global__ void k_first(const int32_t* I, const int32_t* J, int64_t m, const uin
   }
   left = rec_wave_sum(left);
   if (rec_lane() == 0 && left) atomicAdd((unsigned long long*)remaining, (unsigned long long)left);
+}
+
+// W slot of every pair to apply, inserted (value 0) when absent; a zero entry
+// is the same as no entry for every reader of the table.
+__global__ void k_reserve(WTable W, const int32_t* I, const int32_t* J, int64_t m, int directed,
+                          int64_t* slot, int32_t* err) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  bool ins;
+  int64_t s = rec_hash_insert(W.keys, W.mask, rec_pair_key(I[p], J[p], directed), REC_MAX_PROBE, &ins);
+  if (s < 0) atomicOr(err, 2);
+  else if (ins) W.vals[s] = 0.0;
+  slot[p] = s;
+}
+
+// Pairs whose rows have them as their earliest pending pair form the round.
+__global__ void k_ready(const int32_t* I, const int32_t* J, int64_t m, const uint8_t* done,
+                        const int32_t* first, int directed, int32_t* ready, int64_t* nready) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool go = false;
+  if (p < m && !done[p]) go = first[I[p]] == (int32_t)p && (directed || first[J[p]] == (int32_t)p);
+  int64_t pos = rec_append(nready, go);
+  if (go) ready[pos] = (int32_t)p;
+}
+
+// first[0..n) = no pending pair; the round's ready count to zero
+__global__ void k_round_begin(int32_t* first, int64_t n, int64_t* nready) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) first[e] = 0x7fffffff;
+  if (e == 0) *nready = 0;
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -1210,7 +1257,7 @@ struct Search {
     rec_status st = rec_wtable_compact(ctx, &nnz);
     if (st != REC_OK) return st;
     int64_t nc = 0;
-    if ((st = rec_screen_candidates(ctx, m + nnz, &nc)) != REC_OK) return st;
+    if ((st = rec_screen_candidates(ctx, m, nnz, &nc)) != REC_OK) return st;
     if ((st = check_err()) != REC_OK) return st;
     int32_t* I = ctx->ts_i;
     int32_t* J = ctx->ts_j;
@@ -1228,6 +1275,18 @@ struct Search {
     }
     if (np > ctx->cand_cap || np > ctx->sb.cap) { ctx->err = "screen candidates exceed the buffers"; return REC_E_NOMEM; }
     ctx->sc_stat[7] += (double)np;
+    // group the pairs by i (stable radix sort on the i digits): the score
+    // kernel then loads each i row once per run of pairs
+    if (np > 1) {
+      hipLaunchKernelGGL(k_pack_i, dim3(gridn(np)), dim3(256), 0, s, I, J, np, ctx->sb.klo[0],
+                         ctx->sb.khi[0], ctx->sb.val[0]);
+      Digit dg[4];
+      int nd = 0;
+      for (int b = 0; b < bits_for(ctx->cfg.N); b += 8) dg[nd++] = {0, 32 + b};
+      int cur = 0;
+      if ((st = rec_radix_sort(ctx, np, dg, nd, &cur)) != REC_OK) return st;
+      hipLaunchKernelGGL(k_unpack_ij, dim3(gridn(np)), dim3(256), 0, s, ctx->sb.klo[cur], np, I, J);
+    }
     if ((st = rec_launch_score(ctx, np, I, J, nullptr, g, nullptr, nullptr)) != REC_OK) return st;
     int64_t* d_n = ctx->counter + 9;
     hipMemsetAsync(d_n, 0, sizeof(int64_t), s);
@@ -1418,17 +1477,21 @@ rec_status rec_apply_best(rec_ctx* ctx, int64_t m, const int32_t* I, const int32
   if (m <= 0) return REC_OK;
   if (m > ctx->best_cap) { ctx->err = "too many pairs for the update buffers"; return REC_E_NOMEM; }
   hipMemsetAsync(ctx->done, 0, m, s);
-  int64_t* d_rem = ctx->counter + 10;
+  hipLaunchKernelGGL(k_reserve, dim3(gridn(m)), dim3(256), 0, s, ctx->W, I, J, m, directed, ctx->best_slot,
+                     ctx->err_flag);
+  int64_t* d_ready = ctx->counter + 10;   // pairs in the current round
   int64_t pass = 0;
   while (true) {
     const int batch = 8;
     std::vector<int64_t> rem(batch, 0);
     hipMemsetAsync(ctx->scan_tmp, 0, sizeof(int64_t) * batch, s);
     for (int b = 0; b < batch; ++b) {
-      hipLaunchKernelGGL(k_fill_i32, dim3(gridn(N)), dim3(256), 0, s, ctx->first, N, 0x7fffffff);
+      hipLaunchKernelGGL(k_round_begin, dim3(gridn(N)), dim3(256), 0, s, ctx->first, N, d_ready);
       hipLaunchKernelGGL(k_first, dim3(gridn(m)), dim3(256), 0, s, I, J, m, ctx->done, ctx->first,
                          directed, ctx->scan_tmp + b);
-      rec_status st = rec_launch_update_round(ctx, m, I, J, ctx->first, ctx->done, ctx->dw);
+      hipLaunchKernelGGL(k_ready, dim3(gridn(m)), dim3(256), 0, s, I, J, m, ctx->done, ctx->first,
+                         directed, ctx->ready, d_ready);
+      rec_status st = rec_launch_update_round(ctx, m, I, J, ctx->ready, d_ready, ctx->done, ctx->dw);
       if (st != REC_OK) return st;
     }
     if (hipMemcpyAsync(rem.data(), ctx->scan_tmp, sizeof(int64_t) * batch, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -1442,7 +1505,6 @@ rec_status rec_apply_best(rec_ctx* ctx, int64_t m, const int32_t* I, const int32
     // the earliest pending pair is always ready, so m passes always suffice
     if (pass > m + batch) { ctx->err = "update rounds did not drain"; return REC_E_NUMERIC; }
   }
-  (void)d_rem;
   *rounds = pass;
   ++ctx->w_version;   // the rounds changed W
   if (rec_sum_device(ctx, ctx->dw, m, ctx->dresult + 3) != REC_OK) return REC_E_HIP;
