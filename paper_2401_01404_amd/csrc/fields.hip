@@ -317,31 +317,35 @@ __global__ __launch_bounds__(FT) void k_theta(Fields F) {
   if (lane == 0) F.theta[i] = th;
 }
 
-// Per-row log pseudolikelihood into part[i].
-template <class R, int MODEL>
+// Per-row log pseudolikelihood into part[i] (one wavefront per row).
+template <class R, int NPL, int MODEL>
 __global__ __launch_bounds__(FT) void k_rowll(Fields F, double* part) {
-  __shared__ double sh[FT / REC_WAVE];
-  const int64_t i = blockIdx.x;
+  using L = RowLayout<NPL>;
+  constexpr int VEC = L::VEC, CH = L::CH;
+  const int lane = threadIdx.x & (REC_WAVE - 1);
+  const int64_t i = (int64_t)blockIdx.x * (FT / REC_WAVE) + threadIdx.x / REC_WAVE;
+  if (i >= F.N) return;
   const R* H = reinterpret_cast<const R*>(F.H);
+  const int8_t* Y = MODEL == REC_KINETIC ? F.ys : F.xs;
+  const double v = MODEL == REC_GAUSS ? F.theta[i] * F.theta[i] : 0.0;
   double acc = 0.0;
-  if (MODEL == REC_GAUSS) {
-    double v = F.theta[i] * F.theta[i];
-    for (int64_t s = threadIdx.x; s < F.M; s += FT) {
-      double r = (double)H[i * F.Mp + s];
-      acc += -r * r / (2.0 * v);
-    }
-  } else {
-    const int8_t* Y = MODEL == REC_KINETIC ? F.ys : F.xs;
-    for (int64_t s = threadIdx.x; s < F.M; s += FT) {
-      R h = H[i * F.Mp + s];
-      R y = (R)Y[i * F.Mp + s];
-      acc += (double)(y * h - log2cosh_(h));
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int64_t o = L::at(c, lane), idx = i * F.Mp + o;
+    const Pack<R, VEC> hv = *reinterpret_cast<const Pack<R, VEC>*>(H + idx);
+    double y[VEC];
+    if (MODEL != REC_GAUSS) ld_i8<VEC>(Y + idx, y);
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      if (o + k >= F.M) continue;
+      const R h = hv.v[k];
+      if (MODEL == REC_GAUSS) acc += -(double)h * (double)h / (2.0 * v);
+      else acc += (double)((R)y[k] * h - log2cosh_(h));
     }
   }
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) {
-    if (MODEL == REC_GAUSS)
-      acc += (double)F.M * (-log(F.theta[i]) - 0.5 * log(2.0 * M_PI));
+  acc = rec_wave_sum(acc);
+  if (lane == 0) {
+    if (MODEL == REC_GAUSS) acc += (double)F.M * (-log(F.theta[i]) - 0.5 * log(2.0 * M_PI));
     part[i] = acc;
   }
 }
@@ -395,15 +399,42 @@ __global__ void k_winsert(WTable W, int64_t n, const int32_t* ei, const int32_t*
   W.vals[s] = v;
 }
 
-// occupied, nonzero table entries -> sort records (key = pair key, val = slot)
+// occupied, nonzero table entries -> sort records (key = pair key, val = slot).
+// A block takes WC_PER * 256 slots (thread t: slots t, t + 256, ...), counts
+// its entries, and reserves one output run with a single atomic.
+constexpr int WC_PER = 16;
 __global__ __launch_bounds__(256) void k_wcompact(WTable W, uint64_t cap, uint64_t* klo,
                                                   uint32_t* val, int64_t* n, int64_t max_n) {
   __shared__ long long sh[256 / REC_WAVE + 1];
-  uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint64_t k = s < cap ? W.keys[s] : REC_EMPTY;
-  bool keep = k != REC_EMPTY && W.vals[s] != 0.0;
-  int64_t p = rec_block_append<256 / REC_WAVE>(n, keep, sh);
-  if (p >= 0 && p < max_n) { klo[p] = k; val[p] = (uint32_t)s; }
+  const uint64_t base = (uint64_t)blockIdx.x * (256 * WC_PER) + threadIdx.x;
+  uint32_t keep = 0;
+#pragma unroll
+  for (int u = 0; u < WC_PER; ++u) {
+    const uint64_t s = base + 256u * u;
+    if (s < cap && W.keys[s] != REC_EMPTY && W.vals[s] != 0.0) keep |= 1u << u;
+  }
+  // exclusive prefix of the per-thread counts over the block
+  const int lane = threadIdx.x & (REC_WAVE - 1), wave = threadIdx.x / REC_WAVE;
+  const int cnt = __popc(keep);
+  int inc = cnt;
+#pragma unroll
+  for (int o = 1; o < REC_WAVE; o <<= 1) {
+    const int v = __shfl_up(inc, o, REC_WAVE);
+    if (lane >= o) inc += v;
+  }
+  if (lane == REC_WAVE - 1) sh[wave] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long tot = 0;
+    for (int w = 0; w < 256 / REC_WAVE; ++w) { const long long c = sh[w]; sh[w] = tot; tot += c; }
+    sh[256 / REC_WAVE] = tot ? (long long)atomicAdd((unsigned long long*)n, (unsigned long long)tot) : 0;
+  }
+  __syncthreads();
+  int64_t p = (int64_t)(sh[256 / REC_WAVE] + sh[wave]) + (inc - cnt);
+  for (uint32_t k = keep; k; k &= k - 1, ++p) {
+    const uint64_t s = base + 256u * (uint32_t)__builtin_ctz(k);
+    if (p < max_n) { klo[p] = W.keys[s]; val[p] = (uint32_t)s; }
+  }
 }
 
 __global__ void k_wunpack(const uint64_t* klo, const uint32_t* val, const double* wvals, int64_t n,
@@ -496,17 +527,20 @@ rec_status launch_fields_r(rec_ctx* ctx) { REC_NPL_SWITCH(launch_fields_n, R) }
 template <class R>
 rec_status launch_theta_r(rec_ctx* ctx) { REC_NPL_SWITCH(launch_theta_n, R) }
 
-template <class R>
-rec_status launch_rowll_r(rec_ctx* ctx) {
-  dim3 g(ctx->cfg.N), b(FT);
+template <class R, int NPL>
+rec_status launch_rowll_n(rec_ctx* ctx) {
+  dim3 g((unsigned)((ctx->cfg.N + FT / REC_WAVE - 1) / (FT / REC_WAVE))), b(FT);
   switch (ctx->cfg.model) {
-    case REC_ISING: hipLaunchKernelGGL((k_rowll<R, REC_ISING>), g, b, 0, ctx->stream, ctx->F, ctx->dscratch); break;
-    case REC_GAUSS: hipLaunchKernelGGL((k_rowll<R, REC_GAUSS>), g, b, 0, ctx->stream, ctx->F, ctx->dscratch); break;
-    default: hipLaunchKernelGGL((k_rowll<R, REC_KINETIC>), g, b, 0, ctx->stream, ctx->F, ctx->dscratch);
+    case REC_ISING: hipLaunchKernelGGL((k_rowll<R, NPL, REC_ISING>), g, b, 0, ctx->stream, ctx->F, ctx->dscratch); break;
+    case REC_GAUSS: hipLaunchKernelGGL((k_rowll<R, NPL, REC_GAUSS>), g, b, 0, ctx->stream, ctx->F, ctx->dscratch); break;
+    default: hipLaunchKernelGGL((k_rowll<R, NPL, REC_KINETIC>), g, b, 0, ctx->stream, ctx->F, ctx->dscratch);
   }
   REC_HIP(hipGetLastError());
   return REC_OK;
 }
+
+template <class R>
+rec_status launch_rowll_r(rec_ctx* ctx) { REC_NPL_SWITCH(launch_rowll_n, R) }
 
 }  // namespace
 
@@ -558,7 +592,7 @@ rec_status rec_wtable_compact(rec_ctx* ctx, int64_t* nnz_out) {
   const uint64_t cap = ctx->W.mask + 1;
   int64_t* d_n = ctx->counter + 4;
   REC_HIP(hipMemsetAsync(d_n, 0, sizeof(int64_t), ctx->stream));
-  hipLaunchKernelGGL(k_wcompact, dim3((cap + 255) / 256), dim3(256), 0, ctx->stream, ctx->W, cap,
+  hipLaunchKernelGGL(k_wcompact, dim3((cap + 256 * WC_PER - 1) / (256 * WC_PER)), dim3(256), 0, ctx->stream, ctx->W, cap,
                      ctx->sb.klo[0], ctx->sb.val[0], d_n, ctx->max_nnz);
   int64_t n = 0;
   REC_HIP(hipMemcpyAsync(&n, d_n, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
