@@ -63,24 +63,25 @@ PEAK_F16_MFMA_TFLOPS = 2500.0   # dense FP16 matrix-core peak
 
 # HBM traffic of the pair-score kernels (k_kink + k_exact, or k_score) per
 # algorithmic byte, from two rocprofv3 --pmc runs (FETCH_SIZE, then
-# WRITE_SIZE) of `bench.py --workload W --steps 6 --warmup 0 --no-cpu`, each
+# WRITE_SIZE) of `bench.py --workload W --steps 1 --warmup 0 --no-cpu
+# --no-compare` (the screened search's rescoring kernel k_score), each
 # scaled by a 1 GiB device copy (`bench.py --copy-probe 1024`: FETCH_SIZE
 # reads 0.5x the bytes copied, WRITE_SIZE 1.0x).  Valid only for the score
 # kernel source it was measured on: `traffic` is null once that file changes.
 TRAFFIC = {
-    "C4": {"source_sha256": "d2223f25323d3d7c770349d9dca534e7fc7919d19dd373331e979719c34d0242",
-           "hbm_over_algorithmic": 1.1321,
-           "measured_hbm_bytes_per_launch": 1.7071e+10},
+    "C4": {"source_sha256": "b523a124b02fa7fe57c43690a59b6ef2070312e6e597e7e137fce2df04ee2e46",
+           "hbm_over_algorithmic": 1.0325,
+           "measured_hbm_bytes_per_launch": 1.4602e+09},
 }
 
 
 # HBM traffic of the contraction's full pass (k_kscreen<2,...>) per launch,
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
-# `bench.py --workload W --steps 2 --warmup 0 --no-cpu`, scaled by the same
+# `bench.py --workload W --steps 1 --warmup 0 --no-cpu --no-compare`, scaled by the same
 # 1 GiB copy probe.  Valid only for the source it was measured on.
 TRAFFIC_SCREEN = {
-    "C4": {"source_sha256": "5694bc0441926bae7940794bb4203487f9ce75bb8bfb14e91a13371b91b4638d",
-           "hbm_bytes_per_launch": 2.2155e+10},
+    "C4": {"source_sha256": "ad2cfce22b7b15d76f3c9230b75a389307597050bc8d6692b4a2ef23ac35fcce",
+           "hbm_bytes_per_launch": 3.1754e+10},
 }
 
 

@@ -161,7 +161,9 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   x->best_i = a.take<int32_t>(z.best_cap);
   x->best_j = a.take<int32_t>(z.best_cap);
   x->best_g = a.take<double>(z.best_cap);
-  x->first = a.take<int32_t>(N);
+  x->pred = a.take<int32_t>(2 * z.best_cap);
+  x->pend[0] = a.take<int32_t>(z.best_cap);
+  x->pend[1] = a.take<int32_t>(z.best_cap);
   x->done = a.take<uint8_t>(z.best_cap);
   x->dw = a.take<double>(z.best_cap);
   x->ready = a.take<int32_t>(z.best_cap);

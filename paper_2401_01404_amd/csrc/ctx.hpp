@@ -130,7 +130,8 @@ struct rec_ctx {
   // E_best and update rounds
   int64_t best_cap;
   int32_t *best_i, *best_j; double* best_g;
-  int32_t* first;       // N
+  int32_t* pred;        // 2 best_cap: previous pair on each row of a pair being applied
+  int32_t* pend[2];     // best_cap each: pending pairs of the update rounds (ping-pong)
   uint8_t* done;        // best_cap
   double* dw;           // best_cap
   int32_t* ready;       // best_cap: the pairs of the current update round

@@ -944,12 +944,14 @@ __device__ __forceinline__ void update_pair(const Fields& F, const WTable& W, do
 // that are the earliest pending pair of each of their rows; such pairs touch
 // disjoint rows, so the round equals the sequential rank order. The grid is
 // sized for the device, not the list: each wave takes list entries in a
-// grid-stride loop, so every resident wave solves a ready pair.  W entries
+// grid-stride loop, so every resident wave solves a ready pair (each pair is a
+// serial chain of loads and Newton steps: five waves per SIMD, 94 VGPRs,
+// hide more of it than the four that the unconstrained allocation allows).  W entries
 // are reached through the slots reserved for the list before the rounds
 // (wslot[p], no probing on the serial path of a pair); a pair's entry is
 // written only by that pair, so its value is current when the pair runs.
 template <class R, int NPL, int MODEL>
-__global__ __launch_bounds__(256) void k_update(Fields F, WTable W, double lambda,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_update(Fields F, WTable W, double lambda,
                                                 const int32_t* __restrict__ I,
                                                 const int32_t* __restrict__ J,
                                                 const int32_t* __restrict__ ready,

@@ -800,19 +800,6 @@ __global__ void k_expand_dir(const int32_t* bi, const int32_t* bj, int64_t n, in
 }
 
 // ---- update rounds ----
-__global__ void k_first(const int32_t* I, const int32_t* J, int64_t m, const uint8_t* done,
-                        int32_t* first, int directed, int64_t* remaining) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int left = 0;
-  if (p < m && !done[p]) {
-    atomicMin(&first[I[p]], (int32_t)p);
-    if (!directed) atomicMin(&first[J[p]], (int32_t)p);
-    left = 1;
-  }
-  left = rec_wave_sum(left);
-  if (rec_lane() == 0 && left) atomicAdd((unsigned long long*)remaining, (unsigned long long)left);
-}
-
 // W slot of every pair to apply, inserted (value 0) when absent; a zero entry
 // is the same as no entry for every reader of the table.
 __global__ void k_reserve(WTable W, const int32_t* I, const int32_t* J, int64_t m, int directed,
@@ -826,21 +813,68 @@ __global__ void k_reserve(WTable W, const int32_t* I, const int32_t* J, int64_t 
   slot[p] = s;
 }
 
-// Pairs whose rows have them as their earliest pending pair form the round.
-__global__ void k_ready(const int32_t* I, const int32_t* J, int64_t m, const uint8_t* done,
-                        const int32_t* first, int directed, int32_t* ready, int64_t* nready) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool go = false;
-  if (p < m && !done[p]) go = first[I[p]] == (int32_t)p && (directed || first[J[p]] == (int32_t)p);
-  int64_t pos = rec_append(nready, go);
-  if (go) ready[pos] = (int32_t)p;
+// Row entries of the pairs to apply: key row << 32 | rank, one per row a
+// pair touches (directed pairs: row i only).
+__global__ void k_row_entries(const int32_t* I, const int32_t* J, int64_t m, int directed,
+                              uint64_t* klo, uint64_t* khi, uint32_t* val) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ne = directed ? m : 2 * m;
+  if (e >= ne) return;
+  const int64_t p = directed ? e : e >> 1;
+  const int32_t row = (directed || !(e & 1)) ? I[p] : J[p];
+  klo[e] = ((uint64_t)(uint32_t)row << 32) | (uint32_t)p;
+  khi[e] = 0;
+  val[e] = 0;
 }
 
-// first[0..n) = no pending pair; the round's ready count to zero
-__global__ void k_round_begin(int32_t* first, int64_t n, int64_t* nready) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) first[e] = 0x7fffffff;
-  if (e == 0) *nready = 0;
+// With the entries sorted by (row, rank): pred[2p + side] = the previous pair
+// on the row of that side of pair p, or -1 (side 0: row I[p], 1: row J[p]).
+__global__ void k_pred(const uint64_t* klo, int64_t ne, const int32_t* I, int32_t* pred) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const uint64_t k = klo[e];
+  const uint32_t row = (uint32_t)(k >> 32);
+  const int32_t p = (int32_t)(uint32_t)k;
+  const int32_t prev = (e > 0 && (uint32_t)(klo[e - 1] >> 32) == row) ? (int32_t)(uint32_t)klo[e - 1] : -1;
+  pred[2 * (int64_t)p + ((uint32_t)I[p] == row ? 0 : 1)] = prev;
+}
+
+__global__ void k_iota_i32(int32_t* a, int64_t n, int64_t* count) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) a[e] = (int32_t)e;
+  if (e == 0) *count = n;
+}
+
+// Before a round: log the pending count, clear the round's two counters.
+__global__ void k_round_begin(const int64_t* npend, int64_t* log, int64_t* nready, int64_t* npend_next) {
+  *log = *npend;
+  *nready = 0;
+  *npend_next = 0;
+}
+
+// Split the pending pairs: a pair whose predecessors on its rows are done is
+// the earliest pending pair of those rows and joins the round (ready); the
+// others stay pending.  A grid-stride loop over the device-side count.
+__global__ __launch_bounds__(256) void k_split_ready(const int32_t* pend, const int64_t* npend,
+                                                     const int32_t* pred, const uint8_t* done,
+                                                     int32_t* ready, int64_t* nready,
+                                                     int32_t* pend_next, int64_t* npend_next) {
+  const int64_t n = *npend;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = base + threadIdx.x;
+    const bool have = q < n;
+    int32_t p = 0;
+    bool go = false;
+    if (have) {
+      p = pend[q];
+      const int32_t a = pred[2 * (int64_t)p], b = pred[2 * (int64_t)p + 1];
+      go = (a < 0 || done[a]) && (b < 0 || done[b]);
+    }
+    const int64_t r = rec_append(nready, have && go);
+    if (r >= 0) ready[r] = p;
+    const int64_t k = rec_append(npend_next, have && !go);
+    if (k >= 0) pend_next[k] = p;
+  }
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -1464,35 +1498,56 @@ rec_status rec_search_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int k, 
 }
 
 // Coordinate updates of the m pairs in rank order [Alg. 2], as rounds of
-// node-disjoint pairs (Q: a pair runs once every earlier pair sharing a row
-// with it has run), which reproduces the sequential order exactly.
+// node-disjoint pairs (a pair runs once every earlier pair sharing a row
+// with it has run), which reproduces the sequential order exactly.  Each
+// pair's predecessor on each of its rows comes from one sort of its row
+// entries; a round takes the pending pairs whose predecessors are done.
 rec_status rec_apply_best(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
                           double* delta, int64_t* accepted, int64_t* rounds) {
   hipStream_t s = ctx->stream;
-  const int64_t N = ctx->cfg.N;
   const int directed = ctx->cfg.model == REC_KINETIC;
   *delta = 0.0;
   *accepted = 0;
   *rounds = 0;
   if (m <= 0) return REC_OK;
   if (m > ctx->best_cap) { ctx->err = "too many pairs for the update buffers"; return REC_E_NOMEM; }
+  const int64_t ne = directed ? m : 2 * m;
+  if (ne > ctx->sb.cap) { ctx->err = "too many pairs for the sort buffers"; return REC_E_NOMEM; }
   hipMemsetAsync(ctx->done, 0, m, s);
   hipLaunchKernelGGL(k_reserve, dim3(gridn(m)), dim3(256), 0, s, ctx->W, I, J, m, directed, ctx->best_slot,
                      ctx->err_flag);
-  int64_t* d_ready = ctx->counter + 10;   // pairs in the current round
+  // predecessors on the rows
+  hipLaunchKernelGGL(k_fill_i32, dim3(gridn(2 * m)), dim3(256), 0, s, ctx->pred, 2 * m, -1);
+  hipLaunchKernelGGL(k_row_entries, dim3(gridn(ne)), dim3(256), 0, s, I, J, m, directed, ctx->sb.klo[0],
+                     ctx->sb.khi[0], ctx->sb.val[0]);
+  {
+    Digit dg[8];
+    int nd = 0;
+    for (int b = 0; b < bits_for(m); b += 8) dg[nd++] = {0, b};
+    for (int b = 0; b < bits_for(ctx->cfg.N); b += 8) dg[nd++] = {0, 32 + b};
+    int cur = 0;
+    rec_status st = rec_radix_sort(ctx, ne, dg, nd, &cur);
+    if (st != REC_OK) return st;
+    hipLaunchKernelGGL(k_pred, dim3(gridn(ne)), dim3(256), 0, s, ctx->sb.klo[cur], ne, I, ctx->pred);
+  }
+  // pending lists (ping-pong) and their counts, the round's ready count
+  int64_t* npend[2] = {ctx->counter + 0, ctx->counter + 1};
+  int64_t* d_ready = ctx->counter + 10;
+  hipLaunchKernelGGL(k_iota_i32, dim3(gridn(m)), dim3(256), 0, s, ctx->pend[0], m, npend[0]);
+  const unsigned split_grid = (unsigned)std::min<int64_t>(gridn(m), 1024);
+  int cur = 0;
   int64_t pass = 0;
   while (true) {
     const int batch = 8;
     std::vector<int64_t> rem(batch, 0);
-    hipMemsetAsync(ctx->scan_tmp, 0, sizeof(int64_t) * batch, s);
     for (int b = 0; b < batch; ++b) {
-      hipLaunchKernelGGL(k_round_begin, dim3(gridn(N)), dim3(256), 0, s, ctx->first, N, d_ready);
-      hipLaunchKernelGGL(k_first, dim3(gridn(m)), dim3(256), 0, s, I, J, m, ctx->done, ctx->first,
-                         directed, ctx->scan_tmp + b);
-      hipLaunchKernelGGL(k_ready, dim3(gridn(m)), dim3(256), 0, s, I, J, m, ctx->done, ctx->first,
-                         directed, ctx->ready, d_ready);
+      hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, s, npend[cur], ctx->scan_tmp + b, d_ready,
+                         npend[cur ^ 1]);
+      hipLaunchKernelGGL(k_split_ready, dim3(split_grid), dim3(256), 0, s, ctx->pend[cur], npend[cur], ctx->pred,
+                         ctx->done, ctx->ready, d_ready, ctx->pend[cur ^ 1], npend[cur ^ 1]);
       rec_status st = rec_launch_update_round(ctx, m, I, J, ctx->ready, d_ready, ctx->done, ctx->dw);
       if (st != REC_OK) return st;
+      cur ^= 1;
     }
     if (hipMemcpyAsync(rem.data(), ctx->scan_tmp, sizeof(int64_t) * batch, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { ctx->err = "readback failed"; return REC_E_HIP; }
@@ -1502,7 +1557,7 @@ rec_status rec_apply_best(rec_ctx* ctx, int64_t m, const int32_t* I, const int32
       else finished = true;
     }
     if (finished) break;
-    // the earliest pending pair is always ready, so m passes always suffice
+    // the earliest pending pair is always ready, so m rounds always suffice
     if (pass > m + batch) { ctx->err = "update rounds did not drain"; return REC_E_NUMERIC; }
   }
   *rounds = pass;
