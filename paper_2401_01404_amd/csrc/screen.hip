@@ -816,7 +816,7 @@ namespace {
 // gain) is at least tau_s, every pair whose upper bound reaches tau was
 // collected, so the set is complete; otherwise, or when a buffer overflowed,
 // a collect pass at tau runs.
-constexpr int KS_SAMPLE = 16;   // largest sampling step of the row tiles
+constexpr int KS_SAMPLE = 32;   // largest sampling step of the row tiles
 
 #define REC_TRY_ST(...)                      \
   do {                                       \
