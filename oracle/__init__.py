@@ -61,6 +61,8 @@ def _L():
             "orc_lcosh": (dbl, [dbl]),
             "orc_dlcosh": (dbl, [dbl, dbl]),
             "orc_ctr": (u64, [u64, u64, u64, u64]),
+            "orc_set_dist": (None, [vp, ci]),
+            "orc_grad_pairs": (None, [vp, i64, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -147,26 +149,48 @@ class Oracle:
     def pair_deriv(self, i, j, w):
         return _L().orc_pair_deriv(self.h, int(i), int(j), float(w))
 
+    def grad_pairs(self, I, J):
+        """Absolute gradient of the objective in W_ij at the current state
+        (the gradient distance of the paper's appendix; central difference at
+        the L1 kink), per pair."""
+        I, J = _i32(I), _i32(J)
+        g = np.zeros(len(I), np.float64)
+        _L().orc_grad_pairs(self.h, len(I), _p(I), _p(J), _p(g))
+        return g
+
+    def _dist(self, dist):
+        _L().orc_set_dist(self.h, {"gain": 0, "gradient": 1}[dist])
+
     # --- search --------------------------------------------------------
-    def find_best(self, m, mode="exhaustive", seed=0, eps=1e-3, max_iter=0):
+    def find_best(self, m, mode="exhaustive", seed=0, eps=1e-3, max_iter=0, dist="gain"):
+        """Best m pairs under the search distance ("gain": the exact gain;
+        "gradient": the absolute gradient, see grad_pairs)."""
         mode_id = {"exhaustive": 0, "exact_knn": 1, "nndescent": 2}[mode]
         I = np.zeros(m, np.int32)
         J = np.zeros(m, np.int32)
         G = np.zeros(m, np.float64)
         st = np.zeros(64, np.int64)
-        n = _L().orc_find_best(self.h, m, mode_id, seed, eps, max_iter, _p(I), _p(J), _p(G), _p(st))
+        self._dist(dist)
+        try:
+            n = _L().orc_find_best(self.h, m, mode_id, seed, eps, max_iter, _p(I), _p(J), _p(G), _p(st))
+        finally:
+            self._dist("gain")
         levels = int(st[0])
         stats = dict(levels=levels, nnd_iters=int(st[1]), evals=int(st[2]),
                      level_n=[int(st[3 + 2 * l]) for l in range(min(levels, 30))],
                      level_k=[int(st[4 + 2 * l]) for l in range(min(levels, 30))])
         return I[:n], J[:n], G[:n], stats
 
-    def knn(self, S, k, mode="nndescent", seed=0, level=0, eps=1e-3, max_iter=0):
+    def knn(self, S, k, mode="nndescent", seed=0, level=0, eps=1e-3, max_iter=0, dist="gain"):
         S = _i32(S)
         J = np.zeros(len(S) * k, np.int32)
         G = np.zeros(len(S) * k, np.float64)
-        it = _L().orc_knn(self.h, len(S), _p(S), k, {"exact": 1, "nndescent": 2}[mode], seed, level,
-                          eps, max_iter, _p(J), _p(G))
+        self._dist(dist)
+        try:
+            it = _L().orc_knn(self.h, len(S), _p(S), k, {"exact": 1, "nndescent": 2}[mode], seed, level,
+                              eps, max_iter, _p(J), _p(G))
+        finally:
+            self._dist("gain")
         return J.reshape(len(S), k), G.reshape(len(S), k), it
 
     # --- updates -------------------------------------------------------
@@ -176,11 +200,17 @@ class Oracle:
         d = _L().orc_apply_updates(self.h, len(I), _p(I), _p(J), int(check), _p(bad))
         return d, int(bad[0])
 
-    def gcd_sweep(self, m, mode="exhaustive", seed=0, eps=1e-3, max_iter=0):
+    def gcd_sweep(self, m, mode="exhaustive", seed=0, eps=1e-3, max_iter=0, dist="gain"):
+        """One GCD sweep; E_best ranked by the search distance, every update
+        the exact coordinate maximum."""
         mode_id = {"exhaustive": 0, "exact_knn": 1, "nndescent": 2}[mode]
         obj = np.zeros(1)
         nb = np.zeros(1, np.int64)
-        d = _L().orc_gcd_sweep(self.h, m, mode_id, seed, eps, max_iter, _p(obj), _p(nb))
+        self._dist(dist)
+        try:
+            d = _L().orc_gcd_sweep(self.h, m, mode_id, seed, eps, max_iter, _p(obj), _p(nb))
+        finally:
+            self._dist("gain")
         return d, float(obj[0])
 
     def cd_sweep(self):

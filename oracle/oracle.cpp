@@ -116,6 +116,7 @@ struct Problem {
   std::vector<double> theta;     // Ising/kinetic: field; Gaussian: theta_i = 1/sqrt(W_ii)
   std::vector<double> msum;      // N x M: m_{i,m} = sum_{j != i} W_ij in_{j,m}
   std::vector<double> sq;        // Gaussian: ||x_i||^2
+  int dist = 0;                  // search distance: 0 the exact gain, 1 the absolute gradient
 
   double X(int64_t i, int64_t m) const { return in[i * M + m]; }
   double Y(int64_t i, int64_t m) const { return out[i * M + m]; }
@@ -284,6 +285,39 @@ void pair_gain(const Problem& P, int i, int j, double* gain, double* wopt) {
   *gain = F.f(ws - w0) - lam * (std::fabs(ws) - std::fabs(w0));
 }
 
+// Gradient as distance [Appendix, "Gradient as distance"]: the absolute
+// derivative of the objective with respect to W_ij at the current state,
+// taken as the paper takes it for L1-penalised objectives, by a central
+// difference: away from the kink (w0 != 0) it is F'(w0) - lambda sign(w0);
+// at w0 = 0 the two one-sided penalty terms cancel and it is F'(0).  The
+// score is its absolute value (larger = better, as for the gain).
+double pair_grad(const Problem& P, int i, int j) {
+  if (P.model != KINETIC && i > j) std::swap(i, j);
+  const double w0 = P.w(i, j);
+  double f1;
+  if (P.model == GAUSS) {
+    // F(delta) = a delta - b delta^2 / 2 around the current state
+    const double vi = P.theta[i] * P.theta[i], vj = P.theta[j] * P.theta[j];
+    double a = 0.0;
+    for (int64_t m = 0; m < P.M; ++m)
+      a -= (P.Y(i, m) + vi * P.msum[i * P.M + m]) * P.X(j, m) +
+           (P.Y(j, m) + vj * P.msum[j * P.M + m]) * P.X(i, m);
+    f1 = a;
+  } else {
+    double f2;
+    Smooth{P, i, j}.d12(0.0, f1, f2);
+  }
+  return std::fabs(w0 == 0.0 ? f1 : f1 - P.lambda * sgn(w0));
+}
+
+// The search score of a pair under the problem's distance.
+double pair_dist(const Problem& P, int i, int j) {
+  if (P.dist == 1) return pair_grad(P, i, j);
+  double g, w;
+  pair_gain(P, i, j, &g, &w);
+  return g;
+}
+
 // -------------------------------------------------------------- updates ---
 
 // W_ij <- w, keeping m_i (and m_j) current [App. A].
@@ -394,13 +428,8 @@ bool nb_less(const Nb& a, const Nb& b) {
 struct ScoreFn {
   const Problem& P;
   double operator()(int i, int j) const {
-    double g, w;
-    pair_gain(P, i, j, &g, &w);
-    if (P.model == KINETIC) {
-      double g2, w2;
-      pair_gain(P, j, i, &g2, &w2);
-      g = std::max(g, g2);
-    }
+    double g = pair_dist(P, i, j);
+    if (P.model == KINETIC) g = std::max(g, pair_dist(P, j, i));
     return g;
   }
 };
@@ -518,8 +547,7 @@ std::vector<Pair> exhaustive(const Problem& P, const std::vector<int>& S) {
     int64_t b0 = P.model == KINETIC ? 0 : a + 1;
     for (int64_t b = b0; b < n; ++b) {
       if (b == a) continue;
-      double g, w;
-      pair_gain(P, S[a], S[b], &g, &w);
+      const double g = pair_dist(P, S[a], S[b]);
       if (P.model == KINETIC) rows[a].push_back({S[a], S[b], g});
       else rows[a].push_back({std::min(S[a], S[b]), std::max(S[a], S[b]), g});
     }
@@ -620,9 +648,7 @@ std::vector<Pair> find_best(const Problem& P, int64_t m, int mode, uint64_t seed
   for (auto& p : res)
     for (int d = 0; d < 2; ++d) {
       int i = d ? p.j : p.i, j = d ? p.i : p.j;
-      double g, w;
-      pair_gain(P, i, j, &g, &w);
-      dir.push_back({i, j, g});
+      dir.push_back({i, j, pair_dist(P, i, j)});
     }
   std::sort(dir.begin(), dir.end(), [&](const Pair& x, const Pair& y) { return pair_less(P, x, y); });
   if ((int64_t)dir.size() > m) dir.resize(m);
@@ -843,6 +869,16 @@ double orc_cd_sweep(void* h) {
     }
   theta_update(P);
   return delta;
+}
+
+// Search distance: 0 the exact gain, 1 the absolute gradient (pair_grad).
+void orc_set_dist(void* h, int dist) { ((Problem*)h)->dist = dist; }
+
+// Absolute gradients of pairs (pair_grad), whatever the search distance.
+void orc_grad_pairs(void* h, int64_t n, const int32_t* I, const int32_t* J, double* out) {
+  Problem& P = *(Problem*)h;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t p = 0; p < n; ++p) out[p] = pair_grad(P, I[p], J[p]);
 }
 
 // exported numerics for the pin tests

@@ -558,3 +558,98 @@ def test_gcd_converges_to_kkt_point_and_matches_cd(model):
                 assert abs(g) <= lam * (1 + 1e-6) + 1e-7
             else:
                 assert abs(g - lam * np.sign(W[i, j])) <= 1e-6 * lam
+
+
+# ------------------------------------------------- gradient as distance --
+
+def _state(model, rng, N, M):
+    directed = model == "kinetic"
+    if model == "gauss":
+        Theta = sym_sparse(rng, N, 0.5, 0.3)
+        np.fill_diagonal(Theta, np.abs(Theta).sum(1) + 0.5)
+        X = rng.multivariate_normal(np.zeros(N), np.linalg.inv(Theta), size=M).T.astype(np.float32)
+        W = Theta - np.diag(np.diag(Theta))
+        theta = 1.0 / np.sqrt(np.diag(Theta))
+    elif model == "kinetic":
+        X = rand_pm1(rng, N, M + 1)
+        W = np.where(rng.random((N, N)) < 0.4, rng.normal(0, 0.4, (N, N)), 0.0)
+        np.fill_diagonal(W, 0)
+        theta = rng.normal(0, 0.2, N)
+    else:
+        X = rand_pm1(rng, N, M)
+        W = sym_sparse(rng, N, 0.5, 0.4)
+        theta = rng.normal(0, 0.2, N)
+    return X, W, theta, directed
+
+
+@pytest.mark.parametrize("model", ["ising", "kinetic", "gauss"])
+def test_gradient_distance_is_central_difference_of_objective(model):
+    """Gradient as distance [Appendix]: |d objective / d W_ij| by a central
+    difference of the full objective (pinned above), at couplings w0 != 0 (the
+    penalty contributes -lambda sign(w0)) and at w0 = 0 (the two one-sided
+    penalty terms cancel)."""
+    rng = np.random.default_rng(11)
+    N, M = 7, 60
+    lam = 1.5
+    X, W, theta, directed = _state(model, rng, N, M)
+    O = oracle.Oracle(X, model, lam)
+    O.set_model(*coo(W, directed), theta)
+    pairs = [(i, j) for i in range(N) for j in range(N) if i != j and (directed or i < j)]
+    I = np.array([p[0] for p in pairs], np.int32)
+    J = np.array([p[1] for p in pairs], np.int32)
+    g = O.grad_pairs(I, J)
+    eps = 1e-4
+    nz = 0
+    for k, (i, j) in enumerate(pairs):
+        vals = []
+        for s in (+1, -1):
+            W2 = W.copy()
+            W2[i, j] = W[i, j] + s * eps
+            if not directed:
+                W2[j, i] = W2[i, j]
+            O.set_model(*coo(W2, directed), theta)
+            vals.append(O.objective())
+        fd = abs(vals[0] - vals[1]) / (2 * eps)
+        nz += W[i, j] != 0
+        assert abs(g[k] - fd) <= 1e-5 * max(1.0, fd), (model, i, j, g[k], fd, W[i, j])
+    O.set_model(*coo(W, directed), theta)
+    assert nz >= 3 and nz <= len(pairs) - 3   # both kinds of pair are covered
+
+
+@pytest.mark.parametrize("model", ["ising", "kinetic"])
+def test_gradient_distance_decides_the_kink(model):
+    """At w0 = 0 the exact gain is positive exactly when the absolute gradient
+    exceeds lambda (the L1 optimality condition), so both distances agree on
+    which new pairs can gain."""
+    w = synth.ising_er(60, 200, 3.0, 0.4, 0.1, seed=4) if model == "ising" else \
+        synth.kinetic_er(60, 200, 3.0, 0.4, seed=4)
+    lam = oracle.default_lambda(w.X, model)
+    O = oracle.Oracle(w.X, model, lam)
+    N = w.X.shape[0]
+    pairs = [(i, j) for i in range(N) for j in range(N) if i != j and (model == "kinetic" or i < j)]
+    I = np.array([p[0] for p in pairs], np.int32)
+    J = np.array([p[1] for p in pairs], np.int32)
+    g, _ = O.score_pairs(I, J)
+    d = O.grad_pairs(I, J)
+    far = np.abs(d - lam) > 1e-9 * lam
+    assert far.sum() > 0.99 * len(pairs)
+    assert np.array_equal((g > 0)[far], (d > lam)[far])
+    assert (d > lam).sum() >= 5
+
+
+@pytest.mark.parametrize("model", ["ising", "kinetic"])
+def test_findbest_gradient_exact_knn_equals_exhaustive(model):
+    """FindBest [Alg. 3] under the gradient distance with exact KNN returns the
+    exhaustive ranking by that distance (kinetic: both directions of the
+    unordered pairs, as for the gain)."""
+    w = synth.ising_er(80, 150, 3.0, 0.4, 0.1, seed=6) if model == "ising" else \
+        synth.kinetic_er(80, 150, 3.0, 0.4, seed=6)
+    lam = oracle.default_lambda(w.X, model)
+    O = oracle.Oracle(w.X, model, lam)
+    O.gcd_sweep(40, "exhaustive")                      # a state with couplings
+    for m in [10, 60, 200]:
+        I, J, G, _ = O.find_best(m, "exhaustive", dist="gradient")
+        I2, J2, G2, _ = O.find_best(m, "exact_knn", dist="gradient")
+        assert np.array_equal(I, I2) and np.array_equal(J, J2) and np.array_equal(G, G2)
+        assert np.array_equal(G, O.grad_pairs(I, J))
+        assert np.all(np.diff(G) <= 0)
