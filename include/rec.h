@@ -67,7 +67,7 @@ typedef enum {
   REC_SEARCH_EXHAUSTIVE = 1,  /* all pairs scored exactly, best m kept         */
   REC_SEARCH_SURROGATE = 2,   /* learned proposal ahead of NNDescent            */
   REC_SEARCH_EXACT_KNN = 3,   /* FindBest [Alg. 3] over exhaustive KNN lists    */
-  REC_SEARCH_SCREEN = 4       /* every pair screened at once by an MFMA
+  REC_SEARCH_SCREEN = 4,      /* every pair screened at once by an MFMA
                                  contraction of samples with residuals (the
                                  gradient at the current state, Gaussian: BF16,
                                  Ising/kinetic: FP16) under proven bounds on
@@ -75,6 +75,14 @@ typedef enum {
                                  couplings rescored exactly.  Returns the
                                  exhaustive search's positive-gain top m
                                  (kinetic: ordered pairs).                     */
+  REC_SEARCH_GRADIENT = 5     /* FindBest [Alg. 3] over NNDescent [Alg. 4]
+                                 with the gradient as distance [Appendix,
+                                 "Gradient as distance"]: every search score
+                                 is the absolute gradient of rec_grad_pairs,
+                                 and E_best is the best m by that score (each
+                                 update still takes the exact coordinate
+                                 maximum).  The gains written by
+                                 rec_find_best_candidates are those scores. */
 } rec_search;
 
 typedef struct {
@@ -136,6 +144,19 @@ rec_status rec_destroy(rec_ctx* ctx);
 rec_status rec_score_pairs(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
                            double* gain_dev, double* wopt_dev);
 
+/* Gradient distance of P pairs at the current state [Appendix, "Gradient as
+ * distance"]: dist_dev[p] = |dpi/dW_ij| taken as a central difference at the
+ * L1 kink, i.e. |F'(w0) - lambda sign(w0)| for a current coupling w0 != 0 and
+ * |F'(0)| for w0 = 0, with F the objective without the penalty, restricted to
+ * W_ij.  F' is one pass over the samples: for row a's conditional
+ * sum_m x_b,m (y_a,m - tanh h_a,m) (Ising, kinetic) or -sum_m r_a,m x_b,m
+ * (Gaussian), summed over both conditionals for the symmetric models; kinetic
+ * pairs are ordered (i <- j).  i_dev, j_dev: P int32 indices; dist_dev: P
+ * doubles (FP32 mode rounds each to float).  Synchronises the stream;
+ * REC_E_INVAL for an index outside [0,N) or i == j (that entry NaN). */
+rec_status rec_grad_pairs(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
+                          double* dist_dev);
+
 /* The m best pairs at the current state [Alg. 3 when s is a FindBest search].
  * Writes up to m pairs best first (gain desc, then min(i,j), max(i,j);
  * kinetic: gain desc, i, j) into i_dev/j_dev/gain_dev (capacity m each) and
@@ -181,11 +202,12 @@ rec_status rec_set_model(rec_ctx* ctx, int64_t nnz, const int32_t* ei_dev, const
  * (Gaussian: residual x_i + theta_i^2 sum_j W_ij x_j), N x M row-major. */
 rec_status rec_get_fields(rec_ctx* ctx, double* H_dev);
 
-/* KNN lists of FindKNN [Alg. 4] (mode REC_SEARCH_NNDESCENT) or exact KNN
+/* KNN lists of FindKNN [Alg. 4] (mode REC_SEARCH_NNDESCENT; REC_SEARCH_GRADIENT
+ * for NNDescent under the gradient distance of rec_grad_pairs) or exact KNN
  * (REC_SEARCH_EXACT_KNN) over the node subset S (n sorted indices) at
- * FindBest level `level`: writes n*k neighbour indices and gains, best first
+ * FindBest level `level`: writes n*k neighbour indices and scores, best first
  * per node; *iters_host gets the NNDescent iteration count (kinetic model:
- * under the score max(gain(i <- j), gain(j <- i))).  Synchronises. */
+ * under the score max(d(i <- j), d(j <- i))).  Synchronises. */
 rec_status rec_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int32_t k, int32_t level,
                    int32_t mode, int32_t* nbr_dev, double* gain_dev, int32_t* iters_host);
 

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librec.so")
 
 MODELS = {"ising": 0, "gauss": 1, "kinetic": 2}
 PREC = {"fp64": 0, "fp32": 1}
-SEARCH = {"nndescent": 0, "exhaustive": 1, "surrogate": 2, "exact_knn": 3, "screen": 4}
+SEARCH = {"nndescent": 0, "exhaustive": 1, "surrogate": 2, "exact_knn": 3, "screen": 4, "gradient": 5}
 
 # every symbol include/rec.h declares
 SYMBOLS = ["rec_workspace_size", "rec_create", "rec_destroy", "rec_score_pairs", "rec_find_best_candidates",
@@ -26,7 +26,7 @@ SYMBOLS = ["rec_workspace_size", "rec_create", "rec_destroy", "rec_score_pairs",
            "rec_get_model", "rec_set_model", "rec_get_fields", "rec_knn", "rec_set_timing",
            "rec_kernel_time", "rec_status_str", "rec_last_error", "rec_sketch", "rec_mlp_params",
            "rec_mlp_infer", "rec_mlp_grad", "rec_mlp_train", "rec_surrogate_config",
-           "rec_surrogate_stats", "rec_screen_time"]
+           "rec_surrogate_stats", "rec_screen_time", "rec_grad_pairs"]
 SUR_NPARAM = 41345
 SUR_SKETCH_DIM = 64
 SUR_MAX_BATCH = 8192
@@ -76,6 +76,7 @@ def lib():
             "rec_create": [ctypes.POINTER(RecConfig), vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
             "rec_destroy": [vp],
             "rec_score_pairs": [vp, i64, vp, vp, vp, vp],
+            "rec_grad_pairs": [vp, i64, vp, vp, vp],
             "rec_find_best_candidates": [vp, i64, i32, vp, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(SweepStats)],
             "rec_gcd_sweep": [vp, i32, ctypes.POINTER(SweepStats)],
             "rec_apply_updates": [vp, i64, vp, vp, ctypes.POINTER(dbl)],
@@ -202,6 +203,14 @@ class Context:
         self._check(lib().rec_score_pairs(self.h, len(I), _ptr(I), _ptr(J), _ptr(g), _ptr(w)), self.h)
         return g, w
 
+    def grad_pairs(self, I, J):
+        """Gradient distances |dpi/dW_ij| of the pairs (I[p], J[p])."""
+        t = self.torch
+        I, J = self._i32(I), self._i32(J)
+        d = t.empty(len(I), dtype=t.float64, device=self.device)
+        self._check(lib().rec_grad_pairs(self.h, len(I), _ptr(I), _ptr(J), _ptr(d)), self.h)
+        return d
+
     def find_best(self, m: int, search: str = "nndescent"):
         t = self.torch
         I = t.empty(m, dtype=t.int32, device=self.device)
@@ -265,12 +274,18 @@ class Context:
         self._check(lib().rec_get_fields(self.h, _ptr(H)), self.h)
         return H
 
-    def knn(self, S, k: int, level: int = 0, mode: str = "nndescent"):
+    def knn(self, S, k: int, level: int = 0, mode: str = "nndescent", dist: str = "gain"):
+        """KNN lists over S; dist "gradient" (NNDescent only) scores by the
+        gradient distance instead of the exact gain."""
         t = self.torch
         S = self._i32(S)
         nbr = t.empty((len(S), k), dtype=t.int32, device=self.device)
         g = t.empty((len(S), k), dtype=t.float64, device=self.device)
         it = ctypes.c_int32()
+        if dist == "gradient":
+            if mode != "nndescent":
+                raise ValueError("the gradient distance runs with NNDescent")
+            mode = "gradient"
         self._check(lib().rec_knn(self.h, len(S), _ptr(S), k, level, SEARCH[mode], _ptr(nbr), _ptr(g),
                                   ctypes.byref(it)), self.h)
         return nbr, g, it.value

@@ -405,10 +405,26 @@ rec_status rec_score_pairs(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const 
   return REC_OK;
 }
 
+rec_status rec_grad_pairs(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
+                          double* dist_dev) {
+  REC_CHECK_CTX(ctx);
+  if (P < 0 || (P > 0 && (!i_dev || !j_dev || !dist_dev))) return fail(ctx, REC_E_INVAL, "bad arguments");
+  if (P == 0) return REC_OK;
+  REC_TRY(clear_err(ctx));
+  ctx->grad_dist = true;
+  rec_status st = rec_launch_score(ctx, P, i_dev, j_dev, nullptr, dist_dev, nullptr, nullptr);
+  ctx->grad_dist = false;
+  REC_TRY(st);
+  int32_t e = 0;
+  REC_TRY(read_err(ctx, &e));
+  if (e & 1) return fail(ctx, REC_E_INVAL, "pair index out of range or i == j");
+  return REC_OK;
+}
+
 rec_status rec_find_best_candidates(rec_ctx* ctx, int64_t m, int32_t search, int32_t* i_dev, int32_t* j_dev,
                          double* gain_dev, int64_t* n_out_host, rec_sweep_stats* st) {
   REC_CHECK_CTX(ctx);
-  if (m < 1 || !i_dev || !j_dev || !gain_dev || !n_out_host || search < 0 || search > REC_SEARCH_SCREEN)
+  if (m < 1 || !i_dev || !j_dev || !gain_dev || !n_out_host || search < 0 || search > REC_SEARCH_GRADIENT)
     return fail(ctx, REC_E_INVAL, "bad arguments");
   if (m > ctx->best_cap) return fail(ctx, REC_E_INVAL, "m exceeds the capacity planned for kappa");
   REC_TRY(clear_err(ctx));
@@ -453,7 +469,7 @@ rec_status rec_apply_updates(rec_ctx* ctx, int64_t P, const int32_t* i_dev, cons
 
 rec_status rec_gcd_sweep(rec_ctx* ctx, int32_t search, rec_sweep_stats* st) {
   REC_CHECK_CTX(ctx);
-  if (search < 0 || search > REC_SEARCH_SCREEN) return fail(ctx, REC_E_INVAL, "unknown search");
+  if (search < 0 || search > REC_SEARCH_GRADIENT) return fail(ctx, REC_E_INVAL, "unknown search");
   REC_TRY(clear_err(ctx));
   rec_sweep_stats S{};
   double t0 = now_ms();
@@ -552,7 +568,7 @@ rec_status rec_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int32_t k, int
                    int32_t mode, int32_t* nbr_dev, double* gain_dev, int32_t* iters_host) {
   REC_CHECK_CTX(ctx);
   if (n < 2 || n > ctx->cfg.N || k < 1 || k > n - 1 || !S_dev || !nbr_dev || !gain_dev ||
-      (mode != REC_SEARCH_NNDESCENT && mode != REC_SEARCH_EXACT_KNN))
+      (mode != REC_SEARCH_NNDESCENT && mode != REC_SEARCH_EXACT_KNN && mode != REC_SEARCH_GRADIENT))
     return fail(ctx, REC_E_INVAL, "bad arguments");
   REC_TRY(clear_err(ctx));
   hipLaunchKernelGGL(k_check_set, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, S_dev, n,
@@ -561,8 +577,10 @@ rec_status rec_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int32_t k, int
   REC_TRY(read_err(ctx, &e));
   if (e & 1) return fail(ctx, REC_E_INVAL, "S must be strictly increasing node indices in [0, N)");
   int it = 0;
+  ctx->grad_dist = mode == REC_SEARCH_GRADIENT;   // NNDescent under the gradient distance
   rec_status s = rec_search_knn(ctx, n, S_dev, k, level, mode == REC_SEARCH_EXACT_KNN ? 1 : 0,
                                 nbr_dev, gain_dev, &it);
+  ctx->grad_dist = false;
   if (s != REC_OK) return s;
   REC_HIP(hipStreamSynchronize(ctx->stream));
   if (iters_host) *iters_host = it;

@@ -144,6 +144,8 @@ struct rec_ctx {
   // kinetic model inside FindBest: pairs are unordered and scored by the
   // larger of the two directed gains
   bool sym_search = false;
+  // search distance: the exact gain, or (true) the absolute gradient
+  bool grad_dist = false;
   // screening contraction, Gaussian: bf16 operands N x sc_kp, row norms,
   // theta^2, |x|^2; all models: histogram and threshold
   __bf16* sc_a = nullptr;

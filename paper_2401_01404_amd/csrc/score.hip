@@ -522,6 +522,89 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
   }
 }
 
+// ----------------------------------------------------- gradient distance --
+// Gradient as distance [Appendix, "Gradient as distance"]: the search scores a
+// pair by the absolute derivative of the objective in W_ij at the current
+// state, taken as a central difference at the L1 kink: |F'(w0) - lambda
+// sign(w0)| for a current coupling, |F'(0)| for a new pair.  F' is one pass
+// over the samples (no Newton solve): for row a's conditional,
+//   dF_a / dW_ab = sum_m x_b,m (y_a,m - tanh h_a,m)   (Ising, kinetic),
+//   -sum_m r_a,m x_b,m                              (Gaussian, r the residual),
+// summed over both conditionals for the symmetric models; the kinetic search
+// over unordered pairs takes the larger of the two directions (as for the
+// gain).  Same interface as k_score: pairs (I[p], J[p]) (J through Smap when
+// given), results to gain_out[p] or to the cache slot (owner mode: only
+// owned entries are scored).  One wavefront per pair, ppw pairs per wave.
+template <class R, int MODEL>
+__global__ __launch_bounds__(256) void k_grad(Fields F, WTable W, double lambda, int64_t P,
+                                              const int32_t* __restrict__ I,
+                                              const int32_t* __restrict__ J,
+                                              const int32_t* __restrict__ Smap,
+                                              const uint32_t* __restrict__ slot, int owned,
+                                              double* __restrict__ gain_out, double* __restrict__ ovf,
+                                              uint64_t cache_cap, int32_t* err, int ppw, int64_t* work) {
+  const int lane = rec_lane();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE;
+  const int64_t p0 = wave * ppw;
+  if (p0 >= P) return;
+  const int np = (int)(p0 + ppw < P ? ppw : P - p0);
+  const R* T = reinterpret_cast<const R*>(F.T);
+  const R* Hr = reinterpret_cast<const R*>(F.H);
+  const int8_t* Y = MODEL == REC_ISING ? F.xs : F.ys;
+  // derivative of row a's conditional in W_ab
+  auto dir = [&](int64_t a, int64_t b) -> double {
+    double acc = 0.0;
+    for (int64_t m = lane; m < F.M; m += REC_WAVE) {
+      if (MODEL == REC_GAUSS) acc -= (double)Hr[a * F.Mp + m] * (double)F.xf[b * F.Mp + m];
+      else acc += (double)F.xs[b * F.Mp + m] * ((double)Y[a * F.Mp + m] - (double)T[a * F.Mp + m]);
+    }
+    return rec_wave_sum(acc);
+  };
+  auto dist = [&](double f1, double w0) {
+    return fabs(w0 == 0.0 ? f1 : f1 - lambda * (w0 > 0.0 ? 1.0 : -1.0));
+  };
+  uint32_t sw = 0u;
+  if (lane < np && slot) sw = slot[p0 + lane];
+  uint64_t todo = __ballot(lane < np && !(owned && !(sw & OWNER)));
+  int64_t pairs = 0;
+  while (todo) {
+    const int q = __ffsll((unsigned long long)todo) - 1;
+    todo &= todo - 1;
+    const int64_t p = p0 + q;
+    const int i = I[p];
+    int j = J[p];
+    if (Smap) j = Smap[j];
+    const uint64_t o = slot ? (uint64_t)((uint32_t)rec_uni(__shfl((int)sw, q, REC_WAVE)) & ~OWNER) : (uint64_t)p;
+    double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
+    if (!pair_ok(i, j, F.N)) {
+      if (lane == 0) {
+        *dst = __builtin_nan("");
+        atomicOr(err, 1);
+      }
+      continue;
+    }
+    double g;
+    if constexpr (MODEL == REC_KINETIC) {
+      g = dist(dir(i, j), lookup_w(W, i, j, true));
+    } else if constexpr (MODEL == REC_KINSYM) {
+      g = fmax(dist(dir(i, j), lookup_w(W, i, j, true)), dist(dir(j, i), lookup_w(W, j, i, true)));
+    } else {
+      g = dist(dir(i, j) + dir(j, i), lookup_w(W, i, j, false));
+    }
+    if constexpr (sizeof(R) == 4) g = (double)(float)g;   // FP32 scores
+    if (lane == 0) *dst = g;
+    ++pairs;
+  }
+  if (lane == 0 && work && pairs) {
+    Work wk;
+    wk.pairs = pairs;
+    const int64_t M = F.M, rs = sizeof(R);
+    const int64_t per_dir = MODEL == REC_GAUSS ? (rs + 4) * M : (rs + 2) * M;
+    wk.bytes = pairs * (16 + (MODEL == REC_KINETIC ? 1 : 2) * per_dir);
+    wk.flush(work, wave);
+  }
+}
+
 // ------------------------------------------------------------ screened --
 // Ising and the kinetic search score, with the j side read in two steps.
 //
@@ -1054,10 +1137,34 @@ rec_status launch_update_m(rec_ctx* ctx, int64_t m, const int32_t* I, const int3
   return REC_OK;
 }
 
+template <class R, int MODEL>
+rec_status launch_grad_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
+                         const int32_t* Smap, const uint32_t* slot, int owned, double* g,
+                         const Cache* C) {
+  const int ppw = owned ? 64 : 8;
+  const int64_t waves = (P + ppw - 1) / ppw;
+  const int64_t blocks = (waves * REC_WAVE + 255) / 256;
+  hipLaunchKernelGGL((k_grad<R, MODEL>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream, ctx->F, ctx->W,
+                     ctx->cfg.lambda, P, I, J, Smap, slot, owned, g, C ? C->ovf : nullptr,
+                     C ? (C->mask + 1) : (uint64_t)0, ctx->err_flag, ppw, ctx->work);
+  REC_HIP(hipGetLastError());
+  return REC_OK;
+}
+
 template <class R>
 rec_status launch_score_r(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
                           const int32_t* Smap, const uint32_t* slot, int owned, double* g,
                           double* w, const Cache* C) {
+  if (ctx->grad_dist) {   // search under the gradient distance (no w*)
+    switch (ctx->cfg.model) {
+      case REC_ISING: return launch_grad_m<R, REC_ISING>(ctx, P, I, J, Smap, slot, owned, g, C);
+      case REC_GAUSS: return launch_grad_m<R, REC_GAUSS>(ctx, P, I, J, Smap, slot, owned, g, C);
+      case REC_KINETIC:
+        if (ctx->sym_search) return launch_grad_m<R, REC_KINSYM>(ctx, P, I, J, Smap, slot, owned, g, C);
+        return launch_grad_m<R, REC_KINETIC>(ctx, P, I, J, Smap, slot, owned, g, C);
+    }
+    return REC_E_INVAL;
+  }
   switch (ctx->cfg.model) {
     case REC_ISING: return launch_score_m<R, REC_ISING>(ctx, P, I, J, Smap, slot, owned, g, w, C);
     case REC_GAUSS: return launch_score_m<R, REC_GAUSS>(ctx, P, I, J, Smap, slot, owned, g, w, C);

@@ -1467,6 +1467,11 @@ rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,
     r = S.screen(m, n_out);
   } else if (search == REC_SEARCH_SURROGATE) {
     r = surrogate_find_best(ctx, S, m, n_out, level_n);
+  } else if (search == REC_SEARCH_GRADIENT) {
+    // FindBest over NNDescent with every search score the absolute gradient
+    ctx->grad_dist = true;
+    r = S.find_best(m, 0, n_out, level_n, 64);
+    ctx->grad_dist = false;
   } else {
     r = S.find_best(m, search == REC_SEARCH_EXACT_KNN ? 1 : 0, n_out, level_n, 64);
   }
