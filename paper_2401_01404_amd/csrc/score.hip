@@ -528,14 +528,17 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
 // state, taken as a central difference at the L1 kink: |F'(w0) - lambda
 // sign(w0)| for a current coupling, |F'(0)| for a new pair.  F' is one pass
 // over the samples (no Newton solve): for row a's conditional,
-//   dF_a / dW_ab = sum_m x_b,m (y_a,m - tanh h_a,m)   (Ising, kinetic),
-//   -sum_m r_a,m x_b,m                              (Gaussian, r the residual),
+//   dF_a / dW_ab = sum_m x_b,m r_a,m,  r_a = y_a - tanh h_a   (Ising, kinetic),
+//                = -sum_m r_a,m x_b,m,  r_a the residual       (Gaussian),
 // summed over both conditionals for the symmetric models; the kinetic search
 // over unordered pairs takes the larger of the two directions (as for the
 // gain).  Same interface as k_score: pairs (I[p], J[p]) (J through Smap when
 // given), results to gain_out[p] or to the cache slot (owner mode: only
-// owned entries are scored).  One wavefront per pair, ppw pairs per wave.
-template <class R, int MODEL>
+// owned entries are scored).  A wavefront takes ppw pairs in order; lane l
+// holds the samples c*64*VEC + l*VEC + k of the i side (r_i, x_i) in registers
+// and keeps them while consecutive pairs share i, so a pair streams the j
+// side only (x_j; with r_j for the symmetric and two-direction scores).
+template <class R, int NPL, int MODEL>
 __global__ __launch_bounds__(256) void k_grad(Fields F, WTable W, double lambda, int64_t P,
                                               const int32_t* __restrict__ I,
                                               const int32_t* __restrict__ J,
@@ -543,6 +546,8 @@ __global__ __launch_bounds__(256) void k_grad(Fields F, WTable W, double lambda,
                                               const uint32_t* __restrict__ slot, int owned,
                                               double* __restrict__ gain_out, double* __restrict__ ovf,
                                               uint64_t cache_cap, int32_t* err, int ppw, int64_t* work) {
+  constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  constexpr bool GAUSS = MODEL == REC_GAUSS, TWO = MODEL != REC_KINETIC;   // TWO: j side's residual too
   const int lane = rec_lane();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE;
   const int64_t p0 = wave * ppw;
@@ -551,13 +556,33 @@ __global__ __launch_bounds__(256) void k_grad(Fields F, WTable W, double lambda,
   const R* T = reinterpret_cast<const R*>(F.T);
   const R* Hr = reinterpret_cast<const R*>(F.H);
   const int8_t* Y = MODEL == REC_ISING ? F.xs : F.ys;
-  // derivative of row a's conditional in W_ab
-  auto dir = [&](int64_t a, int64_t b) -> double {
-    double acc = 0.0;
-    for (int64_t m = lane; m < F.M; m += REC_WAVE) {
-      if (MODEL == REC_GAUSS) acc -= (double)Hr[a * F.Mp + m] * (double)F.xf[b * F.Mp + m];
-      else acc += (double)F.xs[b * F.Mp + m] * ((double)Y[a * F.Mp + m] - (double)T[a * F.Mp + m]);
+  // row b's residual and inputs at this lane's samples (Gaussian: r = the
+  // stored residual with the sign of -F'; x = the float samples)
+  auto load_row = [&](int64_t b, double* r, float* x) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int64_t o = b * F.Mp + smp<VEC>(c, lane);
+      if constexpr (GAUSS) {
+        R h[VEC];
+        ld_vec<VEC>(Hr + o, h);
+        ld_vec<VEC>(F.xf + o, x + c * VEC);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) r[c * VEC + k] = -(double)h[k];
+      } else {
+        R t[VEC];
+        float y[VEC];
+        ld_vec<VEC>(T + o, t);
+        ld_x<VEC>(Y + o, y);
+        ld_x<VEC>(F.xs + o, x + c * VEC);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) r[c * VEC + k] = (double)y[k] - (double)t[k];
+      }
     }
+  };
+  auto dot = [&](const double* r, const float* x) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < NPL; ++q) acc += (double)x[q] * r[q];
     return rec_wave_sum(acc);
   };
   auto dist = [&](double f1, double w0) {
@@ -566,7 +591,10 @@ __global__ __launch_bounds__(256) void k_grad(Fields F, WTable W, double lambda,
   uint32_t sw = 0u;
   if (lane < np && slot) sw = slot[p0 + lane];
   uint64_t todo = __ballot(lane < np && !(owned && !(sw & OWNER)));
-  int64_t pairs = 0;
+  int64_t pairs = 0, iloads = 0;
+  double ri[NPL];
+  float xi[NPL];
+  int cur = -1;
   while (todo) {
     const int q = __ffsll((unsigned long long)todo) - 1;
     todo &= todo - 1;
@@ -583,13 +611,27 @@ __global__ __launch_bounds__(256) void k_grad(Fields F, WTable W, double lambda,
       }
       continue;
     }
+    if (i != cur) {
+      load_row(i, ri, xi);
+      cur = i;
+      ++iloads;
+    }
+    double rj[TWO ? NPL : 1];
+    float xj[NPL];
+    if constexpr (TWO) {
+      load_row(j, rj, xj);
+    } else {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) ld_x<VEC>(F.xs + (int64_t)j * F.Mp + smp<VEC>(c, lane), xj + c * VEC);
+    }
+    const double dij = dot(ri, xj);   // row i's conditional in W_ij
     double g;
     if constexpr (MODEL == REC_KINETIC) {
-      g = dist(dir(i, j), lookup_w(W, i, j, true));
+      g = dist(dij, lookup_w(W, i, j, true));
     } else if constexpr (MODEL == REC_KINSYM) {
-      g = fmax(dist(dir(i, j), lookup_w(W, i, j, true)), dist(dir(j, i), lookup_w(W, j, i, true)));
+      g = fmax(dist(dij, lookup_w(W, i, j, true)), dist(dot(rj, xi), lookup_w(W, j, i, true)));
     } else {
-      g = dist(dir(i, j) + dir(j, i), lookup_w(W, i, j, false));
+      g = dist(dij + dot(rj, xi), lookup_w(W, i, j, false));
     }
     if constexpr (sizeof(R) == 4) g = (double)(float)g;   // FP32 scores
     if (lane == 0) *dst = g;
@@ -598,9 +640,10 @@ __global__ __launch_bounds__(256) void k_grad(Fields F, WTable W, double lambda,
   if (lane == 0 && work && pairs) {
     Work wk;
     wk.pairs = pairs;
+    wk.iloads = iloads;
     const int64_t M = F.M, rs = sizeof(R);
-    const int64_t per_dir = MODEL == REC_GAUSS ? (rs + 4) * M : (rs + 2) * M;
-    wk.bytes = pairs * (16 + (MODEL == REC_KINETIC ? 1 : 2) * per_dir);
+    const int64_t row = GAUSS ? (rs + 4) * M : (rs + 2) * M;   // a whole row (r and x)
+    wk.bytes = pairs * (16 + (TWO ? row : M)) + iloads * row;
     wk.flush(work, wave);
   }
 }
@@ -1144,9 +1187,20 @@ rec_status launch_grad_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_
   const int ppw = owned ? 64 : 8;
   const int64_t waves = (P + ppw - 1) / ppw;
   const int64_t blocks = (waves * REC_WAVE + 255) / 256;
-  hipLaunchKernelGGL((k_grad<R, MODEL>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream, ctx->F, ctx->W,
-                     ctx->cfg.lambda, P, I, J, Smap, slot, owned, g, C ? C->ovf : nullptr,
-                     C ? (C->mask + 1) : (uint64_t)0, ctx->err_flag, ppw, ctx->work);
+#define REC_GR(NPL)                                                                                    \
+  hipLaunchKernelGGL((k_grad<R, NPL, MODEL>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream, ctx->F, \
+                     ctx->W, ctx->cfg.lambda, P, I, J, Smap, slot, owned, g, C ? C->ovf : nullptr,      \
+                     C ? (C->mask + 1) : (uint64_t)0, ctx->err_flag, ppw, ctx->work)
+  switch (ctx->F.npl) {
+    case 1: REC_GR(1); break;
+    case 2: REC_GR(2); break;
+    case 4: REC_GR(4); break;
+    case 8: REC_GR(8); break;
+    case 16: REC_GR(16); break;
+    case 32: REC_GR(32); break;
+    default: ctx->err = "unsupported sample count"; return REC_E_INVAL;
+  }
+#undef REC_GR
   REC_HIP(hipGetLastError());
   return REC_OK;
 }
