@@ -557,6 +557,15 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   uint32_t done[KS_WM * 4 * KS_WN / 32];
 #pragma unroll
   for (int d = 0; d < KS_WM * 4 * KS_WN / 32; ++d) done[d] = 0u;
+  // extremes of the column terms over this lane's columns (row pre-test)
+  float cl1min = cl1[0], cl1max = cl1[0], cumin = cu[0], chmin = ch[0];
+#pragma unroll
+  for (int q = 1; q < KS_WN; ++q) {
+    cl1min = fminf(cl1min, cl1[q]);
+    cl1max = fmaxf(cl1max, cl1[q]);
+    cumin = fminf(cumin, cu[q]);
+    chmin = fminf(chmin, ch[q]);
+  }
   for (;;) {
     // One gate per element: |a| must reach lambda - er + the collect
     // threshold or lambda + er + the histogram threshold (kinetic: one value
@@ -572,6 +581,24 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         const float er_row = rv.x, rcv = rv.y, ru = rv.z, rh = rv.w;
         const float big = __builtin_inff();
         const float gate_row = fminf(COLLECT ? P.lam - er_row + ru : big, HIST ? P.lam + er_row + rh : big);
+        // Row pre-test: the largest |a| of the lane's entries in this row
+        // against a lower bound of their gates (kinetic: the row gate; Ising:
+        // the gate with the column terms at their extremes over the lane's
+        // columns; sampling: lambda + the smallest error bound), less a float
+        // slack.  A row that no lane passes is skipped by the whole wave, so
+        // the per-element tests run only on the few rows holding candidates.
+        {
+          float mx = fabsf(acc[m][0][r]);
+#pragma unroll
+          for (int q = 1; q < KS_WN; ++q) mx = fmaxf(mx, fabsf(acc[m][q][r]));
+          float qg;
+          if (MODE == 0 && !ROBUST) qg = P.lam + er_row + cl1min;
+          else if (KIN) qg = gate_row;
+          else qg = fminf(COLLECT ? P.lam - er_row - cl1max + fmaxf(ru, cumin) : big,
+                          HIST ? P.lam + er_row + cl1min + fmaxf(rh, chmin) : big);
+          qg -= fabsf(qg) * 1e-5f + 1e-30f;
+          if (__ballot(mx >= qg) == 0) continue;
+        }
 #pragma unroll
         for (int q = 0; q < KS_WN; ++q) {
           const int bit = (m * 4 + r) * KS_WN + q;
