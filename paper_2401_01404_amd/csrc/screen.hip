@@ -375,18 +375,14 @@ constexpr int KS_WR = 2, KS_WC = 4;
 constexpr int KS_WM = 8, KS_WN = 4;
 constexpr int KS_BM = KS_WR * KS_WM * 16, KS_BN = KS_WC * KS_WN * 16;
 constexpr int KS_Q = 2 * KS_THREADS;   // per-block queue of elements that passed the cheap tests (LDS)
+constexpr int KS_OB = KS_Q;            // per-block batch of collected pairs (LDS); >= one tile's worth
 static_assert(KS_WR * KS_WC * REC_WAVE == KS_THREADS, "one wavefront per sub-tile");
 static_assert(KS_BM <= REC_TAIL_ROWS && KS_BN <= REC_TAIL_ROWS, "tiles must stay inside the zero tail");
 static_assert(KS_BM <= 256 && KS_BN <= 256, "queue keys hold 8-bit rows and columns");
 static_assert(KS_BM % (KS_THREADS / 8) == 0 && KS_BN % (KS_THREADS / 8) == 0, "staging rows per thread");
 
 template <int MODE, int KIN, int ROBUST>
-__global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_kscreen(KScreenArgs P, TileMap TM, int row_step) {
-  int bi, bj;
-  if (!ks_tile(TM, blockIdx.x, &bi, &bj)) return;
-  bi *= row_step;
-  const int64_t r0 = (int64_t)bi * KS_BM, c0 = (int64_t)bj * KS_BN;
-  if (!KIN && r0 >= c0 + KS_BN - 1) return;   // no pair i < j in the tile
+__global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_kscreen(KScreenArgs P, TileMap TM, int row_step, int* tctr, int nvirt) {
   constexpr bool HIST = MODE != 1, COLLECT = MODE != 0;
   __shared__ __attribute__((aligned(16))) _Float16 As[2][KS_BM * KS_K];
   __shared__ __attribute__((aligned(16))) _Float16 Bs[2][KS_BN * KS_K];
@@ -395,10 +391,58 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   __shared__ float kq_e[KS_Q], kq_c[KS_Q];
   __shared__ int kq_n, kc_n;
   __shared__ int64_t kbase;
+  __shared__ int s_q;
+  // collected pairs of this block's tiles, written out in batches (one global
+  // atomic per batch instead of per tile)
+  __shared__ int32_t ob_i[COLLECT ? KS_OB : 1], ob_j[COLLECT ? KS_OB : 1];
+  __shared__ float ob_g[COLLECT ? KS_OB : 1];
+  __shared__ int ob_n;
   const int tid = threadIdx.x, lane = tid & (REC_WAVE - 1), w = tid / REC_WAVE;
   if (HIST)
     for (int q = tid; q < KS_BINS; q += KS_THREADS) hs[q] = 0;
-  if (tid == 0) { kq_n = 0; kc_n = 0; }
+  // Persistent blocks (one per CU): block b takes the virtual block indices
+  // of its XCD (b & 7) from that XCD's counter, i.e. the tiles the hardware
+  // would have dealt to that XCD, so its L2 keeps serving its super-tiles;
+  // the block's histogram is flushed once at the end.
+  const int xcd = blockIdx.x & 7;
+  if (tid == 0) {
+    s_q = atomicAdd(&tctr[xcd], 1);
+    ob_n = 0;
+  }
+  __syncthreads();
+  // write the batch out (all threads; uniform)
+  auto flush = [&]() {
+    const int nb = ob_n;
+    if (tid == 0) kbase = (int64_t)atomicAdd((unsigned long long*)P.cursor, (unsigned long long)nb);
+    __syncthreads();
+    for (int t = tid; t < nb; t += KS_THREADS) {
+      const int64_t pos = kbase + t;
+      if (pos < P.cap) {
+        P.oi[pos] = ob_i[t];
+        P.oj[pos] = ob_j[t];
+        P.og[pos] = ob_g[t];
+      }
+    }
+    __syncthreads();
+    if (tid == 0) ob_n = 0;
+    __syncthreads();
+  };
+  int tq = s_q;
+  for (;;) {
+  const int vb = tq * 8 + xcd;
+  if (vb >= nvirt) break;
+  __syncthreads();   // every thread has read s_q and is done with the last tile's LDS
+  if (tid == 0) {
+    s_q = atomicAdd(&tctr[xcd], 1);
+    kq_n = 0;
+    kc_n = 0;
+  }
+  int bi, bj;
+  bool ok = ks_tile(TM, vb, &bi, &bj);
+  bi *= row_step;
+  const int64_t r0 = (int64_t)bi * KS_BM, c0 = (int64_t)bj * KS_BN;
+  if (!KIN && r0 >= c0 + KS_BN - 1) ok = false;   // no pair i < j in the tile
+  if (ok) {
   // Staging: thread tid moves the 8-sample chunk (tid & 7) of rows tid/8 +
   // (KS_THREADS/8) u of both operands.  Operand rows are fp16 (x copy and
   // residuals) with zero rows past N, so no load needs a bound check.  Ising:
@@ -508,6 +552,11 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   // if e >= sqrt(4 tau^2 + 2 tau c) - 2 tau;  (c/4) phi(q) <= e^2 / (2c), so
   // a lower bound can reach the floor f only if e >= sqrt(2 f c).  Both grow
   // with c, and c >= c_i + min c (Ising) or c = c_i (kinetic).
+  // The epilogue's lane-derived indices are formed from an opaque copy of the
+  // lane id, per tile: otherwise the compiler hoists them out of the tile
+  // loop, and they stay live across the k loop and spill.
+  int elane = lane;
+  asm volatile("" : "+v"(elane));
   const float tau = COLLECT ? *P.tau : 0.f;
   const float fl = HIST && P.hfloor ? *P.hfloor : 0.f;
   const float cmin = KIN ? 0.f : *P.cvmin;
@@ -541,7 +590,7 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   float cl1[KS_WN], ccv[KS_WN], cu[KS_WN], ch[KS_WN];
 #pragma unroll
   for (int q = 0; q < KS_WN; ++q) {
-    const float4 v = colv[wc + q * 16 + (lane & 15)];
+    const float4 v = colv[wc + q * 16 + (elane & 15)];
     cl1[q] = v.x;
     ccv[q] = v.y;
     cu[q] = v.z;
@@ -575,7 +624,7 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     for (int m = 0; m < KS_WM; ++m)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int li = wr + m * 16 + 4 * (lane >> 4) + r;
+        const int li = wr + m * 16 + 4 * (elane >> 4) + r;
         const int64_t i = r0 + li;
         const float4 rv = rowv[li];
         const float er_row = rv.x, rcv = rv.y, ru = rv.z, rh = rv.w;
@@ -609,7 +658,7 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             const float er = er_row + cl1[q];
             const float e = aa - er - P.lam;
             if (e > 0.f) {
-              const int lj = wc + q * 16 + (lane & 15);
+              const int lj = wc + q * 16 + (elane & 15);
               const int64_t j = c0 + lj;
               const bool ok = KIN ? (i < P.N && j < P.N && i != j) : (i < j && j < P.N);
               const int hb = ks_bin(e * e / (2.f * (rcv + ccv[q])));
@@ -624,7 +673,7 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                          HIST ? P.lam + er + fmaxf(rh, ch[q]) : big);
           }
           if (aa >= gate && !((done[bit >> 5] >> (bit & 31)) & 1u)) {
-            const int lj = wc + q * 16 + (lane & 15);
+            const int lj = wc + q * 16 + (elane & 15);
             const int64_t j = c0 + lj;
             const bool ok = KIN ? (i < P.N && j < P.N && i != j) : (i < j && j < P.N);
             const float er = er_row + cl1[q];
@@ -674,12 +723,9 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
       }
       if (COLLECT && ((key[u] >> 30) & 1u)) {
         const float gu = kgain_up(av[u] + er - P.lam, cv2[u]);
-        bool keep = gu >= tau;
-        if (keep && P.W.keys != nullptr) {
-          // a current (nonzero) coupling is handled with the W list instead
-          const int64_t ws = rec_hash_find(P.W.keys, P.W.mask, rec_pair_key(i, j, KIN != 0), REC_MAX_PROBE);
-          if (ws >= 0 && P.W.vals[ws] != 0.0) keep = false;
-        }
+        // (a current coupling collected here is dropped by the filter pass,
+        // which looks the pairs up in W off this kernel's critical path)
+        const bool keep = gu >= tau;
         if (keep) {
           const int pc = atomicAdd(&kc_n, 1);   // pc < KS_Q: at most one per queued element
           kq_key[pc] = (uint32_t)li << 8 | (uint32_t)lj;
@@ -690,22 +736,26 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     if (COLLECT) {
       __syncthreads();
       const int nc = kc_n;
-      if (tid == 0 && nc > 0) kbase = (int64_t)atomicAdd((unsigned long long*)P.cursor, (unsigned long long)nc);
-      __syncthreads();
+      if (ob_n + nc > KS_OB) flush();
+      const int base = ob_n;
       for (int t = tid; t < nc; t += KS_THREADS) {
-        const int64_t pos = kbase + t;
-        if (pos < P.cap) {
-          P.oi[pos] = (int32_t)(r0 + ((kq_key[t] >> 8) & 255));
-          P.oj[pos] = (int32_t)(c0 + (kq_key[t] & 255));
-          P.og[pos] = kq_e[t];
-        }
+        ob_i[base + t] = (int32_t)(r0 + ((kq_key[t] >> 8) & 255));
+        ob_j[base + t] = (int32_t)(c0 + (kq_key[t] & 255));
+        ob_g[base + t] = kq_e[t];
       }
+      __syncthreads();
+      if (tid == 0) ob_n = base + nc;
     }
     __syncthreads();
     if (!ROBUST || !more) break;
     if (tid == 0) { kq_n = 0; kc_n = 0; }
     __syncthreads();
   }
+  }   // tile
+  __syncthreads();
+  tq = s_q;
+  }   // tiles of this block
+  if (COLLECT && ob_n > 0) flush();
   if (HIST)
     for (int q = tid; q < KS_BINS; q += KS_THREADS)
       if (hs[q]) atomicAdd(&P.hist[q], hs[q]);
@@ -798,15 +848,21 @@ __global__ __launch_bounds__(256) void k_ks_couple(KScreenArgs P, const int32_t*
 }
 
 // Keep the collected pairs whose upper bound reaches *tau (the proven
-// threshold, at least the one they were collected at), compacted from the
-// front; the count goes to *cursor.
+// threshold, at least the one they were collected at) and that are not
+// current couplings, compacted from the front; the count goes to *cursor.
 __global__ __launch_bounds__(256) void k_ks_filter(const int32_t* __restrict__ I, const int32_t* __restrict__ J,
                                                    const float* __restrict__ g, int64_t n, const float* tau,
+                                                   WTable W, int directed,
                                                    int32_t* __restrict__ oI, int32_t* __restrict__ oJ,
                                                    int64_t* cursor) {
   __shared__ long long sh[256 / REC_WAVE + 1];
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool keep = e < n && g[e] >= *tau;
+  bool keep = e < n && g[e] >= *tau;
+  if (keep && W.keys != nullptr) {
+    // a current (nonzero) coupling is screened with the W list instead
+    const int64_t ws = rec_hash_find(W.keys, W.mask, rec_pair_key(I[e], J[e], directed != 0), REC_MAX_PROBE);
+    if (ws >= 0 && W.vals[ws] != 0.0) keep = false;
+  }
   const int64_t p = rec_block_append<256 / REC_WAVE>(cursor, keep, sh);
   if (p >= 0) {
     oI[p] = I[e];
@@ -892,6 +948,13 @@ template <int MODE, int ROBUST>
 rec_status launch_ks(rec_ctx* ctx, const KScreenArgs& P, int nbi, int nbj, int row_step) {
   int64_t grid = 0;
   const TileMap T = tile_map(nbi, nbj, &grid);
+  // persistent grid: one block per CU (a multiple of 8, one share per XCD)
+  int dev = 0, ncu = 0;
+  REC_HIP(hipGetDevice(&dev));
+  REC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t pgrid = std::min<int64_t>(grid, std::max(8, ncu / 8 * 8));
+  int* tctr = reinterpret_cast<int*>(ctx->sc_tau + 16);
+  REC_HIP(hipMemsetAsync(tctr, 0, 8 * sizeof(int), ctx->stream));
   // algorithmic work of a full pass: one M-term dot product (2 flops a term)
   // per ordered pair (kinetic) or two per unordered pair (Ising)
   const double N = (double)ctx->cfg.N;
@@ -899,11 +962,11 @@ rec_status launch_ks(rec_ctx* ctx, const KScreenArgs& P, int nbi, int nbj, int r
   rec_status st = ev_begin(ctx);
   if (st != REC_OK) return st;
   if (ctx->cfg.model == REC_KINETIC)
-    hipLaunchKernelGGL((k_kscreen<MODE, 1, ROBUST>), dim3((unsigned)grid), dim3(KS_THREADS), 0, ctx->stream, P, T,
-                       row_step);
+    hipLaunchKernelGGL((k_kscreen<MODE, 1, ROBUST>), dim3((unsigned)pgrid), dim3(KS_THREADS), 0, ctx->stream, P, T,
+                       row_step, tctr, (int)grid);
   else
-    hipLaunchKernelGGL((k_kscreen<MODE, 0, ROBUST>), dim3((unsigned)grid), dim3(KS_THREADS), 0, ctx->stream, P, T,
-                       row_step);
+    hipLaunchKernelGGL((k_kscreen<MODE, 0, ROBUST>), dim3((unsigned)pgrid), dim3(KS_THREADS), 0, ctx->stream, P, T,
+                       row_step, tctr, (int)grid);
   return ev_end(ctx, row_step == 1 ? 0 : 1, row_step == 1 ? flops : 0.0);
 }
 
@@ -1017,7 +1080,7 @@ rec_status kscreen_candidates(rec_ctx* ctx, int64_t m, int64_t nnz, int64_t* n_o
   if (n > 0) {
     REC_HIP(hipMemsetAsync(P.cursor, 0, sizeof(int64_t), s));
     hipLaunchKernelGGL(k_ks_filter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ctx->ts_i, ctx->ts_j,
-                       P.og, n, tau_f, ctx->cand_gi, ctx->cand_v, P.cursor);
+                       P.og, n, tau_f, ctx->W, kin, ctx->cand_gi, ctx->cand_v, P.cursor);
     REC_HIP(hipMemcpyAsync(&n, P.cursor, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     REC_HIP(hipStreamSynchronize(s));
     REC_HIP(hipMemcpyAsync(ctx->ts_i, ctx->cand_gi, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
