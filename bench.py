@@ -45,6 +45,8 @@ WORKLOADS = {
     "C2": "Ising pseudolikelihood, N=10000, M=1000 +-1 Gibbs samples, random 3-regular graph, "
           "w~U[-0.4,0.4], kappa=4 (m=40000), FP32 scores with FP64 sums",
     "C1": "Ising pseudolikelihood, N=100, M=500 +-1 Gibbs samples, ER mean degree 3, kappa=4",
+    "C5": "Ising pseudolikelihood, N=1000000, M=100 +-1 Gibbs samples, ER mean degree 3, "
+          "w~N(0,0.3^2), kappa=4 (m=4000000), FP32 scores with FP64 sums",
 }
 
 # Algorithmic FP32 work of the pair-score kernel, counted per executed pass

@@ -568,8 +568,12 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   // operand buffers are free after the k loop): row (er_i, c_i, up_i, lo_i)
   // with er_i = ce |r_i|_1 + el and up/lo the gate thresholds at c_i + min c;
   // column (ce |r_j|_1, c_j, up_j, lo_j) (Ising; zeros for kinetic).
+  // Kinetic: also each row's pre-test threshold (its gate, or lambda + er_i
+  // for the sampling estimate, less a float slack), so that a wave reads four
+  // rows' thresholds with one load.
   float4* rowv = reinterpret_cast<float4*>(&As[0][0]);
   float4* colv = rowv + KS_BM;
+  float* qrow = reinterpret_cast<float*>(colv + KS_BN);
   for (int t = tid; t < KS_BM + KS_BN; t += KS_THREADS) {
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
     if (t < KS_BM) {
@@ -577,6 +581,14 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
       const float l1 = i < P.N ? P.l1[i] : 0.f, c = i < P.N ? P.cv[i] : 0.f;
       v = make_float4(P.ce * l1 + P.el, c, thr_up(c + cmin), thr_lo(c + cmin));
       rowv[t] = v;
+      if (KIN) {
+        const float big = __builtin_inff();
+        float qg = (MODE == 0 && !ROBUST)
+                       ? P.lam + v.x
+                       : fminf(COLLECT ? P.lam - v.x + v.z : big, HIST ? P.lam + v.x + v.w : big);
+        qg -= fabsf(qg) * 1e-5f + 1e-30f;
+        qrow[t] = qg;
+      }
     } else if (!KIN) {
       const int64_t j = c0 + (t - KS_BM);
       const float l1 = j < P.N ? P.l1[j] : 0.f, c = j < P.N ? P.cv[j] : 0.f;
@@ -621,28 +633,37 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     // per row).  Range and triangle checks run only behind the gate (padding
     // rows and columns hold a = 0).
 #pragma unroll
-    for (int m = 0; m < KS_WM; ++m)
+    for (int m = 0; m < KS_WM; ++m) {
+      float4 q4 = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (KIN) q4 = *reinterpret_cast<const float4*>(&qrow[wr + m * 16 + 4 * (elane >> 4)]);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int li = wr + m * 16 + 4 * (elane >> 4) + r;
         const int64_t i = r0 + li;
+        if (KIN) {   // row pre-test from the stored threshold (see below)
+          float mx = fabsf(acc[m][0][r]);
+#pragma unroll
+          for (int q = 1; q < KS_WN; ++q) mx = fmaxf(mx, fabsf(acc[m][q][r]));
+          const float qg = r == 0 ? q4.x : r == 1 ? q4.y : r == 2 ? q4.z : q4.w;
+          if (__ballot(mx >= qg) == 0) continue;
+        }
         const float4 rv = rowv[li];
         const float er_row = rv.x, rcv = rv.y, ru = rv.z, rh = rv.w;
         const float big = __builtin_inff();
         const float gate_row = fminf(COLLECT ? P.lam - er_row + ru : big, HIST ? P.lam + er_row + rh : big);
         // Row pre-test: the largest |a| of the lane's entries in this row
-        // against a lower bound of their gates (kinetic: the row gate; Ising:
-        // the gate with the column terms at their extremes over the lane's
-        // columns; sampling: lambda + the smallest error bound), less a float
-        // slack.  A row that no lane passes is skipped by the whole wave, so
-        // the per-element tests run only on the few rows holding candidates.
-        {
+        // against a lower bound of their gates (kinetic: the row gate, stored
+        // per row above; Ising: the gate with the column terms at their
+        // extremes over the lane's columns; sampling: lambda + the smallest
+        // error bound), less a float slack.  A row that no lane passes is
+        // skipped by the whole wave, so the per-element tests run only on the
+        // few rows holding candidates.
+        if (!KIN) {
           float mx = fabsf(acc[m][0][r]);
 #pragma unroll
           for (int q = 1; q < KS_WN; ++q) mx = fmaxf(mx, fabsf(acc[m][q][r]));
           float qg;
           if (MODE == 0 && !ROBUST) qg = P.lam + er_row + cl1min;
-          else if (KIN) qg = gate_row;
           else qg = fminf(COLLECT ? P.lam - er_row - cl1max + fmaxf(ru, cumin) : big,
                           HIST ? P.lam + er_row + cl1min + fmaxf(rh, chmin) : big);
           qg -= fabsf(qg) * 1e-5f + 1e-30f;
@@ -695,6 +716,7 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
           }
         }
       }
+    }
     __syncthreads();
     if (MODE == 0 && !ROBUST) break;
     const int nq = min(kq_n, KS_Q);
