@@ -598,7 +598,45 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
       colv[t - KS_BM] = v;
     }
   }
+  // Ising: the column threads (whole wavefronts) reduce the tile's column
+  // terms to their extremes, from which each row's pre-test threshold is
+  // formed: the gate with every column term at its least favourable value.
+  float4* cext = reinterpret_cast<float4*>(qrow + KS_BM);   // one entry per column wavefront
+  static_assert(KS_BM % REC_WAVE == 0 && KS_THREADS - KS_BM <= 4 * REC_WAVE, "column wavefronts");
+  if (!KIN && tid >= KS_BM) {
+    const float4 v = colv[tid - KS_BM];
+    float amax = v.x, amin = v.x, umin = v.z, hmin = v.w;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      amax = fmaxf(amax, __shfl_xor(amax, o, REC_WAVE));
+      amin = fminf(amin, __shfl_xor(amin, o, REC_WAVE));
+      umin = fminf(umin, __shfl_xor(umin, o, REC_WAVE));
+      hmin = fminf(hmin, __shfl_xor(hmin, o, REC_WAVE));
+    }
+    if (lane == 0) cext[(tid - KS_BM) / REC_WAVE] = make_float4(amax, amin, umin, hmin);
+  }
   __syncthreads();
+  if (!KIN) {
+    if (tid < KS_BM) {
+      float amax = cext[0].x, amin = cext[0].y, umin = cext[0].z, hmin = cext[0].w;
+#pragma unroll
+      for (int c = 1; c < (KS_THREADS - KS_BM) / REC_WAVE; ++c) {
+        amax = fmaxf(amax, cext[c].x);
+        amin = fminf(amin, cext[c].y);
+        umin = fminf(umin, cext[c].z);
+        hmin = fminf(hmin, cext[c].w);
+      }
+      const float4 v = rowv[tid];
+      const float big = __builtin_inff();
+      float qg = (MODE == 0 && !ROBUST)
+                     ? P.lam + v.x + amin
+                     : fminf(COLLECT ? P.lam - v.x - amax + fmaxf(v.z, umin) : big,
+                             HIST ? P.lam + v.x + amin + fmaxf(v.w, hmin) : big);
+      qg -= fabsf(qg) * 1e-5f + 1e-30f;
+      qrow[tid] = qg;
+    }
+    __syncthreads();
+  }
   float cl1[KS_WN], ccv[KS_WN], cu[KS_WN], ch[KS_WN];
 #pragma unroll
   for (int q = 0; q < KS_WN; ++q) {
@@ -618,15 +656,6 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   uint32_t done[KS_WM * 4 * KS_WN / 32];
 #pragma unroll
   for (int d = 0; d < KS_WM * 4 * KS_WN / 32; ++d) done[d] = 0u;
-  // extremes of the column terms over this lane's columns (row pre-test)
-  float cl1min = cl1[0], cl1max = cl1[0], cumin = cu[0], chmin = ch[0];
-#pragma unroll
-  for (int q = 1; q < KS_WN; ++q) {
-    cl1min = fminf(cl1min, cl1[q]);
-    cl1max = fmaxf(cl1max, cl1[q]);
-    cumin = fminf(cumin, cu[q]);
-    chmin = fminf(chmin, ch[q]);
-  }
   for (;;) {
     // One gate per element: |a| must reach lambda - er + the collect
     // threshold or lambda + er + the histogram threshold (kinetic: one value
@@ -634,13 +663,12 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     // rows and columns hold a = 0).
 #pragma unroll
     for (int m = 0; m < KS_WM; ++m) {
-      float4 q4 = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (KIN) q4 = *reinterpret_cast<const float4*>(&qrow[wr + m * 16 + 4 * (elane >> 4)]);
+      const float4 q4 = *reinterpret_cast<const float4*>(&qrow[wr + m * 16 + 4 * (elane >> 4)]);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int li = wr + m * 16 + 4 * (elane >> 4) + r;
         const int64_t i = r0 + li;
-        if (KIN) {   // row pre-test from the stored threshold (see below)
+        {   // row pre-test from the stored threshold (see below)
           float mx = fabsf(acc[m][0][r]);
 #pragma unroll
           for (int q = 1; q < KS_WN; ++q) mx = fmaxf(mx, fabsf(acc[m][q][r]));
@@ -651,24 +679,12 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         const float er_row = rv.x, rcv = rv.y, ru = rv.z, rh = rv.w;
         const float big = __builtin_inff();
         const float gate_row = fminf(COLLECT ? P.lam - er_row + ru : big, HIST ? P.lam + er_row + rh : big);
-        // Row pre-test: the largest |a| of the lane's entries in this row
-        // against a lower bound of their gates (kinetic: the row gate, stored
-        // per row above; Ising: the gate with the column terms at their
-        // extremes over the lane's columns; sampling: lambda + the smallest
-        // error bound), less a float slack.  A row that no lane passes is
-        // skipped by the whole wave, so the per-element tests run only on the
-        // few rows holding candidates.
-        if (!KIN) {
-          float mx = fabsf(acc[m][0][r]);
-#pragma unroll
-          for (int q = 1; q < KS_WN; ++q) mx = fmaxf(mx, fabsf(acc[m][q][r]));
-          float qg;
-          if (MODE == 0 && !ROBUST) qg = P.lam + er_row + cl1min;
-          else qg = fminf(COLLECT ? P.lam - er_row - cl1max + fmaxf(ru, cumin) : big,
-                          HIST ? P.lam + er_row + cl1min + fmaxf(rh, chmin) : big);
-          qg -= fabsf(qg) * 1e-5f + 1e-30f;
-          if (__ballot(mx >= qg) == 0) continue;
-        }
+        // (Row pre-test above: the largest |a| of the lane's entries in this
+        // row against a lower bound of their gates, stored per row: kinetic,
+        // the row gate; Ising, the gate with the column terms at their extremes
+        // over the tile; sampling, lambda + the smallest error bound; less a
+        // float slack.  A row that no lane passes is skipped by the whole
+        // wave, so the per-element tests run only on rows holding candidates.)
 #pragma unroll
         for (int q = 0; q < KS_WN; ++q) {
           const int bit = (m * 4 + r) * KS_WN + q;
