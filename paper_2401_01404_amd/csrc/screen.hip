@@ -753,8 +753,9 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
       const int t = u * KS_THREADS + tid;
       if (t >= nq) continue;
       const int li = (int)((key[u] >> 8) & 255), lj = (int)(key[u] & 255);
-      const int i = (int)r0 + li, j = (int)c0 + lj;
-      const float er = P.ce * (P.l1[i] + (KIN ? 0.f : P.l1[j])) + P.el;
+      // the error bound from the tile's row and column terms in LDS (the sum
+      // the gates used), not from global memory
+      const float er = rowv[li].x + colv[lj].x;
       if (HIST && (key[u] >> 31)) {
         const int hb = ks_bin(kgain_lo(av[u] - er - P.lam, cv2[u]));
         if (hb >= 0) atomicAdd(&hs[hb], 1u);
