@@ -145,6 +145,61 @@ def compare_searches(ctx, torch):
     return out
 
 
+def scaling_study(sizes, prec, kappas=(1.0, 4.0), reps=3):
+    """FindBest [Alg. 3] over NNDescent on the paper's runtime-study problems
+    (Gaussian, M = 10, ER mean degree 5, off-diagonal precisions ~ N(-1000,
+    10^2), eps = 1e-3) at W = 0: the median of reps timed calls after one
+    untimed call, per node count and kappa, and the least-squares exponent of
+    time against N and against N log^2 N (which the paper's analysis predicts
+    for a homogeneous update graph)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_2401_01404_amd as rec
+    import synth
+
+    rows = []
+    for N in sizes:
+        w = synth.gauss_scaling(N, 10, seed=0)
+        lam = rec.default_lambda(w.X, "gauss")
+        X = torch.as_tensor(w.X).cuda()
+        for kappa in kappas:
+            ctx = rec.Context(X, "gauss", lam, kappa=kappa, prec=prec)
+            try:
+                ctx.find_best(ctx.m, "nndescent")
+            except rec.RecError as e:   # a size beyond the planned search buffers
+                print(json.dumps({"N": N, "kappa": kappa, "error": str(e)}), file=sys.stderr, flush=True)
+                del ctx
+                continue
+            ts, st = [], None
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, _, _, st = ctx.find_best(ctx.m, "nndescent")
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t) * 1e3)
+            rows.append({"N": N, "kappa": kappa, "m": ctx.m, "find_best_ms": float(np.median(ts)),
+                         "pair_evals": st["pair_evals"], "nnd_iters": st["nnd_iters"],
+                         "levels": st["levels"]})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            del ctx
+        del X
+    fit = {}
+    for kappa in kappas:
+        r = [x for x in rows if x["kappa"] == kappa]
+        if len(r) < 2:
+            continue
+        lx = np.log([x["N"] for x in r])
+        lt = np.log([x["find_best_ms"] for x in r])
+        lnl = np.log([x["N"] * math.log(x["N"]) ** 2 for x in r])
+        fit[str(kappa)] = {"exponent_vs_N": float(np.polyfit(lx, lt, 1)[0]),
+                           "exponent_vs_NlogsqN": float(np.polyfit(lnl, lt, 1)[0])}
+    print(json.dumps({"study": "FindBest runtime vs N (Gaussian, M=10)", "prec": prec, "rows": rows,
+                      "fit": fit}), flush=True)
+
+
 def copy_probe(mib):
     """Plain copies of a known size: each reads and writes mib MiB once."""
     import torch
@@ -174,6 +229,9 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times): the "
                          "reference kernel for scaling HBM byte counters")
+    ap.add_argument("--scaling", default="", metavar="N1,N2,...",
+                    help="only run the FindBest runtime study (Gaussian, M=10, the paper's "
+                         "runtime-figure problems) at these node counts")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -181,6 +239,9 @@ def main():
         sys.exit(2)
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
+        return
+    if args.scaling:
+        scaling_study([int(float(v)) for v in args.scaling.split(",")], args.prec)
         return
 
     import numpy as np

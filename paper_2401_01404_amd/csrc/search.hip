@@ -892,6 +892,17 @@ __global__ void k_count_pos(const double* dw, int64_t m, int64_t* cnt) {
 
 inline int64_t gridn(int64_t n, int b = 256) { return (n + b - 1) / b; }
 
+// Dynamic LDS a block of the candidate and merge kernels may take: the
+// device's per-block maximum (160 KB on gfx950) less room for their static
+// variables.
+size_t lds_limit() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+    return 64 * 1024;
+  return (size_t)v - 1024;
+}
+
 int bits_for(int64_t v) {
   int b = 0;
   while (b < 63 && (int64_t(1) << b) < v) ++b;
@@ -989,7 +1000,7 @@ struct Search {
     rec_status st;
     *iters = 0;
     size_t merge_lds = (size_t)k * (8 + 4 + 1) + 16;
-    if (merge_lds > 64 * 1024) { ctx->err = "k too large for the merge kernel"; return REC_E_INVAL; }
+    if (merge_lds > lds_limit()) { ctx->err = "k too large for the merge kernel"; return REC_E_INVAL; }
     if (mode == 0) {
       // random initial lists [Alg. 4]
       if (n * (int64_t)k > ctx->cand_cap) { ctx->err = "candidate buffer too small for init"; return REC_E_NOMEM; }
@@ -1011,7 +1022,7 @@ struct Search {
     const int iters_to_run = mode == 0 ? max_iter : 1;
     CandArgs P{S, ctx->Gidx, ctx->in_src, ctx->capcnt, n, k, mode};
     size_t cand_lds = words * 4 + (mode == 0 ? (size_t)2 * k * 4 : 0);
-    if (cand_lds > 64 * 1024) { ctx->err = "node set too large for the candidate kernel"; return REC_E_INVAL; }
+    if (cand_lds > lds_limit()) { ctx->err = "node set too large for the candidate kernel"; return REC_E_INVAL; }
     for (int it = 0; it < iters_to_run; ++it) {
       P.Gidx = ctx->Gidx;   // the lists ping-pong between two buffers
       if (mode == 0) {
@@ -1029,7 +1040,7 @@ struct Search {
       // NNDescent with the node's candidates fitting LDS: one pass per chunk
       const int64_t lcap = std::min<int64_t>(4 * (int64_t)k * k, n - 1);
       const size_t once_lds = (size_t)words * 4 + (size_t)(2 * k + lcap) * 4;
-      if (mode == 0 && once_lds <= 64 * 1024) {
+      if (mode == 0 && once_lds <= lds_limit()) {
         hipMemsetAsync(d_delta, 0, sizeof(int64_t), s);
         const int64_t per = std::max<int64_t>(1, ctx->cand_cap / lcap);
         for (int64_t a0 = 0; a0 < n; a0 += per) {

@@ -223,6 +223,18 @@ def kinetic_er(N, T, mean_out=5.0, w_sigma=0.3, seed=0, name="kinetic_er"):
                     dict(N=N, T=T, graph="directed_er", mean_out=mean_out, w_sigma=w_sigma, seed=seed))
 
 
+def gauss_scaling(N, M=10, mean_deg=5.0, mean=-1e3, sd=10.0, eps=1e-3, seed=0, name="gauss_scaling"):
+    """The FindBest runtime study's problems [Sec. 5, the runtime figure]: an ER
+    graph of mean degree 5, off-diagonal precisions ~ N(-1000, 10^2), diagonal
+    sum_j |W_ij| / (1 - eps)^2 with eps = 1e-3, M = 10 samples."""
+    ei, ej = er_undirected(N, mean_deg, seed)
+    off = normal(len(ei), mean, sd, seed, ST_WEIGHT)
+    X, diag = gauss(N, M, ei, ej, off, eps, seed)
+    return Workload(name, "gauss", X, ei, ej, off, diag,
+                    dict(N=N, M=M, graph="er", mean_deg=mean_deg, off_mean=mean, off_sd=sd, eps=eps,
+                         seed=seed))
+
+
 def gauss_er(N, M, mean_deg=4.0, off_max=0.2, eps=1e-3, seed=0, name="gauss_er"):
     ei, ej = er_undirected(N, mean_deg, seed)
     off = uniform(len(ei), -off_max, off_max, seed, ST_WEIGHT)
