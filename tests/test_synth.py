@@ -77,3 +77,18 @@ def test_graphs_and_determinism():
     d, s = synth.er_directed(2000, 5.0, seed=0)
     assert np.all(d != s)
     assert abs(len(d) - 10000) < 5 * np.sqrt(10000)
+
+
+def test_gauss_scaling_recipe():
+    """The runtime study's problems: ER mean degree 5, off-diagonal precisions
+    ~ N(-1000, 10^2), diagonal sum_j |W_ij| / (1 - eps)^2, M = 10 samples."""
+    w = synth.gauss_scaling(4000, 10, seed=3)
+    N = w.N
+    assert w.X.shape == (N, 10) and w.X.dtype == np.float32 and np.all(np.isfinite(w.X))
+    assert abs(2 * len(w.ei) / N - 5.0) < 0.3
+    assert abs(w.w.mean() + 1000.0) < 1.0 and abs(w.w.std() - 10.0) < 0.5
+    deg_abs = np.zeros(N)
+    np.add.at(deg_abs, w.ei, np.abs(w.w))
+    np.add.at(deg_abs, w.ej, np.abs(w.w))
+    has = deg_abs > 0
+    assert np.allclose(w.theta[has], deg_abs[has] / (1 - 1e-3) ** 2)
