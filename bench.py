@@ -72,8 +72,8 @@ PEAK_F16_MFMA_TFLOPS = 2500.0   # dense FP16 matrix-core peak
 # kernel source it was measured on: `traffic` is null once that file changes.
 TRAFFIC = {
     "C4": {"source_sha256": "0797914a94446847a6d8e812cae244808b5a69931f2540bc26574a09eef38ed9",
-           "hbm_over_algorithmic": 1.0326,
-           "measured_hbm_bytes_per_launch": 1.4604e+09},
+           "hbm_over_algorithmic": 1.0325,
+           "measured_hbm_bytes_per_launch": 1.4602e+09},
 }
 
 
@@ -82,8 +82,8 @@ TRAFFIC = {
 # `bench.py --workload W --steps 1 --warmup 0 --no-cpu --no-compare`, scaled by the same
 # 1 GiB copy probe.  Valid only for the source it was measured on.
 TRAFFIC_SCREEN = {
-    "C4": {"source_sha256": "7ae8d3312d2ae7828d441a656062c098c55e4585f0db459cd236b6694b62d7ea",
-           "hbm_bytes_per_launch": 3.3720e+10},
+    "C4": {"source_sha256": "fd75cab5271affc70b88799d33523f613ad48081bffc8522edfd51d03ae42114",
+           "hbm_bytes_per_launch": 3.2590e+10},
 }
 
 
