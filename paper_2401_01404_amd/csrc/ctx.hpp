@@ -239,6 +239,11 @@ rec_status rec_launch_score(rec_ctx* ctx, int64_t P, const int32_t* I, const int
 // (gi[p], S[v[p]]), gain to the cache slot.
 rec_status rec_launch_score_owned(rec_ctx* ctx, int64_t P, const int32_t* gi, const int32_t* v,
                                   const int32_t* S, const uint32_t* slot, const Cache* cache);
+// The per-target-row update chains of directed couplings: one wave per
+// chain, chains taken in queue order (key/len, n entries; *head zeroed).
+rec_status rec_launch_update_chains(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
+                                    const uint64_t* key, const uint32_t* len, const int32_t* cpair,
+                                    int64_t n, int64_t* head, uint8_t* done, double* dw);
 // Apply one round of node-disjoint updates: the pairs ready[0..*nready) of
 // the rank-ordered list (I, J); at most m of them (see update kernels).
 rec_status rec_launch_update_round(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,

@@ -1090,6 +1090,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     update_pair<R, NPL, MODEL>(F, W, lambda, ready[q], I, J, wslot, done, dw);
 }
 
+// Directed couplings change only their target row's fields, so the
+// rank-ordered updates split into independent chains, one per target row,
+// each sequential in rank order [Alg. 2].  One wave runs one whole chain,
+// taking chains from a queue ordered longest first (chain q: sorted entry
+// key[q], low word = first position in cpair, length len[q]; keys with high
+// byte 0xFF mark positions that start no chain and sort last).  A lane reads
+// back only the samples it wrote for the previous pair of its chain (the
+// same sample-to-lane map for the row loads and the row stores), so the
+// chain needs no fence between its pairs.
+template <class R, int NPL, int MODEL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_update_chains(
+    Fields F, WTable W, double lambda, const int32_t* __restrict__ I, const int32_t* __restrict__ J,
+    const uint64_t* __restrict__ key, const uint32_t* __restrict__ len,
+    const int32_t* __restrict__ cpair, int64_t n, unsigned long long* head,
+    const int64_t* __restrict__ wslot, uint8_t* done, double* dw) {
+  const int lane = rec_lane();
+  while (true) {
+    int q = 0;
+    if (lane == 0) {
+      const unsigned long long h = atomicAdd(head, 1ull);
+      q = h < (unsigned long long)n ? (int)h : -1;
+    }
+    q = rec_uni(__shfl(q, 0, REC_WAVE));
+    if (q < 0) break;
+    const uint64_t k = key[q];
+    if ((k >> 32) == 0xFF) break;
+    const int64_t e0 = (int64_t)(uint32_t)k;
+    const int64_t L = (int64_t)len[q];
+    for (int64_t e = e0; e < e0 + L; ++e) update_pair<R, NPL, MODEL>(F, W, lambda, cpair[e], I, J, wslot, done, dw);
+  }
+}
+
 template <class R, int MODEL>
 rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
                           const int32_t* Smap, const uint32_t* slot, int owned, double* gain_out,
@@ -1230,6 +1262,31 @@ rec_status launch_score_r(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
 }
 
 template <class R>
+rec_status launch_chains_r(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
+                           const uint64_t* key, const uint32_t* len, const int32_t* cpair,
+                           int64_t n, int64_t* head, uint8_t* done, double* dw) {
+  if (ctx->cfg.model != REC_KINETIC) { ctx->err = "update chains are for directed couplings"; return REC_E_INVAL; }
+  const int64_t blocks = std::min<int64_t>((m + 3) / 4, 256 * 8);
+  unsigned long long* hd = reinterpret_cast<unsigned long long*>(head);
+#define REC_UC(NPL)                                                                              \
+  hipLaunchKernelGGL((k_update_chains<R, NPL, REC_KINETIC>), dim3((unsigned)blocks), dim3(256), 0, \
+                     ctx->stream, ctx->F, ctx->W, ctx->cfg.lambda, I, J, key, len, cpair, n, hd, \
+                     ctx->best_slot, done, dw)
+  switch (ctx->F.npl) {
+    case 1: REC_UC(1); break;
+    case 2: REC_UC(2); break;
+    case 4: REC_UC(4); break;
+    case 8: REC_UC(8); break;
+    case 16: REC_UC(16); break;
+    case 32: REC_UC(32); break;
+    default: ctx->err = "unsupported sample count"; return REC_E_INVAL;
+  }
+#undef REC_UC
+  REC_HIP(hipGetLastError());
+  return REC_OK;
+}
+
+template <class R>
 rec_status launch_update_r(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
                            const int32_t* ready, const int64_t* nready, uint8_t* done, double* dw) {
   switch (ctx->cfg.model) {
@@ -1300,6 +1357,14 @@ rec_status launch_score_any(rec_ctx* ctx, int64_t P, const int32_t* I, const int
   return st;
 }
 }  // namespace
+
+rec_status rec_launch_update_chains(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
+                                    const uint64_t* key, const uint32_t* len, const int32_t* cpair,
+                                    int64_t n, int64_t* head, uint8_t* done, double* dw) {
+  if (m <= 0 || n <= 0) return REC_OK;
+  return ctx->fp32 ? launch_chains_r<float>(ctx, m, I, J, key, len, cpair, n, head, done, dw)
+                   : launch_chains_r<double>(ctx, m, I, J, key, len, cpair, n, head, done, dw);
+}
 
 rec_status rec_launch_update_round(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
                                    const int32_t* ready, const int64_t* nready, uint8_t* done,

@@ -839,6 +839,30 @@ __global__ void k_pred(const uint64_t* klo, int64_t ne, const int32_t* I, int32_
   pred[2 * (int64_t)p + ((uint32_t)I[p] == row ? 0 : 1)] = prev;
 }
 
+// Directed pairs, entries sorted by (row, rank): cpair[e] = pair of entry e;
+// the entry that starts a row's run gets key (0xFE - min(len - 1, 0xFE)) << 32 | e
+// and len[e] = the run's length (a one-byte key that sorts longer chains
+// first), every other entry key 0xFF << 32 | e; *maxlen = the longest run,
+// which is the number of node-disjoint rounds the same updates would take.
+__global__ void k_chain_keys(const uint64_t* ek, int64_t ne, int32_t* cpair, uint64_t* key,
+                             uint64_t* khi, uint32_t* len, unsigned long long* maxlen) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const uint64_t k = ek[e];
+  const uint32_t row = (uint32_t)(k >> 32);
+  cpair[e] = (int32_t)(uint32_t)k;
+  const bool start = e == 0 || (uint32_t)(ek[e - 1] >> 32) != row;
+  int64_t f = e;
+  if (start)
+    while (f < ne && (uint32_t)(ek[f] >> 32) == row) ++f;
+  const uint64_t n = (uint64_t)(f - e);
+  const uint64_t hi = start ? 0xFEull - (n - 1 < 0xFEull ? n - 1 : 0xFEull) : 0xFFull;
+  key[e] = (hi << 32) | (uint64_t)e;
+  khi[e] = 0;
+  len[e] = (uint32_t)n;
+  if (start) atomicMax(maxlen, (unsigned long long)n);
+}
+
 __global__ void k_iota_i32(int32_t* a, int64_t n, int64_t* count) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) a[e] = (int32_t)e;
@@ -1513,6 +1537,54 @@ rec_status rec_search_knn(rec_ctx* ctx, int64_t n, const int32_t* S_dev, int k, 
   return hipGetLastError() == hipSuccess ? REC_OK : REC_E_HIP;
 }
 
+// After the updates of m pairs: Σ|Δw| and the number of changed couplings
+// (and, when given, a device count read back with them); synchronises.
+static rec_status finish_updates(rec_ctx* ctx, int64_t m, double* delta, int64_t* accepted,
+                                 const int64_t* extra_dev, int64_t* extra = nullptr) {
+  hipStream_t s = ctx->stream;
+  ++ctx->w_version;   // the updates changed W
+  if (rec_sum_device(ctx, ctx->dw, m, ctx->dresult + 3) != REC_OK) return REC_E_HIP;
+  hipMemsetAsync(ctx->counter + 11, 0, sizeof(int64_t), s);
+  hipLaunchKernelGGL(k_count_pos, dim3(gridn(m)), dim3(256), 0, s, ctx->dw, m, ctx->counter + 11);
+  hipMemcpyAsync(delta, ctx->dresult + 3, sizeof(double), hipMemcpyDeviceToHost, s);
+  hipMemcpyAsync(accepted, ctx->counter + 11, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (extra_dev) hipMemcpyAsync(extra, extra_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) { ctx->err = "sync failed"; return REC_E_HIP; }
+  int32_t e = 0;
+  hipMemcpy(&e, ctx->err_flag, 4, hipMemcpyDeviceToHost);
+  if (e & 2) { ctx->err = "W table full (increase max_nnz)"; return REC_E_NOMEM; }
+  return REC_OK;
+}
+
+// Directed couplings: with the row entries (one per pair, row = target)
+// sorted by (row, rank) in sort buffer cur, every target row's pairs form a
+// chain that only that row's fields see, so running each chain in rank
+// order is the sequential order [Alg. 2].  The chains are queued longest
+// first (one 8-bit digit of the radix sort, stable in position) and one
+// launch runs them all; the reported round count is the longest chain,
+// the rounds the node-disjoint schedule would take.
+static rec_status apply_chains(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J, int cur,
+                               double* delta, int64_t* accepted, int64_t* rounds) {
+  hipStream_t s = ctx->stream;
+  const int64_t ne = m;
+  int32_t* cpair = ctx->pred;   // 2m entries; the chains take m
+  int64_t* head = ctx->counter + 0;
+  int64_t* maxlen = ctx->counter + 1;
+  hipMemsetAsync(ctx->counter, 0, 2 * sizeof(int64_t), s);
+  const int o = cur ^ 1;
+  hipLaunchKernelGGL(k_chain_keys, dim3(gridn(ne)), dim3(256), 0, s, ctx->sb.klo[cur], ne, cpair,
+                     ctx->sb.klo[o], ctx->sb.khi[o], ctx->sb.val[o],
+                     reinterpret_cast<unsigned long long*>(maxlen));
+  Digit dg[1] = {{0, 32}};
+  int c = o;
+  rec_status st = rec_radix_sort(ctx, ne, dg, 1, &c);
+  if (st != REC_OK) return st;
+  st = rec_launch_update_chains(ctx, m, I, J, ctx->sb.klo[c], ctx->sb.val[c], cpair, ne, head,
+                                ctx->done, ctx->dw);
+  if (st != REC_OK) return st;
+  return finish_updates(ctx, m, delta, accepted, maxlen, rounds);
+}
+
 // Coordinate updates of the m pairs in rank order [Alg. 2], as rounds of
 // node-disjoint pairs (a pair runs once every earlier pair sharing a row
 // with it has run), which reproduces the sequential order exactly.  Each
@@ -1544,6 +1616,7 @@ rec_status rec_apply_best(rec_ctx* ctx, int64_t m, const int32_t* I, const int32
     int cur = 0;
     rec_status st = rec_radix_sort(ctx, ne, dg, nd, &cur);
     if (st != REC_OK) return st;
+    if (directed) return apply_chains(ctx, m, I, J, cur, delta, accepted, rounds);
     hipLaunchKernelGGL(k_pred, dim3(gridn(ne)), dim3(256), 0, s, ctx->sb.klo[cur], ne, I, ctx->pred);
   }
   // pending lists (ping-pong) and their counts, the round's ready count
@@ -1577,15 +1650,5 @@ rec_status rec_apply_best(rec_ctx* ctx, int64_t m, const int32_t* I, const int32
     if (pass > m + batch) { ctx->err = "update rounds did not drain"; return REC_E_NUMERIC; }
   }
   *rounds = pass;
-  ++ctx->w_version;   // the rounds changed W
-  if (rec_sum_device(ctx, ctx->dw, m, ctx->dresult + 3) != REC_OK) return REC_E_HIP;
-  hipMemsetAsync(ctx->counter + 11, 0, sizeof(int64_t), s);
-  hipLaunchKernelGGL(k_count_pos, dim3(gridn(m)), dim3(256), 0, s, ctx->dw, m, ctx->counter + 11);
-  hipMemcpyAsync(delta, ctx->dresult + 3, sizeof(double), hipMemcpyDeviceToHost, s);
-  hipMemcpyAsync(accepted, ctx->counter + 11, sizeof(int64_t), hipMemcpyDeviceToHost, s);
-  if (hipStreamSynchronize(s) != hipSuccess) { ctx->err = "sync failed"; return REC_E_HIP; }
-  int32_t e = 0;
-  hipMemcpy(&e, ctx->err_flag, 4, hipMemcpyDeviceToHost);
-  if (e & 2) { ctx->err = "W table full (increase max_nnz)"; return REC_E_NOMEM; }
-  return REC_OK;
+  return finish_updates(ctx, m, delta, accepted, nullptr);
 }
