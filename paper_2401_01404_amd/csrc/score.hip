@@ -1090,17 +1090,119 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     update_pair<R, NPL, MODEL>(F, W, lambda, ready[q], I, J, wslot, done, dw);
 }
 
+// The chain of updates of one target row i of a directed model, in rank
+// order (one wave): the row's fields h_i stay in the lanes' registers from
+// the chain's first pair to its last, and h_i, t_i = tanh h_i and the fp16
+// residuals y_i - t_i are written once at the end; every pair sees the
+// fields left by the one before it, as in the sequential order.  Each step
+// has the arithmetic of update_pair, so the results are the same bit for
+// bit.  The current weight is read by lane 0, the lane that writes it, so a
+// pair listed twice in one chain sees its first update.
+template <class R, int NPL>
+__device__ __forceinline__ void update_chain(const Fields& F, const WTable& W, double lambda,
+                                             const int32_t* __restrict__ cpair, int64_t e0, int64_t n,
+                                             const int32_t* __restrict__ I,
+                                             const int32_t* __restrict__ J,
+                                             const int64_t* __restrict__ wslot, uint8_t* done,
+                                             double* dw) {
+  constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  const int lane = rec_lane();
+  const int i = I[cpair[e0]];
+  const int64_t row = (int64_t)i * F.Mp;
+  R* H = reinterpret_cast<R*>(F.H);
+  R* T = reinterpret_cast<R*>(F.T);
+  R h[NPL], u[NPL];
+  int yb[CH];   // targets y_i, VEC bytes per chunk
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int64_t o = smp<VEC>(c, lane);
+    ld_vec<VEC>(H + row + o, h + c * VEC);
+    yb[c] = ld_bytes<VEC>(F.ys + row + o);
+  }
+  bool changed = false;
+  for (int64_t e = e0; e < e0 + n; ++e) {
+    const int32_t p = cpair[e];
+    const int j = J[p];
+    const int64_t ws = wslot[p];
+    // sample terms u = x_j t_i, their sum and the lane's part of S = sum y_i x_j;
+    // t_i from T until the chain first changes the row, then tanh h_i, the
+    // value the row's store would have held (padding: h = t = 0)
+    float s_lane = 0.f;
+    R a = R(0);
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int64_t o = smp<VEC>(c, lane);
+      const int xw = ld_bytes<VEC>(F.xs + (int64_t)j * F.Mp + o);
+      R tv[VEC];
+      if (changed) {
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) tv[k] = tanh_(h[c * VEC + k]);
+      } else {
+        ld_vec<VEC>(T + row + o, tv);
+      }
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        const float x = byte_at(xw, k);
+        const R uq = (R)x * tv[k];
+        u[c * VEC + k] = uq;
+        a += uq;
+        s_lane += x * byte_at(yb[c], k);
+      }
+    }
+    const double phi0 = rec_wave_sum_dpp((double)s_lane - (double)a);
+    double wl = 0.0;
+    if (lane == 0 && ws >= 0)
+      wl = __builtin_bit_cast(double, __atomic_load_n(reinterpret_cast<const uint64_t*>(W.vals + ws), __ATOMIC_RELAXED));
+    const double w0 = rec_uni(__shfl(wl, 0, REC_WAVE));
+    Work wk;
+    const PairOut r = solve_ising<R, NPL, false>(u, u, phi0, s_lane, w0, lambda, F.M, F.Mp, wk);
+    const double d = r.w - w0;
+    if (d != 0.0) {
+      // h_i += d x_j [App. A]; x_j read again rather than held across the solve
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int64_t o = smp<VEC>(c, lane);
+        const int xw = ld_bytes<VEC>(F.xs + (int64_t)j * F.Mp + o);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          const R hn = h[c * VEC + k] + (R)(d * (double)byte_at(xw, k));
+          if (o + k < F.M) h[c * VEC + k] = hn;
+        }
+      }
+      changed = true;
+      if (lane == 0 && ws >= 0) W.vals[ws] = r.w;
+    }
+    if (lane == 0) {
+      dw[p] = fabs(d);
+      done[p] = 1;
+    }
+  }
+  if (changed) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int64_t o = smp<VEC>(c, lane);
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        const int q = c * VEC + k;
+        if (o + k < F.M) {
+          const R t = tanh_(h[q]);
+          H[row + o + k] = h[q];
+          T[row + o + k] = t;
+          F.rh[row + o + k] = rec_f16_bits((float)((R)byte_at(yb[c], k) - t));
+        }
+      }
+    }
+  }
+}
+
 // Directed couplings change only their target row's fields, so the
 // rank-ordered updates split into independent chains, one per target row,
 // each sequential in rank order [Alg. 2].  One wave runs one whole chain,
 // taking chains from a queue ordered longest first (chain q: sorted entry
 // key[q], low word = first position in cpair, length len[q]; keys with high
-// byte 0xFF mark positions that start no chain and sort last).  A lane reads
-// back only the samples it wrote for the previous pair of its chain (the
-// same sample-to-lane map for the row loads and the row stores), so the
-// chain needs no fence between its pairs.
-template <class R, int NPL, int MODEL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_update_chains(
+// byte 0xFF mark positions that start no chain and sort last).
+template <class R, int NPL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_update_chains(
     Fields F, WTable W, double lambda, const int32_t* __restrict__ I, const int32_t* __restrict__ J,
     const uint64_t* __restrict__ key, const uint32_t* __restrict__ len,
     const int32_t* __restrict__ cpair, int64_t n, unsigned long long* head,
@@ -1109,16 +1211,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   while (true) {
     int q = 0;
     if (lane == 0) {
-      const unsigned long long h = atomicAdd(head, 1ull);
-      q = h < (unsigned long long)n ? (int)h : -1;
+      const unsigned long long hd = atomicAdd(head, 1ull);
+      q = hd < (unsigned long long)n ? (int)hd : -1;
     }
     q = rec_uni(__shfl(q, 0, REC_WAVE));
     if (q < 0) break;
     const uint64_t k = key[q];
     if ((k >> 32) == 0xFF) break;
-    const int64_t e0 = (int64_t)(uint32_t)k;
-    const int64_t L = (int64_t)len[q];
-    for (int64_t e = e0; e < e0 + L; ++e) update_pair<R, NPL, MODEL>(F, W, lambda, cpair[e], I, J, wslot, done, dw);
+    update_chain<R, NPL>(F, W, lambda, cpair, (int64_t)(uint32_t)k, (int64_t)len[q], I, J, wslot, done, dw);
   }
 }
 
@@ -1269,7 +1369,7 @@ rec_status launch_chains_r(rec_ctx* ctx, int64_t m, const int32_t* I, const int3
   const int64_t blocks = std::min<int64_t>((m + 3) / 4, 256 * 8);
   unsigned long long* hd = reinterpret_cast<unsigned long long*>(head);
 #define REC_UC(NPL)                                                                              \
-  hipLaunchKernelGGL((k_update_chains<R, NPL, REC_KINETIC>), dim3((unsigned)blocks), dim3(256), 0, \
+  hipLaunchKernelGGL((k_update_chains<R, NPL>), dim3((unsigned)blocks), dim3(256), 0, \
                      ctx->stream, ctx->F, ctx->W, ctx->cfg.lambda, I, J, key, len, cpair, n, hd, \
                      ctx->best_slot, done, dw)
   switch (ctx->F.npl) {
