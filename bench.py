@@ -2,7 +2,7 @@
 """Benchmark: GCD sweeps [Alg. 2] on one MI355X.
 
 One step = one full GCD sweep: the search for the m = kappa N best pairs, the
-coordinate updates of E_best in node-disjoint rounds, the field rebuild, the
+coordinate updates of E_best in rank order, the field rebuild, the
 theta refit and the FP64 objective.  W warm-up sweeps run first (from W = 0),
 then K sweeps are timed.
 
@@ -71,9 +71,9 @@ PEAK_F16_MFMA_TFLOPS = 2500.0   # dense FP16 matrix-core peak
 # reads 0.5x the bytes copied, WRITE_SIZE 1.0x).  Valid only for the score
 # kernel source it was measured on: `traffic` is null once that file changes.
 TRAFFIC = {
-    "C4": {"source_sha256": "0797914a94446847a6d8e812cae244808b5a69931f2540bc26574a09eef38ed9",
-           "hbm_over_algorithmic": 1.0325,
-           "measured_hbm_bytes_per_launch": 1.4602e+09},
+    "C4": {"source_sha256": "bdb4787b37bd8893401e9e3a3f48ca5743bbccfa9d2ed46ee77ee269d5738eca",
+           "hbm_over_algorithmic": 1.0326,
+           "measured_hbm_bytes_per_launch": 1.4604e+09},
 }
 
 
@@ -83,7 +83,7 @@ TRAFFIC = {
 # 1 GiB copy probe.  Valid only for the source it was measured on.
 TRAFFIC_SCREEN = {
     "C4": {"source_sha256": "fd75cab5271affc70b88799d33523f613ad48081bffc8522edfd51d03ae42114",
-           "hbm_bytes_per_launch": 3.2590e+10},
+           "hbm_bytes_per_launch": 3.2592e+10},
 }
 
 

@@ -112,7 +112,7 @@ typedef struct {
   int64_t pair_evals;     /* exact pair scores computed (cache hits not counted)      */
   int64_t nnd_iters;      /* NNDescent iterations summed over FindBest levels         */
   int64_t levels;         /* FindBest recursion levels                                */
-  int64_t rounds;         /* node-disjoint update rounds                               */
+  int64_t rounds;         /* node-disjoint update rounds (kinetic: longest row chain) */
   double t_search_ms;     /* wall time of FindBest                                     */
   double t_update_ms;     /* wall time of the coordinate updates                       */
   double t_theta_ms;      /* wall time of theta update, field refresh and objective    */
@@ -170,7 +170,8 @@ rec_status rec_find_best_candidates(rec_ctx* ctx, int64_t m, int32_t search, int
 
 /* One GCD iteration [Alg. 2]: E_best = FindBest(m = round(kappa N)); every
  * pair of E_best updated to its argmax in rank order (run as node-disjoint
- * rounds, which equals the sequential order); then theta refitted for all
+ * rounds, for the kinetic model as one chain per target row, either of which
+ * equals the sequential order); then theta refitted for all
  * nodes, fields rebuilt from W and the objective evaluated.  Synchronises. */
 rec_status rec_gcd_sweep(rec_ctx* ctx, int32_t search, rec_sweep_stats* stats_host);
 

@@ -399,6 +399,34 @@ def test_kinetic_update_chains_match_sequential_oracle(prec):
     assert abs(obj - O.objective()) <= (1e-10 if prec == "fp64" else 1e-6) * abs(O.objective())
 
 
+def test_kinetic_update_chains_repeated_pairs():
+    """A pair listed twice runs twice in its chain, the second time from the
+    weight the first one set (sequential order [Alg. 2]): the GPU and the
+    oracle agree on Delta, on W and on the objective."""
+    w = synth.kinetic_er(120, 300, 4.0, 0.3, seed=14)
+    lam = oracle.default_lambda(w.X, "kinetic")
+    O = oracle.Oracle(w.X, "kinetic", lam)
+    Io, Jo, _, _ = O.find_best(2 * w.N, "exhaustive")
+    I, J = list(Io.tolist()), list(Jo.tolist())
+    rng = np.random.default_rng(3)
+    for q in rng.choice(len(Io), 20, replace=False):
+        pos = int(rng.integers(q + 1, len(I) + 1))
+        I.insert(pos, int(Io[q]))
+        J.insert(pos, int(Jo[q]))
+    I, J = np.array(I, np.int32), np.array(J, np.int32)
+    C = ctx_for(w, lam, "fp64")
+    d_gpu = C.apply_updates(I, J)
+    d_or, _ = O.apply_updates(I, J)
+    assert abs(d_gpu - d_or) <= 1e-9 * d_or
+    ei, ej, wv, _ = C.get_model()
+    eo, fo, wo, _ = O.get_model()
+    assert np.array_equal(ei.cpu().numpy(), eo) and np.array_equal(ej.cpu().numpy(), fo)
+    assert np.allclose(wv.cpu().numpy(), wo, rtol=1e-9, atol=1e-9)
+    O.theta_update()
+    obj = C.theta_update()
+    assert abs(obj - O.objective()) <= 1e-10 * abs(O.objective())
+
+
 def test_kinetic_sweeps_track_oracle():
     w = synth.kinetic_er(150, 300, 4.0, 0.3, seed=6)
     lam = oracle.default_lambda(w.X, "kinetic")
