@@ -1609,9 +1609,10 @@ rec_status rec_apply_best(rec_ctx* ctx, int64_t m, const int32_t* I, const int32
   hipLaunchKernelGGL(k_row_entries, dim3(gridn(ne)), dim3(256), 0, s, I, J, m, directed, ctx->sb.klo[0],
                      ctx->sb.khi[0], ctx->sb.val[0]);
   {
-    Digit dg[8];
+    // the entries are written in rank order and the radix sort is stable,
+    // so the row digits alone give (row, rank) order
+    Digit dg[4];
     int nd = 0;
-    for (int b = 0; b < bits_for(m); b += 8) dg[nd++] = {0, b};
     for (int b = 0; b < bits_for(ctx->cfg.N); b += 8) dg[nd++] = {0, 32 + b};
     int cur = 0;
     rec_status st = rec_radix_sort(ctx, ne, dg, nd, &cur);
