@@ -620,8 +620,10 @@ rec_status rec_wtable_compact(rec_ctx* ctx, int64_t* nnz_out) {
     hipLaunchKernelGGL(k_csr_records, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, ctx->wi,
                        ctx->wj, n, directed, ctx->sb.klo[0], ctx->sb.val[0], ctx->cnt);
   cur = 0;
-  st = rec_radix_sort(ctx, nrec, dg, nd, &cur);
-  if (st != REC_OK) return st;
+  if (!directed) {   // directed records are the (i, j)-sorted list itself
+    st = rec_radix_sort(ctx, nrec, dg, nd, &cur);
+    if (st != REC_OK) return st;
+  }
   st = rec_exclusive_scan(ctx, ctx->cnt, ctx->row_off, ctx->cfg.N + 1, nullptr);
   if (st != REC_OK) return st;
   if (nrec > 0)

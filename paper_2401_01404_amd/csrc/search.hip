@@ -1549,9 +1549,9 @@ static rec_status finish_updates(rec_ctx* ctx, int64_t m, double* delta, int64_t
   hipMemcpyAsync(delta, ctx->dresult + 3, sizeof(double), hipMemcpyDeviceToHost, s);
   hipMemcpyAsync(accepted, ctx->counter + 11, sizeof(int64_t), hipMemcpyDeviceToHost, s);
   if (extra_dev) hipMemcpyAsync(extra, extra_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s);
-  if (hipStreamSynchronize(s) != hipSuccess) { ctx->err = "sync failed"; return REC_E_HIP; }
   int32_t e = 0;
-  hipMemcpy(&e, ctx->err_flag, 4, hipMemcpyDeviceToHost);
+  hipMemcpyAsync(&e, ctx->err_flag, 4, hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) { ctx->err = "sync failed"; return REC_E_HIP; }
   if (e & 2) { ctx->err = "W table full (increase max_nnz)"; return REC_E_NOMEM; }
   return REC_OK;
 }
