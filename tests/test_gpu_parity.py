@@ -399,6 +399,38 @@ def test_kinetic_update_chains_match_sequential_oracle(prec):
     assert abs(obj - O.objective()) <= (1e-10 if prec == "fp64" else 1e-6) * abs(O.objective())
 
 
+def test_kinetic_update_chains_beyond_queue_key_range():
+    """Chains longer than the 8-bit queue key distinguishes (every source of
+    target 3, 300 sources of target 5, among the exhaustive top 2N) still run
+    whole and in rank order: the GPU and the oracle's sequential updates
+    agree on Delta, W and the objective."""
+    w = synth.kinetic_er(400, 200, 4.0, 0.3, seed=15)
+    lam = oracle.default_lambda(w.X, "kinetic")
+    O = oracle.Oracle(w.X, "kinetic", lam)
+    Io, Jo, _, _ = O.find_best(2 * w.N, "exhaustive")
+    have = set(zip(Io.tolist(), Jo.tolist()))
+    extra = [(3, j) for j in range(w.N) if j != 3] + [(5, j) for j in range(w.N - 300, w.N)]
+    extra = [p for p in extra if p not in have]
+    rng = np.random.default_rng(6)
+    pairs = list(zip(Io.tolist(), Jo.tolist()))
+    for p, pos in zip(extra, rng.integers(0, len(pairs), len(extra))):
+        pairs.insert(int(pos), p)
+    I = np.array([p[0] for p in pairs], np.int32)
+    J = np.array([p[1] for p in pairs], np.int32)
+    assert np.bincount(I).max() > 255
+    C = ctx_for(w, lam, "fp64")
+    d_gpu = C.apply_updates(I, J)
+    d_or, _ = O.apply_updates(I, J)
+    assert abs(d_gpu - d_or) <= 1e-9 * d_or
+    ei, ej, wv, _ = C.get_model()
+    eo, fo, wo, _ = O.get_model()
+    assert np.array_equal(ei.cpu().numpy(), eo) and np.array_equal(ej.cpu().numpy(), fo)
+    assert np.allclose(wv.cpu().numpy(), wo, rtol=1e-9, atol=1e-9)
+    O.theta_update()
+    obj = C.theta_update()
+    assert abs(obj - O.objective()) <= 1e-10 * abs(O.objective())
+
+
 def test_kinetic_update_chains_repeated_pairs():
     """A pair listed twice runs twice in its chain, the second time from the
     weight the first one set (sequential order [Alg. 2]): the GPU and the
