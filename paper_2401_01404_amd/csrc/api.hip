@@ -290,8 +290,7 @@ namespace {
 
 // refresh fields from W with the current theta, refit theta, evaluate
 rec_status refresh(rec_ctx* ctx, double* obj) {
-  REC_TRY(rec_rebuild_fields(ctx));
-  REC_TRY(rec_fit_theta(ctx));
+  REC_TRY(rec_rebuild_fields_fit_theta(ctx));
   return rec_eval_objective(ctx, obj);
 }
 

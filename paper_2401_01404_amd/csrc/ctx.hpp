@@ -221,6 +221,7 @@ rec_status rec_work_read(rec_ctx* ctx, int64_t out[8]);
 rec_status rec_load_data(rec_ctx* ctx, const void* X, int64_t ldx);
 rec_status rec_rebuild_fields(rec_ctx* ctx);              // from W table and theta
 rec_status rec_fit_theta(rec_ctx* ctx);                   // theta update + field shift
+rec_status rec_rebuild_fields_fit_theta(rec_ctx* ctx);    // both in one pass over the rows
 rec_status rec_eval_objective(rec_ctx* ctx, double* out);
 rec_status rec_wtable_compact(rec_ctx* ctx, int64_t* nnz); // W table -> wi/wj/wv (sorted)
 void rec_wtable_clear(rec_ctx* ctx);

@@ -209,8 +209,15 @@ __global__ __launch_bounds__(FT) void k_fields(Fields F, const int64_t* __restri
 //   Gaussian: v = theta^2 is the positive root of C v^2 + M v - A = 0,
 //   A = sum x^2, C = sum m^2, m = (r - x) / theta_old^2.
 // Then the row's fields are shifted to the new theta.
+//
+// With row_off given, the row's fields are first rebuilt from its sorted W row
+// list in registers, exactly as k_fields computes and rounds them, so the
+// refit sees the values k_fields would have stored and the fields are
+// written once instead of twice.
 template <class R, int NPL, int MODEL>
-__global__ __launch_bounds__(FT) void k_theta(Fields F) {
+__global__ __launch_bounds__(FT) void k_theta(Fields F, const int64_t* __restrict__ row_off,
+                                              const int32_t* __restrict__ col,
+                                              const double* __restrict__ colw) {
   using L = RowLayout<NPL>;
   constexpr int VEC = L::VEC, CH = L::CH;
   const int lane = threadIdx.x & (REC_WAVE - 1);
@@ -221,12 +228,38 @@ __global__ __launch_bounds__(FT) void k_theta(Fields F) {
   R* T = reinterpret_cast<R*>(F.T);
   const int8_t* Y = MODEL == REC_KINETIC ? F.ys : F.xs;
   double mm[NPL], y[NPL];
+  double acc[NPL];
+#pragma unroll
+  for (int q = 0; q < NPL; ++q) acc[q] = 0.0;
+  if (row_off) {
+    for (int64_t e = row_off[i]; e < row_off[i + 1]; ++e) {
+      const int64_t j = col[e];
+      const double w = colw[e];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        double x[VEC];
+        if (MODEL == REC_GAUSS) ld_f32<VEC>(F.xf + j * F.Mp + L::at(c, lane), x);
+        else ld_i8<VEC>(F.xs + j * F.Mp + L::at(c, lane), x);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) acc[c * VEC + k] += w * x[k];
+      }
+    }
+  }
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
-    const int64_t idx = i * F.Mp + L::at(c, lane);
-    const Pack<R, VEC> hv = *reinterpret_cast<const Pack<R, VEC>*>(H + idx);
+    const int64_t o = L::at(c, lane), idx = i * F.Mp + o;
     if (MODEL == REC_GAUSS) ld_f32<VEC>(F.xf + idx, y + c * VEC);
     else ld_i8<VEC>(Y + idx, y + c * VEC);
+    Pack<R, VEC> hv;
+    if (row_off) {
+#pragma unroll
+      for (int k = 0; k < VEC; ++k)
+        hv.v[k] = o + k < F.M ? (MODEL == REC_GAUSS ? (R)(y[c * VEC + k] + th0 * th0 * acc[c * VEC + k])
+                                                    : (R)(th0 + acc[c * VEC + k]))
+                              : R(0);
+    } else {
+      hv = *reinterpret_cast<const Pack<R, VEC>*>(H + idx);
+    }
 #pragma unroll
     for (int k = 0; k < VEC; ++k) {
       const double hh = (double)hv.v[k];
@@ -498,16 +531,28 @@ rec_status launch_fields_n(rec_ctx* ctx) {
 }
 
 template <class R, int NPL>
-rec_status launch_theta_n(rec_ctx* ctx) {
+rec_status launch_theta_k(rec_ctx* ctx, bool rebuild) {
   dim3 g((unsigned)((ctx->cfg.N + FT / REC_WAVE - 1) / (FT / REC_WAVE))), b(FT);
+  const int64_t* ro = rebuild ? ctx->row_off : nullptr;
   switch (ctx->cfg.model) {
-    case REC_ISING: hipLaunchKernelGGL((k_theta<R, NPL, REC_ISING>), g, b, 0, ctx->stream, ctx->F); break;
-    case REC_GAUSS: hipLaunchKernelGGL((k_theta<R, NPL, REC_GAUSS>), g, b, 0, ctx->stream, ctx->F); break;
-    default: hipLaunchKernelGGL((k_theta<R, NPL, REC_KINETIC>), g, b, 0, ctx->stream, ctx->F);
+    case REC_ISING:
+      hipLaunchKernelGGL((k_theta<R, NPL, REC_ISING>), g, b, 0, ctx->stream, ctx->F, ro, ctx->col, ctx->colw);
+      break;
+    case REC_GAUSS:
+      hipLaunchKernelGGL((k_theta<R, NPL, REC_GAUSS>), g, b, 0, ctx->stream, ctx->F, ro, ctx->col, ctx->colw);
+      break;
+    default:
+      hipLaunchKernelGGL((k_theta<R, NPL, REC_KINETIC>), g, b, 0, ctx->stream, ctx->F, ro, ctx->col, ctx->colw);
   }
   REC_HIP(hipGetLastError());
   return REC_OK;
 }
+
+template <class R, int NPL>
+rec_status launch_theta_n(rec_ctx* ctx) { return launch_theta_k<R, NPL>(ctx, false); }
+
+template <class R, int NPL>
+rec_status launch_fields_theta_n(rec_ctx* ctx) { return launch_theta_k<R, NPL>(ctx, true); }
 
 // the row kernels keep NPL samples per lane in registers
 #define REC_NPL_SWITCH(FN, R)                                   \
@@ -526,6 +571,9 @@ rec_status launch_fields_r(rec_ctx* ctx) { REC_NPL_SWITCH(launch_fields_n, R) }
 
 template <class R>
 rec_status launch_theta_r(rec_ctx* ctx) { REC_NPL_SWITCH(launch_theta_n, R) }
+
+template <class R>
+rec_status launch_fields_theta_r(rec_ctx* ctx) { REC_NPL_SWITCH(launch_fields_theta_n, R) }
 
 template <class R, int NPL>
 rec_status launch_rowll_n(rec_ctx* ctx) {
@@ -645,6 +693,13 @@ rec_status rec_rebuild_fields(rec_ctx* ctx) {
 
 rec_status rec_fit_theta(rec_ctx* ctx) {
   return ctx->fp32 ? launch_theta_r<float>(ctx) : launch_theta_r<double>(ctx);
+}
+
+rec_status rec_rebuild_fields_fit_theta(rec_ctx* ctx) {
+  int64_t nnz;
+  rec_status st = rec_wtable_compact(ctx, &nnz);
+  if (st != REC_OK) return st;
+  return ctx->fp32 ? launch_fields_theta_r<float>(ctx) : launch_fields_theta_r<double>(ctx);
 }
 
 rec_status rec_sum_device(rec_ctx* ctx, const double* x, int64_t n, double* out) {
