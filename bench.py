@@ -1,30 +1,34 @@
 #!/usr/bin/env python
-"""Benchmark: GCD sweeps [Alg. 2] on one MI355X.
+"""Benchmark of the exact pair score and the GCD sweep [Alg. 2-4] on one MI355X.
+
+Headline (value): pair-score evals/s.  One eval is one complete exact solve
+of a pair's coupling (function D of Alg. 2: the best penalised log-likelihood
+gain over all M samples, and its argmax).  The rate is the number of pairs
+in a fixed batch, scored through rec_score_pairs, over the summed kernel time
+of those calls (HIP events on the library's stream).  The batch is 16
+uniformly drawn partners per node, grouped by node, the shape of a level-0
+NNDescent candidate set.  It is scored at W = 0 (theta fitted, the headline)
+and again after one GCD sweep.  Cache hits and pairs that a screening bound
+excluded are never counted here.
 
 One step = one full GCD sweep: the search for the m = kappa N best pairs, the
-coordinate updates of E_best in rank order, the field rebuild, the
-theta refit and the FP64 objective.  W warm-up sweeps run first (from W = 0),
-then K sweeps are timed.
+coordinate updates in rank order, the field rebuild, the theta refit and the
+FP64 objective.  The timed sweeps use the screened exhaustive search, which
+returns the exhaustive top m (recall 1).  After them, the same state is swept
+once with each search (plain FindBest over NNDescent, the learned proposal,
+the gradient distance, the screen), with the model restored between them,
+and each search's recall of the exact positive-gain top m is measured.
 
-Default search (--search screen): every pair of the workload is decided each
-sweep -- its gain is bounded through the FP16 MFMA contraction of the samples
-with the residuals, and the pairs whose upper bound can reach the m-th best
-gain are scored exactly -- so the sweep returns the exhaustive search's top m
-(recall 1).  value = pairs decided / sweep wall time.  The dominant kernel is
-the contraction (matrix cores, FP16 in, FP32 accumulate); its roofline entry
-is its algorithmic flops (2 M per ordered pair, or per unordered pair and
-side) over its event-timed kernel time, against the dense FP16 peak.  After
-the timed sweeps the same state is searched once with FindBest over NNDescent
-[Alg. 3, 4] and once with the screen, and NNDescent's recall of the exact top
-m is reported beside its time.
+roofline: the pair-score kernels of one rec_score_pairs call on the batch
+(k_kink + k_exact: the L1-kink decision from sign words and fp16 residuals,
+then the exact Newton solve of the sides it cannot settle).  Both the HBM view
+(algorithmic bytes the kernels count / event time, against 8 TB/s) and the
+FP32 VALU view (algorithmic flops / event time, against 157.3 TFLOP/s) are
+computed.  The bound is the larger fraction.  The screening contraction, the
+sweep's dominant kernel, gets its own entry against the FP16 MFMA peak.
 
---search nndescent: FindBest over NNDescent, value = exact pair scores per
-second of sweep wall time; the roofline entry is then the pair-score kernel's
-HBM traffic (algorithmic bytes it counts / its kernel time).
-
-The CPU oracle is timed on a bounded random sample of pairs of the same
-workload for the cpu_baseline entry (exact FP64 scores: one decided pair
-each).
+cpu_baseline: the FP64 CPU oracle (built -O3 -march=native on the host that
+runs it) scoring a bounded prefix of the same batch at the same state.
 """
 import argparse
 import json
@@ -36,12 +40,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
+    "C4s": "Ising pseudolikelihood, N=100000, M=1000 +-1 Gibbs samples, random 3-regular graph, "
+           "w~U[-0.4,0.4], kappa=4 (m=400000), FP32 scores with FP64 sums",
     "C4": "kinetic Ising time series, N=100000, T=1000 transitions of +-1 spins under parallel "
           "Glauber updates, directed ER mean out-degree 5, w~N(0,0.3^2), kappa=4 (m=400000), "
           "FP32 scores with FP64 sums",
     "C3": "Gaussian pseudolikelihood, N=20000, M=200 float32 samples from N(0, Theta^-1), ER mean "
-          "degree 4, offdiag U[-0.2,0.2], diagonally dominant, kappa=4 (m=80000); exhaustive "
-          "search through the BF16 MFMA screen (--search screen) with exact rescoring",
+          "degree 4, offdiag U[-0.2,0.2], diagonally dominant, kappa=4 (m=80000)",
     "C2": "Ising pseudolikelihood, N=10000, M=1000 +-1 Gibbs samples, random 3-regular graph, "
           "w~U[-0.4,0.4], kappa=4 (m=40000), FP32 scores with FP64 sums",
     "C1": "Ising pseudolikelihood, N=100, M=500 +-1 Gibbs samples, ER mean degree 3, kappa=4",
@@ -49,42 +54,32 @@ WORKLOADS = {
           "w~N(0,0.3^2), kappa=4 (m=4000000), FP32 scores with FP64 sums",
 }
 
-# Algorithmic FP32 work of the pair-score kernel, counted per executed pass
+# Algorithmic FP32 work of the pair-score kernels, counted per executed pass
 # over the M samples of one side (fma = 2 flops, rcp = 1):
 #   load/kink pass:  u = x t (1), sum u (1), 1 - u^2 and its sum (fma + add: 3)   = 5
 #   moment pass:     1 - u^2 (2), u-powers and sums (mul, add, mul, add, fma: 6)  = 8
 #   Newton pass:     1 + u tau (2), rcp (1), u + tau (1), mul (1), sums (add, fma: 3) = 8
 #   log pass:        1 + u tau (2), product (1)                                   = 3
 FLOPS_LOAD, FLOPS_MOMENT, FLOPS_EVAL, FLOPS_LOG = 5, 8, 8, 3
-# Peak of the non-packed FP32 vector pipe: 256 CUs x 4 SIMDs x 16 lanes x
-# 2.4 GHz x 2 flops per FMA = 78.6 TFLOP/s (packed FP32 is disabled in this
-# build, so the 157.3 TFLOP/s packed figure is not reachable).
-PEAK_TFLOPS = 78.6
+# MI355X peaks: FP32 vector 157.3 TFLOP/s (256 CUs x 4 SIMDs x 2.4 GHz, an FMA
+# counted as 2 flops, dual-issue/packed rate as published), HBM3E 8 TB/s,
+# dense FP16 matrix cores 2.5 PFLOP/s.
+PEAK_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-PEAK_F16_MFMA_TFLOPS = 2500.0   # dense FP16 matrix-core peak
+PEAK_F16_MFMA_TFLOPS = 2500.0
+BATCH_PER_NODE = 16
 
-# HBM traffic of the pair-score kernels (k_kink + k_exact, or k_score) per
+# HBM traffic of the pair-score kernels on the batch (k_kink + k_exact) per
 # algorithmic byte, from two rocprofv3 --pmc runs (FETCH_SIZE, then
-# WRITE_SIZE) of `bench.py --workload W --steps 1 --warmup 0 --no-cpu
-# --no-compare` (the screened search's rescoring kernel k_score), each
-# scaled by a 1 GiB device copy (`bench.py --copy-probe 1024`: FETCH_SIZE
-# reads 0.5x the bytes copied, WRITE_SIZE 1.0x).  Valid only for the score
-# kernel source it was measured on: `traffic` is null once that file changes.
-TRAFFIC = {
-    "C4": {"source_sha256": "bdb4787b37bd8893401e9e3a3f48ca5743bbccfa9d2ed46ee77ee269d5738eca",
-           "hbm_over_algorithmic": 1.0326,
-           "measured_hbm_bytes_per_launch": 1.4604e+09},
-}
+# WRITE_SIZE) of `bench.py --steps 1 --warmup 0 --no-cpu --no-compare
+# --only-batch`, each scaled by a plain 1 GiB device copy (`bench.py
+# --copy-probe 1024`: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE
+# 1.0x).  Valid only for the score kernel source it was measured on.
+TRAFFIC = {}
 
-
-# HBM traffic of the contraction's full pass (k_kscreen<2,...>) per launch,
-# from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
-# `bench.py --workload W --steps 1 --warmup 0 --no-cpu --no-compare`, scaled by the same
-# 1 GiB copy probe.  Valid only for the source it was measured on.
-TRAFFIC_SCREEN = {
-    "C4": {"source_sha256": "fd75cab5271affc70b88799d33523f613ad48081bffc8522edfd51d03ae42114",
-           "hbm_bytes_per_launch": 3.2592e+10},
-}
+# HBM traffic of the contraction's full pass (k_kscreen) per launch, from the
+# same kind of counter runs; valid only for the source it was measured on.
+TRAFFIC_SCREEN = {}
 
 
 def source_sha(name="score.hip"):
@@ -94,55 +89,306 @@ def source_sha(name="score.hip"):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def cpu_baseline(w, lam, seconds):
-    """The FP64 oracle scoring random pairs of the workload at W = 0."""
+def batch_pairs(N, per_node, seed=12345):
+    """per_node uniform partners j != i for every node i, grouped by i."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    I = np.repeat(np.arange(N, dtype=np.int32), per_node)
+    J = rng.integers(0, N - 1, N * per_node).astype(np.int32)
+    J += (J >= I).astype(np.int32)
+    return I, J
+
+
+def score_batch(ctx, I, J, reps, torch):
+    """reps calls of rec_score_pairs on (I, J); kernel time from the
+    library's HIP events, work from its counters."""
+    ctx.kernel_time()                   # clear
+    ctx.set_timing(True)
+    Id = torch.as_tensor(I).cuda()
+    Jd = torch.as_tensor(J).cuda()
+    ctx.score_pairs(Id, Jd)             # untimed warm-up
+    torch.cuda.synchronize()
+    ctx.kernel_time()
+    g = None
+    for _ in range(reps):
+        g, _ = ctx.score_pairs(Id, Jd)
+    torch.cuda.synchronize()
+    ms, launches, work = ctx.kernel_time()
+    return g, ms, launches, work
+
+
+def batch_roofline(ctx, w, ms, launches, work, P, reps):
+    sides = 2 if w.model == "ising" else 1
+    flops = sides * w.M * (FLOPS_LOAD * work["pairs"] + FLOPS_MOMENT * work["moment_passes"]
+                           + FLOPS_EVAL * work["evals"] + FLOPS_LOG * work["log_passes"])
+    per = max(launches, 1)
+    t = ms / 1e3 / per
+    bytes_l = work["bytes"] / per
+    flops_l = flops / per
+    gbs = bytes_l / t / 1e9
+    tfl = flops_l / t / 1e12
+    fh, fa = gbs / PEAK_HBM_GBS, tfl / PEAK_TFLOPS
+    tr = TRAFFIC.get(w.name)
+    traffic = None
+    if tr and tr["source_sha256"] == source_sha():
+        traffic = tr["hbm_over_algorithmic"] * bytes_l
+    hbm = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": fh}
+    alu = {"bound": "alu", "achieved": tfl, "peak": PEAK_TFLOPS, "unit": "TFLOP/s", "frac": fa}
+    main, other = (hbm, alu) if fh >= fa else (alu, hbm)
+    out = dict(main)
+    out.update({
+        "traffic": traffic,
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+        "kernel": "pair score, one rec_score_pairs call: k_kink (L1-kink decision from sign words "
+                  "and fp16 residuals) + k_exact (exact Newton solve of the unsettled sides)"
+                  if w.model != "gauss" else "pair score: k_score (closed form)",
+        "kernel_ms_avg": ms / per, "launches": launches,
+        "pairs_per_launch": P, "bytes_per_launch": bytes_l, "flops_per_launch": flops_l,
+        "bytes_per_pair": bytes_l / P, "flops_per_pair": flops_l / P,
+        "sides_settled_at_kink": work["screened"] / max(1, sides * work["pairs"]),
+        "newton_evals_per_pair": work["evals"] / max(1, work["pairs"]),
+        "other_view": other,
+    })
+    return out
+
+
+def cpu_baseline(w, lam, I, J, seconds):
+    """The FP64 oracle, built for this host, scoring a prefix of the batch at
+    W = 0 (theta fitted): the same pairs and state as the headline."""
     import numpy as np
     import oracle
+    oracle.use_native()
     O = oracle.Oracle(w.X, w.model, lam)
-    rng = np.random.default_rng(12345)
-
-    def batch(n):
-        I = rng.integers(0, w.N, n).astype(np.int32)
-        J = rng.integers(0, w.N, n).astype(np.int32)
-        J[I == J] = (J[I == J] + 1) % w.N
+    O.score_pairs(I[:256], J[:256])          # thread-pool start
+    n, dt, size, pos = 0, 0.0, 4096, 0
+    while dt < seconds and n < len(I):
+        a, b = pos, min(pos + size, len(I))
         t = time.perf_counter()
-        O.score_pairs(I, J)
-        return time.perf_counter() - t
-
-    batch(64)                      # warm-up (thread pool start)
-    n, dt, size = 0, 0.0, 256
-    while dt < seconds:            # grow batches until the time budget is spent
-        dt += batch(size)
-        n += size
-        size = min(size * 2, 1 << 16)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        O.score_pairs(I[a:b], J[a:b])
+        dt += time.perf_counter() - t
+        n += b - a
+        pos = b
+        size = min(size * 2, 1 << 18)
+    cores = oracle.threads()
     return {"value": n / dt, "unit": "pair-score evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} random pairs of the workload at W=0 (theta fitted), FP64, "
-                      f"{dt:.1f} s on {cores} threads"}
+            "sample": f"the first {n} pairs of the batch ({BATCH_PER_NODE} uniform partners per node, "
+                      f"grouped by node) at W=0, theta fitted; FP64, {dt:.1f} s on {cores} threads "
+                      f"of {oracle.cpu_model()}; oracle built -O3 -march=native -ffp-contract=off"}
 
 
-def compare_searches(ctx, torch):
-    """At the current state: FindBest over NNDescent [Alg. 3, 4] under the
-    exact gain and under the gradient distance [Appendix, "Gradient as
-    distance"], and the screened exhaustive search, each timed once (after one
-    untimed call); each NNDescent form's recall of the exact positive-gain
-    top m."""
-    out = {}
-    res = {}
-    for search in ("screen", "nndescent", "gradient"):
-        ctx.find_best(ctx.m, search)
+def restore(ctx, model):
+    ei, ej, w, th = model
+    ctx.set_model(ei, ej, w, th)
+
+
+def compare_sweeps(ctx, torch, searches, surrogate_warm=2):
+    """From one state: each search's FindBest recall of the exact positive-gain
+    top m (the screen's result) and one full sweep's wall time, the model
+    restored before every call."""
+    import numpy as np
+    model = ctx.get_model()
+    I, J, G, _ = ctx.find_best(ctx.m, "screen")
+    # gains within the FP32 score tolerance of zero (couplings already at
+    # their optimum, whose sign is rounding) are not part of the recall set
+    floor = 1e-7 * ctx.M
+    keep = (G > floor).cpu().numpy()
+    top = set(zip(I.cpu().numpy()[keep].tolist(), J.cpu().numpy()[keep].tolist()))
+    out = {"exact_top_m_positive": int(len(G)), "recall_set": len(top), "recall_gain_floor": floor}
+    for s in searches:
+        if s == "surrogate":
+            ctx.surrogate_config()
+            for _ in range(surrogate_warm):       # let the network train on exact scores
+                restore(ctx, model)
+                ctx.find_best(ctx.m, "surrogate")
+        restore(ctx, model)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        I, J, G, st = ctx.find_best(ctx.m, search)
+        Is, Js, Gs, st = ctx.find_best(ctx.m, s)
         torch.cuda.synchronize()
-        out[f"{search}_find_best_ms"] = (time.perf_counter() - t) * 1e3
-        out[f"{search}_exact_evals"] = st["pair_evals"]
-        res[search] = set(zip(I.cpu().tolist(), J.cpu().tolist()))
-    best = res["screen"]
-    out["exact_top_m"] = len(best)
-    out["nndescent_recall"] = len(best & res["nndescent"]) / max(1, len(best))
-    out["gradient_recall"] = len(best & res["gradient"]) / max(1, len(best))
+        fb_ms = (time.perf_counter() - t) * 1e3
+        got = set(zip(Is.cpu().tolist(), Js.cpu().tolist()))
+        rec = len(top & got) / max(1, len(top))
+        restore(ctx, model)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sw = ctx.sweep(s)
+        torch.cuda.synchronize()
+        r = {"sweep_ms": (time.perf_counter() - t) * 1e3, "find_best_ms": fb_ms, "recall": rec,
+             "exact_evals": st["pair_evals"], "objective_after": sw["objective"]}
+        if s == "surrogate":
+            ss = ctx.surrogate_stats()
+            r["filter_active"] = bool(ss["mode"] == 2)
+            r["estimated_recall"] = ss["recall"]
+            r["scored_frac"] = ss["scored_frac"]
+        out[s] = r
+        print(f"compare {s}: {json.dumps(r)}", file=sys.stderr, flush=True)
+    restore(ctx, model)
+    meets = [s for s in searches if out[s]["recall"] >= 0.99]
+    out["fastest_at_recall_0.99"] = min(meets, key=lambda s: out[s]["sweep_ms"]) if meets else None
     return out
+
+
+def run_workload(name, args, torch, rec, synth, headline):
+    import numpy as np
+    t_gen = time.perf_counter()
+    w = synth.config(name)
+    t_gen = time.perf_counter() - t_gen
+    print(f"{name}: generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    lam = synth.sparsity_lambda(w.X, w.model)
+    kappa = 4.0
+    m = int(np.floor(kappa * w.N + 0.5))
+    sweeps = args.warmup + args.steps + 8
+    # each sweep adds at most m couplings: room for every sweep this run makes
+    max_nnz = max(64 * w.N, sweeps * m)
+    X = torch.as_tensor(w.X).cuda()
+    ctx = rec.Context(X, w.model, lam, kappa=kappa, prec=args.prec, max_nnz=max_nnz)
+    I, J = batch_pairs(w.N, BATCH_PER_NODE)
+    P = len(I)
+    g0, ms0, l0, wk0 = score_batch(ctx, I, J, args.batch_reps, torch)
+    res = {"workload": name, "N": w.N, "M": w.M, "lambda": lam, "kappa": kappa, "m": ctx.m,
+           "generate_s": round(t_gen, 2), "batch_pairs": P}
+    res["batch_w0"] = {"evals_per_s": P * args.batch_reps / (ms0 / 1e3),
+                       "ms_per_call": ms0 / max(l0, 1),
+                       "positive_gains": int((g0 > 0).sum().item())}
+    roof = batch_roofline(ctx, w, ms0, l0, wk0, P, args.batch_reps)
+    print(f"{name}: batch at W=0 {res['batch_w0']}", file=sys.stderr, flush=True)
+    if args.only_batch:
+        return w, lam, ctx, I, J, res, roof, None, None
+    # first sweep, then the same batch at W != 0
+    st1 = ctx.sweep(args.search)
+    g1, ms1, l1, wk1 = score_batch(ctx, I, J, args.batch_reps, torch)
+    res["batch_after_sweep"] = {"evals_per_s": P * args.batch_reps / (ms1 / 1e3),
+                                "ms_per_call": ms1 / max(l1, 1),
+                                "positive_gains": int((g1 > 0).sum().item()),
+                                "roofline": batch_roofline(ctx, w, ms1, l1, wk1, P, args.batch_reps)}
+    for _ in range(max(0, args.warmup - 1)):
+        ctx.sweep(args.search)
+    ctx.screen_time()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        stats.append(ctx.sweep(args.search))
+        s = stats[-1]
+        print(f"{name} step {k}: {s['t_search_ms'] + s['t_update_ms'] + s['t_theta_ms']:.1f} ms, "
+              f"E_best {s['n_best']}, accepted {s['accepted']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    scr = ctx.screen_time()
+    nnz = len(ctx.get_model()[0])
+    res["sweeps"] = {
+        "search": args.search, "ms_per_sweep": wall / max(args.steps, 1) * 1e3,
+        "sweep_ms": [round(s["t_search_ms"] + s["t_update_ms"] + s["t_theta_ms"], 3) for s in stats],
+        "search_ms": [round(s["t_search_ms"], 3) for s in stats],
+        "update_ms": [round(s["t_update_ms"], 3) for s in stats],
+        "theta_ms": [round(s["t_theta_ms"], 3) for s in stats],
+        "e_best": [s["n_best"] for s in stats], "exact_evals": [s["pair_evals"] for s in stats],
+        "objective": [s["objective"] for s in stats], "delta": [s["delta"] for s in stats],
+        "nnz_after": nnz, "first_sweep_objective": st1["objective"],
+        "pairs_screened_per_sweep": scr["pairs_decided"] / max(args.steps, 1),
+        "pairs_rescored_per_sweep": scr["rescored"] / max(args.steps, 1),
+    }
+    roof_screen = None
+    if scr["full_launches"] > 0 and scr["full_ms"] > 0:
+        sflops = scr["full_flops"] / scr["full_launches"]
+        sms = scr["full_ms"] / scr["full_launches"]
+        ach = sflops / (sms / 1e3) / 1e12
+        ts = TRAFFIC_SCREEN.get(name)
+        straffic = ts["hbm_bytes_per_launch"] if ts and ts["source_sha256"] == source_sha("screen.hip") else None
+        roof_screen = {"bound": "mfma", "achieved": ach, "peak": PEAK_F16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                       "frac": ach / PEAK_F16_MFMA_TFLOPS, "traffic": straffic,
+                       "kernel": "screening contraction full pass: k_kscreen (FP16 MFMA 16x16x32, "
+                                 "FP32 accumulate, histogram + collect epilogue)",
+                       "kernel_ms_avg": sms, "launches": int(scr["full_launches"]),
+                       "flops_per_launch": sflops,
+                       "sample_pass_ms_avg": scr["sample_ms"] / max(scr["sample_launches"], 1)}
+    res["roofline_contraction"] = roof_screen
+    if not args.no_compare:
+        res["compare"] = compare_sweeps(ctx, torch, args.compare.split(","))
+    return w, lam, ctx, I, J, res, roof, stats, wall
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C4s", choices=sorted(WORKLOADS))
+    ap.add_argument("--also", default="C4", help="further workloads measured the same way (comma list, "
+                                                  "'' for none), reported under legs")
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--search", default="screen",
+                    choices=["nndescent", "exhaustive", "exact_knn", "screen", "gradient", "surrogate"])
+    ap.add_argument("--compare", default="nndescent,surrogate,gradient,screen")
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--only-batch", action="store_true", help="only the fixed-batch score leg")
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (5 times): the "
+                         "reference kernel for scaling HBM byte counters")
+    ap.add_argument("--scaling", default="", metavar="N1,N2,...",
+                    help="only run the FindBest runtime study (Gaussian, M=10, the paper's "
+                         "runtime-figure problems) at these node counts")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "sharding of this path is described in the design notes, not built.", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
+    if args.scaling:
+        scaling_study([int(float(v)) for v in args.scaling.split(",")], args.prec)
+        return
+
+    import torch
+
+    import paper_2401_01404_amd as rec
+    import synth
+
+    w, lam, ctx, I, J, res, roof, stats, wall = run_workload(args.workload, args, torch, rec, synth, True)
+    value = res["batch_w0"]["evals_per_s"]
+    steps = args.steps if stats is not None else 0
+    line = {
+        "metric": "pair-score evals/s: exact solves of a pair's coupling (gain and argmax over all M "
+                  "samples) on a fixed batch of 16 uniform partners per node at W=0, over the summed "
+                  "kernel time of the rec_score_pairs calls; steps are full GCD sweeps (screened "
+                  "exhaustive search, recall 1)",
+        "value": value,
+        "unit": "pair-score evals/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": (wall / steps * 1e3) if steps else None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "N": w.N, "M": w.M,
+                   "kappa": 4.0, "m": ctx.m, "lambda": lam,
+                   "lambda_rule": "sparsity target q=N noise pairs at W=0", "search": args.search,
+                   "batch": f"{BATCH_PER_NODE} uniform partners per node, {len(I)} pairs",
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "details": res,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, lam, I, J, args.cpu_seconds)
+    del ctx
+    torch.cuda.empty_cache()
+    legs = {}
+    for name in [s for s in args.also.split(",") if s and s != args.workload]:
+        _, _, c2, _, _, r2, roof2, _, _ = run_workload(name, args, torch, rec, synth, False)
+        r2["roofline"] = roof2
+        legs[name] = r2
+        del c2
+        torch.cuda.empty_cache()
+    if legs:
+        line["legs"] = legs
+    print(json.dumps(line), flush=True)
 
 
 def scaling_study(sizes, prec, kappas=(1.0, 4.0), reps=3):
@@ -211,158 +457,6 @@ def copy_probe(mib):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": n * 4, "copies": 5}), flush=True)
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="C4", choices=sorted(WORKLOADS))
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--search", default="screen",
-                    choices=["nndescent", "exhaustive", "exact_knn", "screen", "gradient"])
-    ap.add_argument("--no-compare", action="store_true",
-                    help="skip the NNDescent-vs-screen comparison after the timed sweeps")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
-                    help="only run a plain device-to-device copy of MIB MiB (5 times): the "
-                         "reference kernel for scaling HBM byte counters")
-    ap.add_argument("--scaling", default="", metavar="N1,N2,...",
-                    help="only run the FindBest runtime study (Gaussian, M=10, the paper's "
-                         "runtime-figure problems) at these node counts")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "sharding of this path is described in the design notes, not built.", file=sys.stderr)
-        sys.exit(2)
-    if args.copy_probe > 0:
-        copy_probe(args.copy_probe)
-        return
-    if args.scaling:
-        scaling_study([int(float(v)) for v in args.scaling.split(",")], args.prec)
-        return
-
-    import numpy as np
-    import torch
-
-    import paper_2401_01404_amd as rec
-    import synth
-
-    t_gen = time.perf_counter()
-    w = synth.config(args.workload)
-    t_gen = time.perf_counter() - t_gen
-    lam = rec.default_lambda(w.X, w.model)
-    kappa = 4.0
-    X = torch.as_tensor(w.X).cuda()
-    ctx = rec.Context(X, w.model, lam, kappa=kappa, prec=args.prec)
-    for _ in range(args.warmup):
-        ctx.sweep(args.search)
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for k in range(args.steps):
-        stats.append(ctx.sweep(args.search))
-        print(f"step {k}: {stats[-1]['t_search_ms'] + stats[-1]['t_update_ms'] + stats[-1]['t_theta_ms']:.1f} ms, "
-              f"evals {stats[-1]['pair_evals']}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    score_ms, launches, work = ctx.kernel_time()
-    scr = ctx.screen_time()
-    scored = work["pairs"]
-    evals = sum(s["pair_evals"] for s in stats)
-    screen = args.search == "screen"
-    decided = scr["pairs_decided"]
-    value = (decided if screen else evals) / wall
-
-    sides = 2 if w.model == "ising" else 1
-    flops = sides * w.M * (FLOPS_LOAD * work["pairs"] + FLOPS_MOMENT * work["moment_passes"]
-                           + FLOPS_EVAL * work["evals"] + FLOPS_LOG * work["log_passes"])
-    tflops = flops / (score_ms / 1e3) / 1e12 if score_ms > 0 else None
-    nbytes = work["bytes"]
-    achieved = nbytes / (score_ms / 1e3) / 1e9 if score_ms > 0 else None
-    tr = TRAFFIC.get(args.workload)
-    traffic = None
-    if tr and tr["source_sha256"] == source_sha() and launches > 0:
-        traffic = tr["hbm_over_algorithmic"] * nbytes / launches
-    roof_score = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                  "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
-                  "traffic": traffic,
-                  "traffic_unit": "HBM bytes per launch (measured HBM / algorithmic bytes x "
-                                  "this run's algorithmic bytes per launch)",
-                  "kernel": ("pair score under the gradient distance: k_grad" if args.search == "gradient" else
-                             "pair score: k_kink + k_exact (k_score for directed and Gaussian pairs)"),
-                  "kernel_ms_avg": score_ms / max(launches, 1), "launches": launches,
-                  "bytes_per_launch": nbytes / max(launches, 1),
-                  "pairs_scored": scored, "bytes_per_pair": nbytes / max(scored, 1),
-                  "alu_view": {"achieved_tflops": tflops, "peak_tflops": PEAK_TFLOPS,
-                               "frac": (tflops / PEAK_TFLOPS) if tflops else None,
-                               "flops_per_pair": flops / max(scored, 1)},
-                  "work": work}
-    roof_screen = None
-    if screen and scr["full_launches"] > 0 and scr["full_ms"] > 0:
-        sflops = scr["full_flops"] / scr["full_launches"]
-        sms = scr["full_ms"] / scr["full_launches"]
-        ach = sflops / (sms / 1e3) / 1e12
-        ts = TRAFFIC_SCREEN.get(args.workload)
-        straffic = ts["hbm_bytes_per_launch"] if ts and ts["source_sha256"] == source_sha("screen.hip") else None
-        roof_screen = {"bound": "mfma", "achieved": ach, "peak": PEAK_F16_MFMA_TFLOPS, "unit": "TFLOP/s",
-                       "frac": ach / PEAK_F16_MFMA_TFLOPS, "traffic": straffic,
-                       "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
-                       "kernel": "screening contraction full pass: k_kscreen (FP16 MFMA 16x16x32, "
-                                 "FP32 accumulate, histogram + collect epilogue)",
-                       "kernel_ms_avg": sms, "launches": int(scr["full_launches"]),
-                       "flops_per_launch": sflops,
-                       "sample_pass_ms_avg": scr["sample_ms"] / max(scr["sample_launches"], 1),
-                       "rescored_exactly": scr["rescored"], "second_collect": scr["second_collect"]}
-    metric = ("pair-score evals/s: pairs decided (scored exactly, or excluded from the top m by a "
-              "proven bound) per second of GCD sweep wall time; recall 1 against the exhaustive search"
-              if screen else
-              ("pair-score evals/s (FindBest scores under the gradient distance per second of GCD sweep "
-               "wall time; E_best ranked by that distance, updates exact)" if args.search == "gradient" else
-               "pair-score evals/s (exact FindBest scores per second of GCD sweep wall time)"))
-    line = {
-        "metric": metric,
-        "value": value,
-        "unit": "pair-score evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f16-mfma+f32" if screen and args.prec == "fp32" else ("f32" if args.prec == "fp32" else "f64"),
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "N": w.N, "M": w.M,
-                   "kappa": kappa, "m": ctx.m, "lambda": lam, "search": args.search,
-                   "parallelism": "single GPU"},
-        "roofline": roof_screen if roof_screen else roof_score,
-        "details": {
-            "sweep_ms": [round(s["t_search_ms"] + s["t_update_ms"] + s["t_theta_ms"], 3) for s in stats],
-            "search_ms": [round(s["t_search_ms"], 3) for s in stats],
-            "update_ms": [round(s["t_update_ms"], 3) for s in stats],
-            "theta_ms": [round(s["t_theta_ms"], 3) for s in stats],
-            "pair_evals": [s["pair_evals"] for s in stats],
-            "exact_evals_per_s": evals / wall,
-            "nnd_iters": [s["nnd_iters"] for s in stats],
-            "levels": [s["levels"] for s in stats],
-            "rounds": [s["rounds"] for s in stats],
-            "objective": [s["objective"] for s in stats],
-            "score_kernel_ms_total": score_ms,
-            "score_kernel_pairs_per_s": scored / (score_ms / 1e3) if score_ms > 0 else None,
-            "generate_s": round(t_gen, 2),
-        },
-    }
-    if roof_screen:
-        line["roofline_score_kernel"] = roof_score
-    if screen and not args.no_compare:
-        line["compare"] = compare_searches(ctx, torch)
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(w, lam, args.cpu_seconds)
-    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

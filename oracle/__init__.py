@@ -24,20 +24,60 @@ _lib = None
 MODELS = {"ising": 0, "gauss": 1, "kinetic": 2}
 
 
+# -ffp-contract=off: no fused multiply-adds, so every build rounds the same
+# way whatever the target's instruction set.
+_FLAGS = ["-O3", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c++17"]
+
+
 def build(force: bool = False) -> str:
-    """Compile oracle.cpp with g++ (-O2, OpenMP) into liboracle.so."""
+    """Compile oracle.cpp with g++ (-O3, OpenMP, x86-64-v3: AVX2 hosts) into liboracle.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["g++", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c++17",
-                               "-o", tmp, _SRC])
+        subprocess.check_call(["g++"] + _FLAGS + ["-march=x86-64-v3", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def use_native() -> str:
+    """Rebuild the oracle for this host's CPU (-march=native, same arithmetic:
+    no contraction) and load that build; call before the first Oracle is made.
+    Used by the CPU-baseline timing, which runs on the host that measures it."""
+    global _LIB, _lib
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    path = os.path.join(_HERE, "liboracle_native.so")
+    tmp = path + ".tmp%d" % os.getpid()
+    subprocess.check_call(["g++"] + _FLAGS + ["-march=native", "-o", tmp, _SRC])
+    os.replace(tmp, path)
+    _LIB = path
+    return path
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use (OMP_NUM_THREADS, else
+    the CPUs this process may run on)."""
+    v = os.environ.get("OMP_NUM_THREADS", "")
+    if v.strip().isdigit() and int(v) > 0:
+        return int(v)
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _L():
     global _lib
     if _lib is None:
-        build()
+        if _LIB.endswith("liboracle.so"):
+            build()
         lib = ctypes.CDLL(_LIB)
         i64, i32, u64, dbl, vp, ci = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
                                       ctypes.c_double, ctypes.c_void_p, ctypes.c_int)

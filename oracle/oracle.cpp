@@ -848,6 +848,15 @@ double orc_gcd_sweep(void* h, int64_t m, int mode, uint64_t seed, double eps, in
   std::vector<int32_t> I(m), J(m);
   std::vector<double> G(m);
   int64_t n = orc_find_best(h, m, mode, seed, eps, max_iter, I.data(), J.data(), G.data(), nullptr);
+  // Only the positive gains among the best m are applied: a zero-gain pair
+  // leaves W unchanged when it is picked, and the paper's arbitrary tie
+  // breaking is read as picking none of the zero-gain ties.  (Ranked by the
+  // gradient distance, the list is not ordered by gain: all of it is applied.)
+  if (P.dist == 0) {
+    int64_t pos = 0;
+    while (pos < n && G[pos] > 0.0) ++pos;
+    n = pos;
+  }
   double delta = orc_apply_updates(h, n, I.data(), J.data(), 0, nullptr);
   theta_update(P);
   if (objective_out) *objective_out = objective(P);

@@ -475,6 +475,11 @@ rec_status rec_gcd_sweep(rec_ctx* ctx, int32_t search, rec_sweep_stats* st) {
   int64_t n = 0;
   rec_status s = rec_search_best(ctx, ctx->m_default, search, &n, &S);
   if (s != REC_OK) return s;
+  // E_best keeps the positive gains of the best m: a pair of zero gain would
+  // leave W as it is, and the ties among zero gains are not chosen at all.
+  // Under the gradient distance the ranking is not by gain: every pair stays.
+  if (search != REC_SEARCH_GRADIENT && search != REC_SEARCH_SCREEN)
+    REC_TRY(rec_positive_prefix(ctx, ctx->best_g, n, &n));
   double t1 = now_ms();
   int64_t acc = 0, rounds = 0;
   double delta = 0.0;

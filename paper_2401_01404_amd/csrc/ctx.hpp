@@ -233,6 +233,8 @@ rec_status rec_wtable_insert_list(rec_ctx* ctx, int64_t n, const int32_t* ei, co
 // score.hip
 // Score pairs (I[p], J[p]); results to gain_out[slot ? slot[p] : p] (and the
 // cache overflow area for slots >= cache capacity when cache != null).
+// Number of leading positive entries of the descending array g[0, n) (synchronises).
+rec_status rec_positive_prefix(rec_ctx* ctx, const double* g, int64_t n, int64_t* np);
 rec_status rec_launch_score(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
                             const uint32_t* slot, double* gain_out, double* w_out,
                             const Cache* cache);

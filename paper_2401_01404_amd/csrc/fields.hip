@@ -210,10 +210,11 @@ __global__ __launch_bounds__(FT) void k_fields(Fields F, const int64_t* __restri
 //   A = sum x^2, C = sum m^2, m = (r - x) / theta_old^2.
 // Then the row's fields are shifted to the new theta.
 //
-// With row_off given, the row's fields are first rebuilt from its sorted W row
-// list in registers, exactly as k_fields computes and rounds them, so the
-// refit sees the values k_fields would have stored and the fields are
-// written once instead of twice.
+// With row_off given, the row's coupling sums m are first formed from its
+// sorted W row list in registers (FP64, in the order k_fields sums them); the
+// refit uses them unrounded, and the fields written at the new theta are the
+// ones k_fields computes there, bit for bit.  The fields are then written
+// once instead of twice, and a later rebuild from (W, theta) reproduces them.
 template <class R, int NPL, int MODEL>
 __global__ __launch_bounds__(FT) void k_theta(Fields F, const int64_t* __restrict__ row_off,
                                               const int32_t* __restrict__ col,
@@ -263,7 +264,10 @@ __global__ __launch_bounds__(FT) void k_theta(Fields F, const int64_t* __restric
 #pragma unroll
     for (int k = 0; k < VEC; ++k) {
       const double hh = (double)hv.v[k];
-      mm[c * VEC + k] = MODEL == REC_GAUSS ? (hh - y[c * VEC + k]) / (th0 * th0) : hh - th0;
+      // rebuilt rows keep the unrounded coupling sums, so the fields written
+      // below are the ones k_fields computes at the new theta, bit for bit
+      mm[c * VEC + k] = row_off ? acc[c * VEC + k]
+                                : (MODEL == REC_GAUSS ? (hh - y[c * VEC + k]) / (th0 * th0) : hh - th0);
     }
   }
   auto valid = [&](int q) { return L::at(q / VEC, lane) + q % VEC < F.M; };
@@ -287,7 +291,7 @@ __global__ __launch_bounds__(FT) void k_theta(Fields F, const int64_t* __restric
       Pack<R, VEC> hv;
 #pragma unroll
       for (int k = 0; k < VEC; ++k)
-        hv.v[k] = valid(c * VEC + k) ? (R)(y[c * VEC + k] + v * mm[c * VEC + k]) : R(0);
+        hv.v[k] = valid(c * VEC + k) ? (R)(y[c * VEC + k] + th * th * mm[c * VEC + k]) : R(0);
       *reinterpret_cast<Pack<R, VEC>*>(H + idx) = hv;
     }
   } else {

@@ -913,8 +913,15 @@ __global__ void k_count_pos(const double* dw, int64_t m, int64_t* cnt) {
   if (rec_lane() == 0 && c) atomicAdd((unsigned long long*)cnt, (unsigned long long)c);
 }
 
+// Length of the leading run of positive values of g[0, n) (g sorted in
+// descending order): the one p with g[p] > 0 and not g[p + 1] > 0 writes p + 1.
+__global__ void k_positive_prefix(const double* g, int64_t n, int64_t* out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n && g[p] > 0.0 && (p + 1 == n || !(g[p + 1] > 0.0))) *out = p + 1;
+}
 
 inline int64_t gridn(int64_t n, int b = 256) { return (n + b - 1) / b; }
+
 
 // Dynamic LDS a block of the candidate and merge kernels may take: the
 // device's per-block maximum (160 KB on gfx950) less room for their static
@@ -1441,6 +1448,17 @@ struct Search {
 };
 
 }  // namespace
+
+rec_status rec_positive_prefix(rec_ctx* ctx, const double* g, int64_t n, int64_t* np) {
+  *np = 0;
+  if (n <= 0) return REC_OK;
+  int64_t* d = ctx->counter + 15;
+  if (hipMemsetAsync(d, 0, sizeof(int64_t), ctx->stream) != hipSuccess) return REC_E_HIP;
+  hipLaunchKernelGGL(k_positive_prefix, dim3(gridn(n)), dim3(256), 0, ctx->stream, g, n, d);
+  if (hipMemcpyAsync(np, d, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
+    return REC_E_HIP;
+  return hipStreamSynchronize(ctx->stream) == hipSuccess ? REC_OK : REC_E_HIP;
+}
 
 // FindBest over NNDescent with the learned proposal.  Active (the network is
 // trained and its last recall estimate reaches the bar): each chunk's

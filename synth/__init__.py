@@ -170,6 +170,48 @@ def ctr(seed: int, stream: int, a: int, b: int) -> int:
     return int(_L().synth_ctr(seed, stream, a, b))
 
 
+# ------------------------------------------------------------------ lambda --
+
+def sparsity_lambda(X, model: str, q: float | None = None) -> float:
+    """The L1 penalty of a workload, set for a target sparsity (the appendix
+    on the Ising model leaves lambda to the user, to be picked for the
+    sparsity it gives).
+
+    At W = 0 the derivative of the objective change in one coupling between
+    two independent nodes is a sum of M independent zero-mean terms: Ising
+    f'(0) = 2 sum_m (x_im - xbar_i)(x_jm - xbar_j), standard deviation
+    2 sqrt(M v_i v_j); Gaussian a = -2 x_i . x_j, 2 sqrt(M v_i v_j) with
+    v = ||x||^2 / M; kinetic f'(0) = sum_t (x_{i,t} - xbar_i) x_{j,t-1},
+    sqrt(T v_i).  With sigma that deviation at the median v, lambda =
+    sigma sqrt(2 ln(P / q)) for P coordinates (N(N-1)/2 symmetric, N(N-1)
+    directed) puts the expected number of such pairs whose gain is positive
+    at W = 0 (|f'(0)| > lambda, a two-sided normal tail) at most q; the
+    default q = N.  Pairs of truly coupled nodes (and their indirect
+    correlations) pass in addition, so the couplings found stay O(N)
+    instead of growing by about m each sweep."""
+    X = np.asarray(X)
+    N = X.shape[0]
+    if model == "gauss":
+        M = X.shape[1]
+        v = np.median((X.astype(np.float64) ** 2).mean(axis=1))
+        sigma = 2.0 * np.sqrt(M) * v
+        P = N * (N - 1) / 2.0
+    elif model == "ising":
+        M = X.shape[1]
+        v = np.median(1.0 - X.astype(np.float64).mean(axis=1) ** 2)
+        sigma = 2.0 * np.sqrt(M) * v
+        P = N * (N - 1) / 2.0
+    elif model == "kinetic":
+        M = X.shape[1] - 1
+        v = np.median(1.0 - X[:, 1:].astype(np.float64).mean(axis=1) ** 2)
+        sigma = np.sqrt(M * v)
+        P = float(N) * (N - 1)
+    else:
+        raise KeyError(model)
+    q = float(N) if q is None else float(q)
+    return float(sigma * np.sqrt(2.0 * np.log(max(P / q, np.e))))
+
+
 # --------------------------------------------------------------- workloads --
 
 @dataclass
@@ -250,6 +292,7 @@ def config(cid: str, scale: float = 1.0) -> Workload:
     C2  Ising, random 3-regular, w~U[-0.4,0.4], N=10^4, M=1000
     C3  Gaussian, ER mean degree 4, offdiag U[-0.2,0.2], N=2*10^4, M=200
     C4  kinetic Ising, directed ER mean out-degree 5, w~N(0,0.3^2), N=10^5, T=1000
+    C4s Ising, C2's generator (random 3-regular, w~U[-0.4,0.4]) at N=10^5, M=1000
     C5  Ising, ER mean degree 3, w~N(0,0.3^2), N=10^6, M=100
     Gibbs chains: 1000 burn-in sweeps, 10 sweeps between samples, seed 0.
     """
@@ -265,6 +308,10 @@ def config(cid: str, scale: float = 1.0) -> Workload:
         return gauss_er(n(20_000), 200, 4.0, 0.2, 1e-3, name="C3")
     if cid == "C4":
         return kinetic_er(n(100_000), 1000, 5.0, 0.3, name="C4")
+    if cid == "C4s":
+        N = n(100_000)
+        N += N % 2
+        return ising_regular(N, 1000, 3, 0.4, name="C4s")
     if cid == "C5":
         return ising_er(n(1_000_000), 100, 3.0, 0.3, 0.0, name="C5")
     raise KeyError(cid)
