@@ -14,10 +14,11 @@ excluded are never counted here.
 One step = one full GCD sweep: the search for the m = kappa N best pairs, the
 coordinate updates in rank order, the field rebuild, the theta refit and the
 FP64 objective.  The timed sweeps use the screened exhaustive search, which
-returns the exhaustive top m (recall 1).  After them, the same state is swept
-once with each search (plain FindBest over NNDescent, the learned proposal,
-the gradient distance, the screen), with the model restored between them,
-and each search's recall of the exact positive-gain top m is measured.
+returns the exhaustive top m (recall 1).  Before them, the first sweep (from
+W = 0) and the second (after one screened sweep) are run once with each
+search (plain FindBest over NNDescent, the learned proposal, the gradient
+distance, the screen), the model restored between them, and each search's
+recall of the exact positive-gain top m is measured.
 
 roofline: the pair-score kernels of one rec_score_pairs call on the batch
 (k_kink + k_exact: the L1-kink decision from sign words and fp16 residuals,
@@ -75,7 +76,10 @@ BATCH_PER_NODE = 16
 # --only-batch`, each scaled by a plain 1 GiB device copy (`bench.py
 # --copy-probe 1024`: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE
 # 1.0x).  Valid only for the score kernel source it was measured on.
-TRAFFIC = {}
+TRAFFIC = {
+    "C4s": {"source_sha256": "bdb4787b37bd8893401e9e3a3f48ca5743bbccfa9d2ed46ee77ee269d5738eca",
+            "hbm_over_algorithmic": 0.9985},
+}
 
 # HBM traffic of the contraction's full pass (k_kscreen) per launch, from the
 # same kind of counter runs; valid only for the source it was measured on.
@@ -254,13 +258,18 @@ def run_workload(name, args, torch, rec, synth, headline):
     print(f"{name}: batch at W=0 {res['batch_w0']}", file=sys.stderr, flush=True)
     if args.only_batch:
         return w, lam, ctx, I, J, res, roof, None, None
-    # first sweep, then the same batch at W != 0
+    searches = args.compare.split(",")
+    if not args.no_compare:       # the first sweep from W = 0, by each search
+        res["compare_sweep1"] = compare_sweeps(ctx, torch, searches)
+    # first sweep, then the same batch at W != 0 and the searches again
     st1 = ctx.sweep(args.search)
     g1, ms1, l1, wk1 = score_batch(ctx, I, J, args.batch_reps, torch)
     res["batch_after_sweep"] = {"evals_per_s": P * args.batch_reps / (ms1 / 1e3),
                                 "ms_per_call": ms1 / max(l1, 1),
                                 "positive_gains": int((g1 > 0).sum().item()),
                                 "roofline": batch_roofline(ctx, w, ms1, l1, wk1, P, args.batch_reps)}
+    if not args.no_compare:
+        res["compare_sweep2"] = compare_sweeps(ctx, torch, searches)
     for _ in range(max(0, args.warmup - 1)):
         ctx.sweep(args.search)
     ctx.screen_time()
@@ -303,8 +312,6 @@ def run_workload(name, args, torch, rec, synth, headline):
                        "flops_per_launch": sflops,
                        "sample_pass_ms_avg": scr["sample_ms"] / max(scr["sample_launches"], 1)}
     res["roofline_contraction"] = roof_screen
-    if not args.no_compare:
-        res["compare"] = compare_sweeps(ctx, torch, args.compare.split(","))
     return w, lam, ctx, I, J, res, roof, stats, wall
 
 
