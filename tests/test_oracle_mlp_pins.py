@@ -96,3 +96,34 @@ def test_sketch_estimates_the_kink_test_value():
     assert np.allclose(S[:, 56], w.X.mean(1))
     assert np.allclose(S[:, 61], 0) and np.allclose(S[:, 62], 0)
     assert np.allclose(S[:, 63], th)
+
+
+def test_sketch_statistics_closed_forms():
+    """The statistics block against values the model fixes: at W = 0 with
+    theta fitted (Ising: tanh theta_i = xbar_i) every field equals theta_i, so
+    mean t = xbar, var t = 0, mean |h| = |atanh xbar|, mean r^2 = 1 - xbar^2
+    (r = x - xbar), no degree and no coupling mass; after setting a known W,
+    the degree and |W| columns count that W's entries per node (both ends)."""
+    w = synth.ising_er(12, 300, 3.0, 0.4, 0.1, seed=31)
+    O = oracle.Oracle(w.X, "ising", 1.0)
+    ei, ej, wv, th = O.get_model()
+    S = mlp.sketch("ising", w.X, O.fields(), th, ei, ej, wv, seed=0)
+    xb = w.X.astype(float).mean(1)
+    assert np.allclose(S[:, 57], xb, atol=1e-12)
+    assert np.allclose(S[:, 58], 0, atol=1e-12)
+    assert np.allclose(S[:, 59], np.abs(np.arctanh(xb)), atol=1e-12)
+    assert np.allclose(S[:, 60], 1 - xb ** 2, atol=1e-12)
+    I = np.array([0, 0, 3], np.int32)
+    J = np.array([5, 7, 5], np.int32)
+    V = np.array([0.5, -0.25, 0.125])
+    O.set_model(I, J, V, th)
+    ei, ej, wv, th = O.get_model()
+    S = mlp.sketch("ising", w.X, O.fields(), th, ei, ej, wv, seed=0)
+    deg = np.zeros(12)
+    mass = np.zeros(12)
+    for a, b, v in [(0, 5, 0.5), (0, 7, 0.25), (3, 5, 0.125)]:
+        deg[[a, b]] += 1
+        mass[[a, b]] += v
+    assert np.allclose(S[:, 61], np.log1p(deg)) and np.allclose(S[:, 62], mass)
+    # with couplings the fields vary across samples: var t > 0 on coupled nodes
+    assert np.all(S[[0, 3, 5, 7], 58] > 0) and np.allclose(S[[1, 2], 58], 0, atol=1e-12)

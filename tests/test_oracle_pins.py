@@ -396,21 +396,32 @@ def test_theta_closed_forms_at_w0():
     assert np.allclose(th ** 2, (G.astype(float) ** 2).mean(1), rtol=1e-12)
 
 
-@pytest.mark.parametrize("model", ["ising", "gauss"])
+@pytest.mark.parametrize("model", ["ising", "gauss", "kinetic"])
 def test_theta_update_is_stationary(model):
-    """After the update, d/dtheta_i of node i's conditional vanishes (KKT)."""
+    """After the update, d/dtheta_i of node i's conditional vanishes (KKT),
+    at a W != 0 state (kinetic: a directed W, targets x_{t}, inputs x_{t-1})."""
     rng = np.random.default_rng(12)
     N, M = 8, 90
     W = sym_sparse(rng, N, 0.5, 0.3)
-    if model == "gauss":
+    if model == "kinetic":
+        W = np.triu(W) + 0.7 * np.tril(W)     # directed: W_ij != W_ji
+        X = rand_pm1(rng, N, M + 1)
+    elif model == "gauss":
         X = rng.normal(0, 1, (N, M)).astype(np.float32)
     else:
         X = rand_pm1(rng, N, M)
     O = oracle.Oracle(X, model, 0.0)
-    O.set_model(*coo(W), None)
+    O.set_model(*coo(W, directed=model == "kinetic"), None)
     O.theta_update()
     _, _, _, th = O.get_model()
     Xd = X.astype(float)
+    if model == "kinetic":
+        msum = W @ Xd[:, :-1]
+        grad = (Xd[:, 1:] - np.tanh(th[:, None] + msum)).sum(1)
+        assert np.abs(grad).max() <= 1e-10 * M
+        # and the refit moved theta away from its W = 0 value
+        assert np.abs(th - np.arctanh(Xd[:, 1:].mean(1))).max() > 1e-3
+        return
     msum = W @ Xd
     if model == "ising":
         grad = (Xd - np.tanh(th[:, None] + msum)).sum(1)
@@ -528,13 +539,16 @@ def test_first_update_gain_is_objective_change():
     assert abs((O.objective() - L0) - G[0]) <= 1e-9 * max(1.0, G[0])
 
 
-@pytest.mark.parametrize("model", ["ising", "gauss"])
+@pytest.mark.parametrize("model", ["ising", "gauss", "kinetic"])
 def test_gcd_converges_to_kkt_point_and_matches_cd(model):
     """C-P10: the GCD fixed point is the unique optimum of the convex objective
-    (KKT over all pairs) and equals the CD optimum [Sec. 2-3]."""
+    (KKT over all coordinates: pairs, or ordered pairs for the directed
+    kinetic model) and equals the CD optimum [Sec. 2-3]."""
     N = 24
     if model == "gauss":
         w = synth.gauss_er(N, 80, 3.0, 0.2, 0.3, seed=8)   # well conditioned: fast convergence
+    elif model == "kinetic":
+        w = synth.kinetic_er(N, 300, 3.0, 0.5, seed=8)
     else:
         w = synth.ising_er(N, 150, 3.0, 0.5, 0.1, seed=8)
     lam = oracle.default_lambda(w.X, model, c=1.0)
@@ -551,8 +565,12 @@ def test_gcd_converges_to_kkt_point_and_matches_cd(model):
     ei, ej, wv, th = G.get_model()
     W = np.zeros((N, N))
     W[ei, ej] = wv
+    directed = model == "kinetic"
+    assert len(ei) > 0
     for i in range(N):
-        for j in range(i + 1, N):
+        for j in range(N):
+            if j == i or (not directed and j < i):
+                continue
             g = G.pair_deriv(i, j, W[i, j])
             if W[i, j] == 0:
                 assert abs(g) <= lam * (1 + 1e-6) + 1e-7
@@ -653,3 +671,148 @@ def test_findbest_gradient_exact_knn_equals_exhaustive(model):
         assert np.array_equal(I, I2) and np.array_equal(J, J2) and np.array_equal(G, G2)
         assert np.array_equal(G, O.grad_pairs(I, J))
         assert np.all(np.diff(G) <= 0)
+
+
+# ------------------------------------------------- NNDescent by hand ------
+#
+# One iteration of NNDescent [Alg. 4] in the order-independent form read for
+# it (the per-node parallel form of the appendix): U is the undirected
+# version of the current lists in which node b keeps its own list plus at
+# most k in-neighbours (those with the lowest 32-bit hash of the iteration
+# and the edge, R7); node a's candidates are the U-neighbours of its
+# U-neighbours, less a itself and its current list; its new list is the best
+# k of the old list and the candidates (gain desc, index asc); Delta counts
+# the entries that are new.  Written here from that description, with the
+# counter-based generator taken from the workload module (its own
+# SplitMix64), not from the oracle.
+
+def _below(r, bound):
+    return (r * bound) >> 64
+
+
+def _init_lists(S, k, seed, level, score):
+    """Floyd's sampling of k distinct others per node (R5)."""
+    n = len(S)
+    G = []
+    for a in range(n):
+        tag = (level << 32) | S[a]
+        has, chosen = set(), []
+        for t in range((n - 1) - k, n - 1):
+            v = _below(synth.ctr(seed, 5, tag, t), t + 1)
+            pick = t if v in has else v
+            has.add(pick)
+            chosen.append(pick if pick < a else pick + 1)
+        G.append(sorted(((S[b], score(S[a], S[b])) for b in chosen), key=lambda e: (-e[1], e[0])))
+    return G
+
+
+def _iterate(G, S, k, seed, level, it, score, in_cap=True, second=True):
+    n = len(S)
+    loc = {v: a for a, v in enumerate(S)}
+    inn = [[] for _ in range(n)]
+    for a in range(n):
+        for j, _ in G[a]:
+            h = synth.ctr(seed, 6, (level << 32) | it, (S[a] << 32) | j) >> 32
+            inn[loc[j]].append((h, a))
+    U = []
+    for b in range(n):
+        nb = {loc[j] for j, _ in G[b]}
+        if in_cap:
+            nb |= {a for _, a in sorted(inn[b])[:k]}
+        U.append(nb)
+    new, delta = [], 0
+    for a in range(n):
+        cur = {j for j, _ in G[a]}
+        reach = set()
+        for b in U[a]:
+            reach |= U[b] if second else {b}
+        cand = {S[c] for c in reach if c != a and S[c] not in cur}
+        allv = sorted(G[a] + [(v, score(S[a], v)) for v in cand], key=lambda e: (-e[1], e[0]))[:k]
+        delta += sum(1 for j, _ in allv if j not in cur)
+        new.append(allv)
+    return new, delta
+
+
+def _score_fn(O, N, model):
+    I, J = np.nonzero(~np.eye(N, dtype=bool))
+    g, _ = O.score_pairs(I.astype(np.int32), J.astype(np.int32))
+    D = np.zeros((N, N))
+    D[I, J] = g
+    if model == "kinetic":      # unordered search score: the better direction
+        D = np.maximum(D, D.T)
+    return lambda a, b: float(D[a, b])
+
+
+@pytest.mark.parametrize("model", ["ising", "kinetic"])
+def test_nndescent_iterations_by_hand(model):
+    """The oracle's NNDescent lists after one and two iterations, and its
+    Delta, equal the hand-written iteration above on a 12-node subset of a
+    16-node problem (k = 3, so the in-neighbour cap binds); a version without
+    the capped in-neighbours, or with first neighbours only, gives different
+    lists on the same instance."""
+    if model == "kinetic":
+        w = synth.kinetic_er(16, 300, 3.0, 0.4, seed=21)
+    else:
+        w = synth.ising_er(16, 300, 3.0, 0.4, 0.1, seed=21)
+    O = oracle.Oracle(w.X, model, oracle.default_lambda(w.X, model))
+    score = _score_fn(O, w.N, model)
+    S = [0, 1, 2, 4, 5, 7, 8, 10, 11, 12, 14, 15]
+    n, k, seed, level = len(S), 3, 9, 2
+    G0 = _init_lists(S, k, seed, level, score)
+    for a in range(n):
+        assert sorted(b for b, _ in G0[a]) == sorted(S[c] for c in oracle.knn_init(n, a, k, seed, level, S[a]))
+    G1, d1 = _iterate(G0, S, k, seed, level, 0, score)
+    G2, d2 = _iterate(G1, S, k, seed, level, 1, score)
+    for t, Gh in ((1, G1), (2, G2)):
+        nbr, g, it = O.knn(np.array(S, np.int32), k, "nndescent", seed=seed, level=level, eps=0.0, max_iter=t)
+        assert it == t
+        assert [[j for j, _ in row] for row in Gh] == nbr.tolist()
+        assert np.array_equal(np.array([[v for _, v in row] for row in Gh]), g)
+    # Delta of the first iteration decides when the loop stops (Delta < eps k n)
+    assert d1 >= 1
+    _, _, it = O.knn(np.array(S, np.int32), k, "nndescent", seed=seed, level=level,
+                     eps=(d1 + 0.5) / (k * n), max_iter=5)
+    assert it == 1
+    _, _, it = O.knn(np.array(S, np.int32), k, "nndescent", seed=seed, level=level,
+                     eps=(d1 - 0.5) / (k * n), max_iter=5)
+    assert it >= 2
+    # the instance tells the plausible slips apart
+    Gx, _ = _iterate(G0, S, k, seed, level, 0, score, in_cap=False)
+    Gy, _ = _iterate(G0, S, k, seed, level, 0, score, second=False)
+    assert Gx != G1 and Gy != G1
+
+
+def test_nndescent_with_k_n_minus_1_is_exact():
+    """k = n - 1: the lists hold every other node, so NNDescent returns the
+    exact KNN lists (and finds nothing new to add)."""
+    w = synth.ising_er(20, 200, 3.0, 0.4, 0.1, seed=22)
+    O = oracle.Oracle(w.X, "ising", oracle.default_lambda(w.X, "ising"))
+    S = np.arange(20, dtype=np.int32)
+    nbr, g, it = O.knn(S, 19, "nndescent", seed=3, eps=0.0, max_iter=1)
+    nbr_e, g_e, _ = O.knn(S, 19, "exact")
+    assert np.array_equal(nbr, nbr_e) and np.array_equal(g, g_e)
+
+
+@pytest.mark.parametrize("model", ["ising", "kinetic"])
+def test_nndescent_kth_key_never_worsens(model):
+    """Each node's list only improves across iterations: its k-th key
+    (gain desc, index asc) never gets worse, and every entry of the next list
+    is at least as good as the current k-th."""
+    if model == "kinetic":
+        w = synth.kinetic_er(120, 200, 4.0, 0.3, seed=23)
+    else:
+        w = synth.ising_er(120, 200, 3.0, 0.4, 0.1, seed=23)
+    O = oracle.Oracle(w.X, model, oracle.default_lambda(w.X, model))
+    S = np.arange(120, dtype=np.int32)
+    k = 6
+    prev = None
+    for t in range(1, 7):
+        nbr, g, _ = O.knn(S, k, "nndescent", seed=5, eps=0.0, max_iter=t)
+        if prev is not None:
+            pn, pg = prev
+            for a in range(len(S)):
+                kth_prev = (-pg[a, -1], pn[a, -1])
+                assert (-g[a, -1], nbr[a, -1]) <= kth_prev
+                for c in range(k):
+                    assert (-g[a, c], nbr[a, c]) <= kth_prev
+        prev = (nbr, g)
