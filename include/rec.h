@@ -144,6 +144,21 @@ rec_status rec_destroy(rec_ctx* ctx);
 rec_status rec_score_pairs(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
                            double* gain_dev, double* wopt_dev);
 
+/* rec_score_pairs without any workspace scratch, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same kernels and the same results bit for bit, but
+ * the per-call scratch (the kink screen's queue and counter, the error flags)
+ * is a file-scope static device array of 4 MiB + 256 bytes that each GPU the
+ * library runs on holds until the process ends; its address is looked up once
+ * per device by rec_create().  At most 2^20 pairs per call (REC_E_INVAL
+ * beyond).  Clears what must start at zero with a kernel (no memset), queues
+ * no timing events and counts no work.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (several streams or threads)
+ * race and must be serialised by the caller.  Arguments, layout, ownership
+ * and errors as rec_score_pairs; also synchronises the stream at the end. */
+rec_status rec_score_pairs_noalloc(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
+                                   double* gain_dev, double* wopt_dev);
+
 /* Gradient distance of P pairs at the current state [Appendix, "Gradient as
  * distance"]: dist_dev[p] = |dpi/dW_ij| taken as a central difference at the
  * L1 kink, i.e. |F'(w0) - lambda sign(w0)| for a current coupling w0 != 0 and

@@ -26,7 +26,7 @@ SYMBOLS = ["rec_workspace_size", "rec_create", "rec_destroy", "rec_score_pairs",
            "rec_get_model", "rec_set_model", "rec_get_fields", "rec_knn", "rec_set_timing",
            "rec_kernel_time", "rec_status_str", "rec_last_error", "rec_sketch", "rec_mlp_params",
            "rec_mlp_infer", "rec_mlp_grad", "rec_mlp_train", "rec_surrogate_config",
-           "rec_surrogate_stats", "rec_screen_time", "rec_grad_pairs"]
+           "rec_surrogate_stats", "rec_screen_time", "rec_grad_pairs", "rec_score_pairs_noalloc"]
 SUR_NPARAM = 41345
 SUR_SKETCH_DIM = 64
 SUR_MAX_BATCH = 8192
@@ -76,6 +76,7 @@ def lib():
             "rec_create": [ctypes.POINTER(RecConfig), vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
             "rec_destroy": [vp],
             "rec_score_pairs": [vp, i64, vp, vp, vp, vp],
+            "rec_score_pairs_noalloc": [vp, i64, vp, vp, vp, vp],
             "rec_grad_pairs": [vp, i64, vp, vp, vp],
             "rec_find_best_candidates": [vp, i64, i32, vp, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(SweepStats)],
             "rec_gcd_sweep": [vp, i32, ctypes.POINTER(SweepStats)],
@@ -201,6 +202,17 @@ class Context:
         g = t.empty(len(I), dtype=t.float64, device=self.device)
         w = t.empty(len(I), dtype=t.float64, device=self.device)
         self._check(lib().rec_score_pairs(self.h, len(I), _ptr(I), _ptr(J), _ptr(g), _ptr(w)), self.h)
+        return g, w
+
+    def score_pairs_noalloc(self, I, J, gain=None, wopt=None):
+        """rec_score_pairs_noalloc: the same scores with the library's static
+        scratch (at most 2^20 pairs); writes into gain / wopt when given."""
+        t = self.torch
+        I, J = self._i32(I), self._i32(J)
+        g = gain if gain is not None else t.empty(len(I), dtype=t.float64, device=self.device)
+        w = wopt if wopt is not None else t.empty(len(I), dtype=t.float64, device=self.device)
+        self._check(lib().rec_score_pairs_noalloc(self.h, len(I), _ptr(I), _ptr(J), _ptr(g), _ptr(w)),
+                    self.h)
         return g, w
 
     def grad_pairs(self, I, J):

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -328,6 +329,38 @@ rec_status rec_workspace_size(const rec_config* cfg, size_t* bytes) {
   return REC_OK;
 }
 
+// ---- static scratch of rec_score_pairs_noalloc ----
+// Layout: [0, 8) the kink screen's queue counter, [8, 24) error flags,
+// [256, 256 + 4 REC_NOALLOC_MAX_PAIRS) the queue (one 32-bit entry per pair).
+// Each device holds its own copy for the life of the process.
+constexpr int64_t REC_NOALLOC_MAX_PAIRS = int64_t(1) << 20;
+constexpr size_t REC_NOALLOC_BYTES = 256 + 4 * (size_t)REC_NOALLOC_MAX_PAIRS;
+static __device__ __align__(256) unsigned char scratch[REC_NOALLOC_BYTES];
+
+namespace {
+constexpr int REC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[REC_MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device (the host-side name is not a device address).
+rec_status scratch_for_current_device(int dev, void** out) {
+  if (dev < 0 || dev >= REC_MAX_DEVICES) return REC_E_INVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return REC_E_HIP;
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return REC_OK;
+}
+
+__global__ void k_zero_scratch_head(int64_t* p) {
+  if (threadIdx.x < 3) p[threadIdx.x] = 0;   // counter and the 16 bytes of error flags
+}
+}  // namespace
+
 rec_status rec_create(const rec_config* cfg, const void* X_dev, void* ws_dev, size_t ws_bytes,
                       void* stream, rec_ctx** out) {
   if (!cfg || !X_dev || !ws_dev || !out) return REC_E_INVAL;
@@ -344,6 +377,10 @@ rec_status rec_create(const rec_config* cfg, const void* X_dev, void* ws_dev, si
   ctx->fp32 = cfg->prec == REC_FP32;
   ctx->m_default = z.m;
   if (hipGetDevice(&ctx->dev) != hipSuccess) { delete ctx; return REC_E_HIP; }
+  if (scratch_for_current_device(ctx->dev, &ctx->noalloc_scratch) != REC_OK) {
+    delete ctx;
+    return REC_E_HIP;
+  }
   Arena a;
   a.base = (char*)(((uintptr_t)ws_dev + 255) & ~uintptr_t(255));
   a.size = ws_bytes - (size_t)(a.base - (char*)ws_dev);
@@ -401,6 +438,30 @@ rec_status rec_score_pairs(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const 
   int32_t e = 0;
   REC_TRY(read_err(ctx, &e));
   if (e & 1) return fail(ctx, REC_E_INVAL, "pair index out of range or i == j");
+  return REC_OK;
+}
+
+rec_status rec_score_pairs_noalloc(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
+                                   double* gain_dev, double* wopt_dev) {
+  REC_CHECK_CTX(ctx);
+  if (P < 0 || (P > 0 && (!i_dev || !j_dev || !gain_dev))) return fail(ctx, REC_E_INVAL, "bad arguments");
+  if (P > REC_NOALLOC_MAX_PAIRS)
+    return fail(ctx, REC_E_INVAL, "P exceeds the static scratch of rec_score_pairs_noalloc (2^20 pairs per call)");
+  if (P == 0) return REC_OK;
+  char* base = static_cast<char*>(ctx->noalloc_scratch);
+  if (!base) return fail(ctx, REC_E_STATE, "static scratch not set up for this device");
+  int64_t* head = reinterpret_cast<int64_t*>(base);
+  int32_t* err = reinterpret_cast<int32_t*>(base + 8);
+  hipLaunchKernelGGL(k_zero_scratch_head, dim3(1), dim3(64), 0, ctx->stream, head);
+  const ScoreScratch ss{reinterpret_cast<uint32_t*>(base + 256), head, REC_NOALLOC_MAX_PAIRS, err,
+                        nullptr, true};
+  REC_TRY(rec_launch_score_with(ctx, P, i_dev, j_dev, gain_dev, wopt_dev, ss));
+  REC_HIP(hipGetLastError());
+  int32_t e = 0;
+  REC_HIP(hipMemcpyAsync(&e, err, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  REC_HIP(hipStreamSynchronize(ctx->stream));
+  if (e & 1) return fail(ctx, REC_E_INVAL, "pair index out of range or i == j");
+  if (e & 512) return fail(ctx, REC_E_HIP, "static queue overflow");
   return REC_OK;
 }
 

@@ -82,6 +82,7 @@ struct rec_ctx {
   rec_config cfg;
   hipStream_t stream;
   int dev;
+  void* noalloc_scratch = nullptr;   // this device's address of the static scratch
   rec_status state = REC_OK;
   std::string err;
   bool fp32;
@@ -235,6 +236,22 @@ rec_status rec_wtable_insert_list(rec_ctx* ctx, int64_t n, const int32_t* ei, co
 // cache overflow area for slots >= cache capacity when cache != null).
 // Number of leading positive entries of the descending array g[0, n) (synchronises).
 rec_status rec_positive_prefix(rec_ctx* ctx, const double* g, int64_t n, int64_t* np);
+
+// Per-call scratch of the pair-score kernels: the queue of sides the kink
+// screen leaves to the exact solver and its counter, the error flags and the
+// work counters (may be null).  By default it is carved from the workspace.
+struct ScoreScratch {
+  uint32_t* queue;
+  int64_t* qn;
+  int64_t qcap;
+  int32_t* err;
+  int64_t* work;
+  bool fill;   // clear qn with a fill kernel (no memset node) instead of hipMemsetAsync
+};
+// Score pairs (I, J) into gain_out / w_out with the given scratch, without
+// timing events.
+rec_status rec_launch_score_with(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
+                                 double* gain_out, double* w_out, const ScoreScratch& ss);
 rec_status rec_launch_score(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
                             const uint32_t* slot, double* gain_out, double* w_out,
                             const Cache* cache);

@@ -1222,10 +1222,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
 }
 
+// One 64-bit counter to zero (a kernel node, not a memset node, in a captured graph).
+__global__ void k_zero_i64(int64_t* p) { *p = 0; }
+
 template <class R, int MODEL>
 rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
                           const int32_t* Smap, const uint32_t* slot, int owned, double* gain_out,
-                          double* w_out, const Cache* C) {
+                          double* w_out, const Cache* C, const ScoreScratch& ss) {
   // pairs per wave: owner mode reads 64 candidates, of which only the owned
   // (new) pairs are scored: most candidates after the first iteration are cache hits
   const int ppw = owned ? 64 : 8;
@@ -1233,12 +1236,12 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
   int64_t blocks = (waves * REC_WAVE + 255) / 256;
   double* ovf = C ? C->ovf : nullptr;
   uint64_t cap = C ? (C->mask + 1) : 0;
-  int64_t* ev = ctx->work;
+  int64_t* ev = ss.work;
   if constexpr (MODEL == REC_ISING || MODEL == REC_KINSYM) {
     // settled sides in k_kink, the queue of the rest in k_exact (chunks of at
     // most the queue's capacity)
-    int64_t* qn = ctx->counter + 13;
-    const int64_t qcap = ctx->scr_qcap;
+    int64_t* qn = ss.qn;
+    const int64_t qcap = ss.qcap;
     const int64_t exact_blocks = 2048;
     for (int64_t c0 = 0; c0 < P; c0 += qcap) {
       const int64_t pc = P - c0 < qcap ? P - c0 : qcap;
@@ -1250,14 +1253,15 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
       const uint32_t* sc = slot ? slot + c0 : nullptr;
       double* gc = slot ? gain_out : gain_out + c0;
       double* wc = w_out ? w_out + c0 : nullptr;
-      REC_HIP(hipMemsetAsync(qn, 0, sizeof(int64_t), ctx->stream));
+      if (ss.fill) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, ctx->stream, qn);
+      else REC_HIP(hipMemsetAsync(qn, 0, sizeof(int64_t), ctx->stream));
 #define REC_SC(NPL)                                                                              \
       hipLaunchKernelGGL((k_kink<R, NPL, MODEL>), dim3(cb), dim3(256), 0, ctx->stream, ctx->F,   \
-                         ctx->W, pc, Ic, Jc, Smap, sc, owned, gc, wc, ovf, cap, ctx->err_flag,   \
-                         ppw, groups, ctx->scr_queue, qn, qcap, ev);                             \
+                         ctx->W, pc, Ic, Jc, Smap, sc, owned, gc, wc, ovf, cap, ss.err,          \
+                         ppw, groups, ss.queue, qn, qcap, ev);                                   \
       hipLaunchKernelGGL((k_exact<R, NPL, MODEL>), dim3(exact_blocks), dim3(256), 0, ctx->stream, \
                          ctx->F, ctx->W, ctx->cfg.lambda, Ic, Jc, Smap, sc, gc, wc, ovf, cap,    \
-                         ctx->scr_queue, qn, qcap, ev)
+                         ss.queue, qn, qcap, ev)
       switch (ctx->F.npl) {
         case 1: REC_SC(1); break;
         case 2: REC_SC(2); break;
@@ -1275,7 +1279,7 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
 #define REC_SC(NPL)                                                                              \
   hipLaunchKernelGGL((k_score<R, NPL, MODEL>), dim3(blocks), dim3(256), 0, ctx->stream,          \
                      ctx->F, ctx->W, ctx->cfg.lambda, P, I, J, Smap, slot, owned, gain_out,      \
-                     w_out, ovf, cap, ctx->err_flag, ppw, ev)
+                     w_out, ovf, cap, ss.err, ppw, ev)
   switch (ctx->F.npl) {
     case 1: REC_SC(1); break;
     case 2: REC_SC(2); break;
@@ -1340,7 +1344,7 @@ rec_status launch_grad_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_
 template <class R>
 rec_status launch_score_r(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
                           const int32_t* Smap, const uint32_t* slot, int owned, double* g,
-                          double* w, const Cache* C) {
+                          double* w, const Cache* C, const ScoreScratch& ss) {
   if (ctx->grad_dist) {   // search under the gradient distance (no w*)
     switch (ctx->cfg.model) {
       case REC_ISING: return launch_grad_m<R, REC_ISING>(ctx, P, I, J, Smap, slot, owned, g, C);
@@ -1352,11 +1356,11 @@ rec_status launch_score_r(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
     return REC_E_INVAL;
   }
   switch (ctx->cfg.model) {
-    case REC_ISING: return launch_score_m<R, REC_ISING>(ctx, P, I, J, Smap, slot, owned, g, w, C);
-    case REC_GAUSS: return launch_score_m<R, REC_GAUSS>(ctx, P, I, J, Smap, slot, owned, g, w, C);
+    case REC_ISING: return launch_score_m<R, REC_ISING>(ctx, P, I, J, Smap, slot, owned, g, w, C, ss);
+    case REC_GAUSS: return launch_score_m<R, REC_GAUSS>(ctx, P, I, J, Smap, slot, owned, g, w, C, ss);
     case REC_KINETIC:
-      if (ctx->sym_search) return launch_score_m<R, REC_KINSYM>(ctx, P, I, J, Smap, slot, owned, g, w, C);
-      return launch_score_m<R, REC_KINETIC>(ctx, P, I, J, Smap, slot, owned, g, w, C);
+      if (ctx->sym_search) return launch_score_m<R, REC_KINSYM>(ctx, P, I, J, Smap, slot, owned, g, w, C, ss);
+      return launch_score_m<R, REC_KINETIC>(ctx, P, I, J, Smap, slot, owned, g, w, C, ss);
   }
   return REC_E_INVAL;
 }
@@ -1427,6 +1431,14 @@ rec_status rec_launch_score_owned(rec_ctx* ctx, int64_t P, const int32_t* gi, co
   return launch_score_any(ctx, P, gi, v, S, slot, 1, cache->vals, nullptr, cache);
 }
 
+rec_status rec_launch_score_with(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
+                                 double* gain_out, double* w_out, const ScoreScratch& ss) {
+  if (P <= 0) return REC_OK;
+  if (ctx->grad_dist) return REC_E_INVAL;
+  return ctx->fp32 ? launch_score_r<float>(ctx, P, I, J, nullptr, nullptr, 0, gain_out, w_out, nullptr, ss)
+                   : launch_score_r<double>(ctx, P, I, J, nullptr, nullptr, 0, gain_out, w_out, nullptr, ss);
+}
+
 namespace {
 rec_status launch_score_any(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
                             const int32_t* Smap, const uint32_t* slot, int owned,
@@ -1445,9 +1457,10 @@ rec_status launch_score_any(rec_ctx* ctx, int64_t P, const int32_t* I, const int
     }
     REC_HIP(hipEventRecord(ctx->ev[ctx->ev_used].first, ctx->stream));
   }
+  const ScoreScratch ss{ctx->scr_queue, ctx->counter + 13, ctx->scr_qcap, ctx->err_flag, ctx->work, false};
   rec_status st = ctx->fp32
-                      ? launch_score_r<float>(ctx, P, I, J, Smap, slot, owned, gain_out, w_out, cache)
-                      : launch_score_r<double>(ctx, P, I, J, Smap, slot, owned, gain_out, w_out, cache);
+                      ? launch_score_r<float>(ctx, P, I, J, Smap, slot, owned, gain_out, w_out, cache, ss)
+                      : launch_score_r<double>(ctx, P, I, J, Smap, slot, owned, gain_out, w_out, cache, ss);
   if (ctx->timing && st == REC_OK) {
     REC_HIP(hipEventRecord(ctx->ev[ctx->ev_used].second, ctx->stream));
     ++ctx->ev_used;
