@@ -121,17 +121,25 @@ typedef struct {
 /* Bytes of workspace the library needs for cfg.  Host-only; no device work. */
 rec_status rec_workspace_size(const rec_config* cfg, size_t* bytes);
 
-/* Create a context on the current HIP device.  X_dev: node-major data
- * (int8 +-1 or float32, see cfg->xtype) with row stride cfg->ldx; it is copied
- * into the workspace (padded layout), so X_dev may be freed after the call.
+/* Create a context on the current HIP device: the reconstruction problem of
+ * [Sec. 2] (N x M data X of M samples, or of a time series [Sec. 2, Markov
+ * product form]; unknown W and theta) with the objective of [App. A] (log
+ * pseudolikelihood of the chosen model plus the Laplace prior of weight
+ * lambda on W).  X_dev: node-major data (int8 +-1 or float32, see cfg->xtype)
+ * with row stride cfg->ldx; it is copied into the workspace (padded layout),
+ * so X_dev may be freed after the call.
  * ws_dev: at least rec_workspace_size() bytes, 256-byte aligned.
  * stream: the hipStream_t to queue all work on (NULL = default stream).
- * Fits theta at W = 0 (the W = 0 optimum of every node's conditional).
- * Synchronises the stream.  REC_E_NUMERIC if X holds a value other than +-1
- * (int8 models) or a non-finite value (float32). */
+ * Starts from W = 0 [Alg. 2, initial state] with theta at the W = 0 optimum of
+ * every node's conditional (theta is fitted alongside W [App. A]).  Also looks
+ * up, once per device, the address of the static scratch used by
+ * rec_score_pairs_noalloc.  Synchronises the stream.  REC_E_NUMERIC if X holds
+ * a value other than +-1 (int8 models) or a non-finite value (float32). */
 rec_status rec_create(const rec_config* cfg, const void* X_dev, void* ws_dev, size_t ws_bytes,
                       void* stream, rec_ctx** out);
 
+/* Release the context's host-side state.  The workspace and X belong to the
+ * caller and are not touched; queued work must have finished. */
 rec_status rec_destroy(rec_ctx* ctx);
 
 /* Exact scores of P pairs at the current state [Alg. 2, function D]:
@@ -203,14 +211,23 @@ rec_status rec_theta_update(rec_ctx* ctx, double* objective_host);
 /* log pi(W) at the current state (FP64 sum).  Synchronises. */
 rec_status rec_objective(rec_ctx* ctx, double* objective_host);
 
-/* Export the model: nonzero W entries (symmetric: i < j) into ei/ej/w
- * (capacity cap) and theta (N doubles, may be NULL).  *nnz_host receives the
- * number of nonzero entries (which may exceed cap).  Synchronises. */
+/* Export the model [Sec. 2: the reconstruction is the pair (W, theta); App. A:
+ * theta_i = 1/sqrt(W_ii) for the Gaussian model, the field of node i for the
+ * Ising models]: nonzero W entries (symmetric: i < j; kinetic: ei = target,
+ * ej = source) into ei/ej/w (capacity cap, sorted by (ei, ej)) and theta
+ * (N doubles, may be NULL).  *nnz_host receives the number of nonzero entries
+ * (which may exceed cap).  Synchronises. */
 rec_status rec_get_model(rec_ctx* ctx, int64_t cap, int32_t* ei_dev, int32_t* ej_dev,
                          double* w_dev, double* theta_dev, int64_t* nnz_host);
 
-/* Replace the model (W entries and theta; theta_dev NULL keeps theta) and
- * rebuild the fields.  Clears REC_E_STATE.  Synchronises. */
+/* Replace the model (W entries and theta [Sec. 2; App. A], as rec_get_model
+ * writes them; theta_dev NULL keeps theta) and rebuild the local fields from
+ * them (h_i = theta_i + sum_j W_ij x_j [App. A]), so that
+ * rec_set_model(rec_get_model()) restores the state bit for bit.  For resuming,
+ * or for starting from a model computed elsewhere.  Entries must have
+ * distinct coordinates with finite weights (REC_E_INVAL; the context is then
+ * left in REC_E_STATE); more than cfg.max_nnz entries give REC_E_NOMEM.
+ * Clears REC_E_STATE.  Synchronises. */
 rec_status rec_set_model(rec_ctx* ctx, int64_t nnz, const int32_t* ei_dev, const int32_t* ej_dev,
                          const double* w_dev, const double* theta_dev);
 
