@@ -204,6 +204,23 @@ rec_status rec_gcd_sweep(rec_ctx* ctx, int32_t search, rec_sweep_stats* stats_ho
 rec_status rec_apply_updates(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const int32_t* j_dev,
                              double* delta_host);
 
+/* One sweep of the coordinate-descent baseline [Alg. 1]: every coordinate
+ * W_ij set to its argmax at the current state, each once, then theta refitted
+ * for all nodes, the fields rebuilt from W and the objective evaluated, as at
+ * the end of rec_gcd_sweep.  The paper leaves the visiting order open; here it
+ * is the round-robin (circle method) order: with n = N rounded up to even
+ * (node n - 1 a phantom when N is odd), round r = 0..n-2 visits the pairs
+ * (r, n - 1) and ((r + k) mod (n - 1), (r - k) mod (n - 1)), k = 1..n/2 - 1;
+ * a round's pairs share no node, so each round runs as one parallel launch and
+ * gives the sequential result.  Symmetric models update the pair (min, max);
+ * the kinetic model both ordered couplings (a <- b), then (b <- a).
+ * stats_host (may be NULL): objective, delta = sum |dW|, accepted = changed
+ * couplings, n_best = pair_evals = coordinates visited, rounds = n - 1,
+ * t_update_ms (the rounds), t_theta_ms.  O(N^2 M) work per sweep.
+ * REC_E_NOMEM if the couplings outgrow cfg.max_nnz (the context is then left
+ * in REC_E_STATE).  Synchronises. */
+rec_status rec_cd_sweep(rec_ctx* ctx, rec_sweep_stats* stats_host);
+
 /* Refit theta for all nodes, rebuild fields from W and return log pi(W)
  * [App. A].  Synchronises. */
 rec_status rec_theta_update(rec_ctx* ctx, double* objective_host);

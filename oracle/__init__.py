@@ -98,6 +98,7 @@ def _L():
             "orc_apply_updates": (dbl, [vp, i64, vp, vp, ci, vp]),
             "orc_gcd_sweep": (dbl, [vp, i64, ci, u64, dbl, ci, vp, vp]),
             "orc_cd_sweep": (dbl, [vp]),
+            "orc_cd_sweep_order": (dbl, [vp, ci]),
             "orc_lcosh": (dbl, [dbl]),
             "orc_dlcosh": (dbl, [dbl, dbl]),
             "orc_ctr": (u64, [u64, u64, u64, u64]),
@@ -253,8 +254,11 @@ class Oracle:
             self._dist("gain")
         return d, float(obj[0])
 
-    def cd_sweep(self):
-        return _L().orc_cd_sweep(self.h)
+    def cd_sweep(self, order="rows"):
+        """One CD sweep [Alg. 1] (every coordinate once, then theta); order
+        "rows" (index order) or "round_robin" (the node-disjoint rounds of the
+        circle method).  Returns sum |dW|."""
+        return _L().orc_cd_sweep_order(self.h, {"rows": 0, "round_robin": 1}[order])
 
 
 def knn_init(n, a, k, seed, level, gid):

@@ -864,21 +864,51 @@ double orc_gcd_sweep(void* h, int64_t m, int mode, uint64_t seed, double eps, in
   return delta;
 }
 
-// One CD sweep [Alg. 1]: every pair once in index order, then theta.
-double orc_cd_sweep(void* h) {
+// One CD sweep [Alg. 1]: every coordinate once, then theta.  The paper leaves
+// the visiting order open.  order 0: index order (i, then j).  order 1:
+// round-robin rounds (the circle method): with n = N rounded up to even and
+// node n - 1 a phantom when N is odd, round r = 0..n-2 pairs r with n - 1 and
+// (r + k) mod (n - 1) with (r - k) mod (n - 1) for k = 1..n/2 - 1, in that
+// order of k; every unordered pair appears in exactly one round, and a
+// round's pairs share no node.  Symmetric models update the pair (min, max);
+// the kinetic model updates both ordered couplings of the pair, (a <- b) then
+// (b <- a), with a the first node listed above.
+double orc_cd_sweep_order(void* h, int order) {
   Problem& P = *(Problem*)h;
   double delta = 0.0;
-  for (int i = 0; i < P.N; ++i)
-    for (int j = 0; j < P.N; ++j) {
-      if (i == j || (P.model != KINETIC && j < i)) continue;
-      double g, w;
-      pair_gain(P, i, j, &g, &w);
-      delta += std::fabs(w - P.w(i, j));
-      set_w(P, i, j, w);
-    }
+  auto visit = [&](int i, int j) {
+    double g, w;
+    pair_gain(P, i, j, &g, &w);
+    delta += std::fabs(w - P.w(i, j));
+    set_w(P, i, j, w);
+  };
+  if (order == 0) {
+    for (int i = 0; i < P.N; ++i)
+      for (int j = 0; j < P.N; ++j) {
+        if (i == j || (P.model != KINETIC && j < i)) continue;
+        visit(i, j);
+      }
+  } else {
+    const int64_t n = P.N + (P.N & 1);
+    for (int64_t r = 0; r + 1 < n; ++r)
+      for (int64_t k = 0; k < n / 2; ++k) {
+        int64_t a, b;
+        if (k == 0) { a = r; b = n - 1; }
+        else { a = (r + k) % (n - 1); b = (r - k + (n - 1)) % (n - 1); }
+        if (a >= P.N || b >= P.N) continue;   // the phantom node
+        if (P.model == KINETIC) {
+          visit((int)a, (int)b);
+          visit((int)b, (int)a);
+        } else {
+          visit((int)std::min(a, b), (int)std::max(a, b));
+        }
+      }
+  }
   theta_update(P);
   return delta;
 }
+
+double orc_cd_sweep(void* h) { return orc_cd_sweep_order(h, 0); }
 
 // Search distance: 0 the exact gain, 1 the absolute gradient (pair_grad).
 void orc_set_dist(void* h, int dist) { ((Problem*)h)->dist = dist; }

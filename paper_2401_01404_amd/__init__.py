@@ -26,7 +26,8 @@ SYMBOLS = ["rec_workspace_size", "rec_create", "rec_destroy", "rec_score_pairs",
            "rec_get_model", "rec_set_model", "rec_get_fields", "rec_knn", "rec_set_timing",
            "rec_kernel_time", "rec_status_str", "rec_last_error", "rec_sketch", "rec_mlp_params",
            "rec_mlp_infer", "rec_mlp_grad", "rec_mlp_train", "rec_surrogate_config",
-           "rec_surrogate_stats", "rec_screen_time", "rec_grad_pairs", "rec_score_pairs_noalloc"]
+           "rec_surrogate_stats", "rec_screen_time", "rec_grad_pairs", "rec_score_pairs_noalloc",
+           "rec_cd_sweep"]
 SUR_NPARAM = 41345
 SUR_SKETCH_DIM = 64
 SUR_MAX_BATCH = 8192
@@ -80,6 +81,7 @@ def lib():
             "rec_grad_pairs": [vp, i64, vp, vp, vp],
             "rec_find_best_candidates": [vp, i64, i32, vp, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(SweepStats)],
             "rec_gcd_sweep": [vp, i32, ctypes.POINTER(SweepStats)],
+            "rec_cd_sweep": [vp, ctypes.POINTER(SweepStats)],
             "rec_apply_updates": [vp, i64, vp, vp, ctypes.POINTER(dbl)],
             "rec_theta_update": [vp, ctypes.POINTER(dbl)],
             "rec_objective": [vp, ctypes.POINTER(dbl)],
@@ -238,6 +240,12 @@ class Context:
     def sweep(self, search: str = "nndescent"):
         st = SweepStats()
         self._check(lib().rec_gcd_sweep(self.h, SEARCH[search], ctypes.byref(st)), self.h)
+        return st.as_dict()
+
+    def cd_sweep(self):
+        """One coordinate-descent sweep [Alg. 1] in round-robin order."""
+        st = SweepStats()
+        self._check(lib().rec_cd_sweep(self.h, ctypes.byref(st)), self.h)
         return st.as_dict()
 
     def apply_updates(self, I, J):

@@ -116,6 +116,7 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   x->work = a.take<int64_t>(REC_WORK_N * REC_WORK_COPIES);
   x->dscratch = a.take<double>(std::max<int64_t>(N, 1024));
   x->dresult = a.take<double>(16);
+  x->cd_acc = a.take<double>(N / 2 + 1);
   x->err_flag = a.take<int32_t>(4);
   for (int b = 0; b < 2; ++b) {
     x->sb.khi[b] = a.take<uint64_t>(z.sort_cap);
@@ -560,6 +561,47 @@ rec_status rec_gcd_sweep(rec_ctx* ctx, int32_t search, rec_sweep_stats* st) {
   S.t_update_ms = t2 - t1;
   S.t_theta_ms = t3 - t2;
   if (st) *st = S;
+  return REC_OK;
+}
+
+rec_status rec_cd_sweep(rec_ctx* ctx, rec_sweep_stats* st) {
+  REC_CHECK_CTX(ctx);
+  REC_TRY(clear_err(ctx));
+  const int64_t N = ctx->cfg.N, n = N + (N & 1);
+  double t0 = now_ms();
+  REC_HIP(hipMemsetAsync(ctx->cd_acc, 0, sizeof(double) * (n / 2), ctx->stream));
+  int64_t* changes = ctx->counter + 6;
+  REC_HIP(hipMemsetAsync(changes, 0, sizeof(int64_t), ctx->stream));
+  ++ctx->w_version;   // the rounds write W
+  for (int64_t r = 0; r + 1 < n; ++r) {
+    rec_status s = rec_launch_cd_round(ctx, r, n, ctx->cd_acc, changes);
+    if (s != REC_OK) { ctx->state = REC_E_STATE; return s; }
+  }
+  REC_TRY(rec_sum_device(ctx, ctx->cd_acc, n / 2, ctx->dresult + 3));
+  double delta = 0.0;
+  int64_t acc = 0;
+  REC_HIP(hipMemcpyAsync(&delta, ctx->dresult + 3, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  REC_HIP(hipMemcpyAsync(&acc, changes, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+  int32_t e = 0;
+  REC_TRY(read_err(ctx, &e));
+  if (e & 2) { ctx->state = REC_E_STATE; return fail(ctx, REC_E_NOMEM, "W table full"); }
+  double t1 = now_ms();
+  double obj = 0.0;
+  rec_status s = refresh(ctx, &obj);
+  if (s != REC_OK) { ctx->state = REC_E_STATE; return s; }
+  double t2 = now_ms();
+  if (st) {
+    rec_sweep_stats S{};
+    S.objective = obj;
+    S.delta = delta;
+    S.accepted = acc;
+    S.n_best = ctx->cfg.model == REC_KINETIC ? N * (N - 1) : N * (N - 1) / 2;
+    S.pair_evals = S.n_best;
+    S.rounds = n - 1;
+    S.t_update_ms = t1 - t0;
+    S.t_theta_ms = t2 - t1;
+    *st = S;
+  }
   return REC_OK;
 }
 

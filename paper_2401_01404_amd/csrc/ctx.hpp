@@ -83,6 +83,7 @@ struct rec_ctx {
   hipStream_t stream;
   int dev;
   void* noalloc_scratch = nullptr;   // this device's address of the static scratch
+  double* cd_acc = nullptr;          // CD sweep: |dW| per round-robin pair slot (N/2 + 1)
   rec_status state = REC_OK;
   std::string err;
   bool fp32;
@@ -234,6 +235,10 @@ rec_status rec_wtable_insert_list(rec_ctx* ctx, int64_t n, const int32_t* ei, co
 // score.hip
 // Score pairs (I[p], J[p]); results to gain_out[slot ? slot[p] : p] (and the
 // cache overflow area for slots >= cache capacity when cache != null).
+// Round r of a round-robin CD sweep over n (even) nodes [Alg. 1]; acc: n/2
+// doubles of |dW| per pair slot, changes: count of changed couplings.
+rec_status rec_launch_cd_round(rec_ctx* ctx, int64_t r, int64_t n, double* acc, int64_t* changes);
+
 // Number of leading positive entries of the descending array g[0, n) (synchronises).
 rec_status rec_positive_prefix(rec_ctx* ctx, const double* g, int64_t n, int64_t* np);
 

@@ -1090,6 +1090,93 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     update_pair<R, NPL, MODEL>(F, W, lambda, ready[q], I, J, wslot, done, dw);
 }
 
+// One coordinate of a CD sweep [Alg. 1] (one wave): W_ij <- its argmax at the
+// current state, with the arithmetic of update_pair, but the coupling found
+// or created in the W table on the spot (a CD sweep visits every pair, so no
+// slots are reserved beforehand; only changed couplings are written).
+template <class R, int NPL, int MODEL>
+__device__ __forceinline__ void cd_pair(const Fields& F, const WTable& W, double lambda, int i, int j,
+                                        double* acc, int64_t* changes, int32_t* err) {
+  constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  constexpr bool DIR = MODEL == REC_KINETIC;
+  const int lane = rec_lane();
+  Lane<R, NPL> L;
+  load_i<R, NPL, MODEL>(F, i, L, lane);
+  JRaw<R, NPL, MODEL> rw;
+  fetch_j<R, NPL, MODEL>(F, j, rw, lane);
+  float s_lane;
+  double phi_l = form_j<R, NPL, MODEL>(rw, L, &s_lane);
+  double phi0 = MODEL == REC_GAUSS ? 0.0 : rec_wave_sum_dpp(phi_l);
+  const double w0 = rec_uni(lookup_w(W, i, j, DIR));
+  Work wk;
+  PairOut r = solve<R, NPL, MODEL>(F, L, phi0, s_lane, i, j, w0, lambda, wk);
+  const double d = r.w - w0;
+  if (d == 0.0) return;
+  R* H = reinterpret_cast<R*>(F.H);
+  R* T = reinterpret_cast<R*>(F.T);
+  for (int side = 0; side < (DIR ? 1 : 2); ++side) {
+    const int row = side == 0 ? i : j, other = side == 0 ? j : i;
+    double scale = d;
+    if constexpr (MODEL == REC_GAUSS) scale = d * F.theta[row] * F.theta[row];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int64_t o = smp<VEC>(c, lane);
+      float xv[VEC];
+      if constexpr (MODEL == REC_GAUSS) ld_f<VEC>(F.xf + (int64_t)other * F.Mp + o, xv);
+      else ld_x<VEC>(F.xs + (int64_t)other * F.Mp + o, xv);
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        const int64_t idx = (int64_t)row * F.Mp + o + k;
+        const R h = H[idx] + (R)(scale * (double)xv[k]);
+        if (o + k < F.M) {
+          H[idx] = h;
+          if constexpr (MODEL != REC_GAUSS) {
+            const R t = tanh_(h);
+            T[idx] = t;
+            const int8_t* Y = MODEL == REC_KINETIC ? F.ys : F.xs;
+            F.rh[idx] = rec_f16_bits((float)((R)Y[idx] - t));
+          }
+        }
+      }
+    }
+  }
+  if (lane == 0) {
+    bool ins;
+    const int64_t slot = rec_hash_insert(W.keys, W.mask, rec_pair_key(i, j, DIR), REC_MAX_PROBE, &ins);
+    if (slot < 0) atomicOr(err, 2);
+    else W.vals[slot] = r.w;
+    *acc += fabs(d);
+    atomicAdd((unsigned long long*)changes, 1ull);
+  }
+}
+
+// Round r of a round-robin CD sweep over n = N rounded up to even nodes
+// (node n - 1 a phantom when N is odd): pair k pairs r with n - 1 (k = 0) or
+// (r + k) mod (n - 1) with (r - k) mod (n - 1).  The round's pairs share no
+// node, so they run in parallel exactly as in sequence.  acc[k] collects pair
+// k's |dW| over the rounds (one wave per k and round, so its sum is fixed).
+// Symmetric models update (min, max); the kinetic model both ordered
+// couplings, (a <- b) then (b <- a).
+template <class R, int NPL, int MODEL>
+__global__ __launch_bounds__(256) void k_cd_round(Fields F, WTable W, double lambda, int64_t r,
+                                                  int64_t n, double* acc, int64_t* changes,
+                                                  int32_t* err) {
+  const int64_t half = n / 2;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / REC_WAVE);
+  for (int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE; k < half; k += nw) {
+    int64_t a, b;
+    if (k == 0) { a = r; b = n - 1; }
+    else { a = (r + k) % (n - 1); b = (r - k + (n - 1)) % (n - 1); }
+    if (a >= F.N || b >= F.N) continue;
+    if constexpr (MODEL == REC_KINETIC) {
+      cd_pair<R, NPL, MODEL>(F, W, lambda, (int)a, (int)b, acc + k, changes, err);
+      cd_pair<R, NPL, MODEL>(F, W, lambda, (int)b, (int)a, acc + k, changes, err);
+    } else {
+      cd_pair<R, NPL, MODEL>(F, W, lambda, (int)(a < b ? a : b), (int)(a < b ? b : a), acc + k, changes, err);
+    }
+  }
+}
+
 // The chain of updates of one target row i of a directed model, in rank
 // order (one wave): the row's fields h_i stay in the lanes' registers from
 // the chain's first pair to its last, and h_i, t_i = tanh h_i and the fp16
@@ -1477,6 +1564,42 @@ rec_status rec_launch_update_chains(rec_ctx* ctx, int64_t m, const int32_t* I, c
   if (m <= 0 || n <= 0) return REC_OK;
   return ctx->fp32 ? launch_chains_r<float>(ctx, m, I, J, key, len, cpair, n, head, done, dw)
                    : launch_chains_r<double>(ctx, m, I, J, key, len, cpair, n, head, done, dw);
+}
+
+namespace {
+template <class R, int MODEL>
+rec_status launch_cd_m(rec_ctx* ctx, int64_t r, int64_t n, double* acc, int64_t* changes) {
+  const int64_t waves = n / 2;
+  const int64_t blocks = std::min<int64_t>((waves * REC_WAVE + 255) / 256, 256 * 8);
+#define REC_CD(NPL)                                                                               \
+  hipLaunchKernelGGL((k_cd_round<R, NPL, MODEL>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream, \
+                     ctx->F, ctx->W, ctx->cfg.lambda, r, n, acc, changes, ctx->err_flag)
+  switch (ctx->F.npl) {
+    case 1: REC_CD(1); break;
+    case 2: REC_CD(2); break;
+    case 4: REC_CD(4); break;
+    case 8: REC_CD(8); break;
+    case 16: REC_CD(16); break;
+    case 32: REC_CD(32); break;
+    default: ctx->err = "unsupported sample count"; return REC_E_INVAL;
+  }
+#undef REC_CD
+  return hipGetLastError() == hipSuccess ? REC_OK : REC_E_HIP;
+}
+
+template <class R>
+rec_status launch_cd_r(rec_ctx* ctx, int64_t r, int64_t n, double* acc, int64_t* changes) {
+  switch (ctx->cfg.model) {
+    case REC_ISING: return launch_cd_m<R, REC_ISING>(ctx, r, n, acc, changes);
+    case REC_GAUSS: return launch_cd_m<R, REC_GAUSS>(ctx, r, n, acc, changes);
+    case REC_KINETIC: return launch_cd_m<R, REC_KINETIC>(ctx, r, n, acc, changes);
+  }
+  return REC_E_INVAL;
+}
+}  // namespace
+
+rec_status rec_launch_cd_round(rec_ctx* ctx, int64_t r, int64_t n, double* acc, int64_t* changes) {
+  return ctx->fp32 ? launch_cd_r<float>(ctx, r, n, acc, changes) : launch_cd_r<double>(ctx, r, n, acc, changes);
 }
 
 rec_status rec_launch_update_round(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
