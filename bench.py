@@ -338,6 +338,10 @@ def main():
     ap.add_argument("--scaling", default="", metavar="N1,N2,...",
                     help="only run the FindBest runtime study (Gaussian, M=10, the paper's "
                          "runtime-figure problems) at these node counts")
+    ap.add_argument("--convergence", default="", metavar="N1,N2,...",
+                    help="only run the GCD-vs-CD convergence study (Gaussian, M=100) at these node counts")
+    ap.add_argument("--kappas", default="0.5,1,2,4,10", help="kappa values of the convergence study")
+    ap.add_argument("--conv-search", default="nndescent,screen", help="GCD searches of the convergence study")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -348,6 +352,10 @@ def main():
         return
     if args.scaling:
         scaling_study([int(float(v)) for v in args.scaling.split(",")], args.prec)
+        return
+    if args.convergence:
+        convergence_study([int(float(v)) for v in args.convergence.split(",")],
+                          [float(v) for v in args.kappas.split(",")], args.conv_search.split(","), args.prec)
         return
 
     import torch
@@ -451,6 +459,75 @@ def scaling_study(sizes, prec, kappas=(1.0, 4.0), reps=3):
                            "exponent_vs_NlogsqN": float(np.polyfit(lnl, lt, 1)[0])}
     print(json.dumps({"study": "FindBest runtime vs N (Gaussian, M=10)", "prec": prec, "rows": rows,
                       "fit": fit}), flush=True)
+
+
+def convergence_study(sizes, kappas, searches, prec, max_sweeps=300, cd_max=200,
+                      fractions=(0.9, 0.99, 0.999)):
+    """GCD [Alg. 2] against the coordinate-descent baseline [Alg. 1] on the
+    paper's convergence-figure problems: the runtime-figure Gaussian
+    parameterisation (ER mean degree 5, off-diagonal precisions ~ N(-1000,
+    10^2), diagonally dominant) with M = 100 samples, at each N; GCD for each
+    kappa and search.  Every run starts from W = 0 (objective L0) and sweeps
+    until the sweep's sum |dW| falls below 1e-9 of the first sweep's or a sweep
+    cap; the trajectory of (wall time, objective, sum |dW|) is recorded.  Per
+    N the reference L_ref is the best final objective over all runs, and each
+    run's time to reach the fraction f of the improvement, (L - L0) >= f
+    (L_ref - L0), is reported with CD's time over it."""
+    import numpy as np
+    import torch
+
+    import paper_2401_01404_amd as rec
+    import synth
+
+    out = []
+    for N in sizes:
+        w = synth.gauss_scaling(N, 100, seed=0)
+        lam = synth.sparsity_lambda(w.X, "gauss")
+        X = torch.as_tensor(w.X).cuda()
+        runs = []
+        plans = [("cd", None, None)] + [("gcd", k, s) for s in searches for k in kappas]
+        L0 = None
+        for kind, kappa, search in plans:
+            ctx = rec.Context(X, "gauss", lam, kappa=kappa or 1.0, prec=prec)
+            L0 = ctx.objective()
+            traj, t_cum, d0 = [], 0.0, None
+            cap = cd_max if kind == "cd" else max_sweeps
+            for it in range(cap):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                st = ctx.cd_sweep() if kind == "cd" else ctx.sweep(search)
+                torch.cuda.synchronize()
+                t_cum += time.perf_counter() - t
+                traj.append((round(t_cum, 6), st["objective"], st["delta"]))
+                d0 = st["delta"] if d0 is None else d0
+                if st["delta"] <= 1e-9 * max(d0, 1e-300):
+                    break
+            runs.append({"method": kind, "kappa": kappa, "search": search, "sweeps": len(traj),
+                         "seconds": t_cum, "ms_per_sweep": t_cum / len(traj) * 1e3,
+                         "final_objective": traj[-1][1], "trajectory": traj})
+            print(json.dumps({k: v for k, v in runs[-1].items() if k != "trajectory"} | {"N": N}),
+                  file=sys.stderr, flush=True)
+            del ctx
+        ref = max(r["final_objective"] for r in runs)
+        for r in runs:
+            r["seconds_to_fraction"] = {}
+            r["sweeps_to_fraction"] = {}
+            for f in fractions:
+                hit = [(q, t) for q, (t, o, _) in enumerate(r["trajectory"]) if o - L0 >= f * (ref - L0)]
+                r["seconds_to_fraction"][str(f)] = hit[0][1] if hit else None
+                r["sweeps_to_fraction"][str(f)] = hit[0][0] + 1 if hit else None
+        cd = runs[0]
+        for r in runs:
+            r["cd_time_over_this"] = {
+                f: (cd["seconds_to_fraction"][f] / r["seconds_to_fraction"][f])
+                if cd["seconds_to_fraction"][f] and r["seconds_to_fraction"][f] else None
+                for f in r["seconds_to_fraction"]}
+        out.append({"N": N, "M": 100, "lambda": lam, "objective_w0": L0, "reference_objective": ref,
+                    "runs": runs})
+        del X
+        torch.cuda.empty_cache()
+    print(json.dumps({"study": "GCD vs CD convergence (Gaussian, M=100, runtime-figure parameters)",
+                      "prec": prec, "results": out}), flush=True)
 
 
 def copy_probe(mib):
