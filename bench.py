@@ -26,7 +26,7 @@ then the exact Newton solve of the sides it cannot settle).  Both the HBM view
 (algorithmic bytes the kernels count / event time, against 8 TB/s) and the
 FP32 VALU view (algorithmic flops / event time, against 157.3 TFLOP/s) are
 computed.  The bound is the larger fraction.  The screening contraction, the
-sweep's dominant kernel, gets its own entry against the FP16 MFMA peak.
+sweep's dominant kernel, gets its own entry against the dense int8 MFMA peak.
 
 cpu_baseline: the FP64 CPU oracle (built -O3 -march=native on the host that
 runs it) scoring a bounded prefix of the same batch at the same state.
@@ -64,10 +64,10 @@ WORKLOADS = {
 FLOPS_LOAD, FLOPS_MOMENT, FLOPS_EVAL, FLOPS_LOG = 5, 8, 8, 3
 # MI355X peaks: FP32 vector 157.3 TFLOP/s (256 CUs x 4 SIMDs x 2.4 GHz, an FMA
 # counted as 2 flops, dual-issue/packed rate as published), HBM3E 8 TB/s,
-# dense FP16 matrix cores 2.5 PFLOP/s.
+# dense int8 matrix cores 5.0 POP/s (the screening contraction's dtype).
 PEAK_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-PEAK_F16_MFMA_TFLOPS = 2500.0
+PEAK_I8_MFMA_TOPS = 5000.0
 BATCH_PER_NODE = 16
 
 # HBM traffic of the pair-score kernels on the batch (k_kink + k_exact) per
@@ -304,10 +304,10 @@ def run_workload(name, args, torch, rec, synth, headline):
         ach = sflops / (sms / 1e3) / 1e12
         ts = TRAFFIC_SCREEN.get(name)
         straffic = ts["hbm_bytes_per_launch"] if ts and ts["source_sha256"] == source_sha("screen.hip") else None
-        roof_screen = {"bound": "mfma", "achieved": ach, "peak": PEAK_F16_MFMA_TFLOPS, "unit": "TFLOP/s",
-                       "frac": ach / PEAK_F16_MFMA_TFLOPS, "traffic": straffic,
-                       "kernel": "screening contraction full pass: k_kscreen (FP16 MFMA 16x16x32, "
-                                 "FP32 accumulate, histogram + collect epilogue)",
+        roof_screen = {"bound": "mfma", "achieved": ach, "peak": PEAK_I8_MFMA_TOPS, "unit": "TOP/s",
+                       "frac": ach / PEAK_I8_MFMA_TOPS, "traffic": straffic,
+                       "kernel": "screening contraction full pass: k_kscreen (int8 MFMA 16x16x64, "
+                                 "int32 accumulate, histogram + collect epilogue)",
                        "kernel_ms_avg": sms, "launches": int(scr["full_launches"]),
                        "flops_per_launch": sflops,
                        "sample_pass_ms_avg": scr["sample_ms"] / max(scr["sample_launches"], 1)}

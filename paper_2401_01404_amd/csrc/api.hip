@@ -45,7 +45,9 @@ rec_status plan(const rec_config* c, Sizes* z, const char** why) {
   if (!(c->lambda >= 0) || !std::isfinite(c->lambda)) { *why = "lambda must be finite and >= 0"; return REC_E_INVAL; }
   if (!(c->kappa > 0) || !std::isfinite(c->kappa)) { *why = "kappa must be > 0"; return REC_E_INVAL; }
   const int64_t N = c->N;
-  int npl = 1;
+  // Ising / kinetic rows hold at least 128 samples: the screening
+  // contraction takes 128-sample steps, each inside one operand half
+  int npl = c->model == REC_GAUSS ? 1 : 2;
   while (64 * npl < c->M) npl *= 2;
   z->npl = npl;
   z->Mp = 64 * (int64_t)npl;
@@ -86,7 +88,8 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   const size_t rs = c->prec == REC_FP32 ? 4 : 8;
   const int64_t nsz = N * z.Mp;
   Fields& F = x->F;
-  F.xs = a.take<int8_t>(nsz);
+  // the +-1 input side carries REC_TAIL_ROWS zero rows past N (a contraction operand)
+  F.xs = a.take<int8_t>(c->model == REC_GAUSS ? nsz : (N + REC_TAIL_ROWS) * z.Mp);
   F.ys = c->model == REC_KINETIC ? a.take<int8_t>(nsz) : F.xs;
   F.xf = c->model == REC_GAUSS ? a.take<float>(nsz) : nullptr;
   F.H = a.take<char>(nsz * rs);
@@ -94,11 +97,10 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   if (c->model != REC_GAUSS) {
     F.xq = a.take<uint32_t>(N * 64);
     F.yq = c->model == REC_KINETIC ? a.take<uint32_t>(N * 64) : F.xq;
-    F.rh = a.take<uint16_t>((N + REC_TAIL_ROWS) * z.Mp);
-    F.xh = a.take<uint16_t>((N + REC_TAIL_ROWS) * z.Mp);
+    F.rq = a.take<int8_t>((N + REC_TAIL_ROWS) * z.Mp);
   } else {
     F.xq = F.yq = nullptr;
-    F.rh = F.xh = nullptr;
+    F.rq = nullptr;
   }
   F.sq = a.take<double>(N);
   F.theta = a.take<double>(N);
@@ -393,15 +395,16 @@ rec_status rec_create(const rec_config* cfg, const void* X_dev, void* ws_dev, si
   F.Mp = z.Mp;
   F.npl = z.npl;
   F.model = cfg->model;
-  // The screens compare kink sums with lambda.  Rounding y - tanh h (|.| < 2)
-  // to fp16 moves each term by at most 2^-10 (one fp16 ulp at the top
-  // binade, covering double rounding through float) plus 2^-24 below the
-  // normal range: M (2^-9 + 2^-24) for a sum.  The exact-sign part uses r_i =
-  // y - t rounded once in the working precision (<= 2^-23 per term) and float
-  // partial sums of at most 32 terms per lane in both the screen and the exact
-  // path; 0.02 covers those sums (<= 64 lanes x 2 x 32 x 32 x 2^-24 < 4e-3).
+  // The screens compare kink sums with lambda.  The int8 copy q of y - tanh h
+  // (|.| < 2, rounded to float first: 2^-24 relative) moves each term by at
+  // most 1/127 + 2^-22 (rec_q8): M (1/127 + 2^-22 + 2^-23) for a sum.  The
+  // exact-sign part uses r_i = y - t rounded once in the working precision
+  // (<= 2^-23 per term) and float partial sums of at most 32 terms per lane in
+  // both the screen and the exact path; 0.02 covers those sums (<= 64 lanes x
+  // 2 x 32 x 32 x 2^-24 < 4e-3).
   const double eps_sign = (double)cfg->M * std::ldexp(1.0, -22) + 0.02;
-  F.scr = cfg->lambda - ((double)cfg->M * (std::ldexp(1.0, -9) + std::ldexp(1.0, -24)) + eps_sign);
+  F.scr = cfg->lambda -
+          ((double)cfg->M * (1.0 / 127.0 + std::ldexp(1.0, -22) + std::ldexp(1.0, -23)) + eps_sign);
   F.scra = cfg->lambda - eps_sign;
   auto bad = [&](rec_status st) { delete ctx; return st; };
   if (hipMemsetAsync(ctx->err_flag, 0, 16, ctx->stream) != hipSuccess) return bad(REC_E_HIP);

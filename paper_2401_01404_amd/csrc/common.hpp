@@ -209,6 +209,17 @@ __device__ __forceinline__ int64_t rec_block_append(int64_t* cursor, bool pred, 
 constexpr int REC_WORK_COPIES = 256;
 constexpr int REC_WORK_N = 8;
 
+// Residual copies for the screens: int8 q = round(63.5 r), |r| < 2, so
+// |q| <= 127.  The value of q is q / 63.5; one term's error |r - q / 63.5| is
+// at most 1/127 plus the float product's rounding (2^-24 of 127, < 2^-22 in
+// all).
+constexpr float REC_Q8_SCALE = 63.5f;
+constexpr float REC_Q8_INV = 1.0f / 63.5f;
+__device__ __forceinline__ int8_t rec_q8(float r) {
+  const float v = rintf(r * REC_Q8_SCALE);
+  return (int8_t)fminf(fmaxf(v, -127.f), 127.f);
+}
+
 // fp16 bits of v (round to nearest even) and back
 __device__ __forceinline__ uint16_t rec_f16_bits(float v) {
   return __builtin_bit_cast(uint16_t, (_Float16)v);

@@ -23,15 +23,14 @@ struct Fields {
   double* theta;        // N
   // Ising / kinetic screen data.  xq, yq: N x 64 lane words, bit c*VEC + k of
   // lane l is sample c*64*VEC + l*VEC + k of xs (yq: ys) being +1 (padding
-  // reads as -1 and is cancelled by zeros on the other side); rh: N x Mp
-  // fp16 residuals y - tanh h (padding 0).
+  // reads as -1 and is cancelled by zeros on the other side); rq: N x Mp
+  // int8 residuals q = round(63.5 (y - tanh h)) (padding 0).  rq and xs
+  // carry REC_TAIL_ROWS zero rows past N (the contraction's tiles never need
+  // a bound check).
   const uint32_t* xq;
   const uint32_t* yq;
-  uint16_t* rh;
-  // fp16 copy of xs for the screening contraction; rh and xh carry
-  // REC_TAIL_ROWS zero rows past N
-  uint16_t* xh;
-  double scr;           // screen threshold: lambda minus the fp16 (and float) error bound
+  int8_t* rq;
+  double scr;           // screen threshold: lambda minus the int8 (and float) error bound
   double scra;          // exact-sign screen threshold: lambda minus the float rounding bound
   int64_t N, M, Mp;     // valid samples M, padded row length Mp = 64 * npl
   int npl;              // samples per lane

@@ -6,7 +6,7 @@
 // Fields [App. A, "keeping track of the weighted sum of the neighbors"]:
 // m_i = sum_{j != i} W_ij x_j per sample, summed in FP64 over the sorted
 // row list of W and rounded once to the working precision; Ising and kinetic
-// store h = theta + m and t = tanh h, the Gaussian model stores the residual
+// store h = theta + m, t = tanh h and the int8 copy of y - t, the Gaussian model stores the residual
 // r = x + theta^2 m.
 //
 // Objective [App. A]: sum over nodes and samples of the log conditional plus
@@ -69,16 +69,6 @@ __global__ __launch_bounds__(FT) void k_load_int8(const int8_t* __restrict__ X, 
     }
     xs[i * Mp + s] = a;
     if (kinetic) ys[i * Mp + s] = b;
-  }
-}
-
-// fp16 copy of the +-1 input side (the screening contraction's operand)
-__global__ __launch_bounds__(FT) void k_x_half(const int8_t* __restrict__ xs, int64_t Mp,
-                                               uint16_t* __restrict__ xh) {
-  const int64_t i = blockIdx.x;
-  for (int64_t s = threadIdx.x; s < Mp; s += FT) {
-    const int8_t v = xs[i * Mp + s];
-    xh[i * Mp + s] = v > 0 ? 0x3C00u : (v < 0 ? 0xBC00u : 0u);
   }
 }
 
@@ -175,7 +165,7 @@ __global__ __launch_bounds__(FT) void k_fields(Fields F, const int64_t* __restri
   for (int c = 0; c < CH; ++c) {
     const int64_t o = L::at(c, lane), idx = i * F.Mp + o;
     Pack<R, VEC> hv, tv;
-    Pack<uint16_t, VEC> rv;
+    Pack<int8_t, VEC> rv;
     if (MODEL == REC_GAUSS) {
       double x[VEC];
       ld_f32<VEC>(F.xf + idx, x);
@@ -193,11 +183,11 @@ __global__ __launch_bounds__(FT) void k_fields(Fields F, const int64_t* __restri
         const R t = in ? tanh_<R>(h) : R(0);
         hv.v[k] = h;
         tv.v[k] = t;
-        rv.v[k] = rec_f16_bits((float)((R)y[k] - t));
+        rv.v[k] = rec_q8((float)((R)y[k] - t));
       }
       *reinterpret_cast<Pack<R, VEC>*>(H + idx) = hv;
       *reinterpret_cast<Pack<R, VEC>*>(T + idx) = tv;
-      *reinterpret_cast<Pack<uint16_t, VEC>*>(F.rh + idx) = rv;
+      *reinterpret_cast<Pack<int8_t, VEC>*>(F.rq + idx) = rv;
     }
   }
 }
@@ -336,7 +326,7 @@ __global__ __launch_bounds__(FT) void k_theta(Fields F, const int64_t* __restric
     for (int c = 0; c < CH; ++c) {
       const int64_t idx = i * F.Mp + L::at(c, lane);
       Pack<R, VEC> hv, tv;
-      Pack<uint16_t, VEC> rv;
+      Pack<int8_t, VEC> rv;
 #pragma unroll
       for (int k = 0; k < VEC; ++k) {
         const bool in = valid(c * VEC + k);
@@ -344,11 +334,11 @@ __global__ __launch_bounds__(FT) void k_theta(Fields F, const int64_t* __restric
         const R t = in ? tanh_<R>(h) : R(0);
         hv.v[k] = h;
         tv.v[k] = t;
-        rv.v[k] = rec_f16_bits((float)((R)y[c * VEC + k] - t));
+        rv.v[k] = rec_q8((float)((R)y[c * VEC + k] - t));
       }
       *reinterpret_cast<Pack<R, VEC>*>(H + idx) = hv;
       *reinterpret_cast<Pack<R, VEC>*>(T + idx) = tv;
-      *reinterpret_cast<Pack<uint16_t, VEC>*>(F.rh + idx) = rv;
+      *reinterpret_cast<Pack<int8_t, VEC>*>(F.rq + idx) = rv;
     }
   }
   if (lane == 0) F.theta[i] = th;
@@ -610,10 +600,10 @@ rec_status rec_load_data(rec_ctx* ctx, const void* X, int64_t ldx) {
     if (ctx->cfg.model == REC_KINETIC)
       hipLaunchKernelGGL(k_pack_bits, dim3(N), dim3(REC_WAVE), 0, ctx->stream, ctx->F.ys, ctx->F.Mp,
                          ctx->F.npl, const_cast<uint32_t*>(ctx->F.yq));
-    hipLaunchKernelGGL(k_x_half, dim3(N), dim3(FT), 0, ctx->stream, ctx->F.xs, ctx->F.Mp, ctx->F.xh);
-    const size_t tail = (size_t)(REC_TAIL_ROWS * ctx->F.Mp) * sizeof(uint16_t);
-    REC_HIP(hipMemsetAsync(ctx->F.xh + N * ctx->F.Mp, 0, tail, ctx->stream));
-    REC_HIP(hipMemsetAsync(ctx->F.rh + N * ctx->F.Mp, 0, tail, ctx->stream));
+    // zero tail rows of the contraction's operands
+    const size_t tail = (size_t)(REC_TAIL_ROWS * ctx->F.Mp);
+    REC_HIP(hipMemsetAsync(const_cast<int8_t*>(ctx->F.xs) + N * ctx->F.Mp, 0, tail, ctx->stream));
+    REC_HIP(hipMemsetAsync(ctx->F.rq + N * ctx->F.Mp, 0, tail, ctx->stream));
   }
   REC_HIP(hipGetLastError());
   return REC_OK;

@@ -655,9 +655,9 @@ __global__ __launch_bounds__(256) void k_grad(Fields F, WTable W, double lambda,
 // kink test).  Phi(0) splits into a part that needs only the signs of x_j
 // and the resident i row, and a part sum_m x_i (y_j - t_j) that needs the j
 // row's tanh values.  The first read fetches the sign words of x_j (and of
-// y_j for the kinetic search) and fp16 copies of y_j - t_j (2.1 bytes per
-// sample instead of 5-6); their error moves the second part by at most the
-// bound folded into F.scr, so |screen| <= F.scr proves |Phi(0)| <= lambda
+// y_j for the kinetic search) and int8 copies q_j = round(63.5 (y_j - t_j))
+// (1.1 bytes per sample instead of 5-6); their error moves the second part by
+// at most the bound folded into F.scr, so |screen| <= F.scr proves |Phi(0)| <= lambda
 // and the side's gain is exactly zero, the value the full evaluation gives.
 // The first part is screened the same way from a resident fp32/fp64 copy of
 // r_i (its only error is float rounding, bounded in F.scra).  Otherwise the
@@ -665,10 +665,10 @@ __global__ __launch_bounds__(256) void k_grad(Fields F, WTable W, double lambda,
 // result is the same bits either way.
 template <int NPL, bool SYM>
 struct JScr {
-  static constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC, HW = NPL >= 2 ? NPL / 2 : 1;
+  static constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
   uint32_t xw;             // signs of x_j (bit q = lane register q)
   uint32_t yw;             // kinetic search: signs of the targets y_j
-  uint32_t hw[HW];         // fp16 y_j - t_j, two per word (register q in word q / 2)
+  uint32_t qw[CH];         // int8 copies of y_j - t_j, VEC per word (register c VEC + k in byte k of word c)
 };
 
 template <int NPL, bool SYM>
@@ -676,27 +676,22 @@ __device__ __forceinline__ void fetch_scr(const Fields& F, int j, JScr<NPL, SYM>
   constexpr int VEC = JScr<NPL, SYM>::VEC, CH = JScr<NPL, SYM>::CH;
   r.xw = F.xq[(int64_t)j * REC_WAVE + lane];
   if constexpr (SYM) r.yw = F.yq[(int64_t)j * REC_WAVE + lane];
-  const uint16_t* hr = F.rh + (int64_t)j * F.Mp;
+  const int8_t* qr = F.rq + (int64_t)j * F.Mp;
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     const int64_t o = smp<VEC>(c, lane);
-    if constexpr (VEC == 4) {
-      uint2 v = *reinterpret_cast<const uint2*>(hr + o);
-      r.hw[2 * c] = v.x;
-      r.hw[2 * c + 1] = v.y;
-    } else if constexpr (VEC == 2) {
-      r.hw[c] = *reinterpret_cast<const uint32_t*>(hr + o);
-    } else {
-      r.hw[0] = hr[o];
-    }
+    if constexpr (VEC == 4) r.qw[c] = *reinterpret_cast<const uint32_t*>(qr + o);
+    else if constexpr (VEC == 2) r.qw[c] = *reinterpret_cast<const uint16_t*>(qr + o);
+    else r.qw[c] = (uint8_t)qr[o];
   }
 }
 
 __device__ __forceinline__ float sgn_at(uint32_t w, int q) { return ((w >> q) & 1u) ? 1.f : -1.f; }
-template <int HW>
-__device__ __forceinline__ float h_at(const uint32_t (&hw)[HW], int q) {
-  uint32_t w = hw[q >> 1];
-  return rec_f16_val((q & 1) ? (w >> 16) : (w & 0xffffu));
+// the int8 copy of register q (exact small integer; scaled once per sum)
+template <int NPL, int CH>
+__device__ __forceinline__ float q_at(const uint32_t (&qw)[CH], int q) {
+  constexpr int VEC = NPL < 4 ? NPL : 4;
+  return (float)(int8_t)(qw[q / VEC] >> (8 * (q % VEC)));
 }
 
 // the j row of tanh values, fetched only for pairs the screen does not settle
@@ -712,8 +707,8 @@ __device__ __forceinline__ void fetch_t(const Fields& F, int j, R (&t)[NPL], int
 // registers: r_i = y_i - t_i (zero in the padding) and the sign words of the
 // inputs x_i.  Both kink sums are then one select and one add per sample:
 //   sum_m x_{j,m} r_{i,m}  (the i <- j part, exact signs)     and
-//   sum_m x_{i,m} rh_{j,m} (the j <- i part, fp16 residuals of j),
-// with padding cancelled by the zeros of r_i and rh_j.  The exact path (a
+//   sum_m x_{i,m} q_{j,m} / 63.5 (the j <- i part, int8 residuals of j),
+// with padding cancelled by the zeros of r_i and q_j.  The exact path (a
 // side whose test does not settle it) reloads t_i and the int8 rows of i,
 // which the wave's previous pairs keep in cache, and evaluates the side with
 // the same arithmetic as k_score, so its results are the same bits.
@@ -839,13 +834,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     }
     if (i != cur) { load_i_r<R, NPL, MODEL>(F, i, L, lane); cur = i; ++wk.iloads; }
     R sa = R(0);
-    float sb = 0.f;
+    float sb = 0.f;   // sum of x_i q_j: an integer below 2^24 in magnitude, exact in float
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       sa += ((rw.xw >> k) & 1u) ? L.ri[k] : -L.ri[k];
-      const float h = h_at(rw.hw, k);
+      const float h = q_at<NPL>(rw.qw, k);
       sb += ((L.xw >> k) & 1u) ? h : -h;
     }
+    sb *= REC_Q8_INV;
     bool na, nb = false;
     if constexpr (MODEL == REC_ISING) {
       na = w0 != 0.0 || fabs(rec_wave_sum_dpp((double)sa + (double)sb)) > F.scr;
@@ -877,7 +873,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   if (lane == 0 && work) {
     const int64_t M = F.M, rs = sizeof(R);
     const int64_t items = SYM ? wk.pairs / 2 : wk.pairs;
-    const int64_t sbytes = (M + 7) / 8 * (SYM ? 2 : 1) + 2 * M;   // signs + fp16 residuals
+    const int64_t sbytes = (M + 7) / 8 * (SYM ? 2 : 1) + M;   // signs + int8 residuals
     wk.bytes = items * (16 + (slot ? 4 : 0) + sbytes) + wk.iloads * (rs * M + M + (M + 7) / 8);
     wk.flush(work, wave);
   }
@@ -1052,7 +1048,7 @@ __device__ __forceinline__ void update_pair(const Fields& F, const WTable& W, do
               R t = tanh_(h);
               T[idx] = t;
               const int8_t* Y = MODEL == REC_KINETIC ? F.ys : F.xs;
-              F.rh[idx] = rec_f16_bits((float)((R)Y[idx] - t));
+              F.rq[idx] = rec_q8((float)((R)Y[idx] - t));
             }
           }
         }
@@ -1134,7 +1130,7 @@ __device__ __forceinline__ void cd_pair(const Fields& F, const WTable& W, double
             const R t = tanh_(h);
             T[idx] = t;
             const int8_t* Y = MODEL == REC_KINETIC ? F.ys : F.xs;
-            F.rh[idx] = rec_f16_bits((float)((R)Y[idx] - t));
+            F.rq[idx] = rec_q8((float)((R)Y[idx] - t));
           }
         }
       }
@@ -1179,7 +1175,7 @@ __global__ __launch_bounds__(256) void k_cd_round(Fields F, WTable W, double lam
 
 // The chain of updates of one target row i of a directed model, in rank
 // order (one wave): the row's fields h_i stay in the lanes' registers from
-// the chain's first pair to its last, and h_i, t_i = tanh h_i and the fp16
+// the chain's first pair to its last, and h_i, t_i = tanh h_i and the int8
 // residuals y_i - t_i are written once at the end; every pair sees the
 // fields left by the one before it, as in the sequential order.  Each step
 // has the arithmetic of update_pair, so the results are the same bit for
@@ -1275,7 +1271,7 @@ __device__ __forceinline__ void update_chain(const Fields& F, const WTable& W, d
           const R t = tanh_(h[q]);
           H[row + o + k] = h[q];
           T[row + o + k] = t;
-          F.rh[row + o + k] = rec_f16_bits((float)((R)byte_at(yb[c], k) - t));
+          F.rq[row + o + k] = rec_q8((float)((R)byte_at(yb[c], k) - t));
         }
       }
     }

@@ -19,9 +19,9 @@
 // rescored by the exact score kernel.  The result equals the exhaustive
 // search's positive-gain top m: the screen drops no pair that could reach it.
 //
-// Ising and kinetic models: the same two passes over an FP16 contraction of
-// the +-1 samples with the residuals, with gain bounds from the curvature of
-// the log-cosh terms (see the second half of this file).
+// Ising and kinetic models: the same two passes over an int8 contraction of
+// the +-1 samples with the int8 residual copies, with gain bounds from the
+// curvature of the log-cosh terms (see the second half of this file).
 #include <math.h>
 #include <string.h>
 
@@ -32,6 +32,10 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef int intx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// word 3 of a raw buffer descriptor on gfx9-family GPUs (32-bit data, no swizzle)
+constexpr int KS_RSRC3 = 0x00020000;
 
 constexpr int SC_T = 128;      // output tile (rows and columns)
 constexpr int SC_K = 32;       // k step of one MFMA
@@ -226,11 +230,12 @@ __global__ void k_screen_tau(const uint32_t* hist, int64_t target, float* tau) {
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 struct KScreenArgs {
-  const uint16_t* xh;   // (N + 128) x Mp fp16 input side (+-1; padding and tail rows 0)
-  const uint16_t* rh;   // (N + 128) x Mp fp16 residuals (padding and tail rows 0)
+  const int8_t* xs;     // (N + REC_TAIL_ROWS) x Mp int8 input side (+-1; padding and tail rows 0)
+  const int8_t* rq;     // (N + REC_TAIL_ROWS) x Mp int8 residuals (padding and tail rows 0)
   int64_t N, Mp;
-  int nsteps;           // k steps of 32: Ising 2 Mp / 32, kinetic Mp / 32
-  const float* l1;      // |r_i|_1, rounded up
+  int opbytes;          // bytes of each operand array, (N + REC_TAIL_ROWS) Mp < 2^31
+  int nsteps;           // k steps of KS_K samples: Ising 2 Mp / KS_K, kinetic Mp / KS_K
+  const float* l1;      // E_i, the int8 copy's total error on row i, rounded up
   const float* cv;      // c_i = sum_t (1 - tanh^2 h_it)
   const float* cvmin;   // min_i c_i (Ising: bounds c_i + c_j from below per row)
   float lam, ce, el;
@@ -247,18 +252,23 @@ struct KScreenArgs {
   int32_t* err;
 };
 
-// per node: |r_i|_1 (from the fp16 residuals the contraction reads) and c_i
+// per node: E_i = sum_m |r_im - q_im / 63.5|, the total error of the int8
+// residual copy the contraction reads against the working-precision residual
+// r = y - tanh h (rounded up), and c_i = sum_m (1 - tanh^2 h_im)
 template <class R>
 __global__ __launch_bounds__(256) void k_kscreen_prep(Fields F, float* __restrict__ l1,
                                                       float* __restrict__ cv) {
   __shared__ double sh[8];
   const int64_t i = blockIdx.x;
   const R* T = reinterpret_cast<const R*>(F.T) + i * F.Mp;
-  const uint16_t* rh = F.rh + i * F.Mp;
+  const int8_t* q = F.rq + i * F.Mp;
+  const int8_t* y = F.ys + i * F.Mp;
   double s1 = 0.0, s2 = 0.0;
-  for (int64_t k = threadIdx.x; k < F.Mp; k += blockDim.x) {
-    s1 += fabs((double)rec_f16_val(rh[k]));
-    if (k < F.M) { const double t = (double)T[k]; s2 += 1.0 - t * t; }
+  for (int64_t k = threadIdx.x; k < F.M; k += blockDim.x) {
+    const double t = (double)T[k];
+    const double r = (double)((R)y[k] - T[k]);
+    s1 += fabs(r - (double)q[k] / 63.5);
+    s2 += 1.0 - t * t;
   }
   s1 = rec_wave_sum(s1);
   s2 = rec_wave_sum(s2);
@@ -267,8 +277,8 @@ __global__ __launch_bounds__(256) void k_kscreen_prep(Fields F, float* __restric
   __syncthreads();
   if (threadIdx.x == 0) {
     double a = 0.0, b = 0.0;
-    for (int q = 0; q < (int)(blockDim.x / REC_WAVE); ++q) { a += sh[q]; b += sh[4 + q]; }
-    l1[i] = (float)(a * (1.0 + 1e-6));
+    for (int qq = 0; qq < (int)(blockDim.x / REC_WAVE); ++qq) { a += sh[qq]; b += sh[4 + qq]; }
+    l1[i] = (float)(a * (1.0 + 1e-6) + 1e-30);
     cv[i] = (float)b;
   }
 }
@@ -313,13 +323,13 @@ __device__ __forceinline__ float kgain_up(float e, float c) {
   return 0.25f * c * p * (1.f + 1e-5f);
 }
 
-// LDS operand layout: rows of KS_K = 64 fp16 (128 bytes, no padding); the
-// 16-byte chunk c of row r sits at slot c ^ (r & 7).  A fragment read (rows
+// LDS operand layout: rows of KS_K = 128 int8 samples (128 bytes, no
+// padding); the 16-byte chunk c of row r sits at slot c ^ (r & 7).  A fragment read (rows
 // 16k..16k+15 at one chunk) and a staging write (8 lanes per row) touch 8
 // distinct 16-byte slots in every 8 lanes: no bank conflicts (checked with
 // the LDS bank-conflict counters on gfx950, which serve ds_read_b128 in
 // 8-lane groups; padded rows and XORs over wider lines conflict 2-way).
-__device__ __forceinline__ int ks_swz(int r, int c) { return r * 64 + 8 * (c ^ (r & 7)); }
+__device__ __forceinline__ int ks_swz(int r, int c) { return r * 128 + 16 * (c ^ (r & 7)); }   // bytes
 
 
 // Histogram of positive float bounds for the Ising / kinetic screen: 16 bins
@@ -359,7 +369,8 @@ __device__ __forceinline__ bool ks_tile(const TileMap& T, int b, int* bi, int* b
 }
 
 // One KS_BM x KS_BN tile of the contraction per block (8 waves of 128 x 64,
-// each 8 x 4 MFMA 16x16x32 blocks).  Operands go global -> registers two k
+// each 8 x 4 MFMA 16x16x64 int8 blocks with int32 accumulators: the +-1
+// samples times the int8 residual copies sum exactly).  Operands go global -> registers two k
 // steps ahead of use and registers -> LDS one step ahead (LDS double-buffered),
 // so a load has two steps of MFMA work to arrive.  Ising: tiles that hold a
 // pair i < j, k in [0, Mp) pairs x_i with r_j and k in [Mp, 2Mp) r_i with x_j.
@@ -370,7 +381,7 @@ __device__ __forceinline__ bool ks_tile(const TileMap& T, int b, int* bi, int* b
 // KS_WM x KS_WN blocks of 16 x 16 outputs; the block covers KS_BM rows x
 // KS_BN columns.
 constexpr int KS_THREADS = 512;
-constexpr int KS_K = 64;   // samples per k step (two MFMA k-substeps)
+constexpr int KS_K = 128;  // samples (bytes) per k step (two MFMA k-substeps of 64)
 constexpr int KS_WR = 2, KS_WC = 4;
 constexpr int KS_WM = 8, KS_WN = 4;
 constexpr int KS_BM = KS_WR * KS_WM * 16, KS_BN = KS_WC * KS_WN * 16;
@@ -384,8 +395,8 @@ static_assert(KS_BM % (KS_THREADS / 8) == 0 && KS_BN % (KS_THREADS / 8) == 0, "s
 template <int MODE, int KIN, int ROBUST>
 __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_kscreen(KScreenArgs P, TileMap TM, int row_step, int* tctr, int nvirt) {
   constexpr bool HIST = MODE != 1, COLLECT = MODE != 0;
-  __shared__ __attribute__((aligned(16))) _Float16 As[2][KS_BM * KS_K];
-  __shared__ __attribute__((aligned(16))) _Float16 Bs[2][KS_BN * KS_K];
+  __shared__ __attribute__((aligned(16))) int8_t As[2][KS_BM * KS_K];
+  __shared__ __attribute__((aligned(16))) int8_t Bs[2][KS_BN * KS_K];
   __shared__ uint32_t hs[HIST ? KS_BINS : 1];
   __shared__ uint32_t kq_key[KS_Q];   // bit 31 histogram, bit 30 collect; row << 8 | column in the tile
   __shared__ float kq_e[KS_Q], kq_c[KS_Q];
@@ -443,11 +454,12 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   const int64_t r0 = (int64_t)bi * KS_BM, c0 = (int64_t)bj * KS_BN;
   if (!KIN && r0 >= c0 + KS_BN - 1) ok = false;   // no pair i < j in the tile
   if (ok) {
-  // Staging: thread tid moves the 8-sample chunk (tid & 7) of rows tid/8 +
-  // (KS_THREADS/8) u of both operands.  Operand rows are fp16 (x copy and
-  // residuals) with zero rows past N, so no load needs a bound check.  Ising:
-  // in the first half of k, A = x and B = r; in the second, A = r and B = x.
-  // Kinetic: A = r (targets), B = x (sources).
+  // Staging: thread tid moves the 16-sample chunk (tid & 7) of rows tid/8 +
+  // (KS_THREADS/8) u of both operands.  Operand rows are int8 (the +-1 input
+  // side and the residual copies) with zero rows past N, so no load needs a
+  // bound check.  Ising: in the first half of k, A = x and B = r; in the
+  // second, A = r and B = x.  Kinetic: A = r (targets), B = x (sources).
+  // Rows hold a multiple of KS_K samples, so a step lies inside one half.
   constexpr int SRS = KS_THREADS / 8;   // staging row stride
   constexpr int NA = KS_BM / SRS, NB = KS_BN / SRS;
   static_assert(NA == 4 && NB == 4, "stage layout below holds four rows per operand");
@@ -457,45 +469,48 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   int wa[NA];
 #pragma unroll
   for (int u = 0; u < NA; ++u) {
-    oa[u] = (uint32_t)((r0 + sr + SRS * u) * P.Mp + part * 8);
+    oa[u] = (uint32_t)((r0 + sr + SRS * u) * P.Mp + part * 16);
     wa[u] = ks_swz(sr + SRS * u, part);
   }
 #pragma unroll
-  for (int u = 0; u < NB; ++u) ob[u] = (uint32_t)((c0 + sr + SRS * u) * P.Mp + part * 8);
+  for (int u = 0; u < NB; ++u) ob[u] = (uint32_t)((c0 + sr + SRS * u) * P.Mp + part * 16);
   // staged values travel by value (no addressable aggregates: they stay in
   // registers)
-  struct Stage { uint4 a0, a1, a2, a3, b0, b1, b2, b3; };
+  struct Stage { u32x4 a0, a1, a2, a3, b0, b1, b2, b3; };
+  // buffer loads: one uniform descriptor per operand array and a 32-bit lane
+  // offset (no 64-bit lane addresses); the step's offset goes in soffset
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void*)P.xs, 0, P.opbytes, KS_RSRC3);
+  const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc((void*)P.rq, 0, P.opbytes, KS_RSRC3);
   auto load = [&](int s) -> Stage {
-    const bool first = !KIN && (int64_t)s * KS_K < P.Mp;
-    const int64_t k = (int64_t)s * KS_K - (KIN || first ? 0 : P.Mp);
-    const uint16_t* pa = (first ? P.xh : P.rh) + k;
-    const uint16_t* pb = (first ? P.rh : P.xh) + k;
+    const bool first = !KIN && s * KS_K < P.Mp;
+    const int k = s * KS_K - (KIN || first ? 0 : (int)P.Mp);
+    const __amdgpu_buffer_rsrc_t ra = first ? rx : rr, rb = first ? rr : rx;
     Stage R;
-    R.a0 = *reinterpret_cast<const uint4*>(pa + oa[0]);
-    R.a1 = *reinterpret_cast<const uint4*>(pa + oa[1]);
-    R.a2 = *reinterpret_cast<const uint4*>(pa + oa[2]);
-    R.a3 = *reinterpret_cast<const uint4*>(pa + oa[3]);
-    R.b0 = *reinterpret_cast<const uint4*>(pb + ob[0]);
-    R.b1 = *reinterpret_cast<const uint4*>(pb + ob[1]);
-    R.b2 = *reinterpret_cast<const uint4*>(pb + ob[2]);
-    R.b3 = *reinterpret_cast<const uint4*>(pb + ob[3]);
+    R.a0 = __builtin_amdgcn_raw_buffer_load_b128(ra, (int)oa[0], k, 0);
+    R.a1 = __builtin_amdgcn_raw_buffer_load_b128(ra, (int)oa[1], k, 0);
+    R.a2 = __builtin_amdgcn_raw_buffer_load_b128(ra, (int)oa[2], k, 0);
+    R.a3 = __builtin_amdgcn_raw_buffer_load_b128(ra, (int)oa[3], k, 0);
+    R.b0 = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)ob[0], k, 0);
+    R.b1 = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)ob[1], k, 0);
+    R.b2 = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)ob[2], k, 0);
+    R.b3 = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)ob[3], k, 0);
     return R;
   };
   auto store = [&](Stage R, int buf) {
-    *reinterpret_cast<uint4*>(As[buf] + wa[0]) = R.a0;
-    *reinterpret_cast<uint4*>(As[buf] + wa[1]) = R.a1;
-    *reinterpret_cast<uint4*>(As[buf] + wa[2]) = R.a2;
-    *reinterpret_cast<uint4*>(As[buf] + wa[3]) = R.a3;
-    *reinterpret_cast<uint4*>(Bs[buf] + wa[0]) = R.b0;
-    *reinterpret_cast<uint4*>(Bs[buf] + wa[1]) = R.b1;
-    *reinterpret_cast<uint4*>(Bs[buf] + wa[2]) = R.b2;
-    *reinterpret_cast<uint4*>(Bs[buf] + wa[3]) = R.b3;
+    *reinterpret_cast<u32x4*>(As[buf] + wa[0]) = R.a0;
+    *reinterpret_cast<u32x4*>(As[buf] + wa[1]) = R.a1;
+    *reinterpret_cast<u32x4*>(As[buf] + wa[2]) = R.a2;
+    *reinterpret_cast<u32x4*>(As[buf] + wa[3]) = R.a3;
+    *reinterpret_cast<u32x4*>(Bs[buf] + wa[0]) = R.b0;
+    *reinterpret_cast<u32x4*>(Bs[buf] + wa[1]) = R.b1;
+    *reinterpret_cast<u32x4*>(Bs[buf] + wa[2]) = R.b2;
+    *reinterpret_cast<u32x4*>(Bs[buf] + wa[3]) = R.b3;
   };
-  floatx4 acc[KS_WM][KS_WN];
+  intx4 iacc[KS_WM][KS_WN];
 #pragma unroll
   for (int m = 0; m < KS_WM; ++m)
 #pragma unroll
-    for (int q = 0; q < KS_WN; ++q) acc[m][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < KS_WN; ++q) iacc[m][q] = intx4{0, 0, 0, 0};
   const int wr = (w / KS_WC) * (KS_WM * 16), wc = (w % KS_WC) * (KS_WN * 16);
   // fragments of k-substep h: lane l reads row (block base + l % 16), chunk
   // 4h + l / 16
@@ -510,15 +525,15 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   auto compute = [&](int buf) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      halfx8 bf[KS_WN];
+      intx4 bf[KS_WN];
 #pragma unroll
-      for (int q = 0; q < KS_WN; ++q) bf[q] = *reinterpret_cast<const halfx8*>(Bs[buf] + fb[q][h]);
+      for (int q = 0; q < KS_WN; ++q) bf[q] = *reinterpret_cast<const intx4*>(Bs[buf] + fb[q][h]);
 #pragma unroll
       for (int m = 0; m < KS_WM; ++m) {
-        const halfx8 af = *reinterpret_cast<const halfx8*>(As[buf] + fa[m][h]);
+        const intx4 af = *reinterpret_cast<const intx4*>(As[buf] + fa[m][h]);
 #pragma unroll
         for (int q = 0; q < KS_WN; ++q)
-          acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af, bf[q], acc[m][q], 0, 0, 0);
+          iacc[m][q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[q], iacc[m][q], 0, 0, 0);
       }
     }
   };
@@ -544,6 +559,10 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     compute(0);
     __syncthreads();
   }
+  // a = (sum of x q) / 63.5: the int32 sums are exact and below 2^24 in
+  // magnitude (127 x 2 Mp), so the float conversion is exact and the scaling
+  // rounds once (2^-24 relative, inside the slack el); converted where used
+#define KS_ACC(m, q, r) ((float)iacc[m][q][r] * REC_Q8_INV)
   // Epilogue: lane holds rows 4*(lane/16) + r, column lane % 16 of each
   // 16x16 block.  Each element first meets per-row and per-column necessary
   // conditions (a few ALU operations); the rare survivors go to a block
@@ -669,9 +688,9 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         const int li = wr + m * 16 + 4 * (elane >> 4) + r;
         const int64_t i = r0 + li;
         {   // row pre-test from the stored threshold (see below)
-          float mx = fabsf(acc[m][0][r]);
+          float mx = fabsf(KS_ACC(m, 0, r));
 #pragma unroll
-          for (int q = 1; q < KS_WN; ++q) mx = fmaxf(mx, fabsf(acc[m][q][r]));
+          for (int q = 1; q < KS_WN; ++q) mx = fmaxf(mx, fabsf(KS_ACC(m, q, r)));
           const float qg = r == 0 ? q4.x : r == 1 ? q4.y : r == 2 ? q4.z : q4.w;
           if (__ballot(mx >= qg) == 0) continue;
         }
@@ -688,7 +707,7 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
         for (int q = 0; q < KS_WN; ++q) {
           const int bit = (m * 4 + r) * KS_WN + q;
-          const float aa = fabsf(acc[m][q][r]);
+          const float aa = fabsf(KS_ACC(m, q, r));
           if (MODE == 0 && !ROBUST) {
             // sampling estimate: histogram e^2 / (2c) (the quadratic model of
             // the gain) inline, no queue
@@ -799,10 +818,11 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     for (int q = tid; q < KS_BINS; q += KS_THREADS)
       if (hs[q]) atomicAdd(&P.hist[q], hs[q]);
 }
+#undef KS_ACC
 
 // Current couplings (w0 != 0), first pass, before the full pass's threshold
 // is taken: one wavefront per coupling forms a, the gradient at the current
-// state, from the fp16 rows (error bounded as for the contraction) and keeps
+// state, from the int8 rows (error bounded as for the contraction) and keeps
 // it in wa.  The contraction histograms every pair as if it were new,
 // couplings included; here each coupling adds one count in the bin of an
 // upper bound on the value the contraction could have binned for it (a off
@@ -823,24 +843,24 @@ __global__ __launch_bounds__(256) void k_ks_couple_a(KScreenArgs P, const int32_
   const int64_t e_end = min(nnz, ((int64_t)blockIdx.x + 1) * KS_CA_PER_BLOCK);
   for (int64_t e = (int64_t)blockIdx.x * KS_CA_PER_BLOCK + (threadIdx.x / REC_WAVE); e < e_end; e += 4) {
     const int64_t i = wi[e], j = wj[e];
-    const uint16_t* ri = P.rh + i * P.Mp;
-    const uint16_t* xj = P.xh + j * P.Mp;
-    const uint16_t* rj = P.rh + j * P.Mp;
-    const uint16_t* xi = P.xh + i * P.Mp;
-    float acc = 0.f;
-    for (int64_t k = (int64_t)lane * 8; k < P.Mp; k += 8 * REC_WAVE) {
-      const halfx8 a = *reinterpret_cast<const halfx8*>(ri + k);
-      const halfx8 b = *reinterpret_cast<const halfx8*>(xj + k);
+    const int8_t* ri = P.rq + i * P.Mp;
+    const int8_t* xj = P.xs + j * P.Mp;
+    const int8_t* rj = P.rq + j * P.Mp;
+    const int8_t* xi = P.xs + i * P.Mp;
+    int isum = 0;   // exact: |sum| <= 127 x 2 Mp
+    for (int64_t k = (int64_t)lane * 16; k < P.Mp; k += 16 * REC_WAVE) {
+      const intx4 a = *reinterpret_cast<const intx4*>(ri + k);
+      const intx4 b = *reinterpret_cast<const intx4*>(xj + k);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) acc += (float)a[q] * (float)b[q];
+      for (int q = 0; q < 4; ++q) isum = __builtin_amdgcn_sdot4(a[q], b[q], isum, false);
       if (!KIN) {
-        const halfx8 c = *reinterpret_cast<const halfx8*>(rj + k);
-        const halfx8 d = *reinterpret_cast<const halfx8*>(xi + k);
+        const intx4 c = *reinterpret_cast<const intx4*>(rj + k);
+        const intx4 d = *reinterpret_cast<const intx4*>(xi + k);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc += (float)c[q] * (float)d[q];
+        for (int q = 0; q < 4; ++q) isum = __builtin_amdgcn_sdot4(c[q], d[q], isum, false);
       }
     }
-    acc = rec_wave_sum(acc);
+    const float acc = (float)rec_wave_sum(isum) * REC_Q8_INV;
     if (lane == 0) {
       wa[e] = acc;
       const float er = P.ce * (P.l1[i] + (KIN ? 0.f : P.l1[j])) + P.el;
@@ -1012,8 +1032,9 @@ rec_status launch_ks(rec_ctx* ctx, const KScreenArgs& P, int nbi, int nbj, int r
 KScreenArgs ks_args(rec_ctx* ctx) {
   const int kin = ctx->cfg.model == REC_KINETIC;
   KScreenArgs P;
-  P.xh = ctx->F.xh;
-  P.rh = ctx->F.rh;
+  P.xs = ctx->F.xs;
+  P.rq = ctx->F.rq;
+  P.opbytes = (int)((ctx->cfg.N + REC_TAIL_ROWS) * ctx->F.Mp);
   P.N = ctx->cfg.N;
   P.Mp = ctx->F.Mp;
   const int64_t K = kin ? ctx->F.Mp : 2 * ctx->F.Mp;
@@ -1022,11 +1043,12 @@ KScreenArgs ks_args(rec_ctx* ctx) {
   P.cv = ctx->sc_cv;
   P.cvmin = ctx->sc_tau + 3;
   P.lam = (float)ctx->cfg.lambda;
-  // fp16 rounding of r (and of its float source), fp32 accumulation over K terms
-  P.ce = (float)(std::ldexp(1.0, -11) * (1.0 + std::ldexp(1.0, -10)) + std::ldexp(1.0, -22) +
-                 (double)K * std::ldexp(1.0, -23));
-  // lambda's float rounding, fp16 subnormals, the exact kernel's own rounding
-  P.el = (float)(1e-6 * ctx->cfg.lambda + (double)K * std::ldexp(1.0, -24) + 1e-30);
+  // The int8 copies' error on a pair is at most E_i (+ E_j for the Ising
+  // model), the per-row sums in l1 (rounded up); the int32 sums are exact.
+  P.ce = 1.0f + 1e-6f;
+  // lambda's float rounding, the one rounding of the scaled sum (2^-24 of at
+  // most 2 K), the exact kernel's own float rounding (K 2^-24)
+  P.el = (float)(1e-6 * ctx->cfg.lambda + (double)K * std::ldexp(1.0, -22) + 1e-30);
   P.W = ctx->W;
   P.oi = ctx->ts_i;
   P.oj = ctx->ts_j;
@@ -1045,7 +1067,7 @@ rec_status kscreen_candidates(rec_ctx* ctx, int64_t m, int64_t nnz, int64_t* n_o
   hipStream_t s = ctx->stream;
   const int64_t N = ctx->cfg.N;
   const int kin = ctx->cfg.model == REC_KINETIC;
-  if (ctx->sc_l1 == nullptr || ctx->F.rh == nullptr) { ctx->err = "screen buffers missing"; return REC_E_INVAL; }
+  if (ctx->sc_l1 == nullptr || ctx->F.rq == nullptr) { ctx->err = "screen buffers missing"; return REC_E_INVAL; }
   float* tau_c = ctx->sc_tau;       // threshold the collect pass uses
   float* tau_f = ctx->sc_tau + 1;   // proven threshold from the full histogram
   float* floor = ctx->sc_tau + 2;   // histogram floor of the full pass
