@@ -395,17 +395,20 @@ rec_status rec_create(const rec_config* cfg, const void* X_dev, void* ws_dev, si
   F.Mp = z.Mp;
   F.npl = z.npl;
   F.model = cfg->model;
-  // The screens compare kink sums with lambda.  The int8 copy q of y - tanh h
-  // (|.| < 2, rounded to float first: 2^-24 relative) moves each term by at
-  // most 1/127 + 2^-22 (rec_q8): M (1/127 + 2^-22 + 2^-23) for a sum.  The
-  // exact-sign part uses r_i = y - t rounded once in the working precision
-  // (<= 2^-23 per term) and float partial sums of at most 32 terms per lane in
-  // both the screen and the exact path; 0.02 covers those sums (<= 64 lanes x
-  // 2 x 32 x 32 x 2^-24 < 4e-3).
-  const double eps_sign = (double)cfg->M * std::ldexp(1.0, -22) + 0.02;
-  F.scr = cfg->lambda -
-          ((double)cfg->M * (1.0 / 127.0 + std::ldexp(1.0, -22) + std::ldexp(1.0, -23)) + eps_sign);
-  F.scra = cfg->lambda - eps_sign;
+  // The kink screens compare sums of int8 copies with lambda.  Each copy
+  // q = round(63.5 (y - tanh h)) (of the float-rounded value) is off by at
+  // most 1/127 + 2^-22 a term (rec_q8), so a one-sided sum over M samples is
+  // off the exact residual sum by M (1/127 + 2^-22), two sides by twice that;
+  // the sums themselves are exact integers and their scaling rounds once
+  // (2^-24 of a value below 2 M, in the 1e-6 lambda term).  The exact path
+  // forms the same sums from working-precision values with float partial
+  // sums of at most 32 terms per lane: M 2^-22 + 0.02 covers its rounding
+  // (<= 64 lanes x 2 x 32 x 32 x 2^-24 < 4e-3).  A screened sum at most the
+  // threshold therefore proves that the exact path finds |Phi(0)| <= lambda.
+  const double eps_exact = (double)cfg->M * std::ldexp(1.0, -22) + 0.02 + 1e-6 * cfg->lambda;
+  const double side = (double)cfg->M * (1.0 / 127.0 + std::ldexp(1.0, -22));
+  F.scr = (float)(cfg->lambda - (side + eps_exact));
+  F.scr2 = (float)(cfg->lambda - (2.0 * side + eps_exact));
   auto bad = [&](rec_status st) { delete ctx; return st; };
   if (hipMemsetAsync(ctx->err_flag, 0, 16, ctx->stream) != hipSuccess) return bad(REC_E_HIP);
   if (hipMemsetAsync(ctx->counter, 0, 16 * 8, ctx->stream) != hipSuccess) return bad(REC_E_HIP);

@@ -30,8 +30,8 @@ struct Fields {
   const uint32_t* xq;
   const uint32_t* yq;
   int8_t* rq;
-  double scr;           // screen threshold: lambda minus the int8 (and float) error bound
-  double scra;          // exact-sign screen threshold: lambda minus the float rounding bound
+  float scr;            // kink screen, one int8 side: lambda minus its error bound and the exact path's rounding
+  float scr2;           // kink screen, two int8 sides (Ising): the same with both sides' bounds
   int64_t N, M, Mp;     // valid samples M, padded row length Mp = 64 * npl
   int npl;              // samples per lane
   int model;            // rec_model

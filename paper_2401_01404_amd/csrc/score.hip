@@ -704,34 +704,33 @@ __device__ __forceinline__ void fetch_t(const Fields& F, int j, R (&t)[NPL], int
 }
 
 // The i side of the screened kernels keeps only what the kink tests need in
-// registers: r_i = y_i - t_i (zero in the padding) and the sign words of the
-// inputs x_i.  Both kink sums are then one select and one add per sample:
-//   sum_m x_{j,m} r_{i,m}  (the i <- j part, exact signs)     and
-//   sum_m x_{i,m} q_{j,m} / 63.5 (the j <- i part, int8 residuals of j),
-// with padding cancelled by the zeros of r_i and q_j.  The exact path (a
-// side whose test does not settle it) reloads t_i and the int8 rows of i,
-// which the wave's previous pairs keep in cache, and evaluates the side with
-// the same arithmetic as k_score, so its results are the same bits.
+// registers: the int8 copy q_i of y_i - t_i (zero in the padding) and the
+// sign words of the inputs x_i.  Both kink sums are then one select and one
+// add per sample, in exact small integers:
+//   sum_m x_{j,m} q_{i,m}  (the i <- j part)   and
+//   sum_m x_{i,m} q_{j,m}  (the j <- i part),
+// each over 63.5, each off the exact residual sum by at most M (1/127 +
+// 2^-22) (rec_q8), with padding cancelled by the zeros of q_i and q_j.  The
+// exact path (a side whose test does not settle it) reloads t_i and the int8
+// rows of i and evaluates the side with the same arithmetic as k_score, so
+// its results are the same bits.
 template <class R, int NPL>
 struct LaneR {
-  R ri[NPL];
-  uint32_t xw;   // signs of the inputs x_i (lane word)
+  static constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  uint32_t qw[CH];   // q_i, VEC bytes per word in the lane layout
+  uint32_t xw;       // signs of the inputs x_i (lane word)
 };
 
 template <class R, int NPL, int MODEL>
 __device__ __forceinline__ void load_i_r(const Fields& F, int i, LaneR<R, NPL>& L, int lane) {
   constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
-  const int64_t row = (int64_t)i * F.Mp;
-  const R* Tr = reinterpret_cast<const R*>(F.T) + row;
-  const int8_t* Y = (MODEL == REC_KINSYM ? F.ys : F.xs) + row;
+  const int8_t* qr = F.rq + (int64_t)i * F.Mp;
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     const int64_t o = smp<VEC>(c, lane);
-    R t[VEC];
-    ld_vec<VEC>(Tr + o, t);
-    const int yb = ld_bytes<VEC>(Y + o);
-#pragma unroll
-    for (int k = 0; k < VEC; ++k) L.ri[c * VEC + k] = (R)byte_at(yb, k) - t[k];
+    if constexpr (VEC == 4) L.qw[c] = *reinterpret_cast<const uint32_t*>(qr + o);
+    else if constexpr (VEC == 2) L.qw[c] = *reinterpret_cast<const uint16_t*>(qr + o);
+    else L.qw[c] = (uint8_t)qr[o];
   }
   L.xw = F.xq[(int64_t)i * REC_WAVE + lane];
 }
@@ -783,7 +782,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   const int64_t wbeg = wave * ppw * groups;
   if (wbeg >= P) return;
   LaneR<R, NPL> L;
-  JScr<NPL, SYM> nx;   // screen data of the next pair, in flight
+  JScr<NPL, SYM> nx, nx2;   // screen data of the next two pairs, in flight
   int cur = -1;
   Work wk;
   for (int g = 0; g < groups; ++g) {
@@ -813,7 +812,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     int ii = rec_uni(__shfl(li, qq, REC_WAVE)), jj = rec_uni(__shfl(lj, qq, REC_WAVE));
     if (pair_ok(ii, jj, F.N)) fetch_scr<NPL, SYM>(F, jj, dst, lane);
   };
+  // two pairs' screen data in flight ahead of the one being tested
   if (todo) prefetch(todo, nx);
+  if (todo & (todo - 1)) prefetch(todo & (todo - 1), nx2);
   while (todo) {
     const int q = __ffsll((unsigned long long)todo) - 1;
     todo &= todo - 1;
@@ -821,7 +822,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     int i = rec_uni(__shfl(li, q, REC_WAVE)), j = rec_uni(__shfl(lj, q, REC_WAVE));
     double w0 = rec_uni(__shfl(lw, q, REC_WAVE));
     JScr<NPL, SYM> rw = nx;
-    if (todo) prefetch(todo, nx);
+    nx = nx2;
+    if (todo & (todo - 1)) prefetch(todo & (todo - 1), nx2);
     uint64_t o = slot ? (uint64_t)(slot[p] & ~OWNER) : (uint64_t)p;
     double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
     if (!pair_ok(i, j, F.N)) {
@@ -833,24 +835,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
       continue;
     }
     if (i != cur) { load_i_r<R, NPL, MODEL>(F, i, L, lane); cur = i; ++wk.iloads; }
-    R sa = R(0);
-    float sb = 0.f;   // sum of x_i q_j: an integer below 2^24 in magnitude, exact in float
+    // integer sums (|.| <= 127 M < 2^24: exact in float, also the wave sums)
+    float sa = 0.f, sb = 0.f;
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
-      sa += ((rw.xw >> k) & 1u) ? L.ri[k] : -L.ri[k];
-      const float h = q_at<NPL>(rw.qw, k);
-      sb += ((L.xw >> k) & 1u) ? h : -h;
+      const float qi = q_at<NPL>(L.qw, k), qj = q_at<NPL>(rw.qw, k);
+      sa += ((rw.xw >> k) & 1u) ? qi : -qi;
+      sb += ((L.xw >> k) & 1u) ? qj : -qj;
     }
-    sb *= REC_Q8_INV;
     bool na, nb = false;
     if constexpr (MODEL == REC_ISING) {
-      na = w0 != 0.0 || fabs(rec_wave_sum_dpp((double)sa + (double)sb)) > F.scr;
+      na = w0 != 0.0 || fabsf(rec_wave_sum(sa + sb)) * REC_Q8_INV > F.scr2;
       ++wk.pairs;
       if (!na) ++wk.screened;
     } else {
       const double w0b = rec_uni(__shfl(lw2, q, REC_WAVE));
-      na = w0 != 0.0 || fabs(rec_wave_sum_dpp((double)sa)) > F.scra;
-      nb = w0b != 0.0 || fabs(rec_wave_sum_dpp((double)sb)) > F.scr;
+      na = w0 != 0.0 || fabsf(rec_wave_sum(sa)) * REC_Q8_INV > F.scr;
+      nb = w0b != 0.0 || fabsf(rec_wave_sum(sb)) * REC_Q8_INV > F.scr;
       wk.pairs += 2;
       wk.screened += (na ? 0 : 1) + (nb ? 0 : 1);
     }
@@ -874,7 +875,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const int64_t M = F.M, rs = sizeof(R);
     const int64_t items = SYM ? wk.pairs / 2 : wk.pairs;
     const int64_t sbytes = (M + 7) / 8 * (SYM ? 2 : 1) + M;   // signs + int8 residuals
-    wk.bytes = items * (16 + (slot ? 4 : 0) + sbytes) + wk.iloads * (rs * M + M + (M + 7) / 8);
+    wk.bytes = items * (16 + (slot ? 4 : 0) + sbytes) + wk.iloads * (M + (M + 7) / 8);
     wk.flush(work, wave);
   }
 }
@@ -1314,7 +1315,7 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
                           double* w_out, const Cache* C, const ScoreScratch& ss) {
   // pairs per wave: owner mode reads 64 candidates, of which only the owned
   // (new) pairs are scored: most candidates after the first iteration are cache hits
-  const int ppw = owned ? 64 : 8;
+  const int ppw = owned ? 64 : 16;
   int64_t waves = (P + ppw - 1) / ppw;
   int64_t blocks = (waves * REC_WAVE + 255) / 256;
   double* ovf = C ? C->ovf : nullptr;
