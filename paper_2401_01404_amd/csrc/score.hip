@@ -714,11 +714,20 @@ __device__ __forceinline__ void fetch_t(const Fields& F, int j, R (&t)[NPL], int
 // exact path (a side whose test does not settle it) reloads t_i and the int8
 // rows of i and evaluates the side with the same arithmetic as k_score, so
 // its results are the same bits.
+// Bits b_0..b_3 of a sign nibble spread to the bytes of a word (byte k = b_k):
+// the multiply moves bit k to bit 8k, no two partial products overlap.
+__device__ __forceinline__ uint32_t spread01(uint32_t nib) { return (nib * 0x00204081u) & 0x01010101u; }
+// The same as +-1 bytes (0x01 for a set bit, 0xFF otherwise): 0xFE times a 0/1
+// byte never carries into the next byte.
+__device__ __forceinline__ uint32_t spread_pm1(uint32_t nib) { return ~(spread01(nib) * 0xFEu); }
+
 template <class R, int NPL>
 struct LaneR {
   static constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
   uint32_t qw[CH];   // q_i, VEC bytes per word in the lane layout
+  uint32_t pm[CH];   // x_i as +-1 bytes in the same layout (0 past VEC bytes)
   uint32_t xw;       // signs of the inputs x_i (lane word)
+  int sq;            // sum of the lane's q_i
 };
 
 template <class R, int NPL, int MODEL>
@@ -733,6 +742,13 @@ __device__ __forceinline__ void load_i_r(const Fields& F, int i, LaneR<R, NPL>& 
     else L.qw[c] = (uint8_t)qr[o];
   }
   L.xw = F.xq[(int64_t)i * REC_WAVE + lane];
+  L.sq = 0;
+  constexpr uint32_t vmask = VEC == 4 ? 0xffffffffu : (1u << (8 * VEC)) - 1u;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    L.pm[c] = spread_pm1((L.xw >> (c * VEC)) & ((1u << VEC) - 1u)) & vmask;
+    L.sq = __builtin_amdgcn_sdot4((int)L.qw[c], 0x01010101, L.sq, false);
+  }
 }
 
 // exact-path i side: t_i and the int8 rows (targets, and inputs for the
@@ -782,7 +798,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   const int64_t wbeg = wave * ppw * groups;
   if (wbeg >= P) return;
   LaneR<R, NPL> L;
-  JScr<NPL, SYM> nx, nx2;   // screen data of the next two pairs, in flight
+  JScr<NPL, SYM> nx, nx2, nx3, nx4;   // screen data of the next four pairs, in flight
   int cur = -1;
   Work wk;
   for (int g = 0; g < groups; ++g) {
@@ -800,21 +816,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
       li = I[p0 + lane];
       lj = J[p0 + lane];
       if (Smap) lj = Smap[lj];
-      if (pair_ok(li, lj, F.N)) {
-        lw = lookup_w(W, li, lj, SYM);
-        if constexpr (SYM) lw2 = lookup_w(W, lj, li, true);
-      }
     }
   }
   uint64_t todo = __ballot(lane < np && li != SKIP);
-  auto prefetch = [&](uint64_t bits, JScr<NPL, SYM>& dst) {
-    const int qq = __ffsll((unsigned long long)bits) - 1;
+  uint64_t pf = todo;   // pairs whose screen data is not yet requested
+  auto prefetch = [&](JScr<NPL, SYM>& dst) {
+    const int qq = __ffsll((unsigned long long)pf) - 1;
+    pf &= pf - 1;
     int ii = rec_uni(__shfl(li, qq, REC_WAVE)), jj = rec_uni(__shfl(lj, qq, REC_WAVE));
     if (pair_ok(ii, jj, F.N)) fetch_scr<NPL, SYM>(F, jj, dst, lane);
   };
-  // two pairs' screen data in flight ahead of the one being tested
-  if (todo) prefetch(todo, nx);
-  if (todo & (todo - 1)) prefetch(todo & (todo - 1), nx2);
+  // four pairs' screen data in flight ahead of the one being tested, issued
+  // before the weight lookups (hash probes) so that the probes' latency
+  // overlaps the rows' (and the first i row's)
+  if (pf) prefetch(nx);
+  if (pf) prefetch(nx2);
+  if (pf) prefetch(nx3);
+  if (pf) prefetch(nx4);
+  if (todo && g == 0) {
+    const int i0 = rec_uni(__shfl(li, __ffsll((unsigned long long)todo) - 1, REC_WAVE));
+    if (i0 >= 0 && i0 < F.N) { load_i_r<R, NPL, MODEL>(F, i0, L, lane); cur = i0; ++wk.iloads; }
+  }
+  if (lane < np && li != SKIP && pair_ok(li, lj, F.N)) {
+    lw = lookup_w(W, li, lj, SYM);
+    if constexpr (SYM) lw2 = lookup_w(W, lj, li, true);
+  }
   while (todo) {
     const int q = __ffsll((unsigned long long)todo) - 1;
     todo &= todo - 1;
@@ -823,7 +849,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     double w0 = rec_uni(__shfl(lw, q, REC_WAVE));
     JScr<NPL, SYM> rw = nx;
     nx = nx2;
-    if (todo & (todo - 1)) prefetch(todo & (todo - 1), nx2);
+    nx2 = nx3;
+    nx3 = nx4;
+    if (pf) prefetch(nx4);
     uint64_t o = slot ? (uint64_t)(slot[p] & ~OWNER) : (uint64_t)p;
     double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
     if (!pair_ok(i, j, F.N)) {
@@ -835,23 +863,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
       continue;
     }
     if (i != cur) { load_i_r<R, NPL, MODEL>(F, i, L, lane); cur = i; ++wk.iloads; }
-    // integer sums (|.| <= 127 M < 2^24: exact in float, also the wave sums)
-    float sa = 0.f, sb = 0.f;
+    // integer sums with 4-way byte dot products: sum x_j q_i = 2 (sum of q_i
+    // where x_j = +1) - sum q_i, and sum x_i q_j against x_i's +-1 bytes
+    // (|.| <= 127 M: exact, also the wave sums)
+    int sa = 0, sb = 0;
 #pragma unroll
-    for (int k = 0; k < NPL; ++k) {
-      const float qi = q_at<NPL>(L.qw, k), qj = q_at<NPL>(rw.qw, k);
-      sa += ((rw.xw >> k) & 1u) ? qi : -qi;
-      sb += ((L.xw >> k) & 1u) ? qj : -qj;
+    for (int c = 0; c < LaneR<R, NPL>::CH; ++c) {
+      constexpr int VEC = LaneR<R, NPL>::VEC;
+      sa = __builtin_amdgcn_sdot4((int)L.qw[c], (int)spread01((rw.xw >> (c * VEC)) & ((1u << VEC) - 1u)), sa, false);
+      sb = __builtin_amdgcn_sdot4((int)rw.qw[c], (int)L.pm[c], sb, false);
     }
+    sa = 2 * sa - L.sq;
     bool na, nb = false;
     if constexpr (MODEL == REC_ISING) {
-      na = w0 != 0.0 || fabsf(rec_wave_sum(sa + sb)) * REC_Q8_INV > F.scr2;
+      na = w0 != 0.0 || (float)abs(rec_wave_sum_dpp(sa + sb)) * REC_Q8_INV > F.scr2;
       ++wk.pairs;
       if (!na) ++wk.screened;
     } else {
       const double w0b = rec_uni(__shfl(lw2, q, REC_WAVE));
-      na = w0 != 0.0 || fabsf(rec_wave_sum(sa)) * REC_Q8_INV > F.scr;
-      nb = w0b != 0.0 || fabsf(rec_wave_sum(sb)) * REC_Q8_INV > F.scr;
+      na = w0 != 0.0 || (float)abs(rec_wave_sum_dpp(sa)) * REC_Q8_INV > F.scr;
+      nb = w0b != 0.0 || (float)abs(rec_wave_sum_dpp(sb)) * REC_Q8_INV > F.scr;
       wk.pairs += 2;
       wk.screened += (na ? 0 : 1) + (nb ? 0 : 1);
     }
@@ -1315,7 +1346,7 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
                           double* w_out, const Cache* C, const ScoreScratch& ss) {
   // pairs per wave: owner mode reads 64 candidates, of which only the owned
   // (new) pairs are scored: most candidates after the first iteration are cache hits
-  const int ppw = owned ? 64 : 16;
+  const int ppw = owned ? 64 : 32;
   int64_t waves = (P + ppw - 1) / ppw;
   int64_t blocks = (waves * REC_WAVE + 255) / 256;
   double* ovf = C ? C->ovf : nullptr;
