@@ -441,9 +441,25 @@ def scaling_study(sizes, prec, kappas=(1.0, 4.0), reps=3):
                 _, _, _, st = ctx.find_best(ctx.m, "nndescent")
                 torch.cuda.synchronize()
                 ts.append((time.perf_counter() - t) * 1e3)
+            # the recursion's node counts against the paper's prediction [Sec. 3,
+            # Eq. s]: s_{t+1} = F(ceil(4 kappa / s_t)), F the tail distribution of
+            # the degrees of the graph of the pairs found, s_0 = 1; "one_step"
+            # applies it to each measured s_t
+            level_n = ctx.search_levels()
+            I, J, _, _ = ctx.find_best(ctx.m, "nndescent")
+            deg = np.bincount(np.concatenate([I.cpu().numpy(), J.cpu().numpy()]), minlength=N)
+            tail = np.cumsum(np.bincount(deg)[::-1])[::-1] / N      # tail[d] = F(d)
+            F = lambda d: float(tail[d]) if d < len(tail) else 0.0
+            pred, s_t = [1.0], 1.0
+            while len(pred) < len(level_n) + 2 and s_t > 0:
+                s_t = F(int(math.ceil(4 * kappa / s_t)))
+                pred.append(s_t)
+            one_step = [None] + [F(int(math.ceil(4 * ctx.m / n_t))) for n_t in level_n[:-1]]
             rows.append({"N": N, "kappa": kappa, "m": ctx.m, "find_best_ms": float(np.median(ts)),
                          "pair_evals": st["pair_evals"], "nnd_iters": st["nnd_iters"],
-                         "levels": st["levels"]})
+                         "levels": st["levels"], "s_t": [n_t / N for n_t in level_n],
+                         "s_t_predicted": pred[:len(level_n)],
+                         "s_t_one_step": one_step})
             print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
             del ctx
         del X

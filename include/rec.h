@@ -191,6 +191,15 @@ rec_status rec_grad_pairs(rec_ctx* ctx, int64_t P, const int32_t* i_dev, const i
 rec_status rec_find_best_candidates(rec_ctx* ctx, int64_t m, int32_t search, int32_t* i_dev, int32_t* j_dev,
                          double* gain_dev, int64_t* n_out_host, rec_sweep_stats* stats_host);
 
+/* Node count N_t of every recursion level t of the last FindBest search
+ * [Alg. 3] on this context (the set S of level t; N_0 = N): *levels_host gets
+ * the number of levels (0 after an exhaustive or screened search, which has
+ * none), level_n_host its first min(cap, levels) counts.  Host-only; no
+ * device work.  For comparing the recursion with Sec. 3's prediction
+ * s_{t+1} = F(ceil(4 kappa / s_t)), s_t = N_t / N, F the tail distribution
+ * of the degrees of the pairs found. */
+rec_status rec_search_levels(rec_ctx* ctx, int32_t cap, int64_t* level_n_host, int32_t* levels_host);
+
 /* One GCD iteration [Alg. 2]: E_best = FindBest(m = round(kappa N)); every
  * pair of E_best updated to its argmax in rank order (run as node-disjoint
  * rounds, for the kinetic model as one chain per target row, either of which

@@ -27,7 +27,7 @@ SYMBOLS = ["rec_workspace_size", "rec_create", "rec_destroy", "rec_score_pairs",
            "rec_kernel_time", "rec_status_str", "rec_last_error", "rec_sketch", "rec_mlp_params",
            "rec_mlp_infer", "rec_mlp_grad", "rec_mlp_train", "rec_surrogate_config",
            "rec_surrogate_stats", "rec_screen_time", "rec_grad_pairs", "rec_score_pairs_noalloc",
-           "rec_cd_sweep"]
+           "rec_cd_sweep", "rec_search_levels"]
 SUR_NPARAM = 41345
 SUR_SKETCH_DIM = 64
 SUR_MAX_BATCH = 8192
@@ -82,6 +82,7 @@ def lib():
             "rec_find_best_candidates": [vp, i64, i32, vp, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(SweepStats)],
             "rec_gcd_sweep": [vp, i32, ctypes.POINTER(SweepStats)],
             "rec_cd_sweep": [vp, ctypes.POINTER(SweepStats)],
+            "rec_search_levels": [vp, i32, vp, ctypes.POINTER(i32)],
             "rec_apply_updates": [vp, i64, vp, vp, ctypes.POINTER(dbl)],
             "rec_theta_update": [vp, ctypes.POINTER(dbl)],
             "rec_objective": [vp, ctypes.POINTER(dbl)],
@@ -241,6 +242,13 @@ class Context:
         st = SweepStats()
         self._check(lib().rec_gcd_sweep(self.h, SEARCH[search], ctypes.byref(st)), self.h)
         return st.as_dict()
+
+    def search_levels(self):
+        """Node counts N_t of the levels of the last FindBest search."""
+        buf = (ctypes.c_int64 * 64)()
+        n = ctypes.c_int32()
+        self._check(lib().rec_search_levels(self.h, 64, ctypes.cast(buf, ctypes.c_void_p), ctypes.byref(n)), self.h)
+        return [int(buf[l]) for l in range(n.value)]
 
     def cd_sweep(self):
         """One coordinate-descent sweep [Alg. 1] in round-robin order."""

@@ -65,7 +65,9 @@ rec_status plan(const rec_config* c, Sizes* z, const char** why) {
   // slot words: cache slots + overflow slots must stay below 2^31 (top bit = owner)
   int lc = c->log2_cache;
   if (lc <= 0) {
-    int64_t target = std::min<int64_t>(4 * z->cand_cap, 2 * pairs + 1024);
+    // every pair a FindBest call scores, at a load of at most a half where
+    // memory allows (about N k^2 per NNDescent level; 1024 N covers it)
+    int64_t target = std::min<int64_t>(std::max<int64_t>(4 * z->cand_cap, 1024 * N), 2 * pairs + 1024);
     lc = 16;
     while ((int64_t(1) << lc) < target && lc < 30) ++lc;
   }
@@ -608,6 +610,13 @@ rec_status rec_cd_sweep(rec_ctx* ctx, rec_sweep_stats* st) {
     S.t_theta_ms = t2 - t1;
     *st = S;
   }
+  return REC_OK;
+}
+
+rec_status rec_search_levels(rec_ctx* ctx, int32_t cap, int64_t* level_n_host, int32_t* levels_host) {
+  if (!ctx || !levels_host || cap < 0 || (cap > 0 && !level_n_host)) return REC_E_INVAL;
+  *levels_host = ctx->last_levels;
+  for (int l = 0; l < ctx->last_levels && l < cap; ++l) level_n_host[l] = ctx->last_level_n[l];
   return REC_OK;
 }
 

@@ -83,6 +83,8 @@ struct rec_ctx {
   int dev;
   void* noalloc_scratch = nullptr;   // this device's address of the static scratch
   double* cd_acc = nullptr;          // CD sweep: |dW| per round-robin pair slot (N/2 + 1)
+  int64_t last_level_n[64] = {};     // node count of each FindBest level of the last search
+  int32_t last_levels = 0;
   rec_status state = REC_OK;
   std::string err;
   bool fp32;

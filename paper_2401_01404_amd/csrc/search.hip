@@ -1077,6 +1077,9 @@ struct Search {
         for (int64_t a0 = 0; a0 < n; a0 += per) {
           const int64_t a1 = std::min(n, a0 + per);
           hipMemsetAsync(d_cur, 0, sizeof(int64_t), s);
+          // the overflow area holds the scores of the chunk's candidates that
+          // found no cache slot; the chunk's merge is their last reader
+          hipMemsetAsync(d_ovf_n, 0, sizeof(int64_t), s);
           hipLaunchKernelGGL(k_cand_once, dim3(a1 - a0), dim3(BT), once_lds, s, P, level, a0, a1, (int)lcap,
                              ctx->cnt, ctx->off, d_cur, ctx->cand_cap, ctx->cand_v, ctx->cand_gi,
                              ctx->cand_slot, A);
@@ -1125,6 +1128,7 @@ struct Search {
         while (a1 < n && hoff[a1 + 1] - hoff[a0] <= ctx->cand_cap) ++a1;
         if (hoff[a1] - hoff[a0] > ctx->cand_cap) { ctx->err = "candidate buffer too small"; return REC_E_NOMEM; }
         int64_t base = hoff[a0];
+        hipMemsetAsync(d_ovf_n, 0, sizeof(int64_t), s);   // as above: one chunk's uncached scores
         hipLaunchKernelGGL(k_cand<1>, dim3(a1 - a0), dim3(BT), cand_lds, s, P, level, a0, a1, ctx->cnt,
                            ctx->off, base, ctx->cand_v, ctx->cand_gi, ctx->cand_slot, A);
         const int64_t nch = hoff[a1] - hoff[a0];
@@ -1529,6 +1533,11 @@ rec_status rec_search_best(rec_ctx* ctx, int64_t m, int search, int64_t* n_out,
     r = S.find_best(m, search == REC_SEARCH_EXACT_KNN ? 1 : 0, n_out, level_n, 64);
   }
   if (r != REC_OK) return r;
+  ctx->last_levels = 0;
+  if (search != REC_SEARCH_EXHAUSTIVE && search != REC_SEARCH_SCREEN) {
+    ctx->last_levels = (int32_t)std::min<int64_t>(S.levels, 64);
+    for (int l = 0; l < ctx->last_levels; ++l) ctx->last_level_n[l] = level_n[l];
+  }
   if (st) {
     int64_t w1[REC_WORK_N];
     if (rec_work_read(ctx, w1) != REC_OK) return REC_E_HIP;
