@@ -70,7 +70,7 @@ typedef enum {
   REC_SEARCH_SCREEN = 4,      /* every pair screened at once by an MFMA
                                  contraction of samples with residuals (the
                                  gradient at the current state, Gaussian: BF16,
-                                 Ising/kinetic: FP16) under proven bounds on
+                                 Ising/kinetic: int8) under proven bounds on
                                  each pair's gain; survivors and current
                                  couplings rescored exactly.  Returns the
                                  exhaustive search's positive-gain top m
@@ -337,7 +337,7 @@ rec_status rec_surrogate_stats(rec_ctx* ctx, double* out_host);
  * launches and eight work counters (work_host: 8 int64, may be NULL): pairs
  * scored, moment passes, full Newton evaluations, log passes (each pass is
  * one sweep over the M samples of the pair's one or two sides), pair sides
- * settled by the fp16 residual screen, j-side rows fetched, i-side row
+ * settled by the int8 residual screen, j-side rows fetched, i-side row
  * loads, and the algorithmic bytes the kernels read and write (indices,
  * scores and the rows they need, at M samples).  Synchronises; resets the
  * sums. */

@@ -220,14 +220,6 @@ __device__ __forceinline__ int8_t rec_q8(float r) {
   return (int8_t)fminf(fmaxf(v, -127.f), 127.f);
 }
 
-// fp16 bits of v (round to nearest even) and back
-__device__ __forceinline__ uint16_t rec_f16_bits(float v) {
-  return __builtin_bit_cast(uint16_t, (_Float16)v);
-}
-__device__ __forceinline__ float rec_f16_val(uint32_t bits16) {
-  return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
-}
-
 // numerics shared by the kernels (double)
 __device__ __forceinline__ double rec_lcosh_tau(double tau) {   // log cosh(atanh tau)
   return -0.5 * log1p(-tau * tau);

@@ -156,7 +156,7 @@ struct rec_ctx {
   int sc_kp = 0;
   float *sc_nrm = nullptr, *sc_th2 = nullptr, *sc_sq = nullptr, *sc_tau = nullptr;
   // Ising / kinetic screen: per node |r_i|_1 and curvature sum (1 - t^2);
-  // per current coupling its gradient from the fp16 rows (max_nnz)
+  // per current coupling its gradient from the int8 rows (max_nnz)
   float *sc_l1 = nullptr, *sc_cv = nullptr, *sc_wa = nullptr;
   // screen instrumentation: [0] full-pass ms, [1] full-pass launches, [2]
   // their algorithmic flops, [3] sample-pass ms, [4] sample launches, [5]

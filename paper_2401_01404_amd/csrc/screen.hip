@@ -219,15 +219,14 @@ __global__ void k_screen_tau(const uint32_t* hist, int64_t target, float* tau) {
 // bounds brackets the best gain of the L1-penalised step [Alg. 2, function D]:
 //   (c/4) phi(q) <= gain <= (c/4) psi(q),   q = 2e/c,
 //   phi(q) = (1 + q) ln(1 + q) - q,   psi(q) = q + (1 - q) ln(1 - q)  (q < 1; else no bound),
-// and gain = 0 when |a| <= lambda (the kink test).  a is formed in FP16 on the
-// matrix cores (x = +-1 exact; r rounded to fp16 with relative error 2^-11)
-// with FP32 accumulation, so |a - a_exact| <= ce (|r_i|_1 + |r_j|_1) + el.
+// and gain = 0 when |a| <= lambda (the kink test).  a is formed on the int8
+// matrix cores from x = +-1 and the int8 residual copies q = round(63.5 r)
+// with exact int32 sums, so |a - a_exact| <= ce (E_i + E_j) + el, E_i the
+// row's summed quantisation error (sum of |r - q / 63.5|).
 // The two passes then run as for the Gaussian screen: a histogram of the
 // lower bounds gives tau, and every w0 = 0 pair whose upper bound reaches tau
 // goes to the exact score kernel together with the current couplings.  The
 // result equals the exhaustive search's positive-gain top m.
-
-typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 struct KScreenArgs {
   const int8_t* xs;     // (N + REC_TAIL_ROWS) x Mp int8 input side (+-1; padding and tail rows 0)
@@ -370,9 +369,9 @@ __device__ __forceinline__ bool ks_tile(const TileMap& T, int b, int* bi, int* b
 
 // One KS_BM x KS_BN tile of the contraction per block (8 waves of 128 x 64,
 // each 8 x 4 MFMA 16x16x64 int8 blocks with int32 accumulators: the +-1
-// samples times the int8 residual copies sum exactly).  Operands go global -> registers two k
-// steps ahead of use and registers -> LDS one step ahead (LDS double-buffered),
-// so a load has two steps of MFMA work to arrive.  Ising: tiles that hold a
+// samples times the int8 residual copies sum exactly).  Operands go global ->
+// LDS directly, one step ahead of use (LDS double-buffered), and a tile's
+// first step loads during the previous tile's epilogue.  Ising: tiles that hold a
 // pair i < j, k in [0, Mp) pairs x_i with r_j and k in [Mp, 2Mp) r_i with x_j.
 // Kinetic: every tile, rows are targets (r_i), columns sources (x_j).
 // MODE 0: histogram of lower bounds; 1: collect pairs whose upper bound
@@ -395,11 +394,16 @@ static_assert(KS_BM % (KS_THREADS / 8) == 0 && KS_BN % (KS_THREADS / 8) == 0, "s
 template <int MODE, int KIN, int ROBUST>
 __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_kscreen(KScreenArgs P, TileMap TM, int row_step, int* tctr, int nvirt) {
   constexpr bool HIST = MODE != 1, COLLECT = MODE != 0;
-  __shared__ __attribute__((aligned(16))) int8_t As[2][KS_BM * KS_K];
-  __shared__ __attribute__((aligned(16))) int8_t Bs[2][KS_BN * KS_K];
+  // operand buffers (two steps of each operand), separate objects so that
+  // reads of one need not wait on loads landing in another
+  __shared__ __attribute__((aligned(16))) int8_t As0[KS_BM * KS_K], As1[KS_BM * KS_K];
+  __shared__ __attribute__((aligned(16))) int8_t Bs0[KS_BN * KS_K], Bs1[KS_BN * KS_K];
   __shared__ uint32_t hs[HIST ? KS_BINS : 1];
   __shared__ uint32_t kq_key[KS_Q];   // bit 31 histogram, bit 30 collect; row << 8 | column in the tile
-  __shared__ float kq_e[KS_Q], kq_c[KS_Q];
+  __shared__ float kq_e[KS_Q];
+  // the tile's raw per-row and per-column terms (|r|_1 and c), loaded with
+  // the operands' first step
+  __shared__ float tl1r[KS_BM], tcvr[KS_BM], tl1c[KS_BN], tcvc[KS_BN];
   __shared__ int kq_n, kc_n;
   __shared__ int64_t kbase;
   __shared__ int s_q;
@@ -438,7 +442,71 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     if (tid == 0) ob_n = 0;
     __syncthreads();
   };
+  // Staging: operands go global -> LDS directly (buffer loads to LDS, no
+  // registers): one wave instruction fills 8 rows of 128 bytes, lane l
+  // moving row R + l/8 into slot l % 8, which under the swizzle holds sample
+  // chunk (l % 8) ^ (l / 8) (R is a multiple of 8).  Wave w fills rows
+  // 8 w + SRS u of both operands.  Operand rows are int8 (the +-1 input side
+  // and the residual copies) with zero rows past N, so no load needs a bound
+  // check.  Ising: in the first half of k, A = x and B = r; in the second,
+  // A = r and B = x.  Kinetic: A = r (targets), B = x (sources).  Rows hold a
+  // multiple of KS_K samples, so a step lies inside one half.
+  constexpr int SRS = KS_THREADS / 8;   // rows per staging round (all waves)
+  constexpr int NA = KS_BM / SRS, NB = KS_BN / SRS;
+  static_assert(KS_THREADS / REC_WAVE >= 4 && KS_BM == 4 * REC_WAVE && KS_BN == 4 * REC_WAVE, "term loads");
+  const int n = P.nsteps;
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  const int srow = 8 * wu + (lane >> 3), schunk = (lane & 7) ^ (lane >> 3);
+  const uint32_t ostep = (uint32_t)(SRS * P.Mp);   // global offset between staging rounds
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void*)P.xs, 0, P.opbytes, KS_RSRC3);
+  const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc((void*)P.rq, 0, P.opbytes, KS_RSRC3);
+  // the per-row terms: reads past N return 0 (range-checked buffer loads)
+  const __amdgpu_buffer_rsrc_t rl1 = __builtin_amdgcn_make_buffer_rsrc((void*)P.l1, 0, (int)(P.N * 4), KS_RSRC3);
+  const __amdgpu_buffer_rsrc_t rcv = __builtin_amdgcn_make_buffer_rsrc((void*)P.cv, 0, (int)(P.N * 4), KS_RSRC3);
+  // step s of the tile at rows r0, columns c0 into LDS buffers A, B
+  auto issue = [&](int s, int64_t r0, int64_t c0, int8_t* A, int8_t* B) {
+    const bool first = !KIN && s * KS_K < P.Mp;
+    const int k = s * KS_K - (KIN || first ? 0 : (int)P.Mp);
+    const __amdgpu_buffer_rsrc_t ra = first ? rx : rr, rb = first ? rr : rx;
+    const uint32_t oa0 = (uint32_t)((r0 + srow) * P.Mp + schunk * 16);
+    const uint32_t ob0 = (uint32_t)((c0 + srow) * P.Mp + schunk * 16);
+#pragma unroll
+    for (int u = 0; u < NA; ++u)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (__attribute__((address_space(3))) void*)(A + (8 * wu + SRS * u) * KS_K),
+                                               16, (int)(oa0 + u * ostep), k, 0, 0);
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (__attribute__((address_space(3))) void*)(B + (8 * wu + SRS * u) * KS_K),
+                                               16, (int)(ob0 + u * ostep), k, 0, 0);
+  };
+  // the first step of a tile and its row and column terms (waves 0-3: 64
+  // rows or columns of one term each)
+  auto issue_tile = [&](int64_t r0, int64_t c0) {
+    issue(0, r0, c0, As0, Bs0);
+    if (wu < 4) {
+      const __amdgpu_buffer_rsrc_t rt = (wu & 1) ? rcv : rl1;
+      float* dst = wu == 0 ? tl1r : wu == 1 ? tcvr : wu == 2 ? tl1c : tcvc;
+      const int64_t base = wu < 2 ? r0 : c0;
+      for (int h = 0; h < 4; ++h)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rt, (__attribute__((address_space(3))) void*)(dst + h * REC_WAVE), 4,
+                                                 (int)((base + h * REC_WAVE + lane) * 4), 0, 0, 0);
+    }
+  };
+  // this wave's loads to LDS have landed (the barrier that follows makes
+  // every wave's visible)
+  auto landed = [&]() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); };
+  // tile of virtual block index v: its rows and columns, false if it has no
+  // pair to score
+  auto tile_of = [&](int v, int64_t* r0, int64_t* c0) -> bool {
+    int bi, bj;
+    bool ok = v < nvirt && ks_tile(TM, v, &bi, &bj);
+    *r0 = (int64_t)(bi * row_step) * KS_BM;
+    *c0 = (int64_t)bj * KS_BN;
+    if (!KIN && *r0 >= *c0 + KS_BN - 1) ok = false;   // no pair i < j in the tile
+    return ok;
+  };
   int tq = s_q;
+  bool pre = false;   // the tile's first step was loaded during the last epilogue
   for (;;) {
   const int vb = tq * 8 + xcd;
   if (vb >= nvirt) break;
@@ -448,64 +516,9 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     kq_n = 0;
     kc_n = 0;
   }
-  int bi, bj;
-  bool ok = ks_tile(TM, vb, &bi, &bj);
-  bi *= row_step;
-  const int64_t r0 = (int64_t)bi * KS_BM, c0 = (int64_t)bj * KS_BN;
-  if (!KIN && r0 >= c0 + KS_BN - 1) ok = false;   // no pair i < j in the tile
+  int64_t r0, c0;
+  const bool ok = tile_of(vb, &r0, &c0);
   if (ok) {
-  // Staging: thread tid moves the 16-sample chunk (tid & 7) of rows tid/8 +
-  // (KS_THREADS/8) u of both operands.  Operand rows are int8 (the +-1 input
-  // side and the residual copies) with zero rows past N, so no load needs a
-  // bound check.  Ising: in the first half of k, A = x and B = r; in the
-  // second, A = r and B = x.  Kinetic: A = r (targets), B = x (sources).
-  // Rows hold a multiple of KS_K samples, so a step lies inside one half.
-  constexpr int SRS = KS_THREADS / 8;   // staging row stride
-  constexpr int NA = KS_BM / SRS, NB = KS_BN / SRS;
-  static_assert(NA == 4 && NB == 4, "stage layout below holds four rows per operand");
-  const int n = P.nsteps;
-  const int sr = tid >> 3, part = tid & 7;
-  uint32_t oa[NA], ob[NB];
-  int wa[NA];
-#pragma unroll
-  for (int u = 0; u < NA; ++u) {
-    oa[u] = (uint32_t)((r0 + sr + SRS * u) * P.Mp + part * 16);
-    wa[u] = ks_swz(sr + SRS * u, part);
-  }
-#pragma unroll
-  for (int u = 0; u < NB; ++u) ob[u] = (uint32_t)((c0 + sr + SRS * u) * P.Mp + part * 16);
-  // staged values travel by value (no addressable aggregates: they stay in
-  // registers)
-  struct Stage { u32x4 a0, a1, a2, a3, b0, b1, b2, b3; };
-  // buffer loads: one uniform descriptor per operand array and a 32-bit lane
-  // offset (no 64-bit lane addresses); the step's offset goes in soffset
-  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void*)P.xs, 0, P.opbytes, KS_RSRC3);
-  const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc((void*)P.rq, 0, P.opbytes, KS_RSRC3);
-  auto load = [&](int s) -> Stage {
-    const bool first = !KIN && s * KS_K < P.Mp;
-    const int k = s * KS_K - (KIN || first ? 0 : (int)P.Mp);
-    const __amdgpu_buffer_rsrc_t ra = first ? rx : rr, rb = first ? rr : rx;
-    Stage R;
-    R.a0 = __builtin_amdgcn_raw_buffer_load_b128(ra, (int)oa[0], k, 0);
-    R.a1 = __builtin_amdgcn_raw_buffer_load_b128(ra, (int)oa[1], k, 0);
-    R.a2 = __builtin_amdgcn_raw_buffer_load_b128(ra, (int)oa[2], k, 0);
-    R.a3 = __builtin_amdgcn_raw_buffer_load_b128(ra, (int)oa[3], k, 0);
-    R.b0 = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)ob[0], k, 0);
-    R.b1 = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)ob[1], k, 0);
-    R.b2 = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)ob[2], k, 0);
-    R.b3 = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)ob[3], k, 0);
-    return R;
-  };
-  auto store = [&](Stage R, int buf) {
-    *reinterpret_cast<u32x4*>(As[buf] + wa[0]) = R.a0;
-    *reinterpret_cast<u32x4*>(As[buf] + wa[1]) = R.a1;
-    *reinterpret_cast<u32x4*>(As[buf] + wa[2]) = R.a2;
-    *reinterpret_cast<u32x4*>(As[buf] + wa[3]) = R.a3;
-    *reinterpret_cast<u32x4*>(Bs[buf] + wa[0]) = R.b0;
-    *reinterpret_cast<u32x4*>(Bs[buf] + wa[1]) = R.b1;
-    *reinterpret_cast<u32x4*>(Bs[buf] + wa[2]) = R.b2;
-    *reinterpret_cast<u32x4*>(Bs[buf] + wa[3]) = R.b3;
-  };
   intx4 iacc[KS_WM][KS_WN];
 #pragma unroll
   for (int m = 0; m < KS_WM; ++m)
@@ -522,43 +535,41 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
     for (int f = 0; f < KS_WN; ++f) fb[f][h] = ks_swz(wc + f * 16 + (lane & 15), 4 * h + (lane >> 4));
   }
-  auto compute = [&](int buf) {
+  auto compute = [&](const int8_t* A, const int8_t* B) {
+    __builtin_amdgcn_iglp_opt(0);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       intx4 bf[KS_WN];
 #pragma unroll
-      for (int q = 0; q < KS_WN; ++q) bf[q] = *reinterpret_cast<const intx4*>(Bs[buf] + fb[q][h]);
+      for (int q = 0; q < KS_WN; ++q) bf[q] = *reinterpret_cast<const intx4*>(B + fb[q][h]);
 #pragma unroll
       for (int m = 0; m < KS_WM; ++m) {
-        const intx4 af = *reinterpret_cast<const intx4*>(As[buf] + fa[m][h]);
+        const intx4 af = *reinterpret_cast<const intx4*>(A + fa[m][h]);
 #pragma unroll
         for (int q = 0; q < KS_WN; ++q)
           iacc[m][q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[q], iacc[m][q], 0, 0, 0);
       }
     }
   };
-  // The loop body has no branches, so every iteration leaves the same loads
-  // in flight and none is waited on before its data is needed; past the end,
-  // loads repeat the last step and the stores land in a buffer nobody reads.
-  // An odd last step (already in buffer 0) runs after the loop.
-  Stage R0 = load(0), R1 = load(min(1, n - 1));
-  store(R0, 0);
+  // Step s reads buffer s % 2 while step s + 1 lands in the other, which
+  // every wave finished reading at the barrier ending step s - 1.  The loop
+  // body has no branches: past the end, the last step loads again into a
+  // buffer nobody reads (it lands before the barrier).
+  if (!pre) issue_tile(r0, c0);
+  landed();
   __syncthreads();
-  // step s reads LDS buffer s % 2; registers hold step s + 1 while step s + 2 loads
   for (int s = 0; s + 1 < n; s += 2) {
-    R0 = load(min(s + 2, n - 1));
-    compute(0);
-    store(R1, 1);
+    issue(s + 1, r0, c0, As1, Bs1);
+    compute(As0, Bs0);
+    landed();
     __syncthreads();
-    R1 = load(min(s + 3, n - 1));
-    compute(1);
-    store(R0, 0);
-    __syncthreads();
-  }
-  if (n & 1) {
-    compute(0);
+    issue(min(s + 2, n - 1), r0, c0, As0, Bs0);
+    compute(As1, Bs1);
+    landed();
     __syncthreads();
   }
+  // (an odd last step reads buffer 0; the epilogue's LDS lies in buffer 1)
+  if (n & 1) compute(As0, Bs0);
   // a = (sum of x q) / 63.5: the int32 sums are exact and below 2^24 in
   // magnitude (127 x 2 Mp), so the float conversion is exact and the scaling
   // rounds once (2^-24 relative, inside the slack el); converted where used
@@ -590,14 +601,13 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   // Kinetic: also each row's pre-test threshold (its gate, or lambda + er_i
   // for the sampling estimate, less a float slack), so that a wave reads four
   // rows' thresholds with one load.
-  float4* rowv = reinterpret_cast<float4*>(&As[0][0]);
+  float4* rowv = reinterpret_cast<float4*>(As1);
   float4* colv = rowv + KS_BM;
   float* qrow = reinterpret_cast<float*>(colv + KS_BN);
   for (int t = tid; t < KS_BM + KS_BN; t += KS_THREADS) {
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
     if (t < KS_BM) {
-      const int64_t i = r0 + t;
-      const float l1 = i < P.N ? P.l1[i] : 0.f, c = i < P.N ? P.cv[i] : 0.f;
+      const float l1 = tl1r[t], c = tcvr[t];   // 0 past N
       v = make_float4(P.ce * l1 + P.el, c, thr_up(c + cmin), thr_lo(c + cmin));
       rowv[t] = v;
       if (KIN) {
@@ -609,8 +619,7 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         qrow[t] = qg;
       }
     } else if (!KIN) {
-      const int64_t j = c0 + (t - KS_BM);
-      const float l1 = j < P.N ? P.l1[j] : 0.f, c = j < P.N ? P.cv[j] : 0.f;
+      const float l1 = tl1c[t - KS_BM], c = tcvc[t - KS_BM];   // 0 past N
       v = make_float4(P.ce * l1, c, thr_up(c + cmin), thr_lo(c + cmin));
       colv[t - KS_BM] = v;
     } else {
@@ -635,6 +644,15 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     if (lane == 0) cext[(tid - KS_BM) / REC_WAVE] = make_float4(amax, amin, umin, hmin);
   }
   __syncthreads();
+  // Every thread has read the tile's terms and the operand buffers are free:
+  // the next tile's first step and terms load during the rest of the
+  // epilogue (s_q holds the next virtual block since the barrier after its
+  // atomic).
+  {
+    int64_t r0n, c0n;
+    pre = tile_of(s_q * 8 + xcd, &r0n, &c0n);
+    if (pre) issue_tile(r0n, c0n);
+  }
   if (!KIN) {
     if (tid < KS_BM) {
       float amax = cext[0].x, amin = cext[0].y, umin = cext[0].z, hmin = cext[0].w;
@@ -667,7 +685,8 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   }
   // Every element that passes its gate and the range/threshold checks
   // enters the block queue (key: bit 31 histogram, bit 30 collect, row << 8 |
-  // column; then |a| and c), which is then settled.  ROBUST: once the queue
+  // column; then |a|; c comes from the row and column terms), which is then
+  // settled.  ROBUST: once the queue
   // is full the rest wait for the next round (done bits: element (m, r, q) is
   // bit (m*4 + r)*KS_WN + q) until a round fits; otherwise one round, and an
   // overflow is flagged for the caller.  MODE 0 without ROBUST is the
@@ -742,7 +761,6 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
               if (p < KS_Q) {
                 kq_key[p] = (h ? 0x80000000u : 0u) | (cc ? 0x40000000u : 0u) | (uint32_t)li << 8 | (uint32_t)lj;
                 kq_e[p] = aa;
-                kq_c[p] = rcv + ccv[q];
               } else {
                 fin = false;
               }
@@ -764,7 +782,11 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int t = u * KS_THREADS + tid;
-      if (t < nq) { key[u] = kq_key[t]; av[u] = kq_e[t]; cv2[u] = kq_c[t]; }
+      if (t < nq) {
+        key[u] = kq_key[t];
+        av[u] = kq_e[t];
+        cv2[u] = rowv[(key[u] >> 8) & 255].y + colv[key[u] & 255].y;   // c of the pair, as the gate formed it
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -809,6 +831,8 @@ __global__ __launch_bounds__(KS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     if (tid == 0) { kq_n = 0; kc_n = 0; }
     __syncthreads();
   }
+  } else {
+    pre = false;
   }   // tile
   __syncthreads();
   tq = s_q;

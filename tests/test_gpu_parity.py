@@ -505,7 +505,7 @@ def lambda_in_gap(phi):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_screen_zero_set_ising(c1, prec):
     """With lambda inside the bulk of |Phi(0)|, about half the pairs sit below
-    the kink; the fp16 residual screen must settle exactly the pairs the
+    the kink; the int8 residual screen must settle exactly the pairs the
     exact kink test zeroes: the zero sets agree with the oracle's, and the
     other gains agree to tolerance.  Checked at W = 0 and at W != 0."""
     I, J = all_pairs(c1.N)
@@ -628,7 +628,7 @@ def screen_equals_exhaustive(C, m):
 @pytest.mark.parametrize("model", ["ising", "kinetic"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_screen_search_equals_exhaustive(model, prec):
-    """The FP16 MFMA screen with its curvature bounds drops no pair of the top
+    """The int8 MFMA screen with its curvature bounds drops no pair of the top
     m: the screened search returns exactly the exhaustive search's
     positive-gain top m (kinetic: ordered pairs), at W = 0 and at W != 0."""
     w = SCREEN_CASES[model]()
