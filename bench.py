@@ -73,17 +73,20 @@ BATCH_PER_NODE = 16
 # HBM traffic of the pair-score kernels on the batch (k_kink + k_exact) per
 # algorithmic byte, from two rocprofv3 --pmc runs (FETCH_SIZE, then
 # WRITE_SIZE) of `bench.py --steps 1 --warmup 0 --no-cpu --no-compare
-# --only-batch`, each scaled by a plain 1 GiB device copy (`bench.py
+# --also=`, each scaled by a plain 1 GiB device copy (`bench.py
 # --copy-probe 1024`: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE
 # 1.0x).  Valid only for the score kernel source it was measured on.
 TRAFFIC = {
-    "C4s": {"source_sha256": "bdb4787b37bd8893401e9e3a3f48ca5743bbccfa9d2ed46ee77ee269d5738eca",
-            "hbm_over_algorithmic": 0.9985},
+    "C4s": {"source_sha256": "72c8196a1b07feb8edc1b914a5cbb6eb6bec1dd040c0bcf6eae2eeb507755d0f",
+            "hbm_over_algorithmic": 1.2221},
 }
 
 # HBM traffic of the contraction's full pass (k_kscreen) per launch, from the
 # same kind of counter runs; valid only for the source it was measured on.
-TRAFFIC_SCREEN = {}
+TRAFFIC_SCREEN = {
+    "C4s": {"source_sha256": "49f81fec4650db837e5b82348936afa3383ad88a8bfbabbd0eea5ea5c5a53284",
+            "hbm_bytes_per_launch": 1.8212e10},
+}
 
 
 def source_sha(name="score.hip"):
@@ -165,19 +168,20 @@ def cpu_baseline(w, lam, I, J, seconds):
     O = oracle.Oracle(w.X, w.model, lam)
     O.score_pairs(I[:256], J[:256])          # thread-pool start
     n, dt, size, pos = 0, 0.0, 4096, 0
-    while dt < seconds and n < len(I):
+    while dt < seconds:
         a, b = pos, min(pos + size, len(I))
         t = time.perf_counter()
         O.score_pairs(I[a:b], J[a:b])
         dt += time.perf_counter() - t
         n += b - a
-        pos = b
+        pos = b % len(I)
         size = min(size * 2, 1 << 18)
     cores = oracle.threads()
     return {"value": n / dt, "unit": "pair-score evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"the first {n} pairs of the batch ({BATCH_PER_NODE} uniform partners per node, "
-                      f"grouped by node) at W=0, theta fitted; FP64, {dt:.1f} s on {cores} threads "
-                      f"of {oracle.cpu_model()}; oracle built -O3 -march=native -ffp-contract=off"}
+            "sample": f"{n} pair solves over the batch in order, cycled ({len(I)} pairs: {BATCH_PER_NODE} "
+                      f"uniform partners per node, grouped by node) at W=0, theta fitted; FP64, {dt:.1f} s "
+                      f"on {cores} threads of {oracle.cpu_model()}; oracle built -O3 -march=native "
+                      f"-ffp-contract=off"}
 
 
 def restore(ctx, model):
