@@ -42,17 +42,17 @@ sys.path.insert(0, ROOT)
 
 WORKLOADS = {
     "C4s": "Ising pseudolikelihood, N=100000, M=1000 +-1 Gibbs samples, random 3-regular graph, "
-           "w~U[-0.4,0.4], kappa=4 (m=400000), FP32 scores with FP64 sums",
+           "w~U[-0.4,0.4], FP32 scores with FP64 sums",
     "C4": "kinetic Ising time series, N=100000, T=1000 transitions of +-1 spins under parallel "
-          "Glauber updates, directed ER mean out-degree 5, w~N(0,0.3^2), kappa=4 (m=400000), "
+          "Glauber updates, directed ER mean out-degree 5, w~N(0,0.3^2), "
           "FP32 scores with FP64 sums",
     "C3": "Gaussian pseudolikelihood, N=20000, M=200 float32 samples from N(0, Theta^-1), ER mean "
-          "degree 4, offdiag U[-0.2,0.2], diagonally dominant, kappa=4 (m=80000)",
+          "degree 4, offdiag U[-0.2,0.2], diagonally dominant",
     "C2": "Ising pseudolikelihood, N=10000, M=1000 +-1 Gibbs samples, random 3-regular graph, "
-          "w~U[-0.4,0.4], kappa=4 (m=40000), FP32 scores with FP64 sums",
-    "C1": "Ising pseudolikelihood, N=100, M=500 +-1 Gibbs samples, ER mean degree 3, kappa=4",
+          "w~U[-0.4,0.4], FP32 scores with FP64 sums",
+    "C1": "Ising pseudolikelihood, N=100, M=500 +-1 Gibbs samples, ER mean degree 3",
     "C5": "Ising pseudolikelihood, N=1000000, M=100 +-1 Gibbs samples, ER mean degree 3, "
-          "w~N(0,0.3^2), kappa=4 (m=4000000), FP32 scores with FP64 sums",
+          "w~N(0,0.3^2), FP32 scores with FP64 sums",
 }
 
 # Algorithmic FP32 work of the pair-score kernels, counted per executed pass
@@ -243,7 +243,7 @@ def run_workload(name, args, torch, rec, synth, headline):
     t_gen = time.perf_counter() - t_gen
     print(f"{name}: generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
     lam = synth.sparsity_lambda(w.X, w.model)
-    kappa = 4.0
+    kappa = args.kappa
     m = int(np.floor(kappa * w.N + 0.5))
     sweeps = args.warmup + args.steps + 8
     # each sweep adds at most m couplings: room for every sweep this run makes
@@ -328,6 +328,7 @@ def main():
     ap.add_argument("--also", default="C4", help="further workloads measured the same way (comma list, "
                                                   "'' for none), reported under legs")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--kappa", type=float, default=4.0, help="m = kappa N best pairs per sweep")
     ap.add_argument("--search", default="screen",
                     choices=["nndescent", "exhaustive", "exact_knn", "screen", "gradient", "surrogate"])
     ap.add_argument("--compare", default="nndescent,surrogate,gradient,screen")
@@ -387,7 +388,7 @@ def main():
         "dtype": "f32" if args.prec == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "N": w.N, "M": w.M,
-                   "kappa": 4.0, "m": ctx.m, "lambda": lam,
+                   "kappa": args.kappa, "m": ctx.m, "lambda": lam,
                    "lambda_rule": "sparsity target q=N noise pairs at W=0", "search": args.search,
                    "batch": f"{BATCH_PER_NODE} uniform partners per node, {len(I)} pairs",
                    "parallelism": "single GPU"},
