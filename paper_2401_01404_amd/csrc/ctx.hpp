@@ -5,12 +5,14 @@
 #include <stdint.h>
 
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
 #include "../../include/rec.h"
+#include "common.hpp"
 
-constexpr int64_t REC_TAIL_ROWS = 256;   // zero rows after the N rows of rh and xh
+constexpr int64_t REC_TAIL_ROWS = 256;   // zero rows after the N rows of xs and rq
 
 // Device view of the data and fields, passed by value to kernels.
 struct Fields {
@@ -21,14 +23,15 @@ struct Fields {
   void* T;              // N x Mp tanh(H) (Ising/kinetic), real
   const double* sq;     // Gaussian: ||x_i||^2
   double* theta;        // N
-  // Ising / kinetic screen data.  xq, yq: N x 64 lane words, bit c*VEC + k of
-  // lane l is sample c*64*VEC + l*VEC + k of xs (yq: ys) being +1 (padding
+  // Ising / kinetic screen data.  xq, yq: N x 64 lane words of npl bits
+  // (16-bit words when npl <= 16, else 32-bit: rec_sign_word), bit c*VEC + k
+  // of lane l is sample c*64*VEC + l*VEC + k of xs (yq: ys) being +1 (padding
   // reads as -1 and is cancelled by zeros on the other side); rq: N x Mp
   // int8 residuals q = round(63.5 (y - tanh h)) (padding 0).  rq and xs
   // carry REC_TAIL_ROWS zero rows past N (the contraction's tiles never need
   // a bound check).
-  const uint32_t* xq;
-  const uint32_t* yq;
+  const void* xq;
+  const void* yq;
   int8_t* rq;
   float scr;            // kink screen, one int8 side: lambda minus its error bound and the exact path's rounding
   float scr2;           // kink screen, two int8 sides (Ising): the same with both sides' bounds
@@ -36,6 +39,15 @@ struct Fields {
   int npl;              // samples per lane
   int model;            // rec_model
 };
+
+// lane word of the sign rows xq / yq: npl bits per lane, stored in 16 bits
+// when they fit (the row is then 128 bytes), else 32
+template <int NPL>
+using rec_sign_t = typename std::conditional<(NPL <= 16), uint16_t, uint32_t>::type;
+template <int NPL>
+__device__ __forceinline__ uint32_t rec_sign_word(const void* q, int64_t row, int lane) {
+  return (uint32_t)reinterpret_cast<const rec_sign_t<NPL>*>(q)[row * REC_WAVE + lane];
+}
 
 // Open-addressing table of W entries: key = pair key, value = weight.
 struct WTable {

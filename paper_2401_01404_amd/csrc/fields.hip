@@ -75,7 +75,7 @@ __global__ __launch_bounds__(FT) void k_load_int8(const int8_t* __restrict__ X, 
 // Lane words of the screen: bit c*VEC + k of lane l = sample
 // c*64*VEC + l*VEC + k is +1 (one wave per node).
 __global__ __launch_bounds__(REC_WAVE) void k_pack_bits(const int8_t* __restrict__ x, int64_t Mp,
-                                                        int npl, uint32_t* __restrict__ q) {
+                                                        int npl, void* __restrict__ q) {
   const int64_t i = blockIdx.x;
   const int l = threadIdx.x;
   const int vec = npl < 4 ? npl : 4, ch = npl / vec;
@@ -85,7 +85,10 @@ __global__ __launch_bounds__(REC_WAVE) void k_pack_bits(const int8_t* __restrict
       int64_t s = (int64_t)c * REC_WAVE * vec + (int64_t)l * vec + k;
       if (x[i * Mp + s] > 0) w |= 1u << (c * vec + k);
     }
-  q[i * REC_WAVE + l] = w;
+  if (npl <= 16)
+    reinterpret_cast<uint16_t*>(q)[i * REC_WAVE + l] = (uint16_t)w;
+  else
+    reinterpret_cast<uint32_t*>(q)[i * REC_WAVE + l] = w;
 }
 
 __global__ __launch_bounds__(FT) void k_load_f32(const float* __restrict__ X, int64_t ldx, int64_t M,
@@ -596,10 +599,10 @@ rec_status rec_load_data(rec_ctx* ctx, const void* X, int64_t ldx) {
                        ctx->F.M, ctx->F.Mp, ctx->cfg.model == REC_KINETIC ? 1 : 0,
                        (int8_t*)ctx->F.xs, (int8_t*)ctx->F.ys, ctx->err_flag);
     hipLaunchKernelGGL(k_pack_bits, dim3(N), dim3(REC_WAVE), 0, ctx->stream, ctx->F.xs, ctx->F.Mp,
-                       ctx->F.npl, const_cast<uint32_t*>(ctx->F.xq));
+                       ctx->F.npl, const_cast<void*>(ctx->F.xq));
     if (ctx->cfg.model == REC_KINETIC)
       hipLaunchKernelGGL(k_pack_bits, dim3(N), dim3(REC_WAVE), 0, ctx->stream, ctx->F.ys, ctx->F.Mp,
-                         ctx->F.npl, const_cast<uint32_t*>(ctx->F.yq));
+                         ctx->F.npl, const_cast<void*>(ctx->F.yq));
     // zero tail rows of the contraction's operands
     const size_t tail = (size_t)(REC_TAIL_ROWS * ctx->F.Mp);
     REC_HIP(hipMemsetAsync(const_cast<int8_t*>(ctx->F.xs) + N * ctx->F.Mp, 0, tail, ctx->stream));

@@ -674,8 +674,8 @@ struct JScr {
 template <int NPL, bool SYM>
 __device__ __forceinline__ void fetch_scr(const Fields& F, int j, JScr<NPL, SYM>& r, int lane) {
   constexpr int VEC = JScr<NPL, SYM>::VEC, CH = JScr<NPL, SYM>::CH;
-  r.xw = F.xq[(int64_t)j * REC_WAVE + lane];
-  if constexpr (SYM) r.yw = F.yq[(int64_t)j * REC_WAVE + lane];
+  r.xw = rec_sign_word<NPL>(F.xq, j, lane);
+  if constexpr (SYM) r.yw = rec_sign_word<NPL>(F.yq, j, lane);
   const int8_t* qr = F.rq + (int64_t)j * F.Mp;
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
@@ -741,7 +741,7 @@ __device__ __forceinline__ void load_i_r(const Fields& F, int i, LaneR<R, NPL>& 
     else if constexpr (VEC == 2) L.qw[c] = *reinterpret_cast<const uint16_t*>(qr + o);
     else L.qw[c] = (uint8_t)qr[o];
   }
-  L.xw = F.xq[(int64_t)i * REC_WAVE + lane];
+  L.xw = rec_sign_word<NPL>(F.xq, i, lane);
   L.sq = 0;
   constexpr uint32_t vmask = VEC == 4 ? 0xffffffffu : (1u << (8 * VEC)) - 1u;
 #pragma unroll
@@ -949,7 +949,7 @@ __global__ __launch_bounds__(256) void k_exact(Fields F, WTable W, double lambda
     uint64_t o = slot ? (uint64_t)(slot[p] & ~OWNER) : (uint64_t)p;
     double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
     if (i != cur) { load_i_exact<R, NPL, MODEL>(F, i, ti, yb, xb, lane); cur = i; ++wk.iloads; }
-    const uint32_t xw = F.xq[(int64_t)j * REC_WAVE + lane];
+    const uint32_t xw = rec_sign_word<NPL>(F.xq, j, lane);
     PairOut r;
     if constexpr (MODEL == REC_ISING) {
       const double w0 = rec_uni(lookup_w(W, i, j, false));
@@ -1000,7 +1000,7 @@ __global__ __launch_bounds__(256) void k_exact(Fields F, WTable W, double lambda
       }
       if (nb) {
         ++wk.tfetch;
-        const uint32_t yw = F.yq[(int64_t)j * REC_WAVE + lane];
+        const uint32_t yw = rec_sign_word<NPL>(F.yq, j, lane);
         fetch_t<R, NPL>(F, j, wv, lane);
         float s2 = 0.f;
         R b = R(0);
