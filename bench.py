@@ -77,8 +77,8 @@ BATCH_PER_NODE = 16
 # --copy-probe 1024`: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE
 # 1.0x).  Valid only for the score kernel source it was measured on.
 TRAFFIC = {
-    "C4s": {"source_sha256": "72c8196a1b07feb8edc1b914a5cbb6eb6bec1dd040c0bcf6eae2eeb507755d0f",
-            "hbm_over_algorithmic": 1.2221},
+    "C4s": {"source_sha256": "98ab2652db7263ade26a36a525d84b531d5b40a6d315dbf3190ecefb414d8221",
+            "hbm_over_algorithmic": 1.1092},
 }
 
 # HBM traffic of the contraction's full pass (k_kscreen) per launch, from the

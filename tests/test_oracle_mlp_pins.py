@@ -127,3 +127,46 @@ def test_sketch_statistics_closed_forms():
     assert np.allclose(S[:, 61], np.log1p(deg)) and np.allclose(S[:, 62], mass)
     # with couplings the fields vary across samples: var t > 0 on coupled nodes
     assert np.all(S[[0, 3, 5, 7], 58] > 0) and np.allclose(S[[1, 2], 58], 0, atol=1e-12)
+
+
+def test_sketch_noise_is_the_projection_limit():
+    """The sketch's estimate of Phi(0) is as good as 28 random +-1 projections
+    allow, and no better: over the pairs of C1 at W = 0 its correlation with
+    the exact Phi(0) equals the one predicted from the projection noise (the
+    variance of the estimator over independent projection draws, computed
+    here with numpy's generator, not the library's), within 0.08; the same
+    estimator with 1024 projections per half would correlate above 0.85.  So
+    the proposal's ranking is limited by what 64 numbers per node can carry
+    about a pair, while the kink test that the residual screen evaluates
+    from 1 B per sample ranks the pairs exactly."""
+    w = synth.config("C1")
+    lam = oracle.default_lambda(w.X, "ising")
+    O = oracle.Oracle(w.X, "ising", lam)
+    ei, ej, wv, th = O.get_model()
+    H = O.fields()
+    S = mlp.sketch("ising", w.X, H, th, ei, ej, wv, seed=0)
+    I, J = np.triu_indices(w.N, 1)
+    est = ((S[I, :28] * S[J, :28]).sum(1) - (S[I, 28:56] * S[J, 28:56]).sum(1)) * w.M / 56.0
+    phi = np.array([O.pair_deriv(i, j, 0.0) for i, j in zip(I, J)])
+    measured = np.corrcoef(est, phi)[0, 1]
+    x = w.X.astype(np.float64)
+    r = x - np.tanh(H)
+
+    def draws(D, n, seed):
+        """n independent estimates per pair with D projections per half."""
+        rng = np.random.default_rng(seed)
+        out = []
+        for _ in range(n):
+            P = rng.choice([-1.0, 1.0], size=(D, w.M))
+            u, v = (x + r) @ P.T, (x - r) @ P.T
+            out.append(((u[I] * u[J]).sum(1) - (v[I] * v[J]).sum(1)) / (2.0 * D))
+        return np.array(out)
+
+    E = draws(28, 48, 5)
+    assert abs(E.mean(0) - phi).max() < 6 * np.sqrt(E.var(0).max() / 48)   # unbiased
+    noise = E.var(0).mean()
+    predicted = phi.std() / np.sqrt(phi.var() + noise)
+    assert abs(measured - predicted) <= 0.08, (measured, predicted)
+    wide = np.corrcoef(draws(1024, 1, 6)[0], phi)[0, 1]
+    assert wide > 0.85, wide
+    print(f"sketch vs Phi(0): measured {measured:.3f}, predicted {predicted:.3f}, 1024 projections {wide:.3f}")
