@@ -674,12 +674,15 @@ struct JScr {
 template <int NPL, bool SYM>
 __device__ __forceinline__ void fetch_scr(const Fields& F, int j, JScr<NPL, SYM>& r, int lane) {
   constexpr int VEC = JScr<NPL, SYM>::VEC, CH = JScr<NPL, SYM>::CH;
-  r.xw = rec_sign_word<NPL>(F.xq, j, lane);
-  if constexpr (SYM) r.yw = rec_sign_word<NPL>(F.yq, j, lane);
+  // j is wave-uniform: the row bases are scalar and every lane adds a 32-bit
+  // offset (no 64-bit lane addresses)
+  using ST = rec_sign_t<NPL>;
+  r.xw = (uint32_t)(reinterpret_cast<const ST*>(F.xq) + (int64_t)j * REC_WAVE)[lane];
+  if constexpr (SYM) r.yw = (uint32_t)(reinterpret_cast<const ST*>(F.yq) + (int64_t)j * REC_WAVE)[lane];
   const int8_t* qr = F.rq + (int64_t)j * F.Mp;
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
-    const int64_t o = smp<VEC>(c, lane);
+    const uint32_t o = (uint32_t)(c * REC_WAVE * VEC + lane * VEC);
     if constexpr (VEC == 4) r.qw[c] = *reinterpret_cast<const uint32_t*>(qr + o);
     else if constexpr (VEC == 2) r.qw[c] = *reinterpret_cast<const uint16_t*>(qr + o);
     else r.qw[c] = (uint8_t)qr[o];
@@ -798,7 +801,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   const int64_t wbeg = wave * ppw * groups;
   if (wbeg >= P) return;
   LaneR<R, NPL> L;
-  JScr<NPL, SYM> nx, nx2, nx3, nx4;   // screen data of the next four pairs, in flight
+  constexpr int KD = 4;
+  JScr<NPL, SYM> nx[KD];   // screen data of the next KD pairs, in flight
   int cur = -1;
   Work wk;
   for (int g = 0; g < groups; ++g) {
@@ -829,10 +833,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   // four pairs' screen data in flight ahead of the one being tested, issued
   // before the weight lookups (hash probes) so that the probes' latency
   // overlaps the rows' (and the first i row's)
-  if (pf) prefetch(nx);
-  if (pf) prefetch(nx2);
-  if (pf) prefetch(nx3);
-  if (pf) prefetch(nx4);
+#pragma unroll
+  for (int d = 0; d < KD; ++d)
+    if (pf) prefetch(nx[d]);
   if (todo && g == 0) {
     const int i0 = rec_uni(__shfl(li, __ffsll((unsigned long long)todo) - 1, REC_WAVE));
     if (i0 >= 0 && i0 < F.N) { load_i_r<R, NPL, MODEL>(F, i0, L, lane); cur = i0; ++wk.iloads; }
@@ -841,17 +844,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     lw = lookup_w(W, li, lj, SYM);
     if constexpr (SYM) lw2 = lookup_w(W, lj, li, true);
   }
+  // Pair t of the group uses slot t % KD of the ring, refilled with pair
+  // t + KD's data once the pair is tested: no register moves between slots.
   while (todo) {
+#pragma unroll
+  for (int d = 0; d < KD; ++d) {
+    if (!todo) break;
     const int q = __ffsll((unsigned long long)todo) - 1;
     todo &= todo - 1;
     const int64_t p = p0 + q;
     int i = rec_uni(__shfl(li, q, REC_WAVE)), j = rec_uni(__shfl(lj, q, REC_WAVE));
     double w0 = rec_uni(__shfl(lw, q, REC_WAVE));
-    JScr<NPL, SYM> rw = nx;
-    nx = nx2;
-    nx2 = nx3;
-    nx3 = nx4;
-    if (pf) prefetch(nx4);
+    const JScr<NPL, SYM>& rw = nx[d];
     uint64_t o = slot ? (uint64_t)(slot[p] & ~OWNER) : (uint64_t)p;
     double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
     if (!pair_ok(i, j, F.N)) {
@@ -860,6 +864,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         if (w_out) w_out[p] = __builtin_nan("");
         atomicOr(err, 1);
       }
+      if (pf) prefetch(nx[d]);
       continue;
     }
     if (i != cur) { load_i_r<R, NPL, MODEL>(F, i, L, lane); cur = i; ++wk.iloads; }
@@ -894,6 +899,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     } else if (lane == q) {
       mine = (uint32_t)p | (na ? QA : 0u) | (nb ? QB : 0u);
     }
+    if (pf) prefetch(nx[d]);
+  }
   }
   // one atomic per wave and group for the queued pairs
   const int64_t pos = rec_append(qn, mine != 0u);
