@@ -100,9 +100,11 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
     F.xq = a.take<uint32_t>(N * 64);
     F.yq = c->model == REC_KINETIC ? a.take<uint32_t>(N * 64) : F.xq;
     F.rq = a.take<int8_t>((N + REC_TAIL_ROWS) * z.Mp);
+    F.u4 = a.take<uint32_t>(N * rec_u4_words(z.npl) * 64);
   } else {
     F.xq = F.yq = nullptr;
     F.rq = nullptr;
+    F.u4 = nullptr;
   }
   F.sq = a.take<double>(N);
   F.theta = a.take<double>(N);
@@ -411,6 +413,16 @@ rec_status rec_create(const rec_config* cfg, const void* X_dev, void* ws_dev, si
   const double side = (double)cfg->M * (1.0 / 127.0 + std::ldexp(1.0, -22));
   F.scr = (float)(cfg->lambda - (side + eps_exact));
   F.scr2 = (float)(cfg->lambda - (2.0 * side + eps_exact));
+  // The 4-bit copies u = round(7.5 (1 - y tanh h)) of 1 - y tanh h in [0, 2]
+  // (computed in float from the working-precision tanh) are off by at most
+  // 1/15 + 2^-20 a term, so with the signs exact a one-sided sum is off by
+  // M (1/15 + 2^-20).  The kink kernel forms S = 7.5 x (the screened sum) in
+  // exact integers, so |S| <= floor(7.5 (lambda - bound - eps_exact)) proves
+  // |Phi(0)| <= lambda; a pair that fails goes on to the int8 test.
+  const double side4 = (double)cfg->M * (1.0 / 15.0 + std::ldexp(1.0, -20));
+  auto t4of = [](double v) { return (int32_t)std::min(2147483647.0, std::max(-1.0, std::floor(7.5 * v))); };
+  F.t4 = t4of(cfg->lambda - (side4 + eps_exact));
+  F.t42 = t4of(cfg->lambda - (2.0 * side4 + eps_exact));
   auto bad = [&](rec_status st) { delete ctx; return st; };
   if (hipMemsetAsync(ctx->err_flag, 0, 16, ctx->stream) != hipSuccess) return bad(REC_E_HIP);
   if (hipMemsetAsync(ctx->counter, 0, 16 * 8, ctx->stream) != hipSuccess) return bad(REC_E_HIP);

@@ -30,11 +30,18 @@ struct Fields {
   // int8 residuals q = round(63.5 (y - tanh h)) (padding 0).  rq and xs
   // carry REC_TAIL_ROWS zero rows past N (the contraction's tiles never need
   // a bound check).
+  // u4: N x (rec_u4_words(npl) x 64) lane words, nibble n = c*VEC + k of
+  // lane l (word n / 8, bits 4 (n % 8)) holding round(7.5 (1 - y tanh h)) of
+  // sample c*64*VEC + l*VEC + k (0 in the padding): with the sign of y from
+  // the sign rows, y - tanh h = y (1 - y tanh h), 1 - y tanh h in [0, 2].
   const void* xq;
   const void* yq;
   int8_t* rq;
+  uint32_t* u4;
   float scr;            // kink screen, one int8 side: lambda minus its error bound and the exact path's rounding
   float scr2;           // kink screen, two int8 sides (Ising): the same with both sides' bounds
+  int32_t t4;           // kink screen, one 4-bit side: integer sums |S| <= t4 prove |Phi(0)| <= lambda
+  int32_t t42;          // kink screen, two 4-bit sides (Ising)
   int64_t N, M, Mp;     // valid samples M, padded row length Mp = 64 * npl
   int npl;              // samples per lane
   int model;            // rec_model
@@ -47,6 +54,18 @@ using rec_sign_t = typename std::conditional<(NPL <= 16), uint16_t, uint32_t>::t
 template <int NPL>
 __device__ __forceinline__ uint32_t rec_sign_word(const void* q, int64_t row, int lane) {
   return (uint32_t)reinterpret_cast<const rec_sign_t<NPL>*>(q)[row * REC_WAVE + lane];
+}
+
+// 4-bit residual rows: lane words per row and the nibble of one sample
+__host__ __device__ constexpr int rec_u4_words(int npl) { return npl < 8 ? 1 : npl / 8; }
+__device__ __forceinline__ uint32_t rec_u4(float u) {   // u = 1 - y tanh h in [0, 2]
+  return (uint32_t)fminf(fmaxf(rintf(u * 7.5f), 0.f), 15.f);
+}
+// bits b_0..b_7 of a byte spread to the nibbles of a word (nibble k = b_k)
+__device__ __forceinline__ uint32_t rec_spread8(uint32_t b) {
+  b = (b | (b << 12)) & 0x000F000Fu;
+  b = (b | (b << 6)) & 0x03030303u;
+  return (b | (b << 3)) & 0x11111111u;
 }
 
 // Open-addressing table of W entries: key = pair key, value = weight.

@@ -164,6 +164,10 @@ __global__ __launch_bounds__(FT) void k_fields(Fields F, const int64_t* __restri
   const double th = F.theta[i];
   R* H = reinterpret_cast<R*>(F.H);
   R* T = reinterpret_cast<R*>(F.T);
+  constexpr int UW = rec_u4_words(NPL);
+  uint32_t uw[UW];
+#pragma unroll
+  for (int w = 0; w < UW; ++w) uw[w] = 0u;
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     const int64_t o = L::at(c, lane), idx = i * F.Mp + o;
@@ -187,11 +191,17 @@ __global__ __launch_bounds__(FT) void k_fields(Fields F, const int64_t* __restri
         hv.v[k] = h;
         tv.v[k] = t;
         rv.v[k] = rec_q8((float)((R)y[k] - t));
+        const int n = c * VEC + k;
+        if (in) uw[n >> 3] |= rec_u4((float)(R(1) - (R)y[k] * t)) << (4 * (n & 7));
       }
       *reinterpret_cast<Pack<R, VEC>*>(H + idx) = hv;
       *reinterpret_cast<Pack<R, VEC>*>(T + idx) = tv;
       *reinterpret_cast<Pack<int8_t, VEC>*>(F.rq + idx) = rv;
     }
+  }
+  if (MODEL != REC_GAUSS) {
+#pragma unroll
+    for (int w = 0; w < UW; ++w) F.u4[(i * UW + w) * REC_WAVE + lane] = uw[w];
   }
 }
 
@@ -325,6 +335,10 @@ __global__ __launch_bounds__(FT) void k_theta(Fields F, const int64_t* __restric
         th = t;
       }
     }
+    constexpr int UW = rec_u4_words(NPL);
+    uint32_t uw[UW];
+#pragma unroll
+    for (int w = 0; w < UW; ++w) uw[w] = 0u;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int64_t idx = i * F.Mp + L::at(c, lane);
@@ -338,11 +352,15 @@ __global__ __launch_bounds__(FT) void k_theta(Fields F, const int64_t* __restric
         hv.v[k] = h;
         tv.v[k] = t;
         rv.v[k] = rec_q8((float)((R)y[c * VEC + k] - t));
+        const int n = c * VEC + k;
+        if (in) uw[n >> 3] |= rec_u4((float)(R(1) - (R)y[c * VEC + k] * t)) << (4 * (n & 7));
       }
       *reinterpret_cast<Pack<R, VEC>*>(H + idx) = hv;
       *reinterpret_cast<Pack<R, VEC>*>(T + idx) = tv;
       *reinterpret_cast<Pack<int8_t, VEC>*>(F.rq + idx) = rv;
     }
+#pragma unroll
+    for (int w = 0; w < UW; ++w) F.u4[(i * UW + w) * REC_WAVE + lane] = uw[w];
   }
   if (lane == 0) F.theta[i] = th;
 }

@@ -665,27 +665,37 @@ __global__ __launch_bounds__(256) void k_grad(Fields F, WTable W, double lambda,
 // result is the same bits either way.
 template <int NPL, bool SYM>
 struct JScr {
-  static constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  static constexpr int UW = rec_u4_words(NPL);
   uint32_t xw;             // signs of x_j (bit q = lane register q)
   uint32_t yw;             // kinetic search: signs of the targets y_j
-  uint32_t qw[CH];         // int8 copies of y_j - t_j, VEC per word (register c VEC + k in byte k of word c)
+  uint32_t uw[UW];         // 4-bit copies of 1 - y_j t_j (register q in nibble q % 8 of word q / 8)
 };
 
 template <int NPL, bool SYM>
 __device__ __forceinline__ void fetch_scr(const Fields& F, int j, JScr<NPL, SYM>& r, int lane) {
-  constexpr int VEC = JScr<NPL, SYM>::VEC, CH = JScr<NPL, SYM>::CH;
+  constexpr int UW = JScr<NPL, SYM>::UW;
   // j is wave-uniform: the row bases are scalar and every lane adds a 32-bit
   // offset (no 64-bit lane addresses)
   using ST = rec_sign_t<NPL>;
   r.xw = (uint32_t)(reinterpret_cast<const ST*>(F.xq) + (int64_t)j * REC_WAVE)[lane];
   if constexpr (SYM) r.yw = (uint32_t)(reinterpret_cast<const ST*>(F.yq) + (int64_t)j * REC_WAVE)[lane];
+  const uint32_t* ur = F.u4 + (int64_t)j * UW * REC_WAVE;
+#pragma unroll
+  for (int w = 0; w < UW; ++w) r.uw[w] = ur[w * REC_WAVE + lane];
+}
+
+// the int8 copies of y_j - t_j, VEC per word (register c VEC + k in byte k of
+// word c), for the sides the 4-bit test leaves open
+template <int NPL>
+__device__ __forceinline__ void fetch_q8(const Fields& F, int j, uint32_t (&qw)[NPL / (NPL < 4 ? NPL : 4)], int lane) {
+  constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
   const int8_t* qr = F.rq + (int64_t)j * F.Mp;
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     const uint32_t o = (uint32_t)(c * REC_WAVE * VEC + lane * VEC);
-    if constexpr (VEC == 4) r.qw[c] = *reinterpret_cast<const uint32_t*>(qr + o);
-    else if constexpr (VEC == 2) r.qw[c] = *reinterpret_cast<const uint16_t*>(qr + o);
-    else r.qw[c] = (uint8_t)qr[o];
+    if constexpr (VEC == 4) qw[c] = *reinterpret_cast<const uint32_t*>(qr + o);
+    else if constexpr (VEC == 2) qw[c] = *reinterpret_cast<const uint16_t*>(qr + o);
+    else qw[c] = (uint8_t)qr[o];
   }
 }
 
@@ -726,10 +736,13 @@ __device__ __forceinline__ uint32_t spread_pm1(uint32_t nib) { return ~(spread01
 
 template <class R, int NPL>
 struct LaneR {
-  static constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC;
+  static constexpr int VEC = NPL < 4 ? NPL : 4, CH = NPL / VEC, UW = rec_u4_words(NPL);
+  uint32_t ui[UW];   // 4-bit copies of 1 - y_i t_i (as JScr::uw)
+  int su;            // sum of the lane's 4-bit copies
   uint32_t qw[CH];   // q_i, VEC bytes per word in the lane layout
   uint32_t pm[CH];   // x_i as +-1 bytes in the same layout (0 past VEC bytes)
   uint32_t xw;       // signs of the inputs x_i (lane word)
+  uint32_t yw;       // kinetic search: signs of the targets y_i
   int sq;            // sum of the lane's q_i
 };
 
@@ -745,6 +758,13 @@ __device__ __forceinline__ void load_i_r(const Fields& F, int i, LaneR<R, NPL>& 
     else L.qw[c] = (uint8_t)qr[o];
   }
   L.xw = rec_sign_word<NPL>(F.xq, i, lane);
+  L.yw = MODEL == REC_KINSYM ? rec_sign_word<NPL>(F.yq, i, lane) : L.xw;
+  L.su = 0;
+#pragma unroll
+  for (int w = 0; w < LaneR<R, NPL>::UW; ++w) {
+    L.ui[w] = F.u4[((int64_t)i * LaneR<R, NPL>::UW + w) * REC_WAVE + lane];
+    L.su = (int)__builtin_amdgcn_udot8(L.ui[w], 0x11111111u, (uint32_t)L.su, false);
+  }
   L.sq = 0;
   constexpr uint32_t vmask = VEC == 4 ? 0xffffffffu : (1u << (8 * VEC)) - 1u;
 #pragma unroll
@@ -795,13 +815,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   constexpr bool SYM = MODEL == REC_KINSYM;
   const int lane = rec_lane();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE;
+  // byte -> its bits spread to the nibbles of a word (rec_spread8), one LDS
+  // read instead of nine ALU operations per word of signs
+  __shared__ uint32_t spread[256];
+  for (int t = threadIdx.x; t < 256; t += blockDim.x) spread[t] = rec_spread8((uint32_t)t);
+  __syncthreads();
   // a wave walks `groups` consecutive groups of ppw slots (owner mode: most
   // slots are cache hits, so one group holds few pairs; the i row and the
   // wave's set-up are shared by the groups)
   const int64_t wbeg = wave * ppw * groups;
   if (wbeg >= P) return;
   LaneR<R, NPL> L;
-  constexpr int KD = 4;
+  constexpr int KD = NPL >= 32 ? 3 : 6;
   JScr<NPL, SYM> nx[KD];   // screen data of the next KD pairs, in flight
   int cur = -1;
   Work wk;
@@ -868,26 +893,71 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
       continue;
     }
     if (i != cur) { load_i_r<R, NPL, MODEL>(F, i, L, lane); cur = i; ++wk.iloads; }
-    // integer sums with 4-way byte dot products: sum x_j q_i = 2 (sum of q_i
-    // where x_j = +1) - sum q_i, and sum x_i q_j against x_i's +-1 bytes
-    // (|.| <= 127 M: exact, also the wave sums)
-    int sa = 0, sb = 0;
-#pragma unroll
-    for (int c = 0; c < LaneR<R, NPL>::CH; ++c) {
-      constexpr int VEC = LaneR<R, NPL>::VEC;
-      sa = __builtin_amdgcn_sdot4((int)L.qw[c], (int)spread01((rw.xw >> (c * VEC)) & ((1u << VEC) - 1u)), sa, false);
-      sb = __builtin_amdgcn_sdot4((int)rw.qw[c], (int)L.pm[c], sb, false);
-    }
-    sa = 2 * sa - L.sq;
+    // The kink test in two stages.  First from the 4-bit copies u of
+    // 1 - y t (y - t = y u): with s = +-1 the product of two signs and
+    // b = (s + 1) / 2 as nibbles, sum s u = 2 (sum of u where s = +1) - sum u,
+    // in exact integers by 8-way nibble dot products (7.5 x the screened sum);
+    // a side it leaves open takes the int8 test, then the exact path.
+    constexpr int UW = LaneR<R, NPL>::UW;
     bool na, nb = false;
     if constexpr (MODEL == REC_ISING) {
-      na = w0 != 0.0 || (float)abs(rec_wave_sum_dpp(sa + sb)) * REC_Q8_INV > F.scr2;
+      // Phi(0) = sum x_i x_j (u_i + u_j) (y = x)
+      const uint32_t sx = ~(L.xw ^ rw.xw);
+      uint32_t v = 0, uj = 0;
+#pragma unroll
+      for (int w = 0; w < UW; ++w) {
+        const uint32_t b = spread[(sx >> (8 * w)) & 0xffu];
+        v = __builtin_amdgcn_udot8(b, L.ui[w], v, false);
+        v = __builtin_amdgcn_udot8(b, rw.uw[w], v, false);
+        uj = __builtin_amdgcn_udot8(0x11111111u, rw.uw[w], uj, false);
+      }
+      na = w0 != 0.0 || abs(rec_wave_sum_dpp(2 * (int)v - L.su - (int)uj)) > F.t42;
+      if (na && w0 == 0.0) {
+        uint32_t qw[LaneR<R, NPL>::CH];
+        fetch_q8<NPL>(F, j, qw, lane);
+        // sum x_j q_i = 2 (sum of q_i where x_j = +1) - sum q_i, and sum x_i q_j
+        // against x_i's +-1 bytes (|.| <= 127 M: exact, also the wave sums)
+        int sa = 0, sb = 0;
+#pragma unroll
+        for (int c = 0; c < LaneR<R, NPL>::CH; ++c) {
+          constexpr int VEC = LaneR<R, NPL>::VEC;
+          sa = __builtin_amdgcn_sdot4((int)L.qw[c], (int)spread01((rw.xw >> (c * VEC)) & ((1u << VEC) - 1u)), sa, false);
+          sb = __builtin_amdgcn_sdot4((int)qw[c], (int)L.pm[c], sb, false);
+        }
+        sa = 2 * sa - L.sq;
+        na = (float)abs(rec_wave_sum_dpp(sa + sb)) * REC_Q8_INV > F.scr2;
+        ++wk.tfetch;
+      }
       ++wk.pairs;
       if (!na) ++wk.screened;
     } else {
+      // i <- j: sum x_j y_i u_i;  j <- i: sum x_i y_j u_j
       const double w0b = rec_uni(__shfl(lw2, q, REC_WAVE));
-      na = w0 != 0.0 || (float)abs(rec_wave_sum_dpp(sa)) * REC_Q8_INV > F.scr;
-      nb = w0b != 0.0 || (float)abs(rec_wave_sum_dpp(sb)) * REC_Q8_INV > F.scr;
+      const uint32_t sa4 = ~(rw.xw ^ L.yw), sb4 = ~(L.xw ^ rw.yw);
+      uint32_t va = 0, vb = 0, uj = 0;
+#pragma unroll
+      for (int w = 0; w < UW; ++w) {
+        va = __builtin_amdgcn_udot8(spread[(sa4 >> (8 * w)) & 0xffu], L.ui[w], va, false);
+        vb = __builtin_amdgcn_udot8(spread[(sb4 >> (8 * w)) & 0xffu], rw.uw[w], vb, false);
+        uj = __builtin_amdgcn_udot8(0x11111111u, rw.uw[w], uj, false);
+      }
+      na = w0 != 0.0 || abs(rec_wave_sum_dpp(2 * (int)va - L.su)) > F.t4;
+      nb = w0b != 0.0 || abs(rec_wave_sum_dpp(2 * (int)vb - (int)uj)) > F.t4;
+      if ((na && w0 == 0.0) || (nb && w0b == 0.0)) {
+        uint32_t qw[LaneR<R, NPL>::CH];
+        fetch_q8<NPL>(F, j, qw, lane);
+        int sa = 0, sb = 0;
+#pragma unroll
+        for (int c = 0; c < LaneR<R, NPL>::CH; ++c) {
+          constexpr int VEC = LaneR<R, NPL>::VEC;
+          sa = __builtin_amdgcn_sdot4((int)L.qw[c], (int)spread01((rw.xw >> (c * VEC)) & ((1u << VEC) - 1u)), sa, false);
+          sb = __builtin_amdgcn_sdot4((int)qw[c], (int)L.pm[c], sb, false);
+        }
+        sa = 2 * sa - L.sq;
+        if (na && w0 == 0.0) na = (float)abs(rec_wave_sum_dpp(sa)) * REC_Q8_INV > F.scr;
+        if (nb && w0b == 0.0) nb = (float)abs(rec_wave_sum_dpp(sb)) * REC_Q8_INV > F.scr;
+        ++wk.tfetch;
+      }
       wk.pairs += 2;
       wk.screened += (na ? 0 : 1) + (nb ? 0 : 1);
     }
@@ -910,10 +980,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   }
   }
   if (lane == 0 && work) {
-    const int64_t M = F.M, rs = sizeof(R);
+    const int64_t M = F.M;
     const int64_t items = SYM ? wk.pairs / 2 : wk.pairs;
-    const int64_t sbytes = (M + 7) / 8 * (SYM ? 2 : 1) + M;   // signs + int8 residuals
-    wk.bytes = items * (16 + (slot ? 4 : 0) + sbytes) + wk.iloads * (M + (M + 7) / 8);
+    const int64_t sb = (M + 7) / 8 * (SYM ? 2 : 1);   // sign words
+    // per pair: indices and score, the j side's signs and 4-bit copies (plus
+    // its int8 row when the 4-bit test left a side open); per i load: its
+    // signs, 4-bit copies and int8 row
+    wk.bytes = items * (16 + (slot ? 4 : 0) + sb + (M + 1) / 2) + wk.tfetch * M +
+               wk.iloads * (sb + (M + 1) / 2 + M);
+    wk.tfetch = 0;   // (int8 rows, not tanh rows: counted in the bytes)
     wk.flush(work, wave);
   }
 }
@@ -1071,6 +1146,10 @@ __device__ __forceinline__ void update_pair(const Fields& F, const WTable& W, do
       int row = side == 0 ? i : j, other = side == 0 ? j : i;
       double scale = d;
       if constexpr (MODEL == REC_GAUSS) scale = d * F.theta[row] * F.theta[row];
+      constexpr int UW = rec_u4_words(NPL);
+      uint32_t uw[UW];
+#pragma unroll
+      for (int w = 0; w < UW; ++w) uw[w] = 0u;
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
         int64_t o = smp<VEC>(c, lane);
@@ -1087,10 +1166,17 @@ __device__ __forceinline__ void update_pair(const Fields& F, const WTable& W, do
               R t = tanh_(h);
               T[idx] = t;
               const int8_t* Y = MODEL == REC_KINETIC ? F.ys : F.xs;
-              F.rq[idx] = rec_q8((float)((R)Y[idx] - t));
+              const R yv = (R)Y[idx];
+              F.rq[idx] = rec_q8((float)(yv - t));
+              const int n = c * VEC + k;
+              uw[n >> 3] |= rec_u4((float)(R(1) - yv * t)) << (4 * (n & 7));
             }
           }
         }
+      }
+      if constexpr (MODEL != REC_GAUSS) {
+#pragma unroll
+        for (int w = 0; w < UW; ++w) F.u4[((int64_t)row * UW + w) * REC_WAVE + lane] = uw[w];
       }
     }
     if (lane == 0 && ws >= 0) W.vals[ws] = r.w;
@@ -1153,6 +1239,10 @@ __device__ __forceinline__ void cd_pair(const Fields& F, const WTable& W, double
     const int row = side == 0 ? i : j, other = side == 0 ? j : i;
     double scale = d;
     if constexpr (MODEL == REC_GAUSS) scale = d * F.theta[row] * F.theta[row];
+    constexpr int UW = rec_u4_words(NPL);
+    uint32_t uw[UW];
+#pragma unroll
+    for (int w = 0; w < UW; ++w) uw[w] = 0u;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int64_t o = smp<VEC>(c, lane);
@@ -1169,10 +1259,17 @@ __device__ __forceinline__ void cd_pair(const Fields& F, const WTable& W, double
             const R t = tanh_(h);
             T[idx] = t;
             const int8_t* Y = MODEL == REC_KINETIC ? F.ys : F.xs;
-            F.rq[idx] = rec_q8((float)((R)Y[idx] - t));
+            const R yv = (R)Y[idx];
+            F.rq[idx] = rec_q8((float)(yv - t));
+            const int n = c * VEC + k;
+            uw[n >> 3] |= rec_u4((float)(R(1) - yv * t)) << (4 * (n & 7));
           }
         }
       }
+    }
+    if constexpr (MODEL != REC_GAUSS) {
+#pragma unroll
+      for (int w = 0; w < UW; ++w) F.u4[((int64_t)row * UW + w) * REC_WAVE + lane] = uw[w];
     }
   }
   if (lane == 0) {
@@ -1300,6 +1397,10 @@ __device__ __forceinline__ void update_chain(const Fields& F, const WTable& W, d
     }
   }
   if (changed) {
+    constexpr int UW = rec_u4_words(NPL);
+    uint32_t uw[UW];
+#pragma unroll
+    for (int w = 0; w < UW; ++w) uw[w] = 0u;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int64_t o = smp<VEC>(c, lane);
@@ -1310,10 +1411,15 @@ __device__ __forceinline__ void update_chain(const Fields& F, const WTable& W, d
           const R t = tanh_(h[q]);
           H[row + o + k] = h[q];
           T[row + o + k] = t;
-          F.rq[row + o + k] = rec_q8((float)((R)byte_at(yb[c], k) - t));
+          const R yv = (R)byte_at(yb[c], k);
+          F.rq[row + o + k] = rec_q8((float)(yv - t));
+          uw[q >> 3] |= rec_u4((float)(R(1) - yv * t)) << (4 * (q & 7));
         }
       }
     }
+    const int64_t r = row / F.Mp;
+#pragma unroll
+    for (int w = 0; w < UW; ++w) F.u4[(r * UW + w) * REC_WAVE + lane] = uw[w];
   }
 }
 
