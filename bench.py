@@ -77,8 +77,8 @@ BATCH_PER_NODE = 16
 # --copy-probe 1024`: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE
 # 1.0x).  Valid only for the score kernel source it was measured on.
 TRAFFIC = {
-    "C4s": {"source_sha256": "98ab2652db7263ade26a36a525d84b531d5b40a6d315dbf3190ecefb414d8221",
-            "hbm_over_algorithmic": 1.1092},
+    "C4s": {"source_sha256": "99ec89150858acbafc82633ba4bee9a566c88d65f380c321d2d87d2ede1c2e3e",
+            "hbm_over_algorithmic": 1.1637},
 }
 
 # HBM traffic of the contraction's full pass (k_kscreen) per launch, from the
