@@ -175,6 +175,7 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   x->done = a.take<uint8_t>(z.best_cap);
   x->dw = a.take<double>(z.best_cap);
   x->ready = a.take<int32_t>(z.best_cap);
+  x->depth = a.take<int32_t>(z.best_cap);
   x->best_slot = a.take<int64_t>(z.best_cap);
   x->ex_cap = z.ex_cap;
   x->max_nnz = z.max_nnz;

@@ -169,6 +169,7 @@ struct rec_ctx {
   uint8_t* done;        // best_cap
   double* dw;           // best_cap
   int32_t* ready;       // best_cap: the pairs of the current update round
+  int32_t* depth;       // best_cap: the round each applied pair ran in (1-based)
   int64_t* best_slot;   // best_cap: W table slot of each pair being applied
   // exhaustive search chunk buffers
   int64_t ex_cap;
@@ -303,9 +304,19 @@ rec_status rec_launch_update_chains(rec_ctx* ctx, int64_t m, const int32_t* I, c
                                     int64_t n, int64_t* head, uint8_t* done, double* dw);
 // Apply one round of node-disjoint updates: the pairs ready[0..*nready) of
 // the rank-ordered list (I, J); at most m of them (see update kernels).
+// depth[p] = round for each pair applied.
 rec_status rec_launch_update_round(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
                                    const int32_t* ready, const int64_t* nready, uint8_t* done,
-                                   double* dw);
+                                   double* dw, int32_t* depth, int32_t round);
+// The pairs of the rank-ordered list (I, J)[0, m) not yet done (done[p] == 0)
+// as one dataflow launch over the grid: pair p runs once its predecessors
+// pred[2p], pred[2p+1] (or -1) are done.  depth[p] = 1 + the larger depth of
+// its predecessors; *rounds receives the largest depth of the pairs it ran.
+// *ticket, *rounds and *abort_flag zeroed by the caller.  A wait longer than
+// spin_limit polls sets error bit 1024 and ends the launch.
+rec_status rec_launch_update_flow(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J, const int32_t* pred,
+                                  uint8_t* done, double* dw, int32_t* depth, int64_t* ticket, int64_t* rounds,
+                                  int64_t* abort_flag, int64_t spin_limit);
 
 // sort.hip
 // Stable LSD radix sort of (khi, klo, val) by the 8-bit digits listed

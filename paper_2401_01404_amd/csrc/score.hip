@@ -1183,7 +1183,7 @@ __device__ __forceinline__ void update_pair(const Fields& F, const WTable& W, do
   }
   if (lane == 0) {
     dw[p] = fabs(d);
-    done[p] = 1;
+    if (done) done[p] = 1;
   }
 }
 
@@ -1204,11 +1204,86 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                                                 const int32_t* __restrict__ ready,
                                                 const int64_t* __restrict__ nready,
                                                 const int64_t* __restrict__ wslot, uint8_t* done,
-                                                double* dw) {
+                                                double* dw, int32_t* depth, int32_t round) {
   const int64_t n = *nready;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x / REC_WAVE);
-  for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE; q < n; q += nw)
-    update_pair<R, NPL, MODEL>(F, W, lambda, ready[q], I, J, wslot, done, dw);
+  for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE; q < n; q += nw) {
+    const int32_t p = ready[q];
+    update_pair<R, NPL, MODEL>(F, W, lambda, p, I, J, wslot, done, dw);
+    if (rec_lane() == 0) depth[p] = round;
+  }
+}
+
+// The last pairs of the node-disjoint schedule as a dataflow over the whole
+// grid.  Once the rounds ready few pairs each (the runs of updates on hub
+// rows), a round costs its three launches, not its work; here the pairs not
+// yet done run without rounds.  Each wave takes the next rank from a ticket
+// counter, skips it if the rounds did it, waits until the pair's
+// predecessors on both rows are done, applies the update and publishes its
+// done flag (2) after a release fence at device scope.  A predecessor done by
+// the rounds (flag 1) is visible at the launch; one done in this launch
+// (flag 2) is read after an acquire fence at device scope (the writer may sit
+// on another XCD, behind another L2).  The order of the updates on every row
+// is the rank order, so the results are those of the rounds, bit for bit.
+//
+// Progress: tickets are taken in rank order and a wave takes a ticket only
+// while it runs, so the smallest taken and unfinished pair has all its
+// predecessors (smaller ranks, all taken) finished and its wave running; it
+// finishes, and by induction every pair does, whatever the residency of the
+// grid.  The wait is bounded all the same: after spin_limit polls the wave
+// raises an abort flag that every waiting wave reads, all waves leave, and the
+// host reports the error (bit 1024).
+//
+// depth[p] = 1 + the larger depth of the predecessors, the round the pair
+// would have run in; the largest goes to *rounds.
+template <class R, int NPL, int MODEL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_update_flow(
+    Fields F, WTable W, double lambda, const int32_t* __restrict__ I, const int32_t* __restrict__ J, int64_t m,
+    const int32_t* __restrict__ pred, const int64_t* __restrict__ wslot, uint8_t* done, double* dw,
+    int32_t* depth, unsigned long long* ticket, unsigned long long* rounds, int64_t* abort_flag, int32_t* err,
+    int64_t spin_limit) {
+  const int lane = rec_lane();
+  for (;;) {
+    unsigned long long t = 0;
+    if (lane == 0) t = atomicAdd(ticket, 1ull);
+    const int64_t p = (int64_t)(((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(t >> 32)) << 32) |
+                                (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)t));
+    if (p >= m) break;
+    if (done[p] != 0) continue;   // done by the rounds (only this wave can run p here)
+    const int32_t a = pred[2 * p], b = pred[2 * p + 1];
+    int ok = 1, fresh = 0;
+    if (lane == 0) {
+      for (int64_t polls = 0;; ++polls) {
+        const int fa = a < 0 ? 1 : __hip_atomic_load(done + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int fb = b < 0 ? 1 : __hip_atomic_load(done + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (fa != 0 && fb != 0) {
+          fresh = fa == 2 || fb == 2;
+          break;
+        }
+        if (polls >= spin_limit || __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    if (!__builtin_amdgcn_readfirstlane(ok)) {
+      if (lane == 0) {
+        __hip_atomic_store(abort_flag, (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        atomicOr(err, 1024);
+      }
+      break;
+    }
+    if (__builtin_amdgcn_readfirstlane(fresh)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    update_pair<R, NPL, MODEL>(F, W, lambda, p, I, J, wslot, nullptr, dw);
+    if (lane == 0) {
+      const int32_t d = 1 + max(a < 0 ? 0 : depth[a], b < 0 ? 0 : depth[b]);
+      depth[p] = d;
+      atomicMax(rounds, (unsigned long long)d);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) __hip_atomic_store(done + p, (uint8_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // One coordinate of a CD sweep [Alg. 1] (one wave): W_ij <- its argmax at the
@@ -1524,12 +1599,13 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
 
 template <class R, int MODEL>
 rec_status launch_update_m(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
-                           const int32_t* ready, const int64_t* nready, uint8_t* done, double* dw) {
+                           const int32_t* ready, const int64_t* nready, uint8_t* done, double* dw,
+                           int32_t* depth, int32_t round) {
   // enough 4-wave blocks to fill every CU a few times over, never more than the pairs
   const int64_t blocks = std::min<int64_t>((m + 3) / 4, 256 * 8);
 #define REC_UP(NPL)                                                                              \
   hipLaunchKernelGGL((k_update<R, NPL, MODEL>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream, \
-                     ctx->F, ctx->W, ctx->cfg.lambda, I, J, ready, nready, ctx->best_slot, done, dw)
+                     ctx->F, ctx->W, ctx->cfg.lambda, I, J, ready, nready, ctx->best_slot, done, dw, depth, round)
   switch (ctx->F.npl) {
     case 1: REC_UP(1); break;
     case 2: REC_UP(2); break;
@@ -1542,6 +1618,50 @@ rec_status launch_update_m(rec_ctx* ctx, int64_t m, const int32_t* I, const int3
 #undef REC_UP
   REC_HIP(hipGetLastError());
   return REC_OK;
+}
+
+// One wave per resident slot (five 4-wave blocks per CU at the kernel's
+// occupancy), never more waves than pairs.
+template <class R, int MODEL>
+rec_status launch_update_flow_m(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J, const int32_t* pred,
+                                uint8_t* done, double* dw, int32_t* depth, int64_t* ticket, int64_t* rounds,
+                                int64_t* abort_flag, int64_t spin_limit) {
+  const int64_t blocks = std::min<int64_t>((m + 3) / 4, 256 * 5);
+#define REC_UP(NPL)                                                                                          \
+  hipLaunchKernelGGL((k_update_flow<R, NPL, MODEL>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream,       \
+                     ctx->F, ctx->W, ctx->cfg.lambda, I, J, m, pred, ctx->best_slot, done, dw, depth,         \
+                     reinterpret_cast<unsigned long long*>(ticket), reinterpret_cast<unsigned long long*>(rounds), \
+                     abort_flag, ctx->err_flag, spin_limit)
+  switch (ctx->F.npl) {
+    case 1: REC_UP(1); break;
+    case 2: REC_UP(2); break;
+    case 4: REC_UP(4); break;
+    case 8: REC_UP(8); break;
+    case 16: REC_UP(16); break;
+    case 32: REC_UP(32); break;
+    default: ctx->err = "unsupported sample count"; return REC_E_INVAL;
+  }
+#undef REC_UP
+  REC_HIP(hipGetLastError());
+  return REC_OK;
+}
+
+template <class R>
+rec_status launch_update_flow_r(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J, const int32_t* pred,
+                                uint8_t* done, double* dw, int32_t* depth, int64_t* ticket, int64_t* rounds,
+                                int64_t* abort_flag, int64_t spin_limit) {
+  switch (ctx->cfg.model) {
+    case REC_ISING:
+      return launch_update_flow_m<R, REC_ISING>(ctx, m, I, J, pred, done, dw, depth, ticket, rounds, abort_flag,
+                                                spin_limit);
+    case REC_GAUSS:
+      return launch_update_flow_m<R, REC_GAUSS>(ctx, m, I, J, pred, done, dw, depth, ticket, rounds, abort_flag,
+                                                spin_limit);
+    case REC_KINETIC:
+      return launch_update_flow_m<R, REC_KINETIC>(ctx, m, I, J, pred, done, dw, depth, ticket, rounds,
+                                                  abort_flag, spin_limit);
+  }
+  return REC_E_INVAL;
 }
 
 template <class R, int MODEL>
@@ -1620,11 +1740,12 @@ rec_status launch_chains_r(rec_ctx* ctx, int64_t m, const int32_t* I, const int3
 
 template <class R>
 rec_status launch_update_r(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
-                           const int32_t* ready, const int64_t* nready, uint8_t* done, double* dw) {
+                           const int32_t* ready, const int64_t* nready, uint8_t* done, double* dw,
+                           int32_t* depth, int32_t round) {
   switch (ctx->cfg.model) {
-    case REC_ISING: return launch_update_m<R, REC_ISING>(ctx, m, I, J, ready, nready, done, dw);
-    case REC_GAUSS: return launch_update_m<R, REC_GAUSS>(ctx, m, I, J, ready, nready, done, dw);
-    case REC_KINETIC: return launch_update_m<R, REC_KINETIC>(ctx, m, I, J, ready, nready, done, dw);
+    case REC_ISING: return launch_update_m<R, REC_ISING>(ctx, m, I, J, ready, nready, done, dw, depth, round);
+    case REC_GAUSS: return launch_update_m<R, REC_GAUSS>(ctx, m, I, J, ready, nready, done, dw, depth, round);
+    case REC_KINETIC: return launch_update_m<R, REC_KINETIC>(ctx, m, I, J, ready, nready, done, dw, depth, round);
   }
   return REC_E_INVAL;
 }
@@ -1745,8 +1866,18 @@ rec_status rec_launch_cd_round(rec_ctx* ctx, int64_t r, int64_t n, double* acc, 
 
 rec_status rec_launch_update_round(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J,
                                    const int32_t* ready, const int64_t* nready, uint8_t* done,
-                                   double* dw) {
+                                   double* dw, int32_t* depth, int32_t round) {
   if (m <= 0) return REC_OK;
-  return ctx->fp32 ? launch_update_r<float>(ctx, m, I, J, ready, nready, done, dw)
-                   : launch_update_r<double>(ctx, m, I, J, ready, nready, done, dw);
+  return ctx->fp32 ? launch_update_r<float>(ctx, m, I, J, ready, nready, done, dw, depth, round)
+                   : launch_update_r<double>(ctx, m, I, J, ready, nready, done, dw, depth, round);
+}
+
+rec_status rec_launch_update_flow(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J, const int32_t* pred,
+                                  uint8_t* done, double* dw, int32_t* depth, int64_t* ticket, int64_t* rounds,
+                                  int64_t* abort_flag, int64_t spin_limit) {
+  if (m <= 0) return REC_OK;
+  return ctx->fp32 ? launch_update_flow_r<float>(ctx, m, I, J, pred, done, dw, depth, ticket, rounds, abort_flag,
+                                                 spin_limit)
+                   : launch_update_flow_r<double>(ctx, m, I, J, pred, done, dw, depth, ticket, rounds, abort_flag,
+                                                  spin_limit);
 }

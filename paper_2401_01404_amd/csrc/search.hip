@@ -998,6 +998,7 @@ struct Search {
       return REC_E_NOMEM;
     }
     if (e & 2) { ctx->err = "W table full (increase max_nnz)"; return REC_E_NOMEM; }
+  if (e & 1024) { ctx->err = "update rounds did not drain"; return REC_E_NUMERIC; }
     if (e & 64) { ctx->err = "internal: duplicate neighbour in a merged list"; return REC_E_NUMERIC; }
     if (e & 256) { ctx->err = "screen candidates exceed the candidate buffer"; return REC_E_NOMEM; }
     if (e & 512) { ctx->err = "internal: exact-scoring queue overflow"; return REC_E_NUMERIC; }
@@ -1580,6 +1581,7 @@ static rec_status finish_updates(rec_ctx* ctx, int64_t m, double* delta, int64_t
   hipMemcpyAsync(&e, ctx->err_flag, 4, hipMemcpyDeviceToHost, s);
   if (hipStreamSynchronize(s) != hipSuccess) { ctx->err = "sync failed"; return REC_E_HIP; }
   if (e & 2) { ctx->err = "W table full (increase max_nnz)"; return REC_E_NOMEM; }
+  if (e & 1024) { ctx->err = "update rounds did not drain"; return REC_E_NUMERIC; }
   return REC_OK;
 }
 
@@ -1653,29 +1655,50 @@ rec_status rec_apply_best(rec_ctx* ctx, int64_t m, const int32_t* I, const int32
   hipLaunchKernelGGL(k_iota_i32, dim3(gridn(m)), dim3(256), 0, s, ctx->pend[0], m, npend[0]);
   const unsigned split_grid = (unsigned)std::min<int64_t>(gridn(m), 1024);
   int cur = 0;
-  int64_t pass = 0;
+  int64_t pass = 0;      // rounds that ran pairs
+  int32_t launched = 0;  // rounds launched (the empty ones after the last come last)
+  // Rounds over the whole grid while they ready many pairs each; once a round
+  // readies fewer than flow_min, the pairs left run as one dataflow launch
+  // without three launches a round (the runs of updates on hub rows take as
+  // many rounds as the hub has pairs).
+  const int64_t flow_min = 256;
   while (true) {
     const int batch = 8;
-    std::vector<int64_t> rem(batch, 0);
+    std::vector<int64_t> rem(batch + 1, 0);
     for (int b = 0; b < batch; ++b) {
       hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, s, npend[cur], ctx->scan_tmp + b, d_ready,
                          npend[cur ^ 1]);
       hipLaunchKernelGGL(k_split_ready, dim3(split_grid), dim3(256), 0, s, ctx->pend[cur], npend[cur], ctx->pred,
                          ctx->done, ctx->ready, d_ready, ctx->pend[cur ^ 1], npend[cur ^ 1]);
-      rec_status st = rec_launch_update_round(ctx, m, I, J, ctx->ready, d_ready, ctx->done, ctx->dw);
+      rec_status st = rec_launch_update_round(ctx, m, I, J, ctx->ready, d_ready, ctx->done, ctx->dw, ctx->depth,
+                                              ++launched);
       if (st != REC_OK) return st;
       cur ^= 1;
     }
     if (hipMemcpyAsync(rem.data(), ctx->scan_tmp, sizeof(int64_t) * batch, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(rem.data() + batch, npend[cur], sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { ctx->err = "readback failed"; return REC_E_HIP; }
-    bool finished = false;
-    for (int b = 0; b < batch; ++b) {
+    for (int b = 0; b < batch; ++b)
       if (rem[b] > 0) ++pass;
-      else finished = true;
-    }
-    if (finished) break;
+    if (rem[batch] == 0) break;
     // the earliest pending pair is always ready, so m rounds always suffice
     if (pass > m + batch) { ctx->err = "update rounds did not drain"; return REC_E_NUMERIC; }
+    if (rem[batch - 1] - rem[batch] < flow_min) {
+      // ticket, depth maximum and abort flag: counter slots the rounds no longer use
+      int64_t* ticket = ctx->counter + 0;
+      int64_t* d_depth = ctx->counter + 1;
+      int64_t* abort_flag = ctx->counter + 14;
+      hipMemsetAsync(ticket, 0, 2 * sizeof(int64_t), s);
+      hipMemsetAsync(abort_flag, 0, sizeof(int64_t), s);
+      rec_status st = rec_launch_update_flow(ctx, m, I, J, ctx->pred, ctx->done, ctx->dw, ctx->depth, ticket,
+                                             d_depth, abort_flag, int64_t(1) << 24);
+      if (st != REC_OK) return st;
+      int64_t tail = 0;
+      if (hipMemcpyAsync(&tail, d_depth, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) { ctx->err = "readback failed"; return REC_E_HIP; }
+      pass = std::max(pass, tail);
+      break;
+    }
   }
   *rounds = pass;
   return finish_updates(ctx, m, delta, accepted, nullptr);

@@ -159,6 +159,66 @@ def test_apply_updates_matches_sequential_oracle(c1, c1_lam, prec):
     assert abs(obj - O.objective()) <= (1e-10 if prec == "fp64" else 1e-6) * abs(O.objective())
 
 
+def _schedule_rounds(I, J):
+    """Rounds of the node-disjoint schedule of a rank-ordered pair list: a
+    pair runs one round after the later of the last pairs on its two rows."""
+    last = {}
+    depth = 0
+    for i, j in zip(I.tolist(), J.tolist()):
+        d = 1 + max(last.get(i, 0), last.get(j, 0))
+        last[i] = last[j] = d
+        depth = max(depth, d)
+    return depth
+
+
+def test_apply_updates_hub_rows_match_sequential_oracle(c1, c1_lam):
+    """Rows in hundreds of pairs (node 3 with every other node, node 7 with
+    60 of them, at seeded positions of the exhaustive top 2N): the rounds
+    ready few pairs each and the pairs left run in one block as a dataflow;
+    Delta, W and the objective equal the oracle's sequential updates."""
+    O = oracle.Oracle(c1.X, "ising", c1_lam)
+    Io, Jo, _, _ = O.find_best(2 * c1.N, "exhaustive")
+    have = set(zip(Io.tolist(), Jo.tolist()))
+    extra = [(min(3, j), max(3, j)) for j in range(c1.N) if j != 3]
+    extra += [(7, j) for j in range(c1.N - 60, c1.N)]
+    extra = [p for p in extra if p not in have]
+    rng = np.random.default_rng(21)
+    pairs = list(zip(Io.tolist(), Jo.tolist()))
+    for p, pos in zip(extra, rng.integers(0, len(pairs), len(extra))):
+        pairs.insert(int(pos), p)
+    I = np.array([p[0] for p in pairs], np.int32)
+    J = np.array([p[1] for p in pairs], np.int32)
+    assert _schedule_rounds(I, J) >= c1.N - 1
+    C = ctx_for(c1, c1_lam, "fp64")
+    d_gpu = C.apply_updates(I, J)
+    d_or, bad = O.apply_updates(I, J)
+    assert bad == 0
+    assert abs(d_gpu - d_or) <= 1e-9 * d_or
+    ei, ej, wv, _ = C.get_model()
+    eo, fo, wo, _ = O.get_model()
+    assert np.array_equal(ei.cpu().numpy(), eo) and np.array_equal(ej.cpu().numpy(), fo)
+    assert np.allclose(wv.cpu().numpy(), wo, rtol=1e-9, atol=1e-9)
+    O.theta_update()
+    obj = C.theta_update()
+    assert abs(obj - O.objective()) <= 1e-10 * abs(O.objective())
+
+
+def test_sweep_reports_the_schedule_rounds(c1, c1_lam):
+    """The round count a sweep reports is the longest run of the
+    node-disjoint schedule over the pairs it applied (the positive-gain
+    prefix of the exhaustive best m), whether the pairs ran in grid-wide
+    rounds or in the one-block dataflow."""
+    C = ctx_for(c1, c1_lam, "fp64", kappa=4.0)
+    for s in range(3):
+        I, J, G, _ = C.find_best(4 * c1.N, "exhaustive")
+        g = G.cpu().numpy()
+        n = int(np.argmin(g > 0)) if (g <= 0).any() else len(g)
+        I, J = I.cpu().numpy()[:n], J.cpu().numpy()[:n]
+        st = C.sweep("exhaustive")
+        assert st["n_best"] == n, (s, st)
+        assert st["rounds"] == _schedule_rounds(I, J), (s, st)
+
+
 def test_gcd_sweeps_exhaustive_track_oracle(c1, c1_lam):
     O = oracle.Oracle(c1.X, "ising", c1_lam)
     C = ctx_for(c1, c1_lam, "fp64", kappa=1.0)
