@@ -1154,12 +1154,25 @@ __device__ __forceinline__ void update_pair(const Fields& F, const WTable& W, do
       for (int c = 0; c < CH; ++c) {
         int64_t o = smp<VEC>(c, lane);
         float xv[VEC];
-        if constexpr (MODEL == REC_GAUSS) ld_f<VEC>(F.xf + (int64_t)other * F.Mp + o, xv);
-        else ld_x<VEC>(F.xs + (int64_t)other * F.Mp + o, xv);
+        R hv[VEC];
+        if constexpr (MODEL == REC_GAUSS) {
+          // the wave holds both rows already: r_i (= h_i) and x_i as the i
+          // side, x_j and r_j as the j side; no other wave writes them now
+#pragma unroll
+          for (int k = 0; k < VEC; ++k) {
+            const int q = c * VEC + k;
+            xv[k] = side == 0 ? (float)L.u[q] : (float)L.xi[q];
+            hv[k] = side == 0 ? L.ti[q] : L.v[q];
+          }
+        } else {
+          ld_x<VEC>(F.xs + (int64_t)other * F.Mp + o, xv);
+#pragma unroll
+          for (int k = 0; k < VEC; ++k) hv[k] = H[(int64_t)row * F.Mp + o + k];
+        }
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
           int64_t idx = (int64_t)row * F.Mp + o + k;
-          R h = H[idx] + (R)(scale * (double)xv[k]);
+          R h = hv[k] + (R)(scale * (double)xv[k]);
           if (o + k < F.M) {
             H[idx] = h;
             if constexpr (MODEL != REC_GAUSS) {
@@ -1253,18 +1266,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const int32_t a = pred[2 * p], b = pred[2 * p + 1];
     int ok = 1, fresh = 0;
     if (lane == 0) {
+      // poll only the flags not yet seen set; the abort flag every 32 polls;
+      // a long wait polls less often (most waiting wavefronts sit far down a
+      // chain, and their polls share the memory path with the chain's head)
+      int fa = a < 0 ? 1 : 0, fb = b < 0 ? 1 : 0;
       for (int64_t polls = 0;; ++polls) {
-        const int fa = a < 0 ? 1 : __hip_atomic_load(done + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int fb = b < 0 ? 1 : __hip_atomic_load(done + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (fa == 0) fa = __hip_atomic_load(done + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (fb == 0) fb = __hip_atomic_load(done + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (fa != 0 && fb != 0) {
           fresh = fa == 2 || fb == 2;
           break;
         }
-        if (polls >= spin_limit || __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        if (polls >= spin_limit ||
+            ((polls & 31) == 31 && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
           ok = 0;
           break;
         }
-        __builtin_amdgcn_s_sleep(1);
+        if (polls < 64) __builtin_amdgcn_s_sleep(1);
+        else __builtin_amdgcn_s_sleep(16);
       }
     }
     if (!__builtin_amdgcn_readfirstlane(ok)) {
@@ -1275,9 +1294,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       break;
     }
     if (__builtin_amdgcn_readfirstlane(fresh)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // the predecessors' depths are read here, beside the pair's row loads,
+    // not on the path from the update to the release
+    int32_t d = 0;
+    if (lane == 0) d = 1 + max(a < 0 ? 0 : depth[a], b < 0 ? 0 : depth[b]);
     update_pair<R, NPL, MODEL>(F, W, lambda, p, I, J, wslot, nullptr, dw);
     if (lane == 0) {
-      const int32_t d = 1 + max(a < 0 ? 0 : depth[a], b < 0 ? 0 : depth[b]);
       depth[p] = d;
       atomicMax(rounds, (unsigned long long)d);
     }
@@ -1620,13 +1642,15 @@ rec_status launch_update_m(rec_ctx* ctx, int64_t m, const int32_t* I, const int3
   return REC_OK;
 }
 
-// One wave per resident slot (five 4-wave blocks per CU at the kernel's
-// occupancy), never more waves than pairs.
+// One 4-wave block per CU, never more waves than pairs: the launch starts
+// once the rounds ready fewer than a few hundred pairs each, so more
+// wavefronts would mostly wait, and their polls would slow the loads of the
+// pairs that run.
 template <class R, int MODEL>
 rec_status launch_update_flow_m(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J, const int32_t* pred,
                                 uint8_t* done, double* dw, int32_t* depth, int64_t* ticket, int64_t* rounds,
                                 int64_t* abort_flag, int64_t spin_limit) {
-  const int64_t blocks = std::min<int64_t>((m + 3) / 4, 256 * 5);
+  const int64_t blocks = std::min<int64_t>((m + 3) / 4, 256);
 #define REC_UP(NPL)                                                                                          \
   hipLaunchKernelGGL((k_update_flow<R, NPL, MODEL>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream,       \
                      ctx->F, ctx->W, ctx->cfg.lambda, I, J, m, pred, ctx->best_slot, done, dw, depth,         \

@@ -171,12 +171,16 @@ def _schedule_rounds(I, J):
     return depth
 
 
-def test_apply_updates_hub_rows_match_sequential_oracle(c1, c1_lam):
-    """Rows in hundreds of pairs (node 3 with every other node, node 7 with
-    60 of them, at seeded positions of the exhaustive top 2N): the rounds
-    ready few pairs each and the pairs left run in one block as a dataflow;
-    Delta, W and the objective equal the oracle's sequential updates."""
-    O = oracle.Oracle(c1.X, "ising", c1_lam)
+@pytest.mark.parametrize("model", ["ising", "gauss"])
+def test_apply_updates_hub_rows_match_sequential_oracle(c1, c1_lam, model):
+    """Rows in many pairs (node 3 with every other node, node 7 with 60 of
+    them, at seeded positions of the exhaustive top 2N): the rounds ready few
+    pairs each and the pairs left run as one dataflow launch; Delta, W and
+    the objective equal the oracle's sequential updates."""
+    if model == "gauss":
+        c1 = synth.gauss_er(150, 200, 4.0, 0.2, 1e-3, seed=3)
+        c1_lam = oracle.default_lambda(c1.X, "gauss")
+    O = oracle.Oracle(c1.X, model, c1_lam)
     Io, Jo, _, _ = O.find_best(2 * c1.N, "exhaustive")
     have = set(zip(Io.tolist(), Jo.tolist()))
     extra = [(min(3, j), max(3, j)) for j in range(c1.N) if j != 3]
