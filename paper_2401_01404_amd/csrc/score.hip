@@ -1642,15 +1642,16 @@ rec_status launch_update_m(rec_ctx* ctx, int64_t m, const int32_t* I, const int3
   return REC_OK;
 }
 
-// One 4-wave block per CU, never more waves than pairs: the launch starts
-// once the rounds ready fewer than a few hundred pairs each, so more
-// wavefronts would mostly wait, and their polls would slow the loads of the
-// pairs that run.
+// 64 blocks of 4 waves (8 per XCD), never more waves than pairs: the launch
+// starts once the rounds ready fewer than a few hundred pairs each, so more
+// wavefronts would mostly wait, and their polls slow the loads of the pairs
+// that run (C3 updates per sweep: 1280 blocks 30-38 ms, 256 blocks 18-24 ms,
+// 64 or 32 blocks 10-17 ms, 8 blocks 14-19 ms).
 template <class R, int MODEL>
 rec_status launch_update_flow_m(rec_ctx* ctx, int64_t m, const int32_t* I, const int32_t* J, const int32_t* pred,
                                 uint8_t* done, double* dw, int32_t* depth, int64_t* ticket, int64_t* rounds,
                                 int64_t* abort_flag, int64_t spin_limit) {
-  const int64_t blocks = std::min<int64_t>((m + 3) / 4, 256);
+  const int64_t blocks = std::min<int64_t>((m + 3) / 4, 64);
 #define REC_UP(NPL)                                                                                          \
   hipLaunchKernelGGL((k_update_flow<R, NPL, MODEL>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream,       \
                      ctx->F, ctx->W, ctx->cfg.lambda, I, J, m, pred, ctx->best_slot, done, dw, depth,         \
