@@ -117,6 +117,16 @@ __device__ __forceinline__ double rec_uni(double v) {
 template <class T>
 __device__ __forceinline__ T rec_wave_sum_uni(T v) { return rec_uni(rec_wave_sum(v)); }
 
+// Lane q's value of v as a scalar (q uniform): one v_readlane per dword, no
+// LDS round trip as a shuffle takes.
+__device__ __forceinline__ int rec_lane_val(int v, int q) { return __builtin_amdgcn_readlane(v, q); }
+__device__ __forceinline__ double rec_lane_val(double v, int q) {
+  uint64_t u = __builtin_bit_cast(uint64_t, v);
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, q);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), q);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // Full-wave sums with DPP row operations (xor 1, xor 2, half-row mirror,
 // row mirror: every lane of a 16-lane row then holds the row sum) and four
 // readlanes for the rows; the result is uniform (scalar).  All 64 lanes must

@@ -428,8 +428,10 @@ __device__ __forceinline__ PairOut solve(const Fields& F, const Lane<R, NPL>& L,
   }
 }
 
+// 0 <= i, j < N (N < 2^31) and i != j, in 32-bit scalar compares
 __device__ __forceinline__ bool pair_ok(int i, int j, int64_t N) {
-  return i >= 0 && j >= 0 && i < N && j < N && i != j;
+  const uint32_t n = (uint32_t)N;
+  return (uint32_t)i < n && (uint32_t)j < n && i != j;
 }
 
 constexpr int SKIP = -2;   // pair not owned by this launch (owner mode)
@@ -475,23 +477,26 @@ __global__ __launch_bounds__(256) void k_score(Fields F, WTable W, double lambda
   uint64_t todo = __ballot(lane < np && li != SKIP);
   if (todo) {
     int q0 = __ffsll((unsigned long long)todo) - 1;
-    int i0 = rec_uni(__shfl(li, q0, REC_WAVE)), j0 = rec_uni(__shfl(lj, q0, REC_WAVE));
+    int i0 = rec_lane_val(li, q0), j0 = rec_lane_val(lj, q0);
     if (pair_ok(i0, j0, F.N)) fetch_j<R, NPL, MODEL>(F, j0, nx, lane);
   }
   while (todo) {
     const int q = __ffsll((unsigned long long)todo) - 1;
     todo &= todo - 1;
     const int64_t p = p0 + q;
-    int i = rec_uni(__shfl(li, q, REC_WAVE)), j = rec_uni(__shfl(lj, q, REC_WAVE));
-    double w0 = rec_uni(__shfl(lw, q, REC_WAVE));
+    int i = rec_lane_val(li, q), j = rec_lane_val(lj, q);
+    double w0 = rec_lane_val(lw, q);
     JRaw<R, NPL, MODEL> rw = nx;   // holds this pair's row (fetched ahead)
     if (todo) {                    // next pair's row in flight while this one computes
       const int q1 = __ffsll((unsigned long long)todo) - 1;
-      int i1 = rec_uni(__shfl(li, q1, REC_WAVE)), j1 = rec_uni(__shfl(lj, q1, REC_WAVE));
+      int i1 = rec_lane_val(li, q1), j1 = rec_lane_val(lj, q1);
       if (pair_ok(i1, j1, F.N)) fetch_j<R, NPL, MODEL>(F, j1, nx, lane);
     }
-    uint64_t o = slot ? (uint64_t)(slot[p] & ~OWNER) : (uint64_t)p;
-    double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
+    double* dst = gain_out + p;
+    if (slot) {
+      const uint64_t o = (uint64_t)(slot[p] & ~OWNER);
+      dst = o >= cache_cap ? ovf + (o - cache_cap) : gain_out + o;
+    }
     if (!pair_ok(i, j, F.N)) {
       if (lane == 0) {
         *dst = __builtin_nan("");
@@ -602,7 +607,7 @@ __global__ __launch_bounds__(256) void k_grad(Fields F, WTable W, double lambda,
     const int i = I[p];
     int j = J[p];
     if (Smap) j = Smap[j];
-    const uint64_t o = slot ? (uint64_t)((uint32_t)rec_uni(__shfl((int)sw, q, REC_WAVE)) & ~OWNER) : (uint64_t)p;
+    const uint64_t o = slot ? (uint64_t)((uint32_t)rec_lane_val((int)sw, q) & ~OWNER) : (uint64_t)p;
     double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
     if (!pair_ok(i, j, F.N)) {
       if (lane == 0) {
@@ -852,7 +857,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   auto prefetch = [&](JScr<NPL, SYM>& dst) {
     const int qq = __ffsll((unsigned long long)pf) - 1;
     pf &= pf - 1;
-    int ii = rec_uni(__shfl(li, qq, REC_WAVE)), jj = rec_uni(__shfl(lj, qq, REC_WAVE));
+    int ii = rec_lane_val(li, qq), jj = rec_lane_val(lj, qq);
     if (pair_ok(ii, jj, F.N)) fetch_scr<NPL, SYM>(F, jj, dst, lane);
   };
   // four pairs' screen data in flight ahead of the one being tested, issued
@@ -862,7 +867,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   for (int d = 0; d < KD; ++d)
     if (pf) prefetch(nx[d]);
   if (todo && g == 0) {
-    const int i0 = rec_uni(__shfl(li, __ffsll((unsigned long long)todo) - 1, REC_WAVE));
+    const int i0 = rec_lane_val(li, __ffsll((unsigned long long)todo) - 1);
     if (i0 >= 0 && i0 < F.N) { load_i_r<R, NPL, MODEL>(F, i0, L, lane); cur = i0; ++wk.iloads; }
   }
   if (lane < np && li != SKIP && pair_ok(li, lj, F.N)) {
@@ -878,11 +883,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const int q = __ffsll((unsigned long long)todo) - 1;
     todo &= todo - 1;
     const int64_t p = p0 + q;
-    int i = rec_uni(__shfl(li, q, REC_WAVE)), j = rec_uni(__shfl(lj, q, REC_WAVE));
-    double w0 = rec_uni(__shfl(lw, q, REC_WAVE));
+    int i = rec_lane_val(li, q), j = rec_lane_val(lj, q);
+    double w0 = rec_lane_val(lw, q);
     const JScr<NPL, SYM>& rw = nx[d];
-    uint64_t o = slot ? (uint64_t)(slot[p] & ~OWNER) : (uint64_t)p;
-    double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
+    double* dst = gain_out + p;
+    if (slot) {
+      const uint64_t o = (uint64_t)(slot[p] & ~OWNER);
+      dst = o >= cache_cap ? ovf + (o - cache_cap) : gain_out + o;
+    }
     if (!pair_ok(i, j, F.N)) {
       if (lane == 0) {
         *dst = __builtin_nan("");
@@ -932,7 +940,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
       if (!na) ++wk.screened;
     } else {
       // i <- j: sum x_j y_i u_i;  j <- i: sum x_i y_j u_j
-      const double w0b = rec_uni(__shfl(lw2, q, REC_WAVE));
+      const double w0b = rec_lane_val(lw2, q);
       const uint32_t sa4 = ~(rw.xw ^ L.yw), sb4 = ~(L.xw ^ rw.yw);
       uint32_t va = 0, vb = 0, uj = 0;
 #pragma unroll
@@ -1028,8 +1036,11 @@ __global__ __launch_bounds__(256) void k_exact(Fields F, WTable W, double lambda
     int j = J[p];
     if (Smap) j = Smap[j];
     j = rec_uni(j);
-    uint64_t o = slot ? (uint64_t)(slot[p] & ~OWNER) : (uint64_t)p;
-    double* dst = (slot && o >= cache_cap) ? ovf + (o - cache_cap) : gain_out + o;
+    double* dst = gain_out + p;
+    if (slot) {
+      const uint64_t o = (uint64_t)(slot[p] & ~OWNER);
+      dst = o >= cache_cap ? ovf + (o - cache_cap) : gain_out + o;
+    }
     if (i != cur) { load_i_exact<R, NPL, MODEL>(F, i, ti, yb, xb, lane); cur = i; ++wk.iloads; }
     const uint32_t xw = rec_sign_word<NPL>(F.xq, j, lane);
     PairOut r;
@@ -1469,7 +1480,7 @@ __device__ __forceinline__ void update_chain(const Fields& F, const WTable& W, d
     double wl = 0.0;
     if (lane == 0 && ws >= 0)
       wl = __builtin_bit_cast(double, __atomic_load_n(reinterpret_cast<const uint64_t*>(W.vals + ws), __ATOMIC_RELAXED));
-    const double w0 = rec_uni(__shfl(wl, 0, REC_WAVE));
+    const double w0 = rec_lane_val(wl, 0);
     Work wk;
     const PairOut r = solve_ising<R, NPL, false>(u, u, phi0, s_lane, w0, lambda, F.M, F.Mp, wk);
     const double d = r.w - w0;
@@ -1539,7 +1550,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       const unsigned long long hd = atomicAdd(head, 1ull);
       q = hd < (unsigned long long)n ? (int)hd : -1;
     }
-    q = rec_uni(__shfl(q, 0, REC_WAVE));
+    q = rec_lane_val(q, 0);
     if (q < 0) break;
     const uint64_t k = key[q];
     if ((k >> 32) == 0xFF) break;
