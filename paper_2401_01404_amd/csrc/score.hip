@@ -819,7 +819,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
                                               int64_t qcap, int64_t* work) {
   constexpr bool SYM = MODEL == REC_KINSYM;
   const int lane = rec_lane();
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE;
+  // (uniform: the pair addresses derived from it stay scalar)
+  const int64_t wave = rec_uni((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / REC_WAVE));
   // byte -> its bits spread to the nibbles of a word (rec_spread8), one LDS
   // read instead of nine ALU operations per word of signs
   __shared__ uint32_t spread[256];
@@ -835,8 +836,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   JScr<NPL, SYM> nx[KD];   // screen data of the next KD pairs, in flight
   int cur = -1;
   Work wk;
+  int32_t n_items = 0, n_settled = 0;   // pairs (sides) tested and settled, 32-bit scalar counts
   for (int g = 0; g < groups; ++g) {
   uint32_t mine = 0;   // lane q: queue entry of the group's pair q (0: none)
+  uint64_t settled = 0;   // bit q: pair q settled at the kink, its zeros stored after the group
   const int64_t p0 = wbeg + (int64_t)g * ppw;
   if (p0 >= P) break;
   int np = (int)(p0 + ppw < P ? ppw : P - p0);
@@ -884,15 +887,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     todo &= todo - 1;
     const int64_t p = p0 + q;
     int i = rec_lane_val(li, q), j = rec_lane_val(lj, q);
-    double w0 = rec_lane_val(lw, q);
+    const bool w0z = rec_lane_is_zero(lw, q);   // w0 == 0, tested on its bits in scalar registers
     const JScr<NPL, SYM>& rw = nx[d];
-    double* dst = gain_out + p;
-    if (slot) {
-      const uint64_t o = (uint64_t)(slot[p] & ~OWNER);
-      dst = o >= cache_cap ? ovf + (o - cache_cap) : gain_out + o;
-    }
     if (!pair_ok(i, j, F.N)) {
       if (lane == 0) {
+        double* dst = gain_out + p;
+        if (slot) {
+          const uint64_t o = (uint64_t)(slot[p] & ~OWNER);
+          dst = o >= cache_cap ? ovf + (o - cache_cap) : gain_out + o;
+        }
         *dst = __builtin_nan("");
         if (w_out) w_out[p] = __builtin_nan("");
         atomicOr(err, 1);
@@ -919,8 +922,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         v = __builtin_amdgcn_udot8(b, rw.uw[w], v, false);
         uj = __builtin_amdgcn_udot8(0x11111111u, rw.uw[w], uj, false);
       }
-      na = w0 != 0.0 || abs(rec_wave_sum_dpp(2 * (int)v - L.su - (int)uj)) > F.t42;
-      if (na && w0 == 0.0) {
+      na = !w0z || abs(rec_wave_sum_dpp(2 * (int)v - L.su - (int)uj)) > F.t42;
+      if (na && w0z) {
         uint32_t qw[LaneR<R, NPL>::CH];
         fetch_q8<NPL>(F, j, qw, lane);
         // sum x_j q_i = 2 (sum of q_i where x_j = +1) - sum q_i, and sum x_i q_j
@@ -936,11 +939,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         na = (float)abs(rec_wave_sum_dpp(sa + sb)) * REC_Q8_INV > F.scr2;
         ++wk.tfetch;
       }
-      ++wk.pairs;
-      if (!na) ++wk.screened;
+      ++n_items;
+      if (!na) ++n_settled;
     } else {
       // i <- j: sum x_j y_i u_i;  j <- i: sum x_i y_j u_j
-      const double w0b = rec_lane_val(lw2, q);
+      const bool w0bz = rec_lane_is_zero(lw2, q);
       const uint32_t sa4 = ~(rw.xw ^ L.yw), sb4 = ~(L.xw ^ rw.yw);
       uint32_t va = 0, vb = 0, uj = 0;
 #pragma unroll
@@ -949,9 +952,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         vb = __builtin_amdgcn_udot8(spread[(sb4 >> (8 * w)) & 0xffu], rw.uw[w], vb, false);
         uj = __builtin_amdgcn_udot8(0x11111111u, rw.uw[w], uj, false);
       }
-      na = w0 != 0.0 || abs(rec_wave_sum_dpp(2 * (int)va - L.su)) > F.t4;
-      nb = w0b != 0.0 || abs(rec_wave_sum_dpp(2 * (int)vb - (int)uj)) > F.t4;
-      if ((na && w0 == 0.0) || (nb && w0b == 0.0)) {
+      na = !w0z || abs(rec_wave_sum_dpp(2 * (int)va - L.su)) > F.t4;
+      nb = !w0bz || abs(rec_wave_sum_dpp(2 * (int)vb - (int)uj)) > F.t4;
+      if ((na && w0z) || (nb && w0bz)) {
         uint32_t qw[LaneR<R, NPL>::CH];
         fetch_q8<NPL>(F, j, qw, lane);
         int sa = 0, sb = 0;
@@ -962,23 +965,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
           sb = __builtin_amdgcn_sdot4((int)qw[c], (int)L.pm[c], sb, false);
         }
         sa = 2 * sa - L.sq;
-        if (na && w0 == 0.0) na = (float)abs(rec_wave_sum_dpp(sa)) * REC_Q8_INV > F.scr;
-        if (nb && w0b == 0.0) nb = (float)abs(rec_wave_sum_dpp(sb)) * REC_Q8_INV > F.scr;
+        if (na && w0z) na = (float)abs(rec_wave_sum_dpp(sa)) * REC_Q8_INV > F.scr;
+        if (nb && w0bz) nb = (float)abs(rec_wave_sum_dpp(sb)) * REC_Q8_INV > F.scr;
         ++wk.tfetch;
       }
-      wk.pairs += 2;
-      wk.screened += (na ? 0 : 1) + (nb ? 0 : 1);
+      n_items += 2;
+      n_settled += (na ? 0 : 1) + (nb ? 0 : 1);
     }
     if (!na && !nb) {
-      if (lane == 0) {
-        *dst = 0.0;
-        if (w_out) w_out[p] = 0.0;
-      }
+      settled |= 1ull << q;
     } else if (lane == q) {
       mine = (uint32_t)p | (na ? QA : 0u) | (nb ? QB : 0u);
     }
     if (pf) prefetch(nx[d]);
   }
+  }
+  // the settled pairs' zeros, lane q for pair q
+  if ((settled >> lane) & 1ull) {
+    const int64_t p = p0 + lane;
+    double* dst = gain_out + p;
+    if (slot) {
+      const uint64_t o = (uint64_t)(slot[p] & ~OWNER);
+      dst = o >= cache_cap ? ovf + (o - cache_cap) : gain_out + o;
+    }
+    *dst = 0.0;
+    if (w_out) w_out[p] = 0.0;
   }
   // one atomic per wave and group for the queued pairs
   const int64_t pos = rec_append(qn, mine != 0u);
@@ -987,6 +998,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     else atomicOr(err, 512);
   }
   }
+  wk.pairs += n_items;
+  wk.screened += n_settled;
   if (lane == 0 && work) {
     const int64_t M = F.M;
     const int64_t items = SYM ? wk.pairs / 2 : wk.pairs;
