@@ -21,8 +21,9 @@ distance, the screen), the model restored between them, and each search's
 recall of the exact positive-gain top m is measured.
 
 roofline: the pair-score kernels of one rec_score_pairs call on the batch
-(k_kink + k_exact: the L1-kink decision from sign words and int8 residuals,
-then the exact Newton solve of the sides it cannot settle).  Both the HBM view
+(k_kink + k_exact: the L1-kink decision from sign words and 4-bit copies of
+1 - y tanh h, then int8 residuals for the sides left open, then the exact
+Newton solve of the sides neither settles).  Both the HBM view
 (algorithmic bytes the kernels count / event time, against 8 TB/s) and the
 FP32 VALU view (algorithmic flops / event time, against 157.3 TFLOP/s) are
 computed.  The bound is the larger fraction.  The screening contraction, the
@@ -147,7 +148,8 @@ def batch_roofline(ctx, w, ms, launches, work, P, reps):
         "traffic": traffic,
         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
         "kernel": "pair score, one rec_score_pairs call: k_kink (L1-kink decision from sign words "
-                  "and int8 residuals) + k_exact (exact Newton solve of the unsettled sides)"
+                  "and 4-bit copies, int8 residuals for the sides left open) + k_exact (exact Newton "
+                  "solve of the unsettled sides)"
                   if w.model != "gauss" else "pair score: k_score (closed form)",
         "kernel_ms_avg": ms / per, "launches": launches,
         "pairs_per_launch": P, "bytes_per_launch": bytes_l, "flops_per_launch": flops_l,

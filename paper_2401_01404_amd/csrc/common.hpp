@@ -120,13 +120,6 @@ __device__ __forceinline__ T rec_wave_sum_uni(T v) { return rec_uni(rec_wave_sum
 // Lane q's value of v as a scalar (q uniform): one v_readlane per dword, no
 // LDS round trip as a shuffle takes.
 __device__ __forceinline__ int rec_lane_val(int v, int q) { return __builtin_amdgcn_readlane(v, q); }
-// Whether lane q's v is +-0, on its bits in scalar registers.
-__device__ __forceinline__ bool rec_lane_is_zero(double v, int q) {
-  uint64_t u = __builtin_bit_cast(uint64_t, v);
-  uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, q);
-  uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), q);
-  return ((hi << 1) | lo) == 0u;
-}
 __device__ __forceinline__ double rec_lane_val(double v, int q) {
   uint64_t u = __builtin_bit_cast(uint64_t, v);
   uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, q);

@@ -855,13 +855,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
       if (Smap) lj = Smap[lj];
     }
   }
-  uint64_t todo = __ballot(lane < np && li != SKIP);
+  // the group's pairs checked once, one per lane: the loop below takes only
+  // valid ones; an invalid pair gets NaN and the error bit here
+  const bool lane_pair = lane < np && li != SKIP;
+  const bool lane_ok = lane_pair && pair_ok(li, lj, F.N);
+  uint64_t todo = __ballot(lane_ok);
+  if (lane_pair && !lane_ok) {
+    const int64_t p = p0 + lane;
+    double* dst = gain_out + p;
+    if (slot) {
+      const uint64_t o = (uint64_t)(slot[p] & ~OWNER);
+      dst = o >= cache_cap ? ovf + (o - cache_cap) : gain_out + o;
+    }
+    *dst = __builtin_nan("");
+    if (w_out) w_out[p] = __builtin_nan("");
+    atomicOr(err, 1);
+  }
+  if constexpr (!SYM) n_items += __builtin_popcountll(todo);
   uint64_t pf = todo;   // pairs whose screen data is not yet requested
   auto prefetch = [&](JScr<NPL, SYM>& dst) {
     const int qq = __ffsll((unsigned long long)pf) - 1;
     pf &= pf - 1;
-    int ii = rec_lane_val(li, qq), jj = rec_lane_val(lj, qq);
-    if (pair_ok(ii, jj, F.N)) fetch_scr<NPL, SYM>(F, jj, dst, lane);
+    fetch_scr<NPL, SYM>(F, rec_lane_val(lj, qq), dst, lane);
   };
   // four pairs' screen data in flight ahead of the one being tested, issued
   // before the weight lookups (hash probes) so that the probes' latency
@@ -873,10 +888,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const int i0 = rec_lane_val(li, __ffsll((unsigned long long)todo) - 1);
     if (i0 >= 0 && i0 < F.N) { load_i_r<R, NPL, MODEL>(F, i0, L, lane); cur = i0; ++wk.iloads; }
   }
-  if (lane < np && li != SKIP && pair_ok(li, lj, F.N)) {
+  if (lane_ok) {
     lw = lookup_w(W, li, lj, SYM);
     if constexpr (SYM) lw2 = lookup_w(W, lj, li, true);
   }
+  // bit q: pair q's current weight(s) are zero (+-0)
+  const uint64_t wz = __ballot(lw == 0.0);
+  const uint64_t wz2 = SYM ? __ballot(lw2 == 0.0) : 0ull;
   // Pair t of the group uses slot t % KD of the ring, refilled with pair
   // t + KD's data once the pair is tested: no register moves between slots.
   while (todo) {
@@ -886,23 +904,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const int q = __ffsll((unsigned long long)todo) - 1;
     todo &= todo - 1;
     const int64_t p = p0 + q;
-    int i = rec_lane_val(li, q), j = rec_lane_val(lj, q);
-    const bool w0z = rec_lane_is_zero(lw, q);   // w0 == 0, tested on its bits in scalar registers
+    const int i = rec_lane_val(li, q), j = rec_lane_val(lj, q);
+    const bool w0z = (wz >> q) & 1ull;
     const JScr<NPL, SYM>& rw = nx[d];
-    if (!pair_ok(i, j, F.N)) {
-      if (lane == 0) {
-        double* dst = gain_out + p;
-        if (slot) {
-          const uint64_t o = (uint64_t)(slot[p] & ~OWNER);
-          dst = o >= cache_cap ? ovf + (o - cache_cap) : gain_out + o;
-        }
-        *dst = __builtin_nan("");
-        if (w_out) w_out[p] = __builtin_nan("");
-        atomicOr(err, 1);
-      }
-      if (pf) prefetch(nx[d]);
-      continue;
-    }
     if (i != cur) { load_i_r<R, NPL, MODEL>(F, i, L, lane); cur = i; ++wk.iloads; }
     // The kink test in two stages.  First from the 4-bit copies u of
     // 1 - y t (y - t = y u): with s = +-1 the product of two signs and
@@ -939,11 +943,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         na = (float)abs(rec_wave_sum_dpp(sa + sb)) * REC_Q8_INV > F.scr2;
         ++wk.tfetch;
       }
-      ++n_items;
-      if (!na) ++n_settled;
+
     } else {
       // i <- j: sum x_j y_i u_i;  j <- i: sum x_i y_j u_j
-      const bool w0bz = rec_lane_is_zero(lw2, q);
+      const bool w0bz = (wz2 >> q) & 1ull;
       const uint32_t sa4 = ~(rw.xw ^ L.yw), sb4 = ~(L.xw ^ rw.yw);
       uint32_t va = 0, vb = 0, uj = 0;
 #pragma unroll
@@ -980,6 +983,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     if (pf) prefetch(nx[d]);
   }
   }
+  if constexpr (!SYM) n_settled += __builtin_popcountll(settled);
   // the settled pairs' zeros, lane q for pair q
   if ((settled >> lane) & 1ull) {
     const int64_t p = p0 + lane;

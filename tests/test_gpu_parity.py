@@ -159,6 +159,30 @@ def test_apply_updates_matches_sequential_oracle(c1, c1_lam, prec):
     assert abs(obj - O.objective()) <= (1e-10 if prec == "fp64" else 1e-6) * abs(O.objective())
 
 
+@pytest.mark.parametrize("model", ["ising", "kinetic"])
+def test_invalid_pairs_in_a_batch_fail_loudly(model):
+    """A batch with invalid pairs (i == j, a negative index, j == N) among
+    valid ones at group edges raises the invalid-argument error; the next
+    valid batch scores as the oracle does."""
+    import paper_2401_01404_amd as rec
+    w = synth.ising_er(200, 300, 3.0, 0.4, 0.1, seed=4) if model == "ising" else \
+        synth.kinetic_er(200, 300, 4.0, 0.3, seed=4)
+    lam = oracle.default_lambda(w.X, model)
+    C = ctx_for(w, lam, "fp32")
+    rng = np.random.default_rng(9)
+    I = rng.integers(0, w.N, 700).astype(np.int32)
+    J = ((I + rng.integers(1, w.N, 700)) % w.N).astype(np.int32)
+    for pos, (i, j) in zip([0, 63, 64, 255, 699], [(5, 5), (-1, 3), (7, w.N), (9, 9), (w.N, 0)]):
+        Ib, Jb = I.copy(), J.copy()
+        Ib[pos], Jb[pos] = i, j
+        with pytest.raises(rec.RecError) as e:
+            C.score_pairs(Ib, Jb)
+        assert e.value.status == -1
+    g, _ = C.score_pairs(I, J)
+    go, _ = oracle.Oracle(w.X, model, lam).score_pairs(I, J)
+    assert close(g.cpu().numpy(), go, RTOL["fp32"], w.M).all()
+
+
 def _schedule_rounds(I, J):
     """Rounds of the node-disjoint schedule of a rank-ordered pair list: a
     pair runs one round after the later of the last pairs on its two rows."""
