@@ -1233,13 +1233,15 @@ __device__ __forceinline__ void update_pair(const Fields& F, const WTable& W, do
 // disjoint rows, so the round equals the sequential rank order. The grid is
 // sized for the device, not the list: each wave takes list entries in a
 // grid-stride loop, so every resident wave solves a ready pair (each pair is a
-// serial chain of loads and Newton steps: five waves per SIMD, 94 VGPRs,
-// hide more of it than the four that the unconstrained allocation allows).  W entries
+// serial chain of loads and Newton steps: five waves per SIMD hide more of it
+// than four for rows of up to 8 samples a lane; at 16 and more, five waves'
+// 102 VGPRs spill (32 in FP32) and four waves without spills are faster, C4s
+// updates 1.4-2.9 ms per sweep against 1.8-3.3).  W entries
 // are reached through the slots reserved for the list before the rounds
 // (wslot[p], no probing on the serial path of a pair); a pair's entry is
 // written only by that pair, so its value is current when the pair runs.
 template <class R, int NPL, int MODEL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_update(Fields F, WTable W, double lambda,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NPL >= 16 ? 4 : 5))) void k_update(Fields F, WTable W, double lambda,
                                                 const int32_t* __restrict__ I,
                                                 const int32_t* __restrict__ J,
                                                 const int32_t* __restrict__ ready,
@@ -1278,7 +1280,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 // depth[p] = 1 + the larger depth of the predecessors, the round the pair
 // would have run in; the largest goes to *rounds.
 template <class R, int NPL, int MODEL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_update_flow(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NPL >= 16 ? 4 : 5))) void k_update_flow(
     Fields F, WTable W, double lambda, const int32_t* __restrict__ I, const int32_t* __restrict__ J, int64_t m,
     const int32_t* __restrict__ pred, const int64_t* __restrict__ wslot, uint8_t* done, double* dw,
     int32_t* depth, unsigned long long* ticket, unsigned long long* rounds, int64_t* abort_flag, int32_t* err,

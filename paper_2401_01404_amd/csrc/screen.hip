@@ -154,6 +154,7 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs P) {
   }
   // epilogue: lane holds rows 4*(lane/16) + r, column lane % 16 of each 16x16 block
   const float tau = PASS == 1 ? *P.tau : 0.f;
+  uint64_t kept = 0;   // pass 1: bit (m, n, r) = 16 m + 4 n + r, the element's upper bound reaches tau
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -167,24 +168,35 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs P) {
         if (ok) gain_bounds(P, acc[m][n][r], i, j, &glo, &gup);
         if (PASS == 0) {
           if (glo > 0.f) atomicAdd(&hs[__builtin_bit_cast(uint32_t, glo) >> 19], 1u);
-        } else {
-          bool keep = gup > 0.f && gup >= tau;
-          if (keep && P.W.keys != nullptr) {
-            // a current (nonzero) coupling is rescored from the W list instead
-            int64_t ws = rec_hash_find(P.W.keys, P.W.mask, rec_pair_key((int)i, (int)j, false), REC_MAX_PROBE);
-            if (ws >= 0 && P.W.vals[ws] != 0.0) keep = false;
-          }
-          int64_t pos = rec_append(P.cursor, keep);
-          if (pos >= 0) {
-            if (pos < P.cap) {
-              P.oi[pos] = (int32_t)i;
-              P.oj[pos] = (int32_t)j;
-            } else {
-              atomicOr(P.err, 256);
-            }
-          }
+        } else if (gup > 0.f && gup >= tau) {
+          kept |= 1ull << (16 * m + 4 * n + r);
         }
       }
+  // pass 1: the few kept elements (about 2e-3 of them) go to the list, one
+  // per lane per round, as many rounds as the fullest lane has elements
+  if (PASS == 1) {
+    while (__ballot(kept != 0ull)) {
+      bool keep = kept != 0ull;
+      const int b = keep ? __builtin_ctzll(kept) : 0;
+      kept &= kept - 1;
+      const int64_t i = r0 + wr + (b >> 4) * 16 + 4 * (lane >> 4) + (b & 3);
+      const int64_t j = c0 + wc + ((b >> 2) & 3) * 16 + (lane & 15);
+      if (keep && P.W.keys != nullptr) {
+        // a current (nonzero) coupling is rescored from the W list instead
+        int64_t ws = rec_hash_find(P.W.keys, P.W.mask, rec_pair_key((int)i, (int)j, false), REC_MAX_PROBE);
+        if (ws >= 0 && P.W.vals[ws] != 0.0) keep = false;
+      }
+      int64_t pos = rec_append(P.cursor, keep);
+      if (pos >= 0) {
+        if (pos < P.cap) {
+          P.oi[pos] = (int32_t)i;
+          P.oj[pos] = (int32_t)j;
+        } else {
+          atomicOr(P.err, 256);
+        }
+      }
+    }
+  }
   if (PASS == 0) {
     __syncthreads();
     for (int q = tid; q < SC_BINS; q += 256)
