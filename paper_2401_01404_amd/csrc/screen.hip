@@ -125,19 +125,31 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs P) {
 #pragma unroll
     for (int n = 0; n < 4; ++n) acc[m][n] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
-  for (int k0 = 0; k0 < P.Kp; k0 += SC_K) {
-    // 128 rows x 32 bf16 per matrix = 512 chunks of 16 bytes; two per thread
+  // 128 rows x 32 bf16 per matrix and step = 512 chunks of 16 bytes, two per
+  // thread; the next step's chunks are loaded into registers while this
+  // step's MFMAs run (the global latency is not on every step's path)
+  uint4 va[2], vb[2];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int q = tid; q < 512; q += 256) {
-      const int row = q >> 2, ch = q & 3;
+    for (int h = 0; h < 2; ++h) {
+      const int q = tid + 256 * h, row = q >> 2, ch = q & 3;
       const int64_t ga = r0 + row, gb = c0 + row;
-      uint4 va = make_uint4(0u, 0u, 0u, 0u), vb = make_uint4(0u, 0u, 0u, 0u);
-      if (ga < P.N) va = *reinterpret_cast<const uint4*>(P.A + ga * P.Kp + k0 + ch * 8);
-      if (gb < P.N) vb = *reinterpret_cast<const uint4*>(P.B + gb * P.Kp + k0 + ch * 8);
-      *reinterpret_cast<uint4*>(As + row * SC_LD + ch * 8) = va;
-      *reinterpret_cast<uint4*>(Bs + row * SC_LD + ch * 8) = vb;
+      va[h] = make_uint4(0u, 0u, 0u, 0u);
+      vb[h] = make_uint4(0u, 0u, 0u, 0u);
+      if (ga < P.N) va[h] = *reinterpret_cast<const uint4*>(P.A + ga * P.Kp + k0 + ch * 8);
+      if (gb < P.N) vb[h] = *reinterpret_cast<const uint4*>(P.B + gb * P.Kp + k0 + ch * 8);
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < P.Kp; k0 += SC_K) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = tid + 256 * h, row = q >> 2, ch = q & 3;
+      *reinterpret_cast<uint4*>(As + row * SC_LD + ch * 8) = va[h];
+      *reinterpret_cast<uint4*>(Bs + row * SC_LD + ch * 8) = vb[h];
     }
     __syncthreads();
+    if (k0 + SC_K < P.Kp) fetch(k0 + SC_K);
     bf16x8 af[4], bf[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
