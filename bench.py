@@ -78,15 +78,15 @@ BATCH_PER_NODE = 16
 # --copy-probe 1024`: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE
 # 1.0x).  Valid only for the score kernel source it was measured on.
 TRAFFIC = {
-    "C4s": {"source_sha256": "070be172060f7b60bbe0b97b4d6ae5c0d8d066f2fb9c91c1002aaec6e43d898d",
+    "C4s": {"source_sha256": "02dbc91d835bdf7663b7465847958b730cace144a3e9017b8d37c8e85b9ab124",
             "hbm_over_algorithmic": 1.1644},
 }
 
 # HBM traffic of the contraction's full pass (k_kscreen) per launch, from the
 # same kind of counter runs; valid only for the source it was measured on.
 TRAFFIC_SCREEN = {
-    "C4s": {"source_sha256": "49f81fec4650db837e5b82348936afa3383ad88a8bfbabbd0eea5ea5c5a53284",
-            "hbm_bytes_per_launch": 1.8212e10},
+    "C4s": {"source_sha256": "f203fc8a4897eae5cc4c16fe48ab02483e49fffbb160b5d4b846be5964cc92c7",
+            "hbm_bytes_per_launch": 1.8225e10},
 }
 
 
