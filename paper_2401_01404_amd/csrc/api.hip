@@ -594,6 +594,7 @@ rec_status rec_cd_sweep(rec_ctx* ctx, rec_sweep_stats* st) {
   int64_t* changes = ctx->counter + 6;
   REC_HIP(hipMemsetAsync(changes, 0, sizeof(int64_t), ctx->stream));
   ++ctx->w_version;   // the rounds write W
+  ctx->w_any = true;
   for (int64_t r = 0; r + 1 < n; ++r) {
     rec_status s = rec_launch_cd_round(ctx, r, n, ctx->cd_acc, changes);
     if (s != REC_OK) { ctx->state = REC_E_STATE; return s; }

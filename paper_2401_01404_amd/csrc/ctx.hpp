@@ -129,6 +129,10 @@ struct rec_ctx {
   // W changes bump w_version; a compaction (sorted lists, row lists) is
   // reused while the version it was made at is current
   uint64_t w_version = 1, w_compacted = 0;
+  // false only between a clear of the W table and the next launch that may
+  // insert into it: the scoring kernels then skip the lookups (each a random
+  // cache line of keys) and take w = 0
+  bool w_any = true;
   int64_t w_nnz = 0;
 
   // W as sorted row lists (CSR) for the field rebuild

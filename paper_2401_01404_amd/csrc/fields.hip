@@ -632,6 +632,7 @@ rec_status rec_load_data(rec_ctx* ctx, const void* X, int64_t ldx) {
 
 void rec_wtable_clear(rec_ctx* ctx) {
   ++ctx->w_version;
+  ctx->w_any = false;
   hipMemsetAsync(ctx->W.keys, 0xff, (ctx->W.mask + 1) * sizeof(uint64_t), ctx->stream);
   hipMemsetAsync(ctx->W.count, 0, sizeof(int64_t), ctx->stream);
 }
@@ -640,6 +641,7 @@ rec_status rec_wtable_insert_list(rec_ctx* ctx, int64_t n, const int32_t* ei, co
                                   const double* w) {
   if (n <= 0) return REC_OK;
   ++ctx->w_version;
+  ctx->w_any = true;
   hipLaunchKernelGGL(k_winsert, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, ctx->W, n, ei, ej,
                      w, ctx->cfg.N, ctx->cfg.model == REC_KINETIC ? 1 : 0, ctx->err_flag);
   REC_HIP(hipGetLastError());

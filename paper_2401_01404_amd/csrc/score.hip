@@ -1584,6 +1584,10 @@ template <class R, int MODEL>
 rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
                           const int32_t* Smap, const uint32_t* slot, int owned, double* gain_out,
                           double* w_out, const Cache* C, const ScoreScratch& ss) {
+  // an empty W (right after a clear: W = 0) is passed without keys, and the
+  // kernels take w = 0 without probing it
+  WTable Wl = ctx->W;
+  if (!ctx->w_any) Wl.keys = nullptr;
   // pairs per wave: owner mode reads 64 candidates, of which only the owned
   // (new) pairs are scored: most candidates after the first iteration are cache hits
   const int ppw = owned ? 64 : 32;
@@ -1612,10 +1616,10 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
       else REC_HIP(hipMemsetAsync(qn, 0, sizeof(int64_t), ctx->stream));
 #define REC_SC(NPL)                                                                              \
       hipLaunchKernelGGL((k_kink<R, NPL, MODEL>), dim3(cb), dim3(256), 0, ctx->stream, ctx->F,   \
-                         ctx->W, pc, Ic, Jc, Smap, sc, owned, gc, wc, ovf, cap, ss.err,          \
+                         Wl, pc, Ic, Jc, Smap, sc, owned, gc, wc, ovf, cap, ss.err,          \
                          ppw, groups, ss.queue, qn, qcap, ev);                                   \
       hipLaunchKernelGGL((k_exact<R, NPL, MODEL>), dim3(exact_blocks), dim3(256), 0, ctx->stream, \
-                         ctx->F, ctx->W, ctx->cfg.lambda, Ic, Jc, Smap, sc, gc, wc, ovf, cap,    \
+                         ctx->F, Wl, ctx->cfg.lambda, Ic, Jc, Smap, sc, gc, wc, ovf, cap,        \
                          ss.queue, qn, qcap, ev)
       switch (ctx->F.npl) {
         case 1: REC_SC(1); break;
@@ -1633,7 +1637,7 @@ rec_status launch_score_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32
   }
 #define REC_SC(NPL)                                                                              \
   hipLaunchKernelGGL((k_score<R, NPL, MODEL>), dim3(blocks), dim3(256), 0, ctx->stream,          \
-                     ctx->F, ctx->W, ctx->cfg.lambda, P, I, J, Smap, slot, owned, gain_out,      \
+                     ctx->F, Wl, ctx->cfg.lambda, P, I, J, Smap, slot, owned, gain_out,          \
                      w_out, ovf, cap, ss.err, ppw, ev)
   switch (ctx->F.npl) {
     case 1: REC_SC(1); break;
@@ -1723,12 +1727,14 @@ template <class R, int MODEL>
 rec_status launch_grad_m(rec_ctx* ctx, int64_t P, const int32_t* I, const int32_t* J,
                          const int32_t* Smap, const uint32_t* slot, int owned, double* g,
                          const Cache* C) {
+  WTable Wl = ctx->W;   // without keys while W is empty, as for the scores
+  if (!ctx->w_any) Wl.keys = nullptr;
   const int ppw = owned ? 64 : 8;
   const int64_t waves = (P + ppw - 1) / ppw;
   const int64_t blocks = (waves * REC_WAVE + 255) / 256;
 #define REC_GR(NPL)                                                                                    \
   hipLaunchKernelGGL((k_grad<R, NPL, MODEL>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream, ctx->F, \
-                     ctx->W, ctx->cfg.lambda, P, I, J, Smap, slot, owned, g, C ? C->ovf : nullptr,      \
+                     Wl, ctx->cfg.lambda, P, I, J, Smap, slot, owned, g, C ? C->ovf : nullptr,          \
                      C ? (C->mask + 1) : (uint64_t)0, ctx->err_flag, ppw, ctx->work)
   switch (ctx->F.npl) {
     case 1: REC_GR(1); break;

@@ -1631,6 +1631,7 @@ rec_status rec_apply_best(rec_ctx* ctx, int64_t m, const int32_t* I, const int32
   const int64_t ne = directed ? m : 2 * m;
   if (ne > ctx->sb.cap) { ctx->err = "too many pairs for the sort buffers"; return REC_E_NOMEM; }
   hipMemsetAsync(ctx->done, 0, m, s);
+  ctx->w_any = true;   // the reserved slots are W entries
   hipLaunchKernelGGL(k_reserve, dim3(gridn(m)), dim3(256), 0, s, ctx->W, I, J, m, directed, ctx->best_slot,
                      ctx->err_flag);
   // predecessors on the rows
