@@ -78,8 +78,8 @@ BATCH_PER_NODE = 16
 # --copy-probe 1024`: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE
 # 1.0x).  Valid only for the score kernel source it was measured on.
 TRAFFIC = {
-    "C4s": {"source_sha256": "9472b1fc8a9f122a3d31ac04723f11dbd05e44c115fee97b7af5fce116c0d6c3",
-            "hbm_over_algorithmic": 0.9894},
+    "C4s": {"source_sha256": "e74e94c1c8fd4688df36b218aeb30fc3f5f6210e6ee50b7d37ba4f43d95c1827",
+            "hbm_over_algorithmic": 0.9893},
 }
 
 # HBM traffic of the contraction's full pass (k_kscreen) per launch, from the

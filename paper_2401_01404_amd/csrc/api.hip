@@ -111,7 +111,7 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   x->W.keys = a.take<uint64_t>(z.wcap);
   x->W.vals = a.take<double>(z.wcap);
   x->W.mask = (uint64_t)(z.wcap - 1);
-  x->W.count = a.take<int64_t>(1);
+  x->W.bloom = a.take<uint32_t>(REC_WBLOOM_WORDS);
   x->row_off = a.take<int64_t>(N + 1);
   x->col = a.take<int32_t>(2 * z.max_nnz);
   x->colw = a.take<double>(2 * z.max_nnz);

@@ -73,8 +73,30 @@ struct WTable {
   uint64_t* keys;
   double* vals;
   uint64_t mask;        // capacity - 1
-  int64_t* count;       // device counter of occupied slots
+  uint32_t* bloom;      // REC_WBLOOM_WORDS words: a filter of the keys ever inserted
 };
+
+// The key filter of W: each inserted key sets two bits of one 32-bit word
+// (a blocked Bloom filter, 256 KB, resident in L2).  A key whose bits are not
+// both set was never inserted, and its lookup ends without a probe of the
+// table (a random line of keys in HBM).  Keys are never removed, so the
+// filter only grows until the table is cleared.
+constexpr int REC_WBLOOM_WORDS = 1 << 16;
+__device__ __forceinline__ void rec_wbloom_pos(uint64_t key, uint32_t* word, uint32_t* bits) {
+  const uint64_t h = key * 0x9E3779B97F4A7C15ull;
+  *word = (uint32_t)(h >> 48);
+  *bits = (1u << ((h >> 5) & 31u)) | (1u << ((h >> 10) & 31u));
+}
+__device__ __forceinline__ void rec_wbloom_set(const WTable& W, uint64_t key) {
+  uint32_t w, b;
+  rec_wbloom_pos(key, &w, &b);
+  atomicOr(W.bloom + w, b);
+}
+__device__ __forceinline__ bool rec_wbloom_maybe(const WTable& W, uint64_t key) {
+  uint32_t w, b;
+  rec_wbloom_pos(key, &w, &b);
+  return (W.bloom[w] & b) == b;
+}
 
 // Score memo inside one FindBest call [App. B, caching].
 struct Cache {

@@ -442,8 +442,10 @@ __global__ void k_winsert(WTable W, int64_t n, const int32_t* ei, const int32_t*
   if (i < 0 || j < 0 || i >= N || j >= N || i == j || !isfinite(v)) { atomicOr(err, 8); return; }
   if (v == 0.0) return;
   bool ins;
-  int64_t s = rec_hash_insert(W.keys, W.mask, rec_pair_key(i, j, directed), REC_MAX_PROBE, &ins);
+  const uint64_t key = rec_pair_key(i, j, directed);
+  int64_t s = rec_hash_insert(W.keys, W.mask, key, REC_MAX_PROBE, &ins);
   if (s < 0) { atomicOr(err, 2); return; }
+  rec_wbloom_set(W, key);
   W.vals[s] = v;
 }
 
@@ -634,7 +636,7 @@ void rec_wtable_clear(rec_ctx* ctx) {
   ++ctx->w_version;
   ctx->w_any = false;
   hipMemsetAsync(ctx->W.keys, 0xff, (ctx->W.mask + 1) * sizeof(uint64_t), ctx->stream);
-  hipMemsetAsync(ctx->W.count, 0, sizeof(int64_t), ctx->stream);
+  hipMemsetAsync(ctx->W.bloom, 0, REC_WBLOOM_WORDS * sizeof(uint32_t), ctx->stream);
 }
 
 rec_status rec_wtable_insert_list(rec_ctx* ctx, int64_t n, const int32_t* ei, const int32_t* ej,

@@ -107,7 +107,9 @@ __device__ __forceinline__ int64_t smp(int c, int lane) {
 
 __device__ __forceinline__ double lookup_w(const WTable& W, int i, int j, bool directed) {
   if (W.keys == nullptr) return 0.0;
-  int64_t s = rec_hash_find(W.keys, W.mask, rec_pair_key(i, j, directed), REC_MAX_PROBE);
+  const uint64_t key = rec_pair_key(i, j, directed);
+  if (!rec_wbloom_maybe(W, key)) return 0.0;   // never inserted
+  int64_t s = rec_hash_find(W.keys, W.mask, key, REC_MAX_PROBE);
   return s < 0 ? 0.0 : W.vals[s];
 }
 
@@ -1401,9 +1403,14 @@ __device__ __forceinline__ void cd_pair(const Fields& F, const WTable& W, double
   }
   if (lane == 0) {
     bool ins;
-    const int64_t slot = rec_hash_insert(W.keys, W.mask, rec_pair_key(i, j, DIR), REC_MAX_PROBE, &ins);
-    if (slot < 0) atomicOr(err, 2);
-    else W.vals[slot] = r.w;
+    const uint64_t key = rec_pair_key(i, j, DIR);
+    const int64_t slot = rec_hash_insert(W.keys, W.mask, key, REC_MAX_PROBE, &ins);
+    if (slot < 0) {
+      atomicOr(err, 2);
+    } else {
+      rec_wbloom_set(W, key);
+      W.vals[slot] = r.w;
+    }
     *acc += fabs(d);
     atomicAdd((unsigned long long*)changes, 1ull);
   }

@@ -807,9 +807,13 @@ __global__ void k_reserve(WTable W, const int32_t* I, const int32_t* J, int64_t 
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= m) return;
   bool ins;
-  int64_t s = rec_hash_insert(W.keys, W.mask, rec_pair_key(I[p], J[p], directed), REC_MAX_PROBE, &ins);
+  const uint64_t key = rec_pair_key(I[p], J[p], directed);
+  int64_t s = rec_hash_insert(W.keys, W.mask, key, REC_MAX_PROBE, &ins);
   if (s < 0) atomicOr(err, 2);
-  else if (ins) W.vals[s] = 0.0;
+  else {
+    rec_wbloom_set(W, key);
+    if (ins) W.vals[s] = 0.0;
+  }
   slot[p] = s;
 }
 
