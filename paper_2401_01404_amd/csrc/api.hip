@@ -154,7 +154,6 @@ void layout(rec_ctx* x, const rec_config* c, const Sizes& z, Arena& a) {
   x->ts_j = a.take<int32_t>(z.cand_cap);
   x->ts_slot = a.take<uint32_t>(z.cand_cap);
   x->inoff = a.take<int64_t>(N + 2);
-  x->inoff_cnt = a.take<int32_t>(N);
   x->capcnt = a.take<int32_t>(N);
   x->in_src = a.take<int32_t>(z.list_cap);
   x->dset_keys = a.take<uint64_t>(z.dcap);

@@ -177,7 +177,6 @@ struct rec_ctx {
   int64_t cand_cap;
   int32_t* cand_v; int32_t* cand_gi; uint32_t* cand_slot;
   int32_t *ts_i, *ts_j; uint32_t* ts_slot;    // to-score list
-  int32_t* inoff_cnt;   // N (fill cursors)
   int64_t* inoff;       // N + 1
   int32_t* in_src;      // list_cap: capped in-neighbours, k per node
   int32_t* capcnt;      // N

@@ -206,23 +206,39 @@ __global__ __launch_bounds__(REC_WAVE) void k_knn_init(const int32_t* S, int64_t
 // ------------------------------------------------------------ in-edges --
 // Undirected view U: every node b keeps all its out-neighbours and, of its
 // in-neighbours a (edges a -> b), the k with the smallest (hash32, a) keys.
-__global__ void k_in_count(const int32_t* Gidx, int64_t n, int k, int64_t* indeg) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * k) return;
-  atomicAdd((unsigned long long*)&indeg[Gidx[e]], 1ULL);
+// In-neighbours of the KNN graph by target, without atomics: the n k edges
+// (record = target, edge index) are sorted by target (stable, so sources
+// ascend within a target), each target's range is read off the sorted
+// targets, and each in-edge gets its key (hash << 32 | source).  Device-scope
+// atomics on random targets (a count, then a cursor per edge) had run at
+// about 1.4e9 a second.
+__global__ void k_in_records(const int32_t* Gidx, int64_t ne, uint64_t* tgt, uint32_t* eidx) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  tgt[e] = (uint64_t)(uint32_t)Gidx[e];
+  eidx[e] = (uint32_t)e;
 }
 
-__global__ void k_in_fill(const int32_t* S, const int32_t* Gidx, int64_t n, int k, uint64_t seed,
-                          int level, int iter, const int64_t* inoff, int32_t* cursor,
-                          uint64_t* in_key) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * k) return;
-  int64_t a = e / k;
-  int b = Gidx[e];
+// inoff[b] = first sorted position of target b, for b in [0, n]; position p
+// writes the targets in (t[p - 1], t[p]] (p = 0: from 0; p = ne: up to n),
+// so every entry is written once
+__global__ void k_in_bounds(const uint64_t* tgt, int64_t ne, int64_t n, int64_t* inoff) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > ne) return;
+  const int64_t lo = p == 0 ? -1 : (int64_t)tgt[p - 1];
+  const int64_t hi = p == ne ? n : (int64_t)tgt[p];
+  for (int64_t b = lo + 1; b <= hi; ++b) inoff[b] = p;
+}
+
+__global__ void k_in_keys(const int32_t* S, const uint64_t* tgt, const uint32_t* eidx, int64_t ne, int k,
+                          uint64_t seed, int level, int iter, uint64_t* in_key) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ne) return;
+  const int64_t a = (int64_t)eidx[p] / k;
+  const int b = (int)tgt[p];
   uint64_t h = rec_ctr(seed, REC_STREAM_CAP, ((uint64_t)(uint32_t)level << 32) | (uint32_t)iter,
                        ((uint64_t)(uint32_t)S[a] << 32) | (uint32_t)S[b]) >> 32;
-  int64_t pos = inoff[b] + atomicAdd(&cursor[b], 1);
-  in_key[pos] = (h << 32) | (uint64_t)a;
+  in_key[p] = (h << 32) | (uint64_t)a;
 }
 
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
@@ -234,13 +250,19 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
   return v;
 }
 
-// one wave per node: capin[b*k + c] = sources of the (up to) k smallest keys
-__global__ __launch_bounds__(REC_WAVE) void k_in_select(int64_t n, int k, const int64_t* inoff,
-                                                        const uint64_t* in_key, int32_t* capin,
-                                                        int32_t* capcnt) {
-  const int64_t b = blockIdx.x;
+// one wave per node (four nodes per block): capin[b*k + c] = sources of the
+// (up to) k smallest keys, in increasing key order.  A node's keys (up to
+// IN_REG per lane) are read once into registers and the k rounds of wave
+// minima run on them; a node with more in-edges (a hub of the KNN graph)
+// is read once into per-lane sorted lists.
+constexpr int IN_REG = 4;
+constexpr int IN_TOP = 32;   // per-lane list of the hub path (k up to 32)
+__global__ __launch_bounds__(256) void k_in_select(int64_t n, int k, const int64_t* inoff,
+                                                   const uint64_t* in_key, int32_t* capin,
+                                                   int32_t* capcnt) {
+  const int64_t b = (int64_t)blockIdx.x * (256 / REC_WAVE) + threadIdx.x / REC_WAVE;
   if (b >= n) return;
-  const int lane = threadIdx.x;
+  const int lane = rec_lane();
   const int64_t e0 = inoff[b], deg = inoff[b + 1] - e0;
   if (deg <= k) {
     for (int64_t c = lane; c < deg; c += REC_WAVE) capin[b * k + c] = (int32_t)(in_key[e0 + c] & 0xffffffffu);
@@ -248,15 +270,60 @@ __global__ __launch_bounds__(REC_WAVE) void k_in_select(int64_t n, int k, const 
     return;
   }
   uint64_t prev = 0;
-  for (int r = 0; r < k; ++r) {
-    uint64_t best = ~0ULL;
-    for (int64_t c = lane; c < deg; c += REC_WAVE) {
-      uint64_t key = in_key[e0 + c];
-      if ((r == 0 || key > prev) && key < best) best = key;
+  if (deg <= (int64_t)REC_WAVE * IN_REG) {
+    // keys are (hash << 32 | source), sources < 2^31: never all ones
+    uint64_t kv[IN_REG];
+#pragma unroll
+    for (int t = 0; t < IN_REG; ++t) {
+      const int64_t c = lane + (int64_t)t * REC_WAVE;
+      kv[t] = c < deg ? in_key[e0 + c] : ~0ULL;
     }
-    best = wave_min_u64(best);
-    if (lane == 0) capin[b * k + r] = (int32_t)(best & 0xffffffffu);
-    prev = best;
+    for (int r = 0; r < k; ++r) {
+      uint64_t best = ~0ULL;
+#pragma unroll
+      for (int t = 0; t < IN_REG; ++t)
+        if ((r == 0 || kv[t] > prev) && kv[t] < best) best = kv[t];
+      best = wave_min_u64(best);
+      if (lane == 0) capin[b * k + r] = (int32_t)(best & 0xffffffffu);
+      prev = best;
+    }
+  } else if (k <= IN_TOP) {
+    // hubs: one pass over the keys, each lane keeping its own IN_TOP smallest
+    // in a sorted register list; the k smallest overall are among the lanes'
+    // lists, taken by k rounds of wave minima over the list heads (the lane
+    // holding the minimum drops its head)
+    uint64_t lst[IN_TOP];
+#pragma unroll
+    for (int t = 0; t < IN_TOP; ++t) lst[t] = ~0ULL;
+    for (int64_t c = lane; c < deg; c += REC_WAVE) {
+      const uint64_t key = in_key[e0 + c];
+      if (key < lst[IN_TOP - 1]) {
+#pragma unroll
+        for (int t = IN_TOP - 1; t > 0; --t)
+          if (key < lst[t]) lst[t] = lst[t - 1] > key ? lst[t - 1] : key;
+        if (key < lst[0]) lst[0] = key;
+      }
+    }
+    for (int r = 0; r < k; ++r) {
+      const uint64_t best = wave_min_u64(lst[0]);
+      if (lane == 0) capin[b * k + r] = (int32_t)(best & 0xffffffffu);
+      if (lst[0] == best) {
+#pragma unroll
+        for (int t = 0; t < IN_TOP - 1; ++t) lst[t] = lst[t + 1];
+        lst[IN_TOP - 1] = ~0ULL;
+      }
+    }
+  } else {
+    for (int r = 0; r < k; ++r) {
+      uint64_t best = ~0ULL;
+      for (int64_t c = lane; c < deg; c += REC_WAVE) {
+        uint64_t key = in_key[e0 + c];
+        if ((r == 0 || key > prev) && key < best) best = key;
+      }
+      best = wave_min_u64(best);
+      if (lane == 0) capin[b * k + r] = (int32_t)(best & 0xffffffffu);
+      prev = best;
+    }
   }
   if (lane == 0) capcnt[b] = k;
 }
@@ -1064,14 +1131,19 @@ struct Search {
       if (mode == 0) {
         // undirected view U: the k in-neighbours of each node with the smallest keys
         int64_t ne = n * k;
-        hipMemsetAsync(ctx->cnt, 0, sizeof(int64_t) * (n + 1), s);
-        hipMemsetAsync(ctx->inoff_cnt, 0, sizeof(int32_t) * n, s);
-        hipLaunchKernelGGL(k_in_count, dim3(gridn(ne)), dim3(256), 0, s, ctx->Gidx, n, k, ctx->cnt);
-        if ((st = rec_exclusive_scan(ctx, ctx->cnt, ctx->inoff, n + 1, nullptr)) != REC_OK) return st;
-        hipLaunchKernelGGL(k_in_fill, dim3(gridn(ne)), dim3(256), 0, s, S, ctx->Gidx, n, k, seed,
-                           level, it, ctx->inoff, ctx->inoff_cnt, ctx->sb.klo[0]);
-        hipLaunchKernelGGL(k_in_select, dim3(n), dim3(REC_WAVE), 0, s, n, k, ctx->inoff,
-                           ctx->sb.klo[0], ctx->in_src, ctx->capcnt);
+        hipLaunchKernelGGL(k_in_records, dim3(gridn(std::max<int64_t>(ne, 1))), dim3(256), 0, s, ctx->Gidx, ne,
+                           ctx->sb.klo[0], ctx->sb.val[0]);
+        Digit dg[4];
+        int nd = 0;
+        for (int bit = 0; bit < bits_for(n); bit += 8) dg[nd++] = {0, bit};
+        int sc = 0;
+        if ((st = rec_radix_sort(ctx, ne, dg, nd, &sc)) != REC_OK) return st;
+        hipLaunchKernelGGL(k_in_bounds, dim3(gridn(ne + 1)), dim3(256), 0, s, ctx->sb.klo[sc], ne, n, ctx->inoff);
+        uint64_t* in_key = ctx->sb.klo[1 - sc];
+        hipLaunchKernelGGL(k_in_keys, dim3(gridn(std::max<int64_t>(ne, 1))), dim3(256), 0, s, S, ctx->sb.klo[sc],
+                           ctx->sb.val[sc], ne, k, seed, level, it, in_key);
+        hipLaunchKernelGGL(k_in_select, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, k, ctx->inoff,
+                           in_key, ctx->in_src, ctx->capcnt);
       }
       // NNDescent with the node's candidates fitting LDS: one pass per chunk
       const int64_t lcap = std::min<int64_t>(4 * (int64_t)k * k, n - 1);

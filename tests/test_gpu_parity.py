@@ -327,6 +327,36 @@ def test_knn_lists_match_oracle(mid_state, subset):
             assert it == it_o
 
 
+def test_knn_lists_match_oracle_with_a_hub():
+    """A hub of the KNN graph: Gaussian samples where node j mixes node 0's
+    with its own noise at correlation rho_j in [0.3, 0.9], so node 0 is every
+    node's most correlated partner and sits in nearly all 600 lists; its
+    capped in-neighbours (k of several hundred in-edges) take the per-lane
+    selection for hubs.  Real-valued samples leave no tied gains (+-1 samples
+    at W = 0 tie in exact arithmetic, and the two sides' rounding orders then
+    split the ties differently), so the NNDescent lists and the iteration
+    count equal the oracle's."""
+    import types
+    rng = np.random.default_rng(31)
+    N, M, k = 600, 300, 8
+    x0 = rng.standard_normal(M)
+    rho = 0.3 + 0.6 * rng.random(N - 1)
+    X = np.empty((N, M))
+    X[0] = x0
+    X[1:] = rho[:, None] * x0 + np.sqrt(1 - rho[:, None] ** 2) * rng.standard_normal((N - 1, M))
+    X = X.astype(np.float32)
+    w = types.SimpleNamespace(X=X, model="gauss", N=N, M=M)
+    lam = 0.05 * oracle.default_lambda(X, "gauss")
+    O = oracle.Oracle(X, "gauss", lam)
+    C = ctx_for(w, lam, "fp64")
+    S = np.arange(N, dtype=np.int32)
+    Jo, Go, it_o = O.knn(S, k, "nndescent", seed=0, level=0)
+    nbr, g, it = C.knn(S, k, 0, "nndescent")
+    compare_lists(nbr.cpu().numpy(), g.cpu().numpy(), Jo, Go, 1e-10)
+    assert it == it_o
+    assert (Jo == 0).sum() > 256   # node 0's in-degree in the final lists
+
+
 def test_findbest_nndescent_matches_oracle(mid_state):
     w, lam, O = mid_state
     ei, ej, wv, th = O.get_model()
