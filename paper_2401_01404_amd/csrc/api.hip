@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -383,6 +384,14 @@ rec_status rec_create(const rec_config* cfg, const void* X_dev, void* ws_dev, si
   ctx->stream = (hipStream_t)stream;
   ctx->fp32 = cfg->prec == REC_FP32;
   ctx->m_default = z.m;
+  // the update dataflow's bound on one wait (polls of a predecessor's flag);
+  // REC_FLOW_SPIN_LIMIT overrides it (0: a pair that must wait ends the
+  // launch with an error, the way the failure path is exercised)
+  if (const char* e = std::getenv("REC_FLOW_SPIN_LIMIT")) {
+    char* end = nullptr;
+    const long long v = std::strtoll(e, &end, 10);
+    if (end != e && v >= 0) ctx->flow_spin_limit = v;
+  }
   if (hipGetDevice(&ctx->dev) != hipSuccess) { delete ctx; return REC_E_HIP; }
   if (scratch_for_current_device(ctx->dev, &ctx->noalloc_scratch) != REC_OK) {
     delete ctx;

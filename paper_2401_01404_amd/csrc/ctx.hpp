@@ -155,6 +155,10 @@ struct rec_ctx {
   // insert into it: the scoring kernels then skip the lookups (each a random
   // cache line of keys) and take w = 0
   bool w_any = true;
+  // bound on one wait of the update dataflow, in polls of a flag (about
+  // 1-2 us each): far beyond any chain of predecessors, so hitting it means a
+  // broken schedule, reported as an error instead of a hang
+  int64_t flow_spin_limit = int64_t(1) << 24;
   int64_t w_nnz = 0;
 
   // W as sorted row lists (CSR) for the field rebuild

@@ -1768,7 +1768,7 @@ rec_status rec_apply_best(rec_ctx* ctx, int64_t m, const int32_t* I, const int32
       hipMemsetAsync(ticket, 0, 2 * sizeof(int64_t), s);
       hipMemsetAsync(abort_flag, 0, sizeof(int64_t), s);
       rec_status st = rec_launch_update_flow(ctx, m, I, J, ctx->pred, ctx->done, ctx->dw, ctx->depth, ticket,
-                                             d_depth, abort_flag, int64_t(1) << 24);
+                                             d_depth, abort_flag, ctx->flow_spin_limit);
       if (st != REC_OK) return st;
       int64_t tail = 0;
       if (hipMemcpyAsync(&tail, d_depth, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -231,6 +231,38 @@ def test_apply_updates_hub_rows_match_sequential_oracle(c1, c1_lam, model):
     assert abs(obj - O.objective()) <= 1e-10 * abs(O.objective())
 
 
+def test_update_dataflow_wait_bound_reports_an_error(c1, c1_lam, monkeypatch):
+    """The dataflow's bounded wait, forced from the host: with the bound at
+    zero polls (REC_FLOW_SPIN_LIMIT=0, read when a context is created) a pair
+    of the hub rows that has to wait for its predecessor ends the launch:
+    every wavefront leaves (the waiting ones read the abort flag) and the call
+    reports that the rounds did not drain.  A context made afterwards, with
+    the default bound, applies the same list as the oracle does."""
+    import paper_2401_01404_amd as rec
+    O = oracle.Oracle(c1.X, "ising", c1_lam)
+    Io, Jo, _, _ = O.find_best(2 * c1.N, "exhaustive")
+    have = set(zip(Io.tolist(), Jo.tolist()))
+    extra = [(min(3, j), max(3, j)) for j in range(c1.N) if j != 3]
+    extra = [p for p in extra if p not in have]
+    rng = np.random.default_rng(22)
+    pairs = list(zip(Io.tolist(), Jo.tolist()))
+    for p, pos in zip(extra, rng.integers(0, len(pairs), len(extra))):
+        pairs.insert(int(pos), p)
+    I = np.array([p[0] for p in pairs], np.int32)
+    J = np.array([p[1] for p in pairs], np.int32)
+    monkeypatch.setenv("REC_FLOW_SPIN_LIMIT", "0")
+    C = ctx_for(c1, c1_lam, "fp64")
+    with pytest.raises(rec.RecError) as e:
+        C.apply_updates(I, J)
+    assert "did not drain" in str(e.value)
+    del C
+    monkeypatch.delenv("REC_FLOW_SPIN_LIMIT")
+    C2 = ctx_for(c1, c1_lam, "fp64")
+    d_gpu = C2.apply_updates(I, J)
+    d_or, _ = O.apply_updates(I, J)
+    assert abs(d_gpu - d_or) <= 1e-9 * d_or
+
+
 def test_sweep_reports_the_schedule_rounds(c1, c1_lam):
     """The round count a sweep reports is the longest run of the
     node-disjoint schedule over the pairs it applied (the positive-gain
